@@ -1,0 +1,233 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) electrostatic PIC-MCC step.
+ *
+ * The library advances the plasma above a cathode as in the paper's plasma
+ * model: superparticles (electrons, Cu neutrals, Cu+ ions) are injected as
+ * emitted electrons and evaporated or sputtered neutrals, their charge
+ * drives Poisson's equation (Eq. 1) with Dirichlet or Neumann conditions on
+ * the z faces, they move under the electric force, electrons collide with
+ * neutrals by Monte Carlo collisions whose probability per step is
+ * P = 1 - exp(-u n sigma(E) dt) (Eq. 4, in null-collision form), and the
+ * particles that reach the cathode are handed back to the surface model
+ * (Appendix A: transfer of ions to MD).
+ *
+ * Conventions
+ *   - Units are SI at the boundary (m, s, V, V/m, m/s, m^2, eV where named).
+ *   - Grid: nx * ny * nz cells of edge dx; nodes i in [0,nx), j in [0,ny)
+ *     periodic, k in [0,nz] from the cathode (z = 0) to the anode
+ *     (z = nz*dx).  Node arrays hold nx*ny*(nz+1) values, x fastest, then y,
+ *     then z (index (k*ny + j)*nx + i).
+ *   - Particle arrays are structure-of-arrays: a "pos3n" buffer holds
+ *     x[0..n), then y[0..n), then z[0..n); "vel3n" likewise.
+ *   - Every pointer argument named *device* must be device memory visible
+ *     to the stream given at pic_init; the library never allocates device
+ *     memory: all state lives in the caller-provided workspace.
+ *   - All work is enqueued on the context's stream.  Calls that return
+ *     results to the host (pic_step, pic_advance, pic_field, poisson_solve,
+ *     pic_read_*) synchronise that stream before returning.
+ *   - A context is not thread-safe; use one per host thread and stream.
+ *
+ * Errors: every call returns a pic_status; no C++ exception crosses the
+ * ABI.  Device-side conditions (capacity overflow, non-finite values) are
+ * sticky flags read at the end of the step and returned by that call;
+ * pic_last_error() gives a text description of the last failure.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_ABI_VERSION 1
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_ERR_ARG = -1,       /* invalid argument or configuration           */
+  PIC_ERR_CAPACITY = -2,  /* a particle/event buffer would overflow       */
+  PIC_ERR_NOCONV = -3,    /* Poisson solve did not reach rel_tol          */
+  PIC_ERR_NONFINITE = -4, /* NaN/Inf found in particle or field data      */
+  PIC_ERR_HIP = -5,       /* a HIP runtime call failed                    */
+  PIC_ERR_STATE = -6      /* call not valid in the current state          */
+} pic_status;
+
+enum { PIC_ELECTRON = 0, PIC_NEUTRAL = 1, PIC_ION = 2 };
+enum { PIC_BC_DIRICHLET = 0, PIC_BC_NEUMANN = 1 };
+enum { PIC_FP64 = 0, PIC_MIXED = 1 };
+enum { PIC_ION_LOTZ = 0, PIC_ION_CONST = 1 };
+enum { PIC_WARM_ZERO = 0, PIC_WARM_GIVEN = 1 };
+
+typedef struct pic_ctx pic_ctx;
+
+/* Grid, boundary conditions, solver and capacities (Eq. 1 and its
+ * Dirichlet/Neumann boundary data). */
+typedef struct {
+  int32_t nx, ny, nz;      /* cells per axis; each must be >= 2 and even  */
+  double dx;               /* cell edge, m                                 */
+  int32_t bc_lo, bc_hi;    /* PIC_BC_* for the cathode / anode face        */
+  double v_lo, v_hi;       /* Dirichlet: potential, V.  Neumann: dphi/dz
+                              at the face, V/m.  Both Neumann is rejected
+                              (singular with periodic x, y).              */
+  int32_t precision;       /* PIC_FP64, or PIC_MIXED: FP32 particles and
+                              FP32 smoothing with FP64 refinement          */
+  int32_t field_solve;     /* 1: particle charge drives phi; 0: boundary
+                              data only (test configurations)             */
+  int32_t mg_levels;       /* multigrid levels, 0 = as deep as possible    */
+  int32_t max_vcycles;     /* V-cycle limit per solve (PIC_ERR_NOCONV)     */
+  int32_t nu_pre, nu_post; /* red-black Gauss-Seidel sweeps per level      */
+  int32_t coarse_sweeps;   /* sweeps on a coarsest level wider than 1x1    */
+  int32_t sort_every;      /* reserved, must be 1: particles are binned by
+                              tile after every step                        */
+  double rel_tol;          /* ||b - A phi||_2 / ||b||_2 target, e.g. 1e-10 */
+  uint64_t seed;           /* Philox key                                   */
+  uint32_t w_sp;           /* superparticle weight (all species), >= 1     */
+  uint32_t reserved;
+  int64_t capacity[3];     /* particles per species (electron, Cu, Cu+)    */
+  int64_t queue_capacity;  /* particles pic_inject may queue per step      */
+  int64_t max_events;      /* ionisation events / cathode absorptions /
+                              Fowler-Nordheim electrons per step           */
+} pic_config;
+
+/* Electron-neutral collision model (Eq. 4; ionisation and elastic). */
+typedef struct {
+  int32_t enabled;         /* 0 disables MCC                               */
+  int32_t ion_model;       /* PIC_ION_LOTZ or PIC_ION_CONST                */
+  double sigma_el;         /* elastic cross section, m^2                   */
+  double lotz_a;           /* Lotz constant, m^2 eV^2 (4.5e-18 = 4.5e-14
+                              cm^2 eV^2)                                   */
+  double ion_I_eV;         /* ionisation threshold, eV (Cu: 7.73)          */
+  double sigma_ion_const;  /* PIC_ION_CONST cross section above I, m^2     */
+  double E_max_eV;         /* majorant energy of the null-collision method */
+} pic_collisions;
+
+/* Per-step particle sources at the cathode and in the gap. */
+typedef struct {
+  int32_t disk_on, fn_on, sphere_on, reserved;
+  /* Disk at z = 0: electrons with a flux-weighted half-Maxwellian normal
+   * speed at kT_e, neutrals with a half-space Maxwellian at T_n. */
+  double disk_cx, disk_cy, disk_radius;
+  int64_t disk_n_e;
+  double disk_kT_e_eV;
+  int64_t disk_n_n;
+  double disk_T_n_K;
+  /* Fowler-Nordheim emission from the surface nodes inside a disk, driven
+   * by the local field -E_z(z = 0) (elementary FN, work function phi_w). */
+  double fn_cx, fn_cy, fn_radius, fn_phi_w_eV, fn_kT_e_eV;
+  /* Sphere (e.g. an evaporating nanoparticle): neutrals from its surface,
+   * Maxwellian at T with the inward normal component reflected. */
+  double sph_cx, sph_cy, sph_cz, sph_radius;
+  int64_t sph_n;
+  double sph_T_K;
+} pic_sources;
+
+typedef struct {
+  int32_t vcycles;         /* V-cycles taken                               */
+  int32_t converged;       /* 1 if rel_residual <= rel_tol                 */
+  double rel_residual;     /* final ||b - A phi|| / ||b||                  */
+  double b_norm;           /* ||b||_2 of the scaled system                 */
+} pic_solve_info;
+
+typedef struct {
+  int64_t counts[3];          /* live particles after the step             */
+  int64_t emitted[3];         /* particles added by queue and sources      */
+  int64_t fn_emitted;         /* of which Fowler-Nordheim electrons        */
+  int64_t cathode[3];         /* absorbed at z = 0                         */
+  int64_t anode[3];           /* absorbed at z = nz*dx                     */
+  int64_t candidates;         /* null-collision candidates                 */
+  int64_t elastic;
+  int64_t ionisations;        /* successful (matched) ionisations          */
+  int64_t starved;            /* ionisations without a neutral left        */
+  int64_t over_majorant;      /* candidates above E_max                    */
+  int64_t near_threshold;     /* draws within 1e-6 of a threshold that
+                                 involves a transcendental function        */
+  int64_t total_charge_units; /* sum of node charges, 2^-39 w_sp e units   */
+  double kinetic[3];          /* kinetic energy after the push, J          */
+  double field_energy;        /* 1/2 sum q phi over nodes, J               */
+  pic_solve_info solve;
+  int64_t step;               /* steps completed                           */
+  uint64_t next_id;           /* next particle id to assign                */
+} pic_diag;
+
+/* Particles absorbed at the cathode in the last step, sorted by
+ * (species, id): the ions (and neutrals, electrons) the surface model takes
+ * back.  Device pointers owned by the library, valid until the next
+ * pic_step / pic_advance / pic_destroy. */
+typedef struct {
+  int64_t n;
+  const int32_t* species;  /* device                                      */
+  const uint64_t* id;      /* device                                      */
+  const double* pos;       /* device, 3n SoA: crossing point, z = 0        */
+  const double* vel;       /* device, 3n SoA: half-step velocity           */
+} pic_absorbed;
+
+/* Workspace size for a configuration; the caller allocates it (e.g. with
+ * torch) with at least 256-byte alignment. */
+pic_status pic_workspace_bytes(const pic_config* cfg, size_t* bytes);
+
+/* Validate cfg, carve the workspace, build the multigrid hierarchy and zero
+ * the state.  hip_stream is a hipStream_t (NULL = default stream). */
+pic_status pic_init(const pic_config* cfg, void* workspace_device,
+                    size_t bytes, void* hip_stream, pic_ctx** out);
+void pic_destroy(pic_ctx* ctx);
+
+pic_status pic_set_collisions(pic_ctx* ctx, const pic_collisions* c);
+pic_status pic_set_sources(pic_ctx* ctx, const pic_sources* s);
+
+/* Queue n particles of one species (emitted electrons, evaporated or
+ * sputtered neutrals, ...).  pos3n/vel3n are device buffers the caller keeps
+ * alive until the stream passes this call.  Queued particles receive ids
+ * next_id + rank (call order) at the next step and are pushed in it; their
+ * velocity is taken as the half-step velocity. */
+pic_status pic_inject(pic_ctx* ctx, int32_t species, int64_t n,
+                      const double* pos3n_device, const double* vel3n_device);
+
+/* One full step: deposit charge, solve Poisson (warm start: the previous
+ * phi), compute E, add queued and source particles, push, collide, bin.
+ * out (may be NULL) receives the cathode-absorbed list; diag (may be NULL)
+ * the step's diagnostics. */
+pic_status pic_step(pic_ctx* ctx, double dt, pic_absorbed* out,
+                    pic_diag* diag);
+
+/* rho (charge density at nodes, C/m^3) -> phi (V) with the context's grid
+ * and boundary data.  phi is read as the initial guess when
+ * warm == PIC_WARM_GIVEN.  Does not touch the particle state. */
+pic_status poisson_solve(pic_ctx* ctx, const double* rho_device,
+                         double* phi_device, int32_t warm,
+                         pic_solve_info* info);
+
+/* The three stages pic_step is made of, for tests and for callers that
+ * supply their own field. */
+pic_status pic_deposit(pic_ctx* ctx);                        /* -> charge  */
+pic_status pic_field(pic_ctx* ctx, pic_solve_info* info);    /* -> phi, E  */
+pic_status pic_set_phi(pic_ctx* ctx, const double* phi_device); /* -> E    */
+pic_status pic_advance(pic_ctx* ctx, double dt, pic_absorbed* out,
+                       pic_diag* diag);
+
+/* State access.  pic_load_particles replaces a species' population with
+ * caller data (ids included); positions must satisfy 0 <= z/dx < nz. */
+pic_status pic_load_particles(pic_ctx* ctx, int32_t species, int64_t n,
+                              const double* pos3n_device,
+                              const double* vel3n_device,
+                              const uint64_t* ids_device);
+pic_status pic_count(pic_ctx* ctx, int32_t species, int64_t* n);
+pic_status pic_read_particles(pic_ctx* ctx, int32_t species, int64_t cap,
+                              double* pos3n_device, double* vel3n_device,
+                              uint64_t* ids_device, int64_t* n);
+/* Copies of the node fields; any pointer may be NULL.  acc: int64 charge
+ * units; phi: V; E3: 3 arrays of node values (Ex block, Ey, Ez), V/m. */
+pic_status pic_read_fields(pic_ctx* ctx, int64_t* acc_device,
+                           double* phi_device, double* E3_device);
+pic_status pic_set_clock(pic_ctx* ctx, int64_t step, uint64_t next_id);
+pic_status pic_get_diag(pic_ctx* ctx, pic_diag* diag);
+
+const char* pic_last_error(const pic_ctx* ctx);
+int32_t pic_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

@@ -245,8 +245,9 @@ def fn_current_density(F, phi_w_eV):
 
 def sources(state, params, E, dt, near):
     """New particles of this step, with ids next_id + rank in fixed order:
-    injection queue (call order), disk electrons, disk neutrals, Fowler-
-    Nordheim electrons (node order), sphere neutrals.
+    injection queue (call order), disk electrons, disk neutrals, sphere
+    neutrals, Fowler-Nordheim electrons (node order, last because only
+    their number depends on the field).
 
     Returns per-species lists of (x, y, z, vx, vy, vz, ids) and the number of
     emitted electrons by source.
@@ -293,6 +294,33 @@ def sources(state, params, E, dt, near):
             new[C.NEUTRAL].append((x, y, z, rr * np.cos(th), rr * np.sin(th),
                                    _flux_vz(u5, vth2), ids))
 
+    sph = src.get("sphere")
+    if sph and int(sph.get("n", 0)):
+        n = int(sph["n"])
+        ids = take(n)
+        u1, u2 = uniforms(ids, step, TAG_SRC0, seed)
+        c = 1.0 - 2.0 * u1
+        s = np.sqrt(1.0 - c * c)
+        ps = C.TWO_PI * u2
+        nx_, ny_, nz_ = s * np.cos(ps), s * np.sin(ps), c
+        x = _wrap(sph["cx"] + sph["radius"] * nx_, g.lx)
+        y = _wrap(sph["cy"] + sph["radius"] * ny_, g.ly)
+        z = sph["cz"] + sph["radius"] * nz_
+        sig = np.sqrt((C.K_B * sph["T_K"]) / C.M_CU)
+        u3, u4 = uniforms(ids, step, TAG_SRC1, seed)
+        rr = np.sqrt(-2.0 * np.log(1.0 - u3))
+        g1, g2 = rr * np.cos(C.TWO_PI * u4), rr * np.sin(C.TWO_PI * u4)
+        u5, u6 = uniforms(ids, step, TAG_SRC2, seed)
+        g3 = np.sqrt(-2.0 * np.log(1.0 - u5)) * np.cos(C.TWO_PI * u6)
+        vx, vy, vz = sig * g1, sig * g2, sig * g3
+        vn = (vx * nx_ + vy * ny_) + vz * nz_
+        inward = vn < 0.0
+        t = 2.0 * vn
+        vx = np.where(inward, vx - t * nx_, vx)
+        vy = np.where(inward, vy - t * ny_, vy)
+        vz = np.where(inward, vz - t * nz_, vz)
+        new[C.NEUTRAL].append((x, y, z, vx, vy, vz, ids))
+
     n_fn = 0
     fn = src.get("fn")
     if fn:
@@ -327,33 +355,6 @@ def sources(state, params, E, dt, near):
             zero = np.zeros(n_fn)
             new[C.ELECTRON].append((x, y, zero, zero.copy(), zero.copy(),
                                     _flux_vz(u3, vth2), ids))
-
-    sph = src.get("sphere")
-    if sph and int(sph.get("n", 0)):
-        n = int(sph["n"])
-        ids = take(n)
-        u1, u2 = uniforms(ids, step, TAG_SRC0, seed)
-        c = 1.0 - 2.0 * u1
-        s = np.sqrt(1.0 - c * c)
-        ps = C.TWO_PI * u2
-        nx_, ny_, nz_ = s * np.cos(ps), s * np.sin(ps), c
-        x = _wrap(sph["cx"] + sph["radius"] * nx_, g.lx)
-        y = _wrap(sph["cy"] + sph["radius"] * ny_, g.ly)
-        z = sph["cz"] + sph["radius"] * nz_
-        sig = np.sqrt((C.K_B * sph["T_K"]) / C.M_CU)
-        u3, u4 = uniforms(ids, step, TAG_SRC1, seed)
-        rr = np.sqrt(-2.0 * np.log(1.0 - u3))
-        g1, g2 = rr * np.cos(C.TWO_PI * u4), rr * np.sin(C.TWO_PI * u4)
-        u5, u6 = uniforms(ids, step, TAG_SRC2, seed)
-        g3 = np.sqrt(-2.0 * np.log(1.0 - u5)) * np.cos(C.TWO_PI * u6)
-        vx, vy, vz = sig * g1, sig * g2, sig * g3
-        vn = (vx * nx_ + vy * ny_) + vz * nz_
-        inward = vn < 0.0
-        t = 2.0 * vn
-        vx = np.where(inward, vx - t * nx_, vx)
-        vy = np.where(inward, vy - t * ny_, vy)
-        vz = np.where(inward, vz - t * nz_, vz)
-        new[C.NEUTRAL].append((x, y, z, vx, vy, vz, ids))
 
     state.next_id = nid
     return new, n_fn

@@ -1,0 +1,561 @@
+// Field solve of the PIC step: right-hand side from the int64 node charge,
+// vertex-centred geometric multigrid for the 7-point discretisation of
+// Poisson's equation (Eq. 1) with Dirichlet or Neumann z faces and periodic
+// x, y, and E = -grad(phi) at the nodes.
+//
+// All these kernels stream node arrays: they are HBM-bound (a few FLOP per
+// byte), so they are written for coalesced 64-lane access along x and use no
+// matrix cores.  The red-black Gauss-Seidel smoother is generic in the
+// precision (FP64, or FP32 for the correction solve of the mixed form).
+#include "pic_ctx.h"
+
+namespace pic {
+namespace {
+
+constexpr int kRedBlocks = 1024;  // fixed reduction grid: deterministic sums
+constexpr int kThreads = 256;
+
+struct LevelC {
+  int nx, ny, nz, k0, k1, bc_lo, bc_hi;
+  long long nxy;
+  double h2;
+};
+
+LevelC level_c(const pic_ctx* c, int l) {
+  const Level& L = c->lev[l];
+  LevelC r;
+  r.nx = L.nx; r.ny = L.ny; r.nz = L.nz;
+  r.bc_lo = c->cfg.bc_lo; r.bc_hi = c->cfg.bc_hi;
+  r.k0 = r.bc_lo == PIC_BC_DIRICHLET ? 1 : 0;
+  r.k1 = r.bc_hi == PIC_BC_DIRICHLET ? L.nz - 1 : L.nz;
+  r.nxy = (long long)L.nx * L.ny;
+  r.h2 = L.h2;
+  return r;
+}
+
+// Sum of the six neighbours of node (i, j, k) with the mirror ghost on a
+// Neumann face.
+template <typename T>
+__device__ __forceinline__ T nb_sum(const T* u, const LevelC& L, int i, int j,
+                                    int k) {
+  const long long row = ((long long)k * L.ny + j) * L.nx;
+  const int im = i ? i - 1 : L.nx - 1, ip = i + 1 < L.nx ? i + 1 : 0;
+  const int jm = j ? j - 1 : L.ny - 1, jp = j + 1 < L.ny ? j + 1 : 0;
+  const long long rjm = ((long long)k * L.ny + jm) * L.nx;
+  const long long rjp = ((long long)k * L.ny + jp) * L.nx;
+  T s = u[row + im] + u[row + ip];
+  s = s + (u[rjm + i] + u[rjp + i]);
+  T zs;
+  if (k == 0)
+    zs = T(2) * u[row + L.nxy + i];
+  else if (k == L.nz)
+    zs = T(2) * u[row - L.nxy + i];
+  else
+    zs = u[row - L.nxy + i] + u[row + L.nxy + i];
+  return s + zs;
+}
+
+// ---- right-hand side --------------------------------------------------------
+// b = acc * c_rho (a Neumann face node owns half a cell: x2) or
+// b = rho * dx^2/eps0 (caller density), plus the Neumann data of the z
+// faces; phi gets the Dirichlet face values.  Block partials of sum(b^2)
+// and of the integer charge.
+__global__ void k_rhs(const long long* __restrict__ acc,
+                      const double* __restrict__ rho, double* __restrict__ b,
+                      double* __restrict__ phi, LevelC L, double dx,
+                      double scale, int from_rho, int field_solve, double v_lo,
+                      double v_hi, double* __restrict__ part,
+                      long long* __restrict__ qpart) {
+  __shared__ double sb[kThreads];
+  __shared__ long long sq[kThreads];
+  double s2 = 0.0;
+  long long sqs = 0;
+  const long long n = L.nxy * (L.nz + 1);
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+       idx < n; idx += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(idx / L.nxy);
+    double v = 0.0;
+    if (from_rho) {
+      v = rho[idx] * scale;
+    } else {
+      const long long a = acc[idx];
+      sqs += a;
+      if (field_solve) v = (double)a * scale;
+    }
+    bool unknown = true;
+    if (k == 0) {
+      if (L.bc_lo == PIC_BC_DIRICHLET) {
+        unknown = false;
+        phi[idx] = v_lo;
+      } else {
+        if (!from_rho) v = v * 2.0;
+        v = v - (2.0 * dx) * v_lo;
+      }
+    }
+    if (k == L.nz) {
+      if (L.bc_hi == PIC_BC_DIRICHLET) {
+        unknown = false;
+        phi[idx] = v_hi;
+      } else {
+        if (!from_rho) v = v * 2.0;
+        v = v + (2.0 * dx) * v_hi;
+      }
+    }
+    if (!unknown) v = 0.0;
+    // The Dirichlet face values sit in phi's face planes, where the stencil
+    // reads them, so they stay out of the stored right-hand side; ||b|| is
+    // the norm of the system with them moved to the right (the relative
+    // residual's denominator).
+    b[idx] = v;
+    double vb = v;
+    if (k == 1 && L.bc_lo == PIC_BC_DIRICHLET) vb = vb + v_lo;
+    if (k == L.nz - 1 && L.bc_hi == PIC_BC_DIRICHLET) vb = vb + v_hi;
+    s2 = s2 + vb * vb;
+  }
+  sb[threadIdx.x] = s2;
+  sq[threadIdx.x] = sqs;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      sb[threadIdx.x] = sb[threadIdx.x] + sb[threadIdx.x + o];
+      sq[threadIdx.x] += sq[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = sb[0];
+    qpart[blockIdx.x] = sq[0];
+  }
+}
+
+// Fixed-tree sum of the block partials.  mode 0: ||b|| (and the integer
+// charge); mode 1: residual check after a V-cycle (counts the cycle, sets
+// done when converged); mode 2: initial residual check of the warm start;
+// mode 3: field energy.
+__global__ void k_final(const double* __restrict__ part,
+                        const long long* __restrict__ qpart, int n,
+                        Counters* dc, int mode, double tol) {
+  __shared__ double s[1024];
+  __shared__ long long q[1024];
+  if ((mode == 1) && dc->done) return;
+  double a = 0.0;
+  long long qa = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    a = a + part[i];
+    if (mode == 0) qa += qpart[i];
+  }
+  s[threadIdx.x] = a;
+  q[threadIdx.x] = qa;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s[threadIdx.x] = s[threadIdx.x] + s[threadIdx.x + o];
+      q[threadIdx.x] += q[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x) return;
+  if (mode == 0) {
+    dc->b_norm = sqrt(s[0]);
+    dc->total_charge = q[0];
+    dc->done = 0;
+    dc->vcycles = 0;
+    dc->rel_res = 1.0;
+  } else if (mode == 1 || mode == 2) {
+    if (mode == 1) dc->vcycles += 1;
+    const double bn = dc->b_norm;
+    const double rr = bn > 0.0 ? sqrt(s[0]) / bn : 0.0;
+    dc->rel_res = rr;
+    if (!(rr == rr)) {
+      dc->err |= kErrNonFinite;
+      dc->done = 1;
+    } else if (rr <= tol) {
+      dc->done = 1;
+    }
+  } else if (mode == 3) {
+    dc->field_energy = 0.5 * s[0];
+  }
+}
+
+// Residual r = f - A u / h2 on level 0 (FP64): block partials of sum(r^2).
+// With rf != nullptr (mixed form) also writes r in FP32 as the right-hand
+// side of the correction solve and zeroes the FP32 correction.
+__global__ void k_residual(const double* __restrict__ u,
+                           const double* __restrict__ f, LevelC L,
+                           double* __restrict__ part, const Counters* dc,
+                           float* __restrict__ rf, float* __restrict__ ef) {
+  __shared__ double sb[kThreads];
+  if (dc->done) return;
+  double s2 = 0.0;
+  const long long nu = L.nxy * (L.k1 - L.k0 + 1);
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nu;
+       t += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(t % L.nx);
+    const long long r = t / L.nx;
+    const int j = (int)(r % L.ny);
+    const int k = L.k0 + (int)(r / L.ny);
+    const long long idx = ((long long)k * L.ny + j) * L.nx + i;
+    const double au = 6.0 * u[idx] - nb_sum(u, L, i, j, k);
+    const double res = f[idx] - au;
+    s2 = s2 + res * res;
+    if (rf) {
+      rf[idx] = (float)res;
+      ef[idx] = 0.0f;
+    }
+  }
+  sb[threadIdx.x] = s2;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sb[threadIdx.x] = sb[threadIdx.x] + sb[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sb[0];
+}
+
+// One colour of a red-black Gauss-Seidel sweep: nodes with
+// (i + j + k) % 2 == color get u = (neighbours + h2 f) / 6.
+template <typename T>
+__global__ void k_rbgs(T* __restrict__ u, const T* __restrict__ f, LevelC L,
+                       int color, const Counters* dc) {
+  if (dc->done) return;
+  const int half = L.nx >> 1;
+  const long long nt = (long long)half * L.ny * (L.k1 - L.k0 + 1);
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int m = (int)(t % half);
+  const long long r = t / half;
+  const int j = (int)(r % L.ny);
+  const int k = L.k0 + (int)(r / L.ny);
+  const int i = 2 * m + ((color + j + k) & 1);
+  const long long idx = ((long long)k * L.ny + j) * L.nx + i;
+  const T h2 = (T)L.h2;
+  u[idx] = (nb_sum(u, L, i, j, k) + h2 * f[idx]) * (T(1) / T(6));
+}
+
+// Full-weighting restriction of the fine residual to the coarse right-hand
+// side; the coarse correction starts at zero.
+template <typename T>
+__global__ void k_restrict(const T* __restrict__ uf, const T* __restrict__ ff,
+                           T* __restrict__ uc, T* __restrict__ fc, LevelC F,
+                           LevelC Cc, const Counters* dc) {
+  if (dc->done) return;
+  const long long nt = Cc.nxy * (Cc.nz + 1);
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int ic = (int)(t % Cc.nx);
+  const long long r = t / Cc.nx;
+  const int jc = (int)(r % Cc.ny);
+  const int kc = (int)(r / Cc.ny);
+  uc[t] = T(0);
+  if (kc < Cc.k0 || kc > Cc.k1) {
+    fc[t] = T(0);
+    return;
+  }
+  const T inv_h2 = T(1) / (T)F.h2;
+  T acc = T(0);
+  for (int dk = -1; dk <= 1; ++dk) {
+    int kf = 2 * kc + dk;
+    if (kf < 0) kf = 1;                 // Neumann mirror
+    if (kf > F.nz) kf = F.nz - 1;
+    const T wz = dk ? T(1) : T(2);
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int jf = wrap_index(2 * jc + dj, F.ny);
+      const T wy = dj ? T(1) : T(2);
+      for (int di = -1; di <= 1; ++di) {
+        const int i_f = wrap_index(2 * ic + di, F.nx);
+        const T wx = di ? T(1) : T(2);
+        const long long fi = ((long long)kf * F.ny + jf) * F.nx + i_f;
+        const T res = ff[fi] - (T(6) * uf[fi] - nb_sum(uf, F, i_f, jf, kf)) * inv_h2;
+        acc = acc + (wx * wy * wz) * res;
+      }
+    }
+  }
+  fc[t] = acc * T(1.0 / 64.0);
+}
+
+// Trilinear prolongation of the coarse correction, added to the fine
+// unknowns.
+template <typename T>
+__global__ void k_prolong(T* __restrict__ uf, const T* __restrict__ uc,
+                          LevelC F, LevelC Cc, const Counters* dc) {
+  if (dc->done) return;
+  const long long nt = F.nxy * (F.k1 - F.k0 + 1);
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const int i = (int)(t % F.nx);
+  const long long r = t / F.nx;
+  const int j = (int)(r % F.ny);
+  const int k = F.k0 + (int)(r / F.ny);
+  int ia[2], ja[2], ka[2];
+  T wa[2], wb[2], wc[2];
+  int na, nb, nc;
+  if (i & 1) { ia[0] = i >> 1; ia[1] = wrap_index((i >> 1) + 1, Cc.nx); wa[0] = wa[1] = T(0.5); na = 2; }
+  else { ia[0] = i >> 1; wa[0] = T(1); na = 1; }
+  if (j & 1) { ja[0] = j >> 1; ja[1] = wrap_index((j >> 1) + 1, Cc.ny); wb[0] = wb[1] = T(0.5); nb = 2; }
+  else { ja[0] = j >> 1; wb[0] = T(1); nb = 1; }
+  if (k & 1) { ka[0] = k >> 1; ka[1] = (k >> 1) + 1; wc[0] = wc[1] = T(0.5); nc = 2; }
+  else { ka[0] = k >> 1; wc[0] = T(1); nc = 1; }
+  T s = T(0);
+  for (int c3 = 0; c3 < nc; ++c3)
+    for (int b3 = 0; b3 < nb; ++b3)
+      for (int a3 = 0; a3 < na; ++a3)
+        s = s + (wa[a3] * wb[b3] * wc[c3]) *
+                    uc[((long long)ka[c3] * Cc.ny + ja[b3]) * Cc.nx + ia[a3]];
+  const long long idx = ((long long)k * F.ny + j) * F.nx + i;
+  uf[idx] = uf[idx] + s;
+}
+
+// Exact solve of a 1x1xN coarsest level (the x, y neighbours are the node
+// itself): tridiagonal 2u - u_{k-1} - u_{k+1} = h2 f, Thomas algorithm.
+template <typename T>
+__global__ void k_coarse_line(T* __restrict__ u, const T* __restrict__ f,
+                              LevelC L, const Counters* dc, T* __restrict__ w) {
+  if (dc->done || threadIdx.x || blockIdx.x) return;
+  const int m = L.k1 - L.k0 + 1;
+  T* cp = w;
+  T* dp = w + m;
+  for (int r = 0; r < m; ++r) {
+    const int k = L.k0 + r;
+    T rhs = (T)L.h2 * f[k];
+    T lo = (k == 0 || r == 0) ? T(0) : T(-1);
+    T up = (k == L.nz || r == m - 1) ? T(0) : T(-1);
+    if (k == 0) up = T(-2);
+    if (k == L.nz) lo = T(-2);
+    if (r == 0 && k > 0) rhs = rhs + u[k - 1];        // Dirichlet data
+    if (r == m - 1 && k < L.nz) rhs = rhs + u[k + 1];
+    if (r == 0) {
+      cp[0] = up / T(2);
+      dp[0] = rhs / T(2);
+    } else {
+      const T den = T(2) - lo * cp[r - 1];
+      cp[r] = up / den;
+      dp[r] = (rhs - lo * dp[r - 1]) / den;
+    }
+  }
+  T x = dp[m - 1];
+  u[L.k0 + m - 1] = x;
+  for (int r = m - 2; r >= 0; --r) {
+    x = dp[r] - cp[r] * x;
+    u[L.k0 + r] = x;
+  }
+}
+
+// Coarsest level wider than one node: red-black sweeps in one workgroup.
+template <typename T>
+__global__ void k_coarse_sweeps(T* __restrict__ u, const T* __restrict__ f,
+                                LevelC L, int sweeps, const Counters* dc) {
+  if (dc->done) return;
+  const int half = L.nx >> 1;
+  const long long nt = (long long)half * L.ny * (L.k1 - L.k0 + 1);
+  const T h2 = (T)L.h2;
+  for (int s = 0; s < sweeps; ++s) {
+    for (int color = 0; color < 2; ++color) {
+      for (long long t = threadIdx.x; t < nt; t += blockDim.x) {
+        const int m = (int)(t % half);
+        const long long r = t / half;
+        const int j = (int)(r % L.ny);
+        const int k = L.k0 + (int)(r / L.ny);
+        const int i = 2 * m + ((color + j + k) & 1);
+        const long long idx = ((long long)k * L.ny + j) * L.nx + i;
+        u[idx] = (nb_sum(u, L, i, j, k) + h2 * f[idx]) * (T(1) / T(6));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// u += e on the level-0 unknowns (mixed form: FP64 correction accumulation).
+__global__ void k_correct(double* __restrict__ u, const float* __restrict__ e,
+                          LevelC L, const Counters* dc) {
+  if (dc->done) return;
+  const long long nu = L.nxy * (L.k1 - L.k0 + 1);
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nu) return;
+  const long long idx = t + (long long)L.k0 * L.nxy;
+  u[idx] = u[idx] + (double)e[idx];
+}
+
+// E = -grad(phi): central differences in x, y and inside z; second-order
+// one-sided on the z faces.  Writes 4 values per node (x, y, z, 0) so a
+// node is one aligned 32-byte (FP64) or 16-byte (FP32) load in the gather.
+// Block partials of sum(q phi) for the field energy.
+template <typename TE>
+__global__ void k_efield(const double* __restrict__ phi,
+                         const long long* __restrict__ acc,
+                         TE* __restrict__ E, LevelC L, double h,
+                         double q_unit, double* __restrict__ part) {
+  __shared__ double sb[kThreads];
+  double s = 0.0;
+  const long long n = L.nxy * (L.nz + 1);
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+       idx < n; idx += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % L.nx);
+    const long long r = idx / L.nx;
+    const int j = (int)(r % L.ny);
+    const int k = (int)(r / L.ny);
+    const long long row = idx - i;
+    const int im = i ? i - 1 : L.nx - 1, ip = i + 1 < L.nx ? i + 1 : 0;
+    const int jm = j ? j - 1 : L.ny - 1, jp = j + 1 < L.ny ? j + 1 : 0;
+    const long long base = (long long)k * L.nxy;
+    const double ex = (phi[row + im] - phi[row + ip]) * h;
+    const double ey = (phi[base + (long long)jm * L.nx + i] -
+                       phi[base + (long long)jp * L.nx + i]) * h;
+    double ez;
+    if (k == 0)
+      ez = ((3.0 * phi[idx] - 4.0 * phi[idx + L.nxy]) + phi[idx + 2 * L.nxy]) * h;
+    else if (k == L.nz)
+      ez = ((-3.0 * phi[idx] + 4.0 * phi[idx - L.nxy]) - phi[idx - 2 * L.nxy]) * h;
+    else
+      ez = (phi[idx - L.nxy] - phi[idx + L.nxy]) * h;
+    E[4 * idx + 0] = (TE)ex;
+    E[4 * idx + 1] = (TE)ey;
+    E[4 * idx + 2] = (TE)ez;
+    E[4 * idx + 3] = (TE)0;
+    s = s + ((double)acc[idx] * q_unit) * phi[idx];
+  }
+  sb[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kThreads / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sb[threadIdx.x] = sb[threadIdx.x] + sb[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sb[0];
+}
+
+inline unsigned nblocks(long long n, int t = kThreads) {
+  return (unsigned)((n + t - 1) / t);
+}
+
+template <typename T>
+T* lev_u(Level& L);
+template <>
+double* lev_u<double>(Level& L) { return L.u; }
+template <>
+float* lev_u<float>(Level& L) { return L.uf; }
+template <typename T>
+T* lev_f(Level& L);
+template <>
+double* lev_f<double>(Level& L) { return L.f; }
+template <>
+float* lev_f<float>(Level& L) { return L.ff; }
+
+// One V(nu_pre, nu_post) cycle from level l down.  Level 0 of an FP32
+// cycle is the correction equation of the mixed form.
+template <typename T>
+void vcycle(pic_ctx* c, int l) {
+  hipStream_t st = c->stream;
+  Level& L = c->lev[l];
+  LevelC Lc = level_c(c, l);
+  T* u = lev_u<T>(L);
+  T* f = lev_f<T>(L);
+  if (l == c->nlev - 1) {
+    if (L.nx == 1 && L.ny == 1) {
+      k_coarse_line<T><<<1, 1, 0, st>>>(u, f, Lc, c->dc,
+                                        reinterpret_cast<T*>(c->partials));
+    } else {
+      k_coarse_sweeps<T><<<1, 1024, 0, st>>>(u, f, Lc, c->cfg.coarse_sweeps,
+                                             c->dc);
+    }
+    return;
+  }
+  const long long nhalf = (long long)(L.nx / 2) * L.ny * (Lc.k1 - Lc.k0 + 1);
+  for (int s = 0; s < c->cfg.nu_pre; ++s)
+    for (int color = 0; color < 2; ++color)
+      k_rbgs<T><<<nblocks(nhalf), kThreads, 0, st>>>(u, f, Lc, color, c->dc);
+  Level& N = c->lev[l + 1];
+  LevelC Nc = level_c(c, l + 1);
+  k_restrict<T><<<nblocks(N.nnodes), kThreads, 0, st>>>(
+      u, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
+  vcycle<T>(c, l + 1);
+  k_prolong<T><<<nblocks(Lc.nxy * (Lc.k1 - Lc.k0 + 1)), kThreads, 0, st>>>(
+      u, lev_u<T>(N), Lc, Nc, c->dc);
+  for (int s = 0; s < c->cfg.nu_post; ++s)
+    for (int color = 0; color < 2; ++color)
+      k_rbgs<T><<<nblocks(nhalf), kThreads, 0, st>>>(u, f, Lc, color, c->dc);
+}
+
+}  // namespace
+
+void field_rhs(pic_ctx* c, const double* rho) {
+  LevelC L0 = level_c(c, 0);
+  const double dx = c->g.dx;
+  double scale;
+  if (rho) {
+    scale = (dx * dx) / kEps0;
+  } else {
+    scale = (((double)c->cfg.w_sp * kE) * kQScale) / (kEps0 * dx);
+  }
+  k_rhs<<<kRedBlocks, kThreads, 0, c->stream>>>(
+      c->acc, rho, c->lev[0].f, c->lev[0].u, L0, dx, scale, rho ? 1 : 0,
+      c->cfg.field_solve, c->cfg.v_lo, c->cfg.v_hi, c->partials,
+      c->qpartials);
+  k_final<<<1, 1024, 0, c->stream>>>(c->partials, c->qpartials, kRedBlocks,
+                                     c->dc, 0, c->cfg.rel_tol);
+}
+
+// Solve A phi = b on level 0 (phi holds the warm start, or zero).  One
+// synchronisation per batch of V-cycles; the batch size follows the last
+// solve so a warm-started step normally syncs once.
+void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
+  hipStream_t st = c->stream;
+  Level& L0 = c->lev[0];
+  LevelC Lc = level_c(c, 0);
+  if (!warm) {
+    const long long nu = Lc.nxy * (Lc.k1 - Lc.k0 + 1);
+    hipMemsetAsync(L0.u + (long long)Lc.k0 * Lc.nxy, 0, nu * sizeof(double),
+                   st);
+  }
+  const long long nu = Lc.nxy * (Lc.k1 - Lc.k0 + 1);
+  float* rf = c->mixed ? L0.ff : nullptr;
+  float* ef = c->mixed ? L0.uf : nullptr;
+  // Initial check of the warm start.
+  k_residual<<<kRedBlocks, kThreads, 0, st>>>(L0.u, L0.f, Lc, c->partials,
+                                              c->dc, rf, ef);
+  k_final<<<1, 1024, 0, st>>>(c->partials, c->qpartials, kRedBlocks, c->dc, 2,
+                              c->cfg.rel_tol);
+  int launched = 0;
+  int batch = c->last_vcycles > 0 ? c->last_vcycles : 4;
+  *status = PIC_OK;
+  while (true) {
+    for (int b = 0; b < batch && launched < c->cfg.max_vcycles; ++b, ++launched) {
+      if (c->mixed) {
+        vcycle<float>(c, 0);
+        k_correct<<<nblocks(nu), kThreads, 0, st>>>(L0.u, L0.uf, Lc, c->dc);
+      } else {
+        vcycle<double>(c, 0);
+      }
+      k_residual<<<kRedBlocks, kThreads, 0, st>>>(L0.u, L0.f, Lc, c->partials,
+                                                  c->dc, rf, ef);
+      k_final<<<1, 1024, 0, st>>>(c->partials, c->qpartials, kRedBlocks,
+                                  c->dc, 1, c->cfg.rel_tol);
+    }
+    hipMemcpyAsync(&c->hc.vcycles, &c->dc->vcycles, 4 * sizeof(int) + 2 * sizeof(double),
+                   hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+    if (c->hc.done || launched >= c->cfg.max_vcycles) break;
+    batch = 1;
+  }
+  info->vcycles = c->hc.vcycles;
+  info->converged = c->hc.done && !(c->hc.err & kErrNonFinite) ? 1 : 0;
+  info->rel_residual = c->hc.rel_res;
+  info->b_norm = c->hc.b_norm;
+  c->last_vcycles = c->hc.vcycles > 0 ? c->hc.vcycles : 1;
+  if (!info->converged) *status = PIC_ERR_NOCONV;
+}
+
+void field_efield(pic_ctx* c) {
+  LevelC L0 = level_c(c, 0);
+  const double h = 0.5 * c->g.inv_dx;
+  const double q_unit = ((double)c->cfg.w_sp * kE) * kQScale;
+  if (c->mixed)
+    k_efield<float><<<kRedBlocks, kThreads, 0, c->stream>>>(
+        c->lev[0].u, c->acc, reinterpret_cast<float*>(c->E), L0, h, q_unit,
+        c->partials);
+  else
+    k_efield<double><<<kRedBlocks, kThreads, 0, c->stream>>>(
+        c->lev[0].u, c->acc, c->E, L0, h, q_unit, c->partials);
+  k_final<<<1, 1024, 0, c->stream>>>(c->partials, c->qpartials, kRedBlocks,
+                                     c->dc, 3, 0.0);
+}
+
+}  // namespace pic

@@ -1,0 +1,578 @@
+// C ABI of the PIC-MCC library: context set-up on a caller-provided
+// workspace, the step driver (deposit -> field -> sources/push/collisions ->
+// binning, one stream, one host synchronisation at the end of a step plus
+// one per batch of multigrid cycles), and state access.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "pic_ctx.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+struct Carver {
+  char* base;
+  size_t off;
+  template <typename T>
+  T* take(long long count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (size_t)(count > 0 ? count : 1) * sizeof(T);
+    return p;
+  }
+};
+
+pic_status set_err(pic_ctx* c, pic_status s, const char* msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+bool hip_ok(pic_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  if (c) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+  }
+  return false;
+}
+
+long long pow2_at_least(long long n) {
+  long long p = 1;
+  while (p < n) p <<= 1;
+  return p;
+}
+
+// Multigrid hierarchy: halve every axis while all stay even, the coarse
+// level keeps at least two z cells, and x, y either stay >= 2 or both reach
+// one node (the coarsest 1x1xN level is then solved exactly in z).
+int plan_levels(const pic_config* cfg, int dims[16][3]) {
+  int nx = cfg->nx, ny = cfg->ny, nz = cfg->nz;
+  int n = 0;
+  dims[n][0] = nx; dims[n][1] = ny; dims[n][2] = nz;
+  ++n;
+  const int limit = cfg->mg_levels > 0 ? std::min(cfg->mg_levels, 16) : 16;
+  while (n < limit) {
+    if ((nx & 1) || (ny & 1) || (nz & 1)) break;
+    const int cx = nx / 2, cy = ny / 2, cz = nz / 2;
+    if (cz < 2) break;
+    const bool both_one = cx == 1 && cy == 1;
+    const bool both_ok = cx >= 2 && cy >= 2;
+    if (!both_one && !both_ok) break;
+    if (!both_one && ((cx & 1) || (cy & 1))) {
+      // Still a valid coarse level for red-black sweeps only if even.
+      break;
+    }
+    nx = cx; ny = cy; nz = cz;
+    dims[n][0] = nx; dims[n][1] = ny; dims[n][2] = nz;
+    ++n;
+    if (both_one) break;
+  }
+  return n;
+}
+
+pic_status validate(const pic_config* c) {
+  if (!c) return PIC_ERR_ARG;
+  if (c->nx < 2 || c->ny < 2 || c->nz < 2 || (c->nx & 1) || (c->ny & 1) ||
+      (c->nz & 1))
+    return PIC_ERR_ARG;
+  if (!(c->dx > 0.0) || !std::isfinite(c->dx)) return PIC_ERR_ARG;
+  if ((c->bc_lo != PIC_BC_DIRICHLET && c->bc_lo != PIC_BC_NEUMANN) ||
+      (c->bc_hi != PIC_BC_DIRICHLET && c->bc_hi != PIC_BC_NEUMANN))
+    return PIC_ERR_ARG;
+  if (c->bc_lo == PIC_BC_NEUMANN && c->bc_hi == PIC_BC_NEUMANN)
+    return PIC_ERR_ARG;
+  if (c->precision != PIC_FP64 && c->precision != PIC_MIXED) return PIC_ERR_ARG;
+  if (!(c->rel_tol > 0.0) || c->max_vcycles < 1 || c->nu_pre < 0 ||
+      c->nu_post < 0 || c->nu_pre + c->nu_post < 1 || c->coarse_sweeps < 1)
+    return PIC_ERR_ARG;
+  if (c->sort_every != 1) return PIC_ERR_ARG;
+  if (c->w_sp < 1) return PIC_ERR_ARG;
+  for (int s = 0; s < 3; ++s)
+    if (c->capacity[s] < 0 || c->capacity[s] > 0xFFFFFFF0ll) return PIC_ERR_ARG;
+  if (c->queue_capacity < 0 || c->max_events < 1) return PIC_ERR_ARG;
+  const long long nodes = (long long)c->nx * c->ny * (c->nz + 1);
+  if (nodes > 0x7FFFFFFFll) return PIC_ERR_ARG;
+  return PIC_OK;
+}
+
+// Lay out every device array of a context in the workspace (base == nullptr:
+// size only).
+size_t carve(pic_ctx* c, char* base) {
+  Carver cv{base, 0};
+  const pic_config& f = c->cfg;
+  const bool mixed = f.precision == PIC_MIXED;
+  for (int s = 0; s < 3; ++s) {
+    const long long cap = f.capacity[s];
+    for (int b = 0; b < 2; ++b) {
+      if (!mixed) {
+        Parts& p = c->P[s][b];
+        p.x = cv.take<double>(cap); p.y = cv.take<double>(cap);
+        p.z = cv.take<double>(cap); p.vx = cv.take<double>(cap);
+        p.vy = cv.take<double>(cap); p.vz = cv.take<double>(cap);
+        p.id = cv.take<uint64_t>(cap);
+      } else {
+        PartsM& p = c->PM[s][b];
+        p.cell = cv.take<uint32_t>(cap);
+        p.ox = cv.take<float>(cap); p.oy = cv.take<float>(cap);
+        p.oz = cv.take<float>(cap); p.vx = cv.take<float>(cap);
+        p.vy = cv.take<float>(cap); p.vz = cv.take<float>(cap);
+        p.id = cv.take<uint64_t>(cap);
+      }
+    }
+    c->key[s] = cv.take<uint32_t>(cap);
+    c->tile_start[s] = cv.take<uint32_t>(c->ntiles + 1);
+  }
+  c->tile_cursor = cv.take<uint32_t>(c->ntiles + 1);
+  const long long nsb = (c->ntiles + 1 + 1023) / 1024;
+  c->scan_block = cv.take<uint32_t>(2 * nsb + 2);
+  c->acc = cv.take<long long>(c->nnodes);
+  c->E = reinterpret_cast<double*>(
+      cv.take<char>(4 * c->nnodes * (long long)(mixed ? 4 : 8)));
+  for (int l = 0; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    L.u = L.f = nullptr;
+    L.uf = L.ff = nullptr;
+    if (l == 0 || !mixed) {
+      L.u = cv.take<double>(L.nnodes);
+      L.f = cv.take<double>(L.nnodes);
+    }
+    if (mixed) {
+      L.uf = cv.take<float>(L.nnodes);
+      L.ff = cv.take<float>(L.nnodes);
+    }
+  }
+  c->partials = cv.take<double>(c->npartials);
+  c->qpartials = cv.take<long long>(1024);
+  c->ncount = cv.take<int>(c->ncells);
+  c->flag = cv.take<uint8_t>(c->ncells);
+  c->cand = cv.take<uint32_t>(f.capacity[0]);
+  c->ev = cv.take<Rec>(c->ev_cap_p2);
+  c->nc = cv.take<Rec>(c->ev_cap_p2);
+  c->ok = cv.take<Rec>(c->ev_cap_p2);
+  c->ab_rec = cv.take<Rec>(c->ev_cap_p2);
+  c->ab_raw_pos = cv.take<double>(3 * f.max_events);
+  c->ab_raw_vel = cv.take<double>(3 * f.max_events);
+  c->ab_species = cv.take<int32_t>(f.max_events);
+  c->ab_id = cv.take<uint64_t>(f.max_events);
+  c->ab_pos = cv.take<double>(3 * f.max_events);
+  c->ab_vel = cv.take<double>(3 * f.max_events);
+  c->q_pos = cv.take<double>(3 * f.queue_capacity);
+  c->q_vel = cv.take<double>(3 * f.queue_capacity);
+  c->fn_scan = cv.take<unsigned>(2 * c->g.nxy + 2);
+  c->dc = cv.take<Counters>(1);
+  return cv.off + kAlign;
+}
+
+void derive(pic_ctx* c) {
+  const pic_config& f = c->cfg;
+  c->mixed = f.precision == PIC_MIXED;
+  GridC& g = c->g;
+  g.nx = f.nx; g.ny = f.ny; g.nz = f.nz;
+  g.tnx = (f.nx + kTile - 1) / kTile;
+  g.tny = (f.ny + kTile - 1) / kTile;
+  g.tnz = (f.nz + kTile - 1) / kTile;
+  g.dx = f.dx;
+  g.inv_dx = 1.0 / f.dx;
+  g.lx = (double)f.nx * f.dx;
+  g.ly = (double)f.ny * f.dx;
+  g.nxy = (long long)f.nx * f.ny;
+  c->nnodes = g.nxy * (f.nz + 1);
+  c->ncells = g.nxy * f.nz;
+  c->ntiles = (long long)g.tnx * g.tny * g.tnz;
+  int dims[16][3];
+  c->nlev = plan_levels(&f, dims);
+  double h2 = 1.0;
+  for (int l = 0; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    L.nx = dims[l][0]; L.ny = dims[l][1]; L.nz = dims[l][2];
+    L.nnodes = (long long)L.nx * L.ny * (L.nz + 1);
+    L.h2 = h2;
+    h2 *= 4.0;
+  }
+  long long maxcap = std::max(f.capacity[0], std::max(f.capacity[1], f.capacity[2]));
+  c->npartials = (int)std::max<long long>(
+      {4096, maxcap / 256 + 16, 2ll * (f.nz + 2) + 16});
+  c->ev_cap_p2 = pow2_at_least(std::max<long long>(f.max_events, 2));
+}
+
+pic_status sync_counters(pic_ctx* c) {
+  if (!hip_ok(c, hipMemcpyAsync(&c->hc, c->dc, sizeof(Counters),
+                                hipMemcpyDeviceToHost, c->stream),
+              "counter readback"))
+    return PIC_ERR_HIP;
+  if (!hip_ok(c, hipStreamSynchronize(c->stream), "stream synchronise"))
+    return PIC_ERR_HIP;
+  return PIC_OK;
+}
+
+pic_status check_flags(pic_ctx* c) {
+  const unsigned e = c->hc.err;
+  if (!e) return PIC_OK;
+  hipMemsetAsync(&c->dc->err, 0, sizeof(unsigned), c->stream);
+  if (e & kErrNonFinite)
+    return set_err(c, PIC_ERR_NONFINITE, "non-finite or out-of-domain value");
+  if (e & kErrCapacity)
+    return set_err(c, PIC_ERR_CAPACITY, "particle capacity exceeded");
+  if (e & kErrEvents)
+    return set_err(c, PIC_ERR_CAPACITY,
+                   "per-step event list (max_events) exceeded");
+  return set_err(c, PIC_ERR_STATE, "device error flag");
+}
+
+__global__ void k_set_n(Counters* dc, int s, unsigned long long n) {
+  dc->n[s] = n;
+}
+
+__global__ void k_deinterleave_E(const char* __restrict__ E, int mixed,
+                                 double* __restrict__ out, long long n) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  for (int d = 0; d < 3; ++d) {
+    out[d * n + t] = mixed ? (double)reinterpret_cast<const float*>(E)[4 * t + d]
+                           : reinterpret_cast<const double*>(E)[4 * t + d];
+  }
+}
+
+void fill_diag(pic_ctx* c, pic_diag* d) {
+  if (!d) return;
+  const Counters& h = c->hc;
+  for (int s = 0; s < 3; ++s) {
+    d->counts[s] = c->n[s];
+    d->cathode[s] = (long long)h.cathode[s];
+    d->anode[s] = (long long)h.anode[s];
+    d->kinetic[s] = h.kinetic[s];
+  }
+  d->fn_emitted = (long long)h.fn_total;
+  d->candidates = (long long)h.n_cand;
+  d->elastic = (long long)h.n_elastic;
+  d->ionisations = (long long)h.n_ok;
+  d->starved = (long long)h.n_events - (long long)h.n_ok;
+  d->over_majorant = (long long)h.n_over;
+  d->near_threshold = (long long)h.n_near;
+  d->total_charge_units = h.total_charge;
+  d->field_energy = h.field_energy;
+  d->solve = c->last_solve;
+  d->step = c->step;
+  d->next_id = c->next_id;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pic_abi_version(void) { return PIC_ABI_VERSION; }
+
+const char* pic_last_error(const pic_ctx* c) {
+  return c ? c->err.c_str() : "null context";
+}
+
+pic_status pic_workspace_bytes(const pic_config* cfg, size_t* bytes) {
+  if (!bytes) return PIC_ERR_ARG;
+  const pic_status v = validate(cfg);
+  if (v != PIC_OK) return v;
+  pic_ctx* c = new (std::nothrow) pic_ctx();
+  if (!c) return PIC_ERR_STATE;
+  c->cfg = *cfg;
+  derive(c);
+  *bytes = carve(c, nullptr);
+  delete c;
+  return PIC_OK;
+}
+
+pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
+                    void* stream, pic_ctx** out) {
+  if (!out) return PIC_ERR_ARG;
+  *out = nullptr;
+  const pic_status v = validate(cfg);
+  if (v != PIC_OK) return v;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) % kAlign)) return PIC_ERR_ARG;
+  pic_ctx* c = new (std::nothrow) pic_ctx();
+  if (!c) return PIC_ERR_STATE;
+  c->cfg = *cfg;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  derive(c);
+  const size_t need = carve(c, nullptr);
+  if (bytes < need) {
+    delete c;
+    return PIC_ERR_ARG;
+  }
+  char* base = reinterpret_cast<char*>(
+      (reinterpret_cast<uintptr_t>(ws) + kAlign - 1) / kAlign * kAlign);
+  c->ws = reinterpret_cast<char*>(ws);
+  c->ws_bytes = bytes;
+  carve(c, base);
+  for (int s = 0; s < 3; ++s) {
+    c->cur[s] = 0;
+    c->n[s] = 0;
+  }
+  c->next_id = 0;
+  c->step = 0;
+  c->queue_used = 0;
+  c->last_vcycles = 0;
+  std::memset(&c->coll, 0, sizeof(c->coll));
+  std::memset(&c->src, 0, sizeof(c->src));
+  std::memset(&c->last_solve, 0, sizeof(c->last_solve));
+  std::memset(&c->hc, 0, sizeof(c->hc));
+  if (!hip_ok(c, hipMemsetAsync(ws, 0, bytes, c->stream), "workspace clear") ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "init synchronise")) {
+    delete c;
+    return PIC_ERR_HIP;
+  }
+  *out = c;
+  return PIC_OK;
+}
+
+void pic_destroy(pic_ctx* c) { delete c; }
+
+pic_status pic_set_collisions(pic_ctx* c, const pic_collisions* k) {
+  if (!c || !k) return PIC_ERR_ARG;
+  if (k->enabled) {
+    if (k->ion_model != PIC_ION_LOTZ && k->ion_model != PIC_ION_CONST)
+      return set_err(c, PIC_ERR_ARG, "unknown ionisation model");
+    if (!(k->sigma_el >= 0.0) || !(k->lotz_a >= 0.0) || !(k->ion_I_eV > 0.0) ||
+        !(k->sigma_ion_const >= 0.0) || !(k->E_max_eV > 0.0))
+      return set_err(c, PIC_ERR_ARG, "invalid collision parameters");
+  }
+  c->coll = *k;
+  return PIC_OK;
+}
+
+pic_status pic_set_sources(pic_ctx* c, const pic_sources* s) {
+  if (!c || !s) return PIC_ERR_ARG;
+  const double lx = c->g.lx, ly = c->g.ly, lmin = std::min(lx, ly);
+  const double lz = (double)c->g.nz * c->g.dx;
+  auto in_xy = [&](double x, double y) {
+    return x >= 0.0 && x < lx && y >= 0.0 && y < ly;
+  };
+  // Source particles must start inside the domain: centres inside, radii
+  // below one period (one wrap suffices), the sphere clear of both faces.
+  if ((s->disk_on && (s->disk_n_e < 0 || s->disk_n_n < 0 ||
+                      !(s->disk_radius >= 0.0) || !(s->disk_radius < lmin) ||
+                      !in_xy(s->disk_cx, s->disk_cy))) ||
+      (s->sphere_on &&
+       (s->sph_n < 0 || !(s->sph_radius >= 0.0) || !(s->sph_radius < lmin) ||
+        !in_xy(s->sph_cx, s->sph_cy) || !(s->sph_cz - s->sph_radius >= 0.0) ||
+        !((s->sph_cz + s->sph_radius) * c->g.inv_dx < (double)c->g.nz))) ||
+      (s->fn_on && !(s->fn_phi_w_eV > 0.0)))
+    return set_err(c, PIC_ERR_ARG, "invalid source parameters");
+  (void)lz;
+  c->src = *s;
+  return PIC_OK;
+}
+
+pic_status pic_inject(pic_ctx* c, int32_t species, int64_t n,
+                      const double* pos, const double* vel) {
+  if (!c || species < 0 || species > 2 || n < 0) return PIC_ERR_ARG;
+  if (n == 0) return PIC_OK;
+  if (!pos || !vel) return set_err(c, PIC_ERR_ARG, "null particle buffer");
+  if (c->queue_used + n > c->cfg.queue_capacity)
+    return set_err(c, PIC_ERR_CAPACITY, "injection queue full");
+  if (!parts_validate(c, pos, vel, n))
+    return set_err(c, PIC_ERR_ARG,
+                   "injected particle outside the domain or non-finite");
+  const long long off = c->queue_used;
+  // The queue keeps each call's SoA block contiguous: 3n values per array.
+  if (!hip_ok(c, hipMemcpyAsync(c->q_pos + 3 * off, pos, 3 * n * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream),
+              "inject copy") ||
+      !hip_ok(c, hipMemcpyAsync(c->q_vel + 3 * off, vel, 3 * n * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream),
+              "inject copy"))
+    return PIC_ERR_HIP;
+  c->queue.push_back(QueueCall{species, n, off});
+  c->queue_used += n;
+  return PIC_OK;
+}
+
+pic_status pic_deposit(pic_ctx* c) {
+  if (!c) return PIC_ERR_ARG;
+  if (c->mixed) return set_err(c, PIC_ERR_STATE, "mixed precision not built");
+  parts_deposit(c);
+  return hip_ok(c, hipGetLastError(), "deposit launch") ? PIC_OK : PIC_ERR_HIP;
+}
+
+pic_status pic_field(pic_ctx* c, pic_solve_info* info) {
+  if (!c) return PIC_ERR_ARG;
+  field_rhs(c, nullptr);
+  int st = PIC_OK;
+  pic_solve_info loc;
+  field_solve(c, true, &loc, &st);
+  c->last_solve = loc;
+  if (info) *info = loc;
+  field_efield(c);
+  if (!hip_ok(c, hipGetLastError(), "field launch")) return PIC_ERR_HIP;
+  if (st != PIC_OK)
+    return set_err(c, (pic_status)st, "Poisson solve did not converge");
+  return PIC_OK;
+}
+
+pic_status pic_set_phi(pic_ctx* c, const double* phi) {
+  if (!c || !phi) return PIC_ERR_ARG;
+  if (!hip_ok(c, hipMemcpyAsync(c->lev[0].u, phi, c->nnodes * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream),
+              "phi copy"))
+    return PIC_ERR_HIP;
+  field_efield(c);
+  return hip_ok(c, hipGetLastError(), "efield launch") ? PIC_OK : PIC_ERR_HIP;
+}
+
+pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
+                       pic_diag* diag) {
+  if (!c) return PIC_ERR_ARG;
+  if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(c, PIC_ERR_ARG, "dt");
+  if (c->mixed) return set_err(c, PIC_ERR_STATE, "mixed precision not built");
+  // Host-known additions must fit.
+  long long add[3] = {0, 0, 0};
+  for (const QueueCall& q : c->queue) add[q.species] += q.n;
+  const pic_sources& s = c->src;
+  if (s.disk_on) {
+    add[0] += s.disk_n_e;
+    add[1] += s.disk_n_n;
+  }
+  if (s.sphere_on) add[1] += s.sph_n;
+  for (int k = 0; k < 3; ++k)
+    if (c->n[k] + add[k] > c->cfg.capacity[k])
+      return set_err(c, PIC_ERR_CAPACITY, "sources exceed particle capacity");
+  const long long n_before[3] = {c->n[0], c->n[1], c->n[2]};
+  parts_sources(c, dt);
+  parts_push_collide(c, dt);
+  parts_bin(c);
+  if (!hip_ok(c, hipGetLastError(), "advance launch")) return PIC_ERR_HIP;
+  pic_status st = sync_counters(c);
+  if (st != PIC_OK) return st;
+  for (int k = 0; k < 3; ++k) c->n[k] = (long long)c->hc.sorted_n[k];
+  c->next_id = c->hc.next_id;
+  c->step += 1;
+  if (diag) {
+    fill_diag(c, diag);
+    for (int k = 0; k < 3; ++k) diag->emitted[k] = add[k];
+    diag->emitted[0] += (long long)c->hc.fn_total;
+    (void)n_before;
+  }
+  if (out) {
+    long long n = (long long)c->hc.n_ab;
+    if (n > c->cfg.max_events) n = c->cfg.max_events;
+    out->n = n;
+    out->species = c->ab_species;
+    out->id = c->ab_id;
+    out->pos = c->ab_pos;
+    out->vel = c->ab_vel;
+  }
+  return check_flags(c);
+}
+
+pic_status pic_step(pic_ctx* c, double dt, pic_absorbed* out, pic_diag* diag) {
+  if (!c) return PIC_ERR_ARG;
+  pic_status st = pic_deposit(c);
+  if (st != PIC_OK) return st;
+  st = pic_field(c, nullptr);
+  if (st != PIC_OK) return st;
+  return pic_advance(c, dt, out, diag);
+}
+
+pic_status poisson_solve(pic_ctx* c, const double* rho, double* phi,
+                         int32_t warm, pic_solve_info* info) {
+  if (!c || !rho || !phi) return PIC_ERR_ARG;
+  if (warm == PIC_WARM_GIVEN) {
+    if (!hip_ok(c, hipMemcpyAsync(c->lev[0].u, phi, c->nnodes * sizeof(double),
+                                  hipMemcpyDeviceToDevice, c->stream),
+                "phi copy"))
+      return PIC_ERR_HIP;
+  }
+  field_rhs(c, rho);
+  int st = PIC_OK;
+  pic_solve_info loc;
+  field_solve(c, warm == PIC_WARM_GIVEN, &loc, &st);
+  if (info) *info = loc;
+  if (!hip_ok(c, hipMemcpyAsync(phi, c->lev[0].u, c->nnodes * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream),
+              "phi copy") ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "synchronise"))
+    return PIC_ERR_HIP;
+  if (st != PIC_OK)
+    return set_err(c, (pic_status)st, "Poisson solve did not converge");
+  return PIC_OK;
+}
+
+pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
+                              const double* pos, const double* vel,
+                              const uint64_t* ids) {
+  if (!c || s < 0 || s > 2 || n < 0) return PIC_ERR_ARG;
+  if (n > c->cfg.capacity[s])
+    return set_err(c, PIC_ERR_CAPACITY, "load exceeds capacity");
+  if (n > 0 && (!pos || !vel || !ids)) return PIC_ERR_ARG;
+  if (c->mixed) return set_err(c, PIC_ERR_STATE, "mixed precision not built");
+  parts_load(c, s, n, pos, vel, ids);
+  c->n[s] = n;
+  k_set_n<<<1, 1, 0, c->stream>>>(c->dc, s, (unsigned long long)n);
+  parts_bin_species(c, s);
+  pic_status st = sync_counters(c);
+  if (st != PIC_OK) return st;
+  c->n[s] = (long long)c->hc.sorted_n[s];
+  if (c->hc.err) {
+    check_flags(c);
+    return set_err(c, PIC_ERR_ARG,
+                   "particles outside the domain or non-finite were dropped");
+  }
+  return PIC_OK;
+}
+
+pic_status pic_count(pic_ctx* c, int32_t s, int64_t* n) {
+  if (!c || s < 0 || s > 2 || !n) return PIC_ERR_ARG;
+  *n = c->n[s];
+  return PIC_OK;
+}
+
+pic_status pic_read_particles(pic_ctx* c, int32_t s, int64_t cap, double* pos,
+                              double* vel, uint64_t* ids, int64_t* n) {
+  if (!c || s < 0 || s > 2) return PIC_ERR_ARG;
+  if (n) *n = c->n[s];
+  if (cap < c->n[s]) return set_err(c, PIC_ERR_CAPACITY, "read buffer small");
+  if (c->n[s] > 0 && (!pos || !vel || !ids)) return PIC_ERR_ARG;
+  parts_read(c, s, c->n[s], pos, vel, ids);
+  if (!hip_ok(c, hipStreamSynchronize(c->stream), "read synchronise"))
+    return PIC_ERR_HIP;
+  return PIC_OK;
+}
+
+pic_status pic_read_fields(pic_ctx* c, int64_t* acc, double* phi, double* E3) {
+  if (!c) return PIC_ERR_ARG;
+  if (acc &&
+      !hip_ok(c, hipMemcpyAsync(acc, c->acc, c->nnodes * sizeof(long long),
+                                hipMemcpyDeviceToDevice, c->stream),
+              "acc copy"))
+    return PIC_ERR_HIP;
+  if (phi &&
+      !hip_ok(c, hipMemcpyAsync(phi, c->lev[0].u, c->nnodes * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream),
+              "phi copy"))
+    return PIC_ERR_HIP;
+  if (E3) {
+    const long long n = c->nnodes;
+    k_deinterleave_E<<<(unsigned)((n + 255) / 256), 256, 0, c->stream>>>(
+        reinterpret_cast<const char*>(c->E), c->mixed ? 1 : 0, E3, n);
+  }
+  if (!hip_ok(c, hipStreamSynchronize(c->stream), "read synchronise"))
+    return PIC_ERR_HIP;
+  return PIC_OK;
+}
+
+pic_status pic_set_clock(pic_ctx* c, int64_t step, uint64_t next_id) {
+  if (!c || step < 0) return PIC_ERR_ARG;
+  c->step = step;
+  c->next_id = next_id;
+  return PIC_OK;
+}
+
+pic_status pic_get_diag(pic_ctx* c, pic_diag* d) {
+  if (!c || !d) return PIC_ERR_ARG;
+  fill_diag(c, d);
+  return PIC_OK;
+}
+
+}  // extern "C"

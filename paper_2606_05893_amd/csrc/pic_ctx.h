@@ -1,0 +1,118 @@
+// Host-side context of the PIC-MCC library and the launchers each kernel
+// file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "pic.h"
+#include "pic_device.h"
+
+namespace pic {
+
+// One multigrid level: nx*ny*(nz+1) nodes with spacing 2^l dx.  Equations
+// on level l are scaled by dx^2: (6u - sum of neighbours) = h2 * f with
+// h2 = 4^l.
+struct Level {
+  int nx, ny, nz;
+  long long nnodes;
+  double h2;
+  double *u, *f;       // FP64 unknowns and right-hand side
+  float *uf, *ff;      // FP32 counterparts (mixed-precision V-cycles)
+};
+
+struct QueueCall {
+  int species;
+  long long n, offset;
+};
+
+}  // namespace pic
+
+struct pic_ctx {
+  pic_config cfg;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  pic::GridC g;
+  long long nnodes, ncells, ntiles;
+  bool mixed;
+
+  // Particles: two buffers per species (binning ping-pong).
+  pic::Parts P[3][2];
+  pic::PartsM PM[3][2];
+  int cur[3];
+  uint32_t* key[3];          // cell index of each particle, or kDead
+  uint32_t* tile_start[3];   // ntiles + 1 offsets of the binned order
+  uint32_t* tile_cursor;     // scatter cursors
+  uint32_t* scan_block;      // block sums of the tile scan
+
+  // Node fields.
+  long long* acc;            // int64 charge units
+  double* E;                 // FP64: 4 doubles per node; mixed: 4 floats
+  int nlev;
+  pic::Level lev[16];
+  double* partials;          // reduction partials
+  int npartials;
+  long long* qpartials;      // integer reduction partials
+
+  // Collisions and ionisation matching.
+  int* ncount;               // neutrals per cell
+  uint8_t* flag;             // cells holding ionisation events
+  uint32_t* cand;            // electron indices of null-collision candidates
+  pic::Rec *ev, *nc, *ok;    // events, neutral candidates, matched events
+  long long ev_cap_p2;       // power-of-two capacity of the record lists
+
+  // Cathode-absorbed list: raw (unsorted) and sorted outputs.
+  pic::Rec* ab_rec;
+  double *ab_raw_pos, *ab_raw_vel;
+  int32_t* ab_species;
+  uint64_t* ab_id;
+  double *ab_pos, *ab_vel;
+
+  // Injection queue and Fowler-Nordheim scratch.
+  double *q_pos, *q_vel;
+  unsigned* fn_scan;         // nx*ny + 1
+
+  pic::Counters* dc;         // device counters
+  pic::Counters hc;          // host copy after the last sync
+
+  // Host mirrors (exact after each synchronising call).
+  long long n[3];
+  unsigned long long next_id;
+  long long step;
+  pic_collisions coll;
+  pic_sources src;
+  std::vector<pic::QueueCall> queue;
+  long long queue_used;
+  int last_vcycles;
+  pic_solve_info last_solve;
+  std::string err;
+};
+
+namespace pic {
+
+// ---- field (k_field.hip) ---------------------------------------------------
+void field_rhs(pic_ctx* c, const double* rho_or_null);
+void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status);
+void field_efield(pic_ctx* c);
+void field_phi_to_level0(pic_ctx* c);
+
+// ---- particles (k_particles.hip) -------------------------------------------
+void parts_begin_step(pic_ctx* c);
+void parts_deposit(pic_ctx* c);
+void parts_sources(pic_ctx* c, double dt);
+void parts_push_collide(pic_ctx* c, double dt);
+void parts_bin(pic_ctx* c);
+void parts_bin_species(pic_ctx* c, int s);
+void parts_finish_step(pic_ctx* c);
+void parts_load(pic_ctx* c, int s, long long n, const double* pos,
+                const double* vel, const uint64_t* ids);
+void parts_read(pic_ctx* c, int s, long long n, double* pos, double* vel,
+                uint64_t* ids);
+void parts_keys(pic_ctx* c, int s);
+bool parts_validate(pic_ctx* c, const double* pos, const double* vel,
+                    long long n);
+
+}  // namespace pic

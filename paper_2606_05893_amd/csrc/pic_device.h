@@ -1,0 +1,163 @@
+// Device-side building blocks of the PIC-MCC kernels (gfx950).
+//
+// Everything here is written for 64-wide CDNA wavefronts.  Floating-point
+// code must be compiled with -ffp-contract=off: the charge weights, the
+// gather and the push are defined operation by operation (no fused
+// multiply-add) so that their results are reproducible bit for bit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+// CODATA 2022.
+constexpr double kE = 1.602176634e-19;       // elementary charge, C
+constexpr double kMe = 9.1093837139e-31;     // electron mass, kg
+constexpr double kEps0 = 8.8541878188e-12;   // vacuum permittivity, F/m
+constexpr double kKB = 1.380649e-23;         // Boltzmann constant, J/K
+constexpr double kAmu = 1.66053906892e-27;   // atomic mass constant, kg
+constexpr double kH = 6.62607015e-34;        // Planck constant, J s
+constexpr double kMcu = 63.546 * kAmu;       // Cu atom / Cu+ ion mass, kg
+constexpr double kTwoPi = 6.283185307179586;
+constexpr double kEuler = 2.718281828459045;
+constexpr double kPi = 3.141592653589793;
+
+// Cloud-in-cell weights are quantised to 13 bits per axis; a particle's
+// three-axis weight product is an integer of at most 2^39.
+constexpr int kQ = 8192;
+constexpr double kQScale = 1.0 / 549755813888.0;  // 2^-39
+
+constexpr uint32_t kDead = 0xFFFFFFFFu;           // key of a removed particle
+constexpr int kTile = 8;                           // deposit tile edge, cells
+
+// Philox tags (counter word 3) of the per-particle draws.
+enum : uint32_t {
+  kTagMcc0 = 0, kTagMcc1 = 1, kTagMcc2 = 2, kTagMcc3 = 3,
+  kTagSrc0 = 8, kTagSrc1 = 9, kTagSrc2 = 10, kTagFn = 12
+};
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// multiplications, key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ void philox10(uint32_t& c0, uint32_t& c1,
+                                         uint32_t& c2, uint32_t& c3,
+                                         uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+}
+
+// Two 53-bit uniforms in [0, 1) for (id, step, tag) under the run's seed.
+__device__ __forceinline__ void uniform2(uint64_t id, uint32_t step,
+                                         uint32_t tag, uint64_t seed,
+                                         double& ua, double& ub) {
+  uint32_t c0 = (uint32_t)id, c1 = (uint32_t)(id >> 32), c2 = step, c3 = tag;
+  philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t a = ((uint64_t)c0 << 21) ^ (uint64_t)(c1 >> 11);
+  const uint64_t b = ((uint64_t)c2 << 21) ^ (uint64_t)(c3 >> 11);
+  ua = (double)a * 0x1p-53;
+  ub = (double)b * 0x1p-53;
+}
+
+// Cell index and quantised upper weight along one axis: g = x * inv_dx,
+// i = floor(g), fq = floor((g - i) * 8192 + 0.5) in [0, 8192].
+__device__ __forceinline__ void cic_axis(double x, double inv_dx, int& i,
+                                         int& fq) {
+  const double g = x * inv_dx;
+  const double fl = floor(g);
+  const double f = g - fl;
+  i = (int)fl;
+  fq = (int)floor(f * 8192.0 + 0.5);
+}
+
+__device__ __forceinline__ int wrap_index(int i, int n) {
+  return i >= n ? i - n : (i < 0 ? i + n : i);
+}
+
+__device__ __forceinline__ double wrap_coord(double x, double len) {
+  if (x < 0.0) x = x + len;
+  if (x >= len) x = x - len;
+  return x;
+}
+
+// Grid constants shared by the kernels (passed by value).
+struct GridC {
+  int nx, ny, nz;
+  int tnx, tny, tnz;       // tiles per axis
+  double dx, inv_dx, lx, ly;
+  long long nxy;           // nodes per z plane
+};
+
+// Structure-of-arrays particle storage of one species, FP64 layout.
+struct Parts {
+  double *x, *y, *z, *vx, *vy, *vz;
+  uint64_t* id;
+};
+
+// Structure-of-arrays particle storage, mixed layout: cell index plus FP32
+// offsets inside the cell (cell units) and FP32 velocities (m/s).
+struct PartsM {
+  uint32_t* cell;
+  float *ox, *oy, *oz, *vx, *vy, *vz;
+  uint64_t* id;
+};
+
+// Device-resident counters of one step.  All are updated with atomics or by
+// single-thread kernels and copied to the host once at the end of a step.
+struct Counters {
+  unsigned long long n[3];          // live particles
+  unsigned long long next_id;
+  unsigned long long fn_total;      // Fowler-Nordheim electrons this step
+  unsigned long long cathode[3], anode[3];
+  unsigned long long n_cand;        // null-collision candidates
+  unsigned long long n_elastic;
+  unsigned long long n_events;      // ionisation events before matching
+  unsigned long long n_ok;          // matched ionisations
+  unsigned long long n_over;        // candidates above E_max
+  unsigned long long n_near;        // near-threshold draws
+  unsigned long long n_ab;          // cathode-absorbed list length
+  unsigned long long n_ncand;       // neutrals in cells with events
+  unsigned long long sorted_n[3];   // counts after the binning pass
+  long long total_charge;
+  unsigned int err;                 // sticky error bits (kErr*)
+  int vcycles;
+  int done;                         // Poisson solve converged
+  int pad;
+  double rel_res;
+  double b_norm;
+  double kinetic[3];
+  double field_energy;
+};
+
+enum : unsigned int {
+  kErrCapacity = 1u, kErrNonFinite = 2u, kErrEvents = 4u, kErrQueue = 8u
+};
+
+// Small-list record sorted by (hi, lo): events, neutral candidates and the
+// absorbed list.
+struct Rec {
+  unsigned long long hi, lo;
+  unsigned int val, pad;
+};
+
+__device__ __forceinline__ bool rec_less(const Rec& a, const Rec& b) {
+  return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs; remapping gives each
+// XCD a contiguous range of work items so neighbouring tiles share an L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+  const unsigned per = nb / 8u;
+  if (per == 0u || b >= per * 8u) return b;
+  return (b % 8u) * per + b / 8u;
+}
+
+}  // namespace pic

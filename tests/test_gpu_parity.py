@@ -1,0 +1,283 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Kernel level (identical inputs): bit-exact node charge, E-field, positions,
+velocities and cell keys of the push, collision outcomes and ids; collided
+velocities and source samples within 1e-12 (libm vs device transcendental
+last-ulp differences).  Draws within 1e-6 of a threshold that involves a
+transcendental are counted by both sides and excluded.
+Step level (identical state, MG vs exact Poisson): phi within 1e-6 of max
+|phi|, positions and velocities within 1e-6 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import constants as C
+from oracle import pic as O
+from oracle import poisson as P
+
+pytestmark = pytest.mark.gpu
+
+
+def grid_of(p):
+    return P.Grid(p["nx"], p["ny"], p["nz"], p["dx"], p.get("bc_lo", 0),
+                  p.get("bc_hi", 0), p.get("v_lo", 0.0), p.get("v_hi", 0.0))
+
+
+def by_id(pos, vel, ids):
+    ids = np.asarray(ids).astype(np.uint64)
+    o = np.argsort(ids)
+    return ids[o], np.asarray(pos)[o], np.asarray(vel)[o]
+
+
+def oracle_arrays(sp):
+    ids = sp["id"]
+    o = np.argsort(ids)
+    pos = np.stack([sp[k] for k in ("x", "y", "z")], 1)[o]
+    vel = np.stack([sp[k] for k in ("vx", "vy", "vz")], 1)[o]
+    return ids[o], pos, vel
+
+
+def gpu_arrays(gpu, s):
+    pos, vel, ids = (t.cpu().numpy() for t in gpu.read(s))
+    return by_id(pos, vel, ids)
+
+
+def small_c2(nx=24, ny=16, nz=40, n_e=4000, n_ion=4000, n_n=3000):
+    p = W.scaled(W.config("c2"), nx, ny, nz, n_e=n_e, n_ion=n_ion, n_n=n_n)
+    return p
+
+
+def load_both(p, gpu, st, seed=5):
+    pre = W.preload(p, seed=seed)
+    for s, (pos, vel, ids) in pre.items():
+        st.load(s, pos, vel, ids)
+        gpu.load(s, pos, vel, ids)
+    n = sum(v[0].shape[0] for v in pre.values())
+    st.next_id = n
+    gpu.set_clock(0, n)
+    return pre
+
+
+def make(p, cap=40000, **kw):
+    from paper_2606_05893_amd import pic as G
+    return G.Pic(p, capacity=(cap, cap, cap), **kw)
+
+
+# --------------------------------------------------------------------------
+def test_deposit_bit_exact(gpu_lib):
+    """Several tiles, ragged tiles (nx = 20, nz = 36 are not multiples of 8),
+    edge positions (nodes, cell centres, periodic seam, top face)."""
+    p = small_c2(nx=20, ny=16, nz=36)
+    gpu = make(p)
+    g = grid_of(p)
+    st = O.State(g)
+    pe, ve, ie = W.random_particles(30000, p, 11)
+    edge = W.edge_positions(p, 3)
+    pe = np.concatenate([pe, edge])
+    ve = np.concatenate([ve, np.zeros_like(edge)])
+    ie = np.arange(pe.shape[0], dtype=np.uint64)
+    pi, vi, ii = W.random_particles(20000, p, 12, id0=10 ** 6)
+    for s, (a, b, c) in ((0, (pe, ve, ie)), (2, (pi, vi, ii))):
+        st.load(s, a, b, c)
+        gpu.load(s, a, b, c)
+    gpu.deposit()
+    acc_g, _, _ = gpu.read_fields()
+    acc_o = O.deposit(st)
+    assert np.array_equal(acc_g.cpu().numpy(), acc_o)
+    assert acc_o.sum() == 2 ** 39 * (20000 - pe.shape[0])
+
+
+def test_deposit_empty(gpu_lib):
+    p = small_c2()
+    gpu = make(p)
+    gpu.deposit()
+    acc, _, _ = gpu.read_fields()
+    assert int(acc.abs().sum()) == 0
+
+
+def test_efield_bit_exact(gpu_lib):
+    p = small_c2()
+    gpu = make(p)
+    g = grid_of(p)
+    phi = np.random.default_rng(3).standard_normal(g.shape) * 10.0
+    gpu.set_phi(phi)
+    _, phi_g, E_g = gpu.read_fields()
+    assert np.array_equal(phi_g.cpu().numpy(), phi)
+    assert np.array_equal(E_g.cpu().numpy(), O.efield(phi, g))
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0), (0, 1)])
+def test_poisson_matches_exact_solve(gpu_lib, bc):
+    p = small_c2(nx=32, ny=16, nz=64)
+    p.update(bc_lo=bc[0], bc_hi=bc[1], v_lo=0.0 if bc[0] == 0 else 3e8,
+             v_hi=128.0 if bc[1] == 0 else -2e8)
+    gpu = make(p)
+    g = grid_of(p)
+    rng = np.random.default_rng(4)
+    rho = rng.standard_normal(g.shape) * 1e4
+    phi_g, info = gpu.poisson_solve(rho)
+    phi_g = phi_g.cpu().numpy()
+    b = P.rhs_from_density(rho, g)
+    phi_o = P.solve_exact(b, g)
+    assert info["converged"] == 1 and info["rel_residual"] <= 1e-10
+    # The residual, recomputed by the oracle on the GPU's potential.
+    assert P.rel_residual(phi_g, b, g) <= 1.5e-10
+    err = np.max(np.abs(phi_g - phi_o)) / np.max(np.abs(phi_o))
+    assert err < 1e-6, err
+    # Warm start from the exact answer converges at once.
+    _, info2 = gpu.poisson_solve(rho, phi=torch.tensor(phi_o))
+    assert info2["vcycles"] <= 1
+
+
+def test_poisson_zero_rhs(gpu_lib):
+    p = small_c2()
+    p["v_hi"] = 0.0
+    gpu = make(p)
+    phi, info = gpu.poisson_solve(np.zeros((p["nz"] + 1, p["ny"], p["nx"])))
+    assert info["converged"] == 1 and float(phi.abs().max()) == 0.0
+
+
+def _advance_case(seed, with_sources=True, dense=True):
+    p = small_c2(nx=16, ny=16, nz=24, n_e=6000, n_ion=3000,
+                 n_n=20000 if dense else 2000)
+    p["collisions"] = dict(p["collisions"])
+    if dense:
+        # Large cross sections so ionisation, starvation and elastic events
+        # all occur in a single step.
+        p["collisions"].update(sigma_el=3e-17, lotz_a=4.5e-15)
+    p["seed"] = seed
+    if not with_sources:
+        p["sources"] = {}
+    else:
+        p["sources"]["sphere"] = dict(cx=16e-9, cy=16e-9, cz=20e-9,
+                                      radius=5e-9, n=300, T_K=3500.0)
+        p["sources"]["disk"]["n_e"] = 200
+    return p
+
+
+@pytest.mark.parametrize("seed", [0, 7])
+def test_advance_bit_exact(gpu_lib, seed):
+    """Sources, push, MCC, ionisation matching and binning from an identical
+    state and field: same particle set by id, bit-exact trajectories of
+    uncollided particles, ulp-close collided ones, same absorbed list."""
+    p = _advance_case(seed)
+    gpu = make(p)
+    g = grid_of(p)
+    st = O.State(g, seed=seed)
+    load_both(p, gpu, st, seed=seed + 1)
+    rng = np.random.default_rng(seed + 2)
+    # A field with structure: parallel plate plus noise, so the FN source
+    # emits at some surface nodes.
+    phi = P.solve_exact(P.add_boundary_terms(np.zeros(g.shape), g), g)
+    phi = phi + rng.standard_normal(g.shape) * 2.0
+    phi[0] = 0.0
+    phi[1] = phi[1] - 60.0 * rng.random(phi[1].shape)
+    gpu.set_phi(phi)
+    E = O.efield(phi, g)
+    # The caller queue: a few particles of every species.
+    for s in range(3):
+        pos, vel, _ = W.random_particles(50, p, 100 + s, z_margin=1)
+        st.inject(s, pos, vel)
+        gpu.inject(s, pos, vel)
+    ab_g, dg = gpu.advance(p["dt"])
+    ab_o, do = O.advance(st, p, E, p["dt"])
+    near = sum(do["near"].values())
+    assert dg["near_threshold"] == near
+    assert do["ionisations"] > 0 and do["elastic"] > 0, do
+    if near == 0:
+        assert dg["ionisations"] == do["ionisations"]
+        assert dg["starved"] == do["starved"]
+        assert dg["elastic"] == do["elastic"]
+        assert dg["candidates"] == do["candidates"]
+        assert dg["fn_emitted"] == do["fn_emitted"]
+    for s in range(3):
+        assert dg["cathode"][s] == do["cathode"][s]
+        assert dg["anode"][s] == do["anode"][s]
+        ig, pg, vg = gpu_arrays(gpu, s)
+        io, po, vo = oracle_arrays(st.sp[s])
+        assert np.array_equal(ig, io), s
+        exact = np.all(pg == po, axis=1) & np.all(vg == vo, axis=1)
+        # Uncollided particles: bit-exact.  Collided / sampled ones (a
+        # transcendental in their history): within 1e-12.
+        assert exact.mean() > 0.9, (s, exact.mean())
+        sc = np.maximum(np.abs(vo), np.sqrt(np.mean(vo ** 2)))
+        assert np.all(np.abs(vg - vo) <= 1e-12 * sc), s
+        assert np.all(np.abs(pg - po) <= 1e-12 * np.maximum(np.abs(po), p["dx"]))
+    # Absorbed list: same (species, id) order, crossing points and velocity.
+    n = ab_g["n"]
+    assert n == ab_o["id"].size
+    if n:
+        assert np.array_equal(ab_g["species"].cpu().numpy(), ab_o["species"])
+        assert np.array_equal(ab_g["id"].cpu().numpy().astype(np.uint64),
+                              ab_o["id"])
+        pos_o = np.stack([ab_o[k] for k in ("x", "y", "z")], 1)
+        assert np.allclose(ab_g["pos"].cpu().numpy(), pos_o, rtol=1e-12,
+                           atol=1e-21)
+    for s in range(3):
+        assert np.isclose(dg["kinetic"][s], do["kinetic"][s], rtol=1e-12)
+
+
+def test_step_tolerance_and_charge(gpu_lib):
+    """A full step (MG solve vs exact): phi within 1e-6, positions and
+    velocities within 1e-6, exact total charge."""
+    p = _advance_case(3, dense=False)
+    gpu = make(p)
+    g = grid_of(p)
+    st = O.State(g, seed=3)
+    load_both(p, gpu, st, seed=9)
+    _, dg = gpu.step(p["dt"])
+    _, do, phi_o = O.step(st, p, p["dt"])
+    _, phi_g, _ = gpu.read_fields()
+    phi_g = phi_g.cpu().numpy()
+    assert np.max(np.abs(phi_g - phi_o)) <= 1e-6 * np.max(np.abs(phi_o))
+    assert dg["total_charge_units"] == do["total_charge_units"]
+    assert dg["solve"]["rel_residual"] <= 1e-10
+    assert np.isclose(dg["field_energy"], do["field_energy"], rtol=1e-6)
+    for s in range(3):
+        ig, pg, vg = gpu_arrays(gpu, s)
+        io, po, vo = oracle_arrays(st.sp[s])
+        assert np.array_equal(ig, io), s
+        assert np.all(np.abs(pg - po) <= 1e-6 * np.maximum(np.abs(po), p["dx"]))
+        vr = np.sqrt(np.mean(vo ** 2))
+        assert np.all(np.abs(vg - vo) <= 1e-6 * np.maximum(np.abs(vo), vr))
+
+
+def test_multi_step_deterministic(gpu_lib):
+    """Twenty steps twice: identical id-keyed state (race detector: all
+    accumulations are integer or fixed-order)."""
+    p = _advance_case(4, dense=True)
+    runs = []
+    for _ in range(2):
+        gpu = make(p)
+        g = grid_of(p)
+        st = O.State(g)
+        load_both(p, gpu, st, seed=2)
+        for _ in range(20):
+            gpu.step(p["dt"])
+        runs.append([gpu_arrays(gpu, s) for s in range(3)])
+    for a, b in zip(*runs):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+def test_capacity_error_is_reported(gpu_lib):
+    from paper_2606_05893_amd import pic as G
+    p = small_c2()
+    gpu = G.Pic(p, capacity=(100, 100, 100))
+    pos, vel, ids = W.random_particles(200, p, 1)
+    with pytest.raises(G.PicError) as e:
+        gpu.load(0, pos, vel, ids)
+    assert e.value.status == -2
+
+
+def test_out_of_domain_load_rejected(gpu_lib):
+    from paper_2606_05893_amd import pic as G
+    p = small_c2()
+    gpu = make(p)
+    pos, vel, ids = W.random_particles(10, p, 1)
+    pos[3, 2] = -1e-9
+    with pytest.raises(G.PicError):
+        gpu.load(0, pos, vel, ids)
+    assert gpu.count(0) == 9
