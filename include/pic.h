@@ -223,6 +223,19 @@ pic_status pic_read_fields(pic_ctx* ctx, int64_t* acc_device,
 pic_status pic_set_clock(pic_ctx* ctx, int64_t step, uint64_t next_id);
 pic_status pic_get_diag(pic_ctx* ctx, pic_diag* diag);
 
+/* Per-phase GPU time, measured with HIP events recorded on the context's
+ * stream around each phase of a step (off by default).  ms[PIC_NPHASES]
+ * receives the time accumulated since timing was enabled, calls[] (may be
+ * NULL) the number of timed executions of each phase. */
+#define PIC_NPHASES 11
+enum {
+  PIC_PH_DEPOSIT = 0, PIC_PH_RHS, PIC_PH_POISSON, PIC_PH_EFIELD,
+  PIC_PH_SOURCES, PIC_PH_PUSH_NEUTRAL, PIC_PH_PUSH_ION, PIC_PH_PUSH_ELECTRON,
+  PIC_PH_COLLIDE, PIC_PH_ABSORBED, PIC_PH_BIN
+};
+pic_status pic_enable_timing(pic_ctx* ctx, int32_t on);
+pic_status pic_phase_times(pic_ctx* ctx, double* ms, int64_t* calls);
+
 const char* pic_last_error(const pic_ctx* ctx);
 int32_t pic_abi_version(void);
 

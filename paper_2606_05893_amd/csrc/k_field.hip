@@ -212,16 +212,23 @@ __global__ void k_residual(const double* __restrict__ u,
   if (threadIdx.x == 0) part[blockIdx.x] = sb[0];
 }
 
-// One colour of a red-black Gauss-Seidel sweep: nodes with
-// (i + j + k) % 2 == color get u = (neighbours + h2 f) / 6.
+// ---- multigrid node operations ---------------------------------------------
+// Each is written for one work item t so that the same code serves the
+// grid-wide kernels of the fine levels and the single-workgroup kernel that
+// runs all the small coarse levels in one launch.
+
+// Nodes of one colour of a red-black Gauss-Seidel sweep: (i + j + k) % 2 ==
+// color get u = (neighbours + h2 f) / 6.
 template <typename T>
-__global__ void k_rbgs(T* __restrict__ u, const T* __restrict__ f, LevelC L,
-                       int color, const Counters* dc) {
-  if (dc->done) return;
+__device__ __forceinline__ long long rbgs_count(const LevelC& L) {
+  return (long long)(L.nx >> 1) * L.ny * (L.k1 - L.k0 + 1);
+}
+template <typename T>
+__device__ __forceinline__ void rbgs_node(T* __restrict__ u,
+                                          const T* __restrict__ f,
+                                          const LevelC& L, int color,
+                                          long long t) {
   const int half = L.nx >> 1;
-  const long long nt = (long long)half * L.ny * (L.k1 - L.k0 + 1);
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= nt) return;
   const int m = (int)(t % half);
   const long long r = t / half;
   const int j = (int)(r % L.ny);
@@ -232,16 +239,15 @@ __global__ void k_rbgs(T* __restrict__ u, const T* __restrict__ f, LevelC L,
   u[idx] = (nb_sum(u, L, i, j, k) + h2 * f[idx]) * (T(1) / T(6));
 }
 
-// Full-weighting restriction of the fine residual to the coarse right-hand
-// side; the coarse correction starts at zero.
+// Full-weighting restriction of the fine residual to coarse node t (the
+// coarse correction starts at zero).
 template <typename T>
-__global__ void k_restrict(const T* __restrict__ uf, const T* __restrict__ ff,
-                           T* __restrict__ uc, T* __restrict__ fc, LevelC F,
-                           LevelC Cc, const Counters* dc) {
-  if (dc->done) return;
-  const long long nt = Cc.nxy * (Cc.nz + 1);
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= nt) return;
+__device__ __forceinline__ void restrict_node(const T* __restrict__ uf,
+                                              const T* __restrict__ ff,
+                                              T* __restrict__ uc,
+                                              T* __restrict__ fc,
+                                              const LevelC& F, const LevelC& Cc,
+                                              long long t) {
   const int ic = (int)(t % Cc.nx);
   const long long r = t / Cc.nx;
   const int jc = (int)(r % Cc.ny);
@@ -273,15 +279,12 @@ __global__ void k_restrict(const T* __restrict__ uf, const T* __restrict__ ff,
   fc[t] = acc * T(1.0 / 64.0);
 }
 
-// Trilinear prolongation of the coarse correction, added to the fine
-// unknowns.
+// Trilinear prolongation of the coarse correction, added to fine unknown t.
 template <typename T>
-__global__ void k_prolong(T* __restrict__ uf, const T* __restrict__ uc,
-                          LevelC F, LevelC Cc, const Counters* dc) {
-  if (dc->done) return;
-  const long long nt = F.nxy * (F.k1 - F.k0 + 1);
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= nt) return;
+__device__ __forceinline__ void prolong_node(T* __restrict__ uf,
+                                             const T* __restrict__ uc,
+                                             const LevelC& F, const LevelC& Cc,
+                                             long long t) {
   const int i = (int)(t % F.nx);
   const long long r = t / F.nx;
   const int j = (int)(r % F.ny);
@@ -306,11 +309,11 @@ __global__ void k_prolong(T* __restrict__ uf, const T* __restrict__ uc,
 }
 
 // Exact solve of a 1x1xN coarsest level (the x, y neighbours are the node
-// itself): tridiagonal 2u - u_{k-1} - u_{k+1} = h2 f, Thomas algorithm.
+// itself): tridiagonal 2u - u_{k-1} - u_{k+1} = h2 f, Thomas algorithm,
+// one thread.
 template <typename T>
-__global__ void k_coarse_line(T* __restrict__ u, const T* __restrict__ f,
-                              LevelC L, const Counters* dc, T* __restrict__ w) {
-  if (dc->done || threadIdx.x || blockIdx.x) return;
+__device__ void line_solve(T* __restrict__ u, const T* __restrict__ f,
+                           const LevelC& L, T* __restrict__ w) {
   const int m = L.k1 - L.k0 + 1;
   T* cp = w;
   T* dp = w + m;
@@ -340,27 +343,180 @@ __global__ void k_coarse_line(T* __restrict__ u, const T* __restrict__ f,
   }
 }
 
-// Coarsest level wider than one node: red-black sweeps in one workgroup.
 template <typename T>
-__global__ void k_coarse_sweeps(T* __restrict__ u, const T* __restrict__ f,
-                                LevelC L, int sweeps, const Counters* dc) {
+__global__ void k_rbgs(T* __restrict__ u, const T* __restrict__ f, LevelC L,
+                       int color, const Counters* dc) {
   if (dc->done) return;
-  const int half = L.nx >> 1;
-  const long long nt = (long long)half * L.ny * (L.k1 - L.k0 + 1);
-  const T h2 = (T)L.h2;
-  for (int s = 0; s < sweeps; ++s) {
-    for (int color = 0; color < 2; ++color) {
-      for (long long t = threadIdx.x; t < nt; t += blockDim.x) {
-        const int m = (int)(t % half);
-        const long long r = t / half;
-        const int j = (int)(r % L.ny);
-        const int k = L.k0 + (int)(r / L.ny);
-        const int i = 2 * m + ((color + j + k) & 1);
-        const long long idx = ((long long)k * L.ny + j) * L.nx + i;
-        u[idx] = (nb_sum(u, L, i, j, k) + h2 * f[idx]) * (T(1) / T(6));
-      }
-      __syncthreads();
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= rbgs_count<T>(L)) return;
+  rbgs_node(u, f, L, color, t);
+}
+
+template <typename T>
+__global__ void k_restrict(const T* __restrict__ uf, const T* __restrict__ ff,
+                           T* __restrict__ uc, T* __restrict__ fc, LevelC F,
+                           LevelC Cc, const Counters* dc) {
+  if (dc->done) return;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= Cc.nxy * (Cc.nz + 1)) return;
+  restrict_node(uf, ff, uc, fc, F, Cc, t);
+}
+
+template <typename T>
+__global__ void k_prolong(T* __restrict__ uf, const T* __restrict__ uc,
+                          LevelC F, LevelC Cc, const Counters* dc) {
+  if (dc->done) return;
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= F.nxy * (F.k1 - F.k0 + 1)) return;
+  prolong_node(uf, uc, F, Cc, t);
+}
+
+// Restriction with the fine residual staged in LDS: a workgroup takes an
+// 8x8x4 block of coarse nodes, computes the residual of the 17x17x9 fine
+// nodes under it once, then applies the 27-point full weighting from LDS.
+constexpr int kRX = 8, kRY = 8, kRZ = 4;
+constexpr int kFX = 2 * kRX + 1, kFY = 2 * kRY + 1, kFZ = 2 * kRZ + 1;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_restrict_tiled(
+    const T* __restrict__ uf, const T* __restrict__ ff, T* __restrict__ uc,
+    T* __restrict__ fc, LevelC F, LevelC Cc, const Counters* dc) {
+  __shared__ T r[kFZ * kFY * kFX];
+  if (dc->done) return;
+  const int tnx = (Cc.nx + kRX - 1) / kRX, tny = (Cc.ny + kRY - 1) / kRY;
+  const int bx = blockIdx.x % tnx, by = (blockIdx.x / tnx) % tny,
+            bz = blockIdx.x / (tnx * tny);
+  const int cx0 = bx * kRX, cy0 = by * kRY, cz0 = bz * kRZ;
+  const T inv_h2 = T(1) / (T)F.h2;
+  for (int q = threadIdx.x; q < kFZ * kFY * kFX; q += blockDim.x) {
+    const int lx = q % kFX, ly = (q / kFX) % kFY, lz = q / (kFX * kFY);
+    const int i = wrap_index(2 * cx0 - 1 + lx, F.nx);
+    const int j = wrap_index(2 * cy0 - 1 + ly, F.ny);
+    int k = 2 * cz0 - 1 + lz;
+    if (k < 0) k = 1;                    // Neumann mirror
+    if (k > F.nz) k = F.nz - 1;
+    T res = T(0);
+    if (k >= F.k0 && k <= F.k1) {
+      const long long fi = ((long long)k * F.ny + j) * F.nx + i;
+      res = ff[fi] - (T(6) * uf[fi] - nb_sum(uf, F, i, j, k)) * inv_h2;
     }
+    r[q] = res;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x % kRX, ty = (threadIdx.x / kRX) % kRY,
+            tz = threadIdx.x / (kRX * kRY);
+  const int ic = cx0 + tx, jc = cy0 + ty, kc = cz0 + tz;
+  if (ic >= Cc.nx || jc >= Cc.ny || kc > Cc.nz) return;
+  const long long t = ((long long)kc * Cc.ny + jc) * Cc.nx + ic;
+  uc[t] = T(0);
+  if (kc < Cc.k0 || kc > Cc.k1) {
+    fc[t] = T(0);
+    return;
+  }
+  T acc = T(0);
+  for (int dk = 0; dk < 3; ++dk) {
+    const T wz = dk == 1 ? T(2) : T(1);
+    for (int dj = 0; dj < 3; ++dj) {
+      const T wy = dj == 1 ? T(2) : T(1);
+      const int row = ((2 * tz + dk) * kFY + (2 * ty + dj)) * kFX + 2 * tx;
+      for (int di = 0; di < 3; ++di) {
+        const T wx = di == 1 ? T(2) : T(1);
+        acc = acc + (wx * wy * wz) * r[row + di];
+      }
+    }
+  }
+  fc[t] = acc * T(1.0 / 64.0);
+}
+
+// The levels from 'first' down, in one workgroup with every level's u and f
+// held in LDS: the lower part of a V-cycle whose levels are too small to
+// fill the GPU (one launch instead of several per level).  f of the first
+// level is read from and u written back to global memory.
+constexpr int kTailLdsBytes = 48 * 1024;
+
+struct TailLevels {
+  void* u0;
+  const void* f0;
+  LevelC L[16];
+  long long off[16];     // offset of each level's u in LDS (elements)
+  int first, last, nu_pre, nu_post, coarse_sweeps;
+  long long total;       // elements of u (and of f) over the levels
+};
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_mg_tail(TailLevels A,
+                                                  const Counters* dc) {
+  __shared__ __attribute__((aligned(16))) char lds[kTailLdsBytes];
+  if (dc->done) return;
+  T* su = reinterpret_cast<T*>(lds);
+  T* sf = su + A.total;
+  const long long tid = threadIdx.x, nth = blockDim.x;
+  {
+    const LevelC& L0 = A.L[A.first];
+    const long long n0 = L0.nxy * (L0.nz + 1);
+    const T* gu = reinterpret_cast<const T*>(A.u0);
+    const T* gf = reinterpret_cast<const T*>(A.f0);
+    for (long long t = tid; t < n0; t += nth) {
+      su[t] = gu[t];
+      sf[t] = gf[t];
+    }
+  }
+  __syncthreads();
+  for (int l = A.first; l < A.last; ++l) {
+    T* u = su + A.off[l];
+    const T* f = sf + A.off[l];
+    const LevelC& L = A.L[l];
+    const long long nr = rbgs_count<T>(L);
+    for (int s = 0; s < A.nu_pre; ++s)
+      for (int color = 0; color < 2; ++color) {
+        for (long long t = tid; t < nr; t += nth) rbgs_node(u, f, L, color, t);
+        __syncthreads();
+      }
+    const LevelC& C = A.L[l + 1];
+    const long long ncn = C.nxy * (C.nz + 1);
+    for (long long t = tid; t < ncn; t += nth)
+      restrict_node(u, f, su + A.off[l + 1], sf + A.off[l + 1], L, C, t);
+    __syncthreads();
+  }
+  {
+    const int l = A.last;
+    T* u = su + A.off[l];
+    const T* f = sf + A.off[l];
+    const LevelC& L = A.L[l];
+    if (L.nx == 1 && L.ny == 1) {
+      // Thomas scratch after the f arrays.
+      if (tid == 0) line_solve(u, f, L, sf + A.total);
+    } else {
+      const long long nr = rbgs_count<T>(L);
+      for (int s = 0; s < A.coarse_sweeps; ++s)
+        for (int color = 0; color < 2; ++color) {
+          for (long long t = tid; t < nr; t += nth) rbgs_node(u, f, L, color, t);
+          __syncthreads();
+        }
+    }
+    __syncthreads();
+  }
+  for (int l = A.last - 1; l >= A.first; --l) {
+    T* u = su + A.off[l];
+    const T* f = sf + A.off[l];
+    const LevelC& L = A.L[l];
+    const LevelC& C = A.L[l + 1];
+    const long long nf = L.nxy * (L.k1 - L.k0 + 1);
+    for (long long t = tid; t < nf; t += nth)
+      prolong_node(u, su + A.off[l + 1], L, C, t);
+    __syncthreads();
+    const long long nr = rbgs_count<T>(L);
+    for (int s = 0; s < A.nu_post; ++s)
+      for (int color = 0; color < 2; ++color) {
+        for (long long t = tid; t < nr; t += nth) rbgs_node(u, f, L, color, t);
+        __syncthreads();
+      }
+  }
+  {
+    const LevelC& L0 = A.L[A.first];
+    const long long n0 = L0.nxy * (L0.nz + 1);
+    T* gu = reinterpret_cast<T*>(A.u0);
+    for (long long t = tid; t < n0; t += nth) gu[t] = su[t];
   }
 }
 
@@ -376,9 +532,9 @@ __global__ void k_correct(double* __restrict__ u, const float* __restrict__ e,
 }
 
 // E = -grad(phi): central differences in x, y and inside z; second-order
-// one-sided on the z faces.  Writes 4 values per node (x, y, z, 0) so a
-// node is one aligned 32-byte (FP64) or 16-byte (FP32) load in the gather.
-// Block partials of sum(q phi) for the field energy.
+// one-sided on the z faces.  Stored as three node arrays (Ex, Ey, Ez): the
+// push stages a tile's nodes in LDS, reading whole rows.  Block partials of
+// sum(q phi) for the field energy.
 template <typename TE>
 __global__ void k_efield(const double* __restrict__ phi,
                          const long long* __restrict__ acc,
@@ -407,10 +563,9 @@ __global__ void k_efield(const double* __restrict__ phi,
       ez = ((-3.0 * phi[idx] + 4.0 * phi[idx - L.nxy]) - phi[idx - 2 * L.nxy]) * h;
     else
       ez = (phi[idx - L.nxy] - phi[idx + L.nxy]) * h;
-    E[4 * idx + 0] = (TE)ex;
-    E[4 * idx + 1] = (TE)ey;
-    E[4 * idx + 2] = (TE)ez;
-    E[4 * idx + 3] = (TE)0;
+    E[idx] = (TE)ex;
+    E[n + idx] = (TE)ey;
+    E[2 * n + idx] = (TE)ez;
     s = s + ((double)acc[idx] * q_unit) * phi[idx];
   }
   sb[threadIdx.x] = s;
@@ -439,33 +594,97 @@ double* lev_f<double>(Level& L) { return L.f; }
 template <>
 float* lev_f<float>(Level& L) { return L.ff; }
 
+// Coarsest level too large for LDS: exact line solve or red-black sweeps in
+// one workgroup, in global memory.
+template <typename T>
+__global__ void k_coarse_global(T* __restrict__ u, const T* __restrict__ f,
+                                LevelC L, int sweeps, const Counters* dc,
+                                T* __restrict__ w) {
+  if (dc->done) return;
+  if (L.nx == 1 && L.ny == 1) {
+    if (threadIdx.x == 0) line_solve(u, f, L, w);
+    return;
+  }
+  const long long nr = rbgs_count<T>(L);
+  for (int s = 0; s < sweeps; ++s)
+    for (int color = 0; color < 2; ++color) {
+      for (long long t = threadIdx.x; t < nr; t += blockDim.x)
+        rbgs_node(u, f, L, color, t);
+      __syncthreads();
+    }
+}
+
+// First level from which all coarser levels fit in the tail kernel's LDS
+// (u and f of every level, plus the coarse line solver's scratch); nlev if
+// not even the coarsest does.
+template <typename T>
+int tail_first(const pic_ctx* c) {
+  int l = c->nlev;
+  long long tot = 0;
+  for (int q = c->nlev - 1; q >= 0; --q) {
+    const long long add = c->lev[q].nnodes;
+    const long long bytes = (2 * (tot + add) + 2 * (c->lev[c->nlev - 1].nz + 2)) *
+                            (long long)sizeof(T);
+    if (bytes > kTailLdsBytes) break;
+    tot += add;
+    l = q;
+  }
+  return l;
+}
+
 // One V(nu_pre, nu_post) cycle from level l down.  Level 0 of an FP32
 // cycle is the correction equation of the mixed form.
 template <typename T>
 void vcycle(pic_ctx* c, int l) {
   hipStream_t st = c->stream;
+  const int tf = tail_first<T>(c);
+  if (l == c->nlev - 1 && tf == c->nlev) {
+    k_coarse_global<T><<<1, 1024, 0, st>>>(lev_u<T>(c->lev[l]),
+                                           lev_f<T>(c->lev[l]), level_c(c, l),
+                                           c->cfg.coarse_sweeps, c->dc,
+                                           reinterpret_cast<T*>(c->partials));
+    return;
+  }
+  {
+    if (l >= tf) {
+      TailLevels A;
+      long long off = 0;
+      for (int q = l; q < c->nlev; ++q) {
+        A.L[q] = level_c(c, q);
+        A.off[q] = off;
+        off += c->lev[q].nnodes;
+      }
+      A.u0 = lev_u<T>(c->lev[l]);
+      A.f0 = lev_f<T>(c->lev[l]);
+      A.total = off;
+      A.first = l;
+      A.last = c->nlev - 1;
+      A.nu_pre = c->cfg.nu_pre;
+      A.nu_post = c->cfg.nu_post;
+      A.coarse_sweeps = c->cfg.coarse_sweeps;
+      k_mg_tail<T><<<1, 1024, 0, st>>>(A, c->dc);
+      return;
+    }
+  }
   Level& L = c->lev[l];
   LevelC Lc = level_c(c, l);
   T* u = lev_u<T>(L);
   T* f = lev_f<T>(L);
-  if (l == c->nlev - 1) {
-    if (L.nx == 1 && L.ny == 1) {
-      k_coarse_line<T><<<1, 1, 0, st>>>(u, f, Lc, c->dc,
-                                        reinterpret_cast<T*>(c->partials));
-    } else {
-      k_coarse_sweeps<T><<<1, 1024, 0, st>>>(u, f, Lc, c->cfg.coarse_sweeps,
-                                             c->dc);
-    }
-    return;
-  }
   const long long nhalf = (long long)(L.nx / 2) * L.ny * (Lc.k1 - Lc.k0 + 1);
   for (int s = 0; s < c->cfg.nu_pre; ++s)
     for (int color = 0; color < 2; ++color)
       k_rbgs<T><<<nblocks(nhalf), kThreads, 0, st>>>(u, f, Lc, color, c->dc);
   Level& N = c->lev[l + 1];
   LevelC Nc = level_c(c, l + 1);
-  k_restrict<T><<<nblocks(N.nnodes), kThreads, 0, st>>>(
-      u, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
+  if (N.nx >= kRX && N.ny >= kRY) {
+    const long long nb = (long long)((N.nx + kRX - 1) / kRX) *
+                         ((N.ny + kRY - 1) / kRY) * ((N.nz + 1 + kRZ - 1) / kRZ);
+    k_restrict_tiled<T><<<(unsigned)nb, 256, 0, st>>>(
+        u, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
+  } else {
+    k_restrict<T><<<nblocks(N.nnodes), kThreads, 0, st>>>(
+        u, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
+  }
   vcycle<T>(c, l + 1);
   k_prolong<T><<<nblocks(Lc.nxy * (Lc.k1 - Lc.k0 + 1)), kThreads, 0, st>>>(
       u, lev_u<T>(N), Lc, Nc, c->dc);

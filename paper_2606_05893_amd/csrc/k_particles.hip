@@ -10,13 +10,15 @@
 // and integer atomics.  Charge is accumulated in LDS per tile with 64-bit
 // integer atomics and flushed once per node, so the sum is exact and
 // independent of order.
+#include <algorithm>
+
 #include "pic_ctx.h"
 
 namespace pic {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kSmallLds = 2048;   // records sorted in LDS by k_sort_small
+constexpr int kSmallLds = 4096;   // records per LDS-sorted chunk
 constexpr int kFixedBlocks = 2048;
 
 inline unsigned nblk(long long n, int t = kT) {
@@ -95,6 +97,41 @@ __device__ __forceinline__ unsigned cell_of(double x, double y, double z,
   return ((unsigned)k * (unsigned)g.ny + (unsigned)j) * (unsigned)g.nx + (unsigned)i;
 }
 
+// ---- chunk work lists ----------------------------------------------------------
+// A tile's binned particles of a species are split into pieces of at most
+// kChunk, so a crowded tile (e.g. the neutrals above an evaporating disk)
+// spreads over several workgroups.  A chunk (tile, piece) serves every
+// species of its list: piece k of a tile covers [ts[t] + k kChunk, ...).
+constexpr unsigned kChunk = 2048;
+
+__device__ __forceinline__ void piece(const uint32_t* __restrict__ ts,
+                                      unsigned t, unsigned k, unsigned& b,
+                                      unsigned& e) {
+  const unsigned tb = ts[t], te = ts[t + 1];
+  b = tb + k * kChunk;
+  if (b > te) b = te;
+  e = te - b > kChunk ? b + kChunk : te;
+}
+
+__global__ void k_chunk_count(const uint32_t* __restrict__ ta,
+                              const uint32_t* __restrict__ tb, long long nt,
+                              unsigned* __restrict__ cnt) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const unsigned na = ta[t + 1] - ta[t];
+  const unsigned nb = tb ? tb[t + 1] - tb[t] : 0u;
+  const unsigned ca = (na + kChunk - 1) / kChunk, cb = (nb + kChunk - 1) / kChunk;
+  cnt[t] = ca > cb ? ca : cb;
+}
+
+__global__ void k_chunk_fill(const unsigned* __restrict__ cstart, long long nt,
+                             uint2* __restrict__ chunks) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= nt) return;
+  const unsigned b = cstart[t], e = cstart[t + 1];
+  for (unsigned k = 0; b + k < e; ++k) chunks[b + k] = make_uint2((unsigned)t, k);
+}
+
 // ---- step bookkeeping ---------------------------------------------------------
 __global__ void k_begin(Counters* dc, unsigned long long n0,
                         unsigned long long n1, unsigned long long n2,
@@ -108,6 +145,7 @@ __global__ void k_begin(Counters* dc, unsigned long long n0,
   }
   dc->n_cand = dc->n_elastic = dc->n_events = dc->n_ok = 0;
   dc->n_over = dc->n_near = dc->n_ab = dc->n_ncand = 0;
+  dc->n_tail_cand = 0;
 }
 
 // ---- sources ------------------------------------------------------------------
@@ -201,7 +239,7 @@ __global__ void k_sphere(Parts p, long long dst, long long n,
 // J = (a/phi) F^2 exp(-b phi^1.5/F) with F = -E_z(z = 0); the expected
 // number J dx^2 dt / e is rounded stochastically.
 template <typename TE>
-__global__ void k_fn_count(const TE* __restrict__ E, unsigned* __restrict__ cnt,
+__global__ void k_fn_count(const TE* __restrict__ Ez, unsigned* __restrict__ cnt,
                            GridC g, double cx, double cy, double radius,
                            double a_phi, double b_phi, double c_fn,
                            uint32_t step, uint64_t seed, Counters* dc) {
@@ -212,7 +250,7 @@ __global__ void k_fn_count(const TE* __restrict__ E, unsigned* __restrict__ cnt,
   const double ddy = (double)j * g.dx - cy;
   unsigned c = 0;
   if ((ddx * ddx + ddy * ddy) <= radius * radius) {
-    const double F = -(double)E[4 * t + 2];
+    const double F = -(double)Ez[t];
     double J = 0.0;
     if (F > 0.0) J = ((a_phi * F) * F) * exp(-(b_phi / F));
     const double mean = J * c_fn;
@@ -300,16 +338,21 @@ __global__ void k_fn_commit(Counters* dc, long long cap) {
 }
 
 // ---- deposition ---------------------------------------------------------------
-// One workgroup per 8x8x8-cell tile: the tile's electrons and ions (binned
-// order) add their quantised CIC weights into a 9x9x9 int64 LDS block with
-// 64-bit LDS atomics; the block is then added to the node array with one
-// global atomic per non-zero node.  Particles outside the tile (never, when
+// One workgroup per chunk of an 8x8x8-cell tile: the chunk's electrons and
+// ions (binned order) add their quantised CIC weights into a 9x9x9 int64
+// LDS block with 64-bit LDS atomics; the block is then added to the node
+// array with one global atomic per non-zero node.  Particles outside the tile (never, when
 // the binning invariant holds) fall back to global atomics.
 __global__ void __launch_bounds__(kT) k_deposit(
     Parts pe, Parts pi, const uint32_t* __restrict__ tse,
-    const uint32_t* __restrict__ tsi, long long* __restrict__ acc, GridC g) {
+    const uint32_t* __restrict__ tsi, const uint2* __restrict__ chunks,
+    const unsigned* __restrict__ nchunks, long long* __restrict__ acc,
+    GridC g) {
   __shared__ unsigned long long s[9 * 9 * 9];
-  const unsigned t = xcd_block(blockIdx.x, gridDim.x);
+  const unsigned nchk = *nchunks;
+  if (blockIdx.x >= nchk) return;
+  const unsigned cb = xcd_block(blockIdx.x, nchk);
+  const unsigned t = chunks[cb].x, kp = chunks[cb].y;
   const int tx = (int)(t % g.tnx);
   const int ty = (int)((t / g.tnx) % g.tny);
   const int tz = (int)(t / ((unsigned)g.tnx * g.tny));
@@ -320,7 +363,8 @@ __global__ void __launch_bounds__(kT) k_deposit(
     const Parts& p = sp ? pi : pe;
     const uint32_t* ts = sp ? tsi : tse;
     const long long sign = sp ? 1 : -1;
-    const unsigned b = ts[t], e = ts[t + 1];
+    unsigned b, e;
+    piece(ts, t, kp, b, e);
     for (unsigned q = b + threadIdx.x; q < e; q += blockDim.x) {
       int ix, fx, iy, fy, iz, fz;
       cic_axis(p.x[q], g.inv_dx, ix, fx);
@@ -373,12 +417,14 @@ struct MccC {
   double two_e_me;        // 2 e / m_e
 };
 
-// Field at a particle with the deposit's quantised weights, accumulated in
-// the fixed order z-corner, y-corner, x-corner.
-__device__ __forceinline__ void gather(const double* __restrict__ E,
-                                       const GridC& g, double x, double y,
-                                       double z, double& ex, double& ey,
-                                       double& ez) {
+// Field at a particle from the node arrays (Ex, Ey, Ez blocks of nn nodes),
+// with the deposit's quantised weights, accumulated in the fixed order
+// z-corner, y-corner, x-corner.
+__device__ __forceinline__ void gather_global(const double* __restrict__ E,
+                                              long long nn, const GridC& g,
+                                              double x, double y, double z,
+                                              double& ex, double& ey,
+                                              double& ez) {
   int ix, fx, iy, fy, iz, fz;
   cic_axis(x, g.inv_dx, ix, fx);
   cic_axis(y, g.inv_dx, iy, fy);
@@ -395,126 +441,321 @@ __device__ __forceinline__ void gather(const double* __restrict__ E,
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const double w = (double)(wx[a] * wy[b] * wz[c]) * kQScale;
-        const double4 e = *reinterpret_cast<const double4*>(
-            E + 4 * (row + wrap_index(ix + a, g.nx)));
-        ex = ex + w * e.x;
-        ey = ey + w * e.y;
-        ez = ez + w * e.z;
+        const long long node = row + wrap_index(ix + a, g.nx);
+        ex = ex + w * E[node];
+        ey = ey + w * E[nn + node];
+        ez = ez + w * E[2 * nn + node];
       }
     }
   }
 }
 
-// Push one species (SP: 0 electron, 1 neutral, 2 ion).  Per particle:
-// gather + kick (charged), drift, cathode/anode absorption, x/y wrap, cell
-// key; neutrals count themselves per cell; electrons take the null-
-// collision candidate draw U1 < 1 - exp(-N_c c_coll) and append candidates.
-template <int SP>
-__global__ void __launch_bounds__(kT) k_push(
-    Parts p, uint32_t* __restrict__ key, const double* __restrict__ E,
-    GridC g, double qm_dt, double dt, double mass_half,
-    int* __restrict__ ncount, uint32_t* __restrict__ cand, MccC m,
-    uint32_t step, uint64_t seed, Rec* __restrict__ ab_rec,
-    double* __restrict__ ab_pos, double* __restrict__ ab_vel, long long ab_cap,
-    Counters* dc, double* __restrict__ part) {
-  __shared__ double sk[kT];
-  const long long n = (long long)dc->n[SP];
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const bool live = i < n;
-  double ke = 0.0;
-  bool cathode = false, is_cand = false;
-  unsigned cell = kDead;
-  double x = 0, y = 0, z = 0, vx = 0, vy = 0, vz = 0;
-  unsigned long long id = 0;
-  if (live) {
-    x = p.x[i]; y = p.y[i]; z = p.z[i];
-    vx = p.vx[i]; vy = p.vy[i]; vz = p.vz[i];
-    if (SP != 1) {
-      double ex, ey, ez;
-      gather(E, g, x, y, z, ex, ey, ez);
-      vx = vx + qm_dt * ex;
-      vy = vy + qm_dt * ey;
-      vz = vz + qm_dt * ez;
-    }
-    x = x + vx * dt;
-    y = y + vy * dt;
-    z = z + vz * dt;
-    ke = (vx * vx + vy * vy) + vz * vz;
-    const double gz = z * g.inv_dx;
-    const double xw = wrap_coord(x, g.lx), yw = wrap_coord(y, g.ly);
-    if (!(xw >= 0.0 && xw < g.lx && yw >= 0.0 && yw < g.ly) || !(gz == gz) ||
-        !isfinite(vx) || !isfinite(vy) || !isfinite(vz)) {
-      // Non-finite, or moved more than one period in a step: removed and
-      // reported.
-      atomicOr(&dc->err, kErrNonFinite);
-    } else if (gz < 0.0) {
-      cathode = true;
-    } else if (gz >= (double)g.nz) {
-      atomicAdd(&dc->anode[SP], 1ull);
-    } else {
-      x = xw;
-      y = yw;
-      cell = cell_of(x, y, z, g);
-      p.x[i] = x; p.y[i] = y; p.z[i] = z;
-      p.vx[i] = vx; p.vy[i] = vy; p.vz[i] = vz;
-      if (SP == 1) atomicAdd(&ncount[cell], 1);
-    }
-    key[i] = cell;
-    if (SP == 0 && cell != kDead && m.enabled) {
-      const int nc = ncount[cell];
-      if (nc > 0) {
-        id = p.id[i];
-        const double pstar = 1.0 - exp(-((double)nc * m.c_coll));
-        double u1, u2;
-        uniform2(id, step, kTagMcc0, seed, u1, u2);
-        if (fabs(u1 - pstar) < 1e-6) atomicAdd(&dc->n_near, 1ull);
-        is_cand = u1 < pstar;
+// The same from a tile's 9x9x9 nodes staged in LDS; (lx, ly, lz) is the
+// particle's cell inside the tile.
+__device__ __forceinline__ void gather_lds(const double* sx, const double* sy,
+                                           const double* sz, int lx, int ly,
+                                           int lz, int fx, int fy, int fz,
+                                           double& ex, double& ey, double& ez) {
+  const long long wx[2] = {kQ - fx, fx}, wy[2] = {kQ - fy, fy},
+                  wz[2] = {kQ - fz, fz};
+  ex = 0.0; ey = 0.0; ez = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int row = ((lz + c) * 9 + (ly + b)) * 9 + lx;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double w = (double)(wx[a] * wy[b] * wz[c]) * kQScale;
+        ex = ex + w * sx[row + a];
+        ey = ey + w * sy[row + a];
+        ez = ez + w * sz[row + a];
       }
     }
   }
-  // Cathode sink list (wave-aggregated).
-  const unsigned long long slot = wave_append(cathode, &dc->n_ab);
-  if (cathode) {
-    atomicAdd(&dc->cathode[SP], 1ull);
-    if ((long long)slot < ab_cap) {
-      const double tc = -z / vz;
-      const double xc = wrap_coord(x + vx * tc, g.lx);
-      const double yc = wrap_coord(y + vy * tc, g.ly);
-      Rec r;
-      r.hi = SP; r.lo = p.id[i]; r.val = (unsigned)slot; r.pad = 0;
-      ab_rec[slot] = r;
-      ab_pos[3 * slot] = xc; ab_pos[3 * slot + 1] = yc; ab_pos[3 * slot + 2] = 0.0;
-      ab_vel[3 * slot] = vx; ab_vel[3 * slot + 1] = vy; ab_vel[3 * slot + 2] = vz;
-    } else {
-      atomicOr(&dc->err, kErrEvents);
+}
+
+// Result of one particle's push.
+struct PushOut {
+  bool cathode, cand;
+  unsigned cell;
+  double ke;           // |v|^2 after the kick
+  double x, y, z, vx, vy, vz;
+};
+
+// Drift, boundaries, write-back and (electrons) the null-collision
+// candidate draw U1 < 1 - exp(-N_c c_coll); velocities already kicked.
+template <int SP>
+__device__ __forceinline__ void finish_push(Parts& p, long long i, double x,
+                                            double y, double z, double vx,
+                                            double vy, double vz, double dt,
+                                            const GridC& g, uint32_t* key,
+                                            int* ncount, const MccC& m,
+                                            uint32_t step, uint64_t seed,
+                                            Counters* dc, PushOut& o) {
+  x = x + vx * dt;
+  y = y + vy * dt;
+  z = z + vz * dt;
+  o.ke = (vx * vx + vy * vy) + vz * vz;
+  o.cathode = false;
+  o.cand = false;
+  o.cell = kDead;
+  const double gz = z * g.inv_dx;
+  const double xw = wrap_coord(x, g.lx), yw = wrap_coord(y, g.ly);
+  if (!(xw >= 0.0 && xw < g.lx && yw >= 0.0 && yw < g.ly) || !(gz == gz) ||
+      !isfinite(vx) || !isfinite(vy) || !isfinite(vz)) {
+    // Non-finite, or moved more than one period in a step: removed and
+    // reported.
+    atomicOr(&dc->err, kErrNonFinite);
+  } else if (gz < 0.0) {
+    o.cathode = true;
+  } else if (gz >= (double)g.nz) {
+    atomicAdd(&dc->anode[SP], 1ull);
+  } else {
+    x = xw;
+    y = yw;
+    o.cell = cell_of(x, y, z, g);
+    p.x[i] = x; p.y[i] = y; p.z[i] = z;
+    p.vx[i] = vx; p.vy[i] = vy; p.vz[i] = vz;
+    if (SP == 1) atomicAdd(&ncount[o.cell], 1);
+  }
+  key[i] = o.cell;
+  if (SP == 0 && o.cell != kDead && m.enabled) {
+    const int nc = ncount[o.cell];
+    if (nc > 0) {
+      const double pstar = 1.0 - exp(-((double)nc * m.c_coll));
+      double u1, u2;
+      uniform2(p.id[i], step, kTagMcc0, seed, u1, u2);
+      if (fabs(u1 - pstar) < 1e-6) atomicAdd(&dc->n_near, 1ull);
+      o.cand = u1 < pstar;
     }
   }
-  if (SP == 0) {
-    const unsigned long long cs = wave_append(is_cand, &dc->n_cand);
-    if (is_cand) cand[cs] = (uint32_t)i;
+  o.x = x; o.y = y; o.z = z; o.vx = vx; o.vy = vy; o.vz = vz;
+}
+
+// Cathode sink record (wave-aggregated slot).  All lanes must call it.
+template <int SP>
+__device__ __forceinline__ void sink(const Parts& p, long long i,
+                                     const PushOut& o, const GridC& g,
+                                     Rec* ab_rec, double* ab_pos,
+                                     double* ab_vel, long long ab_cap,
+                                     Counters* dc) {
+  const unsigned long long slot = wave_append(o.cathode, &dc->n_ab);
+  if (!o.cathode) return;
+  atomicAdd(&dc->cathode[SP], 1ull);
+  if ((long long)slot < ab_cap) {
+    const double tc = -o.z / o.vz;
+    const double xc = wrap_coord(o.x + o.vx * tc, g.lx);
+    const double yc = wrap_coord(o.y + o.vy * tc, g.ly);
+    Rec r;
+    r.hi = SP; r.lo = p.id[i]; r.val = (unsigned)slot;
+    ab_rec[slot] = r;
+    ab_pos[3 * slot] = xc; ab_pos[3 * slot + 1] = yc; ab_pos[3 * slot + 2] = 0.0;
+    ab_vel[3 * slot] = o.vx; ab_vel[3 * slot + 1] = o.vy;
+    ab_vel[3 * slot + 2] = o.vz;
+  } else {
+    atomicOr(&dc->err, kErrEvents);
   }
-  // Kinetic energy partials (fixed tree per block).
-  sk[threadIdx.x] = ke;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sk) {
+  sk[threadIdx.x] = v;
   __syncthreads();
   for (int o = kT / 2; o > 0; o >>= 1) {
     if (threadIdx.x < o) sk[threadIdx.x] = sk[threadIdx.x] + sk[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = sk[0] * mass_half;
+  const double r = sk[0];
+  __syncthreads();
+  return r;
 }
 
-__global__ void k_sum_partials(const double* __restrict__ part, long long n,
-                               double* out) {
+// Charged species, one workgroup per 8x8x8-cell tile: the tile's 9x9x9 E
+// nodes are staged in LDS once and serve both the ions and the electrons
+// binned in the tile.  Electron candidates are written to the tile's own
+// segment of the candidate list (no global counter).
+struct TileArgs {
+  Parts pe, pi;
+  const uint32_t *tse, *tsi;
+  const uint2* chunks;
+  const unsigned* nchunks;
+  uint32_t *keye, *keyi;
+  double qm_e, qm_i, dt;
+  int* ncount;
+  uint32_t* cand;
+  uint32_t* cand_cnt;
+  Rec* ab_rec;
+  double *ab_pos, *ab_vel;
+  long long ab_cap;
+  double *part_e, *part_i;
+};
+
+__global__ void __launch_bounds__(kT) k_push_tile(
+    TileArgs A, const double* __restrict__ E, long long nn, GridC g, MccC m,
+    uint32_t step, uint64_t seed, Counters* dc) {
+  __shared__ double sx[729], sy[729], sz[729];
+  __shared__ double sk[kT];
+  __shared__ unsigned s_cand;
+  const unsigned nchk = *A.nchunks;
+  if (blockIdx.x >= nchk) return;
+  const unsigned cb = xcd_block(blockIdx.x, nchk);
+  const unsigned t = A.chunks[cb].x, kp = A.chunks[cb].y;
+  unsigned be, ee, bi, ei;
+  piece(A.tse, t, kp, be, ee);
+  piece(A.tsi, t, kp, bi, ei);
+  if (be == ee && bi == ei) {
+    if (threadIdx.x == 0) {
+      A.part_e[cb] = 0.0;
+      A.part_i[cb] = 0.0;
+      A.cand_cnt[cb] = 0;
+    }
+    return;
+  }
+  const int tx = (int)(t % g.tnx);
+  const int ty = (int)((t / g.tnx) % g.tny);
+  const int tz = (int)(t / ((unsigned)g.tnx * g.tny));
+  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
+  for (int q = threadIdx.x; q < 729; q += blockDim.x) {
+    const int a = q % 9, b = (q / 9) % 9, c = q / 81;
+    const int gk = z0 + c;
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+    if (gk <= g.nz) {
+      const long long node = ((long long)gk * g.ny + wrap_index(y0 + b, g.ny)) *
+                                 g.nx + wrap_index(x0 + a, g.nx);
+      vx = E[node]; vy = E[nn + node]; vz = E[2 * nn + node];
+    }
+    sx[q] = vx; sy[q] = vy; sz[q] = vz;
+  }
+  if (threadIdx.x == 0) s_cand = 0;
+  __syncthreads();
+  double ke_i = 0.0, ke_e = 0.0;
+  // Ions.
+  for (unsigned base = bi; base < ei; base += blockDim.x) {
+    const long long i = base + threadIdx.x;
+    const bool live = i < ei;
+    PushOut o;
+    o.cathode = false;
+    if (live) {
+      const double x = A.pi.x[i], y = A.pi.y[i], z = A.pi.z[i];
+      int ix, fx, iy, fy, iz, fz;
+      cic_axis(x, g.inv_dx, ix, fx);
+      cic_axis(y, g.inv_dx, iy, fy);
+      cic_axis(z, g.inv_dx, iz, fz);
+      if (ix >= g.nx) ix -= g.nx;
+      if (iy >= g.ny) iy -= g.ny;
+      const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
+      double ex, ey, ez;
+      if (lx >= 0 && lx < kTile && ly >= 0 && ly < kTile && lz >= 0 && lz < kTile)
+        gather_lds(sx, sy, sz, lx, ly, lz, fx, fy, fz, ex, ey, ez);
+      else
+        gather_global(E, nn, g, x, y, z, ex, ey, ez);
+      const double vx = A.pi.vx[i] + A.qm_i * ex;
+      const double vy = A.pi.vy[i] + A.qm_i * ey;
+      const double vz = A.pi.vz[i] + A.qm_i * ez;
+      finish_push<2>(A.pi, i, x, y, z, vx, vy, vz, A.dt, g, A.keyi, A.ncount, m,
+                     step, seed, dc, o);
+      ke_i = ke_i + o.ke;
+    }
+    sink<2>(A.pi, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
+  }
+  // Electrons.
+  for (unsigned base = be; base < ee; base += blockDim.x) {
+    const long long i = base + threadIdx.x;
+    const bool live = i < ee;
+    PushOut o;
+    o.cathode = false;
+    o.cand = false;
+    if (live) {
+      const double x = A.pe.x[i], y = A.pe.y[i], z = A.pe.z[i];
+      int ix, fx, iy, fy, iz, fz;
+      cic_axis(x, g.inv_dx, ix, fx);
+      cic_axis(y, g.inv_dx, iy, fy);
+      cic_axis(z, g.inv_dx, iz, fz);
+      if (ix >= g.nx) ix -= g.nx;
+      if (iy >= g.ny) iy -= g.ny;
+      const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
+      double ex, ey, ez;
+      if (lx >= 0 && lx < kTile && ly >= 0 && ly < kTile && lz >= 0 && lz < kTile)
+        gather_lds(sx, sy, sz, lx, ly, lz, fx, fy, fz, ex, ey, ez);
+      else
+        gather_global(E, nn, g, x, y, z, ex, ey, ez);
+      const double vx = A.pe.vx[i] + A.qm_e * ex;
+      const double vy = A.pe.vy[i] + A.qm_e * ey;
+      const double vz = A.pe.vz[i] + A.qm_e * ez;
+      finish_push<0>(A.pe, i, x, y, z, vx, vy, vz, A.dt, g, A.keye, A.ncount, m,
+                     step, seed, dc, o);
+      ke_e = ke_e + o.ke;
+      if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = (uint32_t)i;
+    }
+    sink<0>(A.pe, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
+  }
+  const double si = block_sum(ke_i, sk);
+  const double se = block_sum(ke_e, sk);
+  if (threadIdx.x == 0) {
+    A.part_i[cb] = si;
+    A.part_e[cb] = se;
+    A.cand_cnt[cb] = s_cand;
+  }
+}
+
+// Particles not covered by tile ranges (sources and queue appended this
+// step; all neutrals): one thread per particle, field from global memory.
+template <int SP>
+__global__ void __launch_bounds__(kT) k_push_list(
+    Parts p, long long first, uint32_t* __restrict__ key,
+    const double* __restrict__ E, long long nn, GridC g, double qm_dt,
+    double dt, int* __restrict__ ncount, uint32_t* __restrict__ cand, MccC m,
+    uint32_t step, uint64_t seed, Rec* __restrict__ ab_rec,
+    double* __restrict__ ab_pos, double* __restrict__ ab_vel, long long ab_cap,
+    Counters* dc, double* __restrict__ part) {
+  __shared__ double sk[kT];
+  const long long n = (long long)dc->n[SP];
+  const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const bool live = i < n;
+  PushOut o;
+  o.cathode = false;
+  o.cand = false;
+  o.ke = 0.0;
+  if (live) {
+    const double x = p.x[i], y = p.y[i], z = p.z[i];
+    double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
+    if (SP != 1) {
+      double ex, ey, ez;
+      gather_global(E, nn, g, x, y, z, ex, ey, ez);
+      vx = vx + qm_dt * ex;
+      vy = vy + qm_dt * ey;
+      vz = vz + qm_dt * ez;
+    }
+    finish_push<SP>(p, i, x, y, z, vx, vy, vz, dt, g, key, ncount, m, step,
+                    seed, dc, o);
+  }
+  sink<SP>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+  if (SP == 0) {
+    const unsigned long long cs = wave_append(o.cand, &dc->n_tail_cand);
+    if (o.cand) cand[first + cs] = (uint32_t)i;
+  }
+  const double s = block_sum(live ? o.ke : 0.0, sk);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Sum of two partial arrays (fixed order), times a factor; the first holds
+// *na_dev entries when na_dev is given (chunk partials), else na.
+__global__ void k_sum_partials(const double* __restrict__ a, long long na,
+                               const unsigned* __restrict__ na_dev,
+                               const double* __restrict__ b, long long nb,
+                               double factor, double* out) {
   __shared__ double s[1024];
-  double a = 0.0;
-  for (long long q = threadIdx.x; q < n; q += blockDim.x) a = a + part[q];
-  s[threadIdx.x] = a;
+  if (na_dev) na = *na_dev;
+  double acc = 0.0;
+  for (long long q = threadIdx.x; q < na; q += blockDim.x) acc = acc + a[q];
+  for (long long q = threadIdx.x; q < nb; q += blockDim.x) acc = acc + b[q];
+  s[threadIdx.x] = acc;
   __syncthreads();
   for (int o = 512; o > 0; o >>= 1) {
     if ((int)threadIdx.x < o) s[threadIdx.x] = s[threadIdx.x] + s[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *out = s[0];
+  if (threadIdx.x == 0) *out = s[0] * factor;
 }
 
 // ---- collisions ---------------------------------------------------------------
@@ -535,89 +776,107 @@ __device__ __forceinline__ double sigma_ion(const MccC& m, double E_eV) {
   return m.sigma_const;
 }
 
-// Candidates: second draw U2 against the cumulative process probabilities
+// Candidates of one chunk (block t < number of chunks) or of the unbinned
+// tail (block t == number of chunks): second draw U2 against the cumulative process probabilities
 // (ionisation, then elastic).  Elastic scattering is applied at once;
 // ionisation events are recorded as (cell, electron id) for matching.
-__global__ void k_mcc(Parts p, const uint32_t* __restrict__ key,
-                      const uint32_t* __restrict__ cand, MccC m, uint32_t step,
-                      uint64_t seed, Rec* __restrict__ ev, uint8_t* __restrict__ flag,
-                      long long ev_cap, Counters* dc) {
-  const long long nc = (long long)dc->n_cand;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nc;
-       t += (long long)gridDim.x * blockDim.x) {
-    const uint32_t i = cand[t];
-    const unsigned long long id = p.id[i];
-    const double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
-    double u1, u2;
-    uniform2(id, step, kTagMcc0, seed, u1, u2);
-    const double v2 = (vx * vx + vy * vy) + vz * vz;
-    const double v = sqrt(v2);
-    const double E_eV = (m.half_me * v2) / kE;
-    if (E_eV > m.E_max) atomicAdd(&dc->n_over, 1ull);
-    const double s_ion = sigma_ion(m, E_eV);
-    const double p_ion = (s_ion * v) * m.inv_gmax;
-    const double p_el = (m.sigma_el * v) * m.inv_gmax;
-    const double p_tot = p_ion + p_el;
-    if ((p_ion > 0.0 && fabs(u2 - p_ion) < 1e-6) || fabs(u2 - p_tot) < 1e-6)
-      atomicAdd(&dc->n_near, 1ull);
-    if (u2 < p_ion) {
-      const unsigned long long s = atomicAdd(&dc->n_events, 1ull);
+__global__ void __launch_bounds__(kT) k_mcc(
+    Parts p, const uint32_t* __restrict__ key, const uint32_t* __restrict__ cand,
+    const uint32_t* __restrict__ tse, const uint32_t* __restrict__ cand_cnt,
+    const uint2* __restrict__ chunks, const unsigned* __restrict__ nchunks,
+    long long tail_first, MccC m, uint32_t step,
+    uint64_t seed, Rec* __restrict__ ev, uint8_t* __restrict__ flag,
+    long long ev_cap, uint32_t* __restrict__ el_cnt, Counters* dc) {
+  __shared__ unsigned s_el;
+  const unsigned t = blockIdx.x;
+  const unsigned nch = *nchunks;
+  if (t > nch) return;
+  long long b, e;
+  if (t < nch) {
+    unsigned pb, pe;
+    piece(tse, chunks[t].x, chunks[t].y, pb, pe);
+    b = pb;
+    e = b + cand_cnt[t];
+  } else {
+    b = tail_first;
+    e = b + (long long)dc->n_tail_cand;
+  }
+  if (threadIdx.x == 0) s_el = 0;
+  __syncthreads();
+  for (long long base = b; base < e; base += blockDim.x) {
+    const long long q = base + threadIdx.x;
+    bool event = false;
+    uint32_t i = 0;
+    unsigned long long id = 0;
+    if (q < e) {
+      i = cand[q];
+      id = p.id[i];
+      const double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
+      double u1, u2;
+      uniform2(id, step, kTagMcc0, seed, u1, u2);
+      const double v2 = (vx * vx + vy * vy) + vz * vz;
+      const double v = sqrt(v2);
+      const double E_eV = (m.half_me * v2) / kE;
+      if (E_eV > m.E_max) atomicAdd(&dc->n_over, 1ull);
+      const double s_ion = sigma_ion(m, E_eV);
+      const double p_ion = (s_ion * v) * m.inv_gmax;
+      const double p_el = (m.sigma_el * v) * m.inv_gmax;
+      const double p_tot = p_ion + p_el;
+      if ((p_ion > 0.0 && fabs(u2 - p_ion) < 1e-6) || fabs(u2 - p_tot) < 1e-6)
+        atomicAdd(&dc->n_near, 1ull);
+      if (u2 < p_ion) {
+        event = true;
+      } else if (u2 < p_tot) {
+        atomicAdd(&s_el, 1u);
+        double u3, u4, nx, ny, nz;
+        uniform2(id, step, kTagMcc1, seed, u3, u4);
+        isotropic(u3, u4, nx, ny, nz);
+        const double cosx = ((vx * nx + vy * ny) + vz * nz) / v;
+        const double fac = sqrt(1.0 - m.ratio * (1.0 - cosx));
+        const double sp = v * fac;
+        p.vx[i] = sp * nx;
+        p.vy[i] = sp * ny;
+        p.vz[i] = sp * nz;
+      }
+    }
+    const unsigned long long s = wave_append(event, &dc->n_events);
+    if (event) {
       const uint32_t cell = key[i];
       if ((long long)s < ev_cap) {
         Rec r;
-        r.hi = cell; r.lo = id; r.val = i; r.pad = 0;
+        r.hi = cell; r.lo = id; r.val = i;
         ev[s] = r;
         flag[cell] = 1;
       } else {
         atomicOr(&dc->err, kErrEvents);
       }
-    } else if (u2 < p_tot) {
-      atomicAdd(&dc->n_elastic, 1ull);
-      double u3, u4, nx, ny, nz;
-      uniform2(id, step, kTagMcc1, seed, u3, u4);
-      isotropic(u3, u4, nx, ny, nz);
-      const double cosx = ((vx * nx + vy * ny) + vz * nz) / v;
-      const double fac = sqrt(1.0 - m.ratio * (1.0 - cosx));
-      const double sp = v * fac;
-      p.vx[i] = sp * nx;
-      p.vy[i] = sp * ny;
-      p.vz[i] = sp * nz;
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) el_cnt[t] = s_el;
 }
 
-// Bitonic sort of a small record list by (hi, lo) in one workgroup: in LDS
-// when it fits, otherwise in place in global memory.  At most cap records
-// are valid; the buffer holds the next power of two above cap.
-__global__ void __launch_bounds__(1024) k_sort_small(
+// Sort of a record list by (hi, lo) (keys are unique): every 4096-record
+// chunk is sorted in LDS by its own workgroup (bitonic), then rounds of
+// pairwise merges place each record at its rank in its own run plus the
+// number of smaller keys in the partner run (binary search).  The host
+// launches the rounds for the list's capacity; short lists make the extra
+// rounds plain copies.
+__global__ void __launch_bounds__(1024) k_sort_chunks(
     Rec* __restrict__ a, const unsigned long long* __restrict__ count,
     long long cap) {
   __shared__ Rec s[kSmallLds];
   long long n = (long long)*count;
   if (n > cap) n = cap;
-  if (n <= 1) return;
+  const long long base = (long long)blockIdx.x * kSmallLds;
+  if (base >= n || n <= 1) return;
+  const long long m = n - base < kSmallLds ? n - base : kSmallLds;
   long long P = 1;
-  while (P < n) P <<= 1;
-  const Rec maxr = {~0ull, ~0ull, 0u, 0u};
-  if (P <= kSmallLds) {
-    for (long long q = threadIdx.x; q < P; q += blockDim.x) s[q] = q < n ? a[q] : maxr;
-    __syncthreads();
-    for (long long k = 2; k <= P; k <<= 1)
-      for (long long j = k >> 1; j > 0; j >>= 1) {
-        for (long long q = threadIdx.x; q < P; q += blockDim.x) {
-          const long long o = q ^ j;
-          if (o > q) {
-            const bool up = (q & k) == 0;
-            const Rec x = s[q], y = s[o];
-            if (up ? rec_less(y, x) : rec_less(x, y)) { s[q] = y; s[o] = x; }
-          }
-        }
-        __syncthreads();
-      }
-    for (long long q = threadIdx.x; q < n; q += blockDim.x) a[q] = s[q];
-    return;
-  }
-  for (long long q = n + threadIdx.x; q < P; q += blockDim.x) a[q] = maxr;
+  while (P < m) P <<= 1;
+  Rec maxr;
+  maxr.lo = ~0ull; maxr.hi = ~0u; maxr.val = 0u;
+  for (long long q = threadIdx.x; q < P; q += blockDim.x)
+    s[q] = q < m ? a[base + q] : maxr;
   __syncthreads();
   for (long long k = 2; k <= P; k <<= 1)
     for (long long j = k >> 1; j > 0; j >>= 1) {
@@ -625,12 +884,45 @@ __global__ void __launch_bounds__(1024) k_sort_small(
         const long long o = q ^ j;
         if (o > q) {
           const bool up = (q & k) == 0;
-          const Rec x = a[q], y = a[o];
-          if (up ? rec_less(y, x) : rec_less(x, y)) { a[q] = y; a[o] = x; }
+          const Rec x = s[q], y = s[o];
+          if (up ? rec_less(y, x) : rec_less(x, y)) { s[q] = y; s[o] = x; }
         }
       }
       __syncthreads();
     }
+  for (long long q = threadIdx.x; q < m; q += blockDim.x) a[base + q] = s[q];
+}
+
+// One merge round: runs of width w (sorted) pairwise into runs of 2w.
+__global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst,
+                              const unsigned long long* __restrict__ count,
+                              long long cap, long long w) {
+  long long n = (long long)*count;
+  if (n > cap) n = cap;
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long pair = i / (2 * w);
+  const long long a0 = pair * 2 * w;
+  const long long a1 = a0 + w < n ? a0 + w : n;      // run A = [a0, a1)
+  const long long b1 = a1 + w < n ? a1 + w : n;      // run B = [a1, b1)
+  const Rec x = src[i];
+  long long pos;
+  if (i < a1) {
+    long long lo = a1, hi = b1;                        // count of B < x
+    while (lo < hi) {
+      const long long mid = (lo + hi) >> 1;
+      if (rec_less(src[mid], x)) lo = mid + 1; else hi = mid;
+    }
+    pos = a0 + (i - a0) + (lo - a1);
+  } else {
+    long long lo = a0, hi = a1;                        // count of A < x
+    while (lo < hi) {
+      const long long mid = (lo + hi) >> 1;
+      if (rec_less(src[mid], x)) lo = mid + 1; else hi = mid;
+    }
+    pos = a0 + (i - a1) + (lo - a0);
+  }
+  dst[pos] = x;
 }
 
 // Neutrals in cells that hold ionisation events.
@@ -651,7 +943,7 @@ __global__ void k_neutral_cands(Parts p, const uint32_t* __restrict__ key,
   if (hit) {
     if ((long long)s < cap) {
       Rec r;
-      r.hi = cell; r.lo = p.id[i]; r.val = (unsigned)i; r.pad = 0;
+      r.hi = cell; r.lo = p.id[i]; r.val = (unsigned)i;
       nc[s] = r;
     } else {
       atomicOr(&dc->err, kErrEvents);
@@ -662,14 +954,17 @@ __global__ void k_neutral_cands(Parts p, const uint32_t* __restrict__ key,
 // Events (sorted by cell, id): the r-th event of a cell takes the cell's
 // r-th neutral (sorted by id) if there is one.
 __global__ void k_match(const Rec* __restrict__ ev, const Rec* __restrict__ nc,
-                        Rec* __restrict__ ok, long long cap, Counters* dc) {
+                        Rec* __restrict__ ok, uint2* __restrict__ okp,
+                        long long cap, Counters* dc) {
   long long ne = (long long)dc->n_events;
   if (ne > cap) ne = cap;
   long long nn = (long long)dc->n_ncand;
   if (nn > cap) nn = cap;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne;
-       e += (long long)gridDim.x * blockDim.x) {
-    const unsigned long long cell = ev[e].hi;
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  bool hit = false;
+  unsigned nidx = 0;
+  if (e < ne) {
+    const unsigned cell = ev[e].hi;
     long long r = 0;
     while (e - r - 1 >= 0 && ev[e - r - 1].hi == cell) ++r;
     long long lo = 0, hi = nn;
@@ -677,14 +972,17 @@ __global__ void k_match(const Rec* __restrict__ ev, const Rec* __restrict__ nc,
       const long long mid = (lo + hi) >> 1;
       if (nc[mid].hi < cell) lo = mid + 1; else hi = mid;
     }
-    long long end = lo;
-    while (end < nn && nc[end].hi == cell) ++end;
-    if (lo + r < end) {
-      const unsigned long long s = atomicAdd(&dc->n_ok, 1ull);
-      Rec o;
-      o.hi = 0; o.lo = ev[e].lo; o.val = ev[e].val; o.pad = nc[lo + r].val;
-      ok[s] = o;
+    if (lo + r < nn && nc[lo + r].hi == cell) {
+      hit = true;
+      nidx = nc[lo + r].val;
     }
+  }
+  const unsigned long long s = wave_append(hit, &dc->n_ok);
+  if (hit) {
+    Rec o;
+    o.hi = 0; o.lo = ev[e].lo; o.val = (unsigned)s;
+    ok[s] = o;
+    okp[s] = make_uint2(ev[e].val, nidx);
   }
 }
 
@@ -693,15 +991,16 @@ __global__ void k_match(const Rec* __restrict__ ev, const Rec* __restrict__ nc,
 // becomes the Cu+ ion (same position, velocity, id).
 __global__ void k_ionise(Parts pe, Parts pn, Parts pi, uint32_t* __restrict__ ke,
                          uint32_t* __restrict__ kn, uint32_t* __restrict__ ki,
-                         const Rec* __restrict__ ok, MccC m, uint32_t step,
-                         uint64_t seed, long long cap_e, long long cap_i,
-                         Counters* dc) {
+                         const Rec* __restrict__ ok, const uint2* __restrict__ okp,
+                         MccC m, uint32_t step, uint64_t seed, long long cap_e,
+                         long long cap_i, Counters* dc) {
   const long long nok = (long long)dc->n_ok;
   const long long ne0 = (long long)dc->n[0], ni0 = (long long)dc->n[2];
   const unsigned long long id0 = dc->next_id;
   for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < nok;
        r += (long long)gridDim.x * blockDim.x) {
-    const uint32_t ie = ok[r].val, in = ok[r].pad;
+    const uint2 pr = okp[ok[r].val];
+    const uint32_t ie = pr.x, in = pr.y;
     const unsigned long long pid = ok[r].lo;
     double u3, u4, u5, u6, u7, u8;
     uniform2(pid, step, kTagMcc1, seed, u3, u4);
@@ -736,14 +1035,35 @@ __global__ void k_ionise(Parts pe, Parts pn, Parts pi, uint32_t* __restrict__ ke
   }
 }
 
+// Clears the event-cell flags, adds the matched ionisations to the counts
+// and sums the per-tile elastic counts.
 __global__ void k_ionise_commit(Counters* dc, const Rec* __restrict__ ev,
                                 uint8_t* __restrict__ flag, long long cap,
-                                long long cap_e, long long cap_i) {
+                                long long cap_e, long long cap_i,
+                                const uint32_t* __restrict__ el_cnt,
+                                const uint32_t* __restrict__ cand_cnt,
+                                const unsigned* __restrict__ nchunks) {
+  const long long ntiles = *nchunks;
+  __shared__ unsigned long long s[1024], s2[1024];
   long long ne = (long long)dc->n_events;
   if (ne > cap) ne = cap;
   for (long long e = threadIdx.x; e < ne; e += blockDim.x) flag[ev[e].hi] = 0;
+  unsigned long long a = 0, b = 0;
+  for (long long q = threadIdx.x; q <= ntiles; q += blockDim.x) a += el_cnt[q];
+  for (long long q = threadIdx.x; q < ntiles; q += blockDim.x) b += cand_cnt[q];
+  s[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
   __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s[threadIdx.x] += s[threadIdx.x + o];
+      s2[threadIdx.x] += s2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x) return;
+  dc->n_elastic = s[0];
+  dc->n_cand = s2[0] + dc->n_tail_cand;
   long long ok = (long long)dc->n_ok;
   long long add = ok;
   if ((long long)dc->n[0] + add > cap_e) add = cap_e - (long long)dc->n[0];
@@ -776,10 +1096,63 @@ __global__ void k_ab_gather(const Rec* __restrict__ rec,
 }
 
 // ---- binning ------------------------------------------------------------------
-__global__ void k_tile_hist(const uint32_t* __restrict__ key, unsigned* __restrict__ cnt,
-                            GridC g, const unsigned long long* __restrict__ np) {
+// Particles of a binned tile move at most one tile per axis per step, so a
+// tile's particles go to one of its 27 neighbours (slot d); counting per
+// (tile, slot) in LDS needs one global atomic per non-empty slot.
+__device__ __forceinline__ int nb_slot(unsigned src, unsigned dst, const GridC& g) {
+  const int sx = (int)(src % g.tnx), sy = (int)((src / g.tnx) % g.tny),
+            sz = (int)(src / ((unsigned)g.tnx * g.tny));
+  const int dx = (int)(dst % g.tnx), dy = (int)((dst / g.tnx) % g.tny),
+            dz = (int)(dst / ((unsigned)g.tnx * g.tny));
+  int ox = dx - sx, oy = dy - sy;
+  const int oz = dz - sz;
+  if (ox > 1) ox -= g.tnx;
+  if (ox < -1) ox += g.tnx;
+  if (oy > 1) oy -= g.tny;
+  if (oy < -1) oy += g.tny;
+  if (ox < -1 || ox > 1 || oy < -1 || oy > 1 || oz < -1 || oz > 1) return -1;
+  return ((oz + 1) * 3 + (oy + 1)) * 3 + (ox + 1);
+}
+
+// Count the destination tiles of a tile's binned particles.
+__global__ void __launch_bounds__(kT) k_bin_hist_tile(
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ ts,
+    const uint2* __restrict__ chunks, const unsigned* __restrict__ nchunks,
+    unsigned* __restrict__ cnt, GridC g) {
+  __shared__ unsigned sc[27];
+  __shared__ unsigned sdst[27];
+  const unsigned nchk = *nchunks;
+  if (blockIdx.x >= nchk) return;
+  const unsigned cb = xcd_block(blockIdx.x, nchk);
+  const unsigned t = chunks[cb].x;
+  unsigned b, e;
+  piece(ts, t, chunks[cb].y, b, e);
+  if (b == e) return;
+  if (threadIdx.x < 27) sc[threadIdx.x] = 0;
+  __syncthreads();
+  for (unsigned q = b + threadIdx.x; q < e; q += blockDim.x) {
+    const uint32_t k = key[q];
+    if (k == kDead) continue;
+    const unsigned u = tile_of_cell(k, g);
+    const int d = nb_slot(t, u, g);
+    if (d >= 0) {
+      atomicAdd(&sc[d], 1u);
+      sdst[d] = u;
+    } else {
+      atomicAdd(&cnt[u], 1u);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 27 && sc[threadIdx.x]) atomicAdd(&cnt[sdst[threadIdx.x]], sc[threadIdx.x]);
+}
+
+// Unbinned tail (appended particles): run-aggregated global counts.
+__global__ void k_bin_hist_list(const uint32_t* __restrict__ key,
+                                unsigned* __restrict__ cnt, GridC g,
+                                long long first,
+                                const unsigned long long* __restrict__ np) {
   const long long n = (long long)*np;
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
   unsigned t = kDead;
   if (i < n) {
     const uint32_t k = key[i];
@@ -843,25 +1216,74 @@ __global__ void k_scan_apply(const unsigned* __restrict__ in, long long n,
   }
 }
 
-// Move each live particle to its tile's range in the other buffer.  The
-// keys are not carried along: the next push rewrites them.
-__global__ void __launch_bounds__(kT) k_scatter(
+__device__ __forceinline__ void copy_rec(const Parts& src, const Parts& dst,
+                                         long long i, long long d) {
+  dst.x[d] = src.x[i]; dst.y[d] = src.y[i]; dst.z[d] = src.z[i];
+  dst.vx[d] = src.vx[i]; dst.vy[d] = src.vy[i]; dst.vz[d] = src.vz[i];
+  dst.id[d] = src.id[i];
+}
+
+// Move a tile's live particles to their destination ranges in the other
+// buffer: per slot, one global atomic reserves the block's range; ranks
+// within it come from LDS counters.
+__global__ void __launch_bounds__(kT) k_bin_scatter_tile(
     Parts src, Parts dst, const uint32_t* __restrict__ key,
-    unsigned* __restrict__ cursor, GridC g,
+    const uint32_t* __restrict__ ts, const uint2* __restrict__ chunks,
+    const unsigned* __restrict__ nchunks, unsigned* __restrict__ cursor,
+    GridC g) {
+  __shared__ unsigned sc[27], sbase[27], srank[27];
+  __shared__ unsigned sdst[27];
+  const unsigned nchk = *nchunks;
+  if (blockIdx.x >= nchk) return;
+  const unsigned cb = xcd_block(blockIdx.x, nchk);
+  const unsigned t = chunks[cb].x;
+  unsigned b, e;
+  piece(ts, t, chunks[cb].y, b, e);
+  if (b == e) return;
+  if (threadIdx.x < 27) {
+    sc[threadIdx.x] = 0;
+    srank[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  for (unsigned q = b + threadIdx.x; q < e; q += blockDim.x) {
+    const uint32_t k = key[q];
+    if (k == kDead) continue;
+    const unsigned u = tile_of_cell(k, g);
+    const int d = nb_slot(t, u, g);
+    if (d >= 0) {
+      atomicAdd(&sc[d], 1u);
+      sdst[d] = u;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 27 && sc[threadIdx.x])
+    sbase[threadIdx.x] = atomicAdd(&cursor[sdst[threadIdx.x]], sc[threadIdx.x]);
+  __syncthreads();
+  for (unsigned q = b + threadIdx.x; q < e; q += blockDim.x) {
+    const uint32_t k = key[q];
+    if (k == kDead) continue;
+    const unsigned u = tile_of_cell(k, g);
+    const int d = nb_slot(t, u, g);
+    const unsigned pos = d >= 0 ? sbase[d] + atomicAdd(&srank[d], 1u)
+                                : atomicAdd(&cursor[u], 1u);
+    copy_rec(src, dst, q, pos);
+  }
+}
+
+__global__ void __launch_bounds__(kT) k_bin_scatter_list(
+    Parts src, Parts dst, const uint32_t* __restrict__ key,
+    unsigned* __restrict__ cursor, GridC g, long long first,
     const unsigned long long* __restrict__ np) {
   const long long n = (long long)*np;
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
   unsigned t = kDead;
-  uint32_t k = kDead;
   if (i < n) {
-    k = key[i];
+    const uint32_t k = key[i];
     if (k != kDead) t = tile_of_cell(k, g);
   }
   const unsigned d = run_add(t, cursor, true);
   if (t == kDead) return;
-  dst.x[d] = src.x[i]; dst.y[d] = src.y[i]; dst.z[d] = src.z[i];
-  dst.vx[d] = src.vx[i]; dst.vy[d] = src.vy[i]; dst.vz[d] = src.vz[i];
-  dst.id[d] = src.id[i];
+  copy_rec(src, dst, i, d);
 }
 
 __global__ void k_set_count(Counters* dc, int s, const unsigned* __restrict__ ts,
@@ -955,6 +1377,25 @@ long long bound(const pic_ctx* c, int s) {
   return n > 0 ? n : 1;
 }
 
+uint32_t* ts_cur(pic_ctx* c, int s) { return c->tsb[s][c->tcur[s]]; }
+
+// Sort a record list of at most cap entries (device count); tmp holds as
+// many.  The result ends in a.
+void sort_records(pic_ctx* c, Rec* a, Rec* tmp,
+                  const unsigned long long* count, long long cap) {
+  hipStream_t st = c->stream;
+  const long long nchunk = (cap + kSmallLds - 1) / kSmallLds;
+  k_sort_chunks<<<(unsigned)nchunk, 1024, 0, st>>>(a, count, cap);
+  Rec* src = a;
+  Rec* dst = tmp;
+  for (long long w = kSmallLds; w < cap; w *= 2) {
+    k_merge_round<<<nblk(cap), kT, 0, st>>>(src, dst, count, cap, w);
+    Rec* t = src; src = dst; dst = t;
+  }
+  if (src != a)
+    hipMemcpyAsync(a, src, (size_t)cap * sizeof(Rec), hipMemcpyDeviceToDevice, st);
+}
+
 double qm_dt(int s, double dt) {
   const double q = s == 0 ? -kE : (s == 2 ? kE : 0.0);
   const double mass = s == 0 ? kMe : kMcu;
@@ -968,15 +1409,18 @@ void parts_begin_step(pic_ctx* c) {
 }
 
 void parts_deposit(pic_ctx* c) {
+  tmark(c, PIC_PH_DEPOSIT, true);
   hipMemsetAsync(c->acc, 0, c->nnodes * sizeof(long long), c->stream);
-  k_deposit<<<(unsigned)c->ntiles, kT, 0, c->stream>>>(
-      c->P[0][c->cur[0]], c->P[2][c->cur[2]], c->tile_start[0],
-      c->tile_start[2], c->acc, c->g);
+  k_deposit<<<(unsigned)c->nch_bound[0], kT, 0, c->stream>>>(
+      c->P[0][c->cur[0]], c->P[2][c->cur[2]], ts_cur(c, 0), ts_cur(c, 2),
+      c->chunks[0], c->cstart[0] + c->ntiles, c->acc, c->g);
+  tmark(c, PIC_PH_DEPOSIT, false);
 }
 
 // Queue, disk, sphere and Fowler-Nordheim particles, ids in that order.
 void parts_sources(pic_ctx* c, double dt) {
   hipStream_t st = c->stream;
+  tmark(c, PIC_PH_SOURCES, true);
   const uint32_t step = (uint32_t)c->step;
   const uint64_t seed = c->cfg.seed;
   long long n[3] = {c->n[0], c->n[1], c->n[2]};
@@ -1028,11 +1472,11 @@ void parts_sources(pic_ctx* c, double dt) {
     const double c_fn = ((c->g.dx * c->g.dx) * dt) / kE;
     if (c->mixed)
       k_fn_count<float><<<nblk(c->g.nxy), kT, 0, st>>>(
-          reinterpret_cast<const float*>(c->E), c->fn_scan + c->g.nxy + 1, c->g,
+          reinterpret_cast<const float*>(c->E) + 2 * c->nnodes, c->fn_scan + c->g.nxy + 1, c->g,
           s.fn_cx, s.fn_cy, s.fn_radius, a_phi, b_phi, c_fn, step, seed, c->dc);
     else
       k_fn_count<double><<<nblk(c->g.nxy), kT, 0, st>>>(
-          c->E, c->fn_scan + c->g.nxy + 1, c->g, s.fn_cx, s.fn_cy, s.fn_radius,
+          c->E + 2 * c->nnodes, c->fn_scan + c->g.nxy + 1, c->g, s.fn_cx, s.fn_cy, s.fn_radius,
           a_phi, b_phi, c_fn, step, seed, c->dc);
     k_scan1<<<1, 1024, 0, st>>>(c->fn_scan + c->g.nxy + 1, c->fn_scan, c->g.nxy);
     long long cap = c->cfg.max_events;
@@ -1044,6 +1488,7 @@ void parts_sources(pic_ctx* c, double dt) {
         c->dc);
     k_fn_commit<<<1, 1, 0, st>>>(c->dc, cap);
   }
+  tmark(c, PIC_PH_SOURCES, false);
   // Upper bounds of the counts for the launches that follow.
   c->n[0] = n[0] + (s.fn_on ? c->cfg.max_events : 0);
   c->n[1] = n[1];
@@ -1054,83 +1499,173 @@ void parts_push_collide(pic_ctx* c, double dt) {
   hipStream_t st = c->stream;
   const uint32_t step = (uint32_t)c->step;
   const uint64_t seed = c->cfg.seed;
-  MccC m = mcc_constants(c, dt);
+  const MccC m = mcc_constants(c, dt);
+  const long long nn = c->nnodes;
+  const long long nt = c->ntiles;
   hipMemsetAsync(c->ncount, 0, c->ncells * sizeof(int), st);
   const long long ab_cap = c->cfg.max_events;
-  double* kpart = c->partials;
-  // Neutrals first: their per-cell counts are the MCC target densities.
-  const int order[3] = {1, 2, 0};
-  for (int oi = 0; oi < 3; ++oi) {
-    const int s = order[oi];
-    const long long nb = nblk(bound(c, s));
-    Parts p = c->P[s][c->cur[s]];
-    const double mh = 0.5 * (s == 0 ? kMe : kMcu);
-    if (s == 1)
-      k_push<1><<<nb, kT, 0, st>>>(p, c->key[1], c->E, c->g, 0.0, dt, mh,
-                                   c->ncount, c->cand, m, step, seed, c->ab_rec,
-                                   c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc,
-                                   kpart);
-    else if (s == 2)
-      k_push<2><<<nb, kT, 0, st>>>(p, c->key[2], c->E, c->g, qm_dt(2, dt), dt,
-                                   mh, c->ncount, c->cand, m, step, seed,
-                                   c->ab_rec, c->ab_raw_pos, c->ab_raw_vel,
-                                   ab_cap, c->dc, kpart);
-    else
-      k_push<0><<<nb, kT, 0, st>>>(p, c->key[0], c->E, c->g, qm_dt(0, dt), dt,
-                                   mh, c->ncount, c->cand, m, step, seed,
-                                   c->ab_rec, c->ab_raw_pos, c->ab_raw_vel,
-                                   ab_cap, c->dc, kpart);
-    k_sum_partials<<<1, 1024, 0, st>>>(kpart, nb, &c->dc->kinetic[s]);
+  // Partial-sum regions: [0, nt) electrons' tiles, [nt, 2nt) ions' tiles,
+  // then the per-particle kernels' blocks.
+  double* part_e = c->partials;
+  double* part_i = c->partials + c->nch_cap;
+  double* part_l = c->partials + 2 * c->nch_cap;
+  // Neutrals first (all of them, per particle): their per-cell counts are
+  // the MCC target densities.
+  {
+    tmark(c, PIC_PH_PUSH_NEUTRAL, true);
+    const long long nb = nblk(bound(c, 1));
+    k_push_list<1><<<nb, kT, 0, st>>>(
+        c->P[1][c->cur[1]], 0, c->key[1], c->E, nn, c->g, 0.0, dt, c->ncount,
+        c->cand, m, step, seed, c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap,
+        c->dc, part_l);
+    tmark(c, PIC_PH_PUSH_NEUTRAL, false);
+    k_sum_partials<<<1, 1024, 0, st>>>(part_l, nb, nullptr, part_l, 0,
+                                       0.5 * kMcu, &c->dc->kinetic[1]);
   }
-  // Record lists hold max_events entries (buffers are padded to a power of
-  // two for the bitonic sort).
+  // Charged species: binned particles by tile, then the appended tail.
+  tmark(c, PIC_PH_PUSH_ELECTRON, true);
+  TileArgs A;
+  A.pe = c->P[0][c->cur[0]];
+  A.pi = c->P[2][c->cur[2]];
+  A.tse = ts_cur(c, 0);
+  A.tsi = ts_cur(c, 2);
+  A.chunks = c->chunks[0];
+  A.nchunks = c->cstart[0] + nt;
+  A.keye = c->key[0];
+  A.keyi = c->key[2];
+  A.qm_e = qm_dt(0, dt);
+  A.qm_i = qm_dt(2, dt);
+  A.dt = dt;
+  A.ncount = c->ncount;
+  A.cand = c->cand;
+  A.cand_cnt = c->cand_cnt;
+  A.ab_rec = c->ab_rec;
+  A.ab_pos = c->ab_raw_pos;
+  A.ab_vel = c->ab_raw_vel;
+  A.ab_cap = ab_cap;
+  A.part_e = part_e;
+  A.part_i = part_i;
+  const long long nch = c->nch_bound[0];
+  k_push_tile<<<(unsigned)nch, kT, 0, st>>>(A, c->E, nn, c->g, m, step, seed,
+                                            c->dc);
+  tmark(c, PIC_PH_PUSH_ELECTRON, false);
+  tmark(c, PIC_PH_PUSH_ION, true);
+  const long long tail_i = std::max(0ll, bound(c, 2) - c->n_binned[2]);
+  const long long nbi = nblk(tail_i > 0 ? tail_i : 1);
+  k_push_list<2><<<nbi, kT, 0, st>>>(
+      c->P[2][c->cur[2]], c->n_binned[2], c->key[2], c->E, nn, c->g,
+      qm_dt(2, dt), dt, c->ncount, c->cand, m, step, seed, c->ab_rec,
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l);
+  k_sum_partials<<<1, 1024, 0, st>>>(part_i, nch, c->cstart[0] + nt, part_l,
+                                     nbi, 0.5 * kMcu, &c->dc->kinetic[2]);
+  const long long tail_e = std::max(0ll, bound(c, 0) - c->n_binned[0]);
+  const long long nbe = nblk(tail_e > 0 ? tail_e : 1);
+  k_push_list<0><<<nbe, kT, 0, st>>>(
+      c->P[0][c->cur[0]], c->n_binned[0], c->key[0], c->E, nn, c->g,
+      qm_dt(0, dt), dt, c->ncount, c->cand, m, step, seed, c->ab_rec,
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi);
+  k_sum_partials<<<1, 1024, 0, st>>>(part_e, nch, c->cstart[0] + nt,
+                                     part_l + nbi, nbe, 0.5 * kMe,
+                                     &c->dc->kinetic[0]);
+  tmark(c, PIC_PH_PUSH_ION, false);
   const long long cap = c->cfg.max_events;
+  tmark(c, PIC_PH_COLLIDE, true);
   if (m.enabled) {
-    k_mcc<<<kFixedBlocks, kT, 0, st>>>(c->P[0][c->cur[0]], c->key[0], c->cand,
-                                       m, step, seed, c->ev, c->flag, cap, c->dc);
-    k_sort_small<<<1, 1024, 0, st>>>(c->ev, &c->dc->n_events, cap);
+    k_mcc<<<(unsigned)(nch + 1), kT, 0, st>>>(
+        c->P[0][c->cur[0]], c->key[0], c->cand, ts_cur(c, 0), c->cand_cnt,
+        c->chunks[0], c->cstart[0] + nt, c->n_binned[0], m, step, seed, c->ev,
+        c->flag, cap, c->el_cnt, c->dc);
+    sort_records(c, c->ev, c->rec_tmp, &c->dc->n_events, cap);
     k_neutral_cands<<<nblk(bound(c, 1)), kT, 0, st>>>(
         c->P[1][c->cur[1]], c->key[1], c->flag, c->nc, cap, c->dc);
-    k_sort_small<<<1, 1024, 0, st>>>(c->nc, &c->dc->n_ncand, cap);
-    k_match<<<64, kT, 0, st>>>(c->ev, c->nc, c->ok, cap, c->dc);
-    k_sort_small<<<1, 1024, 0, st>>>(c->ok, &c->dc->n_ok, cap);
+    sort_records(c, c->nc, c->rec_tmp, &c->dc->n_ncand, cap);
+    k_match<<<nblk(cap), kT, 0, st>>>(c->ev, c->nc, c->ok, c->okp, cap, c->dc);
+    sort_records(c, c->ok, c->rec_tmp, &c->dc->n_ok, cap);
     k_ionise<<<64, kT, 0, st>>>(c->P[0][c->cur[0]], c->P[1][c->cur[1]],
                                 c->P[2][c->cur[2]], c->key[0], c->key[1],
-                                c->key[2], c->ok, m, step, seed,
+                                c->key[2], c->ok, c->okp, m, step, seed,
                                 c->cfg.capacity[0], c->cfg.capacity[2], c->dc);
     k_ionise_commit<<<1, 1024, 0, st>>>(c->dc, c->ev, c->flag, cap,
-                                        c->cfg.capacity[0], c->cfg.capacity[2]);
+                                        c->cfg.capacity[0], c->cfg.capacity[2],
+                                        c->el_cnt, c->cand_cnt,
+                                        c->cstart[0] + nt);
     c->n[0] += cap;  // bound: secondaries
     c->n[2] += cap;
   }
+  tmark(c, PIC_PH_COLLIDE, false);
   // Cathode list sorted by (species, id).
-  k_sort_small<<<1, 1024, 0, st>>>(c->ab_rec, &c->dc->n_ab, cap);
+  tmark(c, PIC_PH_ABSORBED, true);
+  sort_records(c, c->ab_rec, c->rec_tmp, &c->dc->n_ab, cap);
   k_ab_gather<<<64, kT, 0, st>>>(c->ab_rec, c->ab_raw_pos, c->ab_raw_vel,
                                  c->ab_species, c->ab_id, c->ab_pos, c->ab_vel,
                                  cap, c->dc);
+  tmark(c, PIC_PH_ABSORBED, false);
 }
 
+// Bin one species by tile into the other buffer (removing dead particles):
+// destination counts from the binned ranges (per tile) and the appended
+// tail (per particle), an exclusive scan, then the scatter.
 void parts_bin_species(pic_ctx* c, int s) {
   hipStream_t st = c->stream;
-  const long long nb = nblk(bound(c, s));
-  hipMemsetAsync(c->tile_cursor, 0, (c->ntiles + 1) * sizeof(unsigned), st);
-  k_tile_hist<<<nb, kT, 0, st>>>(c->key[s], c->tile_cursor, c->g, &c->dc->n[s]);
-  const long long nsb = (c->ntiles + 1 + kScanPer - 1) / kScanPer;
-  k_scan_blocks<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, c->ntiles,
-                                              c->scan_block);
+  const long long nt = c->ntiles;
+  uint32_t* ts_old = ts_cur(c, s);
+  uint32_t* ts_new = c->tsb[s][c->tcur[s] ^ 1];
+  hipMemsetAsync(c->tile_cursor, 0, (nt + 1) * sizeof(unsigned), st);
+  const int L = s == 1 ? 1 : 0;     // chunk list of the species
+  k_bin_hist_tile<<<(unsigned)c->nch_bound[L], kT, 0, st>>>(
+      c->key[s], ts_old, c->chunks[L], c->cstart[L] + nt, c->tile_cursor, c->g);
+  const long long tail = std::max(0ll, bound(c, s) - c->n_binned[s]);
+  if (tail > 0)
+    k_bin_hist_list<<<nblk(tail), kT, 0, st>>>(c->key[s], c->tile_cursor, c->g,
+                                               c->n_binned[s], &c->dc->n[s]);
+  const long long nsb = (nt + 1 + kScanPer - 1) / kScanPer;
+  k_scan_blocks<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt, c->scan_block);
   k_scan1<<<1, 1024, 0, st>>>(c->scan_block, c->scan_block + nsb + 1, nsb);
-  k_scan_apply<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, c->ntiles,
-                                             c->scan_block + nsb + 1,
-                                             c->tile_start[s], c->tile_cursor);
+  k_scan_apply<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt,
+                                             c->scan_block + nsb + 1, ts_new,
+                                             c->tile_cursor);
   const int o = c->cur[s] ^ 1;
-  k_scatter<<<nb, kT, 0, st>>>(c->P[s][c->cur[s]], c->P[s][o], c->key[s],
-                               c->tile_cursor, c->g, &c->dc->n[s]);
-  k_set_count<<<1, 1, 0, st>>>(c->dc, s, c->tile_start[s], c->ntiles);
+  k_bin_scatter_tile<<<(unsigned)c->nch_bound[L], kT, 0, st>>>(
+      c->P[s][c->cur[s]], c->P[s][o], c->key[s], ts_old, c->chunks[L],
+      c->cstart[L] + nt, c->tile_cursor, c->g);
+  if (tail > 0)
+    k_bin_scatter_list<<<nblk(tail), kT, 0, st>>>(
+        c->P[s][c->cur[s]], c->P[s][o], c->key[s], c->tile_cursor, c->g,
+        c->n_binned[s], &c->dc->n[s]);
+  k_set_count<<<1, 1, 0, st>>>(c->dc, s, ts_new, nt);
   c->cur[s] = o;
+  c->tcur[s] ^= 1;
+}
+
+// Chunk lists of the current tile ranges: list 0 serves electrons and
+// ions together, list 1 the neutrals.  hb: host bound of the particles the
+// ranges cover (for the launch bounds).
+void parts_chunks(pic_ctx* c, const long long hb[3]) {
+  hipStream_t st = c->stream;
+  const long long nt = c->ntiles;
+  const long long nsb = (nt + 1 + kScanPer - 1) / kScanPer;
+  for (int L = 0; L < 2; ++L) {
+    const uint32_t* ta = L ? ts_cur(c, 1) : ts_cur(c, 0);
+    const uint32_t* tb = L ? nullptr : ts_cur(c, 2);
+    k_chunk_count<<<nblk(nt), kT, 0, st>>>(ta, tb, nt, c->tile_cursor);
+    k_scan_blocks<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt, c->scan_block);
+    k_scan1<<<1, 1024, 0, st>>>(c->scan_block, c->scan_block + nsb + 1, nsb);
+    k_scan_apply<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt,
+                                               c->scan_block + nsb + 1,
+                                               c->cstart[L], c->cstart[L]);
+    k_chunk_fill<<<nblk(nt), kT, 0, st>>>(c->cstart[L], nt, c->chunks[L]);
+    const long long np = L ? hb[1] : hb[0] + hb[2];
+    c->nch_bound[L] = std::min<long long>(nt + np / kChunk + 2, c->nch_cap);
+  }
 }
 
 void parts_bin(pic_ctx* c) {
+  tmark(c, PIC_PH_BIN, true);
   for (int s = 0; s < 3; ++s) parts_bin_species(c, s);
+  long long hb[3];
+  for (int s = 0; s < 3; ++s) hb[s] = bound(c, s);
+  parts_chunks(c, hb);
+  tmark(c, PIC_PH_BIN, false);
 }
 
 void parts_finish_step(pic_ctx* c) { (void)c; }

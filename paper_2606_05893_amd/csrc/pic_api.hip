@@ -125,14 +125,15 @@ size_t carve(pic_ctx* c, char* base) {
       }
     }
     c->key[s] = cv.take<uint32_t>(cap);
-    c->tile_start[s] = cv.take<uint32_t>(c->ntiles + 1);
+    c->tsb[s][0] = cv.take<uint32_t>(c->ntiles + 1);
+    c->tsb[s][1] = cv.take<uint32_t>(c->ntiles + 1);
   }
   c->tile_cursor = cv.take<uint32_t>(c->ntiles + 1);
   const long long nsb = (c->ntiles + 1 + 1023) / 1024;
   c->scan_block = cv.take<uint32_t>(2 * nsb + 2);
   c->acc = cv.take<long long>(c->nnodes);
   c->E = reinterpret_cast<double*>(
-      cv.take<char>(4 * c->nnodes * (long long)(mixed ? 4 : 8)));
+      cv.take<char>(3 * c->nnodes * (long long)(mixed ? 4 : 8)));
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     L.u = L.f = nullptr;
@@ -151,9 +152,17 @@ size_t carve(pic_ctx* c, char* base) {
   c->ncount = cv.take<int>(c->ncells);
   c->flag = cv.take<uint8_t>(c->ncells);
   c->cand = cv.take<uint32_t>(f.capacity[0]);
+  c->cand_cnt = cv.take<uint32_t>(c->nch_cap + 1);
+  c->el_cnt = cv.take<uint32_t>(c->nch_cap + 1);
+  for (int L = 0; L < 2; ++L) {
+    c->chunks[L] = cv.take<uint2>(c->nch_cap);
+    c->cstart[L] = cv.take<uint32_t>(c->ntiles + 1);
+  }
   c->ev = cv.take<Rec>(c->ev_cap_p2);
   c->nc = cv.take<Rec>(c->ev_cap_p2);
   c->ok = cv.take<Rec>(c->ev_cap_p2);
+  c->okp = cv.take<uint2>(c->ev_cap_p2);
+  c->rec_tmp = cv.take<Rec>(c->ev_cap_p2);
   c->ab_rec = cv.take<Rec>(c->ev_cap_p2);
   c->ab_raw_pos = cv.take<double>(3 * f.max_events);
   c->ab_raw_vel = cv.take<double>(3 * f.max_events);
@@ -195,8 +204,10 @@ void derive(pic_ctx* c) {
     h2 *= 4.0;
   }
   long long maxcap = std::max(f.capacity[0], std::max(f.capacity[1], f.capacity[2]));
-  c->npartials = (int)std::max<long long>(
-      {4096, maxcap / 256 + 16, 2ll * (f.nz + 2) + 16});
+  // Chunk lists: at most one chunk per tile plus one per 2048 particles.
+  c->nch_cap = c->ntiles + (f.capacity[0] + f.capacity[1] + f.capacity[2]) / 2048 + 4;
+  c->npartials = (int)(2 * c->nch_cap + 3 * (maxcap / 256 + 64) + 4096 +
+                       2ll * (f.nz + 2));
   c->ev_cap_p2 = pow2_at_least(std::max<long long>(f.max_events, 2));
 }
 
@@ -233,8 +244,24 @@ __global__ void k_deinterleave_E(const char* __restrict__ E, int mixed,
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= n) return;
   for (int d = 0; d < 3; ++d) {
-    out[d * n + t] = mixed ? (double)reinterpret_cast<const float*>(E)[4 * t + d]
-                           : reinterpret_cast<const double*>(E)[4 * t + d];
+    out[d * n + t] = mixed ? (double)reinterpret_cast<const float*>(E)[d * n + t]
+                           : reinterpret_cast<const double*>(E)[d * n + t];
+  }
+}
+
+// Accumulate the elapsed time of every phase recorded since the last
+// collection (the stream has been synchronised).
+void collect_times(pic_ctx* c) {
+  if (!c->timing) return;
+  for (int p = 0; p < PIC_NPHASES; ++p) {
+    if (!c->tpending[p]) continue;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->tev[2 * p], c->tev[2 * p + 1]) ==
+        hipSuccess) {
+      c->tms[p] += ms;
+      c->tcalls[p] += 1;
+    }
+    c->tpending[p] = false;
   }
 }
 
@@ -308,8 +335,11 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   carve(c, base);
   for (int s = 0; s < 3; ++s) {
     c->cur[s] = 0;
+    c->tcur[s] = 0;
     c->n[s] = 0;
+    c->n_binned[s] = 0;
   }
+  c->nch_bound[0] = c->nch_bound[1] = 1;
   c->next_id = 0;
   c->step = 0;
   c->queue_used = 0;
@@ -318,6 +348,8 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   std::memset(&c->src, 0, sizeof(c->src));
   std::memset(&c->last_solve, 0, sizeof(c->last_solve));
   std::memset(&c->hc, 0, sizeof(c->hc));
+  c->timing = false;
+  c->ev_made = false;
   if (!hip_ok(c, hipMemsetAsync(ws, 0, bytes, c->stream), "workspace clear") ||
       !hip_ok(c, hipStreamSynchronize(c->stream), "init synchronise")) {
     delete c;
@@ -327,7 +359,38 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   return PIC_OK;
 }
 
-void pic_destroy(pic_ctx* c) { delete c; }
+void pic_destroy(pic_ctx* c) {
+  if (!c) return;
+  if (c->ev_made)
+    for (int i = 0; i < 2 * PIC_NPHASES; ++i) hipEventDestroy(c->tev[i]);
+  delete c;
+}
+
+pic_status pic_enable_timing(pic_ctx* c, int32_t on) {
+  if (!c) return PIC_ERR_ARG;
+  if (on && !c->ev_made) {
+    for (int i = 0; i < 2 * PIC_NPHASES; ++i)
+      if (!hip_ok(c, hipEventCreate(&c->tev[i]), "event create"))
+        return PIC_ERR_HIP;
+    c->ev_made = true;
+  }
+  c->timing = on != 0;
+  for (int p = 0; p < PIC_NPHASES; ++p) {
+    c->tms[p] = 0.0;
+    c->tcalls[p] = 0;
+    c->tpending[p] = false;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_phase_times(pic_ctx* c, double* ms, int64_t* calls) {
+  if (!c || !ms) return PIC_ERR_ARG;
+  for (int p = 0; p < PIC_NPHASES; ++p) {
+    ms[p] = c->tms[p];
+    if (calls) calls[p] = c->tcalls[p];
+  }
+  return PIC_OK;
+}
 
 pic_status pic_set_collisions(pic_ctx* c, const pic_collisions* k) {
   if (!c || !k) return PIC_ERR_ARG;
@@ -398,13 +461,19 @@ pic_status pic_deposit(pic_ctx* c) {
 
 pic_status pic_field(pic_ctx* c, pic_solve_info* info) {
   if (!c) return PIC_ERR_ARG;
+  tmark(c, PIC_PH_RHS, true);
   field_rhs(c, nullptr);
+  tmark(c, PIC_PH_RHS, false);
   int st = PIC_OK;
   pic_solve_info loc;
+  tmark(c, PIC_PH_POISSON, true);
   field_solve(c, true, &loc, &st);
+  tmark(c, PIC_PH_POISSON, false);
   c->last_solve = loc;
   if (info) *info = loc;
+  tmark(c, PIC_PH_EFIELD, true);
   field_efield(c);
+  tmark(c, PIC_PH_EFIELD, false);
   if (!hip_ok(c, hipGetLastError(), "field launch")) return PIC_ERR_HIP;
   if (st != PIC_OK)
     return set_err(c, (pic_status)st, "Poisson solve did not converge");
@@ -445,9 +514,13 @@ pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
   if (!hip_ok(c, hipGetLastError(), "advance launch")) return PIC_ERR_HIP;
   pic_status st = sync_counters(c);
   if (st != PIC_OK) return st;
-  for (int k = 0; k < 3; ++k) c->n[k] = (long long)c->hc.sorted_n[k];
+  for (int k = 0; k < 3; ++k) {
+    c->n[k] = (long long)c->hc.sorted_n[k];
+    c->n_binned[k] = c->n[k];
+  }
   c->next_id = c->hc.next_id;
   c->step += 1;
+  collect_times(c);
   if (diag) {
     fill_diag(c, diag);
     for (int k = 0; k < 3; ++k) diag->emitted[k] = add[k];
@@ -508,12 +581,19 @@ pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
   if (n > 0 && (!pos || !vel || !ids)) return PIC_ERR_ARG;
   if (c->mixed) return set_err(c, PIC_ERR_STATE, "mixed precision not built");
   parts_load(c, s, n, pos, vel, ids);
+  // The new population has no tile ranges yet: all of it bins as a tail.
+  hipMemsetAsync(c->tsb[s][c->tcur[s]], 0, (c->ntiles + 1) * sizeof(uint32_t),
+                 c->stream);
   c->n[s] = n;
+  c->n_binned[s] = 0;
   k_set_n<<<1, 1, 0, c->stream>>>(c->dc, s, (unsigned long long)n);
   parts_bin_species(c, s);
   pic_status st = sync_counters(c);
   if (st != PIC_OK) return st;
   c->n[s] = (long long)c->hc.sorted_n[s];
+  c->n_binned[s] = c->n[s];
+  const long long hb[3] = {c->n[0], c->n[1], c->n[2]};
+  parts_chunks(c, hb);
   if (c->hc.err) {
     check_flags(c);
     return set_err(c, PIC_ERR_ARG,

@@ -44,9 +44,15 @@ struct pic_ctx {
   pic::PartsM PM[3][2];
   int cur[3];
   uint32_t* key[3];          // cell index of each particle, or kDead
-  uint32_t* tile_start[3];   // ntiles + 1 offsets of the binned order
+  uint32_t* tsb[3][2];       // ntiles + 1 offsets of the binned order
+  int tcur[3];               // which tsb buffer holds the current order
   uint32_t* tile_cursor;     // scatter cursors
   uint32_t* scan_block;      // block sums of the tile scan
+  long long n_binned[3];     // particles covered by the tile ranges
+  uint2* chunks[2];          // (tile, piece) work lists: charged, neutral
+  uint32_t* cstart[2];       // ntiles + 1 chunk offsets per list
+  long long nch_bound[2];    // host bound of the chunk counts
+  long long nch_cap;         // capacity of a chunk list
 
   // Node fields.
   long long* acc;            // int64 charge units
@@ -61,7 +67,11 @@ struct pic_ctx {
   int* ncount;               // neutrals per cell
   uint8_t* flag;             // cells holding ionisation events
   uint32_t* cand;            // electron indices of null-collision candidates
+  uint32_t* cand_cnt;        // candidates per tile
+  uint32_t* el_cnt;          // elastic collisions per tile (+ tail)
   pic::Rec *ev, *nc, *ok;    // events, neutral candidates, matched events
+  uint2* okp;                // (electron, neutral) index of a matched event
+  pic::Rec* rec_tmp;         // merge buffer of the record sorts
   long long ev_cap_p2;       // power-of-two capacity of the record lists
 
   // Cathode-absorbed list: raw (unsorted) and sorted outputs.
@@ -89,9 +99,24 @@ struct pic_ctx {
   int last_vcycles;
   pic_solve_info last_solve;
   std::string err;
+
+  // Optional phase timing (HIP events on the context's stream).
+  bool timing;
+  bool ev_made;
+  hipEvent_t tev[2 * PIC_NPHASES];
+  bool tpending[PIC_NPHASES];
+  double tms[PIC_NPHASES];
+  long long tcalls[PIC_NPHASES];
 };
 
 namespace pic {
+
+// Record the start (begin = true) or end of a timed phase.
+inline void tmark(pic_ctx* c, int ph, bool begin) {
+  if (!c->timing) return;
+  hipEventRecord(c->tev[2 * ph + (begin ? 0 : 1)], c->stream);
+  if (!begin) c->tpending[ph] = true;
+}
 
 // ---- field (k_field.hip) ---------------------------------------------------
 void field_rhs(pic_ctx* c, const double* rho_or_null);
@@ -106,6 +131,7 @@ void parts_sources(pic_ctx* c, double dt);
 void parts_push_collide(pic_ctx* c, double dt);
 void parts_bin(pic_ctx* c);
 void parts_bin_species(pic_ctx* c, int s);
+void parts_chunks(pic_ctx* c, const long long hb[3]);
 void parts_finish_step(pic_ctx* c);
 void parts_load(pic_ctx* c, int s, long long n, const double* pos,
                 const double* vel, const uint64_t* ids);

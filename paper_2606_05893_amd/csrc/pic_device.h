@@ -125,6 +125,7 @@ struct Counters {
   unsigned long long n_near;        // near-threshold draws
   unsigned long long n_ab;          // cathode-absorbed list length
   unsigned long long n_ncand;       // neutrals in cells with events
+  unsigned long long n_tail_cand;   // candidates among unbinned electrons
   unsigned long long sorted_n[3];   // counts after the binning pass
   long long total_charge;
   unsigned int err;                 // sticky error bits (kErr*)
@@ -141,11 +142,12 @@ enum : unsigned int {
   kErrCapacity = 1u, kErrNonFinite = 2u, kErrEvents = 4u, kErrQueue = 8u
 };
 
-// Small-list record sorted by (hi, lo): events, neutral candidates and the
-// absorbed list.
+// Small-list record sorted by (hi, lo): events (cell, electron id),
+// neutral candidates (cell, neutral id), matched events (0, electron id) and
+// the absorbed list (species, id); val is a payload index.
 struct Rec {
-  unsigned long long hi, lo;
-  unsigned int val, pad;
+  unsigned long long lo;
+  unsigned int hi, val;
 };
 
 __device__ __forceinline__ bool rec_less(const Rec& a, const Rec& b) {

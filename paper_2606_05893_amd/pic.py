@@ -109,7 +109,13 @@ EXPORTS = {
     "pic_read_fields": (_c_i32, [_c_p, _c_p, _c_p, _c_p]),
     "pic_set_clock": (_c_i32, [_c_p, _c_i64, _c_u64]),
     "pic_get_diag": (_c_i32, [_c_p, ctypes.POINTER(Diag)]),
+    "pic_enable_timing": (_c_i32, [_c_p, _c_i32]),
+    "pic_phase_times": (_c_i32, [_c_p, ctypes.POINTER(_c_d),
+                                 ctypes.POINTER(_c_i64)]),
 }
+
+PHASES = ("deposit", "rhs", "poisson", "efield", "sources", "push_neutral",
+          "push_ion", "push_electron", "collide", "absorbed", "bin")
 
 _lib = None
 
@@ -332,6 +338,16 @@ class Pic:
         self._call("poisson_solve", _ptr(rho), _ptr(out), 1 if warm else 0,
                    ctypes.byref(info))
         return out, _struct_dict(info)
+
+    def enable_timing(self, on=True):
+        self._call("pic_enable_timing", 1 if on else 0)
+
+    def phase_times(self):
+        """{phase: (total ms, timed executions)} since timing was enabled."""
+        ms = (_c_d * len(PHASES))()
+        calls = (_c_i64 * len(PHASES))()
+        self._call("pic_phase_times", ms, calls)
+        return {k: (ms[i], calls[i]) for i, k in enumerate(PHASES)}
 
     def set_clock(self, step, next_id):
         self._call("pic_set_clock", int(step), int(next_id))
