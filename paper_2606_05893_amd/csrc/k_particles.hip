@@ -149,14 +149,15 @@ __global__ void k_begin(Counters* dc, unsigned long long n0,
 }
 
 // ---- sources ------------------------------------------------------------------
-__global__ void k_append_queue(Parts p, long long dst, const double* __restrict__ qpos,
+template <class PT>
+__global__ void k_append_queue(PT p, long long dst, const double* __restrict__ qpos,
                                const double* __restrict__ qvel, long long n,
-                               unsigned long long id0) {
+                               unsigned long long id0, GridC g) {
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= n) return;
   const long long d = dst + t;
-  p.x[d] = qpos[t]; p.y[d] = qpos[n + t]; p.z[d] = qpos[2 * n + t];
-  p.vx[d] = qvel[t]; p.vy[d] = qvel[n + t]; p.vz[d] = qvel[2 * n + t];
+  Acc<PT>::set_pos(p, d, g, qpos[t], qpos[n + t], qpos[2 * n + t]);
+  Acc<PT>::set_vel(p, d, qvel[t], qvel[n + t], qvel[2 * n + t]);
   p.id[d] = id0 + (unsigned long long)t;
 }
 
@@ -167,7 +168,8 @@ __device__ __forceinline__ double flux_vz(double u, double vth2) {
 // Disk at z = 0.  species 0: electrons (normal speed from a flux-weighted
 // half-Maxwellian, no tangential velocity); species 1: neutrals (Gaussian
 // tangential components, flux-weighted normal component).
-__global__ void k_disk(Parts p, long long dst, long long n,
+template <class PT>
+__global__ void k_disk(PT p, long long dst, long long n,
                        unsigned long long id0, int species, double cx,
                        double cy, double radius, double vth2, GridC g,
                        uint32_t step, uint64_t seed) {
@@ -179,29 +181,25 @@ __global__ void k_disk(Parts p, long long dst, long long n,
   const double r = radius * sqrt(u1);
   const double th = kTwoPi * u2;
   const long long d = dst + t;
-  p.x[d] = wrap_coord(cx + r * cos(th), g.lx);
-  p.y[d] = wrap_coord(cy + r * sin(th), g.ly);
-  p.z[d] = 0.0;
+  Acc<PT>::set_pos(p, d, g, wrap_coord(cx + r * cos(th), g.lx),
+                   wrap_coord(cy + r * sin(th), g.ly), 0.0);
   p.id[d] = id;
   uniform2(id, step, kTagSrc1, seed, u3, u4);
   if (species == 0) {
-    p.vx[d] = 0.0;
-    p.vy[d] = 0.0;
-    p.vz[d] = flux_vz(u3, vth2);
+    Acc<PT>::set_vel(p, d, 0.0, 0.0, flux_vz(u3, vth2));
   } else {
     const double rr = sqrt((-2.0 * vth2) * log(1.0 - u3));
     const double ph = kTwoPi * u4;
-    p.vx[d] = rr * cos(ph);
-    p.vy[d] = rr * sin(ph);
     double u5, u6;
     uniform2(id, step, kTagSrc2, seed, u5, u6);
-    p.vz[d] = flux_vz(u5, vth2);
+    Acc<PT>::set_vel(p, d, rr * cos(ph), rr * sin(ph), flux_vz(u5, vth2));
   }
 }
 
 // Sphere surface source: uniform points on the sphere, Maxwellian velocity
 // with the inward normal component reflected.
-__global__ void k_sphere(Parts p, long long dst, long long n,
+template <class PT>
+__global__ void k_sphere(PT p, long long dst, long long n,
                          unsigned long long id0, double cx, double cy,
                          double cz, double radius, double sig, GridC g,
                          uint32_t step, uint64_t seed) {
@@ -215,9 +213,8 @@ __global__ void k_sphere(Parts p, long long dst, long long n,
   const double ps = kTwoPi * u2;
   const double nx = s * cos(ps), ny = s * sin(ps), nz = c;
   const long long d = dst + t;
-  p.x[d] = wrap_coord(cx + radius * nx, g.lx);
-  p.y[d] = wrap_coord(cy + radius * ny, g.ly);
-  p.z[d] = cz + radius * nz;
+  Acc<PT>::set_pos(p, d, g, wrap_coord(cx + radius * nx, g.lx),
+                   wrap_coord(cy + radius * ny, g.ly), cz + radius * nz);
   p.id[d] = id;
   uniform2(id, step, kTagSrc1, seed, u3, u4);
   const double rr = sqrt(-2.0 * log(1.0 - u3));
@@ -232,7 +229,7 @@ __global__ void k_sphere(Parts p, long long dst, long long n,
     vy = vy - tt * ny;
     vz = vz - tt * nz;
   }
-  p.vx[d] = vx; p.vy[d] = vy; p.vz[d] = vz;
+  Acc<PT>::set_vel(p, d, vx, vy, vz);
 }
 
 // Fowler-Nordheim counts per surface node inside the emitting disk:
@@ -297,8 +294,8 @@ __global__ void k_scan1(const unsigned* __restrict__ in, unsigned* __restrict__ 
   if (tid == 1023) out[n] = s[1023];
 }
 
-template <typename TE>
-__global__ void k_fn_spawn(Parts p, long long dst, long long cap,
+template <class PT>
+__global__ void k_fn_spawn(PT p, long long dst, long long cap,
                            const unsigned* __restrict__ scan, GridC g,
                            unsigned long long id0, double vth2, uint32_t step,
                            uint64_t seed, Counters* dc) {
@@ -320,13 +317,10 @@ __global__ void k_fn_spawn(Parts p, long long dst, long long cap,
   double u1, u2, u3, u4;
   uniform2(id, step, kTagSrc0, seed, u1, u2);
   const long long d = dst + t;
-  p.x[d] = wrap_coord((double)i * g.dx + (u1 - 0.5) * g.dx, g.lx);
-  p.y[d] = wrap_coord((double)j * g.dx + (u2 - 0.5) * g.dx, g.ly);
-  p.z[d] = 0.0;
+  Acc<PT>::set_pos(p, d, g, wrap_coord((double)i * g.dx + (u1 - 0.5) * g.dx, g.lx),
+                   wrap_coord((double)j * g.dx + (u2 - 0.5) * g.dx, g.ly), 0.0);
   uniform2(id, step, kTagSrc1, seed, u3, u4);
-  p.vx[d] = 0.0;
-  p.vy[d] = 0.0;
-  p.vz[d] = flux_vz(u3, vth2);
+  Acc<PT>::set_vel(p, d, 0.0, 0.0, flux_vz(u3, vth2));
   p.id[d] = id;
 }
 
@@ -343,8 +337,9 @@ __global__ void k_fn_commit(Counters* dc, long long cap) {
 // LDS block with 64-bit LDS atomics; the block is then added to the node
 // array with one global atomic per non-zero node.  Particles outside the tile (never, when
 // the binning invariant holds) fall back to global atomics.
+template <class PT>
 __global__ void __launch_bounds__(kT) k_deposit(
-    Parts pe, Parts pi, const uint32_t* __restrict__ tse,
+    PT pe, PT pi, const uint32_t* __restrict__ tse,
     const uint32_t* __restrict__ tsi, const uint2* __restrict__ chunks,
     const unsigned* __restrict__ nchunks, long long* __restrict__ acc,
     GridC g) {
@@ -360,18 +355,14 @@ __global__ void __launch_bounds__(kT) k_deposit(
   for (int q = threadIdx.x; q < 729; q += blockDim.x) s[q] = 0ull;
   __syncthreads();
   for (int sp = 0; sp < 2; ++sp) {
-    const Parts& p = sp ? pi : pe;
+    const PT& p = sp ? pi : pe;
     const uint32_t* ts = sp ? tsi : tse;
     const long long sign = sp ? 1 : -1;
     unsigned b, e;
     piece(ts, t, kp, b, e);
     for (unsigned q = b + threadIdx.x; q < e; q += blockDim.x) {
       int ix, fx, iy, fy, iz, fz;
-      cic_axis(p.x[q], g.inv_dx, ix, fx);
-      cic_axis(p.y[q], g.inv_dx, iy, fy);
-      cic_axis(p.z[q], g.inv_dx, iz, fz);
-      if (ix >= g.nx) ix -= g.nx;
-      if (iy >= g.ny) iy -= g.ny;
+      Acc<PT>::cic(p, q, g, ix, fx, iy, fy, iz, fz);
       const long long wx[2] = {kQ - fx, fx}, wy[2] = {kQ - fy, fy},
                       wz[2] = {kQ - fz, fz};
       const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
@@ -738,6 +729,295 @@ __global__ void __launch_bounds__(kT) k_push_list(
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// ---- mixed-precision push ---------------------------------------------------------
+// Particles as cell index + FP32 offsets in [0, 1) + FP32 velocities; the
+// field is gathered from FP32 node arrays and the kick and drift run in
+// FP32 (the FP32 offset keeps slow neutrals moving, which an FP32 absolute
+// coordinate would freeze).  Cell keys, charge and energies stay exact or
+// FP64.
+struct PushM {
+  float ox, oy, oz, vx, vy, vz;
+  int ix, iy, iz;        // cell after the drift (x, y wrapped)
+};
+
+// Drift in cell units and carry into the cell index; returns the cell key
+// or kDead, and fills the FP64 PushOut (absolute position before the x, y
+// wrap for the cathode crossing point).
+template <int SP>
+__device__ __forceinline__ void finish_push_m(PartsM& p, long long i, PushM q,
+                                              float dtdx, const GridC& g,
+                                              uint32_t* key, int* ncount,
+                                              const MccC& m, uint32_t step,
+                                              uint64_t seed, Counters* dc,
+                                              PushOut& o) {
+  q.ox = q.ox + q.vx * dtdx;
+  q.oy = q.oy + q.vy * dtdx;
+  q.oz = q.oz + q.vz * dtdx;
+  const float cx = floorf(q.ox), cy = floorf(q.oy), cz = floorf(q.oz);
+  q.ox = q.ox - cx; q.oy = q.oy - cy; q.oz = q.oz - cz;
+  int ix = q.ix + (int)cx, iy = q.iy + (int)cy, iz = q.iz + (int)cz;
+  if (q.ox >= 1.0f) { q.ox = 0.0f; ix += 1; }
+  if (q.oy >= 1.0f) { q.oy = 0.0f; iy += 1; }
+  if (q.oz >= 1.0f) { q.oz = 0.0f; iz += 1; }
+  o.vx = (double)q.vx; o.vy = (double)q.vy; o.vz = (double)q.vz;
+  o.x = ((double)ix + (double)q.ox) * g.dx;
+  o.y = ((double)iy + (double)q.oy) * g.dx;
+  o.z = ((double)iz + (double)q.oz) * g.dx;
+  o.ke = (o.vx * o.vx + o.vy * o.vy) + o.vz * o.vz;
+  o.cathode = false;
+  o.cand = false;
+  o.cell = kDead;
+  const int jx = ix >= g.nx ? ix - g.nx : (ix < 0 ? ix + g.nx : ix);
+  const int jy = iy >= g.ny ? iy - g.ny : (iy < 0 ? iy + g.ny : iy);
+  if (jx < 0 || jx >= g.nx || jy < 0 || jy >= g.ny || !(q.ox == q.ox) ||
+      !(q.oy == q.oy) || !(q.oz == q.oz) || !isfinite(q.vx) ||
+      !isfinite(q.vy) || !isfinite(q.vz)) {
+    atomicOr(&dc->err, kErrNonFinite);
+  } else if (iz < 0) {
+    o.cathode = true;
+  } else if (iz >= g.nz) {
+    atomicAdd(&dc->anode[SP], 1ull);
+  } else {
+    o.cell = ((unsigned)iz * (unsigned)g.ny + (unsigned)jy) * (unsigned)g.nx +
+             (unsigned)jx;
+    p.cell[i] = o.cell;
+    p.ox[i] = q.ox; p.oy[i] = q.oy; p.oz[i] = q.oz;
+    p.vx[i] = q.vx; p.vy[i] = q.vy; p.vz[i] = q.vz;
+    if (SP == 1) atomicAdd(&ncount[o.cell], 1);
+  }
+  key[i] = o.cell;
+  if (SP == 0 && o.cell != kDead && m.enabled) {
+    const int nc = ncount[o.cell];
+    if (nc > 0) {
+      const double pstar = 1.0 - exp(-((double)nc * m.c_coll));
+      double u1, u2;
+      uniform2(p.id[i], step, kTagMcc0, seed, u1, u2);
+      if (fabs(u1 - pstar) < 1e-6) atomicAdd(&dc->n_near, 1ull);
+      o.cand = u1 < pstar;
+    }
+  }
+}
+
+// FP32 CIC gather with the quantised weights; E nodes from LDS (tile) or
+// from the global FP32 arrays.
+__device__ __forceinline__ void gather_m(const float* sx, const float* sy,
+                                         const float* sz, int lrow, int rs,
+                                         int ps, int fx, int fy, int fz,
+                                         float& ex, float& ey, float& ez) {
+  const long long wx[2] = {kQ - fx, fx}, wy[2] = {kQ - fy, fy},
+                  wz[2] = {kQ - fz, fz};
+  ex = 0.0f; ey = 0.0f; ez = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const float w = (float)(wx[a] * wy[b] * wz[c]) * 0x1p-39f;
+        const int q = lrow + c * ps + b * rs + a;
+        ex = ex + w * sx[q];
+        ey = ey + w * sy[q];
+        ez = ez + w * sz[q];
+      }
+}
+
+__device__ __forceinline__ void gather_m_global(const float* __restrict__ E,
+                                                long long nn, const GridC& g,
+                                                int ix, int iy, int iz, int fx,
+                                                int fy, int fz, float& ex,
+                                                float& ey, float& ez) {
+  const long long wx[2] = {kQ - fx, fx}, wy[2] = {kQ - fy, fy},
+                  wz[2] = {kQ - fz, fz};
+  ex = 0.0f; ey = 0.0f; ez = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const long long row =
+          ((long long)(iz + c) * g.ny + wrap_index(iy + b, g.ny)) * g.nx;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const float w = (float)(wx[a] * wy[b] * wz[c]) * 0x1p-39f;
+        const long long node = row + wrap_index(ix + a, g.nx);
+        ex = ex + w * E[node];
+        ey = ey + w * E[nn + node];
+        ez = ez + w * E[2 * nn + node];
+      }
+    }
+}
+
+struct TileArgsM {
+  PartsM pe, pi;
+  const uint32_t *tse, *tsi;
+  const uint2* chunks;
+  const unsigned* nchunks;
+  uint32_t *keye, *keyi;
+  float qm_e, qm_i, dtdx;
+  int* ncount;
+  uint32_t* cand;
+  uint32_t* cand_cnt;
+  Rec* ab_rec;
+  double *ab_pos, *ab_vel;
+  long long ab_cap;
+  double *part_e, *part_i;
+};
+
+template <int SP>
+__device__ __forceinline__ void push_one_m(PartsM& p, long long i,
+                                           const float* sx, const float* sy,
+                                           const float* sz, int x0, int y0,
+                                           int z0, const float* __restrict__ E,
+                                           long long nn, const GridC& g,
+                                           float qm, float dtdx, uint32_t* key,
+                                           int* ncount, const MccC& m,
+                                           uint32_t step, uint64_t seed,
+                                           Counters* dc, PushOut& o) {
+  PushM q;
+  Acc<PartsM>::decode(p.cell[i], g, q.ix, q.iy, q.iz);
+  q.ox = p.ox[i]; q.oy = p.oy[i]; q.oz = p.oz[i];
+  q.vx = p.vx[i]; q.vy = p.vy[i]; q.vz = p.vz[i];
+  if (SP != 1) {
+    const int fx = (int)floorf(q.ox * 8192.0f + 0.5f);
+    const int fy = (int)floorf(q.oy * 8192.0f + 0.5f);
+    const int fz = (int)floorf(q.oz * 8192.0f + 0.5f);
+    const int lx = q.ix - x0, ly = q.iy - y0, lz = q.iz - z0;
+    float ex, ey, ez;
+    if (sx && lx >= 0 && lx < kTile && ly >= 0 && ly < kTile && lz >= 0 &&
+        lz < kTile)
+      gather_m(sx, sy, sz, (lz * 9 + ly) * 9 + lx, 9, 81, fx, fy, fz, ex, ey, ez);
+    else
+      gather_m_global(E, nn, g, q.ix, q.iy, q.iz, fx, fy, fz, ex, ey, ez);
+    q.vx = q.vx + qm * ex;
+    q.vy = q.vy + qm * ey;
+    q.vz = q.vz + qm * ez;
+  }
+  finish_push_m<SP>(p, i, q, dtdx, g, key, ncount, m, step, seed, dc, o);
+}
+
+// Sink record from an FP64 PushOut, shared with the FP64 layout.
+__device__ __forceinline__ void sink_m(const PartsM& p, long long i, int sp,
+                                       const PushOut& o, const GridC& g,
+                                       Rec* ab_rec, double* ab_pos,
+                                       double* ab_vel, long long ab_cap,
+                                       Counters* dc) {
+  const unsigned long long slot = wave_append(o.cathode, &dc->n_ab);
+  if (!o.cathode) return;
+  atomicAdd(&dc->cathode[sp], 1ull);
+  if ((long long)slot < ab_cap) {
+    const double tc = -o.z / o.vz;
+    Rec r;
+    r.hi = sp; r.lo = p.id[i]; r.val = (unsigned)slot;
+    ab_rec[slot] = r;
+    ab_pos[3 * slot] = wrap_coord(o.x + o.vx * tc, g.lx);
+    ab_pos[3 * slot + 1] = wrap_coord(o.y + o.vy * tc, g.ly);
+    ab_pos[3 * slot + 2] = 0.0;
+    ab_vel[3 * slot] = o.vx; ab_vel[3 * slot + 1] = o.vy;
+    ab_vel[3 * slot + 2] = o.vz;
+  } else {
+    atomicOr(&dc->err, kErrEvents);
+  }
+}
+
+__global__ void __launch_bounds__(kT) k_push_tile_m(
+    TileArgsM A, const float* __restrict__ E, long long nn, GridC g, MccC m,
+    uint32_t step, uint64_t seed, Counters* dc) {
+  __shared__ float sx[729], sy[729], sz[729];
+  __shared__ double sk[kT];
+  __shared__ unsigned s_cand;
+  const unsigned nchk = *A.nchunks;
+  if (blockIdx.x >= nchk) return;
+  const unsigned cb = xcd_block(blockIdx.x, nchk);
+  const unsigned t = A.chunks[cb].x, kp = A.chunks[cb].y;
+  unsigned be, ee, bi, ei;
+  piece(A.tse, t, kp, be, ee);
+  piece(A.tsi, t, kp, bi, ei);
+  if (be == ee && bi == ei) {
+    if (threadIdx.x == 0) {
+      A.part_e[cb] = 0.0;
+      A.part_i[cb] = 0.0;
+      A.cand_cnt[cb] = 0;
+    }
+    return;
+  }
+  const int tx = (int)(t % g.tnx);
+  const int ty = (int)((t / g.tnx) % g.tny);
+  const int tz = (int)(t / ((unsigned)g.tnx * g.tny));
+  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
+  for (int q = threadIdx.x; q < 729; q += blockDim.x) {
+    const int a = q % 9, b = (q / 9) % 9, c = q / 81;
+    const int gk = z0 + c;
+    float vx = 0.0f, vy = 0.0f, vz = 0.0f;
+    if (gk <= g.nz) {
+      const long long node = ((long long)gk * g.ny + wrap_index(y0 + b, g.ny)) *
+                                 g.nx + wrap_index(x0 + a, g.nx);
+      vx = E[node]; vy = E[nn + node]; vz = E[2 * nn + node];
+    }
+    sx[q] = vx; sy[q] = vy; sz[q] = vz;
+  }
+  if (threadIdx.x == 0) s_cand = 0;
+  __syncthreads();
+  double ke_i = 0.0, ke_e = 0.0;
+  for (unsigned base = bi; base < ei; base += blockDim.x) {
+    const long long i = base + threadIdx.x;
+    PushOut o;
+    o.cathode = false;
+    if (i < ei) {
+      push_one_m<2>(A.pi, i, sx, sy, sz, x0, y0, z0, E, nn, g, A.qm_i, A.dtdx,
+                    A.keyi, A.ncount, m, step, seed, dc, o);
+      ke_i = ke_i + o.ke;
+    }
+    sink_m(A.pi, i, 2, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
+  }
+  for (unsigned base = be; base < ee; base += blockDim.x) {
+    const long long i = base + threadIdx.x;
+    PushOut o;
+    o.cathode = false;
+    o.cand = false;
+    if (i < ee) {
+      push_one_m<0>(A.pe, i, sx, sy, sz, x0, y0, z0, E, nn, g, A.qm_e, A.dtdx,
+                    A.keye, A.ncount, m, step, seed, dc, o);
+      ke_e = ke_e + o.ke;
+      if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = (uint32_t)i;
+    }
+    sink_m(A.pe, i, 0, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
+  }
+  const double si = block_sum(ke_i, sk);
+  const double se = block_sum(ke_e, sk);
+  if (threadIdx.x == 0) {
+    A.part_i[cb] = si;
+    A.part_e[cb] = se;
+    A.cand_cnt[cb] = s_cand;
+  }
+}
+
+template <int SP>
+__global__ void __launch_bounds__(kT) k_push_list_m(
+    PartsM p, long long first, uint32_t* __restrict__ key,
+    const float* __restrict__ E, long long nn, GridC g, float qm, float dtdx,
+    int* __restrict__ ncount, uint32_t* __restrict__ cand, MccC m,
+    uint32_t step, uint64_t seed, Rec* __restrict__ ab_rec,
+    double* __restrict__ ab_pos, double* __restrict__ ab_vel, long long ab_cap,
+    Counters* dc, double* __restrict__ part) {
+  __shared__ double sk[kT];
+  const long long n = (long long)dc->n[SP];
+  const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const bool live = i < n;
+  PushOut o;
+  o.cathode = false;
+  o.cand = false;
+  o.ke = 0.0;
+  if (live)
+    push_one_m<SP>(p, i, nullptr, nullptr, nullptr, 0, 0, 0, E, nn, g, qm,
+                   dtdx, key, ncount, m, step, seed, dc, o);
+  sink_m(p, i, SP, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+  if (SP == 0) {
+    const unsigned long long cs = wave_append(o.cand, &dc->n_tail_cand);
+    if (o.cand) cand[first + cs] = (uint32_t)i;
+  }
+  const double s = block_sum(live ? o.ke : 0.0, sk);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 // Sum of two partial arrays (fixed order), times a factor; the first holds
 // *na_dev entries when na_dev is given (chunk partials), else na.
 __global__ void k_sum_partials(const double* __restrict__ a, long long na,
@@ -780,8 +1060,9 @@ __device__ __forceinline__ double sigma_ion(const MccC& m, double E_eV) {
 // tail (block t == number of chunks): second draw U2 against the cumulative process probabilities
 // (ionisation, then elastic).  Elastic scattering is applied at once;
 // ionisation events are recorded as (cell, electron id) for matching.
+template <class PT>
 __global__ void __launch_bounds__(kT) k_mcc(
-    Parts p, const uint32_t* __restrict__ key, const uint32_t* __restrict__ cand,
+    PT p, const uint32_t* __restrict__ key, const uint32_t* __restrict__ cand,
     const uint32_t* __restrict__ tse, const uint32_t* __restrict__ cand_cnt,
     const uint2* __restrict__ chunks, const unsigned* __restrict__ nchunks,
     long long tail_first, MccC m, uint32_t step,
@@ -811,7 +1092,8 @@ __global__ void __launch_bounds__(kT) k_mcc(
     if (q < e) {
       i = cand[q];
       id = p.id[i];
-      const double vx = p.vx[i], vy = p.vy[i], vz = p.vz[i];
+      double vx, vy, vz;
+      Acc<PT>::vel(p, i, vx, vy, vz);
       double u1, u2;
       uniform2(id, step, kTagMcc0, seed, u1, u2);
       const double v2 = (vx * vx + vy * vy) + vz * vz;
@@ -834,9 +1116,7 @@ __global__ void __launch_bounds__(kT) k_mcc(
         const double cosx = ((vx * nx + vy * ny) + vz * nz) / v;
         const double fac = sqrt(1.0 - m.ratio * (1.0 - cosx));
         const double sp = v * fac;
-        p.vx[i] = sp * nx;
-        p.vy[i] = sp * ny;
-        p.vz[i] = sp * nz;
+        Acc<PT>::set_vel(p, i, sp * nx, sp * ny, sp * nz);
       }
     }
     const unsigned long long s = wave_append(event, &dc->n_events);
@@ -926,7 +1206,8 @@ __global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst
 }
 
 // Neutrals in cells that hold ionisation events.
-__global__ void k_neutral_cands(Parts p, const uint32_t* __restrict__ key,
+template <class PT>
+__global__ void k_neutral_cands(PT p, const uint32_t* __restrict__ key,
                                 const uint8_t* __restrict__ flag,
                                 Rec* __restrict__ nc, long long cap,
                                 Counters* dc) {
@@ -989,7 +1270,8 @@ __global__ void k_match(const Rec* __restrict__ ev, const Rec* __restrict__ nc,
 // Matched events in primary-id order: secondary ids next_id + rank; energy
 // above threshold shared uniformly, both electrons isotropic; the neutral
 // becomes the Cu+ ion (same position, velocity, id).
-__global__ void k_ionise(Parts pe, Parts pn, Parts pi, uint32_t* __restrict__ ke,
+template <class PT>
+__global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
                          uint32_t* __restrict__ kn, uint32_t* __restrict__ ki,
                          const Rec* __restrict__ ok, const uint2* __restrict__ okp,
                          MccC m, uint32_t step, uint64_t seed, long long cap_e,
@@ -1006,7 +1288,8 @@ __global__ void k_ionise(Parts pe, Parts pn, Parts pi, uint32_t* __restrict__ ke
     uniform2(pid, step, kTagMcc1, seed, u3, u4);
     uniform2(pid, step, kTagMcc2, seed, u5, u6);
     uniform2(pid, step, kTagMcc3, seed, u7, u8);
-    const double vx = pe.vx[ie], vy = pe.vy[ie], vz = pe.vz[ie];
+    double vx, vy, vz;
+    Acc<PT>::vel(pe, ie, vx, vy, vz);
     const double v2 = (vx * vx + vy * vy) + vz * vz;
     const double E_eV = (m.half_me * v2) / kE;
     const double avail = E_eV - m.ion_I;
@@ -1017,16 +1300,14 @@ __global__ void k_ionise(Parts pe, Parts pn, Parts pi, uint32_t* __restrict__ ke
     double px, py, pz, sx, sy, sz;
     isotropic(u4, u5, px, py, pz);
     isotropic(u6, u7, sx, sy, sz);
-    pe.vx[ie] = vp * px; pe.vy[ie] = vp * py; pe.vz[ie] = vp * pz;
+    Acc<PT>::set_vel(pe, ie, vp * px, vp * py, vp * pz);
     const long long de = ne0 + r, di = ni0 + r;
     if (de < cap_e && di < cap_i) {
-      pe.x[de] = pe.x[ie]; pe.y[de] = pe.y[ie]; pe.z[de] = pe.z[ie];
-      pe.vx[de] = vs * sx; pe.vy[de] = vs * sy; pe.vz[de] = vs * sz;
+      Acc<PT>::copy_pos(pe, ie, pe, de);
+      Acc<PT>::set_vel(pe, de, vs * sx, vs * sy, vs * sz);
       pe.id[de] = id0 + (unsigned long long)r;
       ke[de] = ke[ie];
-      pi.x[di] = pn.x[in]; pi.y[di] = pn.y[in]; pi.z[di] = pn.z[in];
-      pi.vx[di] = pn.vx[in]; pi.vy[di] = pn.vy[in]; pi.vz[di] = pn.vz[in];
-      pi.id[di] = pn.id[in];
+      Acc<PT>::copy(pn, in, pi, di);
       ki[di] = kn[in];
     } else {
       atomicOr(&dc->err, kErrCapacity);
@@ -1216,18 +1497,13 @@ __global__ void k_scan_apply(const unsigned* __restrict__ in, long long n,
   }
 }
 
-__device__ __forceinline__ void copy_rec(const Parts& src, const Parts& dst,
-                                         long long i, long long d) {
-  dst.x[d] = src.x[i]; dst.y[d] = src.y[i]; dst.z[d] = src.z[i];
-  dst.vx[d] = src.vx[i]; dst.vy[d] = src.vy[i]; dst.vz[d] = src.vz[i];
-  dst.id[d] = src.id[i];
-}
 
 // Move a tile's live particles to their destination ranges in the other
 // buffer: per slot, one global atomic reserves the block's range; ranks
 // within it come from LDS counters.
+template <class PT>
 __global__ void __launch_bounds__(kT) k_bin_scatter_tile(
-    Parts src, Parts dst, const uint32_t* __restrict__ key,
+    PT src, PT dst, const uint32_t* __restrict__ key,
     const uint32_t* __restrict__ ts, const uint2* __restrict__ chunks,
     const unsigned* __restrict__ nchunks, unsigned* __restrict__ cursor,
     GridC g) {
@@ -1266,12 +1542,13 @@ __global__ void __launch_bounds__(kT) k_bin_scatter_tile(
     const int d = nb_slot(t, u, g);
     const unsigned pos = d >= 0 ? sbase[d] + atomicAdd(&srank[d], 1u)
                                 : atomicAdd(&cursor[u], 1u);
-    copy_rec(src, dst, q, pos);
+    Acc<PT>::copy(src, q, dst, pos);
   }
 }
 
+template <class PT>
 __global__ void __launch_bounds__(kT) k_bin_scatter_list(
-    Parts src, Parts dst, const uint32_t* __restrict__ key,
+    PT src, PT dst, const uint32_t* __restrict__ key,
     unsigned* __restrict__ cursor, GridC g, long long first,
     const unsigned long long* __restrict__ np) {
   const long long n = (long long)*np;
@@ -1283,31 +1560,13 @@ __global__ void __launch_bounds__(kT) k_bin_scatter_list(
   }
   const unsigned d = run_add(t, cursor, true);
   if (t == kDead) return;
-  copy_rec(src, dst, i, d);
+  Acc<PT>::copy(src, i, dst, d);
 }
 
 __global__ void k_set_count(Counters* dc, int s, const unsigned* __restrict__ ts,
                             long long ntiles) {
   dc->n[s] = ts[ntiles];
   dc->sorted_n[s] = ts[ntiles];
-}
-
-// Cell keys of loaded particles; flags out-of-domain or non-finite input.
-__global__ void k_keys(Parts p, uint32_t* __restrict__ key, long long n,
-                       GridC g, Counters* dc) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double x = p.x[i], y = p.y[i], z = p.z[i];
-  const double gz = z * g.inv_dx;
-  const bool ok = x >= 0.0 && x < g.lx && y >= 0.0 && y < g.ly && gz >= 0.0 &&
-                  gz < (double)g.nz && isfinite(p.vx[i]) && isfinite(p.vy[i]) &&
-                  isfinite(p.vz[i]);
-  if (!ok) {
-    atomicOr(&dc->err, kErrNonFinite);
-    key[i] = kDead;
-    return;
-  }
-  key[i] = cell_of(x, y, z, g);
 }
 
 // Count injected particles outside the domain (or non-finite).
@@ -1324,22 +1583,54 @@ __global__ void k_validate(const double* __restrict__ pos,
   if (!ok) atomicAdd(bad, 1ull);
 }
 
-__global__ void k_load(Parts p, const double* __restrict__ pos,
-                       const double* __restrict__ vel,
-                       const uint64_t* __restrict__ ids, long long n) {
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  p.x[t] = pos[t]; p.y[t] = pos[n + t]; p.z[t] = pos[2 * n + t];
-  p.vx[t] = vel[t]; p.vy[t] = vel[n + t]; p.vz[t] = vel[2 * n + t];
-  p.id[t] = ids[t];
+__device__ __forceinline__ uint32_t load_key(const Parts&, long long, double x,
+                                             double y, double z,
+                                             const GridC& g) {
+  return cell_of(x, y, z, g);
+}
+__device__ __forceinline__ uint32_t load_key(const PartsM& p, long long t,
+                                             double, double, double,
+                                             const GridC&) {
+  return p.cell[t];
 }
 
-__global__ void k_read(Parts p, double* __restrict__ pos, double* __restrict__ vel,
-                       uint64_t* __restrict__ ids, long long n) {
+// Load caller particles (FP64 SoA) and their cell keys; out-of-domain or
+// non-finite input is flagged and keyed dead (dropped by the binning).
+template <class PT>
+__global__ void k_load(PT p, const double* __restrict__ pos,
+                       const double* __restrict__ vel,
+                       const uint64_t* __restrict__ ids,
+                       uint32_t* __restrict__ key, long long n, GridC g,
+                       Counters* dc) {
   const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (t >= n) return;
-  pos[t] = p.x[t]; pos[n + t] = p.y[t]; pos[2 * n + t] = p.z[t];
-  vel[t] = p.vx[t]; vel[n + t] = p.vy[t]; vel[2 * n + t] = p.vz[t];
+  const double x = pos[t], y = pos[n + t], z = pos[2 * n + t];
+  const double vx = vel[t], vy = vel[n + t], vz = vel[2 * n + t];
+  p.id[t] = ids[t];
+  const double gz = z * g.inv_dx;
+  const bool ok = x >= 0.0 && x < g.lx && y >= 0.0 && y < g.ly && gz >= 0.0 &&
+                  gz < (double)g.nz && isfinite(vx) && isfinite(vy) &&
+                  isfinite(vz);
+  if (!ok) {
+    atomicOr(&dc->err, kErrNonFinite);
+    key[t] = kDead;
+    return;
+  }
+  Acc<PT>::set_pos(p, t, g, x, y, z);
+  Acc<PT>::set_vel(p, t, vx, vy, vz);
+  key[t] = load_key(p, t, x, y, z, g);
+}
+
+template <class PT>
+__global__ void k_read(PT p, double* __restrict__ pos, double* __restrict__ vel,
+                       uint64_t* __restrict__ ids, long long n, GridC g) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  double x, y, z, vx, vy, vz;
+  Acc<PT>::pos(p, t, g, x, y, z);
+  Acc<PT>::vel(p, t, vx, vy, vz);
+  pos[t] = x; pos[n + t] = y; pos[2 * n + t] = z;
+  vel[t] = vx; vel[n + t] = vy; vel[2 * n + t] = vz;
   ids[t] = p.id[t];
 }
 
@@ -1402,34 +1693,37 @@ double qm_dt(int s, double dt) {
   return (q / mass) * dt;
 }
 
-}  // namespace
+// Particle buffers of a layout.
+template <class PT>
+PT buf(pic_ctx* c, int s, int b);
+template <>
+Parts buf<Parts>(pic_ctx* c, int s, int b) { return c->P[s][b]; }
+template <>
+PartsM buf<PartsM>(pic_ctx* c, int s, int b) { return c->PM[s][b]; }
 
-void parts_begin_step(pic_ctx* c) {
-  (void)c;
-}
+template <class PT>
+PT cur(pic_ctx* c, int s) { return buf<PT>(c, s, c->cur[s]); }
 
-void parts_deposit(pic_ctx* c) {
-  tmark(c, PIC_PH_DEPOSIT, true);
-  hipMemsetAsync(c->acc, 0, c->nnodes * sizeof(long long), c->stream);
-  k_deposit<<<(unsigned)c->nch_bound[0], kT, 0, c->stream>>>(
-      c->P[0][c->cur[0]], c->P[2][c->cur[2]], ts_cur(c, 0), ts_cur(c, 2),
-      c->chunks[0], c->cstart[0] + c->ntiles, c->acc, c->g);
-  tmark(c, PIC_PH_DEPOSIT, false);
+template <class PT>
+void deposit_t(pic_ctx* c) {
+  k_deposit<PT><<<(unsigned)c->nch_bound[0], kT, 0, c->stream>>>(
+      cur<PT>(c, 0), cur<PT>(c, 2), ts_cur(c, 0), ts_cur(c, 2), c->chunks[0],
+      c->cstart[0] + c->ntiles, c->acc, c->g);
 }
 
 // Queue, disk, sphere and Fowler-Nordheim particles, ids in that order.
-void parts_sources(pic_ctx* c, double dt) {
+template <class PT>
+void sources_t(pic_ctx* c, double dt) {
   hipStream_t st = c->stream;
-  tmark(c, PIC_PH_SOURCES, true);
   const uint32_t step = (uint32_t)c->step;
   const uint64_t seed = c->cfg.seed;
   long long n[3] = {c->n[0], c->n[1], c->n[2]};
   unsigned long long nid = c->next_id;
   for (const QueueCall& q : c->queue) {
     if (q.n <= 0) continue;
-    k_append_queue<<<nblk(q.n), kT, 0, st>>>(
-        c->P[q.species][c->cur[q.species]], n[q.species], c->q_pos + 3 * q.offset,
-        c->q_vel + 3 * q.offset, q.n, nid);
+    k_append_queue<PT><<<nblk(q.n), kT, 0, st>>>(
+        cur<PT>(c, q.species), n[q.species], c->q_pos + 3 * q.offset,
+        c->q_vel + 3 * q.offset, q.n, nid, c->g);
     n[q.species] += q.n;
     nid += q.n;
   }
@@ -1439,16 +1733,16 @@ void parts_sources(pic_ctx* c, double dt) {
   if (s.disk_on) {
     if (s.disk_n_e > 0) {
       const double vth2 = (s.disk_kT_e_eV * kE) / kMe;
-      k_disk<<<nblk(s.disk_n_e), kT, 0, st>>>(
-          c->P[0][c->cur[0]], n[0], s.disk_n_e, nid, 0, s.disk_cx, s.disk_cy,
+      k_disk<PT><<<nblk(s.disk_n_e), kT, 0, st>>>(
+          cur<PT>(c, 0), n[0], s.disk_n_e, nid, 0, s.disk_cx, s.disk_cy,
           s.disk_radius, vth2, c->g, step, seed);
       n[0] += s.disk_n_e;
       nid += s.disk_n_e;
     }
     if (s.disk_n_n > 0) {
       const double vth2 = (kKB * s.disk_T_n_K) / kMcu;
-      k_disk<<<nblk(s.disk_n_n), kT, 0, st>>>(
-          c->P[1][c->cur[1]], n[1], s.disk_n_n, nid, 1, s.disk_cx, s.disk_cy,
+      k_disk<PT><<<nblk(s.disk_n_n), kT, 0, st>>>(
+          cur<PT>(c, 1), n[1], s.disk_n_n, nid, 1, s.disk_cx, s.disk_cy,
           s.disk_radius, vth2, c->g, step, seed);
       n[1] += s.disk_n_n;
       nid += s.disk_n_n;
@@ -1456,8 +1750,8 @@ void parts_sources(pic_ctx* c, double dt) {
   }
   if (s.sphere_on && s.sph_n > 0) {
     const double sig = sqrt((kKB * s.sph_T_K) / kMcu);
-    k_sphere<<<nblk(s.sph_n), kT, 0, st>>>(
-        c->P[1][c->cur[1]], n[1], s.sph_n, nid, s.sph_cx, s.sph_cy, s.sph_cz,
+    k_sphere<PT><<<nblk(s.sph_n), kT, 0, st>>>(
+        cur<PT>(c, 1), n[1], s.sph_n, nid, s.sph_cx, s.sph_cy, s.sph_cz,
         s.sph_radius, sig, c->g, step, seed);
     n[1] += s.sph_n;
     nid += s.sph_n;
@@ -1472,61 +1766,52 @@ void parts_sources(pic_ctx* c, double dt) {
     const double c_fn = ((c->g.dx * c->g.dx) * dt) / kE;
     if (c->mixed)
       k_fn_count<float><<<nblk(c->g.nxy), kT, 0, st>>>(
-          reinterpret_cast<const float*>(c->E) + 2 * c->nnodes, c->fn_scan + c->g.nxy + 1, c->g,
-          s.fn_cx, s.fn_cy, s.fn_radius, a_phi, b_phi, c_fn, step, seed, c->dc);
+          reinterpret_cast<const float*>(c->E) + 2 * c->nnodes,
+          c->fn_scan + c->g.nxy + 1, c->g, s.fn_cx, s.fn_cy, s.fn_radius, a_phi,
+          b_phi, c_fn, step, seed, c->dc);
     else
       k_fn_count<double><<<nblk(c->g.nxy), kT, 0, st>>>(
-          c->E + 2 * c->nnodes, c->fn_scan + c->g.nxy + 1, c->g, s.fn_cx, s.fn_cy, s.fn_radius,
-          a_phi, b_phi, c_fn, step, seed, c->dc);
+          c->E + 2 * c->nnodes, c->fn_scan + c->g.nxy + 1, c->g, s.fn_cx,
+          s.fn_cy, s.fn_radius, a_phi, b_phi, c_fn, step, seed, c->dc);
     k_scan1<<<1, 1024, 0, st>>>(c->fn_scan + c->g.nxy + 1, c->fn_scan, c->g.nxy);
     long long cap = c->cfg.max_events;
     if (n[0] + cap > c->cfg.capacity[0]) cap = c->cfg.capacity[0] - n[0];
     if (cap < 0) cap = 0;
     const double vth2 = (s.fn_kT_e_eV * kE) / kMe;
-    k_fn_spawn<double><<<nblk(c->cfg.max_events > 0 ? c->cfg.max_events : 1), kT, 0, st>>>(
-        c->P[0][c->cur[0]], n[0], cap, c->fn_scan, c->g, nid, vth2, step, seed,
-        c->dc);
+    k_fn_spawn<PT><<<nblk(c->cfg.max_events > 0 ? c->cfg.max_events : 1), kT, 0, st>>>(
+        cur<PT>(c, 0), n[0], cap, c->fn_scan, c->g, nid, vth2, step, seed, c->dc);
     k_fn_commit<<<1, 1, 0, st>>>(c->dc, cap);
   }
-  tmark(c, PIC_PH_SOURCES, false);
   // Upper bounds of the counts for the launches that follow.
   c->n[0] = n[0] + (s.fn_on ? c->cfg.max_events : 0);
   c->n[1] = n[1];
   c->n[2] = n[2];
 }
 
-void parts_push_collide(pic_ctx* c, double dt) {
+// Pushes of the FP64 layout.
+void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
+               double* part_i, double* part_l, long long& nbi, long long& nbe) {
   hipStream_t st = c->stream;
   const uint32_t step = (uint32_t)c->step;
   const uint64_t seed = c->cfg.seed;
-  const MccC m = mcc_constants(c, dt);
   const long long nn = c->nnodes;
   const long long nt = c->ntiles;
-  hipMemsetAsync(c->ncount, 0, c->ncells * sizeof(int), st);
   const long long ab_cap = c->cfg.max_events;
-  // Partial-sum regions: [0, nt) electrons' tiles, [nt, 2nt) ions' tiles,
-  // then the per-particle kernels' blocks.
-  double* part_e = c->partials;
-  double* part_i = c->partials + c->nch_cap;
-  double* part_l = c->partials + 2 * c->nch_cap;
-  // Neutrals first (all of them, per particle): their per-cell counts are
-  // the MCC target densities.
   {
     tmark(c, PIC_PH_PUSH_NEUTRAL, true);
     const long long nb = nblk(bound(c, 1));
     k_push_list<1><<<nb, kT, 0, st>>>(
-        c->P[1][c->cur[1]], 0, c->key[1], c->E, nn, c->g, 0.0, dt, c->ncount,
+        cur<Parts>(c, 1), 0, c->key[1], c->E, nn, c->g, 0.0, dt, c->ncount,
         c->cand, m, step, seed, c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap,
         c->dc, part_l);
     tmark(c, PIC_PH_PUSH_NEUTRAL, false);
     k_sum_partials<<<1, 1024, 0, st>>>(part_l, nb, nullptr, part_l, 0,
                                        0.5 * kMcu, &c->dc->kinetic[1]);
   }
-  // Charged species: binned particles by tile, then the appended tail.
   tmark(c, PIC_PH_PUSH_ELECTRON, true);
   TileArgs A;
-  A.pe = c->P[0][c->cur[0]];
-  A.pi = c->P[2][c->cur[2]];
+  A.pe = cur<Parts>(c, 0);
+  A.pi = cur<Parts>(c, 2);
   A.tse = ts_cur(c, 0);
   A.tsi = ts_cur(c, 2);
   A.chunks = c->chunks[0];
@@ -1545,46 +1830,128 @@ void parts_push_collide(pic_ctx* c, double dt) {
   A.ab_cap = ab_cap;
   A.part_e = part_e;
   A.part_i = part_i;
-  const long long nch = c->nch_bound[0];
-  k_push_tile<<<(unsigned)nch, kT, 0, st>>>(A, c->E, nn, c->g, m, step, seed,
-                                            c->dc);
+  k_push_tile<<<(unsigned)c->nch_bound[0], kT, 0, st>>>(A, c->E, nn, c->g, m,
+                                                         step, seed, c->dc);
   tmark(c, PIC_PH_PUSH_ELECTRON, false);
   tmark(c, PIC_PH_PUSH_ION, true);
   const long long tail_i = std::max(0ll, bound(c, 2) - c->n_binned[2]);
-  const long long nbi = nblk(tail_i > 0 ? tail_i : 1);
+  nbi = nblk(tail_i > 0 ? tail_i : 1);
   k_push_list<2><<<nbi, kT, 0, st>>>(
-      c->P[2][c->cur[2]], c->n_binned[2], c->key[2], c->E, nn, c->g,
+      cur<Parts>(c, 2), c->n_binned[2], c->key[2], c->E, nn, c->g,
       qm_dt(2, dt), dt, c->ncount, c->cand, m, step, seed, c->ab_rec,
       c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l);
-  k_sum_partials<<<1, 1024, 0, st>>>(part_i, nch, c->cstart[0] + nt, part_l,
-                                     nbi, 0.5 * kMcu, &c->dc->kinetic[2]);
   const long long tail_e = std::max(0ll, bound(c, 0) - c->n_binned[0]);
-  const long long nbe = nblk(tail_e > 0 ? tail_e : 1);
+  nbe = nblk(tail_e > 0 ? tail_e : 1);
   k_push_list<0><<<nbe, kT, 0, st>>>(
-      c->P[0][c->cur[0]], c->n_binned[0], c->key[0], c->E, nn, c->g,
+      cur<Parts>(c, 0), c->n_binned[0], c->key[0], c->E, nn, c->g,
       qm_dt(0, dt), dt, c->ncount, c->cand, m, step, seed, c->ab_rec,
       c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi);
+  tmark(c, PIC_PH_PUSH_ION, false);
+}
+
+// Pushes of the mixed layout (FP32 field, kick and drift).
+void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
+                double* part_i, double* part_l, long long& nbi, long long& nbe) {
+  hipStream_t st = c->stream;
+  const uint32_t step = (uint32_t)c->step;
+  const uint64_t seed = c->cfg.seed;
+  const long long nn = c->nnodes;
+  const long long nt = c->ntiles;
+  const long long ab_cap = c->cfg.max_events;
+  const float* E = reinterpret_cast<const float*>(c->E);
+  const float dtdx = (float)(dt * c->g.inv_dx);
+  {
+    tmark(c, PIC_PH_PUSH_NEUTRAL, true);
+    const long long nb = nblk(bound(c, 1));
+    k_push_list_m<1><<<nb, kT, 0, st>>>(
+        cur<PartsM>(c, 1), 0, c->key[1], E, nn, c->g, 0.0f, dtdx, c->ncount,
+        c->cand, m, step, seed, c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap,
+        c->dc, part_l);
+    tmark(c, PIC_PH_PUSH_NEUTRAL, false);
+    k_sum_partials<<<1, 1024, 0, st>>>(part_l, nb, nullptr, part_l, 0,
+                                       0.5 * kMcu, &c->dc->kinetic[1]);
+  }
+  tmark(c, PIC_PH_PUSH_ELECTRON, true);
+  TileArgsM A;
+  A.pe = cur<PartsM>(c, 0);
+  A.pi = cur<PartsM>(c, 2);
+  A.tse = ts_cur(c, 0);
+  A.tsi = ts_cur(c, 2);
+  A.chunks = c->chunks[0];
+  A.nchunks = c->cstart[0] + nt;
+  A.keye = c->key[0];
+  A.keyi = c->key[2];
+  A.qm_e = (float)qm_dt(0, dt);
+  A.qm_i = (float)qm_dt(2, dt);
+  A.dtdx = dtdx;
+  A.ncount = c->ncount;
+  A.cand = c->cand;
+  A.cand_cnt = c->cand_cnt;
+  A.ab_rec = c->ab_rec;
+  A.ab_pos = c->ab_raw_pos;
+  A.ab_vel = c->ab_raw_vel;
+  A.ab_cap = ab_cap;
+  A.part_e = part_e;
+  A.part_i = part_i;
+  k_push_tile_m<<<(unsigned)c->nch_bound[0], kT, 0, st>>>(A, E, nn, c->g, m,
+                                                           step, seed, c->dc);
+  tmark(c, PIC_PH_PUSH_ELECTRON, false);
+  tmark(c, PIC_PH_PUSH_ION, true);
+  const long long tail_i = std::max(0ll, bound(c, 2) - c->n_binned[2]);
+  nbi = nblk(tail_i > 0 ? tail_i : 1);
+  k_push_list_m<2><<<nbi, kT, 0, st>>>(
+      cur<PartsM>(c, 2), c->n_binned[2], c->key[2], E, nn, c->g,
+      (float)qm_dt(2, dt), dtdx, c->ncount, c->cand, m, step, seed, c->ab_rec,
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l);
+  const long long tail_e = std::max(0ll, bound(c, 0) - c->n_binned[0]);
+  nbe = nblk(tail_e > 0 ? tail_e : 1);
+  k_push_list_m<0><<<nbe, kT, 0, st>>>(
+      cur<PartsM>(c, 0), c->n_binned[0], c->key[0], E, nn, c->g,
+      (float)qm_dt(0, dt), dtdx, c->ncount, c->cand, m, step, seed, c->ab_rec,
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi);
+  tmark(c, PIC_PH_PUSH_ION, false);
+}
+
+template <class PT>
+void push_collide_t(pic_ctx* c, double dt) {
+  hipStream_t st = c->stream;
+  const uint32_t step = (uint32_t)c->step;
+  const uint64_t seed = c->cfg.seed;
+  const MccC m = mcc_constants(c, dt);
+  const long long nt = c->ntiles;
+  hipMemsetAsync(c->ncount, 0, c->ncells * sizeof(int), st);
+  // Partial-sum regions: electron chunks, ion chunks, per-particle blocks.
+  double* part_e = c->partials;
+  double* part_i = c->partials + c->nch_cap;
+  double* part_l = c->partials + 2 * c->nch_cap;
+  long long nbi = 1, nbe = 1;
+  if (c->mixed)
+    push_mixed(c, dt, m, part_e, part_i, part_l, nbi, nbe);
+  else
+    push_fp64(c, dt, m, part_e, part_i, part_l, nbi, nbe);
+  const long long nch = c->nch_bound[0];
+  k_sum_partials<<<1, 1024, 0, st>>>(part_i, nch, c->cstart[0] + nt, part_l,
+                                     nbi, 0.5 * kMcu, &c->dc->kinetic[2]);
   k_sum_partials<<<1, 1024, 0, st>>>(part_e, nch, c->cstart[0] + nt,
                                      part_l + nbi, nbe, 0.5 * kMe,
                                      &c->dc->kinetic[0]);
-  tmark(c, PIC_PH_PUSH_ION, false);
   const long long cap = c->cfg.max_events;
   tmark(c, PIC_PH_COLLIDE, true);
   if (m.enabled) {
-    k_mcc<<<(unsigned)(nch + 1), kT, 0, st>>>(
-        c->P[0][c->cur[0]], c->key[0], c->cand, ts_cur(c, 0), c->cand_cnt,
+    k_mcc<PT><<<(unsigned)(nch + 1), kT, 0, st>>>(
+        cur<PT>(c, 0), c->key[0], c->cand, ts_cur(c, 0), c->cand_cnt,
         c->chunks[0], c->cstart[0] + nt, c->n_binned[0], m, step, seed, c->ev,
         c->flag, cap, c->el_cnt, c->dc);
     sort_records(c, c->ev, c->rec_tmp, &c->dc->n_events, cap);
-    k_neutral_cands<<<nblk(bound(c, 1)), kT, 0, st>>>(
-        c->P[1][c->cur[1]], c->key[1], c->flag, c->nc, cap, c->dc);
+    k_neutral_cands<PT><<<nblk(bound(c, 1)), kT, 0, st>>>(
+        cur<PT>(c, 1), c->key[1], c->flag, c->nc, cap, c->dc);
     sort_records(c, c->nc, c->rec_tmp, &c->dc->n_ncand, cap);
     k_match<<<nblk(cap), kT, 0, st>>>(c->ev, c->nc, c->ok, c->okp, cap, c->dc);
     sort_records(c, c->ok, c->rec_tmp, &c->dc->n_ok, cap);
-    k_ionise<<<64, kT, 0, st>>>(c->P[0][c->cur[0]], c->P[1][c->cur[1]],
-                                c->P[2][c->cur[2]], c->key[0], c->key[1],
-                                c->key[2], c->ok, c->okp, m, step, seed,
-                                c->cfg.capacity[0], c->cfg.capacity[2], c->dc);
+    k_ionise<PT><<<64, kT, 0, st>>>(cur<PT>(c, 0), cur<PT>(c, 1), cur<PT>(c, 2),
+                                    c->key[0], c->key[1], c->key[2], c->ok,
+                                    c->okp, m, step, seed, c->cfg.capacity[0],
+                                    c->cfg.capacity[2], c->dc);
     k_ionise_commit<<<1, 1024, 0, st>>>(c->dc, c->ev, c->flag, cap,
                                         c->cfg.capacity[0], c->cfg.capacity[2],
                                         c->el_cnt, c->cand_cnt,
@@ -1603,9 +1970,10 @@ void parts_push_collide(pic_ctx* c, double dt) {
 }
 
 // Bin one species by tile into the other buffer (removing dead particles):
-// destination counts from the binned ranges (per tile) and the appended
+// destination counts from the binned ranges (per chunk) and the appended
 // tail (per particle), an exclusive scan, then the scatter.
-void parts_bin_species(pic_ctx* c, int s) {
+template <class PT>
+void bin_species_t(pic_ctx* c, int s) {
   hipStream_t st = c->stream;
   const long long nt = c->ntiles;
   uint32_t* ts_old = ts_cur(c, s);
@@ -1625,16 +1993,51 @@ void parts_bin_species(pic_ctx* c, int s) {
                                              c->scan_block + nsb + 1, ts_new,
                                              c->tile_cursor);
   const int o = c->cur[s] ^ 1;
-  k_bin_scatter_tile<<<(unsigned)c->nch_bound[L], kT, 0, st>>>(
-      c->P[s][c->cur[s]], c->P[s][o], c->key[s], ts_old, c->chunks[L],
+  k_bin_scatter_tile<PT><<<(unsigned)c->nch_bound[L], kT, 0, st>>>(
+      cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], ts_old, c->chunks[L],
       c->cstart[L] + nt, c->tile_cursor, c->g);
   if (tail > 0)
-    k_bin_scatter_list<<<nblk(tail), kT, 0, st>>>(
-        c->P[s][c->cur[s]], c->P[s][o], c->key[s], c->tile_cursor, c->g,
+    k_bin_scatter_list<PT><<<nblk(tail), kT, 0, st>>>(
+        cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], c->tile_cursor, c->g,
         c->n_binned[s], &c->dc->n[s]);
   k_set_count<<<1, 1, 0, st>>>(c->dc, s, ts_new, nt);
   c->cur[s] = o;
   c->tcur[s] ^= 1;
+}
+
+}  // namespace
+
+void parts_deposit(pic_ctx* c) {
+  tmark(c, PIC_PH_DEPOSIT, true);
+  hipMemsetAsync(c->acc, 0, c->nnodes * sizeof(long long), c->stream);
+  if (c->mixed)
+    deposit_t<PartsM>(c);
+  else
+    deposit_t<Parts>(c);
+  tmark(c, PIC_PH_DEPOSIT, false);
+}
+
+void parts_sources(pic_ctx* c, double dt) {
+  tmark(c, PIC_PH_SOURCES, true);
+  if (c->mixed)
+    sources_t<PartsM>(c, dt);
+  else
+    sources_t<Parts>(c, dt);
+  tmark(c, PIC_PH_SOURCES, false);
+}
+
+void parts_push_collide(pic_ctx* c, double dt) {
+  if (c->mixed)
+    push_collide_t<PartsM>(c, dt);
+  else
+    push_collide_t<Parts>(c, dt);
+}
+
+void parts_bin_species(pic_ctx* c, int s) {
+  if (c->mixed)
+    bin_species_t<PartsM>(c, s);
+  else
+    bin_species_t<Parts>(c, s);
 }
 
 // Chunk lists of the current tile ranges: list 0 serves electrons and
@@ -1668,16 +2071,17 @@ void parts_bin(pic_ctx* c) {
   tmark(c, PIC_PH_BIN, false);
 }
 
-void parts_finish_step(pic_ctx* c) { (void)c; }
-
 void parts_load(pic_ctx* c, int s, long long n, const double* pos,
                 const double* vel, const uint64_t* ids) {
-  hipStream_t st = c->stream;
-  Parts p = c->P[s][c->cur[s]];
-  if (n > 0) {
-    k_load<<<nblk(n), kT, 0, st>>>(p, pos, vel, ids, n);
-    k_keys<<<nblk(n), kT, 0, st>>>(p, c->key[s], n, c->g, c->dc);
-  }
+  if (n <= 0) return;
+  if (c->mixed)
+    k_load<PartsM><<<nblk(n), kT, 0, c->stream>>>(cur<PartsM>(c, s), pos, vel,
+                                                   ids, c->key[s], n, c->g,
+                                                   c->dc);
+  else
+    k_load<Parts><<<nblk(n), kT, 0, c->stream>>>(cur<Parts>(c, s), pos, vel,
+                                                 ids, c->key[s], n, c->g,
+                                                 c->dc);
 }
 
 bool parts_validate(pic_ctx* c, const double* pos, const double* vel,
@@ -1692,17 +2096,15 @@ bool parts_validate(pic_ctx* c, const double* pos, const double* vel,
   return bad == 0;
 }
 
-void parts_keys(pic_ctx* c, int s) {
-  const long long n = c->n[s];
-  if (n > 0)
-    k_keys<<<nblk(n), kT, 0, c->stream>>>(c->P[s][c->cur[s]], c->key[s], n,
-                                          c->g, c->dc);
-}
-
 void parts_read(pic_ctx* c, int s, long long n, double* pos, double* vel,
                 uint64_t* ids) {
-  if (n > 0)
-    k_read<<<nblk(n), kT, 0, c->stream>>>(c->P[s][c->cur[s]], pos, vel, ids, n);
+  if (n <= 0) return;
+  if (c->mixed)
+    k_read<PartsM><<<nblk(n), kT, 0, c->stream>>>(cur<PartsM>(c, s), pos, vel,
+                                                   ids, n, c->g);
+  else
+    k_read<Parts><<<nblk(n), kT, 0, c->stream>>>(cur<Parts>(c, s), pos, vel,
+                                                 ids, n, c->g);
 }
 
 }  // namespace pic

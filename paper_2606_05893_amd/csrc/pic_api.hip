@@ -454,7 +454,6 @@ pic_status pic_inject(pic_ctx* c, int32_t species, int64_t n,
 
 pic_status pic_deposit(pic_ctx* c) {
   if (!c) return PIC_ERR_ARG;
-  if (c->mixed) return set_err(c, PIC_ERR_STATE, "mixed precision not built");
   parts_deposit(c);
   return hip_ok(c, hipGetLastError(), "deposit launch") ? PIC_OK : PIC_ERR_HIP;
 }
@@ -494,7 +493,6 @@ pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
                        pic_diag* diag) {
   if (!c) return PIC_ERR_ARG;
   if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(c, PIC_ERR_ARG, "dt");
-  if (c->mixed) return set_err(c, PIC_ERR_STATE, "mixed precision not built");
   // Host-known additions must fit.
   long long add[3] = {0, 0, 0};
   for (const QueueCall& q : c->queue) add[q.species] += q.n;
@@ -579,7 +577,6 @@ pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
   if (n > c->cfg.capacity[s])
     return set_err(c, PIC_ERR_CAPACITY, "load exceeds capacity");
   if (n > 0 && (!pos || !vel || !ids)) return PIC_ERR_ARG;
-  if (c->mixed) return set_err(c, PIC_ERR_STATE, "mixed precision not built");
   parts_load(c, s, n, pos, vel, ids);
   // The new population has no tile ranges yet: all of it bins as a tail.
   hipMemsetAsync(c->tsb[s][c->tcur[s]], 0, (c->ntiles + 1) * sizeof(uint32_t),

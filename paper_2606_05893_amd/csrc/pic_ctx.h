@@ -125,19 +125,16 @@ void field_efield(pic_ctx* c);
 void field_phi_to_level0(pic_ctx* c);
 
 // ---- particles (k_particles.hip) -------------------------------------------
-void parts_begin_step(pic_ctx* c);
 void parts_deposit(pic_ctx* c);
 void parts_sources(pic_ctx* c, double dt);
 void parts_push_collide(pic_ctx* c, double dt);
 void parts_bin(pic_ctx* c);
 void parts_bin_species(pic_ctx* c, int s);
 void parts_chunks(pic_ctx* c, const long long hb[3]);
-void parts_finish_step(pic_ctx* c);
 void parts_load(pic_ctx* c, int s, long long n, const double* pos,
                 const double* vel, const uint64_t* ids);
 void parts_read(pic_ctx* c, int s, long long n, double* pos, double* vel,
                 uint64_t* ids);
-void parts_keys(pic_ctx* c, int s);
 bool parts_validate(pic_ctx* c, const double* pos, const double* vel,
                     long long n);
 

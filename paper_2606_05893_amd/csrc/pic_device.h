@@ -110,6 +110,138 @@ struct PartsM {
   uint64_t* id;
 };
 
+// Layout accessors: every particle kernel except the pushes is written once
+// against this interface and instantiated for both layouts.
+template <class PT>
+struct Acc;
+
+template <>
+struct Acc<Parts> {
+  static __device__ __forceinline__ void pos(const Parts& p, long long i,
+                                             const GridC&, double& x,
+                                             double& y, double& z) {
+    x = p.x[i]; y = p.y[i]; z = p.z[i];
+  }
+  static __device__ __forceinline__ void set_pos(const Parts& p, long long i,
+                                                 const GridC&, double x,
+                                                 double y, double z) {
+    p.x[i] = x; p.y[i] = y; p.z[i] = z;
+  }
+  static __device__ __forceinline__ void vel(const Parts& p, long long i,
+                                             double& vx, double& vy,
+                                             double& vz) {
+    vx = p.vx[i]; vy = p.vy[i]; vz = p.vz[i];
+  }
+  static __device__ __forceinline__ void set_vel(const Parts& p, long long i,
+                                                 double vx, double vy,
+                                                 double vz) {
+    p.vx[i] = vx; p.vy[i] = vy; p.vz[i] = vz;
+  }
+  // Cell and quantised upper CIC weight per axis (x, y wrapped).
+  static __device__ __forceinline__ void cic(const Parts& p, long long i,
+                                             const GridC& g, int& ix, int& fx,
+                                             int& iy, int& fy, int& iz,
+                                             int& fz) {
+    cic_axis(p.x[i], g.inv_dx, ix, fx);
+    cic_axis(p.y[i], g.inv_dx, iy, fy);
+    cic_axis(p.z[i], g.inv_dx, iz, fz);
+    if (ix >= g.nx) ix -= g.nx;
+    if (iy >= g.ny) iy -= g.ny;
+  }
+  static __device__ __forceinline__ void copy_pos(const Parts& s, long long i,
+                                                  const Parts& d, long long j) {
+    d.x[j] = s.x[i]; d.y[j] = s.y[i]; d.z[j] = s.z[i];
+  }
+  static __device__ __forceinline__ void copy(const Parts& s, long long i,
+                                              const Parts& d, long long j) {
+    d.x[j] = s.x[i]; d.y[j] = s.y[i]; d.z[j] = s.z[i];
+    d.vx[j] = s.vx[i]; d.vy[j] = s.vy[i]; d.vz[j] = s.vz[i];
+    d.id[j] = s.id[i];
+  }
+};
+
+// Split a coordinate into cell and FP32 offset in [0, 1).
+__device__ __forceinline__ void split_coord(double x, double inv_dx, int n,
+                                            bool periodic, int& i, float& o) {
+  const double gg = x * inv_dx;
+  const double fl = floor(gg);
+  i = (int)fl;
+  o = (float)(gg - fl);
+  if (o >= 1.0f) {
+    o = 0.0f;
+    i += 1;
+  }
+  if (periodic) {
+    if (i >= n) i -= n;
+  } else if (i >= n) {           // within rounding of the top face
+    i = n - 1;
+    o = 0x1.fffffep-1f;
+  }
+}
+
+template <>
+struct Acc<PartsM> {
+  static __device__ __forceinline__ void decode(unsigned cell, const GridC& g,
+                                                int& i, int& j, int& k) {
+    i = (int)(cell % (unsigned)g.nx);
+    const unsigned r = cell / (unsigned)g.nx;
+    j = (int)(r % (unsigned)g.ny);
+    k = (int)(r / (unsigned)g.ny);
+  }
+  static __device__ __forceinline__ void pos(const PartsM& p, long long i,
+                                             const GridC& g, double& x,
+                                             double& y, double& z) {
+    int a, b, c;
+    decode(p.cell[i], g, a, b, c);
+    x = ((double)a + (double)p.ox[i]) * g.dx;
+    y = ((double)b + (double)p.oy[i]) * g.dx;
+    z = ((double)c + (double)p.oz[i]) * g.dx;
+  }
+  static __device__ __forceinline__ void set_pos(const PartsM& p, long long i,
+                                                 const GridC& g, double x,
+                                                 double y, double z) {
+    int a, b, c;
+    float ox, oy, oz;
+    split_coord(x, g.inv_dx, g.nx, true, a, ox);
+    split_coord(y, g.inv_dx, g.ny, true, b, oy);
+    split_coord(z, g.inv_dx, g.nz, false, c, oz);
+    p.cell[i] = ((unsigned)c * (unsigned)g.ny + (unsigned)b) * (unsigned)g.nx +
+                (unsigned)a;
+    p.ox[i] = ox; p.oy[i] = oy; p.oz[i] = oz;
+  }
+  static __device__ __forceinline__ void vel(const PartsM& p, long long i,
+                                             double& vx, double& vy,
+                                             double& vz) {
+    vx = (double)p.vx[i]; vy = (double)p.vy[i]; vz = (double)p.vz[i];
+  }
+  static __device__ __forceinline__ void set_vel(const PartsM& p, long long i,
+                                                 double vx, double vy,
+                                                 double vz) {
+    p.vx[i] = (float)vx; p.vy[i] = (float)vy; p.vz[i] = (float)vz;
+  }
+  static __device__ __forceinline__ void cic(const PartsM& p, long long i,
+                                             const GridC& g, int& ix, int& fx,
+                                             int& iy, int& fy, int& iz,
+                                             int& fz) {
+    decode(p.cell[i], g, ix, iy, iz);
+    fx = (int)floorf(p.ox[i] * 8192.0f + 0.5f);
+    fy = (int)floorf(p.oy[i] * 8192.0f + 0.5f);
+    fz = (int)floorf(p.oz[i] * 8192.0f + 0.5f);
+  }
+  static __device__ __forceinline__ void copy_pos(const PartsM& s, long long i,
+                                                  const PartsM& d, long long j) {
+    d.cell[j] = s.cell[i];
+    d.ox[j] = s.ox[i]; d.oy[j] = s.oy[i]; d.oz[j] = s.oz[i];
+  }
+  static __device__ __forceinline__ void copy(const PartsM& s, long long i,
+                                              const PartsM& d, long long j) {
+    d.cell[j] = s.cell[i];
+    d.ox[j] = s.ox[i]; d.oy[j] = s.oy[i]; d.oz[j] = s.oz[i];
+    d.vx[j] = s.vx[i]; d.vy[j] = s.vy[i]; d.vz[j] = s.vz[i];
+    d.id[j] = s.id[i];
+  }
+};
+
 // Device-resident counters of one step.  All are updated with atomics or by
 // single-thread kernels and copied to the host once at the end of a step.
 struct Counters {
