@@ -236,6 +236,49 @@ enum {
 pic_status pic_enable_timing(pic_ctx* ctx, int32_t on);
 pic_status pic_phase_times(pic_ctx* ctx, double* ms, int64_t* calls);
 
+/* ---- Learned Poisson warm start -------------------------------------------
+ * A 3-D U-Net (levels of 16/32/64/128 channels, 3x3x3 convolutions with
+ * bias and ReLU, 2^3 average pooling, nearest upsampling with
+ * concatenation, 1x1x1 head) maps a normalised pair (residual of the warm
+ * start r = b - A phi_prev, previous potential) to a normalised potential
+ * correction; multigrid then finishes the solve to the same residual and
+ * acts as fallback and judge.  BF16 weights and activations, FP32
+ * accumulation on the matrix cores, FP32 master weights with Adam.
+ * Grids are D x H x W voxels (z, y, x), each a multiple of 8; tensors are
+ * channels-last FP32 at the boundary: input (D,H,W,2), target and output
+ * (D,H,W).  Padding: circular in x, y, zero in z.
+ * Parameter vector (pic_unet_param_count FP32 values): per convolution in
+ * the order e0a e0b e1a e1b e2a e2b ba bb d2a d2b d1a d1b d0a d0b, the
+ * weights W[co][tap][ci] (tap = (dz+1)*9 + (dy+1)*3 + (dx+1)) then the
+ * bias[co]; then the head's 16 weights and its bias. */
+typedef struct pic_unet pic_unet;
+int64_t pic_unet_param_count(void);
+pic_status pic_unet_workspace_bytes(int32_t D, int32_t H, int32_t W,
+                                    size_t* bytes);
+/* D, H, W: the largest grid the object will see. */
+pic_status pic_unet_init(int32_t D, int32_t H, int32_t W,
+                         void* workspace_device, size_t bytes,
+                         void* hip_stream, pic_unet** out);
+void pic_unet_destroy(pic_unet* u);
+/* Set (resets the Adam moments) / get the FP32 parameters. */
+pic_status pic_unet_set_params(pic_unet* u, const float* params_device);
+pic_status pic_unet_get_params(pic_unet* u, float* params_device);
+pic_status pic_unet_forward(pic_unet* u, const float* input_device,
+                            int32_t D, int32_t H, int32_t W,
+                            float* out_device);
+/* Mean-squared-error loss of one sample and its parameter gradient
+ * (grad_device may be NULL). */
+pic_status pic_unet_gradients(pic_unet* u, const float* input_device,
+                              const float* target_device, int32_t D,
+                              int32_t H, int32_t W, float* grad_device,
+                              double* loss);
+/* One Adam step on one sample; loss is that sample's loss before it. */
+pic_status pic_unet_train_step(pic_unet* u, const float* input_device,
+                               const float* target_device, int32_t D,
+                               int32_t H, int32_t W, float lr, float beta1,
+                               float beta2, float eps, double* loss);
+const char* pic_unet_last_error(const pic_unet* u);
+
 const char* pic_last_error(const pic_ctx* ctx);
 int32_t pic_abi_version(void);
 

@@ -1,0 +1,857 @@
+// Learned Poisson warm start: a 3-D U-Net (levels of 16/32/64/128
+// channels, 3x3x3 convolutions, average pooling down, nearest upsampling
+// and concatenation up, 1x1x1 head) with BF16 activations and weights and
+// FP32 accumulation on the CDNA4 matrix cores, plus its backward pass and
+// an Adam optimiser with FP32 master weights.
+//
+// Tensors are channels-last (D, H, W, C) BF16; padding is circular in x, y
+// and zero in z.  The 3x3x3 convolution is an implicit GEMM: M = voxels,
+// N = output channels, K = 27 * C_in flattened as (tap, channel) and walked
+// in chunks of 32 by v_mfma_f32_16x16x32_bf16 (lane l holds row l % 16 and
+// k = 8 (l / 16) .. +7 of A and B; D rows 4 (l / 16) .. +3, column l % 16).
+// The backward-data convolution is the same kernel with the kernel flipped
+// and the channel roles swapped; the weight gradient is a second GEMM whose
+// reduction runs over voxels, staged through LDS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "pic.h"
+#include "pic_ctx.h"
+#include "pic_device.h"
+
+struct pic_unet;
+
+namespace pic {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16;  // storage
+
+__device__ __forceinline__ float bf2f(bf16 h) {
+  return __uint_as_float((unsigned)h << 16);
+}
+__device__ __forceinline__ bf16 f2bf(float x) {
+  // Round to nearest even (inputs are finite here; NaN keeps a NaN pattern).
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (bf16)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 load8(const bf16* p) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+__device__ __forceinline__ bf16x8 zero8() {
+  const uint4 v = make_uint4(0, 0, 0, 0);
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
+struct Dims {
+  int D, H, W;
+  long long V;
+};
+
+__device__ __forceinline__ long long nb_voxel(const Dims& d, int z, int y,
+                                              int x, int tap) {
+  const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+  const int zz = z + dz;
+  if (zz < 0 || zz >= d.D) return -1;
+  int yy = y + dy, xx = x + dx;
+  if (yy < 0) yy += d.H;
+  if (yy >= d.H) yy -= d.H;
+  if (xx < 0) xx += d.W;
+  if (xx >= d.W) xx -= d.W;
+  return ((long long)zz * d.H + yy) * d.W + xx;
+}
+
+constexpr int KP(int cin) { return (27 * cin + 63) / 64 * 64; }
+
+// out = act(conv(in) + bias): CIN input channels (multiple of 8), NT*16
+// output channels.  Four waves of 32 voxels per workgroup.
+template <int CIN, int NT>
+__global__ void __launch_bounds__(256) k_conv3(const bf16* __restrict__ in,
+                                               const bf16* __restrict__ Wk,
+                                               const float* __restrict__ bias,
+                                               bf16* __restrict__ out, Dims d,
+                                               int relu) {
+  constexpr int KPAD = KP(CIN);
+  constexpr int KCH = (27 * CIN + 31) / 32;
+  constexpr int COUT = NT * 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long vb = (long long)blockIdx.x * 128 + wave * 32;
+  int zz[2], yy[2], xx[2];
+  bool ok[2];
+  for (int mt = 0; mt < 2; ++mt) {
+    const long long v = vb + mt * 16 + (lane & 15);
+    ok[mt] = v < d.V;
+    const long long vv = ok[mt] ? v : 0;
+    xx[mt] = (int)(vv % d.W);
+    yy[mt] = (int)((vv / d.W) % d.H);
+    zz[mt] = (int)(vv / ((long long)d.W * d.H));
+  }
+  f4 acc[2][NT];
+  for (int mt = 0; mt < 2; ++mt)
+    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+  const int kl = 8 * (lane >> 4);
+  for (int ch = 0; ch < KCH; ++ch) {
+    const int k0 = ch * 32 + kl;
+    const int tap = k0 / CIN, c = k0 - tap * CIN;
+    bf16x8 a[2];
+    for (int mt = 0; mt < 2; ++mt) {
+      const long long nv = (tap < 27 && ok[mt]) ? nb_voxel(d, zz[mt], yy[mt], xx[mt], tap) : -1;
+      a[mt] = nv >= 0 ? load8(in + nv * CIN + c) : zero8();
+    }
+    for (int nt = 0; nt < NT; ++nt) {
+      const bf16x8 b = load8(Wk + (long long)(nt * 16 + (lane & 15)) * KPAD + k0);
+      for (int mt = 0; mt < 2; ++mt)
+        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][nt], 0, 0, 0);
+    }
+  }
+  for (int mt = 0; mt < 2; ++mt)
+    for (int nt = 0; nt < NT; ++nt) {
+      const int co = nt * 16 + (lane & 15);
+      const float bi = bias ? bias[co] : 0.0f;
+      for (int j = 0; j < 4; ++j) {
+        const long long v = vb + mt * 16 + 4 * (lane >> 4) + j;
+        if (v >= d.V) continue;
+        float r = acc[mt][nt][j] + bi;
+        if (relu) r = r > 0.0f ? r : 0.0f;
+        out[v * COUT + co] = f2bf(r);
+      }
+    }
+}
+
+// Weight gradient dW[co][k] += sum_v g[v][co] x[v + tap(k)][ci(k)] over a
+// chunk of voxels (dW unpadded: row stride 27 CIN); a workgroup owns 64 columns of k, each wave 16 of them
+// for all COUT rows.  32-voxel slices of g and x are staged in LDS.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_wgrad3(const bf16* __restrict__ x,
+                                                const bf16* __restrict__ g,
+                                                float* __restrict__ dW, Dims d,
+                                                long long chunk) {
+  constexpr int MT = COUT / 16;
+  __shared__ __attribute__((aligned(16))) bf16 gs[32][COUT];
+  __shared__ __attribute__((aligned(16))) bf16 xs[32][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kbase = blockIdx.x * 64;
+  const long long v0 = (long long)blockIdx.y * chunk;
+  long long v1 = v0 + chunk;
+  if (v1 > d.V) v1 = d.V;
+  f4 acc[MT];
+  for (int m = 0; m < MT; ++m) acc[m] = f4{0.f, 0.f, 0.f, 0.f};
+  for (long long vs = v0; vs < v1; vs += 32) {
+    // Stage g (32 x COUT) and x (32 x 64 columns).
+    for (int q = threadIdx.x; q < 32 * COUT / 8; q += 256) {
+      const int vr = q / (COUT / 8), c8 = (q % (COUT / 8)) * 8;
+      const long long v = vs + vr;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (v < v1) val = *reinterpret_cast<const uint4*>(g + v * COUT + c8);
+      *reinterpret_cast<uint4*>(&gs[vr][c8]) = val;
+    }
+    {
+      const int q = threadIdx.x;            // 32 voxels x 8 groups of 8
+      const int vr = q >> 3, kg = (q & 7) * 8;
+      const long long v = vs + vr;
+      const int k = kbase + kg;
+      const int tap = k / CIN, c = k - tap * CIN;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (v < v1 && tap < 27) {
+        const int xq = (int)(v % d.W), yq = (int)((v / d.W) % d.H),
+                  zq = (int)(v / ((long long)d.W * d.H));
+        const long long nv = nb_voxel(d, zq, yq, xq, tap);
+        if (nv >= 0) val = *reinterpret_cast<const uint4*>(x + nv * CIN + c);
+      }
+      *reinterpret_cast<uint4*>(&xs[vr][kg]) = val;
+    }
+    __syncthreads();
+    bf16x8 b;
+    {
+      bf16 tmp[8];
+      for (int j = 0; j < 8; ++j) tmp[j] = xs[8 * (lane >> 4) + j][wave * 16 + (lane & 15)];
+      __builtin_memcpy(&b, tmp, 16);
+    }
+    for (int m = 0; m < MT; ++m) {
+      bf16 tmp[8];
+      for (int j = 0; j < 8; ++j) tmp[j] = gs[8 * (lane >> 4) + j][m * 16 + (lane & 15)];
+      bf16x8 a;
+      __builtin_memcpy(&a, tmp, 16);
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[m], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int k = kbase + wave * 16 + (lane & 15);
+  if (k >= 27 * CIN) return;
+  for (int m = 0; m < MT; ++m)
+    for (int j = 0; j < 4; ++j) {
+      const int co = m * 16 + 4 * (lane >> 4) + j;
+      atomicAdd(&dW[(long long)co * (27 * CIN) + k], acc[m][j]);
+    }
+}
+
+// First layer (2 input channels): FP32 arithmetic, 16 outputs per voxel.
+__global__ void k_conv_first(const float* __restrict__ in,
+                             const float* __restrict__ W,  // [16][27][2]
+                             const float* __restrict__ b,
+                             bf16* __restrict__ out, Dims d) {
+  __shared__ float ws[16 * 54 + 16];
+  for (int q = threadIdx.x; q < 16 * 54; q += blockDim.x) ws[q] = W[q];
+  if (threadIdx.x < 16) ws[16 * 54 + threadIdx.x] = b[threadIdx.x];
+  __syncthreads();
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= d.V) return;
+  const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
+            z = (int)(v / ((long long)d.W * d.H));
+  float acc[16];
+  for (int c = 0; c < 16; ++c) acc[c] = ws[16 * 54 + c];
+  for (int tap = 0; tap < 27; ++tap) {
+    const long long nv = nb_voxel(d, z, y, x, tap);
+    if (nv < 0) continue;
+    const float i0 = in[2 * nv], i1 = in[2 * nv + 1];
+    for (int c = 0; c < 16; ++c)
+      acc[c] = acc[c] + ws[c * 54 + tap * 2] * i0 + ws[c * 54 + tap * 2 + 1] * i1;
+  }
+  for (int c = 0; c < 16; ++c) out[v * 16 + c] = f2bf(acc[c] > 0.f ? acc[c] : 0.f);
+}
+
+// dW of the first layer: each thread of a block owns up to 4 of the 864
+// weights and sums over the block's voxel chunk.
+__global__ void k_wgrad_first(const float* __restrict__ in,
+                              const bf16* __restrict__ g, float* __restrict__ dW,
+                              Dims d, long long chunk) {
+  const long long v0 = (long long)blockIdx.x * chunk;
+  long long v1 = v0 + chunk;
+  if (v1 > d.V) v1 = d.V;
+  for (int e = threadIdx.x; e < 864; e += blockDim.x) {
+    const int co = e / 54, r = e % 54, tap = r / 2, ci = r % 2;
+    float s = 0.f;
+    for (long long v = v0; v < v1; ++v) {
+      const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
+                z = (int)(v / ((long long)d.W * d.H));
+      const long long nv = nb_voxel(d, z, y, x, tap);
+      if (nv >= 0) s = s + bf2f(g[v * 16 + co]) * in[2 * nv + ci];
+    }
+    atomicAdd(&dW[e], s);
+  }
+}
+
+// Bias gradient: sum over voxels per channel.
+__global__ void k_bias_grad(const bf16* __restrict__ g, int C, Dims d,
+                            float* __restrict__ db) {
+  const int c = threadIdx.x % C;
+  const int lanes = blockDim.x / C;
+  const int r = threadIdx.x / C;
+  if (r >= lanes) return;
+  float s = 0.f;
+  for (long long v = (long long)blockIdx.x * lanes + r; v < d.V;
+       v += (long long)gridDim.x * lanes)
+    s = s + bf2f(g[v * C + c]);
+  atomicAdd(&db[c], s);
+}
+
+// gpre = gy * (y > 0).
+__global__ void k_relu_bwd(const bf16* __restrict__ gy, const bf16* __restrict__ y,
+                           bf16* __restrict__ gpre, long long n) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  gpre[i] = bf2f(y[i]) > 0.f ? gy[i] : (bf16)0;
+}
+
+// Average pooling 2^3 (out dims d = input dims / 2).
+__global__ void k_pool(const bf16* __restrict__ in, bf16* __restrict__ out,
+                       Dims d, int C) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= d.V * C) return;
+  const int c = (int)(i % C);
+  const long long v = i / C;
+  const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
+            z = (int)(v / ((long long)d.W * d.H));
+  const int W2 = 2 * d.W, H2 = 2 * d.H;
+  float s = 0.f;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 2; ++e)
+        s = s + bf2f(in[((((long long)(2 * z + a) * H2) + 2 * y + b) * W2 + 2 * x + e) * C + c]);
+  out[i] = f2bf(s * 0.125f);
+}
+
+// Gradient through pooling added to an existing fine gradient:
+// gfine[child] = gfine[child] + gcoarse[parent] / 8 (fine dims d).
+__global__ void k_pool_bwd_add(const bf16* __restrict__ gc, bf16* __restrict__ gf,
+                               Dims d, int C) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= d.V * C) return;
+  const int c = (int)(i % C);
+  const long long v = i / C;
+  const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
+            z = (int)(v / ((long long)d.W * d.H));
+  const long long p = (((long long)(z / 2) * (d.H / 2)) + y / 2) * (d.W / 2) + x / 2;
+  gf[i] = f2bf(bf2f(gf[i]) + bf2f(gc[p * C + c]) * 0.125f);
+}
+
+// Concatenation [up(coarse) (Cu channels), skip (Cs)] at fine dims d.
+__global__ void k_up_cat(const bf16* __restrict__ coarse, int Cu,
+                         const bf16* __restrict__ skip, int Cs,
+                         bf16* __restrict__ out, Dims d) {
+  const int C = Cu + Cs;
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= d.V * C) return;
+  const int c = (int)(i % C);
+  const long long v = i / C;
+  if (c < Cu) {
+    const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
+              z = (int)(v / ((long long)d.W * d.H));
+    const long long p = (((long long)(z / 2) * (d.H / 2)) + y / 2) * (d.W / 2) + x / 2;
+    out[i] = coarse[p * Cu + c];
+  } else {
+    out[i] = skip[v * Cs + (c - Cu)];
+  }
+}
+
+// Split the concatenation's gradient: coarse part summed over the 8
+// children (coarse dims dc), skip part copied (fine dims).
+__global__ void k_split_up(const bf16* __restrict__ gcat, int Cu, int Cs,
+                           bf16* __restrict__ gcoarse, Dims dc) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= dc.V * Cu) return;
+  const int c = (int)(i % Cu);
+  const long long p = i / Cu;
+  const int x = (int)(p % dc.W), y = (int)((p / dc.W) % dc.H),
+            z = (int)(p / ((long long)dc.W * dc.H));
+  const int W2 = 2 * dc.W, H2 = 2 * dc.H, C = Cu + Cs;
+  float s = 0.f;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < 2; ++e)
+        s = s + bf2f(gcat[((((long long)(2 * z + a) * H2) + 2 * y + b) * W2 + 2 * x + e) * C + c]);
+  gcoarse[i] = f2bf(s);
+}
+__global__ void k_split_skip(const bf16* __restrict__ gcat, int Cu, int Cs,
+                             bf16* __restrict__ gskip, Dims d) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= d.V * Cs) return;
+  const long long v = i / Cs;
+  gskip[i] = gcat[v * (Cu + Cs) + Cu + (i % Cs)];
+}
+
+// Head: out[v] = sum_c w[c] y[v][c] + b, FP32 output.
+__global__ void k_head(const bf16* __restrict__ y, const float* __restrict__ w,
+                       float* __restrict__ out, long long V) {
+  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  float s = w[16];
+  for (int c = 0; c < 16; ++c) s = s + w[c] * bf2f(y[v * 16 + c]);
+  out[v] = s;
+}
+
+// Loss (mean squared error) partials and the output gradient.
+__global__ void k_mse(const float* __restrict__ out, const float* __restrict__ t,
+                      float* __restrict__ gout, long long V,
+                      double* __restrict__ part) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < V;
+       v += (long long)gridDim.x * blockDim.x) {
+    const float df = out[v] - t[v];
+    a += (double)df * df;
+    gout[v] = 2.0f * df / (float)V;
+  }
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// Head backward: gy[v][c] = gout[v] w[c]; dw[c] += sum gout y; db += sum.
+__global__ void k_head_bwd(const float* __restrict__ gout, const bf16* __restrict__ y,
+                           const float* __restrict__ w, bf16* __restrict__ gy,
+                           float* __restrict__ dw, long long V) {
+  __shared__ float s[17][256];
+  float acc[17];
+  for (int c = 0; c < 17; ++c) acc[c] = 0.f;
+  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < V;
+       v += (long long)gridDim.x * blockDim.x) {
+    const float go = gout[v];
+    for (int c = 0; c < 16; ++c) {
+      gy[v * 16 + c] = f2bf(go * w[c]);
+      acc[c] = acc[c] + go * bf2f(y[v * 16 + c]);
+    }
+    acc[16] = acc[16] + go;
+  }
+  for (int c = 0; c < 17; ++c) s[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int c = 0; c < 17; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 17) atomicAdd(&dw[threadIdx.x], s[threadIdx.x][0]);
+}
+
+__global__ void k_sum_d(const double* __restrict__ part, int n, double* out) {
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+// Adam with FP32 master weights (Kingma & Ba): bias-corrected moments.
+__global__ void k_adam(float* __restrict__ p, float* __restrict__ m,
+                       float* __restrict__ v, const float* __restrict__ g,
+                       long long n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// BF16 copies of a layer's weights: forward Wk[co][k = tap*ci_n + ci] and
+// backward-data Wd[ci][k' = tap'*co_n + co] = W[co][26 - tap'][ci].
+__global__ void k_pack_w(const float* __restrict__ W, int ci_n, int co_n,
+                         bf16* __restrict__ Wk, int kpf, bf16* __restrict__ Wd,
+                         int kpd) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const long long n = (long long)co_n * 27 * ci_n;
+  if (i >= n) return;
+  const int co = (int)(i / (27 * ci_n));
+  const int r = (int)(i % (27 * ci_n));
+  const int tap = r / ci_n, ci = r % ci_n;
+  const bf16 h = f2bf(W[i]);
+  Wk[(long long)co * kpf + tap * ci_n + ci] = h;
+  if (Wd) Wd[(long long)ci * kpd + (26 - tap) * co_n + co] = h;
+}
+
+__global__ void k_f32_to_f64(const float* __restrict__ a, double* __restrict__ b,
+                             long long n) {
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+}  // namespace
+}  // namespace pic
+
+// ============================================================================
+// Host side.
+// ============================================================================
+namespace {
+
+using pic::bf16;
+using pic::Dims;
+
+struct LayerSpec {
+  int ci, co;
+};
+constexpr int kNL = 14;
+constexpr LayerSpec kLayers[kNL] = {
+    {2, 16},   {16, 16},  {16, 32}, {32, 32}, {32, 64},  {64, 64},  {64, 128},
+    {128, 128}, {192, 64}, {64, 64}, {96, 32}, {32, 32},  {48, 16},  {16, 16}};
+enum { E0A, E0B, E1A, E1B, E2A, E2B, BA, BB, D2A, D2B, D1A, D1B, D0A, D0B };
+// Level of each layer's voxels.
+constexpr int kLevel[kNL] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0};
+
+long long param_count() {
+  long long n = 0;
+  for (int l = 0; l < kNL; ++l) n += (long long)kLayers[l].co * 27 * kLayers[l].ci + kLayers[l].co;
+  return n + 17;
+}
+
+constexpr int kpad(int cin) { return (27 * cin + 63) / 64 * 64; }
+
+}  // namespace
+
+struct pic_unet {
+  hipStream_t stream;
+  int D, H, W;                 // maximum grid
+  char* ws;
+  size_t bytes;
+  long long np;                // parameters
+  float *p, *m, *v, *g;        // master, moments, gradient
+  long long woff[kNL], boff[kNL], hoff;
+  bf16 *wk[kNL], *wd[kNL];     // BF16 forward / backward-data weights
+  // Activations (BF16, channels-last).
+  float* x_in;                 // (V0, 2) FP32 input
+  bf16 *y[kNL];                // layer outputs
+  bf16 *p0, *p1, *p2;          // pooled
+  bf16 *c2, *c1, *c0;          // concatenations
+  float *out, *gout, *target;
+  // Gradient scratch per level (two buffers of the level's widest tensor)
+  // and a pre-activation buffer.
+  bf16 *ga[4], *gb[4], *gp[4], *gs[4];
+  float* dscratch;             // double partials (as float storage)
+  double* dpart;
+  int t;                       // Adam step
+  std::string err;
+};
+
+namespace {
+
+struct Carve {
+  char* base;
+  size_t off;
+  template <typename T>
+  T* take(long long n) {
+    off = (off + 255) / 256 * 256;
+    T* r = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += (size_t)(n > 0 ? n : 1) * sizeof(T);
+    return r;
+  }
+};
+
+size_t unet_carve(pic_unet* u, char* base) {
+  Carve cv{base, 0};
+  const long long V0 = (long long)u->D * u->H * u->W;
+  long long Vl[4];
+  for (int l = 0; l < 4; ++l) Vl[l] = V0 >> (3 * l);
+  u->np = param_count();
+  u->p = cv.take<float>(u->np);
+  u->m = cv.take<float>(u->np);
+  u->v = cv.take<float>(u->np);
+  u->g = cv.take<float>(u->np);
+  long long off = 0;
+  for (int l = 0; l < kNL; ++l) {
+    u->woff[l] = off;
+    off += (long long)kLayers[l].co * 27 * kLayers[l].ci;
+    u->boff[l] = off;
+    off += kLayers[l].co;
+    u->wk[l] = cv.take<bf16>((long long)kLayers[l].co * kpad(kLayers[l].ci));
+    u->wd[l] = cv.take<bf16>((long long)kLayers[l].ci * kpad(kLayers[l].co));
+  }
+  u->hoff = off;
+  u->x_in = cv.take<float>(2 * V0);
+  for (int l = 0; l < kNL; ++l) u->y[l] = cv.take<bf16>(Vl[kLevel[l]] * kLayers[l].co);
+  u->p0 = cv.take<bf16>(Vl[1] * 16);
+  u->p1 = cv.take<bf16>(Vl[2] * 32);
+  u->p2 = cv.take<bf16>(Vl[3] * 64);
+  u->c2 = cv.take<bf16>(Vl[2] * 192);
+  u->c1 = cv.take<bf16>(Vl[1] * 96);
+  u->c0 = cv.take<bf16>(Vl[0] * 48);
+  u->out = cv.take<float>(V0);
+  u->gout = cv.take<float>(V0);
+  u->target = cv.take<float>(V0);
+  const int widest[4] = {48, 96, 192, 128};
+  for (int l = 0; l < 4; ++l) {
+    u->ga[l] = cv.take<bf16>(Vl[l] * widest[l]);
+    u->gb[l] = cv.take<bf16>(Vl[l] * widest[l]);
+    u->gp[l] = cv.take<bf16>(Vl[l] * widest[l]);
+    u->gs[l] = cv.take<bf16>(Vl[l] * widest[l]);
+  }
+  u->dpart = cv.take<double>(1024);
+  return cv.off + 256;
+}
+
+inline unsigned nb(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+Dims dims_at(const pic_unet* u, int D, int H, int W, int level) {
+  Dims d;
+  d.D = D >> level;
+  d.H = H >> level;
+  d.W = W >> level;
+  d.V = (long long)d.D * d.H * d.W;
+  return d;
+}
+
+template <int CIN, int NT>
+void conv_launch(hipStream_t st, const bf16* in, const bf16* Wk, const float* b,
+                 bf16* out, Dims d, int relu) {
+  pic::k_conv3<CIN, NT><<<nb(d.V, 128), 256, 0, st>>>(in, Wk, b, out, d, relu);
+}
+
+// Dispatch of the (C_in, C_out) pairs the network and its backward use.
+bool conv(hipStream_t st, int cin, int cout, const bf16* in, const bf16* Wk,
+          const float* b, bf16* out, Dims d, int relu) {
+#define PIC_CONV(CI, CO)                                                   \
+  if (cin == CI && cout == CO) {                                           \
+    conv_launch<CI, CO / 16>(st, in, Wk, b, out, d, relu);                 \
+    return true;                                                           \
+  }
+  PIC_CONV(16, 16) PIC_CONV(16, 32) PIC_CONV(32, 32) PIC_CONV(32, 64)
+  PIC_CONV(64, 64) PIC_CONV(64, 128) PIC_CONV(128, 128) PIC_CONV(192, 64)
+  PIC_CONV(96, 32) PIC_CONV(48, 16)
+  // backward-data shapes (channels swapped)
+  PIC_CONV(32, 16) PIC_CONV(64, 32) PIC_CONV(128, 64) PIC_CONV(64, 192)
+  PIC_CONV(32, 96) PIC_CONV(16, 48)
+#undef PIC_CONV
+  return false;
+}
+
+template <int CIN, int COUT>
+void wgrad_launch(hipStream_t st, const bf16* x, const bf16* g, float* dW,
+                  Dims d) {
+  long long chunk = d.V / 256;
+  if (chunk < 2048) chunk = 2048;
+  chunk = (chunk + 31) / 32 * 32;
+  dim3 grid(kpad(CIN) / 64, (unsigned)((d.V + chunk - 1) / chunk));
+  pic::k_wgrad3<CIN, COUT><<<grid, 256, 0, st>>>(x, g, dW, d, chunk);
+}
+
+bool wgrad(hipStream_t st, int cin, int cout, const bf16* x, const bf16* g,
+           float* dW, Dims d) {
+#define PIC_WG(CI, CO)                                                     \
+  if (cin == CI && cout == CO) {                                           \
+    wgrad_launch<CI, CO>(st, x, g, dW, d);                                 \
+    return true;                                                           \
+  }
+  PIC_WG(16, 16) PIC_WG(16, 32) PIC_WG(32, 32) PIC_WG(32, 64) PIC_WG(64, 64)
+  PIC_WG(64, 128) PIC_WG(128, 128) PIC_WG(192, 64) PIC_WG(96, 32)
+  PIC_WG(48, 16)
+#undef PIC_WG
+  return false;
+}
+
+void pack_weights(pic_unet* u) {
+  for (int l = 0; l < kNL; ++l) {
+    const LayerSpec& s = kLayers[l];
+    if (l == E0A) continue;  // FP32 first layer
+    pic::k_pack_w<<<nb((long long)s.co * 27 * s.ci), 256, 0, u->stream>>>(
+        u->p + u->woff[l], s.ci, s.co, u->wk[l], kpad(s.ci), u->wd[l],
+        kpad(s.co));
+  }
+}
+
+// Forward pass of a D x H x W grid (input already in x_in); out -> u->out.
+bool unet_forward(pic_unet* u, int D, int H, int W) {
+  hipStream_t st = u->stream;
+  Dims d0 = dims_at(u, D, H, W, 0), d1 = dims_at(u, D, H, W, 1),
+       d2 = dims_at(u, D, H, W, 2), d3 = dims_at(u, D, H, W, 3);
+  const float* P = u->p;
+  pic::k_conv_first<<<nb(d0.V), 256, 0, st>>>(u->x_in, P + u->woff[E0A],
+                                             P + u->boff[E0A], u->y[E0A], d0);
+  bool ok = true;
+  auto L = [&](int l, const bf16* in, Dims d) {
+    ok = ok && conv(st, kLayers[l].ci, kLayers[l].co, in, u->wk[l],
+                    P + u->boff[l], u->y[l], d, 1);
+  };
+  L(E0B, u->y[E0A], d0);
+  pic::k_pool<<<nb(d1.V * 16), 256, 0, st>>>(u->y[E0B], u->p0, d1, 16);
+  L(E1A, u->p0, d1);
+  L(E1B, u->y[E1A], d1);
+  pic::k_pool<<<nb(d2.V * 32), 256, 0, st>>>(u->y[E1B], u->p1, d2, 32);
+  L(E2A, u->p1, d2);
+  L(E2B, u->y[E2A], d2);
+  pic::k_pool<<<nb(d3.V * 64), 256, 0, st>>>(u->y[E2B], u->p2, d3, 64);
+  L(BA, u->p2, d3);
+  L(BB, u->y[BA], d3);
+  pic::k_up_cat<<<nb(d2.V * 192), 256, 0, st>>>(u->y[BB], 128, u->y[E2B], 64, u->c2, d2);
+  L(D2A, u->c2, d2);
+  L(D2B, u->y[D2A], d2);
+  pic::k_up_cat<<<nb(d1.V * 96), 256, 0, st>>>(u->y[D2B], 64, u->y[E1B], 32, u->c1, d1);
+  L(D1A, u->c1, d1);
+  L(D1B, u->y[D1A], d1);
+  pic::k_up_cat<<<nb(d0.V * 48), 256, 0, st>>>(u->y[D1B], 32, u->y[E0B], 16, u->c0, d0);
+  L(D0A, u->c0, d0);
+  L(D0B, u->y[D0A], d0);
+  pic::k_head<<<nb(d0.V), 256, 0, st>>>(u->y[D0B], P + u->hoff, u->out, d0.V);
+  return ok;
+}
+
+// Backward pass from u->gout into u->g (zeroed here).
+bool unet_backward(pic_unet* u, int D, int H, int W) {
+  hipStream_t st = u->stream;
+  Dims d[4];
+  for (int l = 0; l < 4; ++l) d[l] = dims_at(u, D, H, W, l);
+  hipMemsetAsync(u->g, 0, u->np * sizeof(float), st);
+  float* G = u->g;
+  bool ok = true;
+  // Head.
+  pic::k_head_bwd<<<512, 256, 0, st>>>(u->gout, u->y[D0B], u->p + u->hoff,
+                                       u->ga[0], G + u->hoff, d[0].V);
+  // Layer backward: gy (post-activation gradient) -> gpre -> dW, db and
+  // (if gx) the input gradient.
+  auto back = [&](int l, const bf16* gy, const bf16* in, bf16* gpre, bf16* gx) {
+    const LayerSpec& s = kLayers[l];
+    const Dims& dd = d[kLevel[l]];
+    pic::k_relu_bwd<<<nb(dd.V * s.co), 256, 0, st>>>(gy, u->y[l], gpre, dd.V * s.co);
+    ok = ok && wgrad(st, s.ci, s.co, in, gpre, G + u->woff[l], dd);
+    pic::k_bias_grad<<<256, 256, 0, st>>>(gpre, s.co, dd, G + u->boff[l]);
+    if (gx) ok = ok && conv(st, s.co, s.ci, gpre, u->wd[l], nullptr, gx, dd, 0);
+  };
+  // Level 0 decoder.
+  back(D0B, u->ga[0], u->y[D0A], u->gp[0], u->gb[0]);
+  back(D0A, u->gb[0], u->c0, u->gp[0], u->ga[0]);        // ga0: grad of c0 (48)
+  pic::k_split_skip<<<nb(d[0].V * 16), 256, 0, st>>>(u->ga[0], 32, 16, u->gs[0], d[0]);
+  pic::k_split_up<<<nb(d[1].V * 32), 256, 0, st>>>(u->ga[0], 32, 16, u->ga[1], d[1]);
+  // Level 1 decoder.
+  back(D1B, u->ga[1], u->y[D1A], u->gp[1], u->gb[1]);
+  back(D1A, u->gb[1], u->c1, u->gp[1], u->ga[1]);        // grad of c1 (96)
+  pic::k_split_skip<<<nb(d[1].V * 32), 256, 0, st>>>(u->ga[1], 64, 32, u->gs[1], d[1]);
+  pic::k_split_up<<<nb(d[2].V * 64), 256, 0, st>>>(u->ga[1], 64, 32, u->ga[2], d[2]);
+  // Level 2 decoder.
+  back(D2B, u->ga[2], u->y[D2A], u->gp[2], u->gb[2]);
+  back(D2A, u->gb[2], u->c2, u->gp[2], u->ga[2]);        // grad of c2 (192)
+  pic::k_split_skip<<<nb(d[2].V * 64), 256, 0, st>>>(u->ga[2], 128, 64, u->gs[2], d[2]);
+  pic::k_split_up<<<nb(d[3].V * 128), 256, 0, st>>>(u->ga[2], 128, 64, u->ga[3], d[3]);
+  // Bottom.
+  back(BB, u->ga[3], u->y[BA], u->gp[3], u->gb[3]);
+  back(BA, u->gb[3], u->p2, u->gp[3], u->ga[3]);         // grad of p2 (64)
+  // Encoder level 2: skip gradient + pooled gradient.
+  pic::k_pool_bwd_add<<<nb(d[2].V * 64), 256, 0, st>>>(u->ga[3], u->gs[2], d[2], 64);
+  back(E2B, u->gs[2], u->y[E2A], u->gp[2], u->gb[2]);
+  back(E2A, u->gb[2], u->p1, u->gp[2], u->ga[2]);        // grad of p1 (32)
+  pic::k_pool_bwd_add<<<nb(d[1].V * 32), 256, 0, st>>>(u->ga[2], u->gs[1], d[1], 32);
+  back(E1B, u->gs[1], u->y[E1A], u->gp[1], u->gb[1]);
+  back(E1A, u->gb[1], u->p0, u->gp[1], u->ga[1]);        // grad of p0 (16)
+  pic::k_pool_bwd_add<<<nb(d[0].V * 16), 256, 0, st>>>(u->ga[1], u->gs[0], d[0], 16);
+  back(E0B, u->gs[0], u->y[E0A], u->gp[0], u->gb[0]);    // grad of e0a (16)
+  // First layer: weights only.
+  pic::k_relu_bwd<<<nb(d[0].V * 16), 256, 0, st>>>(u->gb[0], u->y[E0A], u->gp[0], d[0].V * 16);
+  long long chunk = d[0].V / 512;
+  if (chunk < 1024) chunk = 1024;
+  pic::k_wgrad_first<<<(unsigned)((d[0].V + chunk - 1) / chunk), 256, 0, st>>>(
+      u->x_in, u->gp[0], G + u->woff[E0A], d[0], chunk);
+  pic::k_bias_grad<<<256, 256, 0, st>>>(u->gp[0], 16, d[0], G + u->boff[E0A]);
+  return ok;
+}
+
+pic_status unet_check(pic_unet* u, int D, int H, int W) {
+  if (!u) return PIC_ERR_ARG;
+  if (D < 8 || H < 8 || W < 8 || (D & 7) || (H & 7) || (W & 7) || D > u->D ||
+      H > u->H || W > u->W || (long long)D * H * W > (long long)u->D * u->H * u->W)
+    return PIC_ERR_ARG;
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t pic_unet_param_count(void) { return param_count(); }
+
+pic_status pic_unet_workspace_bytes(int32_t D, int32_t H, int32_t W,
+                                    size_t* bytes) {
+  if (!bytes || D < 8 || H < 8 || W < 8 || (D & 7) || (H & 7) || (W & 7))
+    return PIC_ERR_ARG;
+  pic_unet u;
+  u.D = D; u.H = H; u.W = W;
+  *bytes = unet_carve(&u, nullptr);
+  return PIC_OK;
+}
+
+pic_status pic_unet_init(int32_t D, int32_t H, int32_t W, void* ws,
+                         size_t bytes, void* stream, pic_unet** out) {
+  if (!out) return PIC_ERR_ARG;
+  *out = nullptr;
+  size_t need = 0;
+  if (pic_unet_workspace_bytes(D, H, W, &need) != PIC_OK || !ws || bytes < need)
+    return PIC_ERR_ARG;
+  pic_unet* u = new (std::nothrow) pic_unet();
+  if (!u) return PIC_ERR_STATE;
+  u->D = D; u->H = H; u->W = W;
+  u->stream = reinterpret_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) / 256 * 256);
+  u->ws = reinterpret_cast<char*>(ws);
+  u->bytes = bytes;
+  unet_carve(u, base);
+  u->t = 0;
+  if (hipMemsetAsync(ws, 0, bytes, u->stream) != hipSuccess ||
+      hipStreamSynchronize(u->stream) != hipSuccess) {
+    delete u;
+    return PIC_ERR_HIP;
+  }
+  *out = u;
+  return PIC_OK;
+}
+
+void pic_unet_destroy(pic_unet* u) { delete u; }
+
+const char* pic_unet_last_error(const pic_unet* u) {
+  return u ? u->err.c_str() : "null U-Net";
+}
+
+pic_status pic_unet_set_params(pic_unet* u, const float* params) {
+  if (!u || !params) return PIC_ERR_ARG;
+  if (hipMemcpyAsync(u->p, params, u->np * sizeof(float), hipMemcpyDeviceToDevice,
+                     u->stream) != hipSuccess)
+    return PIC_ERR_HIP;
+  hipMemsetAsync(u->m, 0, u->np * sizeof(float), u->stream);
+  hipMemsetAsync(u->v, 0, u->np * sizeof(float), u->stream);
+  u->t = 0;
+  pack_weights(u);
+  return hipStreamSynchronize(u->stream) == hipSuccess ? PIC_OK : PIC_ERR_HIP;
+}
+
+pic_status pic_unet_get_params(pic_unet* u, float* params) {
+  if (!u || !params) return PIC_ERR_ARG;
+  if (hipMemcpyAsync(params, u->p, u->np * sizeof(float), hipMemcpyDeviceToDevice,
+                     u->stream) != hipSuccess ||
+      hipStreamSynchronize(u->stream) != hipSuccess)
+    return PIC_ERR_HIP;
+  return PIC_OK;
+}
+
+pic_status pic_unet_forward(pic_unet* u, const float* input, int32_t D,
+                            int32_t H, int32_t W, float* out) {
+  const pic_status c = unet_check(u, D, H, W);
+  if (c != PIC_OK) return c;
+  if (!input || !out) return PIC_ERR_ARG;
+  const long long V = (long long)D * H * W;
+  hipMemcpyAsync(u->x_in, input, 2 * V * sizeof(float), hipMemcpyDeviceToDevice,
+                 u->stream);
+  if (!unet_forward(u, D, H, W)) return PIC_ERR_STATE;
+  hipMemcpyAsync(out, u->out, V * sizeof(float), hipMemcpyDeviceToDevice, u->stream);
+  return hipStreamSynchronize(u->stream) == hipSuccess ? PIC_OK : PIC_ERR_HIP;
+}
+
+// Loss and parameter gradient of one sample (no update).
+pic_status pic_unet_gradients(pic_unet* u, const float* input,
+                              const float* target, int32_t D, int32_t H,
+                              int32_t W, float* grad, double* loss) {
+  const pic_status c = unet_check(u, D, H, W);
+  if (c != PIC_OK) return c;
+  if (!input || !target) return PIC_ERR_ARG;
+  const long long V = (long long)D * H * W;
+  hipStream_t st = u->stream;
+  hipMemcpyAsync(u->x_in, input, 2 * V * sizeof(float), hipMemcpyDeviceToDevice, st);
+  hipMemcpyAsync(u->target, target, V * sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (!unet_forward(u, D, H, W)) return PIC_ERR_STATE;
+  pic::k_mse<<<256, 256, 0, st>>>(u->out, u->target, u->gout, V, u->dpart);
+  pic::k_sum_d<<<1, 256, 0, st>>>(u->dpart, 256, u->dpart + 512);
+  if (!unet_backward(u, D, H, W)) return PIC_ERR_STATE;
+  if (grad)
+    hipMemcpyAsync(grad, u->g, u->np * sizeof(float), hipMemcpyDeviceToDevice, st);
+  double l = 0.0;
+  hipMemcpyAsync(&l, u->dpart + 512, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (hipStreamSynchronize(st) != hipSuccess) return PIC_ERR_HIP;
+  if (loss) *loss = l / (double)V;
+  return PIC_OK;
+}
+
+// One Adam step on one sample; returns the sample's loss before the step.
+pic_status pic_unet_train_step(pic_unet* u, const float* input,
+                               const float* target, int32_t D, int32_t H,
+                               int32_t W, float lr, float beta1, float beta2,
+                               float eps, double* loss) {
+  const pic_status s = pic_unet_gradients(u, input, target, D, H, W, nullptr, loss);
+  if (s != PIC_OK) return s;
+  u->t += 1;
+  const float c1 = 1.f - powf(beta1, (float)u->t);
+  const float c2 = 1.f - powf(beta2, (float)u->t);
+  pic::k_adam<<<nb(u->np), 256, 0, u->stream>>>(u->p, u->m, u->v, u->g, u->np,
+                                                 lr, beta1, beta2, eps, c1, c2);
+  pack_weights(u);
+  return hipStreamSynchronize(u->stream) == hipSuccess ? PIC_OK : PIC_ERR_HIP;
+}
+
+}  // extern "C"

@@ -386,3 +386,110 @@ def _hip_d2d(dst, src, nbytes):
                         ctypes.c_size_t(nbytes), 3)   # hipMemcpyDeviceToDevice
     if rc != 0:
         raise RuntimeError(f"hipMemcpy failed: {rc}")
+
+
+UNET_EXPORTS = {
+    "pic_unet_param_count": (_c_i64, []),
+    "pic_unet_workspace_bytes": (_c_i32, [_c_i32, _c_i32, _c_i32,
+                                          ctypes.POINTER(ctypes.c_size_t)]),
+    "pic_unet_init": (_c_i32, [_c_i32, _c_i32, _c_i32, _c_p, ctypes.c_size_t,
+                               _c_p, ctypes.POINTER(_c_p)]),
+    "pic_unet_destroy": (None, [_c_p]),
+    "pic_unet_set_params": (_c_i32, [_c_p, _c_p]),
+    "pic_unet_get_params": (_c_i32, [_c_p, _c_p]),
+    "pic_unet_forward": (_c_i32, [_c_p, _c_p, _c_i32, _c_i32, _c_i32, _c_p]),
+    "pic_unet_gradients": (_c_i32, [_c_p, _c_p, _c_p, _c_i32, _c_i32, _c_i32,
+                                    _c_p, ctypes.POINTER(_c_d)]),
+    "pic_unet_train_step": (_c_i32, [_c_p, _c_p, _c_p, _c_i32, _c_i32, _c_i32,
+                                     ctypes.c_float, ctypes.c_float,
+                                     ctypes.c_float, ctypes.c_float,
+                                     ctypes.POINTER(_c_d)]),
+    "pic_unet_last_error": (ctypes.c_char_p, [_c_p]),
+}
+
+
+def _unet_lib():
+    lib = load_library()
+    if not getattr(lib, "_unet_bound", False):
+        for name, (res, args) in UNET_EXPORTS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        lib._unet_bound = True
+    return lib
+
+
+class UNet:
+    """The learned warm-start network on the current device and stream.
+    Inputs are channels-last FP32 tensors: x (D, H, W, 2), target (D, H, W).
+    """
+
+    def __init__(self, D, H, W, params=None):
+        self.lib = _unet_lib()
+        self.shape = (int(D), int(H), int(W))
+        n = ctypes.c_size_t()
+        self._check(self.lib.pic_unet_workspace_bytes(D, H, W, ctypes.byref(n)))
+        self.ws = torch.empty(n.value + 256, dtype=torch.uint8, device="cuda")
+        base = (self.ws.data_ptr() + 255) // 256 * 256
+        u = ctypes.c_void_p()
+        self._check(self.lib.pic_unet_init(
+            D, H, W, ctypes.c_void_p(base), n.value,
+            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+            ctypes.byref(u)))
+        self.u = u
+        self.n_params = int(self.lib.pic_unet_param_count())
+        if params is not None:
+            self.set_params(params)
+
+    def __del__(self):
+        if getattr(self, "u", None):
+            self.lib.pic_unet_destroy(self.u)
+            self.u = None
+
+    def _check(self, status):
+        if status != 0:
+            msg = ""
+            if getattr(self, "u", None):
+                msg = (self.lib.pic_unet_last_error(self.u) or b"").decode()
+            raise PicError(status, msg)
+
+    def set_params(self, params):
+        p = torch.as_tensor(params, dtype=torch.float32, device="cuda").contiguous()
+        assert p.numel() == self.n_params
+        self._check(self.lib.pic_unet_set_params(self.u, _ptr(p)))
+
+    def get_params(self):
+        p = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        self._check(self.lib.pic_unet_get_params(self.u, _ptr(p)))
+        return p
+
+    def _dims(self, x):
+        D, H, W = x.shape[:3]
+        return int(D), int(H), int(W)
+
+    def forward(self, x):
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        D, H, W = self._dims(x)
+        out = torch.empty((D, H, W), dtype=torch.float32, device="cuda")
+        self._check(self.lib.pic_unet_forward(self.u, _ptr(x), D, H, W, _ptr(out)))
+        return out
+
+    def gradients(self, x, t):
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        t = torch.as_tensor(t, dtype=torch.float32, device="cuda").contiguous()
+        D, H, W = self._dims(x)
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = _c_d()
+        self._check(self.lib.pic_unet_gradients(self.u, _ptr(x), _ptr(t), D, H,
+                                                W, _ptr(g), ctypes.byref(loss)))
+        return g, loss.value
+
+    def train_step(self, x, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        x = torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+        t = torch.as_tensor(t, dtype=torch.float32, device="cuda").contiguous()
+        D, H, W = self._dims(x)
+        loss = _c_d()
+        self._check(self.lib.pic_unet_train_step(self.u, _ptr(x), _ptr(t), D, H,
+                                                 W, lr, beta1, beta2, eps,
+                                                 ctypes.byref(loss)))
+        return loss.value

@@ -176,3 +176,20 @@ def edge_positions(p, seed):
             (np.nextafter(nx * dx, 0.0), np.nextafter(ny * dx, 0.0), top),
             ((nx - 0.5) * dx, (ny - 0.5) * dx, (nz - 0.5) * dx)]
     return np.array(pts, dtype=np.float64)
+
+
+def unet_init(seed=0):
+    """He-normal initial parameters of the warm-start U-Net (flat FP32
+    vector in the documented layout); biases zero, head small."""
+    layers = ((2, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64),
+              (64, 128), (128, 128), (192, 64), (64, 64), (96, 32),
+              (32, 32), (48, 16), (16, 16))
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in layers:
+        parts.append(rng.standard_normal(co * 27 * ci)
+                     * np.sqrt(2.0 / (27 * ci)))
+        parts.append(np.zeros(co))
+    parts.append(rng.standard_normal(16) * 0.1)
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
