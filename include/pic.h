@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 1
+#define PIC_ABI_VERSION 2
 
 typedef enum {
   PIC_OK = 0,
@@ -59,6 +59,10 @@ enum { PIC_BC_DIRICHLET = 0, PIC_BC_NEUMANN = 1 };
 enum { PIC_FP64 = 0, PIC_MIXED = 1 };
 enum { PIC_ION_LOTZ = 0, PIC_ION_CONST = 1 };
 enum { PIC_WARM_ZERO = 0, PIC_WARM_GIVEN = 1 };
+/* Warm start of the field solve in pic_step / pic_field (and of
+ * poisson_solve with PIC_WARM_GIVEN): the previous potential; the same
+ * while recording the learned start's training pair; or the learned start. */
+enum { PIC_WS_PREV = 0, PIC_WS_RECORD = 1, PIC_WS_UNET = 2 };
 
 typedef struct pic_ctx pic_ctx;
 
@@ -128,6 +132,12 @@ typedef struct {
   int32_t converged;       /* 1 if rel_residual <= rel_tol                 */
   double rel_residual;     /* final ||b - A phi|| / ||b||                  */
   double b_norm;           /* ||b||_2 of the scaled system                 */
+  double rel_residual0;    /* of the start the V-cycles began from         */
+  double warm_ratio;       /* learned start: ||r(phi_0)|| / ||r(phi_prev)||
+                              (1 when not used or rejected)                */
+  int32_t warm_used;       /* the network ran in this solve                */
+  int32_t warm_rejected;   /* ... and its start was rejected (non-finite,
+                              or a larger residual than phi_prev's)        */
 } pic_solve_info;
 
 typedef struct {
@@ -227,11 +237,12 @@ pic_status pic_get_diag(pic_ctx* ctx, pic_diag* diag);
  * stream around each phase of a step (off by default).  ms[PIC_NPHASES]
  * receives the time accumulated since timing was enabled, calls[] (may be
  * NULL) the number of timed executions of each phase. */
-#define PIC_NPHASES 11
+#define PIC_NPHASES 12
 enum {
   PIC_PH_DEPOSIT = 0, PIC_PH_RHS, PIC_PH_POISSON, PIC_PH_EFIELD,
   PIC_PH_SOURCES, PIC_PH_PUSH_NEUTRAL, PIC_PH_PUSH_ION, PIC_PH_PUSH_ELECTRON,
-  PIC_PH_COLLIDE, PIC_PH_ABSORBED, PIC_PH_BIN
+  PIC_PH_COLLIDE, PIC_PH_ABSORBED, PIC_PH_BIN,
+  PIC_PH_WARM /* warm-start stage of the solve (inside PIC_PH_POISSON) */
 };
 pic_status pic_enable_timing(pic_ctx* ctx, int32_t on);
 pic_status pic_phase_times(pic_ctx* ctx, double* ms, int64_t* calls);
@@ -278,6 +289,26 @@ pic_status pic_unet_train_step(pic_unet* u, const float* input_device,
                                int32_t H, int32_t W, float lr, float beta1,
                                float beta2, float eps, double* loss);
 const char* pic_unet_last_error(const pic_unet* u);
+
+/* Warm start of the context's field solve.  mode PIC_WS_PREV: the previous
+ * potential.  PIC_WS_RECORD: the same, and each solve records the pair for
+ * pic_warm_pair.  PIC_WS_UNET: each solve also runs net (which must outlive
+ * this use and must not be driven from another stream meanwhile) on the
+ * context's stream: with r0 = b - A phi_prev on the unknowns, sigma its RMS
+ * and V_ref the largest Dirichlet face potential (at least 1 V), the input
+ * is (r0 / sigma, phi_prev / V_ref) on the nz planes k < nz, and
+ * phi_0 = phi_prev + sigma * output on the unknowns of those planes.  phi_0
+ * replaces phi_prev only if its residual is finite and not larger; the
+ * V-cycles then finish the solve to rel_tol either way.  The grid
+ * (D, H, W) = (nz, ny, nx) must be multiples of 8 within the net's maximum,
+ * else PIC_ERR_ARG. */
+pic_status pic_set_warm_start(pic_ctx* ctx, int32_t mode, pic_unet* net);
+
+/* The last recorded solve's network input (nz, ny, nx, 2) and target
+ * (phi - phi_prev) / sigma (nz, ny, nx), FP32 device buffers: the learned
+ * start's training pair.  PIC_ERR_STATE if no solve has been recorded. */
+pic_status pic_warm_pair(pic_ctx* ctx, float* input_device,
+                         float* target_device);
 
 const char* pic_last_error(const pic_ctx* ctx);
 int32_t pic_abi_version(void);

@@ -166,6 +166,7 @@ __global__ void k_final(const double* __restrict__ part,
     const double bn = dc->b_norm;
     const double rr = bn > 0.0 ? sqrt(s[0]) / bn : 0.0;
     dc->rel_res = rr;
+    if (mode == 2) dc->rel_res0 = rr;
     if (!(rr == rr)) {
       dc->err |= kErrNonFinite;
       dc->done = 1;
@@ -210,6 +211,107 @@ __global__ void k_residual(const double* __restrict__ u,
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = sb[0];
+}
+
+// ---- warm start of the solve --------------------------------------------
+// The learned start works on the normalised residual of the previous
+// potential: with r0 = b - A phi_prev and sigma its RMS over the unknowns,
+// the network maps (r0 / sigma, phi_prev / V_ref) on the nz planes k < nz to
+// a correction c, and phi_0 = phi_prev + sigma * c.  The exact correction
+// A^-1 r0 is linear in r0, so the normalised map does not depend on the
+// charge's magnitude or the grid spacing.
+
+// Stage 0 (after the residual partials of phi_prev): ||r0|| and sigma.
+// Stage 1 (after those of phi_0): accept or reject phi_0.
+__global__ void k_warm_final(const double* __restrict__ part, int n,
+                             Counters* dc, int stage, double n_unknown) {
+  __shared__ double s[1024];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) a = a + part[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] = s[threadIdx.x] + s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x) return;
+  const double r = sqrt(s[0]);
+  if (stage == 0) {
+    dc->warm_r0 = r;
+    dc->sigma = r / sqrt(n_unknown);
+    dc->warm_ratio = 1.0;
+    dc->warm_reject = 0;
+  } else {
+    const double r0 = dc->warm_r0;
+    // Non-finite output, or a start worse than the previous potential:
+    // keep phi_prev.
+    const bool bad = !(r == r) || r > r0;
+    dc->warm_reject = bad ? 1 : 0;
+    dc->warm_ratio = bad ? 1.0 : (r0 > 0.0 ? r / r0 : 1.0);
+  }
+}
+
+// Network input and the saved previous potential.
+__global__ void k_warm_input(const double* __restrict__ u,
+                             const double* __restrict__ f, LevelC L,
+                             const Counters* dc, double inv_vref,
+                             float* __restrict__ x,
+                             double* __restrict__ uprev) {
+  const double sg = dc->sigma;
+  const double inv_s = sg > 0.0 ? 1.0 / sg : 0.0;
+  const long long n = L.nxy * (L.nz + 1);
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+       idx < n; idx += (long long)gridDim.x * blockDim.x) {
+    const double uv = u[idx];
+    uprev[idx] = uv;
+    const int k = (int)(idx / L.nxy);
+    if (k >= L.nz) continue;
+    double r = 0.0;
+    if (k >= L.k0 && k <= L.k1) {
+      const long long rem = idx - (long long)k * L.nxy;
+      const int j = (int)(rem / L.nx), i = (int)(rem % L.nx);
+      r = f[idx] - (6.0 * uv - nb_sum(u, L, i, j, k));
+    }
+    float2 v;
+    v.x = (float)(r * inv_s);
+    v.y = (float)(uv * inv_vref);
+    reinterpret_cast<float2*>(x)[idx] = v;
+  }
+}
+
+// phi_0 = phi_prev + sigma * c on the unknowns of the planes k < nz.
+__global__ void k_warm_apply(double* __restrict__ u,
+                             const double* __restrict__ uprev,
+                             const float* __restrict__ c, LevelC L,
+                             const Counters* dc) {
+  const double sg = dc->sigma;
+  const int k1 = L.k1 < L.nz - 1 ? L.k1 : L.nz - 1;
+  const long long lo = (long long)L.k0 * L.nxy, hi = (long long)(k1 + 1) * L.nxy;
+  for (long long idx = lo + blockIdx.x * (long long)blockDim.x + threadIdx.x;
+       idx < hi; idx += (long long)gridDim.x * blockDim.x)
+    u[idx] = uprev[idx] + sg * (double)c[idx];
+}
+
+__global__ void k_warm_revert(double* __restrict__ u,
+                              const double* __restrict__ uprev, LevelC L,
+                              const Counters* dc) {
+  if (!dc->warm_reject) return;
+  const long long lo = (long long)L.k0 * L.nxy, hi = (long long)(L.k1 + 1) * L.nxy;
+  for (long long idx = lo + blockIdx.x * (long long)blockDim.x + threadIdx.x;
+       idx < hi; idx += (long long)gridDim.x * blockDim.x)
+    u[idx] = uprev[idx];
+}
+
+// Training target (phi - phi_prev) / sigma on the planes k < nz.
+__global__ void k_warm_target(const double* __restrict__ u,
+                              const double* __restrict__ uprev, LevelC L,
+                              const Counters* dc, float* __restrict__ t) {
+  const double sg = dc->sigma;
+  const double inv_s = sg > 0.0 ? 1.0 / sg : 0.0;
+  const long long n = L.nxy * L.nz;
+  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+       idx < n; idx += (long long)gridDim.x * blockDim.x)
+    t[idx] = (float)((u[idx] - uprev[idx]) * inv_s);
 }
 
 // ---- multigrid node operations ---------------------------------------------
@@ -727,6 +829,37 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
   const long long nu = Lc.nxy * (Lc.k1 - Lc.k0 + 1);
   float* rf = c->mixed ? L0.ff : nullptr;
   float* ef = c->mixed ? L0.uf : nullptr;
+  bool used_net = false;
+  if (warm && c->warm_mode != PIC_WS_PREV) {
+    tmark(c, PIC_PH_WARM, true);
+    // Record the normalised residual of the previous potential (the
+    // network's input, and with the solution the training target).
+    double vref = 1.0;
+    if (c->cfg.bc_lo == PIC_BC_DIRICHLET && fabs(c->cfg.v_lo) > vref) vref = fabs(c->cfg.v_lo);
+    if (c->cfg.bc_hi == PIC_BC_DIRICHLET && fabs(c->cfg.v_hi) > vref) vref = fabs(c->cfg.v_hi);
+    k_residual<<<kRedBlocks, kThreads, 0, st>>>(L0.u, L0.f, Lc, c->partials,
+                                                c->dc, nullptr, nullptr);
+    k_warm_final<<<1, 1024, 0, st>>>(c->partials, kRedBlocks, c->dc, 0,
+                                     (double)nu);
+    k_warm_input<<<kRedBlocks, kThreads, 0, st>>>(L0.u, L0.f, Lc, c->dc,
+                                                  1.0 / vref, c->warm_x,
+                                                  c->warm_prev);
+    c->warm_recorded = true;
+    const float* out = nullptr;
+    if (c->warm_mode == PIC_WS_UNET && c->net &&
+        pic_unet_infer(c->net, c->warm_x, Lc.nz, Lc.ny, Lc.nx, st, &out)) {
+      used_net = true;
+      k_warm_apply<<<kRedBlocks, kThreads, 0, st>>>(L0.u, c->warm_prev, out,
+                                                    Lc, c->dc);
+      k_residual<<<kRedBlocks, kThreads, 0, st>>>(L0.u, L0.f, Lc, c->partials,
+                                                  c->dc, nullptr, nullptr);
+      k_warm_final<<<1, 1024, 0, st>>>(c->partials, kRedBlocks, c->dc, 1,
+                                       (double)nu);
+      k_warm_revert<<<kRedBlocks, kThreads, 0, st>>>(L0.u, c->warm_prev, Lc,
+                                                     c->dc);
+    }
+    tmark(c, PIC_PH_WARM, false);
+  }
   // Initial check of the warm start.
   k_residual<<<kRedBlocks, kThreads, 0, st>>>(L0.u, L0.f, Lc, c->partials,
                                               c->dc, rf, ef);
@@ -748,7 +881,8 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
       k_final<<<1, 1024, 0, st>>>(c->partials, c->qpartials, kRedBlocks,
                                   c->dc, 1, c->cfg.rel_tol);
     }
-    hipMemcpyAsync(&c->hc.vcycles, &c->dc->vcycles, 4 * sizeof(int) + 2 * sizeof(double),
+    hipMemcpyAsync(&c->hc.vcycles, &c->dc->vcycles,
+                   sizeof(Counters) - offsetof(Counters, vcycles),
                    hipMemcpyDeviceToHost, st);
     hipStreamSynchronize(st);
     if (c->hc.done || launched >= c->cfg.max_vcycles) break;
@@ -758,8 +892,17 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
   info->converged = c->hc.done && !(c->hc.err & kErrNonFinite) ? 1 : 0;
   info->rel_residual = c->hc.rel_res;
   info->b_norm = c->hc.b_norm;
+  info->rel_residual0 = c->hc.rel_res0;
+  info->warm_used = used_net ? 1 : 0;
+  info->warm_rejected = used_net ? c->hc.warm_reject : 0;
+  info->warm_ratio = used_net ? c->hc.warm_ratio : 1.0;
   c->last_vcycles = c->hc.vcycles > 0 ? c->hc.vcycles : 1;
   if (!info->converged) *status = PIC_ERR_NOCONV;
+}
+
+void field_warm_target(pic_ctx* c, float* t) {
+  k_warm_target<<<kRedBlocks, kThreads, 0, c->stream>>>(
+      c->lev[0].u, c->warm_prev, level_c(c, 0), c->dc, t);
 }
 
 void field_efield(pic_ctx* c) {

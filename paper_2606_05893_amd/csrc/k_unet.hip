@@ -735,6 +735,26 @@ pic_status unet_check(pic_unet* u, int D, int H, int W) {
 
 }  // namespace
 
+bool pic_unet_fits(const pic_unet* u, int D, int H, int W) {
+  return unet_check(const_cast<pic_unet*>(u), D, H, W) == PIC_OK;
+}
+
+// Inference for the solve's warm start: the network reads x in place and
+// runs on the solver's stream.
+bool pic_unet_infer(pic_unet* u, const float* x, int D, int H, int W,
+                    hipStream_t st, const float** out) {
+  if (unet_check(u, D, H, W) != PIC_OK) return false;
+  float* keep_x = u->x_in;
+  hipStream_t keep_st = u->stream;
+  u->x_in = const_cast<float*>(x);
+  u->stream = st;
+  const bool ok = unet_forward(u, D, H, W);
+  u->x_in = keep_x;
+  u->stream = keep_st;
+  *out = u->out;
+  return ok;
+}
+
 extern "C" {
 
 int64_t pic_unet_param_count(void) { return param_count(); }

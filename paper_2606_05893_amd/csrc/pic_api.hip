@@ -174,6 +174,8 @@ size_t carve(pic_ctx* c, char* base) {
   c->q_vel = cv.take<double>(3 * f.queue_capacity);
   c->fn_scan = cv.take<unsigned>(2 * c->g.nxy + 2);
   c->dc = cv.take<Counters>(1);
+  c->warm_x = cv.take<float>(2 * c->g.nxy * f.nz);
+  c->warm_prev = cv.take<double>(c->nnodes);
   return cv.off + kAlign;
 }
 
@@ -344,6 +346,9 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->step = 0;
   c->queue_used = 0;
   c->last_vcycles = 0;
+  c->warm_mode = PIC_WS_PREV;
+  c->net = nullptr;
+  c->warm_recorded = false;
   std::memset(&c->coll, 0, sizeof(c->coll));
   std::memset(&c->src, 0, sizeof(c->src));
   std::memset(&c->last_solve, 0, sizeof(c->last_solve));
@@ -567,6 +572,41 @@ pic_status poisson_solve(pic_ctx* c, const double* rho, double* phi,
     return PIC_ERR_HIP;
   if (st != PIC_OK)
     return set_err(c, (pic_status)st, "Poisson solve did not converge");
+  return PIC_OK;
+}
+
+pic_status pic_set_warm_start(pic_ctx* c, int32_t mode, pic_unet* net) {
+  if (!c) return PIC_ERR_ARG;
+  if (mode != PIC_WS_PREV && mode != PIC_WS_RECORD && mode != PIC_WS_UNET)
+    return set_err(c, PIC_ERR_ARG, "unknown warm-start mode");
+  if (mode == PIC_WS_UNET) {
+    if (!net) return set_err(c, PIC_ERR_ARG, "learned warm start needs a network");
+    const pic_config& f = c->cfg;
+    if ((f.nx & 7) || (f.ny & 7) || (f.nz & 7) || f.nx < 8 || f.ny < 8 ||
+        f.nz < 8 || !pic_unet_fits(net, f.nz, f.ny, f.nx))
+      return set_err(c, PIC_ERR_ARG,
+                     "grid (nz, ny, nx) must be multiples of 8 within the network's size");
+  }
+  c->warm_mode = mode;
+  c->net = mode == PIC_WS_UNET ? net : nullptr;
+  c->warm_recorded = false;
+  return PIC_OK;
+}
+
+pic_status pic_warm_pair(pic_ctx* c, float* input, float* target) {
+  if (!c || (!input && !target)) return PIC_ERR_ARG;
+  if (!c->warm_recorded)
+    return set_err(c, PIC_ERR_STATE, "no solve has recorded a warm-start pair");
+  if (input &&
+      !hip_ok(c, hipMemcpyAsync(input, c->warm_x,
+                                2 * c->g.nxy * c->cfg.nz * sizeof(float),
+                                hipMemcpyDeviceToDevice, c->stream),
+              "pair copy"))
+    return PIC_ERR_HIP;
+  if (target) field_warm_target(c, target);
+  if (!hip_ok(c, hipGetLastError(), "pair launch") ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "synchronise"))
+    return PIC_ERR_HIP;
   return PIC_OK;
 }
 

@@ -10,6 +10,14 @@
 #include "pic.h"
 #include "pic_device.h"
 
+// Forward pass of the warm-start network on the caller's stream with the
+// input x of a D x H x W grid; *out receives the network's output buffer.
+// False if the grid does not fit the network.
+bool pic_unet_infer(pic_unet* u, const float* x, int D, int H, int W,
+                    hipStream_t st, const float** out);
+// The grid D x H x W is within the network's maximum.
+bool pic_unet_fits(const pic_unet* u, int D, int H, int W);
+
 namespace pic {
 
 // One multigrid level: nx*ny*(nz+1) nodes with spacing 2^l dx.  Equations
@@ -98,6 +106,14 @@ struct pic_ctx {
   long long queue_used;
   int last_vcycles;
   pic_solve_info last_solve;
+
+  // Warm start of the field solve (PIC_WS_*), the attached network and the
+  // recorded (input, previous potential) of the last solve.
+  int warm_mode;
+  pic_unet* net;
+  float* warm_x;             // (nz, ny, nx, 2) network input
+  double* warm_prev;         // potential before the warm start, all nodes
+  bool warm_recorded;
   std::string err;
 
   // Optional phase timing (HIP events on the context's stream).
@@ -122,6 +138,8 @@ inline void tmark(pic_ctx* c, int ph, bool begin) {
 void field_rhs(pic_ctx* c, const double* rho_or_null);
 void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status);
 void field_efield(pic_ctx* c);
+// Target (phi - phi_prev) / sigma of the last recorded solve, (nz, ny, nx).
+void field_warm_target(pic_ctx* c, float* t);
 void field_phi_to_level0(pic_ctx* c);
 
 // ---- particles (k_particles.hip) -------------------------------------------

@@ -268,6 +268,13 @@ struct Counters {
   double b_norm;
   double kinetic[3];
   double field_energy;
+  // Warm start of the field solve.
+  double warm_r0;                   // ||r|| of the previous potential
+  double sigma;                     // RMS of that residual over unknowns
+  double warm_ratio;                // ||r(phi_0)|| / ||r(phi_prev)||
+  double rel_res0;                  // relative residual before the V-cycles
+  int warm_reject;                  // learned start rejected this solve
+  int warm_pad;
 };
 
 enum : unsigned int {

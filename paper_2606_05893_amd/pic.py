@@ -63,7 +63,9 @@ class Sources(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("vcycles", _c_i32), ("converged", _c_i32),
-                ("rel_residual", _c_d), ("b_norm", _c_d)]
+                ("rel_residual", _c_d), ("b_norm", _c_d),
+                ("rel_residual0", _c_d), ("warm_ratio", _c_d),
+                ("warm_used", _c_i32), ("warm_rejected", _c_i32)]
 
 
 class Diag(ctypes.Structure):
@@ -109,13 +111,16 @@ EXPORTS = {
     "pic_read_fields": (_c_i32, [_c_p, _c_p, _c_p, _c_p]),
     "pic_set_clock": (_c_i32, [_c_p, _c_i64, _c_u64]),
     "pic_get_diag": (_c_i32, [_c_p, ctypes.POINTER(Diag)]),
+    "pic_set_warm_start": (_c_i32, [_c_p, _c_i32, _c_p]),
+    "pic_warm_pair": (_c_i32, [_c_p, _c_p, _c_p]),
     "pic_enable_timing": (_c_i32, [_c_p, _c_i32]),
     "pic_phase_times": (_c_i32, [_c_p, ctypes.POINTER(_c_d),
                                  ctypes.POINTER(_c_i64)]),
 }
 
 PHASES = ("deposit", "rhs", "poisson", "efield", "sources", "push_neutral",
-          "push_ion", "push_electron", "collide", "absorbed", "bin")
+          "push_ion", "push_electron", "collide", "absorbed", "bin", "warm")
+WARM_MODES = {"prev": 0, "record": 1, "unet": 2}
 
 _lib = None
 
@@ -349,6 +354,21 @@ class Pic:
         self._call("pic_phase_times", ms, calls)
         return {k: (ms[i], calls[i]) for i, k in enumerate(PHASES)}
 
+    def set_warm_start(self, mode, net=None):
+        """mode: "prev", "record" or "unet" (net: a UNet on this device)."""
+        self.net = net  # keeps the network alive while attached
+        self._call("pic_set_warm_start", WARM_MODES[mode],
+                   net.u if net is not None else None)
+
+    def warm_pair(self):
+        """(input (nz, ny, nx, 2), target (nz, ny, nx)) FP32 of the last
+        recorded solve."""
+        nz, ny, nx = self.p["nz"], self.p["ny"], self.p["nx"]
+        x = torch.empty((nz, ny, nx, 2), dtype=torch.float32, device="cuda")
+        t = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+        self._call("pic_warm_pair", _ptr(x), _ptr(t))
+        return x, t
+
     def set_clock(self, step, next_id):
         self._call("pic_set_clock", int(step), int(next_id))
 
@@ -440,6 +460,10 @@ class UNet:
         self.n_params = int(self.lib.pic_unet_param_count())
         if params is not None:
             self.set_params(params)
+
+    @staticmethod
+    def param_count():
+        return int(_unet_lib().pic_unet_param_count())
 
     def __del__(self):
         if getattr(self, "u", None):

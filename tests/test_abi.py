@@ -32,7 +32,9 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared() if not hasattr(lib, n)]
     assert not missing, missing
     lib.pic_abi_version.restype = ctypes.c_int32
-    assert lib.pic_abi_version() == 1
+    hdr = open(os.path.join(ROOT, "include", "pic.h")).read()
+    ver = int(re.search(r"#define PIC_ABI_VERSION (\d+)", hdr).group(1))
+    assert lib.pic_abi_version() == ver
 
 
 def test_workspace_size_and_validation_on_host():
