@@ -12,8 +12,13 @@ resident in HBM), ms per step, the dominant kernel's roofline (algorithmic
 bytes per launch over its HIP-event-timed duration), and the CPU oracle on a
 bounded sample of the same workload.
 
+The three forms of the step run one after another on the same preload:
+plain FP64 multigrid (the JSON line's value), mixed precision, and mixed
+precision with the learned warm start, every solve to the same residual.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--precision fp64|mixed] [--no-cpu-baseline]
+                       [--variant all|fp64|mixed|learned_mixed]
+                       [--no-cpu-baseline]
 """
 import argparse
 import json
@@ -33,7 +38,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--variant", default="all",
+                    choices=["all", "fp64", "mixed", "learned_mixed"],
+                    help="fp64: plain FP64 multigrid; mixed: FP32 particles and "
+                         "smoothing with FP64 refinement; learned_mixed: mixed "
+                         "with the U-Net warm start (trained first on pairs "
+                         "from another run); all: the three, value = fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phases", action="store_true",
                     help="print per-phase times to stderr")
@@ -77,6 +87,125 @@ def cpu_baseline(p_full):
             "seconds": el}
 
 
+UNET_LAYERS = ((2, 16, 0), (16, 16, 0), (16, 32, 1), (32, 32, 1), (32, 64, 2),
+               (64, 64, 2), (64, 128, 3), (128, 128, 3), (192, 64, 2),
+               (64, 64, 2), (96, 32, 1), (32, 32, 1), (48, 16, 0), (16, 16, 0))
+
+
+def unet_flops(D, H, W):
+    """FLOP of one forward pass (2 per multiply-add; 3x3x3 convolutions and
+    the 1x1x1 head)."""
+    V0 = D * H * W
+    f = sum(2 * 27 * ci * co * (V0 >> (3 * lv)) for ci, co, lv in UNET_LAYERS)
+    return f + 2 * 16 * V0
+
+
+def capacities(p, total_steps):
+    pl = p["preload"]
+    per_step_n = p["sources"].get("disk", {}).get("n_n", 0) + \
+        p["sources"].get("sphere", {}).get("n", 0)
+    return (pl["n_e"] + 2_000_000,
+            pl["n_n"] + per_step_n * (total_steps + 2) + 1_000_000,
+            pl["n_ion"] + 2_000_000), per_step_n
+
+
+def new_context(G, p, precision, pre, n0, cap):
+    q = dict(p)
+    q["precision"] = precision
+    gpu = G.Pic(q, capacity=cap, max_events=1 << 17, queue_capacity=1 << 10)
+    for s, (pos, vel, ids) in pre.items():
+        gpu.load(s, pos, vel, ids)
+    gpu.set_clock(0, n0)
+    return gpu
+
+
+def train_warm_start(G, W, WS, p, cap, steps=12, epochs=4):
+    """The learned start's network, trained on pairs recorded by a mixed
+    run from another preload (seed 2) than the timed runs (seed 1)."""
+    import torch
+    pre = W.preload(p, seed=2)
+    n0 = sum(v[0].shape[0] for v in pre.values())
+    gpu = new_context(G, p, "mixed", pre, n0, cap)
+    del pre
+    for _ in range(2):
+        gpu.step(p["dt"])
+    pairs, _ = WS.collect_pairs(gpu, p["dt"], steps)
+    del gpu
+    torch.cuda.empty_cache()
+    net = G.UNet(p["nz"], p["ny"], p["nx"], params=W.unet_init(0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = WS.train(net, pairs, epochs=epochs, lr_max=1e-3, lr_min=1e-5)
+    torch.cuda.synchronize()
+    info = {"pairs": len(pairs), "epochs": epochs,
+            "train_s": round(time.perf_counter() - t0, 3),
+            "epoch_loss": [round(v, 5) for v in losses],
+            "source": "mixed run, preload seed 2"}
+    del pairs
+    torch.cuda.empty_cache()
+    return net, info
+
+
+def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None):
+    import numpy as np
+    import torch
+    gpu = new_context(G, p, precision, pre, n0, cap)
+    if net is not None:
+        gpu.set_warm_start("unet", net)
+    dt = p["dt"]
+    for _ in range(warmup):
+        gpu.step(dt)
+    counts = [gpu.count(s) for s in range(3)]
+
+    def timed(k):
+        nonlocal counts
+        psteps = 0
+        solves, electrons, ions = [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            psteps += sum(counts)
+            electrons.append(counts[0])
+            ions.append(counts[2])
+            _, d = gpu.step(dt)
+            counts = d["counts"]
+            solves.append(d["solve"])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, psteps, solves, electrons, ions
+
+    # Throughput without instrumentation, then the same number of steps
+    # with HIP events around every phase and finest-level smoothing launch
+    # for the per-kernel figures.
+    el, psteps, solves, electrons, ions = timed(steps)
+    gpu.enable_timing(True)
+    el_i, _, solves_i, electrons_i, ions_i = timed(steps)
+    ph = gpu.phase_times()
+    nu = gpu.p.get("nu_pre", 2) + gpu.p.get("nu_post", 2)
+    del gpu
+    torch.cuda.empty_cache()
+    out = {"precision": precision,
+           "warm_start": "unet" if net is not None else "previous phi",
+           "value": psteps / el, "ms_per_step": el / steps * 1e3,
+           "ms_per_step_instrumented": el_i / steps * 1e3,
+           "particles_avg": psteps / steps,
+           "electrons_avg": float(np.mean(electrons)),
+           "ions_avg": float(np.mean(ions)),
+           "vcycles_avg": float(np.mean([d["vcycles"] for d in solves])),
+           "start_rel_residual_avg": float(np.mean([d["rel_residual0"] for d in solves])),
+           "final_rel_residual_max": float(max(d["rel_residual"] for d in solves)),
+           "phase_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in ph.items()
+                        if k != "smooth_l0"}}
+    if net is not None:
+        out["warm_ratio_avg"] = float(np.mean([d["warm_ratio"] for d in solves]))
+        out["fallback_rate"] = float(np.mean([d["warm_rejected"] for d in solves]))
+    out["_phases"] = ph
+    out["_vcycles_total"] = sum(d["vcycles"] for d in solves_i)
+    out["_electrons_i"] = float(np.mean(electrons_i))
+    out["_ions_i"] = float(np.mean(ions_i))
+    out["_nu"] = nu
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -84,87 +213,78 @@ def main():
               "multi-GPU sharding of this path is a design, not a build.",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import workloads as W
     from paper_2606_05893_amd import pic as G
+    from paper_2606_05893_amd import warmstart as WS
 
     p = W.config(a.workload)
-    if a.precision:
-        p["precision"] = a.precision
     pl = p["preload"]
-    per_step_n = p["sources"].get("disk", {}).get("n_n", 0) + \
-        p["sources"].get("sphere", {}).get("n", 0)
-    total_steps = a.warmup + a.steps
-    cap = (pl["n_e"] + 2_000_000, pl["n_n"] + per_step_n * (total_steps + 2)
-           + 1_000_000, pl["n_ion"] + 2_000_000)
+    variants = (["fp64", "mixed", "learned_mixed"] if a.variant == "all"
+                else [a.variant])
+    cap, per_step_n = capacities(p, a.warmup + a.steps)
     torch.cuda.set_device(0)
-    gpu = G.Pic(p, capacity=cap, max_events=1 << 17, queue_capacity=1 << 10)
+    net, train_info = None, None
+    if "learned_mixed" in variants:
+        net, train_info = train_warm_start(G, W, WS, p, cap)
     pre = W.preload(p, seed=1)
-    n0 = 0
-    for s, (pos, vel, ids) in pre.items():
-        gpu.load(s, pos, vel, ids)
-        n0 += pos.shape[0]
+    n0 = sum(v[0].shape[0] for v in pre.values())
+    res = {}
+    for v in variants:
+        prec = "fp64" if v == "fp64" else "mixed"
+        res[v] = run_variant(G, p, prec, pre, n0, cap, a.steps, a.warmup,
+                             net if v == "learned_mixed" else None)
     del pre
-    gpu.set_clock(0, n0)
-    dt = p["dt"]
-    for _ in range(a.warmup):
-        gpu.step(dt)
-    counts = [gpu.count(s) for s in range(3)]
-    gpu.enable_timing(True)
-    torch.cuda.synchronize()
-    psteps = 0
-    vcycles = []
-    electrons = []
-    ions = []
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        psteps += sum(counts)
-        electrons.append(counts[0])
-        ions.append(counts[2])
-        _, d = gpu.step(dt)
-        counts = d["counts"]
-        vcycles.append(d["solve"]["vcycles"])
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ph = gpu.phase_times()
-    ms_step = el / a.steps * 1e3
-    value = psteps / el
-
-    # Timed kernel: the charged-particle push (k_push_tile: field gather
-    # from the LDS-staged tile, leapfrog, boundaries, cell keys and the
-    # electrons' null-collision candidate draw).  Algorithmic bytes per
-    # launch: per electron x, y, z, vx, vy, vz read and written (96 B), id
-    # read (8 B), cell key written (4 B); per ion 96 + 4 B; per node the three
-    # E components read once (24 B FP64, 12 B FP32); per cell the neutral
-    # count read once (4 B).
-    ms_push, n_push = ph["push_electron"]
-    ne_avg = float(np.mean(electrons))
-    ni_avg = float(np.mean(ions))
-    nodes = (p["nx"] * p["ny"] * (p["nz"] + 1))
+    head = res[variants[0]]
+    mixed = head["precision"] == "mixed"
+    ph = head["_phases"]
+    nodes = p["nx"] * p["ny"] * (p["nz"] + 1)
     cells = p["nx"] * p["ny"] * p["nz"]
-    mixed = p.get("precision") == "mixed"
+    unknowns = p["nx"] * p["ny"] * (p["nz"] - 1)
+
+    # Dominant kernel: the finest-level red-black Gauss-Seidel colour sweep
+    # (k_rbgs).  Algorithmic bytes per launch: u of every unknown read once
+    # (the colour's neighbours), f of the colour's half read and u of that
+    # half written: 16 B per unknown in FP64, 8 B in FP32.  Launches that
+    # only find the solve converged are timed but not counted as work.
+    ms_sm, n_sm = ph["smooth_l0"]
+    n_eff = 2 * head["_nu"] * head["_vcycles_total"]
+    per_u = 8 if mixed else 16
+    sm_bytes = unknowns * per_u
+    achieved = sm_bytes * n_eff / (ms_sm * 1e-3) / 1e9 if ms_sm > 0 else 0.0
+    roofline = {"bound": "hbm", "kernel": "k_rbgs (finest level, one colour)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_launch": int(sm_bytes),
+                "launches_timed": int(n_sm), "launches_with_work": int(n_eff),
+                "avg_launch_ms": round(ms_sm / max(n_eff, 1), 5)}
+
+    # Charged-particle push (k_push_tile): per electron x, y, z, vx, vy, vz
+    # read and written (96 B FP64; 56 B mixed as cell + FP32 offsets and
+    # velocities), id read (8 B), cell key written (4 B); per ion the same
+    # without the id; per node the three E components read once; per cell
+    # the neutral count read once (4 B).
+    ms_push, n_push = ph["push_electron"]
     per_e = (56 + 8 + 4) if mixed else (96 + 8 + 4)
     per_i = (56 + 4) if mixed else (96 + 4)
     per_node = 12 if mixed else 24
-    alg_bytes = ne_avg * per_e + ni_avg * per_i + nodes * per_node + cells * 4
+    alg_bytes = (head["_electrons_i"] * per_e + head["_ions_i"] * per_i
+                 + nodes * per_node + cells * 4)
     t_push = ms_push / max(n_push, 1) * 1e-3
-    achieved = alg_bytes / t_push / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_push_tile",
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None,
-                "bytes_per_launch": int(alg_bytes),
-                "avg_launch_ms": round(t_push * 1e3, 5)}
-    phases = {k: round(v[0] / max(v[1], 1), 4) for k, v in ph.items()}
+    ach_p = alg_bytes / t_push / 1e9
+    roofline_push = {"bound": "hbm", "kernel": "k_push_tile",
+                     "achieved": round(ach_p, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach_p / HBM_PEAK_GBS, 4),
+                     "bytes_per_launch": int(alg_bytes),
+                     "avg_launch_ms": round(t_push * 1e3, 5)}
     out = {
         "metric": "particle-steps/s + ms/PIC step at 10M particles; "
                   "learned+mixed vs plain MG",
-        "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "value": head["value"], "unit": "particle-steps/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: {p['nx']}x{p['ny']}x{p['nz']} "
@@ -172,17 +292,34 @@ def main():
                                f"{pl['n_e']} e + {pl['n_ion']} Cu+ + "
                                f"{pl['n_n']} Cu, FN disk + "
                                f"{per_step_n} Cu/step, Poisson to 1e-10",
-                   "precision": "mixed" if mixed else "fp64",
-                   "particles_avg": psteps / a.steps,
-                   "electrons_avg": ne_avg,
-                   "vcycles_avg": float(np.mean(vcycles)),
-                   "phase_ms": phases},
+                   "variant": variants[0]},
         "roofline": roofline,
+        "roofline_push": roofline_push,
+        "variants": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")}
+                     for k, v in res.items()},
     }
+    if "learned_mixed" in res:
+        lm = res["learned_mixed"]
+        ms_w, n_w = lm["_phases"]["warm"]
+        fl = unet_flops(p["nz"], p["ny"], p["nx"])
+        t_w = ms_w / max(n_w, 1) * 1e-3
+        out["roofline_unet"] = {
+            "bound": "mfma", "kernel": "U-Net forward (BF16 MFMA) within the "
+                                      "warm-start stage",
+            "achieved": round(fl / t_w / 1e12, 2), "peak": 2500.0,
+            "unit": "TFLOP/s", "frac": round(fl / t_w / 1e12 / 2500.0, 4),
+            "flop_per_inference": fl, "stage_ms": round(t_w * 1e3, 4)}
+        out["warm_start_training"] = train_info
+        if "fp64" in res:
+            out["learned_mixed_vs_fp64_step_time"] = round(
+                lm["ms_per_step"] / res["fp64"]["ms_per_step"], 4)
+        if "mixed" in res:
+            out["learned_mixed_vs_mixed_step_time"] = round(
+                lm["ms_per_step"] / res["mixed"]["ms_per_step"], 4)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     if a.phases:
-        print(json.dumps(phases, indent=1), file=sys.stderr)
+        print(json.dumps(out["variants"], indent=1), file=sys.stderr)
     print(json.dumps(out), flush=True)
 
 

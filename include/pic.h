@@ -234,15 +234,18 @@ pic_status pic_set_clock(pic_ctx* ctx, int64_t step, uint64_t next_id);
 pic_status pic_get_diag(pic_ctx* ctx, pic_diag* diag);
 
 /* Per-phase GPU time, measured with HIP events recorded on the context's
- * stream around each phase of a step (off by default).  ms[PIC_NPHASES]
- * receives the time accumulated since timing was enabled, calls[] (may be
- * NULL) the number of timed executions of each phase. */
-#define PIC_NPHASES 12
+ * stream around each phase of a step (off by default; at most 256 intervals
+ * of a phase per step are timed).  ms[PIC_NPHASES] receives the time
+ * accumulated since timing was enabled, calls[] (may be NULL) the number of
+ * timed intervals of each phase. */
+#define PIC_NPHASES 13
 enum {
   PIC_PH_DEPOSIT = 0, PIC_PH_RHS, PIC_PH_POISSON, PIC_PH_EFIELD,
   PIC_PH_SOURCES, PIC_PH_PUSH_NEUTRAL, PIC_PH_PUSH_ION, PIC_PH_PUSH_ELECTRON,
   PIC_PH_COLLIDE, PIC_PH_ABSORBED, PIC_PH_BIN,
-  PIC_PH_WARM /* warm-start stage of the solve (inside PIC_PH_POISSON) */
+  PIC_PH_WARM,    /* warm-start stage of the solve (inside PIC_PH_POISSON) */
+  PIC_PH_SMOOTH0  /* each finest-level smoothing launch (inside the solve;
+                     calls counts launches)                               */
 };
 pic_status pic_enable_timing(pic_ctx* ctx, int32_t on);
 pic_status pic_phase_times(pic_ctx* ctx, double* ms, int64_t* calls);

@@ -774,8 +774,11 @@ void vcycle(pic_ctx* c, int l) {
   T* f = lev_f<T>(L);
   const long long nhalf = (long long)(L.nx / 2) * L.ny * (Lc.k1 - Lc.k0 + 1);
   for (int s = 0; s < c->cfg.nu_pre; ++s)
-    for (int color = 0; color < 2; ++color)
+    for (int color = 0; color < 2; ++color) {
+      if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
       k_rbgs<T><<<nblocks(nhalf), kThreads, 0, st>>>(u, f, Lc, color, c->dc);
+      if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
+    }
   Level& N = c->lev[l + 1];
   LevelC Nc = level_c(c, l + 1);
   if (N.nx >= kRX && N.ny >= kRY) {
@@ -791,8 +794,11 @@ void vcycle(pic_ctx* c, int l) {
   k_prolong<T><<<nblocks(Lc.nxy * (Lc.k1 - Lc.k0 + 1)), kThreads, 0, st>>>(
       u, lev_u<T>(N), Lc, Nc, c->dc);
   for (int s = 0; s < c->cfg.nu_post; ++s)
-    for (int color = 0; color < 2; ++color)
+    for (int color = 0; color < 2; ++color) {
+      if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
       k_rbgs<T><<<nblocks(nhalf), kThreads, 0, st>>>(u, f, Lc, color, c->dc);
+      if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
+    }
 }
 
 }  // namespace

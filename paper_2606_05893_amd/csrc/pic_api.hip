@@ -256,14 +256,15 @@ __global__ void k_deinterleave_E(const char* __restrict__ E, int mixed,
 void collect_times(pic_ctx* c) {
   if (!c->timing) return;
   for (int p = 0; p < PIC_NPHASES; ++p) {
-    if (!c->tpending[p]) continue;
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, c->tev[2 * p], c->tev[2 * p + 1]) ==
-        hipSuccess) {
-      c->tms[p] += ms;
-      c->tcalls[p] += 1;
+    for (int i = 0; i < c->tn[p]; ++i) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, c->tev[p][i][0], c->tev[p][i][1]) ==
+          hipSuccess) {
+        c->tms[p] += ms;
+        c->tcalls[p] += 1;
+      }
     }
-    c->tpending[p] = false;
+    c->tn[p] = 0;
   }
 }
 
@@ -367,23 +368,27 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
 void pic_destroy(pic_ctx* c) {
   if (!c) return;
   if (c->ev_made)
-    for (int i = 0; i < 2 * PIC_NPHASES; ++i) hipEventDestroy(c->tev[i]);
+    for (int p = 0; p < PIC_NPHASES; ++p)
+      for (int i = 0; i < pic_ctx::kTimeIv; ++i)
+        for (int e = 0; e < 2; ++e) hipEventDestroy(c->tev[p][i][e]);
   delete c;
 }
 
 pic_status pic_enable_timing(pic_ctx* c, int32_t on) {
   if (!c) return PIC_ERR_ARG;
   if (on && !c->ev_made) {
-    for (int i = 0; i < 2 * PIC_NPHASES; ++i)
-      if (!hip_ok(c, hipEventCreate(&c->tev[i]), "event create"))
-        return PIC_ERR_HIP;
+    for (int p = 0; p < PIC_NPHASES; ++p)
+      for (int i = 0; i < pic_ctx::kTimeIv; ++i)
+        for (int e = 0; e < 2; ++e)
+          if (!hip_ok(c, hipEventCreate(&c->tev[p][i][e]), "event create"))
+            return PIC_ERR_HIP;
     c->ev_made = true;
   }
   c->timing = on != 0;
   for (int p = 0; p < PIC_NPHASES; ++p) {
     c->tms[p] = 0.0;
     c->tcalls[p] = 0;
-    c->tpending[p] = false;
+    c->tn[p] = 0;
   }
   return PIC_OK;
 }

@@ -119,8 +119,10 @@ struct pic_ctx {
   // Optional phase timing (HIP events on the context's stream).
   bool timing;
   bool ev_made;
-  hipEvent_t tev[2 * PIC_NPHASES];
-  bool tpending[PIC_NPHASES];
+  // Up to kTimeIv intervals per phase between two collections (one step).
+  static constexpr int kTimeIv = 256;
+  hipEvent_t tev[PIC_NPHASES][kTimeIv][2];
+  int tn[PIC_NPHASES];
   double tms[PIC_NPHASES];
   long long tcalls[PIC_NPHASES];
 };
@@ -130,8 +132,10 @@ namespace pic {
 // Record the start (begin = true) or end of a timed phase.
 inline void tmark(pic_ctx* c, int ph, bool begin) {
   if (!c->timing) return;
-  hipEventRecord(c->tev[2 * ph + (begin ? 0 : 1)], c->stream);
-  if (!begin) c->tpending[ph] = true;
+  const int i = c->tn[ph];
+  if (i >= pic_ctx::kTimeIv) return;
+  hipEventRecord(c->tev[ph][i][begin ? 0 : 1], c->stream);
+  if (!begin) c->tn[ph] = i + 1;
 }
 
 // ---- field (k_field.hip) ---------------------------------------------------

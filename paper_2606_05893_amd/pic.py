@@ -119,7 +119,8 @@ EXPORTS = {
 }
 
 PHASES = ("deposit", "rhs", "poisson", "efield", "sources", "push_neutral",
-          "push_ion", "push_electron", "collide", "absorbed", "bin", "warm")
+          "push_ion", "push_electron", "collide", "absorbed", "bin", "warm",
+          "smooth_l0")
 WARM_MODES = {"prev": 0, "record": 1, "unet": 2}
 
 _lib = None
