@@ -223,7 +223,7 @@ def main():
     pl = p["preload"]
     variants = (["fp64", "mixed", "learned_mixed"] if a.variant == "all"
                 else [a.variant])
-    cap, per_step_n = capacities(p, a.warmup + a.steps)
+    cap, per_step_n = capacities(p, a.warmup + 2 * a.steps)
     torch.cuda.set_device(0)
     net, train_info = None, None
     if "learned_mixed" in variants:
