@@ -58,6 +58,9 @@ enum { PIC_ELECTRON = 0, PIC_NEUTRAL = 1, PIC_ION = 2 };
 enum { PIC_BC_DIRICHLET = 0, PIC_BC_NEUMANN = 1 };
 enum { PIC_FP64 = 0, PIC_MIXED = 1 };
 enum { PIC_ION_LOTZ = 0, PIC_ION_CONST = 1 };
+/* PIC_FLAG_PLAIN_SMOOTHER: smooth with one launch per colour and sweep
+ * instead of the fused two-sweep pass (same arithmetic, same results). */
+enum { PIC_FLAG_PLAIN_SMOOTHER = 1 };
 enum { PIC_WARM_ZERO = 0, PIC_WARM_GIVEN = 1 };
 /* Warm start of the field solve in pic_step / pic_field (and of
  * poisson_solve with PIC_WARM_GIVEN): the previous potential; the same
@@ -88,7 +91,7 @@ typedef struct {
   double rel_tol;          /* ||b - A phi||_2 / ||b||_2 target, e.g. 1e-10 */
   uint64_t seed;           /* Philox key                                   */
   uint32_t w_sp;           /* superparticle weight (all species), >= 1     */
-  uint32_t reserved;
+  uint32_t flags;          /* PIC_FLAG_* (0 by default)                    */
   int64_t capacity[3];     /* particles per species (electron, Cu, Cu+)    */
   int64_t queue_capacity;  /* particles pic_inject may queue per step      */
   int64_t max_events;      /* ionisation events / cathode absorptions /

@@ -7,6 +7,8 @@
 // byte), so they are written for coalesced 64-lane access along x and use no
 // matrix cores.  The red-black Gauss-Seidel smoother is generic in the
 // precision (FP64, or FP32 for the correction solve of the mixed form).
+#include <type_traits>
+
 #include "pic_ctx.h"
 
 namespace pic {
@@ -683,12 +685,236 @@ inline unsigned nblocks(long long n, int t = kThreads) {
   return (unsigned)((n + t - 1) / t);
 }
 
+// ---- fused smoothing ------------------------------------------------------
+// Two red-black Gauss-Seidel sweeps (red, black, red, black) in one pass over
+// the level, from uin to uout.  A workgroup owns a kSX x kSY column of nodes
+// and a segment of z planes and marches up z with a ring of kSR planes of u
+// in LDS: at step p it applies half-sweep h to plane p-h (h = 0..3), so
+// every half-sweep sees the other colour's values of the previous half-sweep
+// on the three planes it reads.  Half-sweep h updates the column widened by
+// 3-h nodes in x, y and z (the halo it leaves valid for h+1), so the final
+// values of the owned nodes are exactly those of four grid-wide colour
+// launches; the widened nodes are recomputed by the neighbouring workgroups
+// from the same old values.  The next-but-one plane of u and the f operands
+// of the next step are loaded into registers while the current step
+// computes.  HBM traffic per pass: u and f read and u written once, against
+// about four times that for separate launches.
+constexpr int kSX = 32, kSY = 8, kSH = 4;
+constexpr int kSPX = kSX + 2 * kSH, kSPY = kSY + 2 * kSH;
+constexpr int kSP = kSPX * kSPY;  // 640 nodes per plane slot
+constexpr int kSR = 6;
+constexpr int kSLoad = (kSP + 255) / 256;
+
+__device__ __forceinline__ int wrap_n(int v, int n) {
+  v = v < 0 ? v + n : v;
+  return v >= n ? v - n : v;
+}
+
+// The colour nodes of half-sweep h's region that thread tid updates (at most
+// two): LDS index and in-plane global offsets for both parities of the
+// plane, and the parity of the row.
+struct HalfSlot {
+  int c0, g0, g1, b;
+  bool on;
+};
+
+template <int H>
+__device__ __forceinline__ HalfSlot half_slot(int tid, int s, int x0, int y0,
+                                              int nx, int ny) {
+  constexpr int e = 3 - H;
+  constexpr int hw = (kSX + 2 * e) / 2;
+  constexpr int cnt = hw * (kSY + 2 * e);
+  HalfSlot r;
+  const int t = tid + 256 * s;
+  r.on = t < cnt;
+  const int row = t / hw, kk = t % hw;
+  const int ly = kSH - e + row, lx = kSH - e + 2 * kk;
+  r.c0 = ly * kSPX + lx;
+  r.g0 = r.g1 = 0;
+  if (r.on) {
+    const int gy = wrap_n(wrap_n(y0 + ly, ny), ny);
+    r.g0 = gy * nx + wrap_n(wrap_n(x0 + lx, nx), nx);
+    r.g1 = gy * nx + wrap_n(wrap_n(x0 + lx + 1, nx), nx);
+  }
+  // Node colour is (x + y + z) & 1, and x0, y0, nx, ny are even, so the
+  // local indices carry the parity: lx + d + ly + q == colour.
+  r.b = ((H & 1) + ly + lx) & 1;
+  return r;
+}
+
+template <int N>
+using IC = std::integral_constant<int, N>;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
+                                                 T* __restrict__ uout,
+                                                 const T* __restrict__ f,
+                                                 LevelC L, int seg,
+                                                 const Counters* dc) {
+  __shared__ T ring[kSR][kSP];
+  if (dc->done) return;
+  const int tiles_x = (L.nx + kSX - 1) / kSX;
+  const int tiles_y = (L.ny + kSY - 1) / kSY;
+  int bi = blockIdx.x;
+  const int tx = bi % tiles_x;
+  bi /= tiles_x;
+  const int ty = bi % tiles_y;
+  const int za = (bi / tiles_y) * seg;
+  const int zb = za + seg < L.nz + 1 ? za + seg : L.nz + 1;
+  const int x0 = tx * kSX - kSH, y0 = ty * kSY - kSH;
+  const T h2 = (T)L.h2;
+  const T sixth = T(1) / T(6);
+  const int tid = threadIdx.x;
+
+  // Plane loads: up to kSLoad nodes of a slot per thread.  Every global
+  // load is issued unconditionally (clamped to a valid node, its result
+  // unused where it is not needed), so the compiler waits for exactly the
+  // loads a use depends on while later ones stay in flight: the u plane of
+  // step p+4 and the f operands of step p+3 are loaded during step p.
+  int loff[kSLoad];
+#pragma unroll
+  for (int r = 0; r < kSLoad; ++r) {
+    const int t = tid + 256 * r;
+    loff[r] = 0;
+    if (t < kSP) {
+      const int gx = wrap_n(wrap_n(x0 + t % kSPX, L.nx), L.nx);
+      const int gy = wrap_n(wrap_n(y0 + t / kSPX, L.ny), L.ny);
+      loff[r] = gy * L.nx + gx;
+    }
+  }
+  // Update slots: half-sweep 0 covers up to 266 nodes (two per thread),
+  // half-sweeps 1-3 at most 216 (one per thread).
+  constexpr int kNS = 5;
+  constexpr int slot_h[kNS] = {0, 0, 1, 2, 3};
+  HalfSlot hs[kNS];
+  hs[0] = half_slot<0>(tid, 0, x0, y0, L.nx, L.ny);
+  hs[1] = half_slot<0>(tid, 1, x0, y0, L.nx, L.ny);
+  hs[2] = half_slot<1>(tid, 0, x0, y0, L.nx, L.ny);
+  hs[3] = half_slot<2>(tid, 0, x0, y0, L.nx, L.ny);
+  hs[4] = half_slot<3>(tid, 0, x0, y0, L.nx, L.ny);
+
+  // Plane q takes half-sweep h when it holds unknowns and lies in h's
+  // widened z range.
+  auto active = [&](int h, int q) {
+    const int e = 3 - h;
+    return q >= L.k0 && q <= L.k1 && q >= za - e && q <= zb - 1 + e;
+  };
+  auto slot = [&](int z) { return ring[(z + 2 * kSR) % kSR]; };
+  auto clampz = [&](int z) { return z < 0 ? 0 : (z > L.nz ? L.nz : z); };
+
+  T pu[2][kSLoad];
+  T fs[3][kNS];
+  auto fetch_u = [&](auto U, int z) {
+    constexpr int iu = decltype(U)::value;
+    const long long base = (long long)clampz(z) * L.nxy;
+#pragma unroll
+    for (int r = 0; r < kSLoad; ++r) pu[iu][r] = uin[base + loff[r]];
+  };
+  auto commit_u = [&](auto U, int z) {
+    constexpr int iu = decltype(U)::value;
+    if (z < 0 || z > L.nz) return;
+    T* rr = slot(z);
+#pragma unroll
+    for (int r = 0; r < kSLoad; ++r)
+      if (tid + 256 * r < kSP) rr[tid + 256 * r] = pu[iu][r];
+  };
+  auto fetch_f = [&](auto F, int p) {
+    constexpr int jf = decltype(F)::value;
+#pragma unroll
+    for (int k = 0; k < kNS; ++k) {
+      const int q = p - slot_h[k];
+      const HalfSlot& z = hs[k];
+      fs[jf][k] = f[(long long)clampz(q) * L.nxy + (((z.b + q) & 1) ? z.g1 : z.g0)];
+    }
+  };
+  auto update = [&](int k, int q, T fv) {
+    const HalfSlot& z = hs[k];
+    if (!z.on) return;
+    const int c = z.c0 + ((z.b + q) & 1);
+    T* cur = slot(q);
+    const T* dn = slot(q - 1);
+    const T* up = slot(q + 1);
+    T sn = cur[c - 1] + cur[c + 1];
+    sn = sn + (cur[c - kSPX] + cur[c + kSPX]);
+    T zs;
+    if (q == 0)
+      zs = T(2) * up[c];
+    else if (q == L.nz)
+      zs = T(2) * dn[c];
+    else
+      zs = dn[c] + up[c];
+    cur[c] = ((sn + zs) + h2 * fv) * sixth;
+  };
+  // Step p: the four half-sweeps (plane p-h), the finished plane p-3 out,
+  // plane p+2 into the ring, and the loads of later steps issued.
+  auto step = [&](auto U, auto F, int p) {
+    constexpr int jf = decltype(F)::value;
+    if (active(0, p)) {
+      update(0, p, fs[jf][0]);
+      update(1, p, fs[jf][1]);
+    }
+    __syncthreads();
+    if (active(1, p - 1)) update(2, p - 1, fs[jf][2]);
+    __syncthreads();
+    if (active(2, p - 2)) update(3, p - 2, fs[jf][3]);
+    __syncthreads();
+    if (active(3, p - 3)) update(4, p - 3, fs[jf][4]);
+    __syncthreads();
+    const int q = p - 3;
+    if (q >= za && q < zb) {
+      const T* r = slot(q);
+      const int lx = kSH + tid % kSX, ly = kSH + tid / kSX;
+      const int gx = x0 + lx, gy = y0 + ly;
+      if (gx < L.nx && gy < L.ny)
+        uout[(long long)q * L.nxy + (long long)gy * L.nx + gx] = r[ly * kSPX + lx];
+    }
+    commit_u(U, p + 2);
+    fetch_u(U, p + 4);
+    fetch_f(F, p + 3);
+    __syncthreads();
+  };
+
+  const int p0 = za - 3, p1 = zb + 2;
+  fetch_u(IC<0>(), p0 - 1);
+  commit_u(IC<0>(), p0 - 1);
+  fetch_u(IC<0>(), p0);
+  commit_u(IC<0>(), p0);
+  fetch_u(IC<0>(), p0 + 1);
+  commit_u(IC<0>(), p0 + 1);
+  fetch_u(IC<0>(), p0 + 2);
+  fetch_u(IC<1>(), p0 + 3);
+  fetch_f(IC<0>(), p0);
+  fetch_f(IC<1>(), p0 + 1);
+  fetch_f(IC<2>(), p0 + 2);
+  __syncthreads();
+  // Register sets rotate with period 2 (u) and 3 (f): unrolled by 6.
+  for (int p = p0; p <= p1; p += 6) {
+    step(IC<0>(), IC<0>(), p);
+    if (p + 1 > p1) break;
+    step(IC<1>(), IC<1>(), p + 1);
+    if (p + 2 > p1) break;
+    step(IC<0>(), IC<2>(), p + 2);
+    if (p + 3 > p1) break;
+    step(IC<1>(), IC<0>(), p + 3);
+    if (p + 4 > p1) break;
+    step(IC<0>(), IC<1>(), p + 4);
+    if (p + 5 > p1) break;
+    step(IC<1>(), IC<2>(), p + 5);
+  }
+}
+
 template <typename T>
 T* lev_u(Level& L);
 template <>
 double* lev_u<double>(Level& L) { return L.u; }
 template <>
 float* lev_u<float>(Level& L) { return L.uf; }
+template <typename T>
+T* lev_s(Level& L);
+template <>
+double* lev_s<double>(Level& L) { return L.us; }
+template <>
+float* lev_s<float>(Level& L) { return L.usf; }
 template <typename T>
 T* lev_f(Level& L);
 template <>
@@ -734,6 +960,26 @@ int tail_first(const pic_ctx* c) {
   return l;
 }
 
+// Workgroups of k_smooth2<T> the current device runs at once.
+template <typename T>
+long long smooth_slots() {
+  static long long cached[64] = {0};
+  int dev = 0;
+  hipGetDevice(&dev);
+  if (dev < 0 || dev >= 64) dev = 0;
+  if (!cached[dev]) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth2<T>, 256, 0) != hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    cached[dev] = (long long)per_cu * cus;
+  }
+  return cached[dev];
+}
+
 // One V(nu_pre, nu_post) cycle from level l down.  Level 0 of an FP32
 // cycle is the correction equation of the mixed form.
 template <typename T>
@@ -773,32 +1019,61 @@ void vcycle(pic_ctx* c, int l) {
   T* u = lev_u<T>(L);
   T* f = lev_f<T>(L);
   const long long nhalf = (long long)(L.nx / 2) * L.ny * (Lc.k1 - Lc.k0 + 1);
-  for (int s = 0; s < c->cfg.nu_pre; ++s)
-    for (int color = 0; color < 2; ++color) {
-      if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
-      k_rbgs<T><<<nblocks(nhalf), kThreads, 0, st>>>(u, f, Lc, color, c->dc);
-      if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
-    }
+  // Fused pass (two sweeps each way): u -> spare before the restriction,
+  // the coarse correction is added to the spare, spare -> u after.
+  T* sp = lev_s<T>(L);
+  const bool fused = sp && !(c->cfg.flags & PIC_FLAG_PLAIN_SMOOTHER) &&
+                     c->cfg.nu_pre == 2 && c->cfg.nu_post == 2 &&
+                     L.nx >= kSX && L.ny >= kSY;
+  unsigned fgrid = 0;
+  int seg = 0;
+  if (fused) {
+    // One round of workgroups: as many z segments as the device keeps
+    // resident, since each segment's march is a latency-bound chain.
+    const long long nxy_t = (long long)((L.nx + kSX - 1) / kSX) * ((L.ny + kSY - 1) / kSY);
+    const long long slots = smooth_slots<T>();
+    seg = (int)(((long long)(L.nz + 1) * nxy_t + slots - 1) / slots);
+    seg = seg < 8 ? 8 : seg;
+    fgrid = (unsigned)(nxy_t * ((L.nz + 1 + seg - 1) / seg));
+  }
+  auto smooth_plain = [&](int sweeps) {
+    for (int s = 0; s < sweeps; ++s)
+      for (int color = 0; color < 2; ++color) {
+        if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
+        k_rbgs<T><<<nblocks(nhalf), kThreads, 0, st>>>(u, f, Lc, color, c->dc);
+        if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
+      }
+  };
+  auto smooth_fused = [&](const T* in, T* out) {
+    if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
+    k_smooth2<T><<<fgrid, 256, 0, st>>>(in, out, f, Lc, seg, c->dc);
+    if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
+  };
+  T* uc = u;  // fine values the restriction reads and the prolongation corrects
+  if (fused) {
+    smooth_fused(u, sp);
+    uc = sp;
+  } else {
+    smooth_plain(c->cfg.nu_pre);
+  }
   Level& N = c->lev[l + 1];
   LevelC Nc = level_c(c, l + 1);
   if (N.nx >= kRX && N.ny >= kRY) {
     const long long nb = (long long)((N.nx + kRX - 1) / kRX) *
                          ((N.ny + kRY - 1) / kRY) * ((N.nz + 1 + kRZ - 1) / kRZ);
     k_restrict_tiled<T><<<(unsigned)nb, 256, 0, st>>>(
-        u, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
+        uc, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
   } else {
     k_restrict<T><<<nblocks(N.nnodes), kThreads, 0, st>>>(
-        u, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
+        uc, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
   }
   vcycle<T>(c, l + 1);
   k_prolong<T><<<nblocks(Lc.nxy * (Lc.k1 - Lc.k0 + 1)), kThreads, 0, st>>>(
-      u, lev_u<T>(N), Lc, Nc, c->dc);
-  for (int s = 0; s < c->cfg.nu_post; ++s)
-    for (int color = 0; color < 2; ++color) {
-      if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
-      k_rbgs<T><<<nblocks(nhalf), kThreads, 0, st>>>(u, f, Lc, color, c->dc);
-      if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
-    }
+      uc, lev_u<T>(N), Lc, Nc, c->dc);
+  if (fused)
+    smooth_fused(sp, u);
+  else
+    smooth_plain(c->cfg.nu_post);
 }
 
 }  // namespace

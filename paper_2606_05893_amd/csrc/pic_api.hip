@@ -136,15 +136,17 @@ size_t carve(pic_ctx* c, char* base) {
       cv.take<char>(3 * c->nnodes * (long long)(mixed ? 4 : 8)));
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
-    L.u = L.f = nullptr;
-    L.uf = L.ff = nullptr;
+    L.u = L.f = L.us = nullptr;
+    L.uf = L.ff = L.usf = nullptr;
     if (l == 0 || !mixed) {
       L.u = cv.take<double>(L.nnodes);
       L.f = cv.take<double>(L.nnodes);
+      if (!mixed) L.us = cv.take<double>(L.nnodes);
     }
     if (mixed) {
       L.uf = cv.take<float>(L.nnodes);
       L.ff = cv.take<float>(L.nnodes);
+      L.usf = cv.take<float>(L.nnodes);
     }
   }
   c->partials = cv.take<double>(c->npartials);

@@ -29,6 +29,8 @@ struct Level {
   double h2;
   double *u, *f;       // FP64 unknowns and right-hand side
   float *uf, *ff;      // FP32 counterparts (mixed-precision V-cycles)
+  double* us;          // spare FP64 / FP32 unknowns: target of the fused
+  float* usf;          // pre-smoothing pass, source of the post-smoothing
 };
 
 struct QueueCall {

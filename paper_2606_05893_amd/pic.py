@@ -17,6 +17,7 @@ ELECTRON, NEUTRAL, ION = 0, 1, 2
 DIRICHLET, NEUMANN = 0, 1
 FP64, MIXED = 0, 1
 ION_LOTZ, ION_CONST = 0, 1
+FLAG_PLAIN_SMOOTHER = 1
 
 STATUS = {0: "PIC_OK", -1: "PIC_ERR_ARG", -2: "PIC_ERR_CAPACITY",
           -3: "PIC_ERR_NOCONV", -4: "PIC_ERR_NONFINITE", -5: "PIC_ERR_HIP",
@@ -38,7 +39,7 @@ class Config(ctypes.Structure):
                 ("max_vcycles", _c_i32), ("nu_pre", _c_i32),
                 ("nu_post", _c_i32), ("coarse_sweeps", _c_i32),
                 ("sort_every", _c_i32), ("rel_tol", _c_d), ("seed", _c_u64),
-                ("w_sp", _c_u32), ("reserved", _c_u32),
+                ("w_sp", _c_u32), ("flags", _c_u32),
                 ("capacity", _c_i64 * 3), ("queue_capacity", _c_i64),
                 ("max_events", _c_i64)]
 
@@ -161,7 +162,7 @@ def _soa(a, dtype=torch.float64):
 
 def make_config(p, capacity=(1 << 16,) * 3, queue_capacity=1 << 16,
                 max_events=1 << 16, rel_tol=1e-10, max_vcycles=100,
-                nu_pre=2, nu_post=2, coarse_sweeps=64):
+                nu_pre=2, nu_post=2, coarse_sweeps=64, flags=0):
     c = Config()
     c.nx, c.ny, c.nz, c.dx = p["nx"], p["ny"], p["nz"], p["dx"]
     c.bc_lo, c.bc_hi = p.get("bc_lo", 0), p.get("bc_hi", 0)
@@ -174,6 +175,7 @@ def make_config(p, capacity=(1 << 16,) * 3, queue_capacity=1 << 16,
     c.rel_tol = rel_tol
     c.seed = int(p.get("seed", 0))
     c.w_sp = int(p.get("w_sp", 1))
+    c.flags = int(flags)
     for s in range(3):
         c.capacity[s] = int(capacity[s])
     c.queue_capacity, c.max_events = int(queue_capacity), int(max_events)
