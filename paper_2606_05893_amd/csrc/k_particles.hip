@@ -507,8 +507,11 @@ __device__ __forceinline__ void finish_push(Parts& p, long long i, double x,
     y = yw;
     o.cell = cell_of(x, y, z, g);
     p.x[i] = x; p.y[i] = y; p.z[i] = z;
-    p.vx[i] = vx; p.vy[i] = vy; p.vz[i] = vz;
-    if (SP == 1) atomicAdd(&ncount[o.cell], 1);
+    // A neutral's velocity does not change; its cell count is added by the
+    // caller (aggregated in LDS).
+    if (SP != 1) {
+      p.vx[i] = vx; p.vy[i] = vy; p.vz[i] = vz;
+    }
   }
   key[i] = o.cell;
   if (SP == 0 && o.cell != kDead && m.enabled) {
@@ -782,8 +785,9 @@ __device__ __forceinline__ void finish_push_m(PartsM& p, long long i, PushM q,
              (unsigned)jx;
     p.cell[i] = o.cell;
     p.ox[i] = q.ox; p.oy[i] = q.oy; p.oz[i] = q.oz;
-    p.vx[i] = q.vx; p.vy[i] = q.vy; p.vz[i] = q.vz;
-    if (SP == 1) atomicAdd(&ncount[o.cell], 1);
+    if (SP != 1) {
+      p.vx[i] = q.vx; p.vy[i] = q.vy; p.vz[i] = q.vz;
+    }
   }
   key[i] = o.cell;
   if (SP == 0 && o.cell != kDead && m.enabled) {
@@ -1015,6 +1019,113 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
     if (o.cand) cand[first + cs] = (uint32_t)i;
   }
   const double s = block_sum(live ? o.ke : 0.0, sk);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// ---- neutral push ---------------------------------------------------------
+// Neutrals drift (no field), cross the boundaries and are counted per cell
+// for the collisions.  The evaporation sources pile up neutrals in a few
+// hundred cells above the cathode, so a global atomic per neutral would
+// serialise on those cells: each workgroup takes kNChunk neutrals and
+// aggregates their cell counts in an LDS hash table first (one global
+// atomic per distinct cell and chunk; probes that find no slot fall back to
+// the global atomic).
+constexpr int kNChunk = 4096;
+constexpr int kHist = 2048;
+constexpr unsigned kHistEmpty = 0xFFFFFFFFu;
+
+__device__ __forceinline__ void hist_clear(unsigned* hk, int* hc) {
+  for (int s = threadIdx.x; s < kHist; s += blockDim.x) {
+    hk[s] = kHistEmpty;
+    hc[s] = 0;
+  }
+}
+
+__device__ __forceinline__ void hist_add(unsigned* hk, int* hc, unsigned cell,
+                                         int* __restrict__ ncount) {
+  const unsigned h = (cell * 2654435761u) >> 21;
+#pragma unroll 1
+  for (int probe = 0; probe < 8; ++probe) {
+    const unsigned s = (h + probe) & (kHist - 1);
+    unsigned k = hk[s];
+    if (k == kHistEmpty) k = atomicCAS(&hk[s], kHistEmpty, cell);
+    if (k == kHistEmpty || k == cell) {
+      atomicAdd(&hc[s], 1);
+      return;
+    }
+  }
+  atomicAdd(&ncount[cell], 1);
+}
+
+__device__ __forceinline__ void hist_flush(unsigned* hk, int* hc,
+                                           int* __restrict__ ncount) {
+  for (int s = threadIdx.x; s < kHist; s += blockDim.x)
+    if (hk[s] != kHistEmpty) atomicAdd(&ncount[hk[s]], hc[s]);
+}
+
+__global__ void __launch_bounds__(kT) k_push_neutral(
+    Parts p, uint32_t* __restrict__ key, GridC g, double dt,
+    int* __restrict__ ncount, MccC m, uint32_t step, uint64_t seed,
+    Rec* __restrict__ ab_rec, double* __restrict__ ab_pos,
+    double* __restrict__ ab_vel, long long ab_cap, Counters* dc,
+    double* __restrict__ part) {
+  __shared__ unsigned hk[kHist];
+  __shared__ int hc[kHist];
+  __shared__ double sk[kT];
+  hist_clear(hk, hc);
+  __syncthreads();
+  const long long n = (long long)dc->n[1];
+  const long long b0 = blockIdx.x * (long long)kNChunk;
+  double ke = 0.0;
+  for (int r = 0; r < kNChunk; r += kT) {
+    const long long i = b0 + r + threadIdx.x;
+    PushOut o;
+    o.cathode = false;
+    o.cand = false;
+    if (i < n) {
+      finish_push<1>(p, i, p.x[i], p.y[i], p.z[i], p.vx[i], p.vy[i], p.vz[i],
+                     dt, g, key, ncount, m, step, seed, dc, o);
+      if (o.cell != kDead) hist_add(hk, hc, o.cell, ncount);
+      ke = ke + o.ke;
+    }
+    sink<1>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+  }
+  __syncthreads();
+  hist_flush(hk, hc, ncount);
+  const double s = block_sum(ke, sk);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kT) k_push_neutral_m(
+    PartsM p, uint32_t* __restrict__ key, GridC g, float dtdx,
+    int* __restrict__ ncount, MccC m, uint32_t step, uint64_t seed,
+    Rec* __restrict__ ab_rec, double* __restrict__ ab_pos,
+    double* __restrict__ ab_vel, long long ab_cap, Counters* dc,
+    double* __restrict__ part) {
+  __shared__ unsigned hk[kHist];
+  __shared__ int hc[kHist];
+  __shared__ double sk[kT];
+  hist_clear(hk, hc);
+  __syncthreads();
+  const long long n = (long long)dc->n[1];
+  const long long b0 = blockIdx.x * (long long)kNChunk;
+  double ke = 0.0;
+  for (int r = 0; r < kNChunk; r += kT) {
+    const long long i = b0 + r + threadIdx.x;
+    PushOut o;
+    o.cathode = false;
+    o.cand = false;
+    if (i < n) {
+      push_one_m<1>(p, i, nullptr, nullptr, nullptr, 0, 0, 0, nullptr, 0, g,
+                    0.0f, dtdx, key, ncount, m, step, seed, dc, o);
+      if (o.cell != kDead) hist_add(hk, hc, o.cell, ncount);
+      ke = ke + o.ke;
+    }
+    sink_m(p, i, 1, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+  }
+  __syncthreads();
+  hist_flush(hk, hc, ncount);
+  const double s = block_sum(ke, sk);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
@@ -1799,11 +1910,11 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
   const long long ab_cap = c->cfg.max_events;
   {
     tmark(c, PIC_PH_PUSH_NEUTRAL, true);
-    const long long nb = nblk(bound(c, 1));
-    k_push_list<1><<<nb, kT, 0, st>>>(
-        cur<Parts>(c, 1), 0, c->key[1], c->E, nn, c->g, 0.0, dt, c->ncount,
-        c->cand, m, step, seed, c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap,
-        c->dc, part_l);
+    const long long nb = (bound(c, 1) + kNChunk - 1) / kNChunk;
+    if (nb > 0)
+      k_push_neutral<<<nb, kT, 0, st>>>(
+          cur<Parts>(c, 1), c->key[1], c->g, dt, c->ncount, m, step, seed,
+          c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l);
     tmark(c, PIC_PH_PUSH_NEUTRAL, false);
     k_sum_partials<<<1, 1024, 0, st>>>(part_l, nb, nullptr, part_l, 0,
                                        0.5 * kMcu, &c->dc->kinetic[1]);
@@ -1862,11 +1973,11 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
   const float dtdx = (float)(dt * c->g.inv_dx);
   {
     tmark(c, PIC_PH_PUSH_NEUTRAL, true);
-    const long long nb = nblk(bound(c, 1));
-    k_push_list_m<1><<<nb, kT, 0, st>>>(
-        cur<PartsM>(c, 1), 0, c->key[1], E, nn, c->g, 0.0f, dtdx, c->ncount,
-        c->cand, m, step, seed, c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap,
-        c->dc, part_l);
+    const long long nb = (bound(c, 1) + kNChunk - 1) / kNChunk;
+    if (nb > 0)
+      k_push_neutral_m<<<nb, kT, 0, st>>>(
+          cur<PartsM>(c, 1), c->key[1], c->g, dtdx, c->ncount, m, step, seed,
+          c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l);
     tmark(c, PIC_PH_PUSH_NEUTRAL, false);
     k_sum_partials<<<1, 1024, 0, st>>>(part_l, nb, nullptr, part_l, 0,
                                        0.5 * kMcu, &c->dc->kinetic[1]);
