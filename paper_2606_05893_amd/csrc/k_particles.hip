@@ -1538,19 +1538,41 @@ __global__ void __launch_bounds__(kT) k_bin_hist_tile(
   if (threadIdx.x < 27 && sc[threadIdx.x]) atomicAdd(&cnt[sdst[threadIdx.x]], sc[threadIdx.x]);
 }
 
-// Unbinned tail (appended particles): run-aggregated global counts.
-__global__ void k_bin_hist_list(const uint32_t* __restrict__ key,
-                                unsigned* __restrict__ cnt, GridC g,
-                                long long first,
-                                const unsigned long long* __restrict__ np) {
-  const long long n = (long long)*np;
-  const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  unsigned t = kDead;
-  if (i < n) {
-    const uint32_t k = key[i];
-    if (k != kDead) t = tile_of_cell(k, g);
+// Slot of key in the LDS hash table (inserted if absent), or -1 when the
+// probes find no room.
+__device__ __forceinline__ int hist_slot(unsigned* hk, unsigned key) {
+  const unsigned h = (key * 2654435761u) >> 21;
+#pragma unroll 1
+  for (int probe = 0; probe < 8; ++probe) {
+    const unsigned s = (h + probe) & (kHist - 1);
+    unsigned k = hk[s];
+    if (k == kHistEmpty) k = atomicCAS(&hk[s], kHistEmpty, key);
+    if (k == kHistEmpty || k == key) return (int)s;
   }
-  run_add(t, cnt, false);
+  return -1;
+}
+
+// Unbinned tail (particles appended this step, e.g. a source's neutrals
+// piling into a few tiles): per chunk of kNChunk, tile counts aggregated in
+// an LDS hash table, one global atomic per distinct tile.
+__global__ void __launch_bounds__(kT) k_bin_hist_list(
+    const uint32_t* __restrict__ key, unsigned* __restrict__ cnt, GridC g,
+    long long first, const unsigned long long* __restrict__ np) {
+  __shared__ unsigned hk[kHist];
+  __shared__ int hc[kHist];
+  hist_clear(hk, hc);
+  __syncthreads();
+  const long long n = (long long)*np;
+  const long long b0 = first + blockIdx.x * (long long)kNChunk;
+  for (int r = 0; r < kNChunk; r += kT) {
+    const long long i = b0 + r + threadIdx.x;
+    if (i >= n) break;
+    const uint32_t k = key[i];
+    if (k == kDead) continue;
+    hist_add(hk, hc, tile_of_cell(k, g), reinterpret_cast<int*>(cnt));
+  }
+  __syncthreads();
+  hist_flush(hk, hc, reinterpret_cast<int*>(cnt));
 }
 
 // Multi-block exclusive scan of the tile counts: per-block sums, a scan of
@@ -1657,21 +1679,55 @@ __global__ void __launch_bounds__(kT) k_bin_scatter_tile(
   }
 }
 
+// The tail's scatter: per chunk, the tile counts in LDS reserve one range
+// per distinct tile with a single global atomic, and each particle takes
+// the next rank in its tile's range (particles whose tile found no hash
+// slot take a global slot directly).
+constexpr int kPerThread = kNChunk / kT;
+
 template <class PT>
 __global__ void __launch_bounds__(kT) k_bin_scatter_list(
     PT src, PT dst, const uint32_t* __restrict__ key,
     unsigned* __restrict__ cursor, GridC g, long long first,
     const unsigned long long* __restrict__ np) {
+  __shared__ unsigned hk[kHist];
+  __shared__ int hc[kHist];
+  __shared__ unsigned hb[kHist];
+  hist_clear(hk, hc);
+  __syncthreads();
   const long long n = (long long)*np;
-  const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  unsigned t = kDead;
-  if (i < n) {
-    const uint32_t k = key[i];
-    if (k != kDead) t = tile_of_cell(k, g);
+  const long long b0 = first + blockIdx.x * (long long)kNChunk;
+  int sl[kPerThread];
+  unsigned pos[kPerThread];
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    sl[r] = -2;  // no particle
+    const long long i = b0 + r * kT + threadIdx.x;
+    if (i < n) {
+      const uint32_t k = key[i];
+      if (k != kDead) {
+        const unsigned t = tile_of_cell(k, g);
+        sl[r] = hist_slot(hk, t);
+        if (sl[r] >= 0)
+          atomicAdd(&hc[sl[r]], 1);
+        else
+          pos[r] = atomicAdd(&cursor[t], 1u);
+      }
+    }
   }
-  const unsigned d = run_add(t, cursor, true);
-  if (t == kDead) return;
-  Acc<PT>::copy(src, i, dst, d);
+  __syncthreads();
+  for (int q = threadIdx.x; q < kHist; q += kT) {
+    if (hk[q] != kHistEmpty) hb[q] = atomicAdd(&cursor[hk[q]], (unsigned)hc[q]);
+    hc[q] = 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kPerThread; ++r) {
+    if (sl[r] == -2) continue;
+    const long long i = b0 + r * kT + threadIdx.x;
+    const unsigned d = sl[r] >= 0 ? hb[sl[r]] + (unsigned)atomicAdd(&hc[sl[r]], 1) : pos[r];
+    Acc<PT>::copy(src, i, dst, d);
+  }
 }
 
 __global__ void k_set_count(Counters* dc, int s, const unsigned* __restrict__ ts,
@@ -2095,8 +2151,8 @@ void bin_species_t(pic_ctx* c, int s) {
       c->key[s], ts_old, c->chunks[L], c->cstart[L] + nt, c->tile_cursor, c->g);
   const long long tail = std::max(0ll, bound(c, s) - c->n_binned[s]);
   if (tail > 0)
-    k_bin_hist_list<<<nblk(tail), kT, 0, st>>>(c->key[s], c->tile_cursor, c->g,
-                                               c->n_binned[s], &c->dc->n[s]);
+    k_bin_hist_list<<<(unsigned)((tail + kNChunk - 1) / kNChunk), kT, 0, st>>>(
+        c->key[s], c->tile_cursor, c->g, c->n_binned[s], &c->dc->n[s]);
   const long long nsb = (nt + 1 + kScanPer - 1) / kScanPer;
   k_scan_blocks<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt, c->scan_block);
   k_scan1<<<1, 1024, 0, st>>>(c->scan_block, c->scan_block + nsb + 1, nsb);
@@ -2108,7 +2164,7 @@ void bin_species_t(pic_ctx* c, int s) {
       cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], ts_old, c->chunks[L],
       c->cstart[L] + nt, c->tile_cursor, c->g);
   if (tail > 0)
-    k_bin_scatter_list<PT><<<nblk(tail), kT, 0, st>>>(
+    k_bin_scatter_list<PT><<<(unsigned)((tail + kNChunk - 1) / kNChunk), kT, 0, st>>>(
         cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], c->tile_cursor, c->g,
         c->n_binned[s], &c->dc->n[s]);
   k_set_count<<<1, 1, 0, st>>>(c->dc, s, ts_new, nt);
