@@ -9,6 +9,7 @@
 // N = output channels, K = 27 * C_in flattened as (tap, channel) and walked
 // in chunks of 32 by v_mfma_f32_16x16x32_bf16 (lane l holds row l % 16 and
 // k = 8 (l / 16) .. +7 of A and B; D rows 4 (l / 16) .. +3, column l % 16).
+// The input tile of a workgroup is staged in LDS per slice of 16 channels.
 // The backward-data convolution is the same kernel with the kernel flipped
 // and the channel roles swapped; the weight gradient is a second GEMM whose
 // reduction runs over voxels, staged through LDS.
@@ -61,6 +62,30 @@ struct Dims {
   long long V;
 };
 
+// Vectors of 8 BF16 channels (16 B) for the data-movement kernels; voxel
+// indices fit 32 bits for every supported grid.
+__device__ __forceinline__ uint4 ld16(const bf16* p) {
+  return *reinterpret_cast<const uint4*>(p);
+}
+__device__ __forceinline__ void st16(bf16* p, uint4 v) {
+  *reinterpret_cast<uint4*>(p) = v;
+}
+__device__ __forceinline__ void unpack8(uint4 v, float* f) {
+  const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    f[2 * q] = __uint_as_float(w[q] << 16);
+    f[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
+  }
+}
+__device__ __forceinline__ void voxel_xyz(unsigned v, const Dims& d, int& x,
+                                          int& y, int& z) {
+  x = (int)(v % (unsigned)d.W);
+  const unsigned r = v / (unsigned)d.W;
+  y = (int)(r % (unsigned)d.H);
+  z = (int)(r / (unsigned)d.H);
+}
+
 __device__ __forceinline__ long long nb_voxel(const Dims& d, int z, int y,
                                               int x, int tap) {
   const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
@@ -76,59 +101,111 @@ __device__ __forceinline__ long long nb_voxel(const Dims& d, int z, int y,
 
 constexpr int KP(int cin) { return (27 * cin + 63) / 64 * 64; }
 
-// out = act(conv(in) + bias): CIN input channels (multiple of 8), NT*16
-// output channels.  Four waves of 32 voxels per workgroup.
-template <int CIN, int NT>
-__global__ void __launch_bounds__(256) k_conv3(const bf16* __restrict__ in,
-                                               const bf16* __restrict__ Wk,
-                                               const float* __restrict__ bias,
-                                               bf16* __restrict__ out, Dims d,
-                                               int relu) {
+// out = act(conv(in) + bias), LDS-tiled.  A workgroup owns an output tile
+// of 16 (x) x TY x TZ voxels; per slice of 16 input channels it stages the
+// tile's halo (18 x (TY+2) x (TZ+2) voxels, 32 B each, x and y periodic, z
+// zero-padded) in LDS, so an input voxel is read from memory about twice
+// per layer instead of once per tap.  A K-chunk of 32 is two taps x 16
+// channels (lane group g = lane / 16: tap 2c + g / 2, channels 8 (g % 2) ..
+// +7); the A operand comes from LDS, the B operand (weights) from the
+// cache.  Each wave owns MT rows of 16 voxels and all COUT / 16 column
+// tiles, with MT * COUT / 16 <= 16 accumulator tiles.
+template <int CIN, int COUT, int TY, int TZ>
+__global__ void __launch_bounds__(256) k_conv3t(const bf16* __restrict__ in,
+                                                const bf16* __restrict__ Wk,
+                                                const float* __restrict__ bias,
+                                                bf16* __restrict__ out, Dims d,
+                                                int relu) {
+  constexpr int NT = COUT / 16;
+  constexpr int TX = 16;
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+  constexpr int HV = HX * HY * HZ;
+  constexpr int MT = TY * TZ / 4;
   constexpr int KPAD = KP(CIN);
-  constexpr int KCH = (27 * CIN + 31) / 32;
-  constexpr int COUT = NT * 16;
+  constexpr int NS = CIN / 16;
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channel multiples of 16");
+  static_assert(MT >= 1 && MT * NT <= 16, "accumulator budget");
+  __shared__ uint4 lds[HV * 2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long vb = (long long)blockIdx.x * 128 + wave * 32;
-  int zz[2], yy[2], xx[2];
-  bool ok[2];
-  for (int mt = 0; mt < 2; ++mt) {
-    const long long v = vb + mt * 16 + (lane & 15);
-    ok[mt] = v < d.V;
-    const long long vv = ok[mt] ? v : 0;
-    xx[mt] = (int)(vv % d.W);
-    yy[mt] = (int)((vv / d.W) % d.H);
-    zz[mt] = (int)(vv / ((long long)d.W * d.H));
-  }
-  f4 acc[2][NT];
-  for (int mt = 0; mt < 2; ++mt)
+  const int ntx = (d.W + TX - 1) / TX, nty = (d.H + TY - 1) / TY;
+  int bi = blockIdx.x;
+  const int tx = bi % ntx;
+  bi /= ntx;
+  const int ty = bi % nty, tz = bi / nty;
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int kg = lane >> 4, rl = lane & 15;
+  const int half = kg & 1;
+  f4 acc[MT][NT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-  const int kl = 8 * (lane >> 4);
-  for (int ch = 0; ch < KCH; ++ch) {
-    const int k0 = ch * 32 + kl;
-    const int tap = k0 / CIN, c = k0 - tap * CIN;
-    bf16x8 a[2];
-    for (int mt = 0; mt < 2; ++mt) {
-      const long long nv = (tap < 27 && ok[mt]) ? nb_voxel(d, zz[mt], yy[mt], xx[mt], tap) : -1;
-      a[mt] = nv >= 0 ? load8(in + nv * CIN + c) : zero8();
+  for (int sl = 0; sl < NS; ++sl) {
+    for (int q = threadIdx.x; q < HV * 2; q += 256) {
+      const int hv = q >> 1, hh = q & 1;
+      const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+      const int gz = z0 + hz - 1;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (gz >= 0 && gz < d.D) {
+        int gy = (y0 + hy - 1) % d.H;
+        gy = gy < 0 ? gy + d.H : gy;
+        int gx = (x0 + hx - 1) % d.W;
+        gx = gx < 0 ? gx + d.W : gx;
+        const size_t gv = ((size_t)gz * d.H + gy) * d.W + gx;
+        val = ld16(in + gv * CIN + sl * 16 + hh * 8);
+      }
+      lds[q] = val;
     }
-    for (int nt = 0; nt < NT; ++nt) {
-      const bf16x8 b = load8(Wk + (long long)(nt * 16 + (lane & 15)) * KPAD + k0);
-      for (int mt = 0; mt < 2; ++mt)
-        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][nt], 0, 0, 0);
-    }
+    __syncthreads();
+    // Chunks 0..12 hold two taps; chunk 13 holds tap 26 and padding.
+    auto chunk = [&](int ch, bool last) {
+      const int tap = 2 * ch + (kg >> 1);
+      const bool tv = !last || tap < 27;
+      const int oz = tap / 9, oy = (tap / 3) % 3, ox = tap % 3;
+      bf16x8 b[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        b[nt] = tv ? load8(Wk + (size_t)(nt * 16 + rl) * KPAD + tap * CIN + sl * 16 + half * 8)
+                   : zero8();
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int r = wave * MT + mt;
+        const int ly = r % TY, lz = r / TY;
+        const int hv = ((lz + oz) * HY + (ly + oy)) * HX + rl + ox;
+        bf16x8 a = zero8();
+        if (tv) {
+          const uint4 w = lds[hv * 2 + half];
+          __builtin_memcpy(&a, &w, 16);
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+          acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nt], acc[mt][nt], 0, 0, 0);
+      }
+    };
+#pragma unroll 1
+    for (int ch = 0; ch < 13; ++ch) chunk(ch, false);
+    chunk(13, true);
+    __syncthreads();
   }
-  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    const int r = wave * MT + mt;
+    const int gy = y0 + r % TY, gz = z0 + r / TY;
+    if (gy >= d.H || gz >= d.D) continue;
+#pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-      const int co = nt * 16 + (lane & 15);
-      const float bi = bias ? bias[co] : 0.0f;
+      const int co = nt * 16 + rl;
+      const float bv = bias ? bias[co] : 0.0f;
+#pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const long long v = vb + mt * 16 + 4 * (lane >> 4) + j;
-        if (v >= d.V) continue;
-        float r = acc[mt][nt][j] + bi;
-        if (relu) r = r > 0.0f ? r : 0.0f;
-        out[v * COUT + co] = f2bf(r);
+        const int x = x0 + 4 * kg + j;
+        if (x >= d.W) continue;
+        float v = acc[mt][nt][j] + bv;
+        if (relu) v = v > 0.0f ? v : 0.0f;
+        out[(((size_t)gz * d.H + gy) * d.W + x) * COUT + co] = f2bf(v);
       }
     }
+  }
 }
 
 // Weight gradient dW[co][k] += sum_v g[v][co] x[v + tap(k)][ci(k)] over a
@@ -199,28 +276,40 @@ __global__ void __launch_bounds__(256) k_wgrad3(const bf16* __restrict__ x,
 }
 
 // First layer (2 input channels): FP32 arithmetic, 16 outputs per voxel.
-__global__ void k_conv_first(const float* __restrict__ in,
-                             const float* __restrict__ W,  // [16][27][2]
-                             const float* __restrict__ b,
-                             bf16* __restrict__ out, Dims d) {
-  __shared__ float ws[16 * 54 + 16];
-  for (int q = threadIdx.x; q < 16 * 54; q += blockDim.x) ws[q] = W[q];
-  if (threadIdx.x < 16) ws[16 * 54 + threadIdx.x] = b[threadIdx.x];
-  __syncthreads();
-  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (v >= d.V) return;
-  const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
-            z = (int)(v / ((long long)d.W * d.H));
+// The weights are indexed uniformly across the wave, so they come through
+// the scalar cache as operands of the vector FMAs.
+__global__ void __launch_bounds__(256) k_conv_first(
+    const float* __restrict__ in, const float* __restrict__ W,  // [16][27][2]
+    const float* __restrict__ b, bf16* __restrict__ out, Dims d) {
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= (unsigned long long)d.V) return;
+  int x, y, z;
+  voxel_xyz(v, d, x, y, z);
   float acc[16];
-  for (int c = 0; c < 16; ++c) acc[c] = ws[16 * 54 + c];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = b[c];
+#pragma unroll 3
   for (int tap = 0; tap < 27; ++tap) {
-    const long long nv = nb_voxel(d, z, y, x, tap);
-    if (nv < 0) continue;
-    const float i0 = in[2 * nv], i1 = in[2 * nv + 1];
+    const int zz = z + tap / 9 - 1;
+    int yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
+    yy = yy < 0 ? yy + d.H : (yy >= d.H ? yy - d.H : yy);
+    xx = xx < 0 ? xx + d.W : (xx >= d.W ? xx - d.W : xx);
+    float2 i2 = make_float2(0.f, 0.f);
+    if (zz >= 0 && zz < d.D)
+      i2 = reinterpret_cast<const float2*>(in)[((unsigned)zz * d.H + yy) * d.W + xx];
+#pragma unroll
     for (int c = 0; c < 16; ++c)
-      acc[c] = acc[c] + ws[c * 54 + tap * 2] * i0 + ws[c * 54 + tap * 2 + 1] * i1;
+      acc[c] = fmaf(W[c * 54 + tap * 2 + 1], i2.y, fmaf(W[c * 54 + tap * 2], i2.x, acc[c]));
   }
-  for (int c = 0; c < 16; ++c) out[v * 16 + c] = f2bf(acc[c] > 0.f ? acc[c] : 0.f);
+  unsigned w[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const float a0 = acc[2 * q] > 0.f ? acc[2 * q] : 0.f;
+    const float a1 = acc[2 * q + 1] > 0.f ? acc[2 * q + 1] : 0.f;
+    w[q] = (unsigned)f2bf(a0) | ((unsigned)f2bf(a1) << 16);
+  }
+  st16(out + (size_t)v * 16, make_uint4(w[0], w[1], w[2], w[3]));
+  st16(out + (size_t)v * 16 + 8, make_uint4(w[4], w[5], w[6], w[7]));
 }
 
 // dW of the first layer: each thread of a block owns up to 4 of the 864
@@ -266,22 +355,30 @@ __global__ void k_relu_bwd(const bf16* __restrict__ gy, const bf16* __restrict__
   gpre[i] = bf2f(y[i]) > 0.f ? gy[i] : (bf16)0;
 }
 
-// Average pooling 2^3 (out dims d = input dims / 2).
+// Average pooling 2^3 (out dims d = input dims / 2), 8 channels a thread.
 __global__ void k_pool(const bf16* __restrict__ in, bf16* __restrict__ out,
                        Dims d, int C) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= d.V * C) return;
-  const int c = (int)(i % C);
-  const long long v = i / C;
-  const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
-            z = (int)(v / ((long long)d.W * d.H));
-  const int W2 = 2 * d.W, H2 = 2 * d.H;
-  float s = 0.f;
+  const unsigned G = (unsigned)C / 8;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (unsigned long long)d.V * G) return;
+  const unsigned v = t / G, g = t % G;
+  int x, y, z;
+  voxel_xyz(v, d, x, y, z);
+  const unsigned W2 = 2 * d.W, H2 = 2 * d.H;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
-      for (int e = 0; e < 2; ++e)
-        s = s + bf2f(in[((((long long)(2 * z + a) * H2) + 2 * y + b) * W2 + 2 * x + e) * C + c]);
-  out[i] = f2bf(s * 0.125f);
+      for (int e = 0; e < 2; ++e) {
+        float f[8];
+        unpack8(ld16(in + ((size_t)((2 * z + a) * H2 + 2 * y + b) * W2 + 2 * x + e) * C + 8 * g), f);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s[q] = s[q] + f[q];
+      }
+  unsigned w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    w[q] = (unsigned)f2bf(s[2 * q] * 0.125f) | ((unsigned)f2bf(s[2 * q + 1] * 0.125f) << 16);
+  st16(out + (size_t)v * C + 8 * g, make_uint4(w[0], w[1], w[2], w[3]));
 }
 
 // Gradient through pooling added to an existing fine gradient:
@@ -298,23 +395,25 @@ __global__ void k_pool_bwd_add(const bf16* __restrict__ gc, bf16* __restrict__ g
   gf[i] = f2bf(bf2f(gf[i]) + bf2f(gc[p * C + c]) * 0.125f);
 }
 
-// Concatenation [up(coarse) (Cu channels), skip (Cs)] at fine dims d.
+// Concatenation [up(coarse) (Cu channels), skip (Cs)] at fine dims d, 8
+// channels a thread.
 __global__ void k_up_cat(const bf16* __restrict__ coarse, int Cu,
                          const bf16* __restrict__ skip, int Cs,
                          bf16* __restrict__ out, Dims d) {
-  const int C = Cu + Cs;
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= d.V * C) return;
-  const int c = (int)(i % C);
-  const long long v = i / C;
-  if (c < Cu) {
-    const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
-              z = (int)(v / ((long long)d.W * d.H));
-    const long long p = (((long long)(z / 2) * (d.H / 2)) + y / 2) * (d.W / 2) + x / 2;
-    out[i] = coarse[p * Cu + c];
+  const unsigned C = Cu + Cs, G = C / 8, Gu = (unsigned)Cu / 8;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (unsigned long long)d.V * G) return;
+  const unsigned v = t / G, g = t % G;
+  uint4 val;
+  if (g < Gu) {
+    int x, y, z;
+    voxel_xyz(v, d, x, y, z);
+    const unsigned p = ((unsigned)(z / 2) * (d.H / 2) + y / 2) * (d.W / 2) + x / 2;
+    val = ld16(coarse + (size_t)p * Cu + 8 * g);
   } else {
-    out[i] = skip[v * Cs + (c - Cu)];
+    val = ld16(skip + (size_t)v * Cs + 8 * (g - Gu));
   }
+  st16(out + (size_t)v * C + 8 * g, val);
 }
 
 // Split the concatenation's gradient: coarse part summed over the 8
@@ -346,10 +445,14 @@ __global__ void k_split_skip(const bf16* __restrict__ gcat, int Cu, int Cs,
 // Head: out[v] = sum_c w[c] y[v][c] + b, FP32 output.
 __global__ void k_head(const bf16* __restrict__ y, const float* __restrict__ w,
                        float* __restrict__ out, long long V) {
-  const long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (v >= V) return;
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= (unsigned long long)V) return;
+  float f[16];
+  unpack8(ld16(y + (size_t)v * 16), f);
+  unpack8(ld16(y + (size_t)v * 16 + 8), f + 8);
   float s = w[16];
-  for (int c = 0; c < 16; ++c) s = s + w[c] * bf2f(y[v * 16 + c]);
+#pragma unroll
+  for (int c = 0; c < 16; ++c) s = s + w[c] * f[c];
   out[v] = s;
 }
 
@@ -573,10 +676,16 @@ Dims dims_at(const pic_unet* u, int D, int H, int W, int level) {
   return d;
 }
 
-template <int CIN, int NT>
+// Tile of k_conv3t for a column count: MT * COUT / 16 <= 16.
+template <int CIN, int COUT>
 void conv_launch(hipStream_t st, const bf16* in, const bf16* Wk, const float* b,
                  bf16* out, Dims d, int relu) {
-  pic::k_conv3<CIN, NT><<<nb(d.V, 128), 256, 0, st>>>(in, Wk, b, out, d, relu);
+  constexpr int NT = COUT / 16;
+  constexpr int TY = NT <= 2 ? 8 : (NT <= 8 ? 4 : 2);
+  constexpr int TZ = NT <= 4 ? 4 : 2;
+  const long long nbk = (long long)((d.W + 15) / 16) * ((d.H + TY - 1) / TY) *
+                        ((d.D + TZ - 1) / TZ);
+  pic::k_conv3t<CIN, COUT, TY, TZ><<<(unsigned)nbk, 256, 0, st>>>(in, Wk, b, out, d, relu);
 }
 
 // Dispatch of the (C_in, C_out) pairs the network and its backward use.
@@ -584,7 +693,7 @@ bool conv(hipStream_t st, int cin, int cout, const bf16* in, const bf16* Wk,
           const float* b, bf16* out, Dims d, int relu) {
 #define PIC_CONV(CI, CO)                                                   \
   if (cin == CI && cout == CO) {                                           \
-    conv_launch<CI, CO / 16>(st, in, Wk, b, out, d, relu);                 \
+    conv_launch<CI, CO>(st, in, Wk, b, out, d, relu);                      \
     return true;                                                           \
   }
   PIC_CONV(16, 16) PIC_CONV(16, 32) PIC_CONV(32, 32) PIC_CONV(32, 64)
@@ -645,22 +754,22 @@ bool unet_forward(pic_unet* u, int D, int H, int W) {
                     P + u->boff[l], u->y[l], d, 1);
   };
   L(E0B, u->y[E0A], d0);
-  pic::k_pool<<<nb(d1.V * 16), 256, 0, st>>>(u->y[E0B], u->p0, d1, 16);
+  pic::k_pool<<<nb(d1.V * 2), 256, 0, st>>>(u->y[E0B], u->p0, d1, 16);
   L(E1A, u->p0, d1);
   L(E1B, u->y[E1A], d1);
-  pic::k_pool<<<nb(d2.V * 32), 256, 0, st>>>(u->y[E1B], u->p1, d2, 32);
+  pic::k_pool<<<nb(d2.V * 4), 256, 0, st>>>(u->y[E1B], u->p1, d2, 32);
   L(E2A, u->p1, d2);
   L(E2B, u->y[E2A], d2);
-  pic::k_pool<<<nb(d3.V * 64), 256, 0, st>>>(u->y[E2B], u->p2, d3, 64);
+  pic::k_pool<<<nb(d3.V * 8), 256, 0, st>>>(u->y[E2B], u->p2, d3, 64);
   L(BA, u->p2, d3);
   L(BB, u->y[BA], d3);
-  pic::k_up_cat<<<nb(d2.V * 192), 256, 0, st>>>(u->y[BB], 128, u->y[E2B], 64, u->c2, d2);
+  pic::k_up_cat<<<nb(d2.V * 24), 256, 0, st>>>(u->y[BB], 128, u->y[E2B], 64, u->c2, d2);
   L(D2A, u->c2, d2);
   L(D2B, u->y[D2A], d2);
-  pic::k_up_cat<<<nb(d1.V * 96), 256, 0, st>>>(u->y[D2B], 64, u->y[E1B], 32, u->c1, d1);
+  pic::k_up_cat<<<nb(d1.V * 12), 256, 0, st>>>(u->y[D2B], 64, u->y[E1B], 32, u->c1, d1);
   L(D1A, u->c1, d1);
   L(D1B, u->y[D1A], d1);
-  pic::k_up_cat<<<nb(d0.V * 48), 256, 0, st>>>(u->y[D1B], 32, u->y[E0B], 16, u->c0, d0);
+  pic::k_up_cat<<<nb(d0.V * 6), 256, 0, st>>>(u->y[D1B], 32, u->y[E0B], 16, u->c0, d0);
   L(D0A, u->c0, d0);
   L(D0B, u->y[D0A], d0);
   pic::k_head<<<nb(d0.V), 256, 0, st>>>(u->y[D0B], P + u->hoff, u->out, d0.V);
