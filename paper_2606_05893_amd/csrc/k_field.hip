@@ -494,8 +494,9 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
   __shared__ T r[kFZ * kFY * kFX];
   if (dc->done) return;
   const int tnx = (Cc.nx + kRX - 1) / kRX, tny = (Cc.ny + kRY - 1) / kRY;
-  const int bx = blockIdx.x % tnx, by = (blockIdx.x / tnx) % tny,
-            bz = blockIdx.x / (tnx * tny);
+  // Neighbouring tiles share halo nodes: keep them on one XCD's L2.
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  const int bx = blk % tnx, by = (blk / tnx) % tny, bz = blk / (tnx * tny);
   const int cx0 = bx * kRX, cy0 = by * kRY, cz0 = bz * kRZ;
   const T inv_h2 = T(1) / (T)F.h2;
   for (int q = threadIdx.x; q < kFZ * kFY * kFX; q += blockDim.x) {
@@ -761,7 +762,8 @@ __global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
   if (dc->done) return;
   const int tiles_x = (L.nx + kSX - 1) / kSX;
   const int tiles_y = (L.ny + kSY - 1) / kSY;
-  int bi = blockIdx.x;
+  // Neighbouring columns share halo nodes: keep them on one XCD's L2.
+  int bi = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tx = bi % tiles_x;
   bi /= tiles_x;
   const int ty = bi % tiles_y;
