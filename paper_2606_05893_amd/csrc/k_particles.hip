@@ -50,6 +50,16 @@ __device__ __forceinline__ unsigned long long wave_append(
   return base + (unsigned long long)__popcll(below);
 }
 
+// Wave-aggregated count: the lanes with pred add one each to *counter
+// (one atomic per wave).  All lanes must call it.
+__device__ __forceinline__ void wave_count(bool pred,
+                                           unsigned long long* counter) {
+  const unsigned long long mask = __ballot(pred);
+  if (!mask) return;
+  if (lane_id() == __ffsll((long long)mask) - 1)
+    atomicAdd(counter, (unsigned long long)__popcll(mask));
+}
+
 // Run-length aggregated counter increment for keys that arrive grouped
 // (binned particles): the first lane of each run of equal keys adds the run
 // length.  Returns, per lane, its slot when 'fetch' is set (the counter's
@@ -468,7 +478,7 @@ __device__ __forceinline__ void gather_lds(const double* sx, const double* sy,
 
 // Result of one particle's push.
 struct PushOut {
-  bool cathode, cand;
+  bool cathode, anode, cand;
   unsigned cell;
   double ke;           // |v|^2 after the kick
   double x, y, z, vx, vy, vz;
@@ -483,12 +493,14 @@ __device__ __forceinline__ void finish_push(Parts& p, long long i, double x,
                                             const GridC& g, uint32_t* key,
                                             int* ncount, const MccC& m,
                                             uint32_t step, uint64_t seed,
-                                            Counters* dc, PushOut& o) {
+                                            Counters* dc, PushOut& o,
+                                            uint64_t idv) {
   x = x + vx * dt;
   y = y + vy * dt;
   z = z + vz * dt;
   o.ke = (vx * vx + vy * vy) + vz * vz;
   o.cathode = false;
+  o.anode = false;
   o.cand = false;
   o.cell = kDead;
   const double gz = z * g.inv_dx;
@@ -501,7 +513,7 @@ __device__ __forceinline__ void finish_push(Parts& p, long long i, double x,
   } else if (gz < 0.0) {
     o.cathode = true;
   } else if (gz >= (double)g.nz) {
-    atomicAdd(&dc->anode[SP], 1ull);
+    o.anode = true;
   } else {
     x = xw;
     y = yw;
@@ -519,7 +531,7 @@ __device__ __forceinline__ void finish_push(Parts& p, long long i, double x,
     if (nc > 0) {
       const double pstar = 1.0 - exp(-((double)nc * m.c_coll));
       double u1, u2;
-      uniform2(p.id[i], step, kTagMcc0, seed, u1, u2);
+      uniform2(idv, step, kTagMcc0, seed, u1, u2);
       if (fabs(u1 - pstar) < 1e-6) atomicAdd(&dc->n_near, 1ull);
       o.cand = u1 < pstar;
     }
@@ -534,9 +546,10 @@ __device__ __forceinline__ void sink(const Parts& p, long long i,
                                      Rec* ab_rec, double* ab_pos,
                                      double* ab_vel, long long ab_cap,
                                      Counters* dc) {
+  wave_count(o.anode, &dc->anode[SP]);
+  wave_count(o.cathode, &dc->cathode[SP]);
   const unsigned long long slot = wave_append(o.cathode, &dc->n_ab);
   if (!o.cathode) return;
-  atomicAdd(&dc->cathode[SP], 1ull);
   if ((long long)slot < ab_cap) {
     const double tc = -o.z / o.vz;
     const double xc = wrap_coord(o.x + o.vx * tc, g.lx);
@@ -629,6 +642,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
     const bool live = i < ei;
     PushOut o;
     o.cathode = false;
+    o.anode = false;
     if (live) {
       const double x = A.pi.x[i], y = A.pi.y[i], z = A.pi.z[i];
       int ix, fx, iy, fy, iz, fz;
@@ -647,7 +661,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
       const double vy = A.pi.vy[i] + A.qm_i * ey;
       const double vz = A.pi.vz[i] + A.qm_i * ez;
       finish_push<2>(A.pi, i, x, y, z, vx, vy, vz, A.dt, g, A.keyi, A.ncount, m,
-                     step, seed, dc, o);
+                     step, seed, dc, o, 0ull);
       ke_i = ke_i + o.ke;
     }
     sink<2>(A.pi, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
@@ -658,6 +672,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
     const bool live = i < ee;
     PushOut o;
     o.cathode = false;
+    o.anode = false;
     o.cand = false;
     if (live) {
       const double x = A.pe.x[i], y = A.pe.y[i], z = A.pe.z[i];
@@ -677,7 +692,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
       const double vy = A.pe.vy[i] + A.qm_e * ey;
       const double vz = A.pe.vz[i] + A.qm_e * ez;
       finish_push<0>(A.pe, i, x, y, z, vx, vy, vz, A.dt, g, A.keye, A.ncount, m,
-                     step, seed, dc, o);
+                     step, seed, dc, o, A.pe.id[i]);
       ke_e = ke_e + o.ke;
       if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = (uint32_t)i;
     }
@@ -708,6 +723,7 @@ __global__ void __launch_bounds__(kT) k_push_list(
   const bool live = i < n;
   PushOut o;
   o.cathode = false;
+  o.anode = false;
   o.cand = false;
   o.ke = 0.0;
   if (live) {
@@ -721,7 +737,7 @@ __global__ void __launch_bounds__(kT) k_push_list(
       vz = vz + qm_dt * ez;
     }
     finish_push<SP>(p, i, x, y, z, vx, vy, vz, dt, g, key, ncount, m, step,
-                    seed, dc, o);
+                    seed, dc, o, SP == 0 ? p.id[i] : 0ull);
   }
   sink<SP>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
   if (SP == 0) {
@@ -768,6 +784,7 @@ __device__ __forceinline__ void finish_push_m(PartsM& p, long long i, PushM q,
   o.z = ((double)iz + (double)q.oz) * g.dx;
   o.ke = (o.vx * o.vx + o.vy * o.vy) + o.vz * o.vz;
   o.cathode = false;
+  o.anode = false;
   o.cand = false;
   o.cell = kDead;
   const int jx = ix >= g.nx ? ix - g.nx : (ix < 0 ? ix + g.nx : ix);
@@ -779,7 +796,7 @@ __device__ __forceinline__ void finish_push_m(PartsM& p, long long i, PushM q,
   } else if (iz < 0) {
     o.cathode = true;
   } else if (iz >= g.nz) {
-    atomicAdd(&dc->anode[SP], 1ull);
+    o.anode = true;
   } else {
     o.cell = ((unsigned)iz * (unsigned)g.ny + (unsigned)jy) * (unsigned)g.nx +
              (unsigned)jx;
@@ -904,9 +921,10 @@ __device__ __forceinline__ void sink_m(const PartsM& p, long long i, int sp,
                                        Rec* ab_rec, double* ab_pos,
                                        double* ab_vel, long long ab_cap,
                                        Counters* dc) {
+  wave_count(o.anode, &dc->anode[sp]);
+  wave_count(o.cathode, &dc->cathode[sp]);
   const unsigned long long slot = wave_append(o.cathode, &dc->n_ab);
   if (!o.cathode) return;
-  atomicAdd(&dc->cathode[sp], 1ull);
   if ((long long)slot < ab_cap) {
     const double tc = -o.z / o.vz;
     Rec r;
@@ -965,6 +983,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
     const long long i = base + threadIdx.x;
     PushOut o;
     o.cathode = false;
+    o.anode = false;
     if (i < ei) {
       push_one_m<2>(A.pi, i, sx, sy, sz, x0, y0, z0, E, nn, g, A.qm_i, A.dtdx,
                     A.keyi, A.ncount, m, step, seed, dc, o);
@@ -976,6 +995,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
     const long long i = base + threadIdx.x;
     PushOut o;
     o.cathode = false;
+    o.anode = false;
     o.cand = false;
     if (i < ee) {
       push_one_m<0>(A.pe, i, sx, sy, sz, x0, y0, z0, E, nn, g, A.qm_e, A.dtdx,
@@ -1008,6 +1028,7 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
   const bool live = i < n;
   PushOut o;
   o.cathode = false;
+  o.anode = false;
   o.cand = false;
   o.ke = 0.0;
   if (live)
@@ -1081,10 +1102,11 @@ __global__ void __launch_bounds__(kT) k_push_neutral(
     const long long i = b0 + r + threadIdx.x;
     PushOut o;
     o.cathode = false;
+    o.anode = false;
     o.cand = false;
     if (i < n) {
       finish_push<1>(p, i, p.x[i], p.y[i], p.z[i], p.vx[i], p.vy[i], p.vz[i],
-                     dt, g, key, ncount, m, step, seed, dc, o);
+                     dt, g, key, ncount, m, step, seed, dc, o, 0ull);
       if (o.cell != kDead) hist_add(hk, hc, o.cell, ncount);
       ke = ke + o.ke;
     }
@@ -1114,6 +1136,7 @@ __global__ void __launch_bounds__(kT) k_push_neutral_m(
     const long long i = b0 + r + threadIdx.x;
     PushOut o;
     o.cathode = false;
+    o.anode = false;
     o.cand = false;
     if (i < n) {
       push_one_m<1>(p, i, nullptr, nullptr, nullptr, 0, 0, 0, nullptr, 0, g,
