@@ -312,47 +312,103 @@ __global__ void __launch_bounds__(256) k_conv_first(
   st16(out + (size_t)v * 16 + 8, make_uint4(w[4], w[5], w[6], w[7]));
 }
 
-// dW of the first layer: each thread of a block owns up to 4 of the 864
-// weights and sums over the block's voxel chunk.
-__global__ void k_wgrad_first(const float* __restrict__ in,
-                              const bf16* __restrict__ g, float* __restrict__ dW,
-                              Dims d, long long chunk) {
-  const long long v0 = (long long)blockIdx.x * chunk;
-  long long v1 = v0 + chunk;
-  if (v1 > d.V) v1 = d.V;
-  for (int e = threadIdx.x; e < 864; e += blockDim.x) {
-    const int co = e / 54, r = e % 54, tap = r / 2, ci = r % 2;
-    float s = 0.f;
-    for (long long v = v0; v < v1; ++v) {
-      const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
-                z = (int)(v / ((long long)d.W * d.H));
-      const long long nv = nb_voxel(d, z, y, x, tap);
-      if (nv >= 0) s = s + bf2f(g[v * 16 + co]) * in[2 * nv + ci];
+// dW of the first layer: a workgroup takes one tap and a chunk of voxels;
+// each thread sums the 16 x 2 products g[v][co] x[v + tap][ci] of its
+// voxels in registers, the wave reduces them with cross-lane shuffles, and
+// the workgroup adds its 32 sums to dW[co][tap][ci] (16 x 27 x 2).
+__global__ void __launch_bounds__(256) k_wgrad_first(
+    const float* __restrict__ in, const bf16* __restrict__ g,
+    float* __restrict__ dW, Dims d, unsigned chunk) {
+  __shared__ float red[4][32];
+  const int tap = blockIdx.y;
+  const int oz = tap / 9 - 1, oy = (tap / 3) % 3 - 1, ox = tap % 3 - 1;
+  const unsigned v0 = blockIdx.x * chunk;
+  const unsigned long long vend = (unsigned long long)v0 + chunk;
+  const unsigned v1 = vend < (unsigned long long)d.V ? (unsigned)vend : (unsigned)d.V;
+  float acc[32];
+#pragma unroll
+  for (int e = 0; e < 32; ++e) acc[e] = 0.f;
+  for (unsigned v = v0 + threadIdx.x; v < v1; v += 256) {
+    int x, y, z;
+    voxel_xyz(v, d, x, y, z);
+    const int zz = z + oz;
+    if (zz < 0 || zz >= d.D) continue;
+    int yy = y + oy, xx = x + ox;
+    yy = yy < 0 ? yy + d.H : (yy >= d.H ? yy - d.H : yy);
+    xx = xx < 0 ? xx + d.W : (xx >= d.W ? xx - d.W : xx);
+    const float2 xi = reinterpret_cast<const float2*>(in)[((unsigned)zz * d.H + yy) * d.W + xx];
+    float gf[16];
+    unpack8(ld16(g + (size_t)v * 16), gf);
+    unpack8(ld16(g + (size_t)v * 16 + 8), gf + 8);
+#pragma unroll
+    for (int co = 0; co < 16; ++co) {
+      acc[2 * co] = fmaf(gf[co], xi.x, acc[2 * co]);
+      acc[2 * co + 1] = fmaf(gf[co], xi.y, acc[2 * co + 1]);
     }
-    atomicAdd(&dW[e], s);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int e = 0; e < 32; ++e) {
+    float t = acc[e];
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    acc[e] = t;
+  }
+  if (lane == 0)
+#pragma unroll
+    for (int e = 0; e < 32; ++e) red[wave][e] = acc[e];
+  __syncthreads();
+  if (threadIdx.x < 32) {
+    const float t = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                    (red[2][threadIdx.x] + red[3][threadIdx.x]);
+    atomicAdd(&dW[(threadIdx.x >> 1) * 54 + tap * 2 + (threadIdx.x & 1)], t);
   }
 }
 
-// Bias gradient: sum over voxels per channel.
-__global__ void k_bias_grad(const bf16* __restrict__ g, int C, Dims d,
-                            float* __restrict__ db) {
-  const int c = threadIdx.x % C;
-  const int lanes = blockDim.x / C;
-  const int r = threadIdx.x / C;
-  if (r >= lanes) return;
-  float s = 0.f;
-  for (long long v = (long long)blockIdx.x * lanes + r; v < d.V;
-       v += (long long)gridDim.x * lanes)
-    s = s + bf2f(g[v * C + c]);
-  atomicAdd(&db[c], s);
+// Bias gradient: sum over voxels per channel.  A thread adds 8 channels of
+// its voxels; the workgroup reduces in LDS and adds one value per channel.
+__global__ void __launch_bounds__(256) k_bias_grad(const bf16* __restrict__ g,
+                                                   int C, Dims d,
+                                                   float* __restrict__ db) {
+  __shared__ float s[256][8];
+  const unsigned G = (unsigned)C / 8;
+  const unsigned rows = 256 / G;
+  const unsigned r = threadIdx.x / G, cg = threadIdx.x % G;
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (r < rows) {
+    for (unsigned long long v = (unsigned long long)blockIdx.x * rows + r;
+         v < (unsigned long long)d.V; v += (unsigned long long)gridDim.x * rows) {
+      float f[8];
+      unpack8(ld16(g + (size_t)v * C + 8 * cg), f);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] += f[q];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s[threadIdx.x][q] = r < rows ? a[q] : 0.f;
+  __syncthreads();
+  if (threadIdx.x < (unsigned)C) {
+    const unsigned c8 = threadIdx.x / 8, q = threadIdx.x % 8;
+    float t = 0.f;
+    for (unsigned rr = 0; rr < rows; ++rr) t += s[rr * G + c8][q];
+    atomicAdd(&db[threadIdx.x], t);
+  }
 }
 
-// gpre = gy * (y > 0).
+// gpre = gy * (y > 0), 8 values a thread.
 __global__ void k_relu_bwd(const bf16* __restrict__ gy, const bf16* __restrict__ y,
                            bf16* __restrict__ gpre, long long n) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  gpre[i] = bf2f(y[i]) > 0.f ? gy[i] : (bf16)0;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if ((unsigned long long)t * 8 >= (unsigned long long)n) return;
+  const uint4 gv = ld16(gy + (size_t)t * 8), yv = ld16(y + (size_t)t * 8);
+  const unsigned gw[4] = {gv.x, gv.y, gv.z, gv.w}, yw[4] = {yv.x, yv.y, yv.z, yv.w};
+  unsigned o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const unsigned lo = (__uint_as_float(yw[q] << 16) > 0.f) ? (gw[q] & 0xffffu) : 0u;
+    const unsigned hi = (__uint_as_float(yw[q] & 0xffff0000u) > 0.f) ? (gw[q] & 0xffff0000u) : 0u;
+    o[q] = lo | hi;
+  }
+  st16(gpre + (size_t)t * 8, make_uint4(o[0], o[1], o[2], o[3]));
 }
 
 // Average pooling 2^3 (out dims d = input dims / 2), 8 channels a thread.
@@ -382,17 +438,26 @@ __global__ void k_pool(const bf16* __restrict__ in, bf16* __restrict__ out,
 }
 
 // Gradient through pooling added to an existing fine gradient:
-// gfine[child] = gfine[child] + gcoarse[parent] / 8 (fine dims d).
+// gfine[child] = gfine[child] + gcoarse[parent] / 8 (fine dims d), 8
+// channels a thread.
 __global__ void k_pool_bwd_add(const bf16* __restrict__ gc, bf16* __restrict__ gf,
                                Dims d, int C) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= d.V * C) return;
-  const int c = (int)(i % C);
-  const long long v = i / C;
-  const int x = (int)(v % d.W), y = (int)((v / d.W) % d.H),
-            z = (int)(v / ((long long)d.W * d.H));
-  const long long p = (((long long)(z / 2) * (d.H / 2)) + y / 2) * (d.W / 2) + x / 2;
-  gf[i] = f2bf(bf2f(gf[i]) + bf2f(gc[p * C + c]) * 0.125f);
+  const unsigned G = (unsigned)C / 8;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (unsigned long long)d.V * G) return;
+  const unsigned v = t / G, g = t % G;
+  int x, y, z;
+  voxel_xyz(v, d, x, y, z);
+  const unsigned p = ((unsigned)(z / 2) * (d.H / 2) + y / 2) * (d.W / 2) + x / 2;
+  float a[8], b[8];
+  unpack8(ld16(gf + (size_t)v * C + 8 * g), a);
+  unpack8(ld16(gc + (size_t)p * C + 8 * g), b);
+  unsigned w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    w[q] = (unsigned)f2bf(a[2 * q] + b[2 * q] * 0.125f) |
+           ((unsigned)f2bf(a[2 * q + 1] + b[2 * q + 1] * 0.125f) << 16);
+  st16(gf + (size_t)v * C + 8 * g, make_uint4(w[0], w[1], w[2], w[3]));
 }
 
 // Concatenation [up(coarse) (Cu channels), skip (Cs)] at fine dims d, 8
@@ -417,29 +482,39 @@ __global__ void k_up_cat(const bf16* __restrict__ coarse, int Cu,
 }
 
 // Split the concatenation's gradient: coarse part summed over the 8
-// children (coarse dims dc), skip part copied (fine dims).
+// children (coarse dims dc), skip part copied (fine dims); 8 channels a
+// thread.
 __global__ void k_split_up(const bf16* __restrict__ gcat, int Cu, int Cs,
                            bf16* __restrict__ gcoarse, Dims dc) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= dc.V * Cu) return;
-  const int c = (int)(i % Cu);
-  const long long p = i / Cu;
-  const int x = (int)(p % dc.W), y = (int)((p / dc.W) % dc.H),
-            z = (int)(p / ((long long)dc.W * dc.H));
-  const int W2 = 2 * dc.W, H2 = 2 * dc.H, C = Cu + Cs;
-  float s = 0.f;
+  const unsigned G = (unsigned)Cu / 8;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (unsigned long long)dc.V * G) return;
+  const unsigned p = t / G, g = t % G;
+  int x, y, z;
+  voxel_xyz(p, dc, x, y, z);
+  const unsigned W2 = 2 * dc.W, H2 = 2 * dc.H, C = Cu + Cs;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
-      for (int e = 0; e < 2; ++e)
-        s = s + bf2f(gcat[((((long long)(2 * z + a) * H2) + 2 * y + b) * W2 + 2 * x + e) * C + c]);
-  gcoarse[i] = f2bf(s);
+      for (int e = 0; e < 2; ++e) {
+        float f[8];
+        unpack8(ld16(gcat + ((size_t)((2 * z + a) * H2 + 2 * y + b) * W2 + 2 * x + e) * C + 8 * g), f);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s[q] = s[q] + f[q];
+      }
+  unsigned w[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    w[q] = (unsigned)f2bf(s[2 * q]) | ((unsigned)f2bf(s[2 * q + 1]) << 16);
+  st16(gcoarse + (size_t)p * Cu + 8 * g, make_uint4(w[0], w[1], w[2], w[3]));
 }
 __global__ void k_split_skip(const bf16* __restrict__ gcat, int Cu, int Cs,
                              bf16* __restrict__ gskip, Dims d) {
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= d.V * Cs) return;
-  const long long v = i / Cs;
-  gskip[i] = gcat[v * (Cu + Cs) + Cu + (i % Cs)];
+  const unsigned G = (unsigned)Cs / 8;
+  const unsigned t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (unsigned long long)d.V * G) return;
+  const unsigned v = t / G, g = t % G;
+  st16(gskip + (size_t)v * Cs + 8 * g, ld16(gcat + (size_t)v * (Cu + Cs) + Cu + 8 * g));
 }
 
 // Head: out[v] = sum_c w[c] y[v][c] + b, FP32 output.
@@ -478,21 +553,31 @@ __global__ void k_mse(const float* __restrict__ out, const float* __restrict__ t
 }
 
 // Head backward: gy[v][c] = gout[v] w[c]; dw[c] += sum gout y; db += sum.
-__global__ void k_head_bwd(const float* __restrict__ gout, const bf16* __restrict__ y,
-                           const float* __restrict__ w, bf16* __restrict__ gy,
-                           float* __restrict__ dw, long long V) {
+__global__ void __launch_bounds__(256) k_head_bwd(
+    const float* __restrict__ gout, const bf16* __restrict__ y,
+    const float* __restrict__ w, bf16* __restrict__ gy, float* __restrict__ dw,
+    long long V) {
   __shared__ float s[17][256];
   float acc[17];
+#pragma unroll
   for (int c = 0; c < 17; ++c) acc[c] = 0.f;
-  for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < V;
-       v += (long long)gridDim.x * blockDim.x) {
+  for (unsigned long long v = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+       v < (unsigned long long)V; v += (unsigned long long)gridDim.x * blockDim.x) {
     const float go = gout[v];
-    for (int c = 0; c < 16; ++c) {
-      gy[v * 16 + c] = f2bf(go * w[c]);
-      acc[c] = acc[c] + go * bf2f(y[v * 16 + c]);
-    }
+    float f[16];
+    unpack8(ld16(y + (size_t)v * 16), f);
+    unpack8(ld16(y + (size_t)v * 16 + 8), f + 8);
+    unsigned o[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      o[q] = (unsigned)f2bf(go * w[2 * q]) | ((unsigned)f2bf(go * w[2 * q + 1]) << 16);
+    st16(gy + (size_t)v * 16, make_uint4(o[0], o[1], o[2], o[3]));
+    st16(gy + (size_t)v * 16 + 8, make_uint4(o[4], o[5], o[6], o[7]));
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = acc[c] + go * f[c];
     acc[16] = acc[16] + go;
   }
+#pragma unroll
   for (int c = 0; c < 17; ++c) s[c][threadIdx.x] = acc[c];
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -792,7 +877,7 @@ bool unet_backward(pic_unet* u, int D, int H, int W) {
   auto back = [&](int l, const bf16* gy, const bf16* in, bf16* gpre, bf16* gx) {
     const LayerSpec& s = kLayers[l];
     const Dims& dd = d[kLevel[l]];
-    pic::k_relu_bwd<<<nb(dd.V * s.co), 256, 0, st>>>(gy, u->y[l], gpre, dd.V * s.co);
+    pic::k_relu_bwd<<<nb(dd.V * s.co / 8), 256, 0, st>>>(gy, u->y[l], gpre, dd.V * s.co);
     ok = ok && wgrad(st, s.ci, s.co, in, gpre, G + u->woff[l], dd);
     pic::k_bias_grad<<<256, 256, 0, st>>>(gpre, s.co, dd, G + u->boff[l]);
     if (gx) ok = ok && conv(st, s.co, s.ci, gpre, u->wd[l], nullptr, gx, dd, 0);
@@ -800,35 +885,34 @@ bool unet_backward(pic_unet* u, int D, int H, int W) {
   // Level 0 decoder.
   back(D0B, u->ga[0], u->y[D0A], u->gp[0], u->gb[0]);
   back(D0A, u->gb[0], u->c0, u->gp[0], u->ga[0]);        // ga0: grad of c0 (48)
-  pic::k_split_skip<<<nb(d[0].V * 16), 256, 0, st>>>(u->ga[0], 32, 16, u->gs[0], d[0]);
-  pic::k_split_up<<<nb(d[1].V * 32), 256, 0, st>>>(u->ga[0], 32, 16, u->ga[1], d[1]);
+  pic::k_split_skip<<<nb(d[0].V * 2), 256, 0, st>>>(u->ga[0], 32, 16, u->gs[0], d[0]);
+  pic::k_split_up<<<nb(d[1].V * 4), 256, 0, st>>>(u->ga[0], 32, 16, u->ga[1], d[1]);
   // Level 1 decoder.
   back(D1B, u->ga[1], u->y[D1A], u->gp[1], u->gb[1]);
   back(D1A, u->gb[1], u->c1, u->gp[1], u->ga[1]);        // grad of c1 (96)
-  pic::k_split_skip<<<nb(d[1].V * 32), 256, 0, st>>>(u->ga[1], 64, 32, u->gs[1], d[1]);
-  pic::k_split_up<<<nb(d[2].V * 64), 256, 0, st>>>(u->ga[1], 64, 32, u->ga[2], d[2]);
+  pic::k_split_skip<<<nb(d[1].V * 4), 256, 0, st>>>(u->ga[1], 64, 32, u->gs[1], d[1]);
+  pic::k_split_up<<<nb(d[2].V * 8), 256, 0, st>>>(u->ga[1], 64, 32, u->ga[2], d[2]);
   // Level 2 decoder.
   back(D2B, u->ga[2], u->y[D2A], u->gp[2], u->gb[2]);
   back(D2A, u->gb[2], u->c2, u->gp[2], u->ga[2]);        // grad of c2 (192)
-  pic::k_split_skip<<<nb(d[2].V * 64), 256, 0, st>>>(u->ga[2], 128, 64, u->gs[2], d[2]);
-  pic::k_split_up<<<nb(d[3].V * 128), 256, 0, st>>>(u->ga[2], 128, 64, u->ga[3], d[3]);
+  pic::k_split_skip<<<nb(d[2].V * 8), 256, 0, st>>>(u->ga[2], 128, 64, u->gs[2], d[2]);
+  pic::k_split_up<<<nb(d[3].V * 16), 256, 0, st>>>(u->ga[2], 128, 64, u->ga[3], d[3]);
   // Bottom.
   back(BB, u->ga[3], u->y[BA], u->gp[3], u->gb[3]);
   back(BA, u->gb[3], u->p2, u->gp[3], u->ga[3]);         // grad of p2 (64)
   // Encoder level 2: skip gradient + pooled gradient.
-  pic::k_pool_bwd_add<<<nb(d[2].V * 64), 256, 0, st>>>(u->ga[3], u->gs[2], d[2], 64);
+  pic::k_pool_bwd_add<<<nb(d[2].V * 8), 256, 0, st>>>(u->ga[3], u->gs[2], d[2], 64);
   back(E2B, u->gs[2], u->y[E2A], u->gp[2], u->gb[2]);
   back(E2A, u->gb[2], u->p1, u->gp[2], u->ga[2]);        // grad of p1 (32)
-  pic::k_pool_bwd_add<<<nb(d[1].V * 32), 256, 0, st>>>(u->ga[2], u->gs[1], d[1], 32);
+  pic::k_pool_bwd_add<<<nb(d[1].V * 4), 256, 0, st>>>(u->ga[2], u->gs[1], d[1], 32);
   back(E1B, u->gs[1], u->y[E1A], u->gp[1], u->gb[1]);
   back(E1A, u->gb[1], u->p0, u->gp[1], u->ga[1]);        // grad of p0 (16)
-  pic::k_pool_bwd_add<<<nb(d[0].V * 16), 256, 0, st>>>(u->ga[1], u->gs[0], d[0], 16);
+  pic::k_pool_bwd_add<<<nb(d[0].V * 2), 256, 0, st>>>(u->ga[1], u->gs[0], d[0], 16);
   back(E0B, u->gs[0], u->y[E0A], u->gp[0], u->gb[0]);    // grad of e0a (16)
   // First layer: weights only.
-  pic::k_relu_bwd<<<nb(d[0].V * 16), 256, 0, st>>>(u->gb[0], u->y[E0A], u->gp[0], d[0].V * 16);
-  long long chunk = d[0].V / 512;
-  if (chunk < 1024) chunk = 1024;
-  pic::k_wgrad_first<<<(unsigned)((d[0].V + chunk - 1) / chunk), 256, 0, st>>>(
+  pic::k_relu_bwd<<<nb(d[0].V * 2), 256, 0, st>>>(u->gb[0], u->y[E0A], u->gp[0], d[0].V * 16);
+  const unsigned chunk = 8192;
+  pic::k_wgrad_first<<<dim3((unsigned)((d[0].V + chunk - 1) / chunk), 27), 256, 0, st>>>(
       u->x_in, u->gp[0], G + u->woff[E0A], d[0], chunk);
   pic::k_bias_grad<<<256, 256, 0, st>>>(u->gp[0], 16, d[0], G + u->boff[E0A]);
   return ok;
