@@ -31,6 +31,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE and WRITE_SIZE
+# (one counter per run) on the c2 FP64 workload, each scaled by what the
+# counter reads for a 1 GiB device copy (reads x 2.0, writes x 1.0); see
+# profiles/c2_fp64_hbm_traffic.md.  Valid only for these kernels as built
+# when measured; set to None when they change.
+MEASURED_TRAFFIC = {
+    ("c2", "fp64", "k_smooth2"): 239.8e6,
+    ("c2", "fp64", "k_push_tile"): 2393.3e6,
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -263,10 +273,12 @@ def main():
         kname = "k_rbgs (finest level, one colour)"
     sm_bytes = unknowns * per_u
     achieved = sm_bytes * n_eff / (ms_sm * 1e-3) / 1e9 if ms_sm > 0 else 0.0
+    prec = head["precision"]
+    tr = MEASURED_TRAFFIC.get((a.workload, prec, "k_smooth2")) if fused else None
     roofline = {"bound": "hbm", "kernel": kname,
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": int(sm_bytes),
+                "traffic": tr, "bytes_per_launch": int(sm_bytes),
                 "launches_timed": int(n_sm), "launches_with_work": int(n_eff),
                 "avg_launch_ms": round(ms_sm / max(n_eff, 1), 5)}
 
@@ -286,6 +298,7 @@ def main():
     roofline_push = {"bound": "hbm", "kernel": "k_push_tile",
                      "achieved": round(ach_p, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach_p / HBM_PEAK_GBS, 4),
+                     "traffic": MEASURED_TRAFFIC.get((a.workload, prec, "k_push_tile")),
                      "bytes_per_launch": int(alg_bytes),
                      "avg_launch_ms": round(t_push * 1e3, 5)}
     out = {
