@@ -234,6 +234,22 @@ pic_status pic_read_particles(pic_ctx* ctx, int32_t species, int64_t cap,
 pic_status pic_read_fields(pic_ctx* ctx, int64_t* acc_device,
                            double* phi_device, double* E3_device);
 pic_status pic_set_clock(pic_ctx* ctx, int64_t step, uint64_t next_id);
+
+/* Checkpoint and resume.  The checkpoint (host memory, caller-owned,
+ * pic_checkpoint_bytes large) holds the grid, precision and seed, the
+ * clock and id counter, the collision and source settings, every
+ * particle in the context's native layout, the last potential (the next
+ * solve's warm start) and the last solve's V-cycle count.  Every random
+ * number is keyed by (id, step), so a context restored from it continues
+ * exactly as the saved one would (particle storage order aside).
+ * pic_checkpoint_save: PIC_ERR_STATE while injections are queued.
+ * pic_checkpoint_load: the context must have the same grid, boundary
+ * data, precision, seed and weight (PIC_ERR_ARG otherwise) and room for
+ * the particles (PIC_ERR_CAPACITY); the warm-start mode is not part of
+ * the checkpoint. */
+pic_status pic_checkpoint_bytes(pic_ctx* ctx, size_t* bytes);
+pic_status pic_checkpoint_save(pic_ctx* ctx, void* host, size_t bytes);
+pic_status pic_checkpoint_load(pic_ctx* ctx, const void* host, size_t bytes);
 pic_status pic_get_diag(pic_ctx* ctx, pic_diag* diag);
 
 /* Per-phase GPU time, measured with HIP events recorded on the context's

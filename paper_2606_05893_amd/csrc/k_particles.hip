@@ -1811,6 +1811,28 @@ __global__ void k_load(PT p, const double* __restrict__ pos,
   key[t] = load_key(p, t, x, y, z, g);
 }
 
+// Cell keys of a population restored in its native layout.
+__global__ void k_restore_keys(Parts p, uint32_t* __restrict__ key, long long n,
+                               GridC g, Counters* dc) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const double x = p.x[t], y = p.y[t], z = p.z[t];
+  const double gz = z * g.inv_dx;
+  const bool ok = x >= 0.0 && x < g.lx && y >= 0.0 && y < g.ly && gz >= 0.0 &&
+                  gz < (double)g.nz;
+  if (!ok) atomicOr(&dc->err, kErrNonFinite);
+  key[t] = ok ? cell_of(x, y, z, g) : kDead;
+}
+__global__ void k_restore_keys(PartsM p, uint32_t* __restrict__ key,
+                               long long n, GridC g, Counters* dc) {
+  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const uint32_t cell = p.cell[t];
+  const bool ok = cell < (uint32_t)((long long)g.nxy * g.nz);
+  if (!ok) atomicOr(&dc->err, kErrNonFinite);
+  key[t] = ok ? cell : kDead;
+}
+
 template <class PT>
 __global__ void k_read(PT p, double* __restrict__ pos, double* __restrict__ vel,
                        uint64_t* __restrict__ ids, long long n, GridC g) {
@@ -2284,6 +2306,30 @@ bool parts_validate(pic_ctx* c, const double* pos, const double* vel,
                  c->stream);
   hipStreamSynchronize(c->stream);
   return bad == 0;
+}
+
+int parts_arrays(pic_ctx* c, int s, void** ptr, size_t* elem) {
+  if (c->mixed) {
+    PartsM p = cur<PartsM>(c, s);
+    void* a[8] = {p.cell, p.ox, p.oy, p.oz, p.vx, p.vy, p.vz, p.id};
+    const size_t e[8] = {4, 4, 4, 4, 4, 4, 4, 8};
+    for (int k = 0; k < 8; ++k) { ptr[k] = a[k]; elem[k] = e[k]; }
+    return 8;
+  }
+  Parts p = cur<Parts>(c, s);
+  void* a[7] = {p.x, p.y, p.z, p.vx, p.vy, p.vz, p.id};
+  for (int k = 0; k < 7; ++k) { ptr[k] = a[k]; elem[k] = 8; }
+  return 7;
+}
+
+void parts_restore_keys(pic_ctx* c, int s, long long n) {
+  if (n <= 0) return;
+  if (c->mixed)
+    k_restore_keys<<<nblk(n), kT, 0, c->stream>>>(cur<PartsM>(c, s), c->key[s], n,
+                                                  c->g, c->dc);
+  else
+    k_restore_keys<<<nblk(n), kT, 0, c->stream>>>(cur<Parts>(c, s), c->key[s], n,
+                                                  c->g, c->dc);
 }
 
 void parts_read(pic_ctx* c, int s, long long n, double* pos, double* vel,

@@ -646,6 +646,163 @@ pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
   return PIC_OK;
 }
 
+// ---- checkpoint ------------------------------------------------------------
+namespace {
+
+struct CkptHeader {
+  char magic[8];
+  int32_t abi, precision;
+  int32_t nx, ny, nz, bc_lo, bc_hi, field_solve;
+  double dx, v_lo, v_hi;
+  uint64_t seed;
+  uint32_t w_sp, pad;
+  int64_t step;
+  uint64_t next_id;
+  int64_t n[3];
+  int32_t last_vcycles, pad2;
+  pic_collisions coll;
+  pic_sources src;
+  int64_t nnodes;
+};
+constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '1'};
+
+size_t record_bytes(const pic_ctx* c) { return c->mixed ? 36 : 56; }
+
+size_t ckpt_bytes(const pic_ctx* c) {
+  size_t b = sizeof(CkptHeader);
+  for (int s = 0; s < 3; ++s) b += (size_t)c->n[s] * record_bytes(c);
+  return b + (size_t)c->nnodes * sizeof(double);
+}
+
+}  // namespace
+
+pic_status pic_checkpoint_bytes(pic_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return PIC_ERR_ARG;
+  *bytes = ckpt_bytes(c);
+  return PIC_OK;
+}
+
+pic_status pic_checkpoint_save(pic_ctx* c, void* host, size_t bytes) {
+  if (!c || !host) return PIC_ERR_ARG;
+  if (!c->queue.empty() || c->queue_used > 0)
+    return set_err(c, PIC_ERR_STATE, "checkpoint with queued injections");
+  if (bytes < ckpt_bytes(c))
+    return set_err(c, PIC_ERR_ARG, "checkpoint buffer too small");
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.abi = PIC_ABI_VERSION;
+  h.precision = c->cfg.precision;
+  h.nx = c->cfg.nx; h.ny = c->cfg.ny; h.nz = c->cfg.nz;
+  h.bc_lo = c->cfg.bc_lo; h.bc_hi = c->cfg.bc_hi;
+  h.field_solve = c->cfg.field_solve;
+  h.dx = c->cfg.dx; h.v_lo = c->cfg.v_lo; h.v_hi = c->cfg.v_hi;
+  h.seed = c->cfg.seed;
+  h.w_sp = c->cfg.w_sp;
+  h.step = c->step;
+  h.next_id = c->next_id;
+  for (int s = 0; s < 3; ++s) h.n[s] = c->n[s];
+  h.last_vcycles = c->last_vcycles;
+  h.coll = c->coll;
+  h.src = c->src;
+  h.nnodes = c->nnodes;
+  char* out = static_cast<char*>(host);
+  std::memcpy(out, &h, sizeof(h));
+  size_t off = sizeof(h);
+  for (int s = 0; s < 3; ++s) {
+    void* ptr[8];
+    size_t elem[8];
+    const int na = parts_arrays(c, s, ptr, elem);
+    for (int k = 0; k < na; ++k) {
+      const size_t nb = (size_t)c->n[s] * elem[k];
+      if (nb && !hip_ok(c, hipMemcpyAsync(out + off, ptr[k], nb,
+                                          hipMemcpyDeviceToHost, c->stream),
+                        "checkpoint copy"))
+        return PIC_ERR_HIP;
+      off += nb;
+    }
+  }
+  if (!hip_ok(c, hipMemcpyAsync(out + off, c->lev[0].u,
+                                (size_t)c->nnodes * sizeof(double),
+                                hipMemcpyDeviceToHost, c->stream),
+              "checkpoint copy") ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "synchronise"))
+    return PIC_ERR_HIP;
+  return PIC_OK;
+}
+
+pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
+  if (!c || !host || bytes < sizeof(CkptHeader)) return PIC_ERR_ARG;
+  CkptHeader h;
+  std::memcpy(&h, host, sizeof(h));
+  if (std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.abi != PIC_ABI_VERSION)
+    return set_err(c, PIC_ERR_ARG, "not a checkpoint of this library version");
+  const pic_config& f = c->cfg;
+  if (h.precision != f.precision || h.nx != f.nx || h.ny != f.ny ||
+      h.nz != f.nz || h.bc_lo != f.bc_lo || h.bc_hi != f.bc_hi ||
+      h.field_solve != f.field_solve || h.dx != f.dx || h.v_lo != f.v_lo ||
+      h.v_hi != f.v_hi || h.seed != f.seed || h.w_sp != f.w_sp ||
+      h.nnodes != c->nnodes)
+    return set_err(c, PIC_ERR_ARG, "checkpoint of another configuration");
+  for (int s = 0; s < 3; ++s)
+    if (h.n[s] < 0 || h.n[s] > f.capacity[s])
+      return set_err(c, PIC_ERR_CAPACITY, "checkpoint exceeds capacity");
+  size_t need = sizeof(CkptHeader) + (size_t)c->nnodes * sizeof(double);
+  for (int s = 0; s < 3; ++s) need += (size_t)h.n[s] * record_bytes(c);
+  if (bytes < need) return set_err(c, PIC_ERR_ARG, "checkpoint truncated");
+  pic_status st = pic_set_collisions(c, &h.coll);
+  if (st == PIC_OK) st = pic_set_sources(c, &h.src);
+  if (st != PIC_OK) return st;
+  for (int s = 0; s < 3; ++s) c->n[s] = h.n[s];
+  const char* in = static_cast<const char*>(host);
+  size_t off = sizeof(h);
+  for (int s = 0; s < 3; ++s) {
+    void* ptr[8];
+    size_t elem[8];
+    const int na = parts_arrays(c, s, ptr, elem);
+    for (int k = 0; k < na; ++k) {
+      const size_t nb = (size_t)h.n[s] * elem[k];
+      if (nb && !hip_ok(c, hipMemcpyAsync(ptr[k], in + off, nb,
+                                          hipMemcpyHostToDevice, c->stream),
+                        "restore copy"))
+        return PIC_ERR_HIP;
+      off += nb;
+    }
+  }
+  if (!hip_ok(c, hipMemcpyAsync(c->lev[0].u, in + off,
+                                (size_t)c->nnodes * sizeof(double),
+                                hipMemcpyHostToDevice, c->stream),
+              "restore copy"))
+    return PIC_ERR_HIP;
+  // Keys from the restored layout, then the binning pass as for a load.
+  for (int s = 0; s < 3; ++s) {
+    parts_restore_keys(c, s, h.n[s]);
+    hipMemsetAsync(c->tsb[s][c->tcur[s]], 0, (c->ntiles + 1) * sizeof(uint32_t),
+                   c->stream);
+    c->n_binned[s] = 0;
+    k_set_n<<<1, 1, 0, c->stream>>>(c->dc, s, (unsigned long long)h.n[s]);
+    parts_bin_species(c, s);
+  }
+  st = sync_counters(c);
+  if (st != PIC_OK) return st;
+  for (int s = 0; s < 3; ++s) {
+    c->n[s] = (long long)c->hc.sorted_n[s];
+    c->n_binned[s] = c->n[s];
+  }
+  const long long hb[3] = {c->n[0], c->n[1], c->n[2]};
+  parts_chunks(c, hb);
+  c->step = h.step;
+  c->next_id = h.next_id;
+  c->last_vcycles = h.last_vcycles;
+  c->queue.clear();
+  c->queue_used = 0;
+  if (c->hc.err) {
+    check_flags(c);
+    return set_err(c, PIC_ERR_ARG, "checkpoint holds particles outside the domain");
+  }
+  return hip_ok(c, hipStreamSynchronize(c->stream), "synchronise") ? PIC_OK : PIC_ERR_HIP;
+}
+
 pic_status pic_count(pic_ctx* c, int32_t s, int64_t* n) {
   if (!c || s < 0 || s > 2 || !n) return PIC_ERR_ARG;
   *n = c->n[s];

@@ -155,6 +155,10 @@ void parts_push_collide(pic_ctx* c, double dt);
 void parts_bin(pic_ctx* c);
 void parts_bin_species(pic_ctx* c, int s);
 void parts_chunks(pic_ctx* c, const long long hb[3]);
+// Device arrays of species s (current buffer, native layout) and their
+// element sizes; returns the number of arrays.
+int parts_arrays(pic_ctx* c, int s, void** ptr, size_t* elem);
+void parts_restore_keys(pic_ctx* c, int s, long long n);
 void parts_load(pic_ctx* c, int s, long long n, const double* pos,
                 const double* vel, const uint64_t* ids);
 void parts_read(pic_ctx* c, int s, long long n, double* pos, double* vel,

@@ -113,6 +113,9 @@ EXPORTS = {
     "pic_set_clock": (_c_i32, [_c_p, _c_i64, _c_u64]),
     "pic_get_diag": (_c_i32, [_c_p, ctypes.POINTER(Diag)]),
     "pic_set_warm_start": (_c_i32, [_c_p, _c_i32, _c_p]),
+    "pic_checkpoint_bytes": (_c_i32, [_c_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "pic_checkpoint_save": (_c_i32, [_c_p, _c_p, ctypes.c_size_t]),
+    "pic_checkpoint_load": (_c_i32, [_c_p, _c_p, ctypes.c_size_t]),
     "pic_warm_pair": (_c_i32, [_c_p, _c_p, _c_p]),
     "pic_enable_timing": (_c_i32, [_c_p, _c_i32]),
     "pic_phase_times": (_c_i32, [_c_p, ctypes.POINTER(_c_d),
@@ -371,6 +374,18 @@ class Pic:
         t = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
         self._call("pic_warm_pair", _ptr(x), _ptr(t))
         return x, t
+
+    def checkpoint(self):
+        """The context's checkpoint as bytes (host memory)."""
+        n = ctypes.c_size_t()
+        self._call("pic_checkpoint_bytes", ctypes.byref(n))
+        buf = ctypes.create_string_buffer(n.value)
+        self._call("pic_checkpoint_save", buf, n.value)
+        return buf.raw
+
+    def restore(self, data):
+        buf = ctypes.create_string_buffer(bytes(data), len(data))
+        self._call("pic_checkpoint_load", buf, len(data))
 
     def set_clock(self, step, next_id):
         self._call("pic_set_clock", int(step), int(next_id))
