@@ -174,3 +174,67 @@ def adam_step(params, m, v, grad, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     mh = m / (1.0 - beta1 ** t)
     vh = v / (1.0 - beta2 ** t)
     params[:] = params - lr * mh / (np.sqrt(vh) + eps)
+
+
+# --------------------------------------------------------------------------
+# Residual loss: the scaled 7-point operator applied to the error
+# --------------------------------------------------------------------------
+def _net_grid(shape, k0):
+    """Poisson grid of the network's planes: nz = D with a Dirichlet top
+    (the plane beyond the network is zero) and a Dirichlet (k0 = 1) or
+    Neumann (k0 = 0) bottom."""
+    from .poisson import DIRICHLET, NEUMANN, Grid
+    D, H, W = shape
+    return Grid(W, H, D, 1.0, DIRICHLET if k0 == 1 else NEUMANN, DIRICHLET)
+
+
+def _embed(e, k0):
+    """Network planes (D, H, W) -> node array (D+1, H, W) with the planes
+    below k0 and the top plane zero."""
+    D, H, W = e.shape
+    out = np.zeros((D + 1, H, W))
+    out[k0:D] = e[k0:D]
+    return out
+
+
+def residual_loss_and_grad(params, x, target, k0):
+    """Loss = sum over the unknown planes of (A (c - t))^2 / V, with A the
+    scaled Poisson operator of the network grid (x, y periodic, zero beyond
+    the top plane, Dirichlet or mirror Neumann bottom); it is the squared
+    residual of the start phi_prev + sigma c over sigma^2, per voxel.
+    Returns (loss, parameter gradient, output)."""
+    from .poisson import apply_operator
+    out, cache = forward(params, x)
+    D, H, W = out.shape
+    g = _net_grid(out.shape, k0)
+    q = apply_operator(_embed(out - target, k0), g)[:D]
+    q[:k0] = 0.0
+    V = out.size
+    loss = float(np.sum(q * q) / V)
+    # d loss / d c = (2 / V) A^T q on the unknowns: A^T through the
+    # operator's definition (rows of A), taken column by column as the
+    # adjoint of apply_operator.
+    g_out = (2.0 / V) * _adjoint(q, g, k0)
+    return loss, backward(params, cache, g_out), out
+
+
+def _adjoint(q, g, k0):
+    """A^T q restricted to the unknown planes, from A's rows: A e at an
+    unknown node is 6 e - (x, y neighbours) - (z neighbours, the lower one
+    mirrored at a Neumann bottom), so each row entry is sent back to the
+    node it multiplies."""
+    D, H, W = q.shape
+    r = np.zeros((D + 1, H, W))
+    for k in range(k0, D):
+        qk = q[k]
+        r[k] += 6.0 * qk
+        r[k] -= np.roll(qk, 1, axis=1) + np.roll(qk, -1, axis=1)
+        r[k] -= np.roll(qk, 1, axis=0) + np.roll(qk, -1, axis=0)
+        if k == 0:
+            r[1] -= 2.0 * qk          # mirror ghost phi_-1 = phi_1
+        else:
+            r[k - 1] -= qk
+            r[k + 1] -= qk
+    out = r[:D]
+    out[:k0] = 0.0
+    return out

@@ -93,3 +93,53 @@ def test_adam_against_closed_form_first_step():
     m, v = np.zeros(3), np.zeros(3)
     U.adam_step(p, m, v, g, 1, lr=0.1, eps=0.0)
     assert np.allclose(p, [0.9, -1.9, 2.9], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("k0", [0, 1])
+def test_residual_loss_pins(k0):
+    """The residual loss is the squared residual of the Poisson operator
+    (its own pinned implementation) over the unknowns; its gradient with
+    respect to the output matches finite differences, which checks the
+    adjoint (including the Neumann mirror)."""
+    from oracle import poisson as P
+    rng = np.random.default_rng(4)
+    shape = (8, 8, 8)
+    c = rng.standard_normal(shape)
+    t = rng.standard_normal(shape)
+    g = U._net_grid(shape, k0)
+    e = U._embed(c - t, k0)
+    q = P.apply_operator(e, g)[:8]
+    q[:k0] = 0.0
+    loss = np.sum(q * q) / c.size
+    # Finite differences of the loss w.r.t. a few output entries.
+    def L(cc):
+        qq = P.apply_operator(U._embed(cc - t, k0), g)[:8]
+        qq[:k0] = 0.0
+        return np.sum(qq * qq) / c.size
+    grad = (2.0 / c.size) * U._adjoint(q, g, k0)
+    for idx in [(0, 0, 0), (1, 2, 3), (7, 7, 7), (0, 5, 1), (3, 0, 7)]:
+        h = 1e-6
+        cp = c.copy(); cp[idx] += h
+        cm = c.copy(); cm[idx] -= h
+        fd = (L(cp) - L(cm)) / (2 * h)
+        assert abs(fd - grad[idx]) <= 1e-6 * max(1.0, abs(fd)), (idx, fd, grad[idx])
+    assert abs(L(c) - loss) < 1e-12
+    # Zero error, zero loss.
+    assert L(t) == 0.0
+
+
+def test_residual_loss_and_grad_matches_finite_differences():
+    p = W.unet_init(5).astype(np.float64)
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((8, 8, 8, 2))
+    t = rng.standard_normal((8, 8, 8))
+    loss, g, _ = U.residual_loss_and_grad(p, x, t, 1)
+    lay, n = U.param_layout()
+    for name, kind, off, shape in lay[-4:]:
+        j = off
+        h = 1e-5
+        pp = p.copy(); pp[j] += h
+        pm = p.copy(); pm[j] -= h
+        fd = (U.residual_loss_and_grad(pp, x, t, 1)[0] -
+              U.residual_loss_and_grad(pm, x, t, 1)[0]) / (2 * h)
+        assert abs(fd - g[j]) <= 1e-5 * max(1.0, abs(fd)), (name, kind, fd, g[j])
