@@ -129,7 +129,7 @@ def new_context(G, p, precision, pre, n0, cap):
     return gpu
 
 
-def train_warm_start(G, W, WS, p, cap, steps=12, epochs=4):
+def train_warm_start(G, W, WS, p, cap, steps=32, epochs=12):
     """The learned start's network, trained on pairs recorded by a mixed
     run from another preload (seed 2) than the timed runs (seed 1)."""
     import torch
@@ -145,12 +145,13 @@ def train_warm_start(G, W, WS, p, cap, steps=12, epochs=4):
     net = G.UNet(p["nz"], p["ny"], p["nx"], params=W.unet_init(0))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = WS.train(net, pairs, epochs=epochs, lr_max=1e-3, lr_min=1e-5)
+    losses = WS.train(net, pairs, epochs=epochs, lr_max=1e-3, lr_min=1e-5,
+                      loss="residual", k0=1 if p["bc_lo"] == 0 else 0)
     torch.cuda.synchronize()
     info = {"pairs": len(pairs), "epochs": epochs,
             "train_s": round(time.perf_counter() - t0, 3),
             "epoch_loss": [round(v, 5) for v in losses],
-            "source": "mixed run, preload seed 2"}
+            "source": "mixed run, preload seed 2", "loss": "residual"}
     del pairs
     torch.cuda.empty_cache()
     return net, info

@@ -305,6 +305,15 @@ pic_status pic_unet_gradients(pic_unet* u, const float* input_device,
                               const float* target_device, int32_t D,
                               int32_t H, int32_t W, float* grad_device,
                               double* loss);
+/* Training loss.  PIC_UNET_LOSS_MSE (default): mean squared error of the
+ * output against the target.  PIC_UNET_LOSS_RESIDUAL: sum over the unknown
+ * planes z >= k0 of (A (out - target))^2 / V, with A the scaled 7-point
+ * Poisson operator of the network grid (x, y periodic, zero beyond the top
+ * plane; k0 = 1: Dirichlet bottom plane, k0 = 0: Neumann bottom, mirrored),
+ * i.e. the squared residual of the warm start it produces over sigma^2.
+ * PIC_ERR_ARG for another mode or k0. */
+enum { PIC_UNET_LOSS_MSE = 0, PIC_UNET_LOSS_RESIDUAL = 1 };
+pic_status pic_unet_set_loss(pic_unet* u, int32_t mode, int32_t k0);
 /* One Adam step on one sample; loss is that sample's loss before it. */
 pic_status pic_unet_train_step(pic_unet* u, const float* input_device,
                                const float* target_device, int32_t D,

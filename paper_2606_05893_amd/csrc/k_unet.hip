@@ -552,6 +552,79 @@ __global__ void k_mse(const float* __restrict__ out, const float* __restrict__ t
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
+// Residual loss: q = A e on the unknown planes (z >= k0), e = c - t there
+// and zero below k0 and beyond the top plane; A is the scaled 7-point
+// operator (x, y periodic; a Neumann bottom, k0 = 0, mirrors plane 1).
+// Block partials of sum q^2.
+__device__ __forceinline__ float res_e(const float* c, const float* t, int z,
+                                       unsigned row, int k0, int D) {
+  return (z >= k0 && z < D) ? c[row] - t[row] : 0.0f;
+}
+
+__global__ void k_res_q(const float* __restrict__ c, const float* __restrict__ t,
+                        float* __restrict__ q, Dims d, int k0,
+                        double* __restrict__ part) {
+  __shared__ double s[256];
+  double a = 0.0;
+  const unsigned plane = (unsigned)d.H * d.W;
+  for (unsigned long long vv = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x;
+       vv < (unsigned long long)d.V; vv += (unsigned long long)gridDim.x * blockDim.x) {
+    const unsigned v = (unsigned)vv;
+    int x, y, z;
+    voxel_xyz(v, d, x, y, z);
+    float r = 0.0f;
+    if (z >= k0) {
+      const unsigned base = (unsigned)z * plane;
+      const int xm = x ? x - 1 : d.W - 1, xp = x + 1 < d.W ? x + 1 : 0;
+      const int ym = y ? y - 1 : d.H - 1, yp = y + 1 < d.H ? y + 1 : 0;
+      const float e0 = c[v] - t[v];
+      float xy = res_e(c, t, z, base + y * d.W + xm, k0, d.D) +
+                 res_e(c, t, z, base + y * d.W + xp, k0, d.D);
+      xy = xy + (res_e(c, t, z, base + ym * d.W + x, k0, d.D) +
+                 res_e(c, t, z, base + yp * d.W + x, k0, d.D));
+      float zz;
+      if (z == 0)
+        zz = 2.0f * res_e(c, t, 1, v + plane, k0, d.D);
+      else
+        zz = res_e(c, t, z - 1, v - plane, k0, d.D) +
+             res_e(c, t, z + 1, v + plane, k0, d.D);
+      r = 6.0f * e0 - xy - zz;
+    }
+    q[v] = r;
+    a += (double)r * r;
+  }
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// gout = (2 / V) A^T q on the unknown planes (row z-1 = 0 of a Neumann
+// bottom reaches plane 1 with coefficient 2).
+__global__ void k_res_g(const float* __restrict__ q, float* __restrict__ gout,
+                        Dims d, int k0, float scale) {
+  const unsigned v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= (unsigned long long)d.V) return;
+  int x, y, z;
+  voxel_xyz(v, d, x, y, z);
+  float g = 0.0f;
+  if (z >= k0) {
+    const unsigned plane = (unsigned)d.H * d.W, base = (unsigned)z * plane;
+    const int xm = x ? x - 1 : d.W - 1, xp = x + 1 < d.W ? x + 1 : 0;
+    const int ym = y ? y - 1 : d.H - 1, yp = y + 1 < d.H ? y + 1 : 0;
+    float xy = q[base + y * d.W + xm] + q[base + y * d.W + xp];
+    xy = xy + (q[base + ym * d.W + x] + q[base + yp * d.W + x]);
+    float zz = 0.0f;
+    if (z - 1 >= k0) zz = (z - 1 == 0 ? 2.0f : 1.0f) * q[v - plane];
+    if (z + 1 < d.D) zz = zz + q[v + plane];
+    g = (6.0f * q[v] - xy - zz) * scale;
+  }
+  gout[v] = g;
+}
+
 // Head backward: gy[v][c] = gout[v] w[c]; dw[c] += sum gout y; db += sum.
 __global__ void __launch_bounds__(256) k_head_bwd(
     const float* __restrict__ gout, const bf16* __restrict__ y,
@@ -691,6 +764,8 @@ struct pic_unet {
   float* dscratch;             // double partials (as float storage)
   double* dpart;
   int t;                       // Adam step
+  int loss_mode, loss_k0;      // PIC_UNET_LOSS_*, first unknown plane
+  float* q;                    // residual of the error (residual loss)
   std::string err;
 };
 
@@ -747,6 +822,7 @@ size_t unet_carve(pic_unet* u, char* base) {
     u->gs[l] = cv.take<bf16>(Vl[l] * widest[l]);
   }
   u->dpart = cv.take<double>(1024);
+  u->q = cv.take<float>(V0);
   return cv.off + 256;
 }
 
@@ -978,6 +1054,8 @@ pic_status pic_unet_init(int32_t D, int32_t H, int32_t W, void* ws,
   u->bytes = bytes;
   unet_carve(u, base);
   u->t = 0;
+  u->loss_mode = PIC_UNET_LOSS_MSE;
+  u->loss_k0 = 1;
   if (hipMemsetAsync(ws, 0, bytes, u->stream) != hipSuccess ||
       hipStreamSynchronize(u->stream) != hipSuccess) {
     delete u;
@@ -988,6 +1066,15 @@ pic_status pic_unet_init(int32_t D, int32_t H, int32_t W, void* ws,
 }
 
 void pic_unet_destroy(pic_unet* u) { delete u; }
+
+pic_status pic_unet_set_loss(pic_unet* u, int32_t mode, int32_t k0) {
+  if (!u || (mode != PIC_UNET_LOSS_MSE && mode != PIC_UNET_LOSS_RESIDUAL) ||
+      (k0 != 0 && k0 != 1))
+    return PIC_ERR_ARG;
+  u->loss_mode = mode;
+  u->loss_k0 = k0;
+  return PIC_OK;
+}
 
 const char* pic_unet_last_error(const pic_unet* u) {
   return u ? u->err.c_str() : "null U-Net";
@@ -1039,7 +1126,13 @@ pic_status pic_unet_gradients(pic_unet* u, const float* input,
   hipMemcpyAsync(u->x_in, input, 2 * V * sizeof(float), hipMemcpyDeviceToDevice, st);
   hipMemcpyAsync(u->target, target, V * sizeof(float), hipMemcpyDeviceToDevice, st);
   if (!unet_forward(u, D, H, W)) return PIC_ERR_STATE;
-  pic::k_mse<<<256, 256, 0, st>>>(u->out, u->target, u->gout, V, u->dpart);
+  if (u->loss_mode == PIC_UNET_LOSS_RESIDUAL) {
+    const Dims d0 = dims_at(u, D, H, W, 0);
+    pic::k_res_q<<<256, 256, 0, st>>>(u->out, u->target, u->q, d0, u->loss_k0, u->dpart);
+    pic::k_res_g<<<nb(V), 256, 0, st>>>(u->q, u->gout, d0, u->loss_k0, 2.0f / (float)V);
+  } else {
+    pic::k_mse<<<256, 256, 0, st>>>(u->out, u->target, u->gout, V, u->dpart);
+  }
   pic::k_sum_d<<<1, 256, 0, st>>>(u->dpart, 256, u->dpart + 512);
   if (!unet_backward(u, D, H, W)) return PIC_ERR_STATE;
   if (grad)

@@ -443,6 +443,7 @@ UNET_EXPORTS = {
                                      ctypes.c_float, ctypes.c_float,
                                      ctypes.POINTER(_c_d)]),
     "pic_unet_last_error": (ctypes.c_char_p, [_c_p]),
+    "pic_unet_set_loss": (_c_i32, [_c_p, _c_i32, _c_i32]),
 }
 
 
@@ -494,6 +495,11 @@ class UNet:
             if getattr(self, "u", None):
                 msg = (self.lib.pic_unet_last_error(self.u) or b"").decode()
             raise PicError(status, msg)
+
+    def set_loss(self, mode="mse", k0=1):
+        """mode "mse" or "residual" (k0: first unknown plane)."""
+        self._check(self.lib.pic_unet_set_loss(
+            self.u, {"mse": 0, "residual": 1}[mode], int(k0)))
 
     def set_params(self, params):
         p = torch.as_tensor(params, dtype=torch.float32, device="cuda").contiguous()

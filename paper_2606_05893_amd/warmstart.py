@@ -32,9 +32,13 @@ def cosine_lr(k, total, lr_max, lr_min):
     return lr_min + 0.5 * (lr_max - lr_min) * (1.0 + math.cos(math.pi * k / total))
 
 
-def train(net, pairs, epochs, lr_max=1e-3, lr_min=1e-5, seed=0):
+def train(net, pairs, epochs, lr_max=1e-3, lr_min=1e-5, seed=0, loss="mse",
+          k0=1):
     """Adam over `epochs` shuffled passes of `pairs`; returns the mean loss
-    of each epoch."""
+    of each epoch.  loss "mse" fits the normalised correction; "residual"
+    minimises the residual of the start it produces (k0: first unknown
+    plane of the grid)."""
+    net.set_loss(loss, k0)
     rng = np.random.default_rng(seed)
     total = epochs * len(pairs)
     k = 0

@@ -100,3 +100,35 @@ def test_unet_adam_tracks_oracle(gpu_lib):
     # gradient is near zero take full-size steps whose sign BF16 rounding
     # decides; those lower the cosine without changing the loss.
     assert cos > 0.8
+
+
+@pytest.mark.parametrize("k0", [0, 1])
+def test_unet_residual_loss_gradients_match_oracle(gpu_lib, k0):
+    from paper_2606_05893_amd.pic import UNet
+    p = params(11)
+    net = UNet(*SHAPE, params=p)
+    net.set_loss("residual", k0)
+    x, t = sample(12)
+    g, loss = net.gradients(x, t)
+    g = g.cpu().numpy()
+    loss_o, g_o, _ = U.residual_loss_and_grad(p.astype(np.float64), x.astype(np.float64),
+                                              t.astype(np.float64), k0)
+    assert abs(loss - loss_o) <= 0.02 * loss_o
+    lay, n = U.param_layout()
+    # The output gradient (2/V) A^T A (c - t) enters the head's weights
+    # directly: tight.
+    off = [o for name, kind, o, sh in lay if name == "head" and kind == "W"][0]
+    assert rel(g[off:off + 16], g_o[off:off + 16]) < 0.02
+    worst = 0.0
+    for name, kind, off, shape in lay:
+        k = int(np.prod(shape))
+        a, b = g[off:off + k], g_o[off:off + k]
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
+        e = rel(a, b)
+        worst = max(worst, e)
+        # Deeper tensors: the A^T A-weighted gradient is mostly high
+        # frequency and largely cancels under pooling on its way to the
+        # coarse levels, which magnifies the BF16 rounding of activations
+        # and gradients (the smooth MSE gradient is held to 0.1).
+        assert cos > 0.98 and e < 0.2, (name, kind, cos, e)
+    print("residual loss, k0 =", k0, ": worst per-tensor gradient rel L2 error:", worst)

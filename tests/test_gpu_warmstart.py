@@ -104,10 +104,12 @@ def test_warm_start_rejects_bad_grid(gpu_lib):
         gpu.set_warm_start("unet", net)
 
 
-def test_trained_network_gains_on_held_out_seed(gpu_lib):
-    """Pairs from runs with preload seeds 1-3 train the network; on seed 0
-    the learned start is compared with the previous potential: residual of
-    the start, V-cycles and step time, every solve finishing at 1e-10."""
+@pytest.mark.parametrize("loss", ["mse", "residual"])
+def test_trained_network_gains_on_held_out_seed(gpu_lib, loss):
+    """Pairs from runs with preload seeds 1-3 train the network (fitting the
+    normalised correction, or minimising the residual of the start); on
+    seed 0 the learned start is compared with the previous potential:
+    residual of the start, V-cycles, every solve finishing at 1e-10."""
     from paper_2606_05893_amd import warmstart as WS
     p = case()
     pairs = []
@@ -119,7 +121,7 @@ def test_trained_network_gains_on_held_out_seed(gpu_lib):
         del gpu
     net = net_for(p, W.unet_init(0))
     t0 = time.perf_counter()
-    losses = WS.train(net, pairs, epochs=6, lr_max=1e-3, lr_min=1e-5)
+    losses = WS.train(net, pairs, epochs=6, lr_max=1e-3, lr_min=1e-5, loss=loss)
     t_train = time.perf_counter() - t0
     runs = {}
     for mode in ("prev", "unet"):
@@ -142,11 +144,17 @@ def test_trained_network_gains_on_held_out_seed(gpu_lib):
     rejected = sum(d["warm_rejected"] for d in unet)
     vc_prev = sum(d["vcycles"] for d in prev)
     vc_unet = sum(d["vcycles"] for d in unet)
-    print({"epoch_loss": losses, "train_s": t_train, "pairs": len(pairs),
+    print({"loss": loss, "epoch_loss": losses, "train_s": t_train, "pairs": len(pairs),
            "start_rel_residual_prev": r0_prev, "start_rel_residual_unet": r0_unet,
            "mean_warm_ratio": ratio, "rejected": rejected,
            "vcycles_prev": vc_prev, "vcycles_unet": vc_unet})
     assert losses[-1] < losses[0]
     assert rejected <= 5
-    assert ratio < 0.7
-    assert vc_unet <= vc_prev
+    if loss == "mse":
+        assert ratio < 0.7
+        assert vc_unet <= vc_prev
+    else:
+        # Minimising the start's residual itself: about a tenth of the
+        # previous potential's, one V-cycle saved per step.
+        assert ratio < 0.3
+        assert vc_unet <= vc_prev - 10
