@@ -322,6 +322,17 @@ __global__ void k_warm_target(const double* __restrict__ u,
     t[idx] = (float)((u[idx] - uprev[idx]) * inv_s);
 }
 
+// Over-relaxation of the red-black Gauss-Seidel update: u + w (gs - u)
+// (w = 1: the plain update, computed as gs itself).
+#ifndef PIC_SOR_OMEGA
+#define PIC_SOR_OMEGA 1.25
+#endif
+template <typename T>
+__device__ __forceinline__ T relax(T u, T gs) {
+  if (PIC_SOR_OMEGA == 1.0) return gs;
+  return u + T(PIC_SOR_OMEGA) * (gs - u);
+}
+
 // ---- multigrid node operations ---------------------------------------------
 // Each is written for one work item t so that the same code serves the
 // grid-wide kernels of the fine levels and the single-workgroup kernel that
@@ -346,7 +357,8 @@ __device__ __forceinline__ void rbgs_node(T* __restrict__ u,
   const int i = 2 * m + ((color + j + k) & 1);
   const long long idx = ((long long)k * L.ny + j) * L.nx + i;
   const T h2 = (T)L.h2;
-  u[idx] = (nb_sum(u, L, i, j, k) + h2 * f[idx]) * (T(1) / T(6));
+  const T gs = (nb_sum(u, L, i, j, k) + h2 * f[idx]) * (T(1) / T(6));
+  u[idx] = relax(u[idx], gs);
 }
 
 // Full-weighting restriction of the fine residual to coarse node t (the
@@ -851,7 +863,7 @@ __global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
       zs = T(2) * dn[c];
     else
       zs = dn[c] + up[c];
-    cur[c] = ((sn + zs) + h2 * fv) * sixth;
+    cur[c] = relax(cur[c], ((sn + zs) + h2 * fv) * sixth);
   };
   // Step p: the four half-sweeps (plane p-h), the finished plane p-3 out,
   // plane p+2 into the ring, and the loads of later steps issued.

@@ -155,6 +155,9 @@ def test_trained_network_gains_on_held_out_seed(gpu_lib, loss):
         assert vc_unet <= vc_prev
     else:
         # Minimising the start's residual itself: about a tenth of the
-        # previous potential's, one V-cycle saved per step.
+        # previous potential's.  Whether that saves a V-cycle depends on
+        # where the multigrid's convergence puts the 1e-10 threshold (with
+        # the over-relaxed smoother it converges about 100x per cycle); it
+        # never costs one.
         assert ratio < 0.3
-        assert vc_unet <= vc_prev - 10
+        assert vc_unet <= vc_prev
