@@ -1277,34 +1277,41 @@ __global__ void __launch_bounds__(kT) k_mcc(
 // launches the rounds for the list's capacity; short lists make the extra
 // rounds plain copies.
 __global__ void __launch_bounds__(1024) k_sort_chunks(
-    Rec* __restrict__ a, const unsigned long long* __restrict__ count,
-    long long cap) {
+    Rec* __restrict__ a, Rec* __restrict__ tmp,
+    const unsigned long long* __restrict__ count, long long cap) {
   __shared__ Rec s[kSmallLds];
   long long n = (long long)*count;
   if (n > cap) n = cap;
   const long long base = (long long)blockIdx.x * kSmallLds;
   if (base >= n || n <= 1) return;
-  const long long m = n - base < kSmallLds ? n - base : kSmallLds;
-  long long P = 1;
+  const int m = (int)(n - base < kSmallLds ? n - base : kSmallLds);
+  int P = 1;
   while (P < m) P <<= 1;
   Rec maxr;
   maxr.lo = ~0ull; maxr.hi = ~0u; maxr.val = 0u;
-  for (long long q = threadIdx.x; q < P; q += blockDim.x)
-    s[q] = q < m ? a[base + q] : maxr;
+  const int tid = threadIdx.x;
+  for (int q = tid; q < P; q += 1024) s[q] = q < m ? a[base + q] : maxr;
   __syncthreads();
-  for (long long k = 2; k <= P; k <<= 1)
-    for (long long j = k >> 1; j > 0; j >>= 1) {
-      for (long long q = threadIdx.x; q < P; q += blockDim.x) {
-        const long long o = q ^ j;
-        if (o > q) {
-          const bool up = (q & k) == 0;
-          const Rec x = s[q], y = s[o];
-          if (up ? rec_less(y, x) : rec_less(x, y)) { s[q] = y; s[o] = x; }
-        }
+  // Bitonic network over P keys: each stage compares the P / 2 pairs
+  // (q, q | j) with bit j of q clear, in the direction of bit k of q.
+  for (int k = 2; k <= P; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int t = tid; t < P / 2; t += 1024) {
+        const int q = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+        const int o = q | j;
+        const bool up = (q & k) == 0;
+        const Rec x = s[q], y = s[o];
+        if (up ? rec_less(y, x) : rec_less(x, y)) { s[q] = y; s[o] = x; }
       }
       __syncthreads();
     }
-  for (long long q = threadIdx.x; q < m; q += blockDim.x) a[base + q] = s[q];
+  // A list of one chunk is complete: it goes to both buffers, so the merge
+  // rounds have nothing to do whichever buffer they end in.
+  const bool single = n <= kSmallLds;
+  for (int q = tid; q < m; q += 1024) {
+    a[base + q] = s[q];
+    if (single) tmp[base + q] = s[q];
+  }
 }
 
 // One merge round: runs of width w (sorted) pairwise into runs of 2w.
@@ -1313,6 +1320,7 @@ __global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst
                               long long cap, long long w) {
   long long n = (long long)*count;
   if (n > cap) n = cap;
+  if (n <= kSmallLds) return;   // sorted by the chunk pass, in both buffers
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const long long pair = i / (2 * w);
@@ -1337,6 +1345,19 @@ __global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst
     pos = a0 + (i - a1) + (lo - a0);
   }
   dst[pos] = x;
+}
+
+// The sorted list back into its own buffer (lists longer than one chunk
+// after an odd number of merge rounds).
+__global__ void k_copy_recs(const Rec* __restrict__ src, Rec* __restrict__ dst,
+                            const unsigned long long* __restrict__ count,
+                            long long cap) {
+  long long n = (long long)*count;
+  if (n > cap) n = cap;
+  if (n <= kSmallLds) return;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
 }
 
 // Neutrals in cells that hold ionisation events.
@@ -1888,15 +1909,14 @@ void sort_records(pic_ctx* c, Rec* a, Rec* tmp,
                   const unsigned long long* count, long long cap) {
   hipStream_t st = c->stream;
   const long long nchunk = (cap + kSmallLds - 1) / kSmallLds;
-  k_sort_chunks<<<(unsigned)nchunk, 1024, 0, st>>>(a, count, cap);
+  k_sort_chunks<<<(unsigned)nchunk, 1024, 0, st>>>(a, tmp, count, cap);
   Rec* src = a;
   Rec* dst = tmp;
   for (long long w = kSmallLds; w < cap; w *= 2) {
     k_merge_round<<<nblk(cap), kT, 0, st>>>(src, dst, count, cap, w);
     Rec* t = src; src = dst; dst = t;
   }
-  if (src != a)
-    hipMemcpyAsync(a, src, (size_t)cap * sizeof(Rec), hipMemcpyDeviceToDevice, st);
+  if (src != a) k_copy_recs<<<256, kT, 0, st>>>(src, a, count, cap);
 }
 
 double qm_dt(int s, double dt) {

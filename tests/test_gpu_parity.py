@@ -281,3 +281,44 @@ def test_out_of_domain_load_rejected(gpu_lib):
     with pytest.raises(G.PicError):
         gpu.load(0, pos, vel, ids)
     assert gpu.count(0) == 9
+
+
+def test_absorbed_list_longer_than_a_sort_chunk(gpu_lib):
+    """About 20 000 electrons and ions cross the cathode in one step: the
+    cathode list (longer than one 4096-record sort chunk, so the merge
+    rounds run) comes back sorted by (species, id) and equal to the
+    oracle's, crossing points and velocities included."""
+    p = small_c2(n_e=10, n_ion=10, n_n=10)
+    p["sources"] = {}
+    p["collisions"] = dict(p["collisions"], enabled=False)
+    g = grid_of(p)
+    gpu = make(p, cap=40000, max_events=1 << 15)
+    st = O.State(g, seed=p["seed"])
+    rng = np.random.default_rng(17)
+    n0 = 0
+    for s, n, mass in ((0, 12000, 9.1093837139e-31), (2, 9000, 63.546 * 1.66053906892e-27)):
+        L = np.array([g.lx, g.ly, 0.3 * p["dx"]])
+        pos = rng.random((n, 3)) * L
+        vel = rng.standard_normal((n, 3)) * 1e3
+        vel[:, 2] = -np.abs(vel[:, 2]) - 0.5 * p["dx"] / p["dt"]   # into the cathode
+        ids = rng.permutation(np.arange(n0, n0 + n, dtype=np.uint64) * 7 + 3)
+        st.load(s, pos, vel, ids)
+        gpu.load(s, pos, vel, ids)
+        n0 += n
+    st.next_id = 10 ** 6
+    gpu.set_clock(0, 10 ** 6)
+    phi = P.solve_exact(P.add_boundary_terms(np.zeros(g.shape), g), g)
+    gpu.set_phi(phi)
+    ab_g, dg = gpu.advance(p["dt"])
+    ab_o, do = O.advance(st, p, O.efield(phi, g), p["dt"])
+    n = ab_g["n"]
+    assert n == ab_o["id"].size and n > 4096 * 4
+    sp = ab_g["species"].cpu().numpy().astype(np.int64)
+    ids = ab_g["id"].cpu().numpy().astype(np.uint64)
+    key = sp.astype(object) * 2 ** 64 + ids.astype(object)
+    assert all(key[i] < key[i + 1] for i in range(n - 1))
+    assert np.array_equal(sp, ab_o["species"]) and np.array_equal(ids, ab_o["id"])
+    pos_o = np.stack([ab_o[k] for k in ("x", "y", "z")], 1)
+    vel_o = np.stack([ab_o[k] for k in ("vx", "vy", "vz")], 1)
+    assert np.allclose(ab_g["pos"].cpu().numpy(), pos_o, rtol=1e-12, atol=1e-21)
+    assert np.array_equal(ab_g["vel"].cpu().numpy(), vel_o)
