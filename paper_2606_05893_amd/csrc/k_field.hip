@@ -199,10 +199,11 @@ __global__ void k_residual(const double* __restrict__ u,
   const long long nu = L.nxy * (L.k1 - L.k0 + 1);
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nu;
        t += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(t % L.nx);
-    const long long r = t / L.nx;
-    const int j = (int)(r % L.ny);
-    const int k = L.k0 + (int)(r / L.ny);
+    const unsigned tt = (unsigned)t;
+    const int i = (int)(tt % (unsigned)L.nx);
+    const unsigned r = tt / (unsigned)L.nx;
+    const int j = (int)(r % (unsigned)L.ny);
+    const int k = L.k0 + (int)(r / (unsigned)L.ny);
     const long long idx = ((long long)k * L.ny + j) * L.nx + i;
     const double au = 6.0 * u[idx] - nb_sum(u, L, i, j, k);
     const double res = f[idx] - au;
@@ -349,11 +350,11 @@ __device__ __forceinline__ void rbgs_node(T* __restrict__ u,
                                           const T* __restrict__ f,
                                           const LevelC& L, int color,
                                           long long t) {
-  const int half = L.nx >> 1;
-  const int m = (int)(t % half);
-  const long long r = t / half;
-  const int j = (int)(r % L.ny);
-  const int k = L.k0 + (int)(r / L.ny);
+  const unsigned half = (unsigned)(L.nx >> 1), tt = (unsigned)t;
+  const int m = (int)(tt % half);
+  const unsigned r = tt / half;
+  const int j = (int)(r % (unsigned)L.ny);
+  const int k = L.k0 + (int)(r / (unsigned)L.ny);
   const int i = 2 * m + ((color + j + k) & 1);
   const long long idx = ((long long)k * L.ny + j) * L.nx + i;
   const T h2 = (T)L.h2;
@@ -370,10 +371,11 @@ __device__ __forceinline__ void restrict_node(const T* __restrict__ uf,
                                               T* __restrict__ fc,
                                               const LevelC& F, const LevelC& Cc,
                                               long long t) {
-  const int ic = (int)(t % Cc.nx);
-  const long long r = t / Cc.nx;
-  const int jc = (int)(r % Cc.ny);
-  const int kc = (int)(r / Cc.ny);
+  const unsigned tt = (unsigned)t;
+  const int ic = (int)(tt % (unsigned)Cc.nx);
+  const unsigned r = tt / (unsigned)Cc.nx;
+  const int jc = (int)(r % (unsigned)Cc.ny);
+  const int kc = (int)(r / (unsigned)Cc.ny);
   uc[t] = T(0);
   if (kc < Cc.k0 || kc > Cc.k1) {
     fc[t] = T(0);
@@ -407,10 +409,12 @@ __device__ __forceinline__ void prolong_node(T* __restrict__ uf,
                                              const T* __restrict__ uc,
                                              const LevelC& F, const LevelC& Cc,
                                              long long t) {
-  const int i = (int)(t % F.nx);
-  const long long r = t / F.nx;
-  const int j = (int)(r % F.ny);
-  const int k = F.k0 + (int)(r / F.ny);
+  // Node indices fit 32 bits: 32-bit division is much cheaper than 64.
+  const unsigned tt = (unsigned)t;
+  const int i = (int)(tt % (unsigned)F.nx);
+  const unsigned r = tt / (unsigned)F.nx;
+  const int j = (int)(r % (unsigned)F.ny);
+  const int k = F.k0 + (int)(r / (unsigned)F.ny);
   int ia[2], ja[2], ka[2];
   T wa[2], wb[2], wc[2];
   int na, nb, nc;
@@ -668,10 +672,11 @@ __global__ void k_efield(const double* __restrict__ phi,
   const long long n = L.nxy * (L.nz + 1);
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
        idx < n; idx += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(idx % L.nx);
-    const long long r = idx / L.nx;
-    const int j = (int)(r % L.ny);
-    const int k = (int)(r / L.ny);
+    const unsigned ui = (unsigned)idx;
+    const int i = (int)(ui % (unsigned)L.nx);
+    const unsigned r = ui / (unsigned)L.nx;
+    const int j = (int)(r % (unsigned)L.ny);
+    const int k = (int)(r / (unsigned)L.ny);
     const long long row = idx - i;
     const int im = i ? i - 1 : L.nx - 1, ip = i + 1 < L.nx ? i + 1 : 0;
     const int jm = j ? j - 1 : L.ny - 1, jp = j + 1 < L.ny ? j + 1 : 0;
@@ -714,9 +719,8 @@ inline unsigned nblocks(long long n, int t = kThreads) {
 // 3-h nodes in x, y and z (the halo it leaves valid for h+1), so the final
 // values of the owned nodes are exactly those of four grid-wide colour
 // launches; the widened nodes are recomputed by the neighbouring workgroups
-// from the same old values.  The next-but-one plane of u and the f operands
-// of the next step are loaded into registers while the current step
-// computes.  HBM traffic per pass: u and f read and u written once, against
+// from the same old values.  The u plane and the f operands two steps
+// ahead are loaded into registers while the current step computes.  HBM traffic per pass: u and f read and u written once, against
 // about four times that for separate launches.
 constexpr int kSX = 32, kSY = 8, kSH = 4;
 constexpr int kSPX = kSX + 2 * kSH, kSPY = kSY + 2 * kSH;
@@ -790,7 +794,7 @@ __global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
   // load is issued unconditionally (clamped to a valid node, its result
   // unused where it is not needed), so the compiler waits for exactly the
   // loads a use depends on while later ones stay in flight: the u plane of
-  // step p+4 and the f operands of step p+3 are loaded during step p.
+  // step p+4 and the f operands of step p+2 are loaded during step p.
   int loff[kSLoad];
 #pragma unroll
   for (int r = 0; r < kSLoad; ++r) {
@@ -823,7 +827,7 @@ __global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
   auto clampz = [&](int z) { return z < 0 ? 0 : (z > L.nz ? L.nz : z); };
 
   T pu[2][kSLoad];
-  T fs[3][kNS];
+  T fs[2][kNS];
   auto fetch_u = [&](auto U, int z) {
     constexpr int iu = decltype(U)::value;
     const long long base = (long long)clampz(z) * L.nxy;
@@ -890,7 +894,7 @@ __global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
     }
     commit_u(U, p + 2);
     fetch_u(U, p + 4);
-    fetch_f(F, p + 3);
+    fetch_f(F, p + 2);
     __syncthreads();
   };
 
@@ -905,21 +909,12 @@ __global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
   fetch_u(IC<1>(), p0 + 3);
   fetch_f(IC<0>(), p0);
   fetch_f(IC<1>(), p0 + 1);
-  fetch_f(IC<2>(), p0 + 2);
   __syncthreads();
-  // Register sets rotate with period 2 (u) and 3 (f): unrolled by 6.
-  for (int p = p0; p <= p1; p += 6) {
+  // Register sets alternate with period 2: unrolled by 2.
+  for (int p = p0; p <= p1; p += 2) {
     step(IC<0>(), IC<0>(), p);
     if (p + 1 > p1) break;
     step(IC<1>(), IC<1>(), p + 1);
-    if (p + 2 > p1) break;
-    step(IC<0>(), IC<2>(), p + 2);
-    if (p + 3 > p1) break;
-    step(IC<1>(), IC<0>(), p + 3);
-    if (p + 4 > p1) break;
-    step(IC<0>(), IC<1>(), p + 4);
-    if (p + 5 > p1) break;
-    step(IC<1>(), IC<2>(), p + 5);
   }
 }
 
