@@ -105,7 +105,9 @@ constexpr int KP(int cin) { return (27 * cin + 63) / 64 * 64; }
 // of 16 (x) x TY x TZ voxels; per slice of 16 input channels it stages the
 // tile's halo (18 x (TY+2) x (TZ+2) voxels, 32 B each, x and y periodic, z
 // zero-padded) in LDS, so an input voxel is read from memory about twice
-// per layer instead of once per tap.  A K-chunk of 32 is two taps x 16
+// per layer instead of once per tap; the two 8-channel halves of a voxel sit
+// in separate LDS planes so that 16 lanes reading consecutive voxels touch
+// 256 contiguous bytes.  A K-chunk of 32 is two taps x 16
 // channels (lane group g = lane / 16: tap 2c + g / 2, channels 8 (g % 2) ..
 // +7); the A operand comes from LDS, the B operand (weights) from the
 // cache.  Each wave owns MT rows of 16 voxels and all COUT / 16 column
@@ -128,7 +130,8 @@ __global__ void __launch_bounds__(256) k_conv3t(const bf16* __restrict__ in,
   __shared__ uint4 lds[HV * 2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ntx = (d.W + TX - 1) / TX, nty = (d.H + TY - 1) / TY;
-  int bi = blockIdx.x;
+  // Neighbouring tiles share halo voxels: keep them on one XCD's L2.
+  int bi = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tx = bi % ntx;
   bi /= ntx;
   const int ty = bi % nty, tz = bi / nty;
@@ -154,7 +157,7 @@ __global__ void __launch_bounds__(256) k_conv3t(const bf16* __restrict__ in,
         const size_t gv = ((size_t)gz * d.H + gy) * d.W + gx;
         val = ld16(in + gv * CIN + sl * 16 + hh * 8);
       }
-      lds[q] = val;
+      lds[hh * HV + hv] = val;
     }
     __syncthreads();
     // Chunks 0..12 hold two taps; chunk 13 holds tap 26 and padding.
@@ -174,7 +177,7 @@ __global__ void __launch_bounds__(256) k_conv3t(const bf16* __restrict__ in,
         const int hv = ((lz + oz) * HY + (ly + oy)) * HX + rl + ox;
         bf16x8 a = zero8();
         if (tv) {
-          const uint4 w = lds[hv * 2 + half];
+          const uint4 w = lds[half * HV + hv];
           __builtin_memcpy(&a, &w, 16);
         }
 #pragma unroll
