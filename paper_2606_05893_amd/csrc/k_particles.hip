@@ -153,6 +153,7 @@ __global__ void k_begin(Counters* dc, unsigned long long n0,
     dc->cathode[s] = 0; dc->anode[s] = 0; dc->kinetic[s] = 0.0;
     dc->sorted_n[s] = 0;
   }
+  dc->n_dead = dc->n_holes = dc->n_movers = 0;
   dc->n_cand = dc->n_elastic = dc->n_events = dc->n_ok = 0;
   dc->n_over = dc->n_near = dc->n_ab = dc->n_ncand = 0;
   dc->n_tail_cand = 0;
@@ -1597,8 +1598,12 @@ __device__ __forceinline__ int hist_slot(unsigned* hk, unsigned key) {
 }
 
 // Unbinned tail (particles appended this step, e.g. a source's neutrals
-// piling into a few tiles): per chunk of kNChunk, tile counts aggregated in
-// an LDS hash table, one global atomic per distinct tile.
+// piling into a few tiles, or a whole population after a load): per chunk
+// of kLChunk, tile counts aggregated in an LDS hash table, one global
+// atomic per distinct tile.  The chunk is small so that a tail of ~1e5
+// particles still spreads over all CUs.
+constexpr int kLChunk = 1024;
+
 __global__ void __launch_bounds__(kT) k_bin_hist_list(
     const uint32_t* __restrict__ key, unsigned* __restrict__ cnt, GridC g,
     long long first, const unsigned long long* __restrict__ np) {
@@ -1607,8 +1612,8 @@ __global__ void __launch_bounds__(kT) k_bin_hist_list(
   hist_clear(hk, hc);
   __syncthreads();
   const long long n = (long long)*np;
-  const long long b0 = first + blockIdx.x * (long long)kNChunk;
-  for (int r = 0; r < kNChunk; r += kT) {
+  const long long b0 = first + blockIdx.x * (long long)kLChunk;
+  for (int r = 0; r < kLChunk; r += kT) {
     const long long i = b0 + r + threadIdx.x;
     if (i >= n) break;
     const uint32_t k = key[i];
@@ -1727,7 +1732,7 @@ __global__ void __launch_bounds__(kT) k_bin_scatter_tile(
 // per distinct tile with a single global atomic, and each particle takes
 // the next rank in its tile's range (particles whose tile found no hash
 // slot take a global slot directly).
-constexpr int kPerThread = kNChunk / kT;
+constexpr int kPerThread = kLChunk / kT;
 
 template <class PT>
 __global__ void __launch_bounds__(kT) k_bin_scatter_list(
@@ -1740,7 +1745,7 @@ __global__ void __launch_bounds__(kT) k_bin_scatter_list(
   hist_clear(hk, hc);
   __syncthreads();
   const long long n = (long long)*np;
-  const long long b0 = first + blockIdx.x * (long long)kNChunk;
+  const long long b0 = first + blockIdx.x * (long long)kLChunk;
   int sl[kPerThread];
   unsigned pos[kPerThread];
 #pragma unroll
@@ -1938,9 +1943,9 @@ PT cur(pic_ctx* c, int s) { return buf<PT>(c, s, c->cur[s]); }
 
 template <class PT>
 void deposit_t(pic_ctx* c) {
-  k_deposit<PT><<<(unsigned)c->nch_bound[0], kT, 0, c->stream>>>(
-      cur<PT>(c, 0), cur<PT>(c, 2), ts_cur(c, 0), ts_cur(c, 2), c->chunks[0],
-      c->cstart[0] + c->ntiles, c->acc, c->g);
+  k_deposit<PT><<<(unsigned)c->nch_bound, kT, 0, c->stream>>>(
+      cur<PT>(c, 0), cur<PT>(c, 2), ts_cur(c, 0), ts_cur(c, 2), c->chunks,
+      c->cstart + c->ntiles, c->acc, c->g);
 }
 
 // Queue, disk, sphere and Fowler-Nordheim particles, ids in that order.
@@ -2046,8 +2051,8 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.pi = cur<Parts>(c, 2);
   A.tse = ts_cur(c, 0);
   A.tsi = ts_cur(c, 2);
-  A.chunks = c->chunks[0];
-  A.nchunks = c->cstart[0] + nt;
+  A.chunks = c->chunks;
+  A.nchunks = c->cstart + nt;
   A.keye = c->key[0];
   A.keyi = c->key[2];
   A.qm_e = qm_dt(0, dt);
@@ -2062,7 +2067,7 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.ab_cap = ab_cap;
   A.part_e = part_e;
   A.part_i = part_i;
-  k_push_tile<<<(unsigned)c->nch_bound[0], kT, 0, st>>>(A, c->E, nn, c->g, m,
+  k_push_tile<<<(unsigned)c->nch_bound, kT, 0, st>>>(A, c->E, nn, c->g, m,
                                                          step, seed, c->dc);
   tmark(c, PIC_PH_PUSH_ELECTRON, false);
   tmark(c, PIC_PH_PUSH_ION, true);
@@ -2109,8 +2114,8 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.pi = cur<PartsM>(c, 2);
   A.tse = ts_cur(c, 0);
   A.tsi = ts_cur(c, 2);
-  A.chunks = c->chunks[0];
-  A.nchunks = c->cstart[0] + nt;
+  A.chunks = c->chunks;
+  A.nchunks = c->cstart + nt;
   A.keye = c->key[0];
   A.keyi = c->key[2];
   A.qm_e = (float)qm_dt(0, dt);
@@ -2125,7 +2130,7 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.ab_cap = ab_cap;
   A.part_e = part_e;
   A.part_i = part_i;
-  k_push_tile_m<<<(unsigned)c->nch_bound[0], kT, 0, st>>>(A, E, nn, c->g, m,
+  k_push_tile_m<<<(unsigned)c->nch_bound, kT, 0, st>>>(A, E, nn, c->g, m,
                                                            step, seed, c->dc);
   tmark(c, PIC_PH_PUSH_ELECTRON, false);
   tmark(c, PIC_PH_PUSH_ION, true);
@@ -2161,10 +2166,10 @@ void push_collide_t(pic_ctx* c, double dt) {
     push_mixed(c, dt, m, part_e, part_i, part_l, nbi, nbe);
   else
     push_fp64(c, dt, m, part_e, part_i, part_l, nbi, nbe);
-  const long long nch = c->nch_bound[0];
-  k_sum_partials<<<1, 1024, 0, st>>>(part_i, nch, c->cstart[0] + nt, part_l,
+  const long long nch = c->nch_bound;
+  k_sum_partials<<<1, 1024, 0, st>>>(part_i, nch, c->cstart + nt, part_l,
                                      nbi, 0.5 * kMcu, &c->dc->kinetic[2]);
-  k_sum_partials<<<1, 1024, 0, st>>>(part_e, nch, c->cstart[0] + nt,
+  k_sum_partials<<<1, 1024, 0, st>>>(part_e, nch, c->cstart + nt,
                                      part_l + nbi, nbe, 0.5 * kMe,
                                      &c->dc->kinetic[0]);
   const long long cap = c->cfg.max_events;
@@ -2172,7 +2177,7 @@ void push_collide_t(pic_ctx* c, double dt) {
   if (m.enabled) {
     k_mcc<PT><<<(unsigned)(nch + 1), kT, 0, st>>>(
         cur<PT>(c, 0), c->key[0], c->cand, ts_cur(c, 0), c->cand_cnt,
-        c->chunks[0], c->cstart[0] + nt, c->n_binned[0], m, step, seed, c->ev,
+        c->chunks, c->cstart + nt, c->n_binned[0], m, step, seed, c->ev,
         c->flag, cap, c->el_cnt, c->dc);
     sort_records(c, c->ev, c->rec_tmp, &c->dc->n_events, cap);
     k_neutral_cands<PT><<<nblk(bound(c, 1)), kT, 0, st>>>(
@@ -2187,7 +2192,7 @@ void push_collide_t(pic_ctx* c, double dt) {
     k_ionise_commit<<<1, 1024, 0, st>>>(c->dc, c->ev, c->flag, cap,
                                         c->cfg.capacity[0], c->cfg.capacity[2],
                                         c->el_cnt, c->cand_cnt,
-                                        c->cstart[0] + nt);
+                                        c->cstart + nt);
     c->n[0] += cap;  // bound: secondaries
     c->n[2] += cap;
   }
@@ -2203,21 +2208,25 @@ void push_collide_t(pic_ctx* c, double dt) {
 
 // Bin one species by tile into the other buffer (removing dead particles):
 // destination counts from the binned ranges (per chunk) and the appended
-// tail (per particle), an exclusive scan, then the scatter.
+// tail (per particle), an exclusive scan, then the scatter.  The neutrals
+// keep no tile ranges between passes (they are compacted in place), so all
+// of them bin as one tail.
 template <class PT>
 void bin_species_t(pic_ctx* c, int s) {
   hipStream_t st = c->stream;
   const long long nt = c->ntiles;
+  const bool tiled = s != 1;
   uint32_t* ts_old = ts_cur(c, s);
   uint32_t* ts_new = c->tsb[s][c->tcur[s] ^ 1];
+  const long long first = tiled ? c->n_binned[s] : 0;
   hipMemsetAsync(c->tile_cursor, 0, (nt + 1) * sizeof(unsigned), st);
-  const int L = s == 1 ? 1 : 0;     // chunk list of the species
-  k_bin_hist_tile<<<(unsigned)c->nch_bound[L], kT, 0, st>>>(
-      c->key[s], ts_old, c->chunks[L], c->cstart[L] + nt, c->tile_cursor, c->g);
-  const long long tail = std::max(0ll, bound(c, s) - c->n_binned[s]);
+  if (tiled)
+    k_bin_hist_tile<<<(unsigned)c->nch_bound, kT, 0, st>>>(
+        c->key[s], ts_old, c->chunks, c->cstart + nt, c->tile_cursor, c->g);
+  const long long tail = std::max(0ll, bound(c, s) - first);
   if (tail > 0)
-    k_bin_hist_list<<<(unsigned)((tail + kNChunk - 1) / kNChunk), kT, 0, st>>>(
-        c->key[s], c->tile_cursor, c->g, c->n_binned[s], &c->dc->n[s]);
+    k_bin_hist_list<<<(unsigned)((tail + kLChunk - 1) / kLChunk), kT, 0, st>>>(
+        c->key[s], c->tile_cursor, c->g, first, &c->dc->n[s]);
   const long long nsb = (nt + 1 + kScanPer - 1) / kScanPer;
   k_scan_blocks<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt, c->scan_block);
   k_scan1<<<1, 1024, 0, st>>>(c->scan_block, c->scan_block + nsb + 1, nsb);
@@ -2225,16 +2234,137 @@ void bin_species_t(pic_ctx* c, int s) {
                                              c->scan_block + nsb + 1, ts_new,
                                              c->tile_cursor);
   const int o = c->cur[s] ^ 1;
-  k_bin_scatter_tile<PT><<<(unsigned)c->nch_bound[L], kT, 0, st>>>(
-      cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], ts_old, c->chunks[L],
-      c->cstart[L] + nt, c->tile_cursor, c->g);
+  if (tiled)
+    k_bin_scatter_tile<PT><<<(unsigned)c->nch_bound, kT, 0, st>>>(
+        cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], ts_old, c->chunks,
+        c->cstart + nt, c->tile_cursor, c->g);
   if (tail > 0)
-    k_bin_scatter_list<PT><<<(unsigned)((tail + kNChunk - 1) / kNChunk), kT, 0, st>>>(
+    k_bin_scatter_list<PT><<<(unsigned)((tail + kLChunk - 1) / kLChunk), kT, 0, st>>>(
         cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], c->tile_cursor, c->g,
-        c->n_binned[s], &c->dc->n[s]);
+        first, &c->dc->n[s]);
   k_set_count<<<1, 1, 0, st>>>(c->dc, s, ts_new, nt);
   c->cur[s] = o;
   c->tcur[s] ^= 1;
+}
+
+// In-place removal of the dead neutrals (key kDead: ionised or absorbed).
+// With n entries of which D are dead, the dead ones below n - D (holes) and
+// the live ones at or above it (movers) are equally many; the j-th mover in
+// list order fills the j-th hole.  Three light passes over the keys and a
+// copy of the movers replace the full scatter of a binning pass.
+// Each workgroup scans kCChunk keys (kCPer per thread, coalesced); the
+// counts are aggregated per workgroup so that the shared counters take one
+// atomic per workgroup, not one per wave.
+constexpr int kCPer = 16;
+constexpr int kCChunk = kCPer * kT;
+
+__device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
+  const int lane = lane_id();
+  return lane ? (unsigned)__popcll(mask & (~0ull >> (64 - lane))) : 0u;
+}
+
+__global__ void __launch_bounds__(kT) k_count_dead(
+    const uint32_t* __restrict__ key, Counters* dc) {
+  __shared__ unsigned sw[kT / 64];
+  const long long n = (long long)dc->n[1];
+  const long long b0 = blockIdx.x * (long long)kCChunk;
+  if (b0 >= n) return;
+  unsigned d = 0;  // wave-uniform
+#pragma unroll
+  for (int r = 0; r < kCPer; ++r) {
+    const long long i = b0 + r * kT + threadIdx.x;
+    const uint32_t k = key[i < n ? i : n - 1];
+    d += (unsigned)__popcll(__ballot(i < n && k == kDead));
+  }
+  if (lane_id() == 0) sw[threadIdx.x / 64] = d;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned t = 0;
+    for (int w = 0; w < kT / 64; ++w) t += sw[w];
+    if (t) atomicAdd(&dc->n_dead, (unsigned long long)t);
+  }
+}
+
+__global__ void __launch_bounds__(kT) k_compact_lists(
+    const uint32_t* __restrict__ key, uint32_t* __restrict__ holes,
+    uint32_t* __restrict__ movers, Counters* dc) {
+  __shared__ unsigned sh[kT / 64], sm[kT / 64];
+  __shared__ unsigned long long base[2];
+  const long long n = (long long)dc->n[1];
+  const long long keep = n - (long long)dc->n_dead;
+  const long long b0 = blockIdx.x * (long long)kCChunk;
+  if (b0 >= n || keep == n) return;
+  unsigned long long mh[kCPer], mm[kCPer];
+  unsigned th = 0, tm = 0;  // wave-uniform
+#pragma unroll
+  for (int r = 0; r < kCPer; ++r) {
+    const long long i = b0 + r * kT + threadIdx.x;
+    const bool dead = key[i < n ? i : n - 1] == kDead;
+    mh[r] = __ballot(i < n && dead && i < keep);
+    mm[r] = __ballot(i < n && !dead && i >= keep);
+    th += (unsigned)__popcll(mh[r]);
+    tm += (unsigned)__popcll(mm[r]);
+  }
+  const int w = threadIdx.x / 64;
+  if (lane_id() == 0) {
+    sh[w] = th;
+    sm[w] = tm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned h = 0, m = 0;
+    for (int q = 0; q < kT / 64; ++q) {
+      const unsigned a = sh[q], b = sm[q];
+      sh[q] = h;
+      sm[q] = m;
+      h += a;
+      m += b;
+    }
+    base[0] = h ? atomicAdd(&dc->n_holes, (unsigned long long)h) : 0ull;
+    base[1] = m ? atomicAdd(&dc->n_movers, (unsigned long long)m) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long oh = base[0] + sh[w], om = base[1] + sm[w];
+#pragma unroll
+  for (int r = 0; r < kCPer; ++r) {
+    const uint32_t i = (uint32_t)(b0 + r * kT + threadIdx.x);
+    if ((mh[r] >> lane_id()) & 1ull) holes[oh + lanes_below(mh[r])] = i;
+    if ((mm[r] >> lane_id()) & 1ull) movers[om + lanes_below(mm[r])] = i;
+    oh += (unsigned)__popcll(mh[r]);
+    om += (unsigned)__popcll(mm[r]);
+  }
+}
+
+template <class PT>
+__global__ void k_compact_move(PT p, uint32_t* __restrict__ key,
+                               const uint32_t* __restrict__ holes,
+                               const uint32_t* __restrict__ movers,
+                               Counters* dc) {
+  // The two lists are equally long; the minimum only guards the reads.
+  const long long h = (long long)min(dc->n_holes, dc->n_movers);
+  for (long long j = blockIdx.x * (long long)blockDim.x + threadIdx.x; j < h;
+       j += (long long)gridDim.x * blockDim.x) {
+    const uint32_t from = movers[j], to = holes[j];
+    Acc<PT>::copy(p, from, p, to);
+    key[to] = key[from];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const unsigned long long k = dc->n[1] - dc->n_dead;
+    dc->n[1] = k;
+    dc->sorted_n[1] = k;
+  }
+}
+
+template <class PT>
+void compact_neutrals_t(pic_ctx* c) {
+  hipStream_t st = c->stream;
+  const long long nb = (bound(c, 1) + kCChunk - 1) / kCChunk;
+  uint32_t* holes = c->cmp_idx;
+  uint32_t* movers = c->cmp_idx + c->cfg.capacity[1];
+  k_count_dead<<<(unsigned)nb, kT, 0, st>>>(c->key[1], c->dc);
+  k_compact_lists<<<(unsigned)nb, kT, 0, st>>>(c->key[1], holes, movers, c->dc);
+  k_compact_move<PT><<<1024, kT, 0, st>>>(
+      cur<PT>(c, 1), c->key[1], holes, movers, c->dc);
 }
 
 }  // namespace
@@ -2272,31 +2402,38 @@ void parts_bin_species(pic_ctx* c, int s) {
     bin_species_t<Parts>(c, s);
 }
 
-// Chunk lists of the current tile ranges: list 0 serves electrons and
-// ions together, list 1 the neutrals.  hb: host bound of the particles the
-// ranges cover (for the launch bounds).
+// Chunk list of the current tile ranges of electrons and ions (one chunk
+// covers up to kChunk of each).  hb: host bound of the particles the ranges
+// cover (for the launch bounds).
 void parts_chunks(pic_ctx* c, const long long hb[3]) {
   hipStream_t st = c->stream;
   const long long nt = c->ntiles;
   const long long nsb = (nt + 1 + kScanPer - 1) / kScanPer;
-  for (int L = 0; L < 2; ++L) {
-    const uint32_t* ta = L ? ts_cur(c, 1) : ts_cur(c, 0);
-    const uint32_t* tb = L ? nullptr : ts_cur(c, 2);
-    k_chunk_count<<<nblk(nt), kT, 0, st>>>(ta, tb, nt, c->tile_cursor);
-    k_scan_blocks<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt, c->scan_block);
-    k_scan1<<<1, 1024, 0, st>>>(c->scan_block, c->scan_block + nsb + 1, nsb);
-    k_scan_apply<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt,
-                                               c->scan_block + nsb + 1,
-                                               c->cstart[L], c->cstart[L]);
-    k_chunk_fill<<<nblk(nt), kT, 0, st>>>(c->cstart[L], nt, c->chunks[L]);
-    const long long np = L ? hb[1] : hb[0] + hb[2];
-    c->nch_bound[L] = std::min<long long>(nt + np / kChunk + 2, c->nch_cap);
-  }
+  k_chunk_count<<<nblk(nt), kT, 0, st>>>(ts_cur(c, 0), ts_cur(c, 2), nt,
+                                         c->tile_cursor);
+  k_scan_blocks<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt, c->scan_block);
+  k_scan1<<<1, 1024, 0, st>>>(c->scan_block, c->scan_block + nsb + 1, nsb);
+  k_scan_apply<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt,
+                                             c->scan_block + nsb + 1, c->cstart,
+                                             c->cstart);
+  k_chunk_fill<<<nblk(nt), kT, 0, st>>>(c->cstart, nt, c->chunks);
+  c->nch_bound = std::min<long long>(nt + (hb[0] + hb[2]) / kChunk + 2, c->nch_cap);
 }
 
+// End of a step: electrons and ions are binned by tile; the neutrals are
+// compacted in place, and binned again once the particles out of tile order
+// (moved into holes or appended since the last pass) reach half of them.
 void parts_bin(pic_ctx* c) {
   tmark(c, PIC_PH_BIN, true);
-  for (int s = 0; s < 3; ++s) parts_bin_species(c, s);
+  parts_bin_species(c, 0);
+  parts_bin_species(c, 2);
+  c->neutrals_binned = 2 * c->n_stirred >= c->n[1];
+  if (c->neutrals_binned)
+    parts_bin_species(c, 1);
+  else if (c->mixed)
+    compact_neutrals_t<PartsM>(c);
+  else
+    compact_neutrals_t<Parts>(c);
   long long hb[3];
   for (int s = 0; s < 3; ++s) hb[s] = bound(c, s);
   parts_chunks(c, hb);

@@ -156,10 +156,9 @@ size_t carve(pic_ctx* c, char* base) {
   c->cand = cv.take<uint32_t>(f.capacity[0]);
   c->cand_cnt = cv.take<uint32_t>(c->nch_cap + 1);
   c->el_cnt = cv.take<uint32_t>(c->nch_cap + 1);
-  for (int L = 0; L < 2; ++L) {
-    c->chunks[L] = cv.take<uint2>(c->nch_cap);
-    c->cstart[L] = cv.take<uint32_t>(c->ntiles + 1);
-  }
+  c->chunks = cv.take<uint2>(c->nch_cap);
+  c->cstart = cv.take<uint32_t>(c->ntiles + 1);
+  c->cmp_idx = cv.take<uint32_t>(2 * f.capacity[1]);
   c->ev = cv.take<Rec>(c->ev_cap_p2);
   c->nc = cv.take<Rec>(c->ev_cap_p2);
   c->ok = cv.take<Rec>(c->ev_cap_p2);
@@ -208,8 +207,9 @@ void derive(pic_ctx* c) {
     h2 *= 4.0;
   }
   long long maxcap = std::max(f.capacity[0], std::max(f.capacity[1], f.capacity[2]));
-  // Chunk lists: at most one chunk per tile plus one per 2048 particles.
-  c->nch_cap = c->ntiles + (f.capacity[0] + f.capacity[1] + f.capacity[2]) / 2048 + 4;
+  // Chunk list of the charged species: at most one chunk per tile plus one
+  // per 2048 particles.
+  c->nch_cap = c->ntiles + (f.capacity[0] + f.capacity[2]) / 2048 + 4;
   c->npartials = (int)(2 * c->nch_cap + 3 * (maxcap / 256 + 64) + 4096 +
                        2ll * (f.nz + 2));
   c->ev_cap_p2 = pow2_at_least(std::max<long long>(f.max_events, 2));
@@ -344,7 +344,9 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
     c->n[s] = 0;
     c->n_binned[s] = 0;
   }
-  c->nch_bound[0] = c->nch_bound[1] = 1;
+  c->nch_bound = 1;
+  c->n_stirred = 0;
+  c->neutrals_binned = false;
   c->next_id = 0;
   c->step = 0;
   c->queue_used = 0;
@@ -528,6 +530,9 @@ pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
     c->n[k] = (long long)c->hc.sorted_n[k];
     c->n_binned[k] = c->n[k];
   }
+  c->n_stirred = c->neutrals_binned
+                     ? 0
+                     : c->n_stirred + add[1] + (long long)c->hc.n_holes;
   c->next_id = c->hc.next_id;
   c->step += 1;
   collect_times(c);
@@ -636,6 +641,7 @@ pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
   if (st != PIC_OK) return st;
   c->n[s] = (long long)c->hc.sorted_n[s];
   c->n_binned[s] = c->n[s];
+  if (s == 1) c->n_stirred = 0;
   const long long hb[3] = {c->n[0], c->n[1], c->n[2]};
   parts_chunks(c, hb);
   if (c->hc.err) {
@@ -789,6 +795,7 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
     c->n[s] = (long long)c->hc.sorted_n[s];
     c->n_binned[s] = c->n[s];
   }
+  c->n_stirred = 0;
   const long long hb[3] = {c->n[0], c->n[1], c->n[2]};
   parts_chunks(c, hb);
   c->step = h.step;

@@ -59,10 +59,14 @@ struct pic_ctx {
   uint32_t* tile_cursor;     // scatter cursors
   uint32_t* scan_block;      // block sums of the tile scan
   long long n_binned[3];     // particles covered by the tile ranges
-  uint2* chunks[2];          // (tile, piece) work lists: charged, neutral
-  uint32_t* cstart[2];       // ntiles + 1 chunk offsets per list
-  long long nch_bound[2];    // host bound of the chunk counts
-  long long nch_cap;         // capacity of a chunk list
+  uint2* chunks;             // (tile, piece) work list of the charged species
+  uint32_t* cstart;          // ntiles + 1 chunk offsets
+  long long nch_bound;       // host bound of the chunk count
+  long long nch_cap;         // capacity of the chunk list
+  // Neutrals are compacted in place between full binning passes.
+  uint32_t* cmp_idx;         // holes then movers, capacity[1] each
+  long long n_stirred;       // neutrals out of tile order since the last pass
+  bool neutrals_binned;      // the last step binned them (else compacted)
 
   // Node fields.
   long long* acc;            // int64 charge units

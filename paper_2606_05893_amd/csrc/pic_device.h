@@ -259,6 +259,9 @@ struct Counters {
   unsigned long long n_ncand;       // neutrals in cells with events
   unsigned long long n_tail_cand;   // candidates among unbinned electrons
   unsigned long long sorted_n[3];   // counts after the binning pass
+  unsigned long long n_dead;        // removed neutrals (compaction)
+  unsigned long long n_holes;       // ... of them below the new count
+  unsigned long long n_movers;      // live neutrals above it (= n_holes)
   long long total_charge;
   unsigned int err;                 // sticky error bits (kErr*)
   int vcycles;

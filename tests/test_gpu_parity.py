@@ -322,3 +322,53 @@ def test_absorbed_list_longer_than_a_sort_chunk(gpu_lib):
     vel_o = np.stack([ab_o[k] for k in ("vx", "vy", "vz")], 1)
     assert np.allclose(ab_g["pos"].cpu().numpy(), pos_o, rtol=1e-12, atol=1e-21)
     assert np.array_equal(ab_g["vel"].cpu().numpy(), vel_o)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_neutral_compaction_and_rebinning_over_steps(gpu_lib, precision):
+    """Five advances in a fixed field with dense ionisation and a neutral
+    source of half the initial population per step: the neutrals are
+    compacted in place on some steps and binned again on others (once the
+    neutrals out of tile order reach half of them).  After every step the
+    particle sets by id match the oracle's (FP64: exactly, with positions
+    within 1e-12; mixed: up to collision draws that FP32 velocities move
+    across a threshold, positions within 1e-4 cells), and no id repeats."""
+    p = _advance_case(11)
+    p["precision"] = precision
+    p["sources"]["sphere"]["n"] = 1000
+    gpu = make(p)
+    g = grid_of(p)
+    st = O.State(g, seed=11)
+    pre = W.preload(p, seed=12)
+    pre[1] = tuple(a[:2000] for a in pre[1])
+    for s, (pos, vel, ids) in pre.items():
+        st.load(s, pos, vel, ids)
+        gpu.load(s, pos, vel, ids)
+    n = int(max(v[2].max() for v in pre.values())) + 1
+    st.next_id = n
+    gpu.set_clock(0, n)
+    phi = P.solve_exact(P.add_boundary_terms(np.zeros(g.shape), g), g)
+    gpu.set_phi(phi)
+    E = O.efield(phi, g)
+    ionised = 0
+    for _ in range(5):
+        _, dg = gpu.advance(p["dt"])
+        _, do = O.advance(st, p, E, p["dt"])
+        ionised += do["ionisations"]
+        for s in range(3):
+            ig, pg, _ = gpu_arrays(gpu, s)
+            io, po, _ = oracle_arrays(st.sp[s])
+            assert dg["counts"][s] == ig.size
+            assert np.unique(ig).size == ig.size, s
+            if precision == "fp64":
+                assert np.array_equal(ig, io), s
+                assert np.all(np.abs(pg - po)
+                              <= 1e-12 * np.maximum(np.abs(po), p["dx"]))
+            else:
+                common, ia, ib = np.intersect1d(ig, io, return_indices=True)
+                assert common.size >= 0.99 * io.size, (s, common.size, io.size)
+                d = np.abs(pg[ia] - po[ib])
+                for a, L in ((0, g.lx), (1, g.ly)):   # periodic x, y
+                    d[:, a] = np.minimum(d[:, a], L - d[:, a])
+                assert np.max(d) <= 1e-4 * p["dx"], s
+    assert ionised > 0
