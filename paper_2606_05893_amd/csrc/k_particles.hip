@@ -18,7 +18,11 @@ namespace pic {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kSmallLds = 4096;   // records per LDS-sorted chunk
+// Records per LDS-sorted chunk and the workgroup that sorts it.  The
+// bitonic pass is bound by LDS bandwidth (16-byte records): small chunks
+// spread a list over many CUs, at the cost of two more merge rounds.
+constexpr int kSortChunk = 1024;
+constexpr int kSortT = 256;
 constexpr int kFixedBlocks = 2048;
 
 inline unsigned nblk(long long n, int t = kT) {
@@ -1271,33 +1275,34 @@ __global__ void __launch_bounds__(kT) k_mcc(
   if (threadIdx.x == 0) el_cnt[t] = s_el;
 }
 
-// Sort of a record list by (hi, lo) (keys are unique): every 4096-record
+// Sort of a record list by (hi, lo) (keys are unique): every kSortChunk
 // chunk is sorted in LDS by its own workgroup (bitonic), then rounds of
 // pairwise merges place each record at its rank in its own run plus the
 // number of smaller keys in the partner run (binary search).  The host
-// launches the rounds for the list's capacity; short lists make the extra
-// rounds plain copies.
-__global__ void __launch_bounds__(1024) k_sort_chunks(
+// launches the rounds for the list's capacity; the rounds whose run width
+// reaches the list's length do nothing, and a last pass brings the result
+// back into the first buffer when an odd number of rounds ran.
+__global__ void __launch_bounds__(kSortT) k_sort_chunks(
     Rec* __restrict__ a, Rec* __restrict__ tmp,
     const unsigned long long* __restrict__ count, long long cap) {
-  __shared__ Rec s[kSmallLds];
+  __shared__ Rec s[kSortChunk];
   long long n = (long long)*count;
   if (n > cap) n = cap;
-  const long long base = (long long)blockIdx.x * kSmallLds;
+  const long long base = (long long)blockIdx.x * kSortChunk;
   if (base >= n || n <= 1) return;
-  const int m = (int)(n - base < kSmallLds ? n - base : kSmallLds);
+  const int m = (int)(n - base < kSortChunk ? n - base : kSortChunk);
   int P = 1;
   while (P < m) P <<= 1;
   Rec maxr;
   maxr.lo = ~0ull; maxr.hi = ~0u; maxr.val = 0u;
   const int tid = threadIdx.x;
-  for (int q = tid; q < P; q += 1024) s[q] = q < m ? a[base + q] : maxr;
+  for (int q = tid; q < P; q += kSortT) s[q] = q < m ? a[base + q] : maxr;
   __syncthreads();
   // Bitonic network over P keys: each stage compares the P / 2 pairs
   // (q, q | j) with bit j of q clear, in the direction of bit k of q.
   for (int k = 2; k <= P; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = tid; t < P / 2; t += 1024) {
+      for (int t = tid; t < P / 2; t += kSortT) {
         const int q = ((t & ~(j - 1)) << 1) | (t & (j - 1));
         const int o = q | j;
         const bool up = (q & k) == 0;
@@ -1306,13 +1311,7 @@ __global__ void __launch_bounds__(1024) k_sort_chunks(
       }
       __syncthreads();
     }
-  // A list of one chunk is complete: it goes to both buffers, so the merge
-  // rounds have nothing to do whichever buffer they end in.
-  const bool single = n <= kSmallLds;
-  for (int q = tid; q < m; q += 1024) {
-    a[base + q] = s[q];
-    if (single) tmp[base + q] = s[q];
-  }
+  for (int q = tid; q < m; q += kSortT) a[base + q] = s[q];
 }
 
 // One merge round: runs of width w (sorted) pairwise into runs of 2w.
@@ -1321,7 +1320,7 @@ __global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst
                               long long cap, long long w) {
   long long n = (long long)*count;
   if (n > cap) n = cap;
-  if (n <= kSmallLds) return;   // sorted by the chunk pass, in both buffers
+  if (w >= n) return;   // one run already
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const long long pair = i / (2 * w);
@@ -1348,14 +1347,16 @@ __global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst
   dst[pos] = x;
 }
 
-// The sorted list back into its own buffer (lists longer than one chunk
-// after an odd number of merge rounds).
+// The sorted list back into the first buffer when the merge rounds that
+// ran (those with run width below the length) were odd in number.
 __global__ void k_copy_recs(const Rec* __restrict__ src, Rec* __restrict__ dst,
                             const unsigned long long* __restrict__ count,
                             long long cap) {
   long long n = (long long)*count;
   if (n > cap) n = cap;
-  if (n <= kSmallLds) return;
+  int rounds = 0;
+  for (long long w = kSortChunk; w < n; w *= 2) ++rounds;
+  if ((rounds & 1) == 0) return;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
     dst[i] = src[i];
@@ -1913,15 +1914,15 @@ uint32_t* ts_cur(pic_ctx* c, int s) { return c->tsb[s][c->tcur[s]]; }
 void sort_records(pic_ctx* c, Rec* a, Rec* tmp,
                   const unsigned long long* count, long long cap) {
   hipStream_t st = c->stream;
-  const long long nchunk = (cap + kSmallLds - 1) / kSmallLds;
-  k_sort_chunks<<<(unsigned)nchunk, 1024, 0, st>>>(a, tmp, count, cap);
+  const long long nchunk = (cap + kSortChunk - 1) / kSortChunk;
+  k_sort_chunks<<<(unsigned)nchunk, kSortT, 0, st>>>(a, tmp, count, cap);
   Rec* src = a;
   Rec* dst = tmp;
-  for (long long w = kSmallLds; w < cap; w *= 2) {
+  for (long long w = kSortChunk; w < cap; w *= 2) {
     k_merge_round<<<nblk(cap), kT, 0, st>>>(src, dst, count, cap, w);
     Rec* t = src; src = dst; dst = t;
   }
-  if (src != a) k_copy_recs<<<256, kT, 0, st>>>(src, a, count, cap);
+  if (cap > kSortChunk) k_copy_recs<<<256, kT, 0, st>>>(tmp, a, count, cap);
 }
 
 double qm_dt(int s, double dt) {
