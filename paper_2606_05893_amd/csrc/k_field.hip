@@ -768,8 +768,19 @@ __device__ __forceinline__ HalfSlot half_slot(int tid, int s, int x0, int y0,
 template <int N>
 using IC = std::integral_constant<int, N>;
 
+// Update slots of a thread: half-sweep 0 covers up to 266 nodes (two per
+// thread), half-sweeps 1-3 at most 216 (one per thread).
+constexpr int kNS = 5;
+__host__ __device__ constexpr int slot_h(int k) { return k < 2 ? 0 : k - 1; }
+static_assert(kSR == 6, "the march below is unrolled by the ring length");
+// Ring index at step j (mod kSR) of the plane p + d.
+__host__ __device__ constexpr int ring_slot(int j, int d) {
+  return ((1 + j + d) % kSR + kSR) % kSR;
+}
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_smooth2(const T* __restrict__ uin,
                                                  T* __restrict__ uout,
                                                  const T* __restrict__ f,
                                                  LevelC L, int seg,
@@ -806,10 +817,6 @@ __global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
       loff[r] = gy * L.nx + gx;
     }
   }
-  // Update slots: half-sweep 0 covers up to 266 nodes (two per thread),
-  // half-sweeps 1-3 at most 216 (one per thread).
-  constexpr int kNS = 5;
-  constexpr int slot_h[kNS] = {0, 0, 1, 2, 3};
   HalfSlot hs[kNS];
   hs[0] = half_slot<0>(tid, 0, x0, y0, L.nx, L.ny);
   hs[1] = half_slot<0>(tid, 1, x0, y0, L.nx, L.ny);
@@ -818,103 +825,120 @@ __global__ void __launch_bounds__(256) k_smooth2(const T* __restrict__ uin,
   hs[4] = half_slot<3>(tid, 0, x0, y0, L.nx, L.ny);
 
   // Plane q takes half-sweep h when it holds unknowns and lies in h's
-  // widened z range.
-  auto active = [&](int h, int q) {
-    const int e = 3 - h;
-    return q >= L.k0 && q <= L.k1 && q >= za - e && q <= zb - 1 + e;
-  };
-  auto slot = [&](int z) { return ring[(z + 2 * kSR) % kSR]; };
+  // widened z range [za - e, zb - 1 + e], e = 3 - h.
+  int lo[4], hi[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    lo[h] = max(L.k0, za - (3 - h));
+    hi[h] = min(L.k1, zb - 1 + (3 - h));
+  }
+  auto active = [&](int h, int q) { return q >= lo[h] && q <= hi[h]; };
   auto clampz = [&](int z) { return z < 0 ? 0 : (z > L.nz ? L.nz : z); };
 
   T pu[2][kSLoad];
   T fs[2][kNS];
   auto fetch_u = [&](auto U, int z) {
     constexpr int iu = decltype(U)::value;
-    const long long base = (long long)clampz(z) * L.nxy;
+    const T* src = uin + (long long)clampz(z) * L.nxy;
 #pragma unroll
-    for (int r = 0; r < kSLoad; ++r) pu[iu][r] = uin[base + loff[r]];
+    for (int r = 0; r < kSLoad; ++r) pu[iu][r] = src[loff[r]];
   };
-  auto commit_u = [&](auto U, int z) {
+  auto commit_u = [&](auto U, auto S, int z) {
     constexpr int iu = decltype(U)::value;
     if (z < 0 || z > L.nz) return;
-    T* rr = slot(z);
+    T* rr = ring[decltype(S)::value];
 #pragma unroll
     for (int r = 0; r < kSLoad; ++r)
       if (tid + 256 * r < kSP) rr[tid + 256 * r] = pu[iu][r];
   };
   auto fetch_f = [&](auto F, int p) {
     constexpr int jf = decltype(F)::value;
+    const T* fp[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) fp[h] = f + (long long)clampz(p - h) * L.nxy;
 #pragma unroll
     for (int k = 0; k < kNS; ++k) {
-      const int q = p - slot_h[k];
+      const int q = p - slot_h(k);
       const HalfSlot& z = hs[k];
-      fs[jf][k] = f[(long long)clampz(q) * L.nxy + (((z.b + q) & 1) ? z.g1 : z.g0)];
+      fs[jf][k] = fp[slot_h(k)][((z.b + q) & 1) ? z.g1 : z.g0];
     }
   };
-  auto update = [&](int k, int q, T fv) {
+  // Update of slot k at step j of the unrolled march (plane q = p - h).
+  auto update = [&](auto K, auto J, int q, T fv) {
+    constexpr int k = decltype(K)::value, j = decltype(J)::value;
+    constexpr int h = slot_h(k);
     const HalfSlot& z = hs[k];
     if (!z.on) return;
     const int c = z.c0 + ((z.b + q) & 1);
-    T* cur = slot(q);
-    const T* dn = slot(q - 1);
-    const T* up = slot(q + 1);
+    T* cur = ring[ring_slot(j, -h)];
+    const T* dn = ring[ring_slot(j, -h - 1)];
+    const T* up = ring[ring_slot(j, 1 - h)];
     T sn = cur[c - 1] + cur[c + 1];
     sn = sn + (cur[c - kSPX] + cur[c + kSPX]);
-    T zs;
-    if (q == 0)
-      zs = T(2) * up[c];
-    else if (q == L.nz)
-      zs = T(2) * dn[c];
-    else
-      zs = dn[c] + up[c];
+    // On a Neumann face the mirror node stands in for the missing one
+    // (up + up on the cathode face, dn + dn on the anode face).
+    const T a = dn[c], b = up[c];
+    const T zs = (q == 0 ? b : a) + (q == L.nz ? a : b);
     cur[c] = relax(cur[c], ((sn + zs) + h2 * fv) * sixth);
   };
-  // Step p: the four half-sweeps (plane p-h), the finished plane p-3 out,
-  // plane p+2 into the ring, and the loads of later steps issued.
-  auto step = [&](auto U, auto F, int p) {
-    constexpr int jf = decltype(F)::value;
+  // Step p (= p0 + j modulo kSR): the four half-sweeps (plane p-h), the
+  // finished plane p-3 out, plane p+2 into the ring, and the loads of later
+  // steps issued.
+  auto step = [&](auto J, int p) {
+    constexpr int j = decltype(J)::value, jf = j & 1;
     if (active(0, p)) {
-      update(0, p, fs[jf][0]);
-      update(1, p, fs[jf][1]);
+      update(IC<0>(), J, p, fs[jf][0]);
+      update(IC<1>(), J, p, fs[jf][1]);
     }
     __syncthreads();
-    if (active(1, p - 1)) update(2, p - 1, fs[jf][2]);
+    if (active(1, p - 1)) update(IC<2>(), J, p - 1, fs[jf][2]);
     __syncthreads();
-    if (active(2, p - 2)) update(3, p - 2, fs[jf][3]);
+    if (active(2, p - 2)) update(IC<3>(), J, p - 2, fs[jf][3]);
     __syncthreads();
-    if (active(3, p - 3)) update(4, p - 3, fs[jf][4]);
+    if (active(3, p - 3)) update(IC<4>(), J, p - 3, fs[jf][4]);
     __syncthreads();
     const int q = p - 3;
     if (q >= za && q < zb) {
-      const T* r = slot(q);
+      const T* r = ring[ring_slot(j, -3)];
       const int lx = kSH + tid % kSX, ly = kSH + tid / kSX;
       const int gx = x0 + lx, gy = y0 + ly;
       if (gx < L.nx && gy < L.ny)
         uout[(long long)q * L.nxy + (long long)gy * L.nx + gx] = r[ly * kSPX + lx];
     }
-    commit_u(U, p + 2);
-    fetch_u(U, p + 4);
-    fetch_f(F, p + 2);
+    commit_u(IC<jf>(), IC<ring_slot(j, 2)>(), p + 2);
+    fetch_u(IC<jf>(), p + 4);
+    fetch_f(IC<jf>(), p + 2);
     __syncthreads();
   };
 
+  // Plane z lives in ring[(z - p0 + 1) mod kSR]; the march is unrolled by
+  // kSR, so every ring index is a constant (and the two register sets
+  // alternate with period 2, which divides kSR).
   const int p0 = za - 3, p1 = zb + 2;
   fetch_u(IC<0>(), p0 - 1);
-  commit_u(IC<0>(), p0 - 1);
+  commit_u(IC<0>(), IC<0>(), p0 - 1);
   fetch_u(IC<0>(), p0);
-  commit_u(IC<0>(), p0);
+  commit_u(IC<0>(), IC<1>(), p0);
   fetch_u(IC<0>(), p0 + 1);
-  commit_u(IC<0>(), p0 + 1);
+  commit_u(IC<0>(), IC<2>(), p0 + 1);
   fetch_u(IC<0>(), p0 + 2);
   fetch_u(IC<1>(), p0 + 3);
   fetch_f(IC<0>(), p0);
   fetch_f(IC<1>(), p0 + 1);
   __syncthreads();
-  // Register sets alternate with period 2: unrolled by 2.
-  for (int p = p0; p <= p1; p += 2) {
-    step(IC<0>(), IC<0>(), p);
+  for (int p = p0;; p += kSR) {
+    step(IC<0>(), p);
     if (p + 1 > p1) break;
-    step(IC<1>(), IC<1>(), p + 1);
+    step(IC<1>(), p + 1);
+    if (p + 2 > p1) break;
+    step(IC<2>(), p + 2);
+    if (p + 3 > p1) break;
+    step(IC<3>(), p + 3);
+    if (p + 4 > p1) break;
+    step(IC<4>(), p + 4);
+    if (p + 5 > p1) break;
+    step(IC<5>(), p + 5);
+    if (p + 6 > p1) break;
   }
 }
 

@@ -1052,8 +1052,8 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
 // Neutrals drift (no field), cross the boundaries and are counted per cell
 // for the collisions.  The evaporation sources pile up neutrals in a few
 // hundred cells above the cathode, so a global atomic per neutral would
-// serialise on those cells: each workgroup takes kNChunk neutrals and
-// aggregates their cell counts in an LDS hash table first (one global
+// serialise on those cells: a workgroup takes chunks of kNChunk neutrals
+// and aggregates their cell counts in an LDS hash table first (one global
 // atomic per distinct cell and chunk; probes that find no slot fall back to
 // the global atomic).
 constexpr int kNChunk = 4096;
@@ -1098,27 +1098,31 @@ __global__ void __launch_bounds__(kT) k_push_neutral(
   __shared__ unsigned hk[kHist];
   __shared__ int hc[kHist];
   __shared__ double sk[kT];
-  hist_clear(hk, hc);
-  __syncthreads();
   const long long n = (long long)dc->n[1];
-  const long long b0 = blockIdx.x * (long long)kNChunk;
+  const long long nchunk = (n + kNChunk - 1) / kNChunk;
   double ke = 0.0;
-  for (int r = 0; r < kNChunk; r += kT) {
-    const long long i = b0 + r + threadIdx.x;
-    PushOut o;
-    o.cathode = false;
-    o.anode = false;
-    o.cand = false;
-    if (i < n) {
-      finish_push<1>(p, i, p.x[i], p.y[i], p.z[i], p.vx[i], p.vy[i], p.vz[i],
-                     dt, g, key, ncount, m, step, seed, dc, o, 0ull);
-      if (o.cell != kDead) hist_add(hk, hc, o.cell, ncount);
-      ke = ke + o.ke;
+  for (long long cb = blockIdx.x; cb < nchunk; cb += gridDim.x) {
+    hist_clear(hk, hc);
+    __syncthreads();
+    const long long b0 = cb * kNChunk;
+    for (int r = 0; r < kNChunk; r += kT) {
+      const long long i = b0 + r + threadIdx.x;
+      PushOut o;
+      o.cathode = false;
+      o.anode = false;
+      o.cand = false;
+      if (i < n) {
+        finish_push<1>(p, i, p.x[i], p.y[i], p.z[i], p.vx[i], p.vy[i],
+                       p.vz[i], dt, g, key, ncount, m, step, seed, dc, o, 0ull);
+        if (o.cell != kDead) hist_add(hk, hc, o.cell, ncount);
+        ke = ke + o.ke;
+      }
+      sink<1>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
     }
-    sink<1>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+    __syncthreads();
+    hist_flush(hk, hc, ncount);
+    __syncthreads();
   }
-  __syncthreads();
-  hist_flush(hk, hc, ncount);
   const double s = block_sum(ke, sk);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -1132,27 +1136,31 @@ __global__ void __launch_bounds__(kT) k_push_neutral_m(
   __shared__ unsigned hk[kHist];
   __shared__ int hc[kHist];
   __shared__ double sk[kT];
-  hist_clear(hk, hc);
-  __syncthreads();
   const long long n = (long long)dc->n[1];
-  const long long b0 = blockIdx.x * (long long)kNChunk;
+  const long long nchunk = (n + kNChunk - 1) / kNChunk;
   double ke = 0.0;
-  for (int r = 0; r < kNChunk; r += kT) {
-    const long long i = b0 + r + threadIdx.x;
-    PushOut o;
-    o.cathode = false;
-    o.anode = false;
-    o.cand = false;
-    if (i < n) {
-      push_one_m<1>(p, i, nullptr, nullptr, nullptr, 0, 0, 0, nullptr, 0, g,
-                    0.0f, dtdx, key, ncount, m, step, seed, dc, o);
-      if (o.cell != kDead) hist_add(hk, hc, o.cell, ncount);
-      ke = ke + o.ke;
+  for (long long cb = blockIdx.x; cb < nchunk; cb += gridDim.x) {
+    hist_clear(hk, hc);
+    __syncthreads();
+    const long long b0 = cb * kNChunk;
+    for (int r = 0; r < kNChunk; r += kT) {
+      const long long i = b0 + r + threadIdx.x;
+      PushOut o;
+      o.cathode = false;
+      o.anode = false;
+      o.cand = false;
+      if (i < n) {
+        push_one_m<1>(p, i, nullptr, nullptr, nullptr, 0, 0, 0, nullptr, 0, g,
+                      0.0f, dtdx, key, ncount, m, step, seed, dc, o);
+        if (o.cell != kDead) hist_add(hk, hc, o.cell, ncount);
+        ke = ke + o.ke;
+      }
+      sink_m(p, i, 1, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
     }
-    sink_m(p, i, 1, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+    __syncthreads();
+    hist_flush(hk, hc, ncount);
+    __syncthreads();
   }
-  __syncthreads();
-  hist_flush(hk, hc, ncount);
   const double s = block_sum(ke, sk);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -1950,8 +1958,10 @@ void deposit_t(pic_ctx* c) {
 }
 
 // Queue, disk, sphere and Fowler-Nordheim particles, ids in that order.
+// The first part (counts known on the host, no field) also resets the
+// step's counters; the Fowler-Nordheim part reads the cathode field.
 template <class PT>
-void sources_t(pic_ctx* c, double dt) {
+void sources_host_t(pic_ctx* c) {
   hipStream_t st = c->stream;
   const uint32_t step = (uint32_t)c->step;
   const uint64_t seed = c->cfg.seed;
@@ -1995,6 +2005,18 @@ void sources_t(pic_ctx* c, double dt) {
     nid += s.sph_n;
   }
   k_begin<<<1, 1, 0, st>>>(c->dc, n[0], n[1], n[2], nid);
+  for (int k = 0; k < 3; ++k) c->n[k] = n[k];
+  c->next_id_src = nid;
+}
+
+template <class PT>
+void sources_fn_t(pic_ctx* c, double dt) {
+  hipStream_t st = c->stream;
+  const uint32_t step = (uint32_t)c->step;
+  const uint64_t seed = c->cfg.seed;
+  const pic_sources& s = c->src;
+  const long long n0 = c->n[0];
+  const unsigned long long nid = c->next_id_src;
   if (s.fn_on) {
     const double phi_j = s.fn_phi_w_eV * kE;
     const double a_fn = pow(kE, 3.0) / (8.0 * kPi * kH);
@@ -2013,17 +2035,41 @@ void sources_t(pic_ctx* c, double dt) {
           s.fn_cy, s.fn_radius, a_phi, b_phi, c_fn, step, seed, c->dc);
     k_scan1<<<1, 1024, 0, st>>>(c->fn_scan + c->g.nxy + 1, c->fn_scan, c->g.nxy);
     long long cap = c->cfg.max_events;
-    if (n[0] + cap > c->cfg.capacity[0]) cap = c->cfg.capacity[0] - n[0];
+    if (n0 + cap > c->cfg.capacity[0]) cap = c->cfg.capacity[0] - n0;
     if (cap < 0) cap = 0;
     const double vth2 = (s.fn_kT_e_eV * kE) / kMe;
     k_fn_spawn<PT><<<nblk(c->cfg.max_events > 0 ? c->cfg.max_events : 1), kT, 0, st>>>(
-        cur<PT>(c, 0), n[0], cap, c->fn_scan, c->g, nid, vth2, step, seed, c->dc);
+        cur<PT>(c, 0), n0, cap, c->fn_scan, c->g, nid, vth2, step, seed, c->dc);
     k_fn_commit<<<1, 1, 0, st>>>(c->dc, cap);
+    // Upper bound of the electron count for the launches that follow.
+    c->n[0] = n0 + c->cfg.max_events;
   }
-  // Upper bounds of the counts for the launches that follow.
-  c->n[0] = n[0] + (s.fn_on ? c->cfg.max_events : 0);
-  c->n[1] = n[1];
-  c->n[2] = n[2];
+}
+
+// Neutral push (no field): cell counts for the collisions, boundary
+// crossings, kinetic energy (partial sums in a region of its own).
+template <class PT>
+void push_neutral_t(pic_ctx* c, double dt) {
+  hipStream_t st = c->stream;
+  const uint32_t step = (uint32_t)c->step;
+  const uint64_t seed = c->cfg.seed;
+  const MccC m = mcc_constants(c, dt);
+  const long long ab_cap = c->cfg.max_events;
+  hipMemsetAsync(c->ncount, 0, c->ncells * sizeof(int), st);
+  tmark(c, PIC_PH_PUSH_NEUTRAL, true);
+  const long long nb = neutral_push_blocks(bound(c, 1));
+  if (c->mixed)
+    k_push_neutral_m<<<nb, kT, 0, st>>>(
+        cur<PartsM>(c, 1), c->key[1], c->g, (float)(dt * c->g.inv_dx),
+        c->ncount, m, step, seed, c->ab_rec, c->ab_raw_pos, c->ab_raw_vel,
+        ab_cap, c->dc, c->part_n);
+  else
+    k_push_neutral<<<nb, kT, 0, st>>>(
+        cur<Parts>(c, 1), c->key[1], c->g, dt, c->ncount, m, step, seed,
+        c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, c->part_n);
+  tmark(c, PIC_PH_PUSH_NEUTRAL, false);
+  k_sum_partials<<<1, 1024, 0, st>>>(c->part_n, nb, nullptr, c->part_n, 0,
+                                     0.5 * kMcu, &c->dc->kinetic[1]);
 }
 
 // Pushes of the FP64 layout.
@@ -2035,17 +2081,6 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
   const long long nn = c->nnodes;
   const long long nt = c->ntiles;
   const long long ab_cap = c->cfg.max_events;
-  {
-    tmark(c, PIC_PH_PUSH_NEUTRAL, true);
-    const long long nb = (bound(c, 1) + kNChunk - 1) / kNChunk;
-    if (nb > 0)
-      k_push_neutral<<<nb, kT, 0, st>>>(
-          cur<Parts>(c, 1), c->key[1], c->g, dt, c->ncount, m, step, seed,
-          c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l);
-    tmark(c, PIC_PH_PUSH_NEUTRAL, false);
-    k_sum_partials<<<1, 1024, 0, st>>>(part_l, nb, nullptr, part_l, 0,
-                                       0.5 * kMcu, &c->dc->kinetic[1]);
-  }
   tmark(c, PIC_PH_PUSH_ELECTRON, true);
   TileArgs A;
   A.pe = cur<Parts>(c, 0);
@@ -2098,17 +2133,6 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
   const long long ab_cap = c->cfg.max_events;
   const float* E = reinterpret_cast<const float*>(c->E);
   const float dtdx = (float)(dt * c->g.inv_dx);
-  {
-    tmark(c, PIC_PH_PUSH_NEUTRAL, true);
-    const long long nb = (bound(c, 1) + kNChunk - 1) / kNChunk;
-    if (nb > 0)
-      k_push_neutral_m<<<nb, kT, 0, st>>>(
-          cur<PartsM>(c, 1), c->key[1], c->g, dtdx, c->ncount, m, step, seed,
-          c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l);
-    tmark(c, PIC_PH_PUSH_NEUTRAL, false);
-    k_sum_partials<<<1, 1024, 0, st>>>(part_l, nb, nullptr, part_l, 0,
-                                       0.5 * kMcu, &c->dc->kinetic[1]);
-  }
   tmark(c, PIC_PH_PUSH_ELECTRON, true);
   TileArgsM A;
   A.pe = cur<PartsM>(c, 0);
@@ -2157,7 +2181,6 @@ void push_collide_t(pic_ctx* c, double dt) {
   const uint64_t seed = c->cfg.seed;
   const MccC m = mcc_constants(c, dt);
   const long long nt = c->ntiles;
-  hipMemsetAsync(c->ncount, 0, c->ncells * sizeof(int), st);
   // Partial-sum regions: electron chunks, ion chunks, per-particle blocks.
   double* part_e = c->partials;
   double* part_i = c->partials + c->nch_cap;
@@ -2380,13 +2403,33 @@ void parts_deposit(pic_ctx* c) {
   tmark(c, PIC_PH_DEPOSIT, false);
 }
 
-void parts_sources(pic_ctx* c, double dt) {
+void parts_sources_host(pic_ctx* c) {
   tmark(c, PIC_PH_SOURCES, true);
   if (c->mixed)
-    sources_t<PartsM>(c, dt);
+    sources_host_t<PartsM>(c);
   else
-    sources_t<Parts>(c, dt);
+    sources_host_t<Parts>(c);
   tmark(c, PIC_PH_SOURCES, false);
+}
+
+void parts_sources_fn(pic_ctx* c, double dt) {
+  tmark(c, PIC_PH_SOURCES, true);
+  if (c->mixed)
+    sources_fn_t<PartsM>(c, dt);
+  else
+    sources_fn_t<Parts>(c, dt);
+  tmark(c, PIC_PH_SOURCES, false);
+}
+
+long long neutral_push_blocks(long long n) {
+  return (n > 0 ? n : 1) / kNChunk + 1;
+}
+
+void parts_push_neutral(pic_ctx* c, double dt) {
+  if (c->mixed)
+    push_neutral_t<PartsM>(c, dt);
+  else
+    push_neutral_t<Parts>(c, dt);
 }
 
 void parts_push_collide(pic_ctx* c, double dt) {

@@ -150,6 +150,7 @@ size_t carve(pic_ctx* c, char* base) {
     }
   }
   c->partials = cv.take<double>(c->npartials);
+  c->part_n = cv.take<double>(neutral_push_blocks(f.capacity[1]));
   c->qpartials = cv.take<long long>(1024);
   c->ncount = cv.take<int>(c->ncells);
   c->flag = cv.take<uint8_t>(c->ncells);
@@ -503,12 +504,12 @@ pic_status pic_set_phi(pic_ctx* c, const double* phi) {
   return hip_ok(c, hipGetLastError(), "efield launch") ? PIC_OK : PIC_ERR_HIP;
 }
 
-pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
-                       pic_diag* diag) {
-  if (!c) return PIC_ERR_ARG;
+namespace {
+
+// Host-known additions of the next step (queue, disk, sphere) must fit.
+pic_status advance_check(pic_ctx* c, double dt, long long add[3]) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(c, PIC_ERR_ARG, "dt");
-  // Host-known additions must fit.
-  long long add[3] = {0, 0, 0};
+  add[0] = add[1] = add[2] = 0;
   for (const QueueCall& q : c->queue) add[q.species] += q.n;
   const pic_sources& s = c->src;
   if (s.disk_on) {
@@ -519,8 +520,15 @@ pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
   for (int k = 0; k < 3; ++k)
     if (c->n[k] + add[k] > c->cfg.capacity[k])
       return set_err(c, PIC_ERR_CAPACITY, "sources exceed particle capacity");
-  const long long n_before[3] = {c->n[0], c->n[1], c->n[2]};
-  parts_sources(c, dt);
+  return PIC_OK;
+}
+
+// The field-dependent rest of a step (after the host-known sources and the
+// neutral push), the binning pass, the synchronisation and the host
+// bookkeeping.
+pic_status advance_finish(pic_ctx* c, double dt, const long long add[3],
+                          pic_absorbed* out, pic_diag* diag) {
+  parts_sources_fn(c, dt);
   parts_push_collide(c, dt);
   parts_bin(c);
   if (!hip_ok(c, hipGetLastError(), "advance launch")) return PIC_ERR_HIP;
@@ -540,7 +548,6 @@ pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
     fill_diag(c, diag);
     for (int k = 0; k < 3; ++k) diag->emitted[k] = add[k];
     diag->emitted[0] += (long long)c->hc.fn_total;
-    (void)n_before;
   }
   if (out) {
     long long n = (long long)c->hc.n_ab;
@@ -552,6 +559,19 @@ pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
     out->vel = c->ab_vel;
   }
   return check_flags(c);
+}
+
+}  // namespace
+
+pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
+                       pic_diag* diag) {
+  if (!c) return PIC_ERR_ARG;
+  long long add[3];
+  const pic_status v = advance_check(c, dt, add);
+  if (v != PIC_OK) return v;
+  parts_sources_host(c);
+  parts_push_neutral(c, dt);
+  return advance_finish(c, dt, add, out, diag);
 }
 
 pic_status pic_step(pic_ctx* c, double dt, pic_absorbed* out, pic_diag* diag) {

@@ -74,6 +74,7 @@ struct pic_ctx {
   int nlev;
   pic::Level lev[16];
   double* partials;          // reduction partials
+  double* part_n;            // neutral push partials (one per workgroup)
   int npartials;
   long long* qpartials;      // integer reduction partials
 
@@ -105,6 +106,7 @@ struct pic_ctx {
   // Host mirrors (exact after each synchronising call).
   long long n[3];
   unsigned long long next_id;
+  unsigned long long next_id_src;  // first id after the host-known sources
   long long step;
   pic_collisions coll;
   pic_sources src;
@@ -154,8 +156,15 @@ void field_phi_to_level0(pic_ctx* c);
 
 // ---- particles (k_particles.hip) -------------------------------------------
 void parts_deposit(pic_ctx* c);
-void parts_sources(pic_ctx* c, double dt);
+// One step's particle work: host-known sources (and the counter reset) and
+// the neutral push need no field; the Fowler-Nordheim source, the charged
+// pushes and the collisions do.
+void parts_sources_host(pic_ctx* c);
+void parts_push_neutral(pic_ctx* c, double dt);
+void parts_sources_fn(pic_ctx* c, double dt);
 void parts_push_collide(pic_ctx* c, double dt);
+// Workgroups (and partial sums) of the neutral push for n neutrals.
+long long neutral_push_blocks(long long n);
 void parts_bin(pic_ctx* c);
 void parts_bin_species(pic_ctx* c, int s);
 void parts_chunks(pic_ctx* c, const long long hb[3]);
