@@ -778,13 +778,12 @@ __host__ __device__ constexpr int ring_slot(int j, int d) {
   return ((1 + j + d) % kSR + kSR) % kSR;
 }
 
-template <typename T>
+// NEU: a z face of the level holds unknowns (Neumann condition), so face
+// planes are updated; with Dirichlet faces they never are.
+template <typename T, bool NEU>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-k_smooth2(const T* __restrict__ uin,
-                                                 T* __restrict__ uout,
-                                                 const T* __restrict__ f,
-                                                 LevelC L, int seg,
-                                                 const Counters* dc) {
+k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
+          const T* __restrict__ f, LevelC L, int seg, const Counters* dc) {
   __shared__ T ring[kSR][kSP];
   if (dc->done) return;
   const int tiles_x = (L.nx + kSX - 1) / kSX;
@@ -843,9 +842,11 @@ k_smooth2(const T* __restrict__ uin,
 #pragma unroll
     for (int r = 0; r < kSLoad; ++r) pu[iu][r] = src[loff[r]];
   };
-  auto commit_u = [&](auto U, auto S, int z) {
+  // A plane outside the level (z < 0 or z > nz) is committed too, from the
+  // clamped loads: its slot is only read as the missing neighbour of a face
+  // plane, which the face update never uses.
+  auto commit_u = [&](auto U, auto S, int) {
     constexpr int iu = decltype(U)::value;
-    if (z < 0 || z > L.nz) return;
     T* rr = ring[decltype(S)::value];
 #pragma unroll
     for (int r = 0; r < kSLoad; ++r)
@@ -878,7 +879,7 @@ k_smooth2(const T* __restrict__ uin,
     // On a Neumann face the mirror node stands in for the missing one
     // (up + up on the cathode face, dn + dn on the anode face).
     const T a = dn[c], b = up[c];
-    const T zs = (q == 0 ? b : a) + (q == L.nz ? a : b);
+    const T zs = NEU ? (q == 0 ? b : a) + (q == L.nz ? a : b) : a + b;
     cur[c] = relax(cur[c], ((sn + zs) + h2 * fv) * sixth);
   };
   // Step p (= p0 + j modulo kSR): the four half-sweeps (plane p-h), the
@@ -999,7 +1000,7 @@ int tail_first(const pic_ctx* c) {
   return l;
 }
 
-// Workgroups of k_smooth2<T> the current device runs at once.
+// Workgroups of k_smooth2<T, *> the current device runs at once.
 template <typename T>
 long long smooth_slots() {
   static long long cached[64] = {0};
@@ -1008,7 +1009,7 @@ long long smooth_slots() {
   if (dev < 0 || dev >= 64) dev = 0;
   if (!cached[dev]) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth2<T>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth2<T, false>, 256, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1085,7 +1086,10 @@ void vcycle(pic_ctx* c, int l) {
   };
   auto smooth_fused = [&](const T* in, T* out) {
     if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
-    k_smooth2<T><<<fgrid, 256, 0, st>>>(in, out, f, Lc, seg, c->dc);
+    if (Lc.k0 == 0 || Lc.k1 == Lc.nz)
+      k_smooth2<T, true><<<fgrid, 256, 0, st>>>(in, out, f, Lc, seg, c->dc);
+    else
+      k_smooth2<T, false><<<fgrid, 256, 0, st>>>(in, out, f, Lc, seg, c->dc);
     if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
   };
   T* uc = u;  // fine values the restriction reads and the prolongation corrects
