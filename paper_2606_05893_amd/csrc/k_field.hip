@@ -488,25 +488,83 @@ __global__ void k_restrict(const T* __restrict__ uf, const T* __restrict__ ff,
   restrict_node(uf, ff, uc, fc, F, Cc, t);
 }
 
+// Prolongation with correction by fine x-pairs: the nodes 2i and 2i+1 of a
+// fine row share their coarse nodes i, i+1, so one thread reads and writes
+// the pair with one vector access each.  A wave covers 64 pairs of one row,
+// so the y and z parities (how many coarse rows and planes contribute) are
+// uniform across it.  Per node the sum runs in the same order as
+// prolong_node (z, then y, then x), so the results are the same.
 template <typename T>
-__global__ void k_prolong(T* __restrict__ uf, const T* __restrict__ uc,
-                          LevelC F, LevelC Cc, const Counters* dc) {
+struct Pair2;
+template <>
+struct Pair2<double> { using type = double2; };
+template <>
+struct Pair2<float> { using type = float2; };
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_prolong_pairs(
+    T* __restrict__ uf, const T* __restrict__ uc, LevelC F, LevelC Cc,
+    int nbx, const Counters* dc) {
   if (dc->done) return;
-  const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (t >= F.nxy * (F.k1 - F.k0 + 1)) return;
-  prolong_node(uf, uc, F, Cc, t);
+  const int blk = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int bx = blk % nbx, by = blk / nbx;
+  const int ic = bx * 64 + (int)(threadIdx.x & 63);
+  const int row = by * 4 + (int)(threadIdx.x >> 6);
+  const int nrows = F.ny * (F.k1 - F.k0 + 1);
+  if (ic >= (F.nx >> 1) || row >= nrows) return;
+  const int j = row % F.ny;
+  const int k = F.k0 + row / F.ny;
+  const int ic1 = wrap_index(ic + 1, Cc.nx);
+  int ja[2], ka[2];
+  T wb[2], wc[2];
+  int nb = 1, nc = 1;
+  ja[0] = j >> 1;
+  wb[0] = T(1);
+  if (j & 1) {
+    ja[1] = wrap_index((j >> 1) + 1, Cc.ny);
+    wb[0] = wb[1] = T(0.5);
+    nb = 2;
+  }
+  ka[0] = k >> 1;
+  wc[0] = T(1);
+  if (k & 1) {
+    ka[1] = (k >> 1) + 1;
+    wc[0] = wc[1] = T(0.5);
+    nc = 2;
+  }
+  T s0 = T(0), s1 = T(0);
+  for (int c3 = 0; c3 < nc; ++c3)
+    for (int b3 = 0; b3 < nb; ++b3) {
+      const T* cr = uc + ((long long)ka[c3] * Cc.ny + ja[b3]) * Cc.nx;
+      const T a = cr[ic], b = cr[ic1];
+      s0 = s0 + ((T(1) * wb[b3]) * wc[c3]) * a;
+      const T w = (T(0.5) * wb[b3]) * wc[c3];
+      s1 = s1 + w * a;
+      s1 = s1 + w * b;
+    }
+  using V = typename Pair2<T>::type;
+  V* p = reinterpret_cast<V*>(uf + ((long long)k * F.ny + j) * F.nx + 2 * ic);
+  V v = *p;
+  v.x = v.x + s0;
+  v.y = v.y + s1;
+  *p = v;
 }
 
 // Restriction with the fine residual staged in LDS: a workgroup takes an
-// 8x8x4 block of coarse nodes, computes the residual of the 17x17x9 fine
-// nodes under it once, then applies the 27-point full weighting from LDS.
+// 8x8x4 block of coarse nodes.  It stages the 19x19x11 fine u nodes the
+// block's residuals read (coalesced, each node once), computes the residual
+// of the 17x17x9 fine nodes under the block from LDS (same stencil and
+// order as nb_sum), then applies the 27-point full weighting from LDS.
 constexpr int kRX = 8, kRY = 8, kRZ = 4;
 constexpr int kFX = 2 * kRX + 1, kFY = 2 * kRY + 1, kFZ = 2 * kRZ + 1;
+constexpr int kUX = kFX + 2, kUY = kFY + 2, kUZ = kFZ + 2;
+constexpr int kUXY = kUX * kUY;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_restrict_tiled(
     const T* __restrict__ uf, const T* __restrict__ ff, T* __restrict__ uc,
     T* __restrict__ fc, LevelC F, LevelC Cc, const Counters* dc) {
+  __shared__ T su[kUZ * kUXY];
   __shared__ T r[kFZ * kFY * kFX];
   if (dc->done) return;
   const int tnx = (Cc.nx + kRX - 1) / kRX, tny = (Cc.ny + kRY - 1) / kRY;
@@ -515,17 +573,42 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
   const int bx = blk % tnx, by = (blk / tnx) % tny, bz = blk / (tnx * tny);
   const int cx0 = bx * kRX, cy0 = by * kRY, cz0 = bz * kRZ;
   const T inv_h2 = T(1) / (T)F.h2;
+  // Staged node (sx, sy, sz) is fine node (2cx0 - 2 + sx, 2cy0 - 2 + sy,
+  // 2cz0 - 2 + sz), x and y wrapped; planes outside [0, nz] are loaded
+  // clamped and never read.  The fine level is at least 16 nodes wide, so
+  // one wrap suffices.
+  const int nxy = (int)F.nxy;
+#pragma unroll 4
+  for (int q = threadIdx.x; q < kUZ * kUXY; q += blockDim.x) {
+    const int sx = q % kUX, sy = (q / kUX) % kUY, sz = q / kUXY;
+    const int i = wrap_index(2 * cx0 - 2 + sx, F.nx);
+    const int j = wrap_index(2 * cy0 - 2 + sy, F.ny);
+    int k = 2 * cz0 - 2 + sz;
+    k = k < 0 ? 0 : (k > F.nz ? F.nz : k);
+    su[q] = uf[k * nxy + j * F.nx + i];
+  }
+  __syncthreads();
   for (int q = threadIdx.x; q < kFZ * kFY * kFX; q += blockDim.x) {
     const int lx = q % kFX, ly = (q / kFX) % kFY, lz = q / (kFX * kFY);
-    const int i = wrap_index(2 * cx0 - 1 + lx, F.nx);
-    const int j = wrap_index(2 * cy0 - 1 + ly, F.ny);
     int k = 2 * cz0 - 1 + lz;
     if (k < 0) k = 1;                    // Neumann mirror
     if (k > F.nz) k = F.nz - 1;
     T res = T(0);
     if (k >= F.k0 && k <= F.k1) {
-      const long long fi = ((long long)k * F.ny + j) * F.nx + i;
-      res = ff[fi] - (T(6) * uf[fi] - nb_sum(uf, F, i, j, k)) * inv_h2;
+      const int i = wrap_index(2 * cx0 - 1 + lx, F.nx);
+      const int j = wrap_index(2 * cy0 - 1 + ly, F.ny);
+      // Plane k sits at sz = k - (2cz0 - 2), in 1..9, so k +- 1 are staged.
+      const int c = ((k - 2 * cz0 + 2) * kUY + ly + 1) * kUX + lx + 1;
+      T sn = su[c - 1] + su[c + 1];
+      sn = sn + (su[c - kUX] + su[c + kUX]);
+      T zs;
+      if (k == 0)
+        zs = T(2) * su[c + kUXY];
+      else if (k == F.nz)
+        zs = T(2) * su[c - kUXY];
+      else
+        zs = su[c - kUXY] + su[c + kUXY];
+      res = ff[k * nxy + j * F.nx + i] - (T(6) * su[c] - (sn + zs)) * inv_h2;
     }
     r[q] = res;
   }
@@ -727,6 +810,16 @@ constexpr int kSPX = kSX + 2 * kSH, kSPY = kSY + 2 * kSH;
 constexpr int kSP = kSPX * kSPY;  // 640 nodes per plane slot
 constexpr int kSR = 6;
 constexpr int kSLoad = (kSP + 255) / 256;
+// A plane slot in LDS holds the even-x nodes of every row, then the odd-x
+// ones: a half-sweep touches one colour, i.e. every other node of a row,
+// and in this layout consecutive lanes read consecutive words (no bank
+// conflicts).
+constexpr int kHX = kSPX / 2, kHP = kHX * kSPY;
+static_assert((kSPX & 1) == 0 && (kSH & 1) == 0, "split layout needs even x");
+
+__host__ __device__ constexpr int split_idx(int lx, int ly) {
+  return (lx & 1) * kHP + ly * kHX + (lx >> 1);
+}
 
 __device__ __forceinline__ int wrap_n(int v, int n) {
   v = v < 0 ? v + n : v;
@@ -737,7 +830,7 @@ __device__ __forceinline__ int wrap_n(int v, int n) {
 // two): LDS index and in-plane global offsets for both parities of the
 // plane, and the parity of the row.
 struct HalfSlot {
-  int c0, g0, g1, b;
+  int c0, c1, g0, g1, b;
   bool on;
 };
 
@@ -753,6 +846,7 @@ __device__ __forceinline__ HalfSlot half_slot(int tid, int s, int x0, int y0,
   const int row = t / hw, kk = t % hw;
   const int ly = kSH - e + row, lx = kSH - e + 2 * kk;
   r.c0 = ly * kSPX + lx;
+  r.c1 = r.c0 + 1;
   r.g0 = r.g1 = 0;
   if (r.on) {
     const int gy = wrap_n(wrap_n(y0 + ly, ny), ny);
@@ -781,7 +875,7 @@ __host__ __device__ constexpr int ring_slot(int j, int d) {
 // NEU: a z face of the level holds unknowns (Neumann condition), so face
 // planes are updated; with Dirichlet faces they never are.
 template <typename T, bool NEU>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 5)))
 k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
           const T* __restrict__ f, LevelC L, int seg, const Counters* dc) {
   __shared__ T ring[kSR][kSP];
@@ -805,15 +899,17 @@ k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
   // unused where it is not needed), so the compiler waits for exactly the
   // loads a use depends on while later ones stay in flight: the u plane of
   // step p+4 and the f operands of step p+2 are loaded during step p.
-  int loff[kSLoad];
+  int loff[kSLoad], lidx[kSLoad];
 #pragma unroll
   for (int r = 0; r < kSLoad; ++r) {
     const int t = tid + 256 * r;
     loff[r] = 0;
+    lidx[r] = 0;
     if (t < kSP) {
       const int gx = wrap_n(wrap_n(x0 + t % kSPX, L.nx), L.nx);
       const int gy = wrap_n(wrap_n(y0 + t / kSPX, L.ny), L.ny);
       loff[r] = gy * L.nx + gx;
+      lidx[r] = t;
     }
   }
   HalfSlot hs[kNS];
@@ -824,21 +920,28 @@ k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
   hs[4] = half_slot<3>(tid, 0, x0, y0, L.nx, L.ny);
 
   // Plane q takes half-sweep h when it holds unknowns and lies in h's
-  // widened z range [za - e, zb - 1 + e], e = 3 - h.
-  int lo[4], hi[4];
+  // widened z range [za - e, zb - 1 + e], e = 3 - h; at step p that plane is
+  // q = p - h, so the test is p - h - lo in [0, hi - lo] (one unsigned
+  // compare).
+  int lo[4];
+  unsigned span[4];
 #pragma unroll
   for (int h = 0; h < 4; ++h) {
-    lo[h] = max(L.k0, za - (3 - h));
-    hi[h] = min(L.k1, zb - 1 + (3 - h));
+    lo[h] = max(L.k0, za - (3 - h)) + h;
+    const int hi = min(L.k1, zb - 1 + (3 - h)) + h;
+    span[h] = hi >= lo[h] ? (unsigned)(hi - lo[h]) : 0u;
+    if (hi < lo[h]) lo[h] = 0x3FFFFFFF;  // never: p - lo wraps above 0
   }
-  auto active = [&](int h, int q) { return q >= lo[h] && q <= hi[h]; };
+  auto active = [&](int h, int p) { return (unsigned)(p - lo[h]) <= span[h]; };
   auto clampz = [&](int z) { return z < 0 ? 0 : (z > L.nz ? L.nz : z); };
+  // Node offsets fit in 32 bits (at most 2^31 - 1 nodes per level).
+  const int nxy = (int)L.nxy;
 
   T pu[2][kSLoad];
   T fs[2][kNS];
   auto fetch_u = [&](auto U, int z) {
     constexpr int iu = decltype(U)::value;
-    const T* src = uin + (long long)clampz(z) * L.nxy;
+    const T* src = uin + clampz(z) * nxy;
 #pragma unroll
     for (int r = 0; r < kSLoad; ++r) pu[iu][r] = src[loff[r]];
   };
@@ -850,18 +953,22 @@ k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
     T* rr = ring[decltype(S)::value];
 #pragma unroll
     for (int r = 0; r < kSLoad; ++r)
-      if (tid + 256 * r < kSP) rr[tid + 256 * r] = pu[iu][r];
+      if (tid + 256 * r < kSP) rr[lidx[r]] = pu[iu][r];
   };
-  auto fetch_f = [&](auto F, int p) {
-    constexpr int jf = decltype(F)::value;
-    const T* fp[4];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) fp[h] = f + (long long)clampz(p - h) * L.nxy;
+  // f plane pointers, kept like the u ring: plane p + d at step j in
+  // fpl[ring_slot(j, d)]; each step adds plane p + 2.
+  const T* fpl[kSR];
+  auto set_fplane = [&](auto S, int z) {
+    fpl[decltype(S)::value] = f + clampz(z) * nxy;
+  };
+  // f operands of step p + 2 (planes p + 2 - h) at step j.
+  auto fetch_f = [&](auto F, auto J, int p) {
+    constexpr int jf = decltype(F)::value, j = decltype(J)::value;
 #pragma unroll
     for (int k = 0; k < kNS; ++k) {
-      const int q = p - slot_h(k);
+      const int q = p + 2 - slot_h(k);
       const HalfSlot& z = hs[k];
-      fs[jf][k] = fp[slot_h(k)][((z.b + q) & 1) ? z.g1 : z.g0];
+      fs[jf][k] = fpl[ring_slot(j, 2 - slot_h(k))][((z.b + q) & 1) ? z.g1 : z.g0];
     }
   };
   // Update of slot k at step j of the unrolled march (plane q = p - h).
@@ -892,11 +999,11 @@ k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
       update(IC<1>(), J, p, fs[jf][1]);
     }
     __syncthreads();
-    if (active(1, p - 1)) update(IC<2>(), J, p - 1, fs[jf][2]);
+    if (active(1, p)) update(IC<2>(), J, p - 1, fs[jf][2]);
     __syncthreads();
-    if (active(2, p - 2)) update(IC<3>(), J, p - 2, fs[jf][3]);
+    if (active(2, p)) update(IC<3>(), J, p - 2, fs[jf][3]);
     __syncthreads();
-    if (active(3, p - 3)) update(IC<4>(), J, p - 3, fs[jf][4]);
+    if (active(3, p)) update(IC<4>(), J, p - 3, fs[jf][4]);
     __syncthreads();
     const int q = p - 3;
     if (q >= za && q < zb) {
@@ -908,7 +1015,8 @@ k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
     }
     commit_u(IC<jf>(), IC<ring_slot(j, 2)>(), p + 2);
     fetch_u(IC<jf>(), p + 4);
-    fetch_f(IC<jf>(), p + 2);
+    set_fplane(IC<ring_slot(j, 2)>(), p + 2);
+    fetch_f(IC<jf>(), J, p);
     __syncthreads();
   };
 
@@ -924,8 +1032,15 @@ k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
   commit_u(IC<0>(), IC<2>(), p0 + 1);
   fetch_u(IC<0>(), p0 + 2);
   fetch_u(IC<1>(), p0 + 3);
-  fetch_f(IC<0>(), p0);
-  fetch_f(IC<1>(), p0 + 1);
+  // f planes p0 - 3 .. p0 + 1 (d = -3 .. 1 at step 0), then the operands
+  // of steps p0 and p0 + 1 (as fetched at steps p0 - 2 and p0 - 1).
+  set_fplane(IC<ring_slot(0, -3)>(), p0 - 3);
+  set_fplane(IC<ring_slot(0, -2)>(), p0 - 2);
+  set_fplane(IC<ring_slot(0, -1)>(), p0 - 1);
+  set_fplane(IC<ring_slot(0, 0)>(), p0);
+  set_fplane(IC<ring_slot(0, 1)>(), p0 + 1);
+  fetch_f(IC<0>(), IC<4>(), p0 - 2);
+  fetch_f(IC<1>(), IC<5>(), p0 - 1);
   __syncthreads();
   for (int p = p0;; p += kSR) {
     step(IC<0>(), p);
@@ -1111,8 +1226,12 @@ void vcycle(pic_ctx* c, int l) {
         uc, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
   }
   vcycle<T>(c, l + 1);
-  k_prolong<T><<<nblocks(Lc.nxy * (Lc.k1 - Lc.k0 + 1)), kThreads, 0, st>>>(
-      uc, lev_u<T>(N), Lc, Nc, c->dc);
+  {
+    const int nbx = (Lc.nx / 2 + 63) / 64;
+    const long long nby = ((long long)Lc.ny * (Lc.k1 - Lc.k0 + 1) + 3) / 4;
+    k_prolong_pairs<T><<<(unsigned)(nbx * nby), 256, 0, st>>>(
+        uc, lev_u<T>(N), Lc, Nc, nbx, c->dc);
+  }
   if (fused)
     smooth_fused(sp, u);
   else

@@ -99,6 +99,44 @@ __device__ __forceinline__ unsigned tile_of_cell(unsigned cell, const GridC& g) 
   return ((k / kTile) * (unsigned)g.tny + j / kTile) * (unsigned)g.tnx + i / kTile;
 }
 
+// Tile (u) of a cell and its slot among the 27 tiles around the source tile
+// (tx, ty, tz), x and y periodic, or -1 when it lies further away.  One
+// decode of the cell (two divisions); tile coordinates are shifts.
+__device__ __forceinline__ int dest_slot(unsigned cell, int tx, int ty, int tz,
+                                         const GridC& g, unsigned& u) {
+  const unsigned i = cell % (unsigned)g.nx;
+  const unsigned r = cell / (unsigned)g.nx;
+  const unsigned j = r % (unsigned)g.ny;
+  const unsigned k = r / (unsigned)g.ny;
+  const int ux = (int)(i / kTile), uy = (int)(j / kTile), uz = (int)(k / kTile);
+  u = ((unsigned)uz * (unsigned)g.tny + (unsigned)uy) * (unsigned)g.tnx + (unsigned)ux;
+  int ox = ux - tx, oy = uy - ty;
+  const int oz = uz - tz;
+  if (ox > 1) ox -= g.tnx;
+  if (ox < -1) ox += g.tnx;
+  if (oy > 1) oy -= g.tny;
+  if (oy < -1) oy += g.tny;
+  if (ox < -1 || ox > 1 || oy < -1 || oy > 1 || oz < -1 || oz > 1) return -1;
+  return ((oz + 1) * 3 + (oy + 1)) * 3 + (ox + 1);
+}
+
+// Count a pushed particle's destination tile for the binning pass: per
+// neighbouring tile in LDS (sc, sd), else straight into the global counts.
+__device__ __forceinline__ void count_dest(unsigned cell, int tx, int ty,
+                                           int tz, const GridC& g,
+                                           unsigned* sc, unsigned* sd,
+                                           unsigned* __restrict__ cnt) {
+  if (cell == kDead) return;
+  unsigned u;
+  const int d = dest_slot(cell, tx, ty, tz, g, u);
+  if (d >= 0) {
+    atomicAdd(&sc[d], 1u);
+    sd[d] = u;
+  } else {
+    atomicAdd(&cnt[u], 1u);
+  }
+}
+
 // Cell of an in-domain position (0 <= z/dx < nz): the one the MCC uses for
 // the target density and the binning uses for tiles.
 __device__ __forceinline__ unsigned cell_of(double x, double y, double z,
@@ -600,6 +638,7 @@ struct TileArgs {
   double *ab_pos, *ab_vel;
   long long ab_cap;
   double *part_e, *part_i;
+  unsigned *cnt_e, *cnt_i;   // destination-tile counts for the binning
 };
 
 __global__ void __launch_bounds__(kT) k_push_tile(
@@ -608,6 +647,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
   __shared__ double sx[729], sy[729], sz[729];
   __shared__ double sk[kT];
   __shared__ unsigned s_cand;
+  __shared__ unsigned s_nc[2][27], s_nd[2][27];  // destinations: e, ions
   const unsigned nchk = *A.nchunks;
   if (blockIdx.x >= nchk) return;
   const unsigned cb = xcd_block(blockIdx.x, nchk);
@@ -639,6 +679,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
     sx[q] = vx; sy[q] = vy; sz[q] = vz;
   }
   if (threadIdx.x == 0) s_cand = 0;
+  if (threadIdx.x < 54) (&s_nc[0][0])[threadIdx.x] = 0u;
   __syncthreads();
   double ke_i = 0.0, ke_e = 0.0;
   // Ions.
@@ -668,6 +709,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
       finish_push<2>(A.pi, i, x, y, z, vx, vy, vz, A.dt, g, A.keyi, A.ncount, m,
                      step, seed, dc, o, 0ull);
       ke_i = ke_i + o.ke;
+      count_dest(o.cell, tx, ty, tz, g, s_nc[1], s_nd[1], A.cnt_i);
     }
     sink<2>(A.pi, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
   }
@@ -699,6 +741,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
       finish_push<0>(A.pe, i, x, y, z, vx, vy, vz, A.dt, g, A.keye, A.ncount, m,
                      step, seed, dc, o, A.pe.id[i]);
       ke_e = ke_e + o.ke;
+      count_dest(o.cell, tx, ty, tz, g, s_nc[0], s_nd[0], A.cnt_e);
       if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = (uint32_t)i;
     }
     sink<0>(A.pe, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
@@ -709,6 +752,12 @@ __global__ void __launch_bounds__(kT) k_push_tile(
     A.part_i[cb] = si;
     A.part_e[cb] = se;
     A.cand_cnt[cb] = s_cand;
+  }
+  // The destination counts are complete (block_sum synchronised).
+  if (threadIdx.x < 54) {
+    const int sp = threadIdx.x / 27, d = threadIdx.x % 27;
+    const unsigned n = s_nc[sp][d];
+    if (n) atomicAdd(&(sp ? A.cnt_i : A.cnt_e)[s_nd[sp][d]], n);
   }
 }
 
@@ -886,6 +935,7 @@ struct TileArgsM {
   double *ab_pos, *ab_vel;
   long long ab_cap;
   double *part_e, *part_i;
+  unsigned *cnt_e, *cnt_i;   // destination-tile counts for the binning
 };
 
 template <int SP>
@@ -951,6 +1001,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
   __shared__ float sx[729], sy[729], sz[729];
   __shared__ double sk[kT];
   __shared__ unsigned s_cand;
+  __shared__ unsigned s_nc[2][27], s_nd[2][27];  // destinations: e, ions
   const unsigned nchk = *A.nchunks;
   if (blockIdx.x >= nchk) return;
   const unsigned cb = xcd_block(blockIdx.x, nchk);
@@ -982,6 +1033,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
     sx[q] = vx; sy[q] = vy; sz[q] = vz;
   }
   if (threadIdx.x == 0) s_cand = 0;
+  if (threadIdx.x < 54) (&s_nc[0][0])[threadIdx.x] = 0u;
   __syncthreads();
   double ke_i = 0.0, ke_e = 0.0;
   for (unsigned base = bi; base < ei; base += blockDim.x) {
@@ -993,6 +1045,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
       push_one_m<2>(A.pi, i, sx, sy, sz, x0, y0, z0, E, nn, g, A.qm_i, A.dtdx,
                     A.keyi, A.ncount, m, step, seed, dc, o);
       ke_i = ke_i + o.ke;
+      count_dest(o.cell, tx, ty, tz, g, s_nc[1], s_nd[1], A.cnt_i);
     }
     sink_m(A.pi, i, 2, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
   }
@@ -1006,6 +1059,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
       push_one_m<0>(A.pe, i, sx, sy, sz, x0, y0, z0, E, nn, g, A.qm_e, A.dtdx,
                     A.keye, A.ncount, m, step, seed, dc, o);
       ke_e = ke_e + o.ke;
+      count_dest(o.cell, tx, ty, tz, g, s_nc[0], s_nd[0], A.cnt_e);
       if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = (uint32_t)i;
     }
     sink_m(A.pe, i, 0, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
@@ -1016,6 +1070,12 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
     A.part_i[cb] = si;
     A.part_e[cb] = se;
     A.cand_cnt[cb] = s_cand;
+  }
+  // The destination counts are complete (block_sum synchronised).
+  if (threadIdx.x < 54) {
+    const int sp = threadIdx.x / 27, d = threadIdx.x % 27;
+    const unsigned n = s_nc[sp][d];
+    if (n) atomicAdd(&(sp ? A.cnt_i : A.cnt_e)[s_nd[sp][d]], n);
   }
 }
 
@@ -1543,22 +1603,9 @@ __global__ void k_ab_gather(const Rec* __restrict__ rec,
 
 // ---- binning ------------------------------------------------------------------
 // Particles of a binned tile move at most one tile per axis per step, so a
-// tile's particles go to one of its 27 neighbours (slot d); counting per
-// (tile, slot) in LDS needs one global atomic per non-empty slot.
-__device__ __forceinline__ int nb_slot(unsigned src, unsigned dst, const GridC& g) {
-  const int sx = (int)(src % g.tnx), sy = (int)((src / g.tnx) % g.tny),
-            sz = (int)(src / ((unsigned)g.tnx * g.tny));
-  const int dx = (int)(dst % g.tnx), dy = (int)((dst / g.tnx) % g.tny),
-            dz = (int)(dst / ((unsigned)g.tnx * g.tny));
-  int ox = dx - sx, oy = dy - sy;
-  const int oz = dz - sz;
-  if (ox > 1) ox -= g.tnx;
-  if (ox < -1) ox += g.tnx;
-  if (oy > 1) oy -= g.tny;
-  if (oy < -1) oy += g.tny;
-  if (ox < -1 || ox > 1 || oy < -1 || oy > 1 || oz < -1 || oz > 1) return -1;
-  return ((oz + 1) * 3 + (oy + 1)) * 3 + (ox + 1);
-}
+// tile's particles go to one of its 27 neighbours (slot d of dest_slot);
+// counting per (tile, slot) in LDS needs one global atomic per non-empty
+// slot (the rare farther moves take a global atomic each).
 
 // Count the destination tiles of a tile's binned particles.
 __global__ void __launch_bounds__(kT) k_bin_hist_tile(
@@ -1576,18 +1623,10 @@ __global__ void __launch_bounds__(kT) k_bin_hist_tile(
   if (b == e) return;
   if (threadIdx.x < 27) sc[threadIdx.x] = 0;
   __syncthreads();
-  for (unsigned q = b + threadIdx.x; q < e; q += blockDim.x) {
-    const uint32_t k = key[q];
-    if (k == kDead) continue;
-    const unsigned u = tile_of_cell(k, g);
-    const int d = nb_slot(t, u, g);
-    if (d >= 0) {
-      atomicAdd(&sc[d], 1u);
-      sdst[d] = u;
-    } else {
-      atomicAdd(&cnt[u], 1u);
-    }
-  }
+  const int tx = (int)(t % g.tnx), ty = (int)((t / g.tnx) % g.tny),
+            tz = (int)(t / ((unsigned)g.tnx * g.tny));
+  for (unsigned q = b + threadIdx.x; q < e; q += blockDim.x)
+    count_dest(key[q], tx, ty, tz, g, sc, sdst, cnt);
   __syncthreads();
   if (threadIdx.x < 27 && sc[threadIdx.x]) atomicAdd(&cnt[sdst[threadIdx.x]], sc[threadIdx.x]);
 }
@@ -1712,11 +1751,13 @@ __global__ void __launch_bounds__(kT) k_bin_scatter_tile(
     srank[threadIdx.x] = 0;
   }
   __syncthreads();
+  const int tx = (int)(t % g.tnx), ty = (int)((t / g.tnx) % g.tny),
+            tz = (int)(t / ((unsigned)g.tnx * g.tny));
   for (unsigned q = b + threadIdx.x; q < e; q += blockDim.x) {
     const uint32_t k = key[q];
     if (k == kDead) continue;
-    const unsigned u = tile_of_cell(k, g);
-    const int d = nb_slot(t, u, g);
+    unsigned u;
+    const int d = dest_slot(k, tx, ty, tz, g, u);
     if (d >= 0) {
       atomicAdd(&sc[d], 1u);
       sdst[d] = u;
@@ -1729,8 +1770,8 @@ __global__ void __launch_bounds__(kT) k_bin_scatter_tile(
   for (unsigned q = b + threadIdx.x; q < e; q += blockDim.x) {
     const uint32_t k = key[q];
     if (k == kDead) continue;
-    const unsigned u = tile_of_cell(k, g);
-    const int d = nb_slot(t, u, g);
+    unsigned u;
+    const int d = dest_slot(k, tx, ty, tz, g, u);
     const unsigned pos = d >= 0 ? sbase[d] + atomicAdd(&srank[d], 1u)
                                 : atomicAdd(&cursor[u], 1u);
     Acc<PT>::copy(src, q, dst, pos);
@@ -2103,6 +2144,8 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.ab_cap = ab_cap;
   A.part_e = part_e;
   A.part_i = part_i;
+  A.cnt_e = c->tcnt[0];
+  A.cnt_i = c->tcnt[1];
   k_push_tile<<<(unsigned)c->nch_bound, kT, 0, st>>>(A, c->E, nn, c->g, m,
                                                          step, seed, c->dc);
   tmark(c, PIC_PH_PUSH_ELECTRON, false);
@@ -2155,6 +2198,8 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.ab_cap = ab_cap;
   A.part_e = part_e;
   A.part_i = part_i;
+  A.cnt_e = c->tcnt[0];
+  A.cnt_i = c->tcnt[1];
   k_push_tile_m<<<(unsigned)c->nch_bound, kT, 0, st>>>(A, E, nn, c->g, m,
                                                            step, seed, c->dc);
   tmark(c, PIC_PH_PUSH_ELECTRON, false);
@@ -2181,6 +2226,9 @@ void push_collide_t(pic_ctx* c, double dt) {
   const uint64_t seed = c->cfg.seed;
   const MccC m = mcc_constants(c, dt);
   const long long nt = c->ntiles;
+  // The tile push counts the binned particles' destination tiles.
+  hipMemsetAsync(c->tcnt[0], 0, 2 * (nt + 1) * sizeof(unsigned), st);
+  c->tcounted = true;
   // Partial-sum regions: electron chunks, ion chunks, per-particle blocks.
   double* part_e = c->partials;
   double* part_i = c->partials + c->nch_cap;
@@ -2243,28 +2291,35 @@ void bin_species_t(pic_ctx* c, int s) {
   uint32_t* ts_old = ts_cur(c, s);
   uint32_t* ts_new = c->tsb[s][c->tcur[s] ^ 1];
   const long long first = tiled ? c->n_binned[s] : 0;
-  hipMemsetAsync(c->tile_cursor, 0, (nt + 1) * sizeof(unsigned), st);
-  if (tiled)
-    k_bin_hist_tile<<<(unsigned)c->nch_bound, kT, 0, st>>>(
-        c->key[s], ts_old, c->chunks, c->cstart + nt, c->tile_cursor, c->g);
+  // Destination counts of the binned ranges: taken by the tile push of this
+  // step, else (after a load or a restore) from the keys.
+  unsigned* cursor = c->tile_cursor;
+  if (tiled && c->tcounted) {
+    cursor = c->tcnt[s == 0 ? 0 : 1];
+  } else {
+    hipMemsetAsync(cursor, 0, (nt + 1) * sizeof(unsigned), st);
+    if (tiled)
+      k_bin_hist_tile<<<(unsigned)c->nch_bound, kT, 0, st>>>(
+          c->key[s], ts_old, c->chunks, c->cstart + nt, cursor, c->g);
+  }
   const long long tail = std::max(0ll, bound(c, s) - first);
   if (tail > 0)
     k_bin_hist_list<<<(unsigned)((tail + kLChunk - 1) / kLChunk), kT, 0, st>>>(
-        c->key[s], c->tile_cursor, c->g, first, &c->dc->n[s]);
+        c->key[s], cursor, c->g, first, &c->dc->n[s]);
   const long long nsb = (nt + 1 + kScanPer - 1) / kScanPer;
-  k_scan_blocks<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt, c->scan_block);
+  k_scan_blocks<<<(unsigned)nsb, kT, 0, st>>>(cursor, nt, c->scan_block);
   k_scan1<<<1, 1024, 0, st>>>(c->scan_block, c->scan_block + nsb + 1, nsb);
-  k_scan_apply<<<(unsigned)nsb, kT, 0, st>>>(c->tile_cursor, nt,
+  k_scan_apply<<<(unsigned)nsb, kT, 0, st>>>(cursor, nt,
                                              c->scan_block + nsb + 1, ts_new,
-                                             c->tile_cursor);
+                                             cursor);
   const int o = c->cur[s] ^ 1;
   if (tiled)
     k_bin_scatter_tile<PT><<<(unsigned)c->nch_bound, kT, 0, st>>>(
         cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], ts_old, c->chunks,
-        c->cstart + nt, c->tile_cursor, c->g);
+        c->cstart + nt, cursor, c->g);
   if (tail > 0)
     k_bin_scatter_list<PT><<<(unsigned)((tail + kLChunk - 1) / kLChunk), kT, 0, st>>>(
-        cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], c->tile_cursor, c->g,
+        cur<PT>(c, s), buf<PT>(c, s, o), c->key[s], cursor, c->g,
         first, &c->dc->n[s]);
   k_set_count<<<1, 1, 0, st>>>(c->dc, s, ts_new, nt);
   c->cur[s] = o;
@@ -2471,6 +2526,7 @@ void parts_bin(pic_ctx* c) {
   tmark(c, PIC_PH_BIN, true);
   parts_bin_species(c, 0);
   parts_bin_species(c, 2);
+  c->tcounted = false;
   c->neutrals_binned = 2 * c->n_stirred >= c->n[1];
   if (c->neutrals_binned)
     parts_bin_species(c, 1);

@@ -129,6 +129,8 @@ size_t carve(pic_ctx* c, char* base) {
     c->tsb[s][1] = cv.take<uint32_t>(c->ntiles + 1);
   }
   c->tile_cursor = cv.take<uint32_t>(c->ntiles + 1);
+  c->tcnt[0] = cv.take<uint32_t>(2 * (c->ntiles + 1));
+  c->tcnt[1] = c->tcnt[0] + (c->ntiles + 1);
   const long long nsb = (c->ntiles + 1 + 1023) / 1024;
   c->scan_block = cv.take<uint32_t>(2 * nsb + 2);
   c->acc = cv.take<long long>(c->nnodes);
@@ -346,6 +348,7 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
     c->n_binned[s] = 0;
   }
   c->nch_bound = 1;
+  c->tcounted = false;
   c->n_stirred = 0;
   c->neutrals_binned = false;
   c->next_id = 0;

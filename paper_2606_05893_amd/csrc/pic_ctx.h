@@ -57,6 +57,8 @@ struct pic_ctx {
   uint32_t* tsb[3][2];       // ntiles + 1 offsets of the binned order
   int tcur[3];               // which tsb buffer holds the current order
   uint32_t* tile_cursor;     // scatter cursors
+  uint32_t* tcnt[2];         // destination-tile counts of the tile push (e, ion)
+  bool tcounted;             // tcnt holds this step's counts
   uint32_t* scan_block;      // block sums of the tile scan
   long long n_binned[3];     // particles covered by the tile ranges
   uint2* chunks;             // (tile, piece) work list of the charged species
