@@ -12,12 +12,14 @@ resident in HBM), ms per step, the dominant kernel's roofline (algorithmic
 bytes per launch over its HIP-event-timed duration), and the CPU oracle on a
 bounded sample of the same workload.
 
-The three forms of the step run one after another on the same preload:
-plain FP64 multigrid (the JSON line's value), mixed precision, and mixed
-precision with the learned warm start, every solve to the same residual.
+The forms of the step run one after another on the same preload: plain
+FP64 multigrid (the JSON line's value), mixed precision, mixed precision
+with the learned warm start, and plain FP64 again with the previous
+potential as the start instead of the extrapolated one; every solve to the
+same residual.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--variant all|fp64|mixed|learned_mixed]
+                       [--variant all|fp64|mixed|learned_mixed|fp64_prev]
                        [--no-cpu-baseline]
 """
 import argparse
@@ -49,7 +51,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--variant", default="all",
-                    choices=["all", "fp64", "mixed", "learned_mixed"],
+                    choices=["all", "fp64", "mixed", "learned_mixed", "fp64_prev"],
                     help="fp64: plain FP64 multigrid; mixed: FP32 particles and "
                          "smoothing with FP64 refinement; learned_mixed: mixed "
                          "with the U-Net warm start (trained first on pairs "
@@ -159,12 +161,20 @@ def train_warm_start(G, W, WS, p, cap, steps=32, epochs=12):
     return net, info
 
 
-def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None):
+WARM_LABEL = {"prev": "previous phi", "extrap": "extrapolated phi",
+              "unet": "unet"}
+
+
+def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
+                warm="extrap"):
     import numpy as np
     import torch
     gpu = new_context(G, p, precision, pre, n0, cap)
     if net is not None:
+        warm = "unet"
         gpu.set_warm_start("unet", net)
+    else:
+        gpu.set_warm_start(warm)
     dt = p["dt"]
     for _ in range(warmup):
         gpu.step(dt)
@@ -197,7 +207,7 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None):
     del gpu
     torch.cuda.empty_cache()
     out = {"precision": precision,
-           "warm_start": "unet" if net is not None else "previous phi",
+           "warm_start": WARM_LABEL[warm],
            "value": psteps / el, "ms_per_step": el / steps * 1e3,
            "ms_per_step_instrumented": el_i / steps * 1e3,
            "particles_avg": psteps / steps,
@@ -234,8 +244,8 @@ def main():
 
     p = W.config(a.workload)
     pl = p["preload"]
-    variants = (["fp64", "mixed", "learned_mixed"] if a.variant == "all"
-                else [a.variant])
+    variants = (["fp64", "mixed", "learned_mixed", "fp64_prev"]
+                if a.variant == "all" else [a.variant])
     cap, per_step_n = capacities(p, a.warmup + 2 * a.steps)
     torch.cuda.set_device(0)
     net, train_info = None, None
@@ -245,9 +255,10 @@ def main():
     n0 = sum(v[0].shape[0] for v in pre.values())
     res = {}
     for v in variants:
-        prec = "fp64" if v == "fp64" else "mixed"
+        prec = "fp64" if v.startswith("fp64") else "mixed"
         res[v] = run_variant(G, p, prec, pre, n0, cap, a.steps, a.warmup,
-                             net if v == "learned_mixed" else None)
+                             net if v == "learned_mixed" else None,
+                             warm="prev" if v == "fp64_prev" else "extrap")
     del pre
     head = res[variants[0]]
     mixed = head["precision"] == "mixed"

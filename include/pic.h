@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 2
+#define PIC_ABI_VERSION 3
 
 typedef enum {
   PIC_OK = 0,
@@ -64,8 +64,9 @@ enum { PIC_FLAG_PLAIN_SMOOTHER = 1 };
 enum { PIC_WARM_ZERO = 0, PIC_WARM_GIVEN = 1 };
 /* Warm start of the field solve in pic_step / pic_field (and of
  * poisson_solve with PIC_WARM_GIVEN): the previous potential; the same
- * while recording the learned start's training pair; or the learned start. */
-enum { PIC_WS_PREV = 0, PIC_WS_RECORD = 1, PIC_WS_UNET = 2 };
+ * while recording the learned start's training pair; the learned start; or
+ * the linear extrapolation of the two previous potentials. */
+enum { PIC_WS_PREV = 0, PIC_WS_RECORD = 1, PIC_WS_UNET = 2, PIC_WS_EXTRAP = 3 };
 
 typedef struct pic_ctx pic_ctx;
 
@@ -322,8 +323,12 @@ pic_status pic_unet_train_step(pic_unet* u, const float* input_device,
 const char* pic_unet_last_error(const pic_unet* u);
 
 /* Warm start of the context's field solve.  mode PIC_WS_PREV: the previous
- * potential.  PIC_WS_RECORD: the same, and each solve records the pair for
- * pic_warm_pair.  PIC_WS_UNET: each solve also runs net (which must outlive
+ * potential.  PIC_WS_EXTRAP: 2 phi_{n-1} - phi_{n-2}, from the converged
+ * potentials of the last two step solves (a classical start, not the
+ * paper's); until two such solves follow one another (after pic_set_phi,
+ * poisson_solve, an unconverged solve or a step in another mode) the
+ * previous potential.  Checkpoints carry both.  PIC_WS_RECORD: the previous
+ * potential, and each solve records the pair for pic_warm_pair.  PIC_WS_UNET: each solve also runs net (which must outlive
  * this use and must not be driven from another stream meanwhile) on the
  * context's stream: with r0 = b - A phi_prev on the unknowns, sigma its RMS
  * and V_ref the largest Dirichlet face potential (at least 1 V), the input

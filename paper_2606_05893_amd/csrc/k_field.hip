@@ -744,6 +744,20 @@ __global__ void __launch_bounds__(1024) k_mg_tail(TailLevels A,
   }
 }
 
+// Extrapolated start of a step solve: phi_0 = 2 phi_{n-1} - phi_{n-2} at
+// every node (the Dirichlet face values are the same in both, so they stay),
+// and the history becomes phi_{n-1}.  Without a valid history the history
+// is only filled.
+__global__ void k_extrap(double* __restrict__ u, double* __restrict__ hist,
+                         long long n, int valid) {
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
+       t += (long long)gridDim.x * blockDim.x) {
+    const double a = u[t];
+    if (valid) u[t] = 2.0 * a - hist[t];
+    hist[t] = a;
+  }
+}
+
 // u += e on the level-0 unknowns (mixed form: FP64 correction accumulation).
 __global__ void k_correct(double* __restrict__ u, const float* __restrict__ e,
                           LevelC L, const Counters* dc) {
@@ -1289,7 +1303,7 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
   float* rf = c->mixed ? L0.ff : nullptr;
   float* ef = c->mixed ? L0.uf : nullptr;
   bool used_net = false;
-  if (warm && c->warm_mode != PIC_WS_PREV) {
+  if (warm && (c->warm_mode == PIC_WS_RECORD || c->warm_mode == PIC_WS_UNET)) {
     tmark(c, PIC_PH_WARM, true);
     // Record the normalised residual of the previous potential (the
     // network's input, and with the solution the training target).
@@ -1366,6 +1380,11 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
   info->warm_ratio = used_net ? c->hc.warm_ratio : 1.0;
   c->last_vcycles = c->hc.vcycles > 0 ? c->hc.vcycles : 1;
   if (!info->converged) *status = PIC_ERR_NOCONV;
+}
+
+void field_extrapolate(pic_ctx* c) {
+  k_extrap<<<kRedBlocks, kThreads, 0, c->stream>>>(
+      c->lev[0].u, c->phi_hist, c->nnodes, c->hist_valid ? 1 : 0);
 }
 
 void field_warm_target(pic_ctx* c, float* t) {

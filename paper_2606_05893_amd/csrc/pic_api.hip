@@ -180,6 +180,7 @@ size_t carve(pic_ctx* c, char* base) {
   c->dc = cv.take<Counters>(1);
   c->warm_x = cv.take<float>(2 * c->g.nxy * f.nz);
   c->warm_prev = cv.take<double>(c->nnodes);
+  c->phi_hist = cv.take<double>(c->nnodes);
   return cv.off + kAlign;
 }
 
@@ -356,6 +357,8 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->queue_used = 0;
   c->last_vcycles = 0;
   c->warm_mode = PIC_WS_PREV;
+  c->u_solved = false;
+  c->hist_valid = false;
   c->net = nullptr;
   c->warm_recorded = false;
   std::memset(&c->coll, 0, sizeof(c->coll));
@@ -478,6 +481,12 @@ pic_status pic_deposit(pic_ctx* c) {
 
 pic_status pic_field(pic_ctx* c, pic_solve_info* info) {
   if (!c) return PIC_ERR_ARG;
+  const bool extrap = c->warm_mode == PIC_WS_EXTRAP;
+  if (extrap) {
+    tmark(c, PIC_PH_WARM, true);
+    field_extrapolate(c);
+    tmark(c, PIC_PH_WARM, false);
+  }
   tmark(c, PIC_PH_RHS, true);
   field_rhs(c, nullptr);
   tmark(c, PIC_PH_RHS, false);
@@ -487,6 +496,9 @@ pic_status pic_field(pic_ctx* c, pic_solve_info* info) {
   field_solve(c, true, &loc, &st);
   tmark(c, PIC_PH_POISSON, false);
   c->last_solve = loc;
+  // The next extrapolation needs this solve and the one before it.
+  c->hist_valid = extrap && c->u_solved && st == PIC_OK;
+  c->u_solved = st == PIC_OK;
   if (info) *info = loc;
   tmark(c, PIC_PH_EFIELD, true);
   field_efield(c);
@@ -499,6 +511,7 @@ pic_status pic_field(pic_ctx* c, pic_solve_info* info) {
 
 pic_status pic_set_phi(pic_ctx* c, const double* phi) {
   if (!c || !phi) return PIC_ERR_ARG;
+  c->u_solved = c->hist_valid = false;
   if (!hip_ok(c, hipMemcpyAsync(c->lev[0].u, phi, c->nnodes * sizeof(double),
                                 hipMemcpyDeviceToDevice, c->stream),
               "phi copy"))
@@ -589,6 +602,7 @@ pic_status pic_step(pic_ctx* c, double dt, pic_absorbed* out, pic_diag* diag) {
 pic_status poisson_solve(pic_ctx* c, const double* rho, double* phi,
                          int32_t warm, pic_solve_info* info) {
   if (!c || !rho || !phi) return PIC_ERR_ARG;
+  c->u_solved = c->hist_valid = false;
   if (warm == PIC_WARM_GIVEN) {
     if (!hip_ok(c, hipMemcpyAsync(c->lev[0].u, phi, c->nnodes * sizeof(double),
                                   hipMemcpyDeviceToDevice, c->stream),
@@ -612,7 +626,8 @@ pic_status poisson_solve(pic_ctx* c, const double* rho, double* phi,
 
 pic_status pic_set_warm_start(pic_ctx* c, int32_t mode, pic_unet* net) {
   if (!c) return PIC_ERR_ARG;
-  if (mode != PIC_WS_PREV && mode != PIC_WS_RECORD && mode != PIC_WS_UNET)
+  if (mode != PIC_WS_PREV && mode != PIC_WS_RECORD && mode != PIC_WS_UNET &&
+      mode != PIC_WS_EXTRAP)
     return set_err(c, PIC_ERR_ARG, "unknown warm-start mode");
   if (mode == PIC_WS_UNET) {
     if (!net) return set_err(c, PIC_ERR_ARG, "learned warm start needs a network");
@@ -688,19 +703,20 @@ struct CkptHeader {
   int64_t step;
   uint64_t next_id;
   int64_t n[3];
-  int32_t last_vcycles, pad2;
+  int32_t last_vcycles, hist_valid;  // bit 0: history, bit 1: u solved
   pic_collisions coll;
   pic_sources src;
   int64_t nnodes;
 };
-constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '1'};
+constexpr char kCkptMagic[8] = {'P', 'I', 'C', 'C', 'K', 'P', 'T', '2'};
 
 size_t record_bytes(const pic_ctx* c) { return c->mixed ? 36 : 56; }
 
 size_t ckpt_bytes(const pic_ctx* c) {
   size_t b = sizeof(CkptHeader);
   for (int s = 0; s < 3; ++s) b += (size_t)c->n[s] * record_bytes(c);
-  return b + (size_t)c->nnodes * sizeof(double);
+  // The potential and the one before it (extrapolated start).
+  return b + 2 * (size_t)c->nnodes * sizeof(double);
 }
 
 }  // namespace
@@ -732,6 +748,7 @@ pic_status pic_checkpoint_save(pic_ctx* c, void* host, size_t bytes) {
   h.next_id = c->next_id;
   for (int s = 0; s < 3; ++s) h.n[s] = c->n[s];
   h.last_vcycles = c->last_vcycles;
+  h.hist_valid = (c->hist_valid ? 1 : 0) | (c->u_solved ? 2 : 0);
   h.coll = c->coll;
   h.src = c->src;
   h.nnodes = c->nnodes;
@@ -751,8 +768,11 @@ pic_status pic_checkpoint_save(pic_ctx* c, void* host, size_t bytes) {
       off += nb;
     }
   }
-  if (!hip_ok(c, hipMemcpyAsync(out + off, c->lev[0].u,
-                                (size_t)c->nnodes * sizeof(double),
+  const size_t nb = (size_t)c->nnodes * sizeof(double);
+  if (!hip_ok(c, hipMemcpyAsync(out + off, c->lev[0].u, nb,
+                                hipMemcpyDeviceToHost, c->stream),
+              "checkpoint copy") ||
+      !hip_ok(c, hipMemcpyAsync(out + off + nb, c->phi_hist, nb,
                                 hipMemcpyDeviceToHost, c->stream),
               "checkpoint copy") ||
       !hip_ok(c, hipStreamSynchronize(c->stream), "synchronise"))
@@ -776,7 +796,7 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
   for (int s = 0; s < 3; ++s)
     if (h.n[s] < 0 || h.n[s] > f.capacity[s])
       return set_err(c, PIC_ERR_CAPACITY, "checkpoint exceeds capacity");
-  size_t need = sizeof(CkptHeader) + (size_t)c->nnodes * sizeof(double);
+  size_t need = sizeof(CkptHeader) + 2 * (size_t)c->nnodes * sizeof(double);
   for (int s = 0; s < 3; ++s) need += (size_t)h.n[s] * record_bytes(c);
   if (bytes < need) return set_err(c, PIC_ERR_ARG, "checkpoint truncated");
   pic_status st = pic_set_collisions(c, &h.coll);
@@ -798,11 +818,16 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
       off += nb;
     }
   }
-  if (!hip_ok(c, hipMemcpyAsync(c->lev[0].u, in + off,
-                                (size_t)c->nnodes * sizeof(double),
+  const size_t nb = (size_t)c->nnodes * sizeof(double);
+  if (!hip_ok(c, hipMemcpyAsync(c->lev[0].u, in + off, nb,
+                                hipMemcpyHostToDevice, c->stream),
+              "restore copy") ||
+      !hip_ok(c, hipMemcpyAsync(c->phi_hist, in + off + nb, nb,
                                 hipMemcpyHostToDevice, c->stream),
               "restore copy"))
     return PIC_ERR_HIP;
+  c->hist_valid = (h.hist_valid & 1) != 0;
+  c->u_solved = (h.hist_valid & 2) != 0;
   // Keys from the restored layout, then the binning pass as for a load.
   for (int s = 0; s < 3; ++s) {
     parts_restore_keys(c, s, h.n[s]);

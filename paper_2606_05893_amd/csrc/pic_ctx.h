@@ -124,6 +124,9 @@ struct pic_ctx {
   float* warm_x;             // (nz, ny, nx, 2) network input
   double* warm_prev;         // potential before the warm start, all nodes
   bool warm_recorded;
+  double* phi_hist;          // potential of the step solve before the last
+  bool u_solved;             // lev[0].u is the last step solve's result
+  bool hist_valid;           // phi_hist is the step solve before that one
   std::string err;
 
   // Optional phase timing (HIP events on the context's stream).
@@ -155,6 +158,9 @@ void field_efield(pic_ctx* c);
 // Target (phi - phi_prev) / sigma of the last recorded solve, (nz, ny, nx).
 void field_warm_target(pic_ctx* c, float* t);
 void field_phi_to_level0(pic_ctx* c);
+// Extrapolated start (phi = 2 phi - phi_hist, phi_hist = old phi) when the
+// history is valid, else the history is just filled.
+void field_extrapolate(pic_ctx* c);
 
 // ---- particles (k_particles.hip) -------------------------------------------
 void parts_deposit(pic_ctx* c);

@@ -125,7 +125,7 @@ EXPORTS = {
 PHASES = ("deposit", "rhs", "poisson", "efield", "sources", "push_neutral",
           "push_ion", "push_electron", "collide", "absorbed", "bin", "warm",
           "smooth_l0")
-WARM_MODES = {"prev": 0, "record": 1, "unet": 2}
+WARM_MODES = {"prev": 0, "record": 1, "unet": 2, "extrap": 3}
 
 _lib = None
 

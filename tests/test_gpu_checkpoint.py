@@ -38,19 +38,26 @@ def state(gpu):
     return out
 
 
+@pytest.mark.parametrize("warm", ["prev", "extrap"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_resume_matches_uninterrupted_run(gpu_lib, precision):
+def test_resume_matches_uninterrupted_run(gpu_lib, precision, warm):
+    """With the extrapolated start the checkpoint carries the potential of
+    the solve before the last too, so the resumed run extrapolates from the
+    same pair."""
     from paper_2606_05893_amd import pic as G
     p = case(precision)
     dt = p["dt"]
     a = make(p)
+    a.set_warm_start(warm)
     da = [a.step(dt)[1] for _ in range(6)]
     b = make(p)
+    b.set_warm_start(warm)
     for _ in range(3):
         b.step(dt)
     blob = b.checkpoint()
     del b
     c = G.Pic(p, capacity=(40000, 40000, 40000))
+    c.set_warm_start(warm)
     c.restore(blob)
     dc = [c.step(dt)[1] for _ in range(3)]
     assert sum(d["ionisations"] for d in da) > 0

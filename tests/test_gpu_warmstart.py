@@ -161,3 +161,45 @@ def test_trained_network_gains_on_held_out_seed(gpu_lib, loss):
         # never costs one.
         assert ratio < 0.3
         assert vc_unet <= vc_prev
+
+
+def test_extrapolated_start(gpu_lib):
+    """PIC_WS_EXTRAP starts step n's solve from 2 phi_{n-1} - phi_{n-2} once
+    two converged step solves precede it (the previous potential before
+    that): the solve's start residual equals the oracle's residual of that
+    potential.  pic_set_phi falls back to the given potential.  Every
+    solve converges, with no more V-cycles in all than from the previous
+    potential."""
+    p = case()
+    g = grid_of(p)
+    k0, k1 = g.k_range
+
+    def rel(phi, acc):
+        b = O.rhs(acc, g, p["w_sp"])
+        r = P.residual(phi, b, g)
+        return np.linalg.norm(r[k0:k1 + 1]) / np.linalg.norm(b[k0:k1 + 1])
+
+    gpu = make(p, 5)
+    gpu.set_warm_start("extrap")
+    phis, vc = [], []
+    for n in range(6):
+        _, d = gpu.step(p["dt"])
+        acc, phi, _ = (a.cpu().numpy() for a in gpu.read_fields())
+        assert d["solve"]["converged"] == 1
+        if n >= 2:
+            start = 2.0 * phis[-1] - phis[-2]
+        elif n == 1:
+            start = phis[-1]
+        if n >= 1:
+            assert np.isclose(d["solve"]["rel_residual0"], rel(start, acc),
+                              rtol=1e-6), n
+        phis.append(phi)
+        vc.append(d["solve"]["vcycles"])
+    gpu.set_phi(phis[-1])
+    _, d = gpu.step(p["dt"])
+    acc = gpu.read_fields()[0].cpu().numpy()
+    assert np.isclose(d["solve"]["rel_residual0"], rel(phis[-1], acc), rtol=1e-6)
+    ref = make(p, 5)
+    vp = [ref.step(p["dt"])[1]["solve"]["vcycles"] for _ in range(6)]
+    print("V-cycles, extrapolated start:", vc, "previous potential:", vp)
+    assert sum(vc) <= sum(vp)
