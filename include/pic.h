@@ -59,8 +59,12 @@ enum { PIC_BC_DIRICHLET = 0, PIC_BC_NEUMANN = 1 };
 enum { PIC_FP64 = 0, PIC_MIXED = 1 };
 enum { PIC_ION_LOTZ = 0, PIC_ION_CONST = 1 };
 /* PIC_FLAG_PLAIN_SMOOTHER: smooth with one launch per colour and sweep
- * instead of the fused two-sweep pass (same arithmetic, same results). */
-enum { PIC_FLAG_PLAIN_SMOOTHER = 1 };
+ * instead of the fused two-sweep pass (same arithmetic, same results).
+ * PIC_FLAG_MG_ALL_LEVELS: run the V-cycle down to the coarsest level
+ * instead of solving the first coarse level of at most 32 x 32 nodes per
+ * plane and 256 unknown planes exactly (2-D DFT in x, y, tridiagonal solve
+ * in z per mode). */
+enum { PIC_FLAG_PLAIN_SMOOTHER = 1, PIC_FLAG_MG_ALL_LEVELS = 2 };
 enum { PIC_WARM_ZERO = 0, PIC_WARM_GIVEN = 1 };
 /* Warm start of the field solve in pic_step / pic_field (and of
  * poisson_solve with PIC_WARM_GIVEN): the previous potential; the same

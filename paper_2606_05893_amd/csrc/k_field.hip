@@ -1143,6 +1143,211 @@ int tail_first(const pic_ctx* c) {
   return l;
 }
 
+// ---- exact solve of one coarse level -----------------------------------------
+// With x and y periodic, the 7-point operator acts on the 2-D Fourier modes
+// of a plane one by one: mode (kx, ky) has 6 - 2cos(2 pi kx/nx) -
+// 2cos(2 pi ky/ny) on the diagonal and the z neighbours off it, so the level
+// equation 6u - sum(neighbours) = h2 f becomes one tridiagonal system in z
+// per mode over the unknown planes (a Neumann face row takes its inner
+// neighbour twice; a Dirichlet face's correction is zero).  A real plane
+// needs the modes kx = 0..nx/2 only.  Spectrum layout: [plane][mode][re,im],
+// mode = ky (nx/2 + 1) + kx.
+
+// Twiddles e^{2 pi i q / n} = (cos, sin), q = 0..n-1.
+template <typename T>
+__device__ __forceinline__ void fill_twiddles(T* tw, int n) {
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * q / n, &sn, &cs);
+    tw[2 * q] = (T)cs;
+    tw[2 * q + 1] = (T)sn;
+  }
+}
+
+// Forward: h2 f of one unknown plane -> its spectrum (row DFTs of the real
+// plane, then column DFTs of the half spectrum).
+template <typename T>
+__global__ void __launch_bounds__(256) k_spec_fwd(LevelC L,
+                                                  const T* __restrict__ f,
+                                                  T* __restrict__ s, int nm,
+                                                  const Counters* dc) {
+  __shared__ T fp[kSpecMaxXY * kSpecMaxXY];
+  __shared__ T rr[kSpecMaxXY * (kSpecMaxXY / 2 + 1) * 2];
+  __shared__ T twx[2 * kSpecMaxXY], twy[2 * kSpecMaxXY];
+  if (dc->done) return;
+  const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1;
+  const int p = blockIdx.x;
+  const T* src = f + (long long)(L.k0 + p) * L.nxy;
+  for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) fp[q] = src[q];
+  fill_twiddles(twx, nx);
+  fill_twiddles(twy, ny);
+  __syncthreads();
+  // R(j, kx) = sum_i f(i, j) e^{-2 pi i kx i / nx}
+  for (int q = threadIdx.x; q < ny * nxh; q += blockDim.x) {
+    const int j = q / nxh, kx = q % nxh;
+    T re = T(0), im = T(0);
+    int w = 0;  // kx * i mod nx
+    for (int i = 0; i < nx; ++i) {
+      const T v = fp[j * nx + i];
+      re = re + v * twx[2 * w];
+      im = im - v * twx[2 * w + 1];
+      w += kx;
+      if (w >= nx) w -= nx;
+    }
+    rr[2 * q] = re;
+    rr[2 * q + 1] = im;
+  }
+  __syncthreads();
+  // F(ky, kx) = sum_j R(j, kx) e^{-2 pi i ky j / ny}, times h2.
+  const T h2 = (T)L.h2;
+  T* out = s + (long long)p * 2 * nm;
+  for (int q = threadIdx.x; q < nm; q += blockDim.x) {
+    const int ky = q / nxh, kx = q % nxh;
+    T re = T(0), im = T(0);
+    int w = 0;
+    for (int j = 0; j < ny; ++j) {
+      const T a = rr[2 * (j * nxh + kx)], b = rr[2 * (j * nxh + kx) + 1];
+      const T c = twy[2 * w], sn = twy[2 * w + 1];
+      re = re + (a * c + b * sn);
+      im = im + (b * c - a * sn);
+      w += ky;
+      if (w >= ny) w -= ny;
+    }
+    out[2 * q] = h2 * re;
+    out[2 * q + 1] = h2 * im;
+  }
+}
+
+// The tridiagonal systems of kSpecG modes per workgroup, staged in LDS:
+// one thread per (mode, real or imaginary part) runs the elimination (the
+// pivots from the mode's diagonal as it goes, the eliminated upper
+// coefficients kept in LDS for the back substitution); all threads stage.
+template <typename T>
+__global__ void __launch_bounds__(256) k_spec_tri(LevelC L, T* __restrict__ s,
+                                                  int nm, int G,
+                                                  const Counters* dc) {
+  extern __shared__ __attribute__((aligned(16))) char spec_lds[];
+  if (dc->done) return;
+  const int np = L.k1 - L.k0 + 1;
+  const int m0 = blockIdx.x * G;
+  const int gm = nm - m0 < G ? nm - m0 : G;  // modes of this workgroup
+  const int w2 = 2 * gm;                     // columns (re, im)
+  T* col = reinterpret_cast<T*>(spec_lds);   // [plane][2G]
+  T* cpl = col + (long long)np * 2 * G;      // [plane][G]
+  for (int q = threadIdx.x; q < np * w2; q += blockDim.x) {
+    const int p = q / w2, c = q % w2;
+    col[p * 2 * G + c] = s[(long long)p * 2 * nm + 2 * m0 + c];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < w2) {
+    const int m = m0 + (t >> 1);
+    const int nxh = L.nx / 2 + 1;
+    const int kx = m % nxh, ky = m / nxh;
+    const T d = (T)(6.0 - 2.0 * cospi(2.0 * kx / L.nx) - 2.0 * cospi(2.0 * ky / L.ny));
+    T cprev = T(0), prev = T(0);
+    for (int p = 0; p < np; ++p) {
+      const int k = L.k0 + p;
+      const T lo = p == 0 ? T(0) : (k == L.nz ? T(-2) : T(-1));
+      const T up = p == np - 1 ? T(0) : (k == 0 ? T(-2) : T(-1));
+      const T inv = T(1) / (d - lo * cprev);
+      cprev = up * inv;
+      if (!(t & 1)) cpl[p * G + (t >> 1)] = cprev;
+      prev = (col[p * 2 * G + t] - lo * prev) * inv;
+      col[p * 2 * G + t] = prev;
+    }
+  }
+  __syncthreads();
+  if (t < w2) {
+    T next = col[(np - 1) * 2 * G + t];
+    for (int p = np - 2; p >= 0; --p) {
+      next = col[p * 2 * G + t] - cpl[p * G + (t >> 1)] * next;
+      col[p * 2 * G + t] = next;
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < np * w2; q += blockDim.x) {
+    const int p = q / w2, c = q % w2;
+    s[(long long)p * 2 * nm + 2 * m0 + c] = col[p * 2 * G + c];
+  }
+}
+
+// Inverse: the solved spectrum of one plane -> u (column inverse DFTs,
+// then the real row inverse DFT: kx = 0 and nx/2 once, the others twice).
+template <typename T>
+__global__ void __launch_bounds__(256) k_spec_inv(LevelC L,
+                                                  const T* __restrict__ s,
+                                                  T* __restrict__ u, int nm,
+                                                  const Counters* dc) {
+  __shared__ T sp[kSpecMaxXY * (kSpecMaxXY / 2 + 1) * 2];
+  __shared__ T gg[kSpecMaxXY * (kSpecMaxXY / 2 + 1) * 2];
+  __shared__ T twx[2 * kSpecMaxXY], twy[2 * kSpecMaxXY];
+  if (dc->done) return;
+  const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1;
+  const int p = blockIdx.x;
+  const T* in = s + (long long)p * 2 * nm;
+  for (int q = threadIdx.x; q < 2 * nm; q += blockDim.x) sp[q] = in[q];
+  fill_twiddles(twx, nx);
+  fill_twiddles(twy, ny);
+  __syncthreads();
+  // G(j, kx) = sum_ky S(ky, kx) e^{+2 pi i ky j / ny}
+  for (int q = threadIdx.x; q < ny * nxh; q += blockDim.x) {
+    const int j = q / nxh, kx = q % nxh;
+    T re = T(0), im = T(0);
+    int w = 0;
+    for (int ky = 0; ky < ny; ++ky) {
+      const T a = sp[2 * (ky * nxh + kx)], b = sp[2 * (ky * nxh + kx) + 1];
+      const T c = twy[2 * w], sn = twy[2 * w + 1];
+      re = re + (a * c - b * sn);
+      im = im + (a * sn + b * c);
+      w += j;
+      if (w >= ny) w -= ny;
+    }
+    gg[2 * q] = re;
+    gg[2 * q + 1] = im;
+  }
+  __syncthreads();
+  const T inv_n = T(1) / (T)(nx * ny);
+  T* dst = u + (long long)(L.k0 + p) * L.nxy;
+  const int kn = nx / 2;
+  for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) {
+    const int j = q / nx, i = q % nx;
+    const T* g = gg + 2 * j * nxh;
+    T acc = g[0] + ((i & 1) ? -g[2 * kn] : g[2 * kn]);
+    T two = T(0);
+    int w = i;  // kx * i mod nx
+    for (int kx = 1; kx < kn; ++kx) {
+      two = two + (g[2 * kx] * twx[2 * w] - g[2 * kx + 1] * twx[2 * w + 1]);
+      w += i;
+      if (w >= nx) w -= nx;
+    }
+    dst[q] = (acc + T(2) * two) * inv_n;
+  }
+}
+
+// Modes per workgroup of k_spec_tri: its LDS holds np x 3G values.
+template <typename T>
+int spec_group(int np) {
+  int G = 64;
+  while (G > 1 && (long long)np * 3 * G * sizeof(T) > 64 * 1024) G /= 2;
+  return G;
+}
+
+template <typename T>
+void spectral_solve(pic_ctx* c, int l) {
+  hipStream_t st = c->stream;
+  Level& L = c->lev[l];
+  const LevelC Lc = level_c(c, l);
+  const int nm = c->spec_modes, np = c->spec_planes;
+  T* s = reinterpret_cast<T*>(c->spec_s);
+  const int G = spec_group<T>(np);
+  const size_t lds = (size_t)np * 3 * G * sizeof(T);
+  k_spec_fwd<T><<<(unsigned)np, 256, 0, st>>>(Lc, lev_f<T>(L), s, nm, c->dc);
+  k_spec_tri<T><<<(unsigned)((nm + G - 1) / G), 256, lds, st>>>(Lc, s, nm, G,
+                                                               c->dc);
+  k_spec_inv<T><<<(unsigned)np, 256, 0, st>>>(Lc, s, lev_u<T>(L), nm, c->dc);
+}
+
 // Workgroups of k_smooth2<T, *> the current device runs at once.
 template <typename T>
 long long smooth_slots() {
@@ -1168,6 +1373,10 @@ long long smooth_slots() {
 template <typename T>
 void vcycle(pic_ctx* c, int l) {
   hipStream_t st = c->stream;
+  if (l == c->spec_level) {
+    spectral_solve<T>(c, l);
+    return;
+  }
   const int tf = tail_first<T>(c);
   if (l == c->nlev - 1 && tf == c->nlev) {
     k_coarse_global<T><<<1, 1024, 0, st>>>(lev_u<T>(c->lev[l]),

@@ -152,6 +152,11 @@ size_t carve(pic_ctx* c, char* base) {
     }
   }
   c->partials = cv.take<double>(c->npartials);
+  {
+    const long long es = mixed ? 4 : 8;
+    const long long pm = (long long)c->spec_planes * c->spec_modes;
+    c->spec_s = cv.take<char>(2 * pm * es);
+  }
   c->part_n = cv.take<double>(neutral_push_blocks(f.capacity[1]));
   c->qpartials = cv.take<long long>(1024);
   c->ncount = cv.take<int>(c->ncells);
@@ -209,6 +214,24 @@ void derive(pic_ctx* c) {
     L.nnodes = (long long)L.nx * L.ny * (L.nz + 1);
     L.h2 = h2;
     h2 *= 4.0;
+  }
+  // The first coarse level small enough for the exact solve.
+  c->spec_level = -1;
+  c->spec_modes = c->spec_planes = 0;
+  if (!(f.flags & PIC_FLAG_MG_ALL_LEVELS)) {
+    for (int l = 1; l < c->nlev; ++l) {
+      const Level& L = c->lev[l];
+      const int k0 = f.bc_lo == PIC_BC_DIRICHLET ? 1 : 0;
+      const int k1 = f.bc_hi == PIC_BC_DIRICHLET ? L.nz - 1 : L.nz;
+      if (L.nx >= 2 && L.ny >= 2 && !(L.nx & 1) && !(L.ny & 1) &&
+          L.nx <= kSpecMaxXY && L.ny <= kSpecMaxXY && k1 >= k0 &&
+          k1 - k0 + 1 <= kSpecMaxPlanes) {
+        c->spec_level = l;
+        c->spec_modes = L.ny * (L.nx / 2 + 1);
+        c->spec_planes = k1 - k0 + 1;
+        break;
+      }
+    }
   }
   long long maxcap = std::max(f.capacity[0], std::max(f.capacity[1], f.capacity[2]));
   // Chunk list of the charged species: at most one chunk per tile plus one

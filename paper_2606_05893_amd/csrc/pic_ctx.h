@@ -33,6 +33,10 @@ struct Level {
   float* usf;          // pre-smoothing pass, source of the post-smoothing
 };
 
+// Largest coarse level the exact (spectral) solve takes: nodes per axis in
+// x and y, unknown planes in z.
+constexpr int kSpecMaxXY = 32, kSpecMaxPlanes = 256;
+
 struct QueueCall {
   int species;
   long long n, offset;
@@ -75,6 +79,11 @@ struct pic_ctx {
   double* E;                 // FP64: 4 doubles per node; mixed: 4 floats
   int nlev;
   pic::Level lev[16];
+  // Exact solve of one coarse level (DFT in x, y; tridiagonal in z per
+  // mode), in the V-cycle's precision; spec_level < 0: none.
+  int spec_level;
+  int spec_modes, spec_planes;   // ny * (nx/2 + 1); unknown planes
+  void* spec_s;                  // spectrum, planes x modes x (re, im)
   double* partials;          // reduction partials
   double* part_n;            // neutral push partials (one per workgroup)
   int npartials;

@@ -18,6 +18,7 @@ DIRICHLET, NEUMANN = 0, 1
 FP64, MIXED = 0, 1
 ION_LOTZ, ION_CONST = 0, 1
 FLAG_PLAIN_SMOOTHER = 1
+FLAG_MG_ALL_LEVELS = 2
 
 STATUS = {0: "PIC_OK", -1: "PIC_ERR_ARG", -2: "PIC_ERR_CAPACITY",
           -3: "PIC_ERR_NOCONV", -4: "PIC_ERR_NONFINITE", -5: "PIC_ERR_HIP",
