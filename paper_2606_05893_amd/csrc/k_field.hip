@@ -1153,6 +1153,30 @@ int tail_first(const pic_ctx* c) {
 // needs the modes kx = 0..nx/2 only.  Spectrum layout: [plane][mode][re,im],
 // mode = ky (nx/2 + 1) + kx.
 
+// Elimination factors per mode, which depend on the grid only: the inverse
+// pivots and the eliminated upper coefficients, plane by plane (layout
+// [plane][mode]).
+template <typename T>
+__global__ void k_spec_factor(LevelC L, T* __restrict__ mi,
+                              T* __restrict__ cp, int nm) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= nm) return;
+  const int nxh = L.nx / 2 + 1;
+  const int kx = m % nxh, ky = m / nxh;
+  const double d = 6.0 - 2.0 * cospi(2.0 * kx / L.nx) - 2.0 * cospi(2.0 * ky / L.ny);
+  const int np = L.k1 - L.k0 + 1;
+  double cprev = 0.0;
+  for (int p = 0; p < np; ++p) {
+    const int k = L.k0 + p;
+    const double lo = p == 0 ? 0.0 : (k == L.nz ? -2.0 : -1.0);
+    const double up = p == np - 1 ? 0.0 : (k == 0 ? -2.0 : -1.0);
+    const double inv = 1.0 / (d - lo * cprev);
+    cprev = up * inv;
+    mi[(long long)p * nm + m] = (T)inv;
+    cp[(long long)p * nm + m] = (T)cprev;
+  }
+}
+
 // Twiddles e^{2 pi i q / n} = (cos, sin), q = 0..n-1.
 template <typename T>
 __device__ __forceinline__ void fill_twiddles(T* tw, int n) {
@@ -1187,6 +1211,7 @@ __global__ void __launch_bounds__(256) k_spec_fwd(LevelC L,
     const int j = q / nxh, kx = q % nxh;
     T re = T(0), im = T(0);
     int w = 0;  // kx * i mod nx
+#pragma unroll 8
     for (int i = 0; i < nx; ++i) {
       const T v = fp[j * nx + i];
       re = re + v * twx[2 * w];
@@ -1205,6 +1230,7 @@ __global__ void __launch_bounds__(256) k_spec_fwd(LevelC L,
     const int ky = q / nxh, kx = q % nxh;
     T re = T(0), im = T(0);
     int w = 0;
+#pragma unroll 8
     for (int j = 0; j < ny; ++j) {
       const T a = rr[2 * (j * nxh + kx)], b = rr[2 * (j * nxh + kx) + 1];
       const T c = twy[2 * w], sn = twy[2 * w + 1];
@@ -1218,12 +1244,14 @@ __global__ void __launch_bounds__(256) k_spec_fwd(LevelC L,
   }
 }
 
-// The tridiagonal systems of kSpecG modes per workgroup, staged in LDS:
-// one thread per (mode, real or imaginary part) runs the elimination (the
-// pivots from the mode's diagonal as it goes, the eliminated upper
-// coefficients kept in LDS for the back substitution); all threads stage.
+// The tridiagonal systems of G modes per workgroup, staged in LDS with
+// their elimination factors: one thread per (mode, real or imaginary part)
+// runs the forward elimination and the back substitution (a multiply-add
+// chain: the factors were computed once); all threads stage.
 template <typename T>
 __global__ void __launch_bounds__(256) k_spec_tri(LevelC L, T* __restrict__ s,
+                                                  const T* __restrict__ mi,
+                                                  const T* __restrict__ cp,
                                                   int nm, int G,
                                                   const Counters* dc) {
   extern __shared__ __attribute__((aligned(16))) char spec_lds[];
@@ -1233,35 +1261,33 @@ __global__ void __launch_bounds__(256) k_spec_tri(LevelC L, T* __restrict__ s,
   const int gm = nm - m0 < G ? nm - m0 : G;  // modes of this workgroup
   const int w2 = 2 * gm;                     // columns (re, im)
   T* col = reinterpret_cast<T*>(spec_lds);   // [plane][2G]
-  T* cpl = col + (long long)np * 2 * G;      // [plane][G]
+  T* smi = col + (long long)np * 2 * G;      // [plane][G]
+  T* scp = smi + (long long)np * G;          // [plane][G]
   for (int q = threadIdx.x; q < np * w2; q += blockDim.x) {
     const int p = q / w2, c = q % w2;
     col[p * 2 * G + c] = s[(long long)p * 2 * nm + 2 * m0 + c];
   }
+  for (int q = threadIdx.x; q < np * gm; q += blockDim.x) {
+    const int p = q / gm, c = q % gm;
+    smi[p * G + c] = mi[(long long)p * nm + m0 + c];
+    scp[p * G + c] = cp[(long long)p * nm + m0 + c];
+  }
   __syncthreads();
   const int t = threadIdx.x;
   if (t < w2) {
-    const int m = m0 + (t >> 1);
-    const int nxh = L.nx / 2 + 1;
-    const int kx = m % nxh, ky = m / nxh;
-    const T d = (T)(6.0 - 2.0 * cospi(2.0 * kx / L.nx) - 2.0 * cospi(2.0 * ky / L.ny));
-    T cprev = T(0), prev = T(0);
+    const int g = t >> 1;
+    T prev = T(0);
+#pragma unroll 4
     for (int p = 0; p < np; ++p) {
       const int k = L.k0 + p;
       const T lo = p == 0 ? T(0) : (k == L.nz ? T(-2) : T(-1));
-      const T up = p == np - 1 ? T(0) : (k == 0 ? T(-2) : T(-1));
-      const T inv = T(1) / (d - lo * cprev);
-      cprev = up * inv;
-      if (!(t & 1)) cpl[p * G + (t >> 1)] = cprev;
-      prev = (col[p * 2 * G + t] - lo * prev) * inv;
+      prev = (col[p * 2 * G + t] - lo * prev) * smi[p * G + g];
       col[p * 2 * G + t] = prev;
     }
-  }
-  __syncthreads();
-  if (t < w2) {
-    T next = col[(np - 1) * 2 * G + t];
+    T next = prev;
+#pragma unroll 4
     for (int p = np - 2; p >= 0; --p) {
-      next = col[p * 2 * G + t] - cpl[p * G + (t >> 1)] * next;
+      next = col[p * 2 * G + t] - scp[p * G + g] * next;
       col[p * 2 * G + t] = next;
     }
   }
@@ -1295,6 +1321,7 @@ __global__ void __launch_bounds__(256) k_spec_inv(LevelC L,
     const int j = q / nxh, kx = q % nxh;
     T re = T(0), im = T(0);
     int w = 0;
+#pragma unroll 8
     for (int ky = 0; ky < ny; ++ky) {
       const T a = sp[2 * (ky * nxh + kx)], b = sp[2 * (ky * nxh + kx) + 1];
       const T c = twy[2 * w], sn = twy[2 * w + 1];
@@ -1316,6 +1343,7 @@ __global__ void __launch_bounds__(256) k_spec_inv(LevelC L,
     T acc = g[0] + ((i & 1) ? -g[2 * kn] : g[2 * kn]);
     T two = T(0);
     int w = i;  // kx * i mod nx
+#pragma unroll 8
     for (int kx = 1; kx < kn; ++kx) {
       two = two + (g[2 * kx] * twx[2 * w] - g[2 * kx + 1] * twx[2 * w + 1]);
       w += i;
@@ -1325,11 +1353,11 @@ __global__ void __launch_bounds__(256) k_spec_inv(LevelC L,
   }
 }
 
-// Modes per workgroup of k_spec_tri: its LDS holds np x 3G values.
+// Modes per workgroup of k_spec_tri: its LDS holds np x 4G values.
 template <typename T>
 int spec_group(int np) {
   int G = 64;
-  while (G > 1 && (long long)np * 3 * G * sizeof(T) > 64 * 1024) G /= 2;
+  while (G > 1 && (long long)np * 4 * G * sizeof(T) > 64 * 1024) G /= 2;
   return G;
 }
 
@@ -1340,11 +1368,17 @@ void spectral_solve(pic_ctx* c, int l) {
   const LevelC Lc = level_c(c, l);
   const int nm = c->spec_modes, np = c->spec_planes;
   T* s = reinterpret_cast<T*>(c->spec_s);
+  T* mi = reinterpret_cast<T*>(c->spec_m);
+  T* cp = reinterpret_cast<T*>(c->spec_c);
+  if (!c->spec_ready) {
+    k_spec_factor<T><<<nblocks(nm), kThreads, 0, st>>>(Lc, mi, cp, nm);
+    c->spec_ready = true;
+  }
   const int G = spec_group<T>(np);
-  const size_t lds = (size_t)np * 3 * G * sizeof(T);
+  const size_t lds = (size_t)np * 4 * G * sizeof(T);
   k_spec_fwd<T><<<(unsigned)np, 256, 0, st>>>(Lc, lev_f<T>(L), s, nm, c->dc);
-  k_spec_tri<T><<<(unsigned)((nm + G - 1) / G), 256, lds, st>>>(Lc, s, nm, G,
-                                                               c->dc);
+  k_spec_tri<T><<<(unsigned)((nm + G - 1) / G), 256, lds, st>>>(
+      Lc, s, mi, cp, nm, G, c->dc);
   k_spec_inv<T><<<(unsigned)np, 256, 0, st>>>(Lc, s, lev_u<T>(L), nm, c->dc);
 }
 

@@ -156,6 +156,8 @@ size_t carve(pic_ctx* c, char* base) {
     const long long es = mixed ? 4 : 8;
     const long long pm = (long long)c->spec_planes * c->spec_modes;
     c->spec_s = cv.take<char>(2 * pm * es);
+    c->spec_m = cv.take<char>(pm * es);
+    c->spec_c = cv.take<char>(pm * es);
   }
   c->part_n = cv.take<double>(neutral_push_blocks(f.capacity[1]));
   c->qpartials = cv.take<long long>(1024);
@@ -380,6 +382,7 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->queue_used = 0;
   c->last_vcycles = 0;
   c->warm_mode = PIC_WS_PREV;
+  c->spec_ready = false;
   c->u_solved = false;
   c->hist_valid = false;
   c->net = nullptr;
