@@ -61,9 +61,9 @@ enum { PIC_ION_LOTZ = 0, PIC_ION_CONST = 1 };
 /* PIC_FLAG_PLAIN_SMOOTHER: smooth with one launch per colour and sweep
  * instead of the fused two-sweep pass (same arithmetic, same results).
  * PIC_FLAG_MG_ALL_LEVELS: run the V-cycle down to the coarsest level
- * instead of solving the first coarse level of at most 32 x 32 nodes per
- * plane and 256 unknown planes exactly (2-D DFT in x, y, tridiagonal solve
- * in z per mode). */
+ * instead of solving the first coarse level small enough exactly (at most
+ * 64 x 64 nodes per plane if both are powers of two, else 32 x 32, and 256
+ * unknown planes: 2-D DFT in x, y, tridiagonal solve in z per mode). */
 enum { PIC_FLAG_PLAIN_SMOOTHER = 1, PIC_FLAG_MG_ALL_LEVELS = 2 };
 enum { PIC_WARM_ZERO = 0, PIC_WARM_GIVEN = 1 };
 /* Warm start of the field solve in pic_step / pic_field (and of

@@ -1247,7 +1247,8 @@ __global__ void __launch_bounds__(256) k_spec_fwd(LevelC L,
 // The tridiagonal systems of G modes per workgroup, staged in LDS with
 // their elimination factors: one thread per (mode, real or imaginary part)
 // runs the forward elimination and the back substitution (a multiply-add
-// chain: the factors were computed once); all threads stage.
+// chain: the factors were computed once), with the operands of the next
+// four planes already loaded into registers; all threads stage.
 template <typename T>
 __global__ void __launch_bounds__(256) k_spec_tri(LevelC L, T* __restrict__ s,
                                                   const T* __restrict__ mi,
@@ -1276,19 +1277,52 @@ __global__ void __launch_bounds__(256) k_spec_tri(LevelC L, T* __restrict__ s,
   const int t = threadIdx.x;
   if (t < w2) {
     const int g = t >> 1;
-    T prev = T(0);
-#pragma unroll 4
-    for (int p = 0; p < np; ++p) {
-      const int k = L.k0 + p;
-      const T lo = p == 0 ? T(0) : (k == L.nz ? T(-2) : T(-1));
-      prev = (col[p * 2 * G + t] - lo * prev) * smi[p * G + g];
-      col[p * 2 * G + t] = prev;
+    constexpr int D = 4;
+    // Operands of planes p .. p + D - 1 (a plane past the end reads the
+    // last one and is not used).
+    T cv[D], fv[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int q = u < np ? u : np - 1;
+      cv[u] = col[q * 2 * G + t];
+      fv[u] = smi[q * G + g];
     }
+    T prev = T(0);
+    for (int p0 = 0; p0 < np; p0 += D) {
+#pragma unroll
+      for (int u = 0; u < D; ++u) {
+        const int p = p0 + u;
+        if (p < np) {
+          const int k = L.k0 + p;
+          const T lo = p == 0 ? T(0) : (k == L.nz ? T(-2) : T(-1));
+          prev = (cv[u] - lo * prev) * fv[u];
+          col[p * 2 * G + t] = prev;
+          const int q = p + D < np ? p + D : np - 1;
+          cv[u] = col[q * 2 * G + t];
+          fv[u] = smi[q * G + g];
+        }
+      }
+    }
+    // Back substitution from plane np - 2 down, same look-ahead.
     T next = prev;
-#pragma unroll 4
-    for (int p = np - 2; p >= 0; --p) {
-      next = col[p * 2 * G + t] - scp[p * G + g] * next;
-      col[p * 2 * G + t] = next;
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int q = np - 2 - u >= 0 ? np - 2 - u : 0;
+      cv[u] = col[q * 2 * G + t];
+      fv[u] = scp[q * G + g];
+    }
+    for (int p0 = np - 2; p0 >= 0; p0 -= D) {
+#pragma unroll
+      for (int u = 0; u < D; ++u) {
+        const int p = p0 - u;
+        if (p >= 0) {
+          next = cv[u] - fv[u] * next;
+          col[p * 2 * G + t] = next;
+          const int q = p - D >= 0 ? p - D : 0;
+          cv[u] = col[q * 2 * G + t];
+          fv[u] = scp[q * G + g];
+        }
+      }
     }
   }
   __syncthreads();
@@ -1361,6 +1395,148 @@ int spec_group(int np) {
   return G;
 }
 
+// Radix-2 FFTs in LDS for planes whose nx and ny are powers of two (at
+// most kSpecMaxFFT): a plane is held as ny x nx complex values; a pass
+// over one axis bit-reverses that axis, then runs its log2(n) butterfly
+// stages in place.  sign = -1 forward, +1 inverse (no scaling).
+__device__ __forceinline__ int ilog2_pow2(int n) { return 31 - __clz(n); }
+
+template <typename T>
+__device__ void fft_axis(T* buf, const T* tw, int nmax, int nx, int ny,
+                         bool along_x, T sign) {
+  // along_x: the ny rows of length nx; else the nx columns of length ny,
+  // with consecutive lanes on consecutive columns (a column's elements are
+  // a row apart, which would put a wave's accesses in one LDS bank).
+  // tw: e^{-2 pi i q / nmax}, q < nmax / 2.  Both sizes are powers of two:
+  // indices split by shifts and masks.
+  const int n = along_x ? nx : ny;
+  const int lines = along_x ? ny : nx;
+  const int lg = ilog2_pow2(n), lgx = ilog2_pow2(nx);
+  const int lgl = ilog2_pow2(lines);
+  // Bit reversal.
+  for (int q = threadIdx.x; q < lines * n; q += blockDim.x) {
+    int ln, a;
+    if (along_x) { ln = q >> lg; a = q & (n - 1); }
+    else { ln = q & (lines - 1); a = q >> lgl; }
+    const int b = (int)(__brev((unsigned)a) >> (32 - lg));
+    if (a < b) {
+      const int ia = along_x ? (ln << lgx) + a : (a << lgx) + ln;
+      const int ib = along_x ? (ln << lgx) + b : (b << lgx) + ln;
+      const T xr = buf[2 * ia], xi = buf[2 * ia + 1];
+      buf[2 * ia] = buf[2 * ib];
+      buf[2 * ia + 1] = buf[2 * ib + 1];
+      buf[2 * ib] = xr;
+      buf[2 * ib + 1] = xi;
+    }
+  }
+  __syncthreads();
+  const int lgmax = ilog2_pow2(nmax);
+  for (int sh = 0; sh < lg; ++sh) {
+    const int half = 1 << sh, tsh = lgmax - sh - 1;  // tstep = nmax / len
+    for (int q = threadIdx.x; q < lines << (lg - 1); q += blockDim.x) {
+      int ln, r;
+      if (along_x) { ln = q >> (lg - 1); r = q & ((n >> 1) - 1); }
+      else { ln = q & (lines - 1); r = q >> lgl; }
+      const int pos = r & (half - 1), i0 = ((r >> sh) << (sh + 1)) + pos;
+      const int i1 = i0 + half;
+      const int tix = pos << tsh;
+      const int a0 = along_x ? (ln << lgx) + i0 : (i0 << lgx) + ln;
+      const int a1 = along_x ? (ln << lgx) + i1 : (i1 << lgx) + ln;
+      // w = e^{sign 2 pi i pos / len}.
+      const T wr = tw[2 * tix], wi = sign * -tw[2 * tix + 1];
+      const T br = buf[2 * a1], bi = buf[2 * a1 + 1];
+      const T cr = br * wr - bi * wi, ci = br * wi + bi * wr;
+      const T ar = buf[2 * a0], ai = buf[2 * a0 + 1];
+      buf[2 * a0] = ar + cr;
+      buf[2 * a0 + 1] = ai + ci;
+      buf[2 * a1] = ar - cr;
+      buf[2 * a1 + 1] = ai - ci;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void fill_fft_twiddles(T* tw, int nmax) {
+  for (int q = threadIdx.x; q < nmax / 2; q += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * q / nmax, &sn, &cs);
+    tw[2 * q] = (T)cs;
+    tw[2 * q + 1] = (T)(-sn);
+  }
+}
+
+// Forward by FFTs: rows of the real plane, then the columns (all nx; the
+// modes kx = 0..nx/2 are kept).
+template <typename T>
+__global__ void __launch_bounds__(256) k_spec_fwd_fft(LevelC L,
+                                                      const T* __restrict__ f,
+                                                      T* __restrict__ s,
+                                                      int nm,
+                                                      const Counters* dc) {
+  __shared__ T buf[2 * kSpecMaxFFT * kSpecMaxFFT];
+  __shared__ T tw[kSpecMaxFFT];
+  if (dc->done) return;
+  const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1;
+  const int nmax = nx > ny ? nx : ny;
+  const int p = blockIdx.x;
+  const T* src = f + (long long)(L.k0 + p) * L.nxy;
+  for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) {
+    buf[2 * q] = src[q];
+    buf[2 * q + 1] = T(0);
+  }
+  fill_fft_twiddles(tw, nmax);
+  __syncthreads();
+  fft_axis(buf, tw, nmax, nx, ny, true, T(-1));
+  fft_axis(buf, tw, nmax, nx, ny, false, T(-1));
+  const T h2 = (T)L.h2;
+  T* out = s + (long long)p * 2 * nm;
+  for (int q = threadIdx.x; q < nm; q += blockDim.x) {
+    const int ky = q / nxh, kx = q % nxh;
+    out[2 * q] = h2 * buf[2 * (ky * nx + kx)];
+    out[2 * q + 1] = h2 * buf[2 * (ky * nx + kx) + 1];
+  }
+}
+
+// Inverse by FFTs: the columns (those of kx = 0..nx/2 matter), the rows
+// completed by Hermitian symmetry (G(j, nx - kx) = conj G(j, kx)), then
+// the rows; u is the real part over nx ny.
+template <typename T>
+__global__ void __launch_bounds__(256) k_spec_inv_fft(LevelC L,
+                                                      const T* __restrict__ s,
+                                                      T* __restrict__ u,
+                                                      int nm,
+                                                      const Counters* dc) {
+  __shared__ T buf[2 * kSpecMaxFFT * kSpecMaxFFT];
+  __shared__ T tw[kSpecMaxFFT];
+  if (dc->done) return;
+  const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1;
+  const int nmax = nx > ny ? nx : ny;
+  const int p = blockIdx.x;
+  const T* in = s + (long long)p * 2 * nm;
+  for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) {
+    const int ky = q / nx, kx = q % nx;
+    const bool have = kx < nxh;   // the other columns are filled below
+    buf[2 * q] = have ? in[2 * (ky * nxh + kx)] : T(0);
+    buf[2 * q + 1] = have ? in[2 * (ky * nxh + kx) + 1] : T(0);
+  }
+  fill_fft_twiddles(tw, nmax);
+  __syncthreads();
+  fft_axis(buf, tw, nmax, nx, ny, false, T(1));
+  for (int q = threadIdx.x; q < ny * (nx - nxh); q += blockDim.x) {
+    const int j = q / (nx - nxh), kx = nxh + q % (nx - nxh);
+    buf[2 * (j * nx + kx)] = buf[2 * (j * nx + nx - kx)];
+    buf[2 * (j * nx + kx) + 1] = -buf[2 * (j * nx + nx - kx) + 1];
+  }
+  __syncthreads();
+  fft_axis(buf, tw, nmax, nx, ny, true, T(1));
+  const T inv_n = T(1) / (T)(nx * ny);
+  T* dst = u + (long long)(L.k0 + p) * L.nxy;
+  for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) dst[q] = buf[2 * q] * inv_n;
+}
+
+__host__ __device__ constexpr bool is_pow2(int n) { return n > 0 && !(n & (n - 1)); }
+
 template <typename T>
 void spectral_solve(pic_ctx* c, int l) {
   hipStream_t st = c->stream;
@@ -1376,10 +1552,18 @@ void spectral_solve(pic_ctx* c, int l) {
   }
   const int G = spec_group<T>(np);
   const size_t lds = (size_t)np * 4 * G * sizeof(T);
-  k_spec_fwd<T><<<(unsigned)np, 256, 0, st>>>(Lc, lev_f<T>(L), s, nm, c->dc);
+  const bool fft = is_pow2(L.nx) && is_pow2(L.ny) && L.nx <= kSpecMaxFFT &&
+                   L.ny <= kSpecMaxFFT;
+  if (fft)
+    k_spec_fwd_fft<T><<<(unsigned)np, 256, 0, st>>>(Lc, lev_f<T>(L), s, nm, c->dc);
+  else
+    k_spec_fwd<T><<<(unsigned)np, 256, 0, st>>>(Lc, lev_f<T>(L), s, nm, c->dc);
   k_spec_tri<T><<<(unsigned)((nm + G - 1) / G), 256, lds, st>>>(
       Lc, s, mi, cp, nm, G, c->dc);
-  k_spec_inv<T><<<(unsigned)np, 256, 0, st>>>(Lc, s, lev_u<T>(L), nm, c->dc);
+  if (fft)
+    k_spec_inv_fft<T><<<(unsigned)np, 256, 0, st>>>(Lc, s, lev_u<T>(L), nm, c->dc);
+  else
+    k_spec_inv<T><<<(unsigned)np, 256, 0, st>>>(Lc, s, lev_u<T>(L), nm, c->dc);
 }
 
 // Workgroups of k_smooth2<T, *> the current device runs at once.

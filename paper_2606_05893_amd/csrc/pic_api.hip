@@ -225,9 +225,12 @@ void derive(pic_ctx* c) {
       const Level& L = c->lev[l];
       const int k0 = f.bc_lo == PIC_BC_DIRICHLET ? 1 : 0;
       const int k1 = f.bc_hi == PIC_BC_DIRICHLET ? L.nz - 1 : L.nz;
+      auto pow2 = [](int n) { return n > 0 && !(n & (n - 1)); };
+      const bool by_fft = pow2(L.nx) && pow2(L.ny) && L.nx <= kSpecMaxFFT &&
+                          L.ny <= kSpecMaxFFT;
+      const bool direct = L.nx <= kSpecMaxXY && L.ny <= kSpecMaxXY;
       if (L.nx >= 2 && L.ny >= 2 && !(L.nx & 1) && !(L.ny & 1) &&
-          L.nx <= kSpecMaxXY && L.ny <= kSpecMaxXY && k1 >= k0 &&
-          k1 - k0 + 1 <= kSpecMaxPlanes) {
+          (by_fft || direct) && k1 >= k0 && k1 - k0 + 1 <= kSpecMaxPlanes) {
         c->spec_level = l;
         c->spec_modes = L.ny * (L.nx / 2 + 1);
         c->spec_planes = k1 - k0 + 1;

@@ -34,8 +34,9 @@ struct Level {
 };
 
 // Largest coarse level the exact (spectral) solve takes: nodes per axis in
-// x and y, unknown planes in z.
-constexpr int kSpecMaxXY = 32, kSpecMaxPlanes = 256;
+// x and y (powers of two by FFT up to kSpecMaxFFT, other even sizes by a
+// direct transform up to kSpecMaxXY), unknown planes in z.
+constexpr int kSpecMaxXY = 32, kSpecMaxFFT = 64, kSpecMaxPlanes = 256;
 
 struct QueueCall {
   int species;
