@@ -1153,12 +1153,34 @@ int tail_first(const pic_ctx* c) {
 // needs the modes kx = 0..nx/2 only.  Spectrum layout: [plane][mode][re,im],
 // mode = ky (nx/2 + 1) + kx.
 
+__device__ __forceinline__ int ilog2_pow2(int n) { return 31 - __clz(n); }
+
+// Block-wide copy of n values, dst(q) <- src(q), with NB loads per thread in
+// flight: the loads take clamped indices (always in range) and only the
+// stores are guarded, so no load waits for the one before it.
+constexpr int kSpecThreads = 256;
+template <int NB, typename T, typename Ld, typename St>
+__device__ __forceinline__ void batch_copy(int n, Ld ld, St st) {
+  for (int q0 = threadIdx.x; q0 < n; q0 += NB * kSpecThreads) {
+    T v[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int q = q0 + u * kSpecThreads;
+      v[u] = ld(q < n ? q : n - 1);
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int q = q0 + u * kSpecThreads;
+      if (q < n) st(q, v[u]);
+    }
+  }
+}
+
 // Elimination factors per mode, which depend on the grid only: the inverse
-// pivots and the eliminated upper coefficients, plane by plane (layout
-// [plane][mode]).
+// pivots, plane by plane (layout [plane][mode]); the eliminated upper
+// coefficient of plane p is up_p times its pivot's inverse.
 template <typename T>
-__global__ void k_spec_factor(LevelC L, T* __restrict__ mi,
-                              T* __restrict__ cp, int nm) {
+__global__ void k_spec_factor(LevelC L, T* __restrict__ mi, int nm) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= nm) return;
   const int nxh = L.nx / 2 + 1;
@@ -1173,7 +1195,6 @@ __global__ void k_spec_factor(LevelC L, T* __restrict__ mi,
     const double inv = 1.0 / (d - lo * cprev);
     cprev = up * inv;
     mi[(long long)p * nm + m] = (T)inv;
-    cp[(long long)p * nm + m] = (T)cprev;
   }
 }
 
@@ -1191,7 +1212,7 @@ __device__ __forceinline__ void fill_twiddles(T* tw, int n) {
 // Forward: h2 f of one unknown plane -> its spectrum (row DFTs of the real
 // plane, then column DFTs of the half spectrum).
 template <typename T>
-__global__ void __launch_bounds__(256) k_spec_fwd(LevelC L,
+__global__ void __launch_bounds__(kSpecThreads) k_spec_fwd(LevelC L,
                                                   const T* __restrict__ f,
                                                   T* __restrict__ s, int nm,
                                                   const Counters* dc) {
@@ -1202,7 +1223,8 @@ __global__ void __launch_bounds__(256) k_spec_fwd(LevelC L,
   const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1;
   const int p = blockIdx.x;
   const T* src = f + (long long)(L.k0 + p) * L.nxy;
-  for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) fp[q] = src[q];
+  batch_copy<4, T>(nx * ny, [&](int q) { return src[q]; },
+                   [&](int q, T v) { fp[q] = v; });
   fill_twiddles(twx, nx);
   fill_twiddles(twy, ny);
   __syncthreads();
@@ -1244,98 +1266,104 @@ __global__ void __launch_bounds__(256) k_spec_fwd(LevelC L,
   }
 }
 
-// The tridiagonal systems of G modes per workgroup, staged in LDS with
-// their elimination factors: one thread per (mode, real or imaginary part)
-// runs the forward elimination and the back substitution (a multiply-add
-// chain: the factors were computed once), with the operands of the next
-// four planes already loaded into registers; all threads stage.
+// The tridiagonal systems, one per (mode, real or imaginary part).  Both
+// sweeps are first-order linear recurrences with coefficients that depend on
+// the grid only: the elimination y_p = mi_p b_p + al_p y_{p-1}, al_p =
+// -lo_p mi_p, and the back substitution x_p = y_p + be_p x_{p+1}, be_p =
+// -up_p mi_p (up_p in {0, -1, -2}, so be_p is exact in either precision).
+// Each lane runs one segment of kSeg planes of one column from a zero start,
+// carrying the product of the coefficients along it; the segment ends are
+// joined through LDS, and every plane is then corrected by its carried
+// product times the joined value.  A workgroup holds 2^lgw columns (half as
+// many modes) and kSpecThreads / 2^lgw segments; the plane data goes from
+// HBM to registers and back once.
+constexpr int kSeg = 16;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_spec_tri(LevelC L, T* __restrict__ s,
-                                                  const T* __restrict__ mi,
-                                                  const T* __restrict__ cp,
-                                                  int nm, int G,
-                                                  const Counters* dc) {
-  extern __shared__ __attribute__((aligned(16))) char spec_lds[];
+__global__ void __launch_bounds__(kSpecThreads) k_spec_tri(
+    LevelC L, T* __restrict__ s, const T* __restrict__ mi, int nm, int lgw,
+    const Counters* dc) {
+  __shared__ T jz[kSpecThreads], ja[kSpecThreads];
   if (dc->done) return;
   const int np = L.k1 - L.k0 + 1;
-  const int m0 = blockIdx.x * G;
-  const int gm = nm - m0 < G ? nm - m0 : G;  // modes of this workgroup
-  const int w2 = 2 * gm;                     // columns (re, im)
-  T* col = reinterpret_cast<T*>(spec_lds);   // [plane][2G]
-  T* smi = col + (long long)np * 2 * G;      // [plane][G]
-  T* scp = smi + (long long)np * G;          // [plane][G]
-  for (int q = threadIdx.x; q < np * w2; q += blockDim.x) {
-    const int p = q / w2, c = q % w2;
-    col[p * 2 * G + c] = s[(long long)p * 2 * nm + 2 * m0 + c];
-  }
-  for (int q = threadIdx.x; q < np * gm; q += blockDim.x) {
-    const int p = q / gm, c = q % gm;
-    smi[p * G + c] = mi[(long long)p * nm + m0 + c];
-    scp[p * G + c] = cp[(long long)p * nm + m0 + c];
-  }
-  __syncthreads();
+  const int w = 1 << lgw;
   const int t = threadIdx.x;
-  if (t < w2) {
-    const int g = t >> 1;
-    constexpr int D = 4;
-    // Operands of planes p .. p + D - 1 (a plane past the end reads the
-    // last one and is not used).
-    T cv[D], fv[D];
+  const int c = t & (w - 1), sg = t >> lgw;
+  const int m0 = blockIdx.x * (w >> 1);
+  const int m = m0 + (c >> 1);
+  const bool mok = m < nm;
+  const int cc = mok ? c : (c & 1);  // a valid column, not stored
+  const int mc = mok ? m : m0;
+  const int p0 = sg * kSeg;
+  T b[kSeg], f[kSeg], a[kSeg];
 #pragma unroll
-    for (int u = 0; u < D; ++u) {
-      const int q = u < np ? u : np - 1;
-      cv[u] = col[q * 2 * G + t];
-      fv[u] = smi[q * G + g];
-    }
-    T prev = T(0);
-    for (int p0 = 0; p0 < np; p0 += D) {
+  for (int u = 0; u < kSeg; ++u) {
+    const int p = p0 + u < np ? p0 + u : np - 1;
+    b[u] = s[(long long)p * 2 * nm + 2 * m0 + cc];
+    f[u] = mi[(long long)p * nm + mc];
+  }
+  // Elimination, segment-local.
+  T z = T(0), A = T(1);
 #pragma unroll
-      for (int u = 0; u < D; ++u) {
-        const int p = p0 + u;
-        if (p < np) {
-          const int k = L.k0 + p;
-          const T lo = p == 0 ? T(0) : (k == L.nz ? T(-2) : T(-1));
-          prev = (cv[u] - lo * prev) * fv[u];
-          col[p * 2 * G + t] = prev;
-          const int q = p + D < np ? p + D : np - 1;
-          cv[u] = col[q * 2 * G + t];
-          fv[u] = smi[q * G + g];
-        }
-      }
+  for (int u = 0; u < kSeg; ++u) {
+    const int p = p0 + u, k = L.k0 + p;
+    if (p < np) {
+      const T al = p == 0 ? T(0) : (k == L.nz ? T(2) : T(1)) * f[u];
+      z = f[u] * b[u] + al * z;
+      A = al * A;
     }
-    // Back substitution from plane np - 2 down, same look-ahead.
-    T next = prev;
+    b[u] = z;
+    a[u] = A;
+  }
+  jz[t] = z;
+  ja[t] = A;
+  __syncthreads();
+  T y = T(0);  // y at the plane before this segment
+  for (int q = 0; q < sg; ++q) y = jz[(q << lgw) + c] + ja[(q << lgw) + c] * y;
 #pragma unroll
-    for (int u = 0; u < D; ++u) {
-      const int q = np - 2 - u >= 0 ? np - 2 - u : 0;
-      cv[u] = col[q * 2 * G + t];
-      fv[u] = scp[q * G + g];
-    }
-    for (int p0 = np - 2; p0 >= 0; p0 -= D) {
+  for (int u = 0; u < kSeg; ++u) b[u] = b[u] + a[u] * y;
+  // Back substitution, segment-local from its last plane.
+  T x = T(0), B = T(1);
 #pragma unroll
-      for (int u = 0; u < D; ++u) {
-        const int p = p0 - u;
-        if (p >= 0) {
-          next = cv[u] - fv[u] * next;
-          col[p * 2 * G + t] = next;
-          const int q = p - D >= 0 ? p - D : 0;
-          cv[u] = col[q * 2 * G + t];
-          fv[u] = scp[q * G + g];
-        }
-      }
+  for (int u = kSeg - 1; u >= 0; --u) {
+    const int p = p0 + u, k = L.k0 + p;
+    if (p < np) {
+      const T be = p == np - 1 ? T(0) : (k == 0 ? T(2) : T(1)) * f[u];
+      x = b[u] + be * x;
+      B = be * B;
     }
+    b[u] = x;
+    a[u] = B;
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < np * w2; q += blockDim.x) {
-    const int p = q / w2, c = q % w2;
-    s[(long long)p * 2 * nm + 2 * m0 + c] = col[p * 2 * G + c];
+  jz[t] = x;
+  ja[t] = B;
+  __syncthreads();
+  const int nsg = kSpecThreads >> lgw;
+  T xn = T(0);  // x at the plane after this segment
+  for (int q = nsg - 1; q > sg; --q)
+    xn = jz[(q << lgw) + c] + ja[(q << lgw) + c] * xn;
+  if (mok) {
+#pragma unroll
+    for (int u = 0; u < kSeg; ++u)
+      if (p0 + u < np)
+        s[(long long)(p0 + u) * 2 * nm + 2 * m0 + c] = b[u] + a[u] * xn;
   }
+}
+
+// Columns per workgroup of k_spec_tri (log2): enough segments of kSeg
+// planes for np, at most 128 columns.
+inline int spec_tri_lgw(int np) {
+  const int segs = (np + kSeg - 1) / kSeg;
+  int lgw = 7;
+  while (lgw > 1 && (kSpecThreads >> lgw) < segs) --lgw;
+  return lgw;
 }
 
 // Inverse: the solved spectrum of one plane -> u (column inverse DFTs,
 // then the real row inverse DFT: kx = 0 and nx/2 once, the others twice).
 template <typename T>
-__global__ void __launch_bounds__(256) k_spec_inv(LevelC L,
+__global__ void __launch_bounds__(kSpecThreads) k_spec_inv(LevelC L,
                                                   const T* __restrict__ s,
                                                   T* __restrict__ u, int nm,
                                                   const Counters* dc) {
@@ -1346,7 +1374,8 @@ __global__ void __launch_bounds__(256) k_spec_inv(LevelC L,
   const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1;
   const int p = blockIdx.x;
   const T* in = s + (long long)p * 2 * nm;
-  for (int q = threadIdx.x; q < 2 * nm; q += blockDim.x) sp[q] = in[q];
+  batch_copy<4, T>(2 * nm, [&](int q) { return in[q]; },
+                   [&](int q, T v) { sp[q] = v; });
   fill_twiddles(twx, nx);
   fill_twiddles(twy, ny);
   __syncthreads();
@@ -1387,152 +1416,343 @@ __global__ void __launch_bounds__(256) k_spec_inv(LevelC L,
   }
 }
 
-// Modes per workgroup of k_spec_tri: its LDS holds np x 4G values.
-template <typename T>
-int spec_group(int np) {
-  int G = 64;
-  while (G > 1 && (long long)np * 4 * G * sizeof(T) > 64 * 1024) G /= 2;
-  return G;
-}
+// FFTs of planes whose nx and ny are powers of two (2 to kSpecMaxFFT), by
+// the four-step split n = n1 n2 (n1 = min(n, 8)): per line, n2 register
+// DFTs of length n1 over stride-n2 elements, the twiddles e^{+-2 pi i j2 k1
+// / n}, then n1 register DFTs of length n2; output k1 + n1 k2.  Each axis
+// costs two LDS exchanges.  Two real rows travel as one complex row z =
+// row(2jp) + i row(2jp + 1) and are separated with the conjugate-symmetric
+// halves of its transform (forward), or assembled from their half spectra
+// (inverse).  One task per thread and phase: kFftThreads covers the largest
+// phase (33 columns x 8).
+constexpr int kFftThreads = 320;
+constexpr int kFftSlots = 2304;  // complex LDS slots, largest layout at 64 x 64
 
-// Radix-2 FFTs in LDS for planes whose nx and ny are powers of two (at
-// most kSpecMaxFFT): a plane is held as ny x nx complex values; a pass
-// over one axis bit-reverses that axis, then runs its log2(n) butterfly
-// stages in place.  sign = -1 forward, +1 inverse (no scaling).
-__device__ __forceinline__ int ilog2_pow2(int n) { return 31 - __clz(n); }
-
+// Complex DFT of length R in {1, 2, 4, 8} on registers 0..R-1, in place and
+// in natural order; sg = -1: e^{-2 pi i j k / R}, +1: e^{+...}.
 template <typename T>
-__device__ void fft_axis(T* buf, const T* tw, int nmax, int nx, int ny,
-                         bool along_x, T sign) {
-  // along_x: the ny rows of length nx; else the nx columns of length ny,
-  // with consecutive lanes on consecutive columns (a column's elements are
-  // a row apart, which would put a wave's accesses in one LDS bank).
-  // tw: e^{-2 pi i q / nmax}, q < nmax / 2.  Both sizes are powers of two:
-  // indices split by shifts and masks.
-  const int n = along_x ? nx : ny;
-  const int lines = along_x ? ny : nx;
-  const int lg = ilog2_pow2(n), lgx = ilog2_pow2(nx);
-  const int lgl = ilog2_pow2(lines);
-  // Bit reversal.
-  for (int q = threadIdx.x; q < lines * n; q += blockDim.x) {
-    int ln, a;
-    if (along_x) { ln = q >> lg; a = q & (n - 1); }
-    else { ln = q & (lines - 1); a = q >> lgl; }
-    const int b = (int)(__brev((unsigned)a) >> (32 - lg));
-    if (a < b) {
-      const int ia = along_x ? (ln << lgx) + a : (a << lgx) + ln;
-      const int ib = along_x ? (ln << lgx) + b : (b << lgx) + ln;
-      const T xr = buf[2 * ia], xi = buf[2 * ia + 1];
-      buf[2 * ia] = buf[2 * ib];
-      buf[2 * ia + 1] = buf[2 * ib + 1];
-      buf[2 * ib] = xr;
-      buf[2 * ib + 1] = xi;
-    }
-  }
-  __syncthreads();
-  const int lgmax = ilog2_pow2(nmax);
-  for (int sh = 0; sh < lg; ++sh) {
-    const int half = 1 << sh, tsh = lgmax - sh - 1;  // tstep = nmax / len
-    for (int q = threadIdx.x; q < lines << (lg - 1); q += blockDim.x) {
-      int ln, r;
-      if (along_x) { ln = q >> (lg - 1); r = q & ((n >> 1) - 1); }
-      else { ln = q & (lines - 1); r = q >> lgl; }
-      const int pos = r & (half - 1), i0 = ((r >> sh) << (sh + 1)) + pos;
-      const int i1 = i0 + half;
-      const int tix = pos << tsh;
-      const int a0 = along_x ? (ln << lgx) + i0 : (i0 << lgx) + ln;
-      const int a1 = along_x ? (ln << lgx) + i1 : (i1 << lgx) + ln;
-      // w = e^{sign 2 pi i pos / len}.
-      const T wr = tw[2 * tix], wi = sign * -tw[2 * tix + 1];
-      const T br = buf[2 * a1], bi = buf[2 * a1 + 1];
-      const T cr = br * wr - bi * wi, ci = br * wi + bi * wr;
-      const T ar = buf[2 * a0], ai = buf[2 * a0 + 1];
-      buf[2 * a0] = ar + cr;
-      buf[2 * a0 + 1] = ai + ci;
-      buf[2 * a1] = ar - cr;
-      buf[2 * a1 + 1] = ai - ci;
-    }
-    __syncthreads();
-  }
+__device__ __forceinline__ void dft4r(T& r0, T& i0, T& r1, T& i1, T& r2, T& i2,
+                                      T& r3, T& i3, T sg) {
+  const T ar = r0 + r2, ai = i0 + i2, br = r0 - r2, bi = i0 - i2;
+  const T cr = r1 + r3, ci = i1 + i3;
+  // (r1 - r3 + i (i1 - i3)) times e^{sg i pi / 2} = sg i
+  const T dr = -sg * (i1 - i3), di = sg * (r1 - r3);
+  r0 = ar + cr; i0 = ai + ci;
+  r2 = ar - cr; i2 = ai - ci;
+  r1 = br + dr; i1 = bi + di;
+  r3 = br - dr; i3 = bi - di;
 }
 
 template <typename T>
-__device__ __forceinline__ void fill_fft_twiddles(T* tw, int nmax) {
-  for (int q = threadIdx.x; q < nmax / 2; q += blockDim.x) {
+__device__ __forceinline__ void dft_reg(T (&xr)[8], T (&xi)[8], int R, T sg) {
+  if (R == 8) {
+    // Even and odd halves, then the radix-2 merge with e^{sg 2 pi i k / 8}.
+    dft4r(xr[0], xi[0], xr[2], xi[2], xr[4], xi[4], xr[6], xi[6], sg);
+    dft4r(xr[1], xi[1], xr[3], xi[3], xr[5], xi[5], xr[7], xi[7], sg);
+    const T h = T(0.70710678118654752440);
+    const T o1r = h * (xr[3] - sg * xi[3]), o1i = h * (sg * xr[3] + xi[3]);
+    const T o2r = -sg * xi[5], o2i = sg * xr[5];
+    const T o3r = -h * (xr[7] + sg * xi[7]), o3i = h * (sg * xr[7] - xi[7]);
+    const T e0r = xr[0], e0i = xi[0], e1r = xr[2], e1i = xi[2];
+    const T e2r = xr[4], e2i = xi[4], e3r = xr[6], e3i = xi[6];
+    const T o0r = xr[1], o0i = xi[1];
+    xr[0] = e0r + o0r; xi[0] = e0i + o0i;
+    xr[4] = e0r - o0r; xi[4] = e0i - o0i;
+    xr[1] = e1r + o1r; xi[1] = e1i + o1i;
+    xr[5] = e1r - o1r; xi[5] = e1i - o1i;
+    xr[2] = e2r + o2r; xi[2] = e2i + o2i;
+    xr[6] = e2r - o2r; xi[6] = e2i - o2i;
+    xr[3] = e3r + o3r; xi[3] = e3i + o3i;
+    xr[7] = e3r - o3r; xi[7] = e3i - o3i;
+  } else if (R == 4) {
+    dft4r(xr[0], xi[0], xr[1], xi[1], xr[2], xi[2], xr[3], xi[3], sg);
+  } else if (R == 2) {
+    const T ar = xr[0], ai = xi[0];
+    xr[0] = ar + xr[1]; xi[0] = ai + xi[1];
+    xr[1] = ar - xr[1]; xi[1] = ai - xi[1];
+  }
+}
+
+// Twiddle table (cos, sin)(2 pi q / n), q < n.
+template <typename C2>
+__device__ __forceinline__ void fill_fft_tw(C2* tw, int n) {
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
     double sn, cs;
-    sincospi(2.0 * q / nmax, &sn, &cs);
-    tw[2 * q] = (T)cs;
-    tw[2 * q + 1] = (T)(-sn);
+    sincospi(2.0 * q / n, &sn, &cs);
+    tw[q].x = cs;
+    tw[q].y = sn;
   }
 }
 
-// Forward by FFTs: rows of the real plane, then the columns (all nx; the
-// modes kx = 0..nx/2 are kept).
-template <typename T>
-__global__ void __launch_bounds__(256) k_spec_fwd_fft(LevelC L,
-                                                      const T* __restrict__ f,
-                                                      T* __restrict__ s,
-                                                      int nm,
-                                                      const Counters* dc) {
-  __shared__ T buf[2 * kSpecMaxFFT * kSpecMaxFFT];
-  __shared__ T tw[kSpecMaxFFT];
-  if (dc->done) return;
-  const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1;
-  const int nmax = nx > ny ? nx : ny;
-  const int p = blockIdx.x;
-  const T* src = f + (long long)(L.k0 + p) * L.nxy;
-  for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) {
-    buf[2 * q] = src[q];
-    buf[2 * q + 1] = T(0);
-  }
-  fill_fft_twiddles(tw, nmax);
-  __syncthreads();
-  fft_axis(buf, tw, nmax, nx, ny, true, T(-1));
-  fft_axis(buf, tw, nmax, nx, ny, false, T(-1));
-  const T h2 = (T)L.h2;
-  T* out = s + (long long)p * 2 * nm;
-  for (int q = threadIdx.x; q < nm; q += blockDim.x) {
-    const int ky = q / nxh, kx = q % nxh;
-    out[2 * q] = h2 * buf[2 * (ky * nx + kx)];
-    out[2 * q + 1] = h2 * buf[2 * (ky * nx + kx) + 1];
+// x_k1 *= e^{sg 2 pi i j2 k1 / n}, k1 < R.
+template <typename T, typename C2>
+__device__ __forceinline__ void twiddle(T (&xr)[8], T (&xi)[8], int R,
+                                        const C2* tw, int n, int j2, T sg) {
+#pragma unroll
+  for (int k1 = 1; k1 < 8; ++k1) {
+    if (k1 < R) {
+      const C2 w = tw[(j2 * k1) & (n - 1)];
+      const T wi = sg * w.y;
+      const T r = xr[k1] * w.x - xi[k1] * wi;
+      xi[k1] = xr[k1] * wi + xi[k1] * w.x;
+      xr[k1] = r;
+    }
   }
 }
 
-// Inverse by FFTs: the columns (those of kx = 0..nx/2 matter), the rows
-// completed by Hermitian symmetry (G(j, nx - kx) = conj G(j, kx)), then
-// the rows; u is the real part over nx ny.
+// Forward: h2 f of one unknown plane -> its half spectrum (kx <= nx/2).
 template <typename T>
-__global__ void __launch_bounds__(256) k_spec_inv_fft(LevelC L,
-                                                      const T* __restrict__ s,
-                                                      T* __restrict__ u,
-                                                      int nm,
-                                                      const Counters* dc) {
-  __shared__ T buf[2 * kSpecMaxFFT * kSpecMaxFFT];
-  __shared__ T tw[kSpecMaxFFT];
+__global__ void __launch_bounds__(kFftThreads) k_spec_fwd_fft(
+    LevelC L, const T* __restrict__ f, T* __restrict__ s, int nm,
+    const Counters* dc) {
+  using C2 = typename Pair2<T>::type;
+  __shared__ C2 buf[kFftSlots];
+  __shared__ C2 twx[kSpecMaxFFT], twy[kSpecMaxFFT];
   if (dc->done) return;
-  const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1;
-  const int nmax = nx > ny ? nx : ny;
-  const int p = blockIdx.x;
-  const T* in = s + (long long)p * 2 * nm;
-  for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) {
-    const int ky = q / nx, kx = q % nx;
-    const bool have = kx < nxh;   // the other columns are filled below
-    buf[2 * q] = have ? in[2 * (ky * nxh + kx)] : T(0);
-    buf[2 * q + 1] = have ? in[2 * (ky * nxh + kx) + 1] : T(0);
+  const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1, nyp = ny / 2;
+  const int n1x = nx < 8 ? nx : 8, n2x = nx / n1x;
+  const int n1y = ny < 8 ? ny : 8, n2y = ny / n1y;
+  const int lg1x = ilog2_pow2(n1x), lg2x = ilog2_pow2(n2x);
+  const int rs1 = n1x * (n2x + 1);  // row stride of the x scratch
+  const int rz = nx + 8;            // row stride of the x spectra
+  const int t = threadIdx.x;
+  const T* src = f + (long long)(L.k0 + blockIdx.x) * L.nxy;
+  fill_fft_tw(twx, nx);
+  fill_fft_tw(twy, ny);
+  T xr[8], xi[8];
+  // Rows: task (jp, j2), j2 fastest.
+  const bool tx1 = t < (nyp << lg2x);
+  const int jp1 = t >> lg2x, j21 = t & (n2x - 1);
+  if (tx1) {
+#pragma unroll
+    for (int j1 = 0; j1 < 8; ++j1) {
+      if (j1 < n1x) {
+        const int i = (j1 << lg2x) + j21;
+        xr[j1] = src[(2 * jp1) * nx + i];
+        xi[j1] = src[(2 * jp1 + 1) * nx + i];
+      }
+    }
   }
-  fill_fft_twiddles(tw, nmax);
   __syncthreads();
-  fft_axis(buf, tw, nmax, nx, ny, false, T(1));
-  for (int q = threadIdx.x; q < ny * (nx - nxh); q += blockDim.x) {
-    const int j = q / (nx - nxh), kx = nxh + q % (nx - nxh);
-    buf[2 * (j * nx + kx)] = buf[2 * (j * nx + nx - kx)];
-    buf[2 * (j * nx + kx) + 1] = -buf[2 * (j * nx + nx - kx) + 1];
+  if (tx1) {
+    dft_reg(xr, xi, n1x, T(-1));
+    twiddle(xr, xi, n1x, twx, nx, j21, T(-1));
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1)
+      if (k1 < n1x) {
+        C2 v;
+        v.x = xr[k1];
+        v.y = xi[k1];
+        buf[jp1 * rs1 + k1 * (n2x + 1) + j21] = v;
+      }
   }
   __syncthreads();
-  fft_axis(buf, tw, nmax, nx, ny, true, T(1));
-  const T inv_n = T(1) / (T)(nx * ny);
-  T* dst = u + (long long)(L.k0 + p) * L.nxy;
-  for (int q = threadIdx.x; q < nx * ny; q += blockDim.x) dst[q] = buf[2 * q] * inv_n;
+  const bool tx2 = t < (nyp << lg1x);
+  const int jp2 = t >> lg1x, k12 = t & (n1x - 1);
+  if (tx2) {
+#pragma unroll
+    for (int j2 = 0; j2 < 8; ++j2)
+      if (j2 < n2x) {
+        const C2 v = buf[jp2 * rs1 + k12 * (n2x + 1) + j2];
+        xr[j2] = v.x;
+        xi[j2] = v.y;
+      }
+    dft_reg(xr, xi, n2x, T(-1));
+  }
+  __syncthreads();
+  if (tx2) {
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2)
+      if (k2 < n2x) {
+        C2 v;
+        v.x = xr[k2];
+        v.y = xi[k2];
+        buf[jp2 * rz + k12 + (k2 << lg1x)] = v;
+      }
+  }
+  __syncthreads();
+  // Columns kx <= nx/2: task (kx, j2), kx fastest; row j of the real
+  // transform is (Z(kx) + conj Z(-kx)) / 2 (j even) or (Z(kx) - conj
+  // Z(-kx)) / 2i (j odd) of its packed row; the 1/2 joins h2 at the end.
+  const bool ty1 = t < nxh * n2y;
+  const int kx1 = t % nxh, j2y = t / nxh;
+  if (ty1) {
+    const int km = (nx - kx1) & (nx - 1);
+#pragma unroll
+    for (int j1 = 0; j1 < 8; ++j1)
+      if (j1 < n1y) {
+        const int j = n2y * j1 + j2y;
+        const C2 za = buf[(j >> 1) * rz + kx1], zb = buf[(j >> 1) * rz + km];
+        const bool odd = j & 1;
+        xr[j1] = odd ? za.y + zb.y : za.x + zb.x;
+        xi[j1] = odd ? zb.x - za.x : za.y - zb.y;
+      }
+    dft_reg(xr, xi, n1y, T(-1));
+    twiddle(xr, xi, n1y, twy, ny, j2y, T(-1));
+  }
+  __syncthreads();
+  if (ty1) {
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1)
+      if (k1 < n1y) {
+        C2 v;
+        v.x = xr[k1];
+        v.y = xi[k1];
+        buf[(k1 * n2y + j2y) * nxh + kx1] = v;
+      }
+  }
+  __syncthreads();
+  const bool ty2 = t < nxh * n1y;
+  const int kx2 = t % nxh, k1y = t / nxh;
+  if (ty2) {
+#pragma unroll
+    for (int j2 = 0; j2 < 8; ++j2)
+      if (j2 < n2y) {
+        const C2 v = buf[(k1y * n2y + j2) * nxh + kx2];
+        xr[j2] = v.x;
+        xi[j2] = v.y;
+      }
+    dft_reg(xr, xi, n2y, T(-1));
+    const T sc = T(0.5) * (T)L.h2;
+    C2* out = reinterpret_cast<C2*>(s + (long long)blockIdx.x * 2 * nm);
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2)
+      if (k2 < n2y) {
+        C2 v;
+        v.x = sc * xr[k2];
+        v.y = sc * xi[k2];
+        out[(k1y + n1y * k2) * nxh + kx2] = v;
+      }
+  }
+}
+
+// Inverse: the solved half spectrum of one plane -> u (columns first, then
+// two rows at a time as one complex row whose halves are the Hermitian
+// extensions of the two; the imaginary parts at kx = 0 and nx/2 are those
+// of a real row's transform, zero).
+template <typename T>
+__global__ void __launch_bounds__(kFftThreads) k_spec_inv_fft(
+    LevelC L, const T* __restrict__ s, T* __restrict__ u, int nm,
+    const Counters* dc) {
+  using C2 = typename Pair2<T>::type;
+  __shared__ C2 buf[kFftSlots];
+  __shared__ C2 twx[kSpecMaxFFT], twy[kSpecMaxFFT];
+  if (dc->done) return;
+  const int nx = L.nx, ny = L.ny, nxh = nx / 2 + 1, nyp = ny / 2;
+  const int n1x = nx < 8 ? nx : 8, n2x = nx / n1x;
+  const int n1y = ny < 8 ? ny : 8, n2y = ny / n1y;
+  const int lg1x = ilog2_pow2(n1x), lg2x = ilog2_pow2(n2x);
+  const int rs1 = n1x * (n2x + 1);
+  const int rg = nxh + 3;  // row stride of the column-transformed spectrum
+  const int t = threadIdx.x;
+  const C2* in = reinterpret_cast<const C2*>(s + (long long)blockIdx.x * 2 * nm);
+  fill_fft_tw(twx, nx);
+  fill_fft_tw(twy, ny);
+  T xr[8], xi[8];
+  const bool ty1 = t < nxh * n2y;
+  const int kx1 = t % nxh, j2y = t / nxh;
+  if (ty1) {
+#pragma unroll
+    for (int j1 = 0; j1 < 8; ++j1)
+      if (j1 < n1y) {
+        const C2 v = in[(n2y * j1 + j2y) * nxh + kx1];
+        xr[j1] = v.x;
+        xi[j1] = v.y;
+      }
+  }
+  __syncthreads();
+  if (ty1) {
+    dft_reg(xr, xi, n1y, T(1));
+    twiddle(xr, xi, n1y, twy, ny, j2y, T(1));
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1)
+      if (k1 < n1y) {
+        C2 v;
+        v.x = xr[k1];
+        v.y = xi[k1];
+        buf[(k1 * n2y + j2y) * nxh + kx1] = v;
+      }
+  }
+  __syncthreads();
+  const bool ty2 = t < nxh * n1y;
+  const int kx2 = t % nxh, k1y = t / nxh;
+  if (ty2) {
+#pragma unroll
+    for (int j2 = 0; j2 < 8; ++j2)
+      if (j2 < n2y) {
+        const C2 v = buf[(k1y * n2y + j2) * nxh + kx2];
+        xr[j2] = v.x;
+        xi[j2] = v.y;
+      }
+    dft_reg(xr, xi, n2y, T(1));
+  }
+  __syncthreads();
+  if (ty2) {
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2)
+      if (k2 < n2y) {
+        C2 v;
+        v.x = xr[k2];
+        v.y = xi[k2];
+        buf[(k1y + n1y * k2) * rg + kx2] = v;
+      }
+  }
+  __syncthreads();
+  // Rows: task (jp, j2), j2 fastest; z(kx) = Ga(kx) + i Gb(kx) with
+  // G(nx - kx) = conj G(kx).
+  const bool tx1 = t < (nyp << lg2x);
+  const int jp1 = t >> lg2x, j21 = t & (n2x - 1);
+  const int nh = nx / 2;
+  if (tx1) {
+#pragma unroll
+    for (int j1 = 0; j1 < 8; ++j1)
+      if (j1 < n1x) {
+        const int kx = (j1 << lg2x) + j21;
+        const bool hi = kx > nh;
+        const int kk = hi ? nx - kx : kx;
+        const C2 ga = buf[(2 * jp1) * rg + kk], gb = buf[(2 * jp1 + 1) * rg + kk];
+        const bool edge = kk == 0 || kk == nh;
+        const T gai = edge ? T(0) : (hi ? -ga.y : ga.y);
+        const T gbi = edge ? T(0) : (hi ? -gb.y : gb.y);
+        xr[j1] = ga.x - gbi;
+        xi[j1] = gai + gb.x;
+      }
+    dft_reg(xr, xi, n1x, T(1));
+    twiddle(xr, xi, n1x, twx, nx, j21, T(1));
+  }
+  __syncthreads();
+  if (tx1) {
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1)
+      if (k1 < n1x) {
+        C2 v;
+        v.x = xr[k1];
+        v.y = xi[k1];
+        buf[jp1 * rs1 + k1 * (n2x + 1) + j21] = v;
+      }
+  }
+  __syncthreads();
+  const bool tx2 = t < (nyp << lg1x);
+  const int jp2 = t >> lg1x, k12 = t & (n1x - 1);
+  if (tx2) {
+#pragma unroll
+    for (int j2 = 0; j2 < 8; ++j2)
+      if (j2 < n2x) {
+        const C2 v = buf[jp2 * rs1 + k12 * (n2x + 1) + j2];
+        xr[j2] = v.x;
+        xi[j2] = v.y;
+      }
+    dft_reg(xr, xi, n2x, T(1));
+    const T sc = T(1) / (T)(nx * ny);
+    T* dst = u + (long long)(L.k0 + blockIdx.x) * L.nxy;
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2)
+      if (k2 < n2x) {
+        const int i = k12 + (k2 << lg1x);
+        dst[(2 * jp2) * nx + i] = sc * xr[k2];
+        dst[(2 * jp2 + 1) * nx + i] = sc * xi[k2];
+      }
+  }
 }
 
 __host__ __device__ constexpr bool is_pow2(int n) { return n > 0 && !(n & (n - 1)); }
@@ -1545,25 +1765,24 @@ void spectral_solve(pic_ctx* c, int l) {
   const int nm = c->spec_modes, np = c->spec_planes;
   T* s = reinterpret_cast<T*>(c->spec_s);
   T* mi = reinterpret_cast<T*>(c->spec_m);
-  T* cp = reinterpret_cast<T*>(c->spec_c);
   if (!c->spec_ready) {
-    k_spec_factor<T><<<nblocks(nm), kThreads, 0, st>>>(Lc, mi, cp, nm);
+    k_spec_factor<T><<<nblocks(nm), kThreads, 0, st>>>(Lc, mi, nm);
     c->spec_ready = true;
   }
-  const int G = spec_group<T>(np);
-  const size_t lds = (size_t)np * 4 * G * sizeof(T);
   const bool fft = is_pow2(L.nx) && is_pow2(L.ny) && L.nx <= kSpecMaxFFT &&
                    L.ny <= kSpecMaxFFT;
   if (fft)
-    k_spec_fwd_fft<T><<<(unsigned)np, 256, 0, st>>>(Lc, lev_f<T>(L), s, nm, c->dc);
+    k_spec_fwd_fft<T><<<(unsigned)np, kFftThreads, 0, st>>>(Lc, lev_f<T>(L), s, nm, c->dc);
   else
-    k_spec_fwd<T><<<(unsigned)np, 256, 0, st>>>(Lc, lev_f<T>(L), s, nm, c->dc);
-  k_spec_tri<T><<<(unsigned)((nm + G - 1) / G), 256, lds, st>>>(
-      Lc, s, mi, cp, nm, G, c->dc);
+    k_spec_fwd<T><<<(unsigned)np, kSpecThreads, 0, st>>>(Lc, lev_f<T>(L), s, nm, c->dc);
+  const int lgw = spec_tri_lgw(np);
+  const int mpb = 1 << (lgw - 1);  // modes per workgroup
+  k_spec_tri<T><<<(unsigned)((nm + mpb - 1) / mpb), kSpecThreads, 0, st>>>(
+      Lc, s, mi, nm, lgw, c->dc);
   if (fft)
-    k_spec_inv_fft<T><<<(unsigned)np, 256, 0, st>>>(Lc, s, lev_u<T>(L), nm, c->dc);
+    k_spec_inv_fft<T><<<(unsigned)np, kFftThreads, 0, st>>>(Lc, s, lev_u<T>(L), nm, c->dc);
   else
-    k_spec_inv<T><<<(unsigned)np, 256, 0, st>>>(Lc, s, lev_u<T>(L), nm, c->dc);
+    k_spec_inv<T><<<(unsigned)np, kSpecThreads, 0, st>>>(Lc, s, lev_u<T>(L), nm, c->dc);
 }
 
 // Workgroups of k_smooth2<T, *> the current device runs at once.

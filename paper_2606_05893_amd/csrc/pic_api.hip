@@ -157,7 +157,6 @@ size_t carve(pic_ctx* c, char* base) {
     const long long pm = (long long)c->spec_planes * c->spec_modes;
     c->spec_s = cv.take<char>(2 * pm * es);
     c->spec_m = cv.take<char>(pm * es);
-    c->spec_c = cv.take<char>(pm * es);
   }
   c->part_n = cv.take<double>(neutral_push_blocks(f.capacity[1]));
   c->qpartials = cv.take<long long>(1024);

@@ -86,7 +86,6 @@ struct pic_ctx {
   int spec_modes, spec_planes;   // ny * (nx/2 + 1); unknown planes
   void* spec_s;                  // spectrum, planes x modes x (re, im)
   void* spec_m;                  // inverse pivots, planes x modes
-  void* spec_c;                  // eliminated upper coefficients
   bool spec_ready;               // pivots computed
   double* partials;          // reduction partials
   double* part_n;            // neutral push partials (one per workgroup)
