@@ -1111,11 +1111,11 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
 // ---- neutral push ---------------------------------------------------------
 // Neutrals drift (no field), cross the boundaries and are counted per cell
 // for the collisions.  The evaporation sources pile up neutrals in a few
-// hundred cells above the cathode, so a global atomic per neutral would
+// hundred cells above the cathode, so a global atomic per new neutral would
 // serialise on those cells: a workgroup takes chunks of kNChunk neutrals
-// and aggregates their cell counts in an LDS hash table first (one global
-// atomic per distinct cell and chunk; probes that find no slot fall back to
-// the global atomic).
+// and aggregates the new neutrals' cell counts in an LDS hash table first
+// (one global atomic per distinct cell and chunk; probes that find no slot
+// fall back to the global atomic).
 constexpr int kNChunk = 4096;
 constexpr int kHist = 2048;
 constexpr unsigned kHistEmpty = 0xFFFFFFFFu;
@@ -1149,10 +1149,15 @@ __device__ __forceinline__ void hist_flush(unsigned* hk, int* hc,
     if (hk[s] != kHistEmpty) atomicAdd(&ncount[hk[s]], hc[s]);
 }
 
+// Neutrals per cell are kept up to date across steps: the first n_old
+// neutrals (those at the start of the step, all counted) change the count
+// only when their cell changes or they leave the domain, and the ones
+// appended since are added.  A neutral's previous cell is that of its
+// stored position, the value the previous step counted.
 __global__ void __launch_bounds__(kT) k_push_neutral(
     Parts p, uint32_t* __restrict__ key, GridC g, double dt,
-    int* __restrict__ ncount, MccC m, uint32_t step, uint64_t seed,
-    Rec* __restrict__ ab_rec, double* __restrict__ ab_pos,
+    int* __restrict__ ncount, long long n_old, MccC m, uint32_t step,
+    uint64_t seed, Rec* __restrict__ ab_rec, double* __restrict__ ab_pos,
     double* __restrict__ ab_vel, long long ab_cap, Counters* dc,
     double* __restrict__ part) {
   __shared__ unsigned hk[kHist];
@@ -1162,9 +1167,12 @@ __global__ void __launch_bounds__(kT) k_push_neutral(
   const long long nchunk = (n + kNChunk - 1) / kNChunk;
   double ke = 0.0;
   for (long long cb = blockIdx.x; cb < nchunk; cb += gridDim.x) {
-    hist_clear(hk, hc);
-    __syncthreads();
     const long long b0 = cb * kNChunk;
+    const bool fresh = b0 + kNChunk > n_old;  // holds appended neutrals
+    if (fresh) {
+      hist_clear(hk, hc);
+      __syncthreads();
+    }
     for (int r = 0; r < kNChunk; r += kT) {
       const long long i = b0 + r + threadIdx.x;
       PushOut o;
@@ -1172,16 +1180,28 @@ __global__ void __launch_bounds__(kT) k_push_neutral(
       o.anode = false;
       o.cand = false;
       if (i < n) {
-        finish_push<1>(p, i, p.x[i], p.y[i], p.z[i], p.vx[i], p.vy[i],
-                       p.vz[i], dt, g, key, ncount, m, step, seed, dc, o, 0ull);
-        if (o.cell != kDead) hist_add(hk, hc, o.cell, ncount);
+        const double x = p.x[i], y = p.y[i], z = p.z[i];
+        const unsigned prev = i < n_old ? cell_of(x, y, z, g) : kDead;
+        finish_push<1>(p, i, x, y, z, p.vx[i], p.vy[i], p.vz[i], dt, g, key,
+                       ncount, m, step, seed, dc, o, 0ull);
+        if (o.cell != prev) {
+          if (prev != kDead) atomicSub(&ncount[prev], 1);
+          if (o.cell != kDead) {
+            if (i >= n_old)
+              hist_add(hk, hc, o.cell, ncount);
+            else
+              atomicAdd(&ncount[o.cell], 1);
+          }
+        }
         ke = ke + o.ke;
       }
       sink<1>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
     }
-    __syncthreads();
-    hist_flush(hk, hc, ncount);
-    __syncthreads();
+    if (fresh) {
+      __syncthreads();
+      hist_flush(hk, hc, ncount);
+      __syncthreads();
+    }
   }
   const double s = block_sum(ke, sk);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -1189,8 +1209,8 @@ __global__ void __launch_bounds__(kT) k_push_neutral(
 
 __global__ void __launch_bounds__(kT) k_push_neutral_m(
     PartsM p, uint32_t* __restrict__ key, GridC g, float dtdx,
-    int* __restrict__ ncount, MccC m, uint32_t step, uint64_t seed,
-    Rec* __restrict__ ab_rec, double* __restrict__ ab_pos,
+    int* __restrict__ ncount, long long n_old, MccC m, uint32_t step,
+    uint64_t seed, Rec* __restrict__ ab_rec, double* __restrict__ ab_pos,
     double* __restrict__ ab_vel, long long ab_cap, Counters* dc,
     double* __restrict__ part) {
   __shared__ unsigned hk[kHist];
@@ -1200,9 +1220,12 @@ __global__ void __launch_bounds__(kT) k_push_neutral_m(
   const long long nchunk = (n + kNChunk - 1) / kNChunk;
   double ke = 0.0;
   for (long long cb = blockIdx.x; cb < nchunk; cb += gridDim.x) {
-    hist_clear(hk, hc);
-    __syncthreads();
     const long long b0 = cb * kNChunk;
+    const bool fresh = b0 + kNChunk > n_old;  // holds appended neutrals
+    if (fresh) {
+      hist_clear(hk, hc);
+      __syncthreads();
+    }
     for (int r = 0; r < kNChunk; r += kT) {
       const long long i = b0 + r + threadIdx.x;
       PushOut o;
@@ -1210,16 +1233,27 @@ __global__ void __launch_bounds__(kT) k_push_neutral_m(
       o.anode = false;
       o.cand = false;
       if (i < n) {
+        const unsigned prev = i < n_old ? p.cell[i] : kDead;
         push_one_m<1>(p, i, nullptr, nullptr, nullptr, 0, 0, 0, nullptr, 0, g,
                       0.0f, dtdx, key, ncount, m, step, seed, dc, o);
-        if (o.cell != kDead) hist_add(hk, hc, o.cell, ncount);
+        if (o.cell != prev) {
+          if (prev != kDead) atomicSub(&ncount[prev], 1);
+          if (o.cell != kDead) {
+            if (i >= n_old)
+              hist_add(hk, hc, o.cell, ncount);
+            else
+              atomicAdd(&ncount[o.cell], 1);
+          }
+        }
         ke = ke + o.ke;
       }
       sink_m(p, i, 1, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
     }
-    __syncthreads();
-    hist_flush(hk, hc, ncount);
-    __syncthreads();
+    if (fresh) {
+      __syncthreads();
+      hist_flush(hk, hc, ncount);
+      __syncthreads();
+    }
   }
   const double s = block_sum(ke, sk);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -1500,7 +1534,7 @@ __global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
                          uint32_t* __restrict__ kn, uint32_t* __restrict__ ki,
                          const Rec* __restrict__ ok, const uint2* __restrict__ okp,
                          MccC m, uint32_t step, uint64_t seed, long long cap_e,
-                         long long cap_i, Counters* dc) {
+                         long long cap_i, int* __restrict__ ncount, Counters* dc) {
   const long long nok = (long long)dc->n_ok;
   const long long ne0 = (long long)dc->n[0], ni0 = (long long)dc->n[2];
   const unsigned long long id0 = dc->next_id;
@@ -1537,6 +1571,8 @@ __global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
     } else {
       atomicOr(&dc->err, kErrCapacity);
     }
+    // The neutral leaves the per-cell counts of the next step.
+    atomicSub(&ncount[kn[in]], 1);
     kn[in] = kDead;
   }
 }
@@ -2007,6 +2043,7 @@ void sources_host_t(pic_ctx* c) {
   const uint32_t step = (uint32_t)c->step;
   const uint64_t seed = c->cfg.seed;
   long long n[3] = {c->n[0], c->n[1], c->n[2]};
+  c->n_start1 = c->n[1];
   unsigned long long nid = c->next_id;
   for (const QueueCall& q : c->queue) {
     if (q.n <= 0) continue;
@@ -2096,18 +2133,23 @@ void push_neutral_t(pic_ctx* c, double dt) {
   const uint64_t seed = c->cfg.seed;
   const MccC m = mcc_constants(c, dt);
   const long long ab_cap = c->cfg.max_events;
-  hipMemsetAsync(c->ncount, 0, c->ncells * sizeof(int), st);
+  // Neutrals per cell: updated from the counts of the step before, or
+  // counted afresh after the population was replaced.
+  const long long n_old = c->ncount_valid ? c->n_start1 : 0;
+  if (!c->ncount_valid) hipMemsetAsync(c->ncount, 0, c->ncells * sizeof(int), st);
   tmark(c, PIC_PH_PUSH_NEUTRAL, true);
   const long long nb = neutral_push_blocks(bound(c, 1));
   if (c->mixed)
     k_push_neutral_m<<<nb, kT, 0, st>>>(
         cur<PartsM>(c, 1), c->key[1], c->g, (float)(dt * c->g.inv_dx),
-        c->ncount, m, step, seed, c->ab_rec, c->ab_raw_pos, c->ab_raw_vel,
-        ab_cap, c->dc, c->part_n);
+        c->ncount, n_old, m, step, seed, c->ab_rec, c->ab_raw_pos,
+        c->ab_raw_vel, ab_cap, c->dc, c->part_n);
   else
     k_push_neutral<<<nb, kT, 0, st>>>(
-        cur<Parts>(c, 1), c->key[1], c->g, dt, c->ncount, m, step, seed,
-        c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, c->part_n);
+        cur<Parts>(c, 1), c->key[1], c->g, dt, c->ncount, n_old, m, step,
+        seed, c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc,
+        c->part_n);
+  c->ncount_valid = true;
   tmark(c, PIC_PH_PUSH_NEUTRAL, false);
   k_sum_partials<<<1, 1024, 0, st>>>(c->part_n, nb, nullptr, c->part_n, 0,
                                      0.5 * kMcu, &c->dc->kinetic[1]);
@@ -2260,7 +2302,7 @@ void push_collide_t(pic_ctx* c, double dt) {
     k_ionise<PT><<<64, kT, 0, st>>>(cur<PT>(c, 0), cur<PT>(c, 1), cur<PT>(c, 2),
                                     c->key[0], c->key[1], c->key[2], c->ok,
                                     c->okp, m, step, seed, c->cfg.capacity[0],
-                                    c->cfg.capacity[2], c->dc);
+                                    c->cfg.capacity[2], c->ncount, c->dc);
     k_ionise_commit<<<1, 1024, 0, st>>>(c->dc, c->ev, c->flag, cap,
                                         c->cfg.capacity[0], c->cfg.capacity[2],
                                         c->el_cnt, c->cand_cnt,

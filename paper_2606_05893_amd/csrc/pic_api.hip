@@ -377,6 +377,8 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   }
   c->nch_bound = 1;
   c->tcounted = false;
+  c->ncount_valid = false;
+  c->n_start1 = 0;
   c->n_stirred = 0;
   c->neutrals_binned = false;
   c->next_id = 0;
@@ -615,7 +617,10 @@ pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
   if (v != PIC_OK) return v;
   parts_sources_host(c);
   parts_push_neutral(c, dt);
-  return advance_finish(c, dt, add, out, diag);
+  const pic_status st = advance_finish(c, dt, add, out, diag);
+  // After a failed step the neutrals are counted afresh.
+  if (st != PIC_OK) c->ncount_valid = false;
+  return st;
 }
 
 pic_status pic_step(pic_ctx* c, double dt, pic_absorbed* out, pic_diag* diag) {
@@ -696,6 +701,7 @@ pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
     return set_err(c, PIC_ERR_CAPACITY, "load exceeds capacity");
   if (n > 0 && (!pos || !vel || !ids)) return PIC_ERR_ARG;
   parts_load(c, s, n, pos, vel, ids);
+  if (s == 1) c->ncount_valid = false;
   // The new population has no tile ranges yet: all of it bins as a tail.
   hipMemsetAsync(c->tsb[s][c->tcur[s]], 0, (c->ntiles + 1) * sizeof(uint32_t),
                  c->stream);
@@ -830,6 +836,7 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
   pic_status st = pic_set_collisions(c, &h.coll);
   if (st == PIC_OK) st = pic_set_sources(c, &h.src);
   if (st != PIC_OK) return st;
+  c->ncount_valid = false;  // the neutrals are replaced
   for (int s = 0; s < 3; ++s) c->n[s] = h.n[s];
   const char* in = static_cast<const char*>(host);
   size_t off = sizeof(h);

@@ -94,6 +94,8 @@ struct pic_ctx {
 
   // Collisions and ionisation matching.
   int* ncount;               // neutrals per cell
+  bool ncount_valid;         // ncount counts the first n_start1 neutrals
+  long long n_start1;        // neutrals at the start of the step's sources
   uint8_t* flag;             // cells holding ionisation events
   uint32_t* cand;            // electron indices of null-collision candidates
   uint32_t* cand_cnt;        // candidates per tile
