@@ -22,7 +22,7 @@ constexpr int kT = 256;
 // bitonic pass is bound by LDS bandwidth (16-byte records): small chunks
 // spread a list over many CUs, at the cost of two more merge rounds.
 constexpr int kSortChunk = 1024;
-constexpr int kSortT = 256;
+constexpr int kSortT = kSortChunk / 2;  // one compare-exchange per thread and stage
 constexpr int kFixedBlocks = 2048;
 
 inline unsigned nblk(long long n, int t = kT) {
@@ -52,6 +52,12 @@ __device__ __forceinline__ unsigned long long wave_append(
   if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
   base = bcast64(base, leader);
   return base + (unsigned long long)__popcll(below);
+}
+
+// Lanes below this one whose bit is set in mask.
+__device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
+  const int lane = lane_id();
+  return lane ? (unsigned)__popcll(mask & (~0ull >> (64 - lane))) : 0u;
 }
 
 // Wave-aggregated count: the lanes with pred add one each to *counter
@@ -198,7 +204,7 @@ __global__ void k_begin(Counters* dc, unsigned long long n0,
   dc->n_dead = dc->n_holes = dc->n_movers = 0;
   dc->n_cand = dc->n_elastic = dc->n_events = dc->n_ok = 0;
   dc->n_over = dc->n_near = dc->n_ab = dc->n_ncand = 0;
-  dc->n_tail_cand = 0;
+  dc->n_tail_cand = dc->n_el_tail = 0;
 }
 
 // ---- sources ------------------------------------------------------------------
@@ -1297,10 +1303,14 @@ __device__ __forceinline__ double sigma_ion(const MccC& m, double E_eV) {
   return m.sigma_const;
 }
 
-// Candidates of one chunk (block t < number of chunks) or of the unbinned
-// tail (block t == number of chunks): second draw U2 against the cumulative process probabilities
-// (ionisation, then elastic).  Elastic scattering is applied at once;
-// ionisation events are recorded as (cell, electron id) for matching.
+// Null-collision candidates: second draw U2 against the cumulative process
+// probabilities (ionisation, then elastic).  Elastic scattering is applied
+// at once; ionisation events are recorded as (cell, electron id) for
+// matching.  One wave per chunk of binned electrons (its candidates sit in
+// the chunk's own segment of the candidate list), then waves of kMccPiece
+// candidates over the unbinned electrons' ones.
+constexpr int kMccPiece = 512;
+
 template <class PT>
 __global__ void __launch_bounds__(kT) k_mcc(
     PT p, const uint32_t* __restrict__ key, const uint32_t* __restrict__ cand,
@@ -1309,10 +1319,8 @@ __global__ void __launch_bounds__(kT) k_mcc(
     long long tail_first, MccC m, uint32_t step,
     uint64_t seed, Rec* __restrict__ ev, uint8_t* __restrict__ flag,
     long long ev_cap, uint32_t* __restrict__ el_cnt, Counters* dc) {
-  __shared__ unsigned s_el;
-  const unsigned t = blockIdx.x;
-  const unsigned nch = *nchunks;
-  if (t > nch) return;
+  const long long nch = *nchunks;
+  const long long t = blockIdx.x * (long long)(kT / 64) + threadIdx.x / 64;
   long long b, e;
   if (t < nch) {
     unsigned pb, pe;
@@ -1320,14 +1328,16 @@ __global__ void __launch_bounds__(kT) k_mcc(
     b = pb;
     e = b + cand_cnt[t];
   } else {
-    b = tail_first;
-    e = b + (long long)dc->n_tail_cand;
+    const long long te = tail_first + (long long)dc->n_tail_cand;
+    b = tail_first + (t - nch) * kMccPiece;
+    e = b + kMccPiece < te ? b + kMccPiece : te;
+    if (b >= e) return;  // whole wave
   }
-  if (threadIdx.x == 0) s_el = 0;
-  __syncthreads();
-  for (long long base = b; base < e; base += blockDim.x) {
-    const long long q = base + threadIdx.x;
-    bool event = false;
+  const int lane = lane_id();
+  unsigned n_el = 0;  // wave-uniform
+  for (long long base = b; base < e; base += 64) {
+    const long long q = base + lane;
+    bool event = false, elastic = false;
     uint32_t i = 0;
     unsigned long long id = 0;
     if (q < e) {
@@ -1350,7 +1360,7 @@ __global__ void __launch_bounds__(kT) k_mcc(
       if (u2 < p_ion) {
         event = true;
       } else if (u2 < p_tot) {
-        atomicAdd(&s_el, 1u);
+        elastic = true;
         double u3, u4, nx, ny, nz;
         uniform2(id, step, kTagMcc1, seed, u3, u4);
         isotropic(u3, u4, nx, ny, nz);
@@ -1360,6 +1370,7 @@ __global__ void __launch_bounds__(kT) k_mcc(
         Acc<PT>::set_vel(p, i, sp * nx, sp * ny, sp * nz);
       }
     }
+    n_el += (unsigned)__popcll(__ballot(elastic));
     const unsigned long long s = wave_append(event, &dc->n_events);
     if (event) {
       const uint32_t cell = key[i];
@@ -1373,8 +1384,12 @@ __global__ void __launch_bounds__(kT) k_mcc(
       }
     }
   }
-  __syncthreads();
-  if (threadIdx.x == 0) el_cnt[t] = s_el;
+  if (lane == 0) {
+    if (t < nch)
+      el_cnt[t] = n_el;
+    else if (n_el)
+      atomicAdd(&dc->n_el_tail, (unsigned long long)n_el);
+  }
 }
 
 // Sort of a record list by (hi, lo) (keys are unique): every kSortChunk
@@ -1393,38 +1408,39 @@ __global__ void __launch_bounds__(kSortT) k_sort_chunks(
   const long long base = (long long)blockIdx.x * kSortChunk;
   if (base >= n || n <= 1) return;
   const int m = (int)(n - base < kSortChunk ? n - base : kSortChunk);
-  int P = 1;
-  while (P < m) P <<= 1;
   Rec maxr;
   maxr.lo = ~0ull; maxr.hi = ~0u; maxr.val = 0u;
   const int tid = threadIdx.x;
-  for (int q = tid; q < P; q += kSortT) s[q] = q < m ? a[base + q] : maxr;
+  // A short chunk is padded with the largest key, so the network is fixed.
+  const Rec r0 = tid < m ? a[base + tid] : maxr;
+  const Rec r1 = tid + kSortT < m ? a[base + tid + kSortT] : maxr;
+  s[tid] = r0;
+  s[tid + kSortT] = r1;
   __syncthreads();
-  // Bitonic network over P keys: each stage compares the P / 2 pairs
-  // (q, q | j) with bit j of q clear, in the direction of bit k of q.
-  for (int k = 2; k <= P; k <<= 1)
+  // Bitonic network: each stage compares the kSortChunk / 2 pairs (q, q | j)
+  // with bit j of q clear, in the direction of bit k of q; thread t takes
+  // the t-th pair.
+#pragma unroll
+  for (int k = 2; k <= kSortChunk; k <<= 1)
+#pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int t = tid; t < P / 2; t += kSortT) {
-        const int q = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-        const int o = q | j;
-        const bool up = (q & k) == 0;
-        const Rec x = s[q], y = s[o];
-        if (up ? rec_less(y, x) : rec_less(x, y)) { s[q] = y; s[o] = x; }
-      }
+      const int q = ((tid & ~(j - 1)) << 1) | (tid & (j - 1));
+      const int o = q | j;
+      const bool up = (q & k) == 0;
+      const Rec x = s[q], y = s[o];
+      if (up ? rec_less(y, x) : rec_less(x, y)) { s[q] = y; s[o] = x; }
       __syncthreads();
     }
-  for (int q = tid; q < m; q += kSortT) a[base + q] = s[q];
+  if (tid < m) a[base + tid] = s[tid];
+  if (tid + kSortT < m) a[base + tid + kSortT] = s[tid + kSortT];
 }
 
-// One merge round: runs of width w (sorted) pairwise into runs of 2w.
-__global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst,
-                              const unsigned long long* __restrict__ count,
-                              long long cap, long long w) {
-  long long n = (long long)*count;
-  if (n > cap) n = cap;
-  if (w >= n) return;   // one run already
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// Record i of a merge round: runs of width w (sorted) pairwise into runs
+// of 2w; its position is its rank in its own run plus the number of smaller
+// keys in the partner run (binary search).
+__device__ __forceinline__ void merge_one(const Rec* __restrict__ src,
+                                          Rec* __restrict__ dst, long long n,
+                                          long long w, long long i) {
   const long long pair = i / (2 * w);
   const long long a0 = pair * 2 * w;
   const long long a1 = a0 + w < n ? a0 + w : n;      // run A = [a0, a1)
@@ -1449,6 +1465,17 @@ __global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst
   dst[pos] = x;
 }
 
+__global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst,
+                              const unsigned long long* __restrict__ count,
+                              long long cap, long long w) {
+  long long n = (long long)*count;
+  if (n > cap) n = cap;
+  if (w >= n) return;   // one run already
+  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  merge_one(src, dst, n, w, i);
+}
+
 // The sorted list back into the first buffer when the merge rounds that
 // ran (those with run width below the length) were odd in number.
 __global__ void k_copy_recs(const Rec* __restrict__ src, Rec* __restrict__ dst,
@@ -1464,30 +1491,64 @@ __global__ void k_copy_recs(const Rec* __restrict__ src, Rec* __restrict__ dst,
     dst[i] = src[i];
 }
 
-// Neutrals in cells that hold ionisation events.
+// Neutrals in cells that hold ionisation events.  A workgroup scans
+// kNCPer x kT neutrals (coalesced) and reserves its slots in the list with
+// one atomic; the list order is free (it is sorted next).
+constexpr int kNCPer = 16;
+constexpr int kNCChunk = kNCPer * kT;
+
 template <class PT>
-__global__ void k_neutral_cands(PT p, const uint32_t* __restrict__ key,
-                                const uint8_t* __restrict__ flag,
-                                Rec* __restrict__ nc, long long cap,
-                                Counters* dc) {
+__global__ void __launch_bounds__(kT) k_neutral_cands(
+    PT p, const uint32_t* __restrict__ key, const uint8_t* __restrict__ flag,
+    Rec* __restrict__ nc, long long cap, Counters* dc) {
+  __shared__ unsigned sw[kT / 64];
+  __shared__ unsigned long long sbase;
   if (dc->n_events == 0) return;
   const long long n = (long long)dc->n[1];
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  bool hit = false;
-  unsigned cell = kDead;
-  if (i < n) {
-    cell = key[i];
-    hit = cell != kDead && flag[cell];
+  const long long b0 = blockIdx.x * (long long)kNCChunk;
+  if (b0 >= n) return;
+  uint32_t cell[kNCPer];
+  unsigned long long mk[kNCPer];
+  unsigned cnt = 0;  // wave-uniform
+#pragma unroll
+  for (int r = 0; r < kNCPer; ++r) {
+    const long long i = b0 + r * kT + threadIdx.x;
+    cell[r] = i < n ? key[i] : kDead;
   }
-  const unsigned long long s = wave_append(hit, &dc->n_ncand);
-  if (hit) {
-    if ((long long)s < cap) {
-      Rec r;
-      r.hi = cell; r.lo = p.id[i]; r.val = (unsigned)i;
-      nc[s] = r;
-    } else {
-      atomicOr(&dc->err, kErrEvents);
+#pragma unroll
+  for (int r = 0; r < kNCPer; ++r) {
+    const bool hit = cell[r] != kDead && flag[cell[r]];
+    mk[r] = __ballot(hit);
+    cnt += (unsigned)__popcll(mk[r]);
+  }
+  const int w = threadIdx.x / 64;
+  if (lane_id() == 0) sw[w] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned tot = 0;
+    for (int q = 0; q < kT / 64; ++q) {
+      const unsigned c = sw[q];
+      sw[q] = tot;
+      tot += c;
     }
+    sbase = tot ? atomicAdd(&dc->n_ncand, (unsigned long long)tot) : 0ull;
+  }
+  __syncthreads();
+  unsigned long long s = sbase + sw[w];
+#pragma unroll
+  for (int r = 0; r < kNCPer; ++r) {
+    if ((mk[r] >> lane_id()) & 1ull) {
+      const unsigned long long slot = s + lanes_below(mk[r]);
+      const long long i = b0 + r * kT + threadIdx.x;
+      if ((long long)slot < cap) {
+        Rec rec;
+        rec.hi = cell[r]; rec.lo = p.id[i]; rec.val = (unsigned)i;
+        nc[slot] = rec;
+      } else {
+        atomicOr(&dc->err, kErrEvents);
+      }
+    }
+    s += (unsigned long long)__popcll(mk[r]);
   }
 }
 
@@ -1591,7 +1652,7 @@ __global__ void k_ionise_commit(Counters* dc, const Rec* __restrict__ ev,
   if (ne > cap) ne = cap;
   for (long long e = threadIdx.x; e < ne; e += blockDim.x) flag[ev[e].hi] = 0;
   unsigned long long a = 0, b = 0;
-  for (long long q = threadIdx.x; q <= ntiles; q += blockDim.x) a += el_cnt[q];
+  for (long long q = threadIdx.x; q < ntiles; q += blockDim.x) a += el_cnt[q];
   for (long long q = threadIdx.x; q < ntiles; q += blockDim.x) b += cand_cnt[q];
   s[threadIdx.x] = a;
   s2[threadIdx.x] = b;
@@ -1604,7 +1665,7 @@ __global__ void k_ionise_commit(Counters* dc, const Rec* __restrict__ ev,
     __syncthreads();
   }
   if (threadIdx.x) return;
-  dc->n_elastic = s[0];
+  dc->n_elastic = s[0] + dc->n_el_tail;
   dc->n_cand = s2[0] + dc->n_tail_cand;
   long long ok = (long long)dc->n_ok;
   long long add = ok;
@@ -2289,12 +2350,16 @@ void push_collide_t(pic_ctx* c, double dt) {
   const long long cap = c->cfg.max_events;
   tmark(c, PIC_PH_COLLIDE, true);
   if (m.enabled) {
-    k_mcc<PT><<<(unsigned)(nch + 1), kT, 0, st>>>(
+    // Waves: one per chunk, then the unbinned electrons' candidates (at
+    // most one per electron appended this step) in pieces.
+    const long long tail = std::max(0ll, bound(c, 0) - c->n_binned[0]);
+    const long long waves = nch + std::max(1ll, (tail + kMccPiece - 1) / kMccPiece);
+    k_mcc<PT><<<(unsigned)((waves + kT / 64 - 1) / (kT / 64)), kT, 0, st>>>(
         cur<PT>(c, 0), c->key[0], c->cand, ts_cur(c, 0), c->cand_cnt,
         c->chunks, c->cstart + nt, c->n_binned[0], m, step, seed, c->ev,
         c->flag, cap, c->el_cnt, c->dc);
     sort_records(c, c->ev, c->rec_tmp, &c->dc->n_events, cap);
-    k_neutral_cands<PT><<<nblk(bound(c, 1)), kT, 0, st>>>(
+    k_neutral_cands<PT><<<(unsigned)((bound(c, 1) + kNCChunk - 1) / kNCChunk), kT, 0, st>>>(
         cur<PT>(c, 1), c->key[1], c->flag, c->nc, cap, c->dc);
     sort_records(c, c->nc, c->rec_tmp, &c->dc->n_ncand, cap);
     k_match<<<nblk(cap), kT, 0, st>>>(c->ev, c->nc, c->ok, c->okp, cap, c->dc);
@@ -2378,11 +2443,6 @@ void bin_species_t(pic_ctx* c, int s) {
 // atomic per workgroup, not one per wave.
 constexpr int kCPer = 16;
 constexpr int kCChunk = kCPer * kT;
-
-__device__ __forceinline__ unsigned lanes_below(unsigned long long mask) {
-  const int lane = lane_id();
-  return lane ? (unsigned)__popcll(mask & (~0ull >> (64 - lane))) : 0u;
-}
 
 __global__ void __launch_bounds__(kT) k_count_dead(
     const uint32_t* __restrict__ key, Counters* dc) {

@@ -258,6 +258,7 @@ struct Counters {
   unsigned long long n_ab;          // cathode-absorbed list length
   unsigned long long n_ncand;       // neutrals in cells with events
   unsigned long long n_tail_cand;   // candidates among unbinned electrons
+  unsigned long long n_el_tail;     // elastic collisions among them
   unsigned long long sorted_n[3];   // counts after the binning pass
   unsigned long long n_dead;        // removed neutrals (compaction)
   unsigned long long n_holes;       // ... of them below the new count
