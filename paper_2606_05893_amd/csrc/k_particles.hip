@@ -458,6 +458,71 @@ __global__ void __launch_bounds__(kT) k_deposit(
   }
 }
 
+// Charge of the state a step leaves, taken in its push: a pushed charged
+// particle adds its quantised CIC weights at the new position, as the
+// deposit pass would from the stored position, into an 11^3 LDS block of
+// the nodes around its tile (x0 - 1 .. x0 + 9 per axis), flushed with one
+// global atomic per non-zero node; a particle outside that block, and the
+// unbinned ones, add with global atomics.  The sums are integers, so their
+// order does not matter.
+constexpr int kDepW = kTile + 3;
+constexpr int kDepN = kDepW * kDepW * kDepW;
+
+__device__ __forceinline__ void dep_global(long long* __restrict__ acc,
+                                           const GridC& g, int ix, int fx,
+                                           int iy, int fy, int iz, int fz,
+                                           long long sign) {
+  const long long wx[2] = {kQ - fx, fx}, wy[2] = {kQ - fy, fy},
+                  wz[2] = {kQ - fz, fz};
+  for (int c = 0; c < 2; ++c)
+    for (int bb = 0; bb < 2; ++bb)
+      for (int a = 0; a < 2; ++a) {
+        const long long node =
+            ((long long)(iz + c) * g.ny + wrap_index(iy + bb, g.ny)) * g.nx +
+            wrap_index(ix + a, g.nx);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&acc[node]),
+                  (unsigned long long)(sign * (wx[a] * wy[bb] * wz[c])));
+      }
+}
+
+__device__ __forceinline__ void dep_tile(unsigned long long* sq,
+                                         long long* __restrict__ acc,
+                                         const GridC& g, int x0, int y0,
+                                         int z0, int ix, int fx, int iy,
+                                         int fy, int iz, int fz,
+                                         long long sign) {
+  const int lx = ix - x0 + 1, ly = iy - y0 + 1, lz = iz - z0 + 1;
+  if (lx < 0 || lx > kDepW - 2 || ly < 0 || ly > kDepW - 2 || lz < 0 ||
+      lz > kDepW - 2) {
+    dep_global(acc, g, ix, fx, iy, fy, iz, fz, sign);
+    return;
+  }
+  const long long wx[2] = {kQ - fx, fx}, wy[2] = {kQ - fy, fy},
+                  wz[2] = {kQ - fz, fz};
+  for (int c = 0; c < 2; ++c)
+    for (int bb = 0; bb < 2; ++bb)
+      for (int a = 0; a < 2; ++a)
+        atomicAdd(&sq[((lz + c) * kDepW + (ly + bb)) * kDepW + (lx + a)],
+                  (unsigned long long)(sign * (wx[a] * wy[bb] * wz[c])));
+}
+
+__device__ __forceinline__ void dep_flush(const unsigned long long* sq,
+                                          long long* __restrict__ acc,
+                                          const GridC& g, int x0, int y0,
+                                          int z0) {
+  for (int q = threadIdx.x; q < kDepN; q += blockDim.x) {
+    const unsigned long long v = sq[q];
+    if (!v) continue;
+    const int a = q % kDepW, bb = (q / kDepW) % kDepW, c = q / (kDepW * kDepW);
+    const int gk = z0 - 1 + c;
+    if (gk < 0 || gk > g.nz) continue;   // (receives no charge)
+    const int gi = wrap_index(x0 - 1 + a, g.nx), gj = wrap_index(y0 - 1 + bb, g.ny);
+    atomicAdd(reinterpret_cast<unsigned long long*>(
+                  &acc[((long long)gk * g.ny + gj) * g.nx + gi]),
+              v);
+  }
+}
+
 // ---- push ---------------------------------------------------------------------
 struct MccC {
   int enabled, ion_model;
@@ -531,7 +596,30 @@ struct PushOut {
   unsigned cell;
   double ke;           // |v|^2 after the kick
   double x, y, z, vx, vy, vz;
+  float oxf, oyf, ozf; // mixed layout: the stored in-cell offsets
 };
+
+// CIC cell and quantised weights of a pushed particle's stored position
+// (FP64: wrapped coordinates; mixed: cell and FP32 offsets), as the
+// deposit computes them from memory.
+__device__ __forceinline__ void cic_stored(const Parts&, const PushOut& o,
+                                           const GridC& g, int& ix, int& fx,
+                                           int& iy, int& fy, int& iz, int& fz) {
+  cic_axis(o.x, g.inv_dx, ix, fx);
+  cic_axis(o.y, g.inv_dx, iy, fy);
+  cic_axis(o.z, g.inv_dx, iz, fz);
+  if (ix >= g.nx) ix -= g.nx;
+  if (iy >= g.ny) iy -= g.ny;
+}
+
+__device__ __forceinline__ void cic_stored(const PartsM&, const PushOut& o,
+                                           const GridC& g, int& ix, int& fx,
+                                           int& iy, int& fy, int& iz, int& fz) {
+  Acc<PartsM>::decode(o.cell, g, ix, iy, iz);
+  fx = (int)floorf(o.oxf * 8192.0f + 0.5f);
+  fy = (int)floorf(o.oyf * 8192.0f + 0.5f);
+  fz = (int)floorf(o.ozf * 8192.0f + 0.5f);
+}
 
 // Drift, boundaries, write-back and (electrons) the null-collision
 // candidate draw U1 < 1 - exp(-N_c c_coll); velocities already kicked.
@@ -645,12 +733,14 @@ struct TileArgs {
   long long ab_cap;
   double *part_e, *part_i;
   unsigned *cnt_e, *cnt_i;   // destination-tile counts for the binning
+  long long* dep;            // charge of the pushed state (int64 units)
 };
 
 __global__ void __launch_bounds__(kT) k_push_tile(
     TileArgs A, const double* __restrict__ E, long long nn, GridC g, MccC m,
     uint32_t step, uint64_t seed, Counters* dc) {
   __shared__ double sx[729], sy[729], sz[729];
+  __shared__ unsigned long long sq[kDepN];
   __shared__ double sk[kT];
   __shared__ unsigned s_cand;
   __shared__ unsigned s_nc[2][27], s_nd[2][27];  // destinations: e, ions
@@ -684,6 +774,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
     }
     sx[q] = vx; sy[q] = vy; sz[q] = vz;
   }
+  for (int q = threadIdx.x; q < kDepN; q += blockDim.x) sq[q] = 0ull;
   if (threadIdx.x == 0) s_cand = 0;
   if (threadIdx.x < 54) (&s_nc[0][0])[threadIdx.x] = 0u;
   __syncthreads();
@@ -716,6 +807,11 @@ __global__ void __launch_bounds__(kT) k_push_tile(
                      step, seed, dc, o, 0ull);
       ke_i = ke_i + o.ke;
       count_dest(o.cell, tx, ty, tz, g, s_nc[1], s_nd[1], A.cnt_i);
+      if (o.cell != kDead) {
+        int dx_, fx_, dy_, fy_, dz_, fz_;
+        cic_stored(Parts(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
+        dep_tile(sq, A.dep, g, x0, y0, z0, dx_, fx_, dy_, fy_, dz_, fz_, 1);
+      }
     }
     sink<2>(A.pi, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
   }
@@ -748,6 +844,11 @@ __global__ void __launch_bounds__(kT) k_push_tile(
                      step, seed, dc, o, A.pe.id[i]);
       ke_e = ke_e + o.ke;
       count_dest(o.cell, tx, ty, tz, g, s_nc[0], s_nd[0], A.cnt_e);
+      if (o.cell != kDead) {
+        int dx_, fx_, dy_, fy_, dz_, fz_;
+        cic_stored(Parts(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
+        dep_tile(sq, A.dep, g, x0, y0, z0, dx_, fx_, dy_, fy_, dz_, fz_, -1);
+      }
       if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = (uint32_t)i;
     }
     sink<0>(A.pe, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
@@ -765,6 +866,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
     const unsigned n = s_nc[sp][d];
     if (n) atomicAdd(&(sp ? A.cnt_i : A.cnt_e)[s_nd[sp][d]], n);
   }
+  dep_flush(sq, A.dep, g, x0, y0, z0);
 }
 
 // Particles not covered by tile ranges (sources and queue appended this
@@ -776,7 +878,7 @@ __global__ void __launch_bounds__(kT) k_push_list(
     double dt, int* __restrict__ ncount, uint32_t* __restrict__ cand, MccC m,
     uint32_t step, uint64_t seed, Rec* __restrict__ ab_rec,
     double* __restrict__ ab_pos, double* __restrict__ ab_vel, long long ab_cap,
-    Counters* dc, double* __restrict__ part) {
+    Counters* dc, double* __restrict__ part, long long* __restrict__ dep) {
   __shared__ double sk[kT];
   const long long n = (long long)dc->n[SP];
   const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -798,6 +900,11 @@ __global__ void __launch_bounds__(kT) k_push_list(
     }
     finish_push<SP>(p, i, x, y, z, vx, vy, vz, dt, g, key, ncount, m, step,
                     seed, dc, o, SP == 0 ? p.id[i] : 0ull);
+    if (SP != 1 && o.cell != kDead) {
+      int dx_, fx_, dy_, fy_, dz_, fz_;
+      cic_stored(Parts(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
+      dep_global(dep, g, dx_, fx_, dy_, fy_, dz_, fz_, SP == 2 ? 1 : -1);
+    }
   }
   sink<SP>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
   if (SP == 0) {
@@ -862,6 +969,7 @@ __device__ __forceinline__ void finish_push_m(PartsM& p, long long i, PushM q,
              (unsigned)jx;
     p.cell[i] = o.cell;
     p.ox[i] = q.ox; p.oy[i] = q.oy; p.oz[i] = q.oz;
+    o.oxf = q.ox; o.oyf = q.oy; o.ozf = q.oz;
     if (SP != 1) {
       p.vx[i] = q.vx; p.vy[i] = q.vy; p.vz[i] = q.vz;
     }
@@ -942,6 +1050,7 @@ struct TileArgsM {
   long long ab_cap;
   double *part_e, *part_i;
   unsigned *cnt_e, *cnt_i;   // destination-tile counts for the binning
+  long long* dep;            // charge of the pushed state (int64 units)
 };
 
 template <int SP>
@@ -1005,6 +1114,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
     TileArgsM A, const float* __restrict__ E, long long nn, GridC g, MccC m,
     uint32_t step, uint64_t seed, Counters* dc) {
   __shared__ float sx[729], sy[729], sz[729];
+  __shared__ unsigned long long sq[kDepN];
   __shared__ double sk[kT];
   __shared__ unsigned s_cand;
   __shared__ unsigned s_nc[2][27], s_nd[2][27];  // destinations: e, ions
@@ -1038,6 +1148,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
     }
     sx[q] = vx; sy[q] = vy; sz[q] = vz;
   }
+  for (int q = threadIdx.x; q < kDepN; q += blockDim.x) sq[q] = 0ull;
   if (threadIdx.x == 0) s_cand = 0;
   if (threadIdx.x < 54) (&s_nc[0][0])[threadIdx.x] = 0u;
   __syncthreads();
@@ -1052,6 +1163,11 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
                     A.keyi, A.ncount, m, step, seed, dc, o);
       ke_i = ke_i + o.ke;
       count_dest(o.cell, tx, ty, tz, g, s_nc[1], s_nd[1], A.cnt_i);
+      if (o.cell != kDead) {
+        int dx_, fx_, dy_, fy_, dz_, fz_;
+        cic_stored(PartsM(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
+        dep_tile(sq, A.dep, g, x0, y0, z0, dx_, fx_, dy_, fy_, dz_, fz_, 1);
+      }
     }
     sink_m(A.pi, i, 2, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
   }
@@ -1066,6 +1182,11 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
                     A.keye, A.ncount, m, step, seed, dc, o);
       ke_e = ke_e + o.ke;
       count_dest(o.cell, tx, ty, tz, g, s_nc[0], s_nd[0], A.cnt_e);
+      if (o.cell != kDead) {
+        int dx_, fx_, dy_, fy_, dz_, fz_;
+        cic_stored(PartsM(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
+        dep_tile(sq, A.dep, g, x0, y0, z0, dx_, fx_, dy_, fy_, dz_, fz_, -1);
+      }
       if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = (uint32_t)i;
     }
     sink_m(A.pe, i, 0, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
@@ -1083,6 +1204,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
     const unsigned n = s_nc[sp][d];
     if (n) atomicAdd(&(sp ? A.cnt_i : A.cnt_e)[s_nd[sp][d]], n);
   }
+  dep_flush(sq, A.dep, g, x0, y0, z0);
 }
 
 template <int SP>
@@ -1092,7 +1214,7 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
     int* __restrict__ ncount, uint32_t* __restrict__ cand, MccC m,
     uint32_t step, uint64_t seed, Rec* __restrict__ ab_rec,
     double* __restrict__ ab_pos, double* __restrict__ ab_vel, long long ab_cap,
-    Counters* dc, double* __restrict__ part) {
+    Counters* dc, double* __restrict__ part, long long* __restrict__ dep) {
   __shared__ double sk[kT];
   const long long n = (long long)dc->n[SP];
   const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -1102,9 +1224,15 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
   o.anode = false;
   o.cand = false;
   o.ke = 0.0;
-  if (live)
+  if (live) {
     push_one_m<SP>(p, i, nullptr, nullptr, nullptr, 0, 0, 0, E, nn, g, qm,
                    dtdx, key, ncount, m, step, seed, dc, o);
+    if (SP != 1 && o.cell != kDead) {
+      int dx_, fx_, dy_, fy_, dz_, fz_;
+      cic_stored(PartsM(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
+      dep_global(dep, g, dx_, fx_, dy_, fy_, dz_, fz_, SP == 2 ? 1 : -1);
+    }
+  }
   sink_m(p, i, SP, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
   if (SP == 0) {
     const unsigned long long cs = wave_append(o.cand, &dc->n_tail_cand);
@@ -1595,7 +1723,8 @@ __global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
                          uint32_t* __restrict__ kn, uint32_t* __restrict__ ki,
                          const Rec* __restrict__ ok, const uint2* __restrict__ okp,
                          MccC m, uint32_t step, uint64_t seed, long long cap_e,
-                         long long cap_i, int* __restrict__ ncount, Counters* dc) {
+                         long long cap_i, int* __restrict__ ncount,
+                         long long* __restrict__ dep, GridC g, Counters* dc) {
   const long long nok = (long long)dc->n_ok;
   const long long ne0 = (long long)dc->n[0], ni0 = (long long)dc->n[2];
   const unsigned long long id0 = dc->next_id;
@@ -1629,6 +1758,12 @@ __global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
       ke[de] = ke[ie];
       Acc<PT>::copy(pn, in, pi, di);
       ki[di] = kn[in];
+      // The pair's charge joins that of the pushed state.
+      int ix, fx, iy, fy, iz, fz;
+      Acc<PT>::cic(pe, de, g, ix, fx, iy, fy, iz, fz);
+      dep_global(dep, g, ix, fx, iy, fy, iz, fz, -1);
+      Acc<PT>::cic(pi, di, g, ix, fx, iy, fy, iz, fz);
+      dep_global(dep, g, ix, fx, iy, fy, iz, fz, 1);
     } else {
       atomicOr(&dc->err, kErrCapacity);
     }
@@ -2249,6 +2384,7 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.part_i = part_i;
   A.cnt_e = c->tcnt[0];
   A.cnt_i = c->tcnt[1];
+  A.dep = c->acc_next;
   k_push_tile<<<(unsigned)c->nch_bound, kT, 0, st>>>(A, c->E, nn, c->g, m,
                                                          step, seed, c->dc);
   tmark(c, PIC_PH_PUSH_ELECTRON, false);
@@ -2258,13 +2394,13 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
   k_push_list<2><<<nbi, kT, 0, st>>>(
       cur<Parts>(c, 2), c->n_binned[2], c->key[2], c->E, nn, c->g,
       qm_dt(2, dt), dt, c->ncount, c->cand, m, step, seed, c->ab_rec,
-      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l);
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l, c->acc_next);
   const long long tail_e = std::max(0ll, bound(c, 0) - c->n_binned[0]);
   nbe = nblk(tail_e > 0 ? tail_e : 1);
   k_push_list<0><<<nbe, kT, 0, st>>>(
       cur<Parts>(c, 0), c->n_binned[0], c->key[0], c->E, nn, c->g,
       qm_dt(0, dt), dt, c->ncount, c->cand, m, step, seed, c->ab_rec,
-      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi);
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi, c->acc_next);
   tmark(c, PIC_PH_PUSH_ION, false);
 }
 
@@ -2303,6 +2439,7 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.part_i = part_i;
   A.cnt_e = c->tcnt[0];
   A.cnt_i = c->tcnt[1];
+  A.dep = c->acc_next;
   k_push_tile_m<<<(unsigned)c->nch_bound, kT, 0, st>>>(A, E, nn, c->g, m,
                                                            step, seed, c->dc);
   tmark(c, PIC_PH_PUSH_ELECTRON, false);
@@ -2312,13 +2449,13 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
   k_push_list_m<2><<<nbi, kT, 0, st>>>(
       cur<PartsM>(c, 2), c->n_binned[2], c->key[2], E, nn, c->g,
       (float)qm_dt(2, dt), dtdx, c->ncount, c->cand, m, step, seed, c->ab_rec,
-      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l);
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l, c->acc_next);
   const long long tail_e = std::max(0ll, bound(c, 0) - c->n_binned[0]);
   nbe = nblk(tail_e > 0 ? tail_e : 1);
   k_push_list_m<0><<<nbe, kT, 0, st>>>(
       cur<PartsM>(c, 0), c->n_binned[0], c->key[0], E, nn, c->g,
       (float)qm_dt(0, dt), dtdx, c->ncount, c->cand, m, step, seed, c->ab_rec,
-      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi);
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi, c->acc_next);
   tmark(c, PIC_PH_PUSH_ION, false);
 }
 
@@ -2337,6 +2474,9 @@ void push_collide_t(pic_ctx* c, double dt) {
   double* part_i = c->partials + c->nch_cap;
   double* part_l = c->partials + 2 * c->nch_cap;
   long long nbi = 1, nbe = 1;
+  // The pushes and the ionisations add the charge of the state this step
+  // leaves; the next deposit takes it instead of a pass of its own.
+  hipMemsetAsync(c->acc_next, 0, c->nnodes * sizeof(long long), st);
   if (c->mixed)
     push_mixed(c, dt, m, part_e, part_i, part_l, nbi, nbe);
   else
@@ -2367,7 +2507,8 @@ void push_collide_t(pic_ctx* c, double dt) {
     k_ionise<PT><<<64, kT, 0, st>>>(cur<PT>(c, 0), cur<PT>(c, 1), cur<PT>(c, 2),
                                     c->key[0], c->key[1], c->key[2], c->ok,
                                     c->okp, m, step, seed, c->cfg.capacity[0],
-                                    c->cfg.capacity[2], c->ncount, c->dc);
+                                    c->cfg.capacity[2], c->ncount, c->acc_next,
+                                    c->g, c->dc);
     k_ionise_commit<<<1, 1024, 0, st>>>(c->dc, c->ev, c->flag, cap,
                                         c->cfg.capacity[0], c->cfg.capacity[2],
                                         c->el_cnt, c->cand_cnt,
@@ -2552,11 +2693,17 @@ void compact_neutrals_t(pic_ctx* c) {
 
 void parts_deposit(pic_ctx* c) {
   tmark(c, PIC_PH_DEPOSIT, true);
-  hipMemsetAsync(c->acc, 0, c->nnodes * sizeof(long long), c->stream);
-  if (c->mixed)
-    deposit_t<PartsM>(c);
-  else
-    deposit_t<Parts>(c);
+  if (c->acc_next_valid) {
+    // The last advance pushed the current particles and added their charge.
+    std::swap(c->acc, c->acc_next);
+    c->acc_next_valid = false;
+  } else {
+    hipMemsetAsync(c->acc, 0, c->nnodes * sizeof(long long), c->stream);
+    if (c->mixed)
+      deposit_t<PartsM>(c);
+    else
+      deposit_t<Parts>(c);
+  }
   tmark(c, PIC_PH_DEPOSIT, false);
 }
 

@@ -134,6 +134,7 @@ size_t carve(pic_ctx* c, char* base) {
   const long long nsb = (c->ntiles + 1 + 1023) / 1024;
   c->scan_block = cv.take<uint32_t>(2 * nsb + 2);
   c->acc = cv.take<long long>(c->nnodes);
+  c->acc_next = cv.take<long long>(c->nnodes);
   c->E = reinterpret_cast<double*>(
       cv.take<char>(3 * c->nnodes * (long long)(mixed ? 4 : 8)));
   for (int l = 0; l < c->nlev; ++l) {
@@ -378,6 +379,7 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->nch_bound = 1;
   c->tcounted = false;
   c->ncount_valid = false;
+  c->acc_next_valid = false;
   c->n_start1 = 0;
   c->n_stirred = 0;
   c->neutrals_binned = false;
@@ -618,7 +620,9 @@ pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
   parts_sources_host(c);
   parts_push_neutral(c, dt);
   const pic_status st = advance_finish(c, dt, add, out, diag);
-  // After a failed step the neutrals are counted afresh.
+  // After a failed step the neutrals are counted and the charge deposited
+  // afresh.
+  c->acc_next_valid = st == PIC_OK;
   if (st != PIC_OK) c->ncount_valid = false;
   return st;
 }
@@ -702,6 +706,7 @@ pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
   if (n > 0 && (!pos || !vel || !ids)) return PIC_ERR_ARG;
   parts_load(c, s, n, pos, vel, ids);
   if (s == 1) c->ncount_valid = false;
+  c->acc_next_valid = false;
   // The new population has no tile ranges yet: all of it bins as a tail.
   hipMemsetAsync(c->tsb[s][c->tcur[s]], 0, (c->ntiles + 1) * sizeof(uint32_t),
                  c->stream);
@@ -837,6 +842,7 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
   if (st == PIC_OK) st = pic_set_sources(c, &h.src);
   if (st != PIC_OK) return st;
   c->ncount_valid = false;  // the neutrals are replaced
+  c->acc_next_valid = false;
   for (int s = 0; s < 3; ++s) c->n[s] = h.n[s];
   const char* in = static_cast<const char*>(host);
   size_t off = sizeof(h);

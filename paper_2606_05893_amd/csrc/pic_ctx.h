@@ -95,6 +95,8 @@ struct pic_ctx {
   // Collisions and ionisation matching.
   int* ncount;               // neutrals per cell
   bool ncount_valid;         // ncount counts the first n_start1 neutrals
+  long long* acc_next;       // charge of the state the last advance left
+  bool acc_next_valid;       // ... and it is the current particles'
   long long n_start1;        // neutrals at the start of the step's sources
   uint8_t* flag;             // cells holding ionisation events
   uint32_t* cand;            // electron indices of null-collision candidates
