@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # when measured; set to None when they change.
 MEASURED_TRAFFIC = {
     ("c2", "fp64", "k_smooth2"): 243.2e6,
-    ("c2", "fp64", "k_push_tile"): 2394.5e6,
+    ("c2", "fp64", "k_push_tile"): 2545.2e6,
 }
 
 
@@ -299,12 +299,13 @@ def main():
     # Charged-particle push (k_push_tile): per electron x, y, z, vx, vy, vz
     # read and written (96 B FP64; 56 B mixed as cell + FP32 offsets and
     # velocities), id read (8 B), cell key written (4 B); per ion the same
-    # without the id; per node the three E components read once; per cell
-    # the neutral count read once (4 B).
+    # without the id; per node the three E components read once (24 B FP64,
+    # 12 B mixed) and the int64 charge of the pushed state read and written
+    # once (16 B); per cell the neutral count read once (4 B).
     ms_push, n_push = ph["push_electron"]
     per_e = (56 + 8 + 4) if mixed else (96 + 8 + 4)
     per_i = (56 + 4) if mixed else (96 + 4)
-    per_node = 12 if mixed else 24
+    per_node = (12 if mixed else 24) + 16
     alg_bytes = (head["_electrons_i"] * per_e + head["_ions_i"] * per_i
                  + nodes * per_node + cells * 4)
     t_push = ms_push / max(n_push, 1) * 1e-3

@@ -1758,11 +1758,12 @@ __global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
       ke[de] = ke[ie];
       Acc<PT>::copy(pn, in, pi, di);
       ki[di] = kn[in];
-      // The pair's charge joins that of the pushed state.
+      // The pair's charge joins that of the pushed state (the secondary
+      // sits at the primary's position, the ion at the neutral's).
       int ix, fx, iy, fy, iz, fz;
-      Acc<PT>::cic(pe, de, g, ix, fx, iy, fy, iz, fz);
+      Acc<PT>::cic(pe, ie, g, ix, fx, iy, fy, iz, fz);
       dep_global(dep, g, ix, fx, iy, fy, iz, fz, -1);
-      Acc<PT>::cic(pi, di, g, ix, fx, iy, fy, iz, fz);
+      Acc<PT>::cic(pn, in, g, ix, fx, iy, fy, iz, fz);
       dep_global(dep, g, ix, fx, iy, fy, iz, fz, 1);
     } else {
       atomicOr(&dc->err, kErrCapacity);
