@@ -197,6 +197,9 @@ __global__ void k_residual(const double* __restrict__ u,
   if (dc->done) return;
   double s2 = 0.0;
   const long long nu = L.nxy * (L.k1 - L.k0 + 1);
+  // Unrolled so that several nodes' loads are in flight per thread; the
+  // partial sum keeps the loop's order.
+#pragma unroll 4
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nu;
        t += (long long)gridDim.x * blockDim.x) {
     const unsigned tt = (unsigned)t;
@@ -580,32 +583,51 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
   // clamped and never read.  The fine level is at least 16 nodes wide, so
   // one wrap suffices.
   const int nxy = (int)F.nxy;
-#pragma unroll 4
-  for (int q = threadIdx.x; q < kUZ * kUXY; q += blockDim.x) {
+  // Every global load of the block is issued before the first use (clamped
+  // to a valid node where the slot is unused), so they are all in flight
+  // together: the u block, then the f values of this thread's residuals.
+  constexpr int kSPer = (kUZ * kUXY + 255) / 256;
+  T uv[kSPer];
+#pragma unroll
+  for (int m = 0; m < kSPer; ++m) {
+    int q = threadIdx.x + 256 * m;
+    q = q < kUZ * kUXY ? q : kUZ * kUXY - 1;
     const int sx = q % kUX, sy = (q / kUX) % kUY, sz = q / kUXY;
     const int i = wrap_index(2 * cx0 - 2 + sx, F.nx);
     const int j = wrap_index(2 * cy0 - 2 + sy, F.ny);
     int k = 2 * cz0 - 2 + sz;
     k = k < 0 ? 0 : (k > F.nz ? F.nz : k);
-    su[q] = uf[k * nxy + j * F.nx + i];
+    uv[m] = uf[k * nxy + j * F.nx + i];
+  }
+  T fv[kRPer];
+  int rk[kRPer], rc[kRPer];
+#pragma unroll
+  for (int m = 0; m < kRPer; ++m) {
+    int q = threadIdx.x + 256 * m;
+    q = q < kFZ * kFY * kFX ? q : kFZ * kFY * kFX - 1;
+    const int lx = q % kFX, ly = (q / kFX) % kFY, lz = q / (kFX * kFY);
+    int k = 2 * cz0 - 1 + lz;
+    if (k < 0) k = 1;                    // Neumann mirror
+    if (k > F.nz) k = F.nz - 1;
+    const int i = wrap_index(2 * cx0 - 1 + lx, F.nx);
+    const int j = wrap_index(2 * cy0 - 1 + ly, F.ny);
+    rk[m] = k;
+    // Plane k sits at sz = k - (2cz0 - 2), in 1..9, so k +- 1 are staged.
+    rc[m] = ((k - 2 * cz0 + 2) * kUY + ly + 1) * kUX + lx + 1;
+    fv[m] = ff[k * nxy + j * F.nx + i];
+  }
+#pragma unroll
+  for (int m = 0; m < kSPer; ++m) {
+    const int q = threadIdx.x + 256 * m;
+    if (q < kUZ * kUXY) su[q] = uv[m];
   }
   __syncthreads();
   T rv[kRPer];
 #pragma unroll
   for (int m = 0; m < kRPer; ++m) {
-    const int q = threadIdx.x + 256 * m;
-    rv[m] = T(0);
-    if (q >= kFZ * kFY * kFX) continue;
-    const int lx = q % kFX, ly = (q / kFX) % kFY, lz = q / (kFX * kFY);
-    int k = 2 * cz0 - 1 + lz;
-    if (k < 0) k = 1;                    // Neumann mirror
-    if (k > F.nz) k = F.nz - 1;
+    const int k = rk[m], c = rc[m];
     T res = T(0);
-    if (k >= F.k0 && k <= F.k1) {
-      const int i = wrap_index(2 * cx0 - 1 + lx, F.nx);
-      const int j = wrap_index(2 * cy0 - 1 + ly, F.ny);
-      // Plane k sits at sz = k - (2cz0 - 2), in 1..9, so k +- 1 are staged.
-      const int c = ((k - 2 * cz0 + 2) * kUY + ly + 1) * kUX + lx + 1;
+    if (threadIdx.x + 256 * m < kFZ * kFY * kFX && k >= F.k0 && k <= F.k1) {
       T sn = su[c - 1] + su[c + 1];
       sn = sn + (su[c - kUX] + su[c + kUX]);
       T zs;
@@ -615,7 +637,7 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
         zs = T(2) * su[c - kUXY];
       else
         zs = su[c - kUXY] + su[c + kUXY];
-      res = ff[k * nxy + j * F.nx + i] - (T(6) * su[c] - (sn + zs)) * inv_h2;
+      res = fv[m] - (T(6) * su[c] - (sn + zs)) * inv_h2;
     }
     rv[m] = res;
   }

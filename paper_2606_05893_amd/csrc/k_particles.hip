@@ -1733,6 +1733,11 @@ __global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
     const uint2 pr = okp[ok[r].val];
     const uint32_t ie = pr.x, in = pr.y;
     const unsigned long long pid = ok[r].lo;
+    // Charge of the new pair (the secondary at the primary's position, the
+    // ion at the neutral's), taken before this event's stores.
+    int cex, cfx, cey, cfy, cez, cfz, cix, cgx, ciy, cgy, ciz, cgz;
+    Acc<PT>::cic(pe, ie, g, cex, cfx, cey, cfy, cez, cfz);
+    Acc<PT>::cic(pn, in, g, cix, cgx, ciy, cgy, ciz, cgz);
     double u3, u4, u5, u6, u7, u8;
     uniform2(pid, step, kTagMcc1, seed, u3, u4);
     uniform2(pid, step, kTagMcc2, seed, u5, u6);
@@ -1758,13 +1763,8 @@ __global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
       ke[de] = ke[ie];
       Acc<PT>::copy(pn, in, pi, di);
       ki[di] = kn[in];
-      // The pair's charge joins that of the pushed state (the secondary
-      // sits at the primary's position, the ion at the neutral's).
-      int ix, fx, iy, fy, iz, fz;
-      Acc<PT>::cic(pe, ie, g, ix, fx, iy, fy, iz, fz);
-      dep_global(dep, g, ix, fx, iy, fy, iz, fz, -1);
-      Acc<PT>::cic(pn, in, g, ix, fx, iy, fy, iz, fz);
-      dep_global(dep, g, ix, fx, iy, fy, iz, fz, 1);
+      dep_global(dep, g, cex, cfx, cey, cfy, cez, cfz, -1);
+      dep_global(dep, g, cix, cgx, ciy, cgy, ciz, cgz, 1);
     } else {
       atomicOr(&dc->err, kErrCapacity);
     }
