@@ -597,6 +597,7 @@ struct PushOut {
   double ke;           // |v|^2 after the kick
   double x, y, z, vx, vy, vz;
   float oxf, oyf, ozf; // mixed layout: the stored in-cell offsets
+  unsigned long long id;  // electron candidates: the id of the draw
 };
 
 // CIC cell and quantised weights of a pushed particle's stored position
@@ -671,9 +672,19 @@ __device__ __forceinline__ void finish_push(Parts& p, long long i, double x,
       uniform2(idv, step, kTagMcc0, seed, u1, u2);
       if (fabs(u1 - pstar) < 1e-6) atomicAdd(&dc->n_near, 1ull);
       o.cand = u1 < pstar;
+      o.id = idv;
     }
   }
   o.x = x; o.y = y; o.z = z; o.vx = vx; o.vy = vy; o.vz = vz;
+}
+
+__device__ __forceinline__ CandRec cand_rec(const PushOut& o, long long i) {
+  CandRec r;
+  r.vx = o.vx; r.vy = o.vy; r.vz = o.vz;
+  r.id = o.id;
+  r.i = (unsigned)i;
+  r.pad = 0u;
+  return r;
 }
 
 // Cathode sink record (wave-aggregated slot).  All lanes must call it.
@@ -726,7 +737,7 @@ struct TileArgs {
   uint32_t *keye, *keyi;
   double qm_e, qm_i, dt;
   int* ncount;
-  uint32_t* cand;
+  CandRec* cand;
   uint32_t* cand_cnt;
   Rec* ab_rec;
   double *ab_pos, *ab_vel;
@@ -849,7 +860,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
         cic_stored(Parts(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
         dep_tile(sq, A.dep, g, x0, y0, z0, dx_, fx_, dy_, fy_, dz_, fz_, -1);
       }
-      if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = (uint32_t)i;
+      if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = cand_rec(o, i);
     }
     sink<0>(A.pe, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
   }
@@ -875,7 +886,7 @@ template <int SP>
 __global__ void __launch_bounds__(kT) k_push_list(
     Parts p, long long first, uint32_t* __restrict__ key,
     const double* __restrict__ E, long long nn, GridC g, double qm_dt,
-    double dt, int* __restrict__ ncount, uint32_t* __restrict__ cand, MccC m,
+    double dt, int* __restrict__ ncount, CandRec* __restrict__ cand, MccC m,
     uint32_t step, uint64_t seed, Rec* __restrict__ ab_rec,
     double* __restrict__ ab_pos, double* __restrict__ ab_vel, long long ab_cap,
     Counters* dc, double* __restrict__ part, long long* __restrict__ dep) {
@@ -909,7 +920,7 @@ __global__ void __launch_bounds__(kT) k_push_list(
   sink<SP>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
   if (SP == 0) {
     const unsigned long long cs = wave_append(o.cand, &dc->n_tail_cand);
-    if (o.cand) cand[first + cs] = (uint32_t)i;
+    if (o.cand) cand[first + cs] = cand_rec(o, i);
   }
   const double s = block_sum(live ? o.ke : 0.0, sk);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -980,7 +991,9 @@ __device__ __forceinline__ void finish_push_m(PartsM& p, long long i, PushM q,
     if (nc > 0) {
       const double pstar = 1.0 - exp(-((double)nc * m.c_coll));
       double u1, u2;
-      uniform2(p.id[i], step, kTagMcc0, seed, u1, u2);
+      const unsigned long long idv = p.id[i];
+      uniform2(idv, step, kTagMcc0, seed, u1, u2);
+      o.id = idv;
       if (fabs(u1 - pstar) < 1e-6) atomicAdd(&dc->n_near, 1ull);
       o.cand = u1 < pstar;
     }
@@ -1043,7 +1056,7 @@ struct TileArgsM {
   uint32_t *keye, *keyi;
   float qm_e, qm_i, dtdx;
   int* ncount;
-  uint32_t* cand;
+  CandRec* cand;
   uint32_t* cand_cnt;
   Rec* ab_rec;
   double *ab_pos, *ab_vel;
@@ -1187,7 +1200,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
         cic_stored(PartsM(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
         dep_tile(sq, A.dep, g, x0, y0, z0, dx_, fx_, dy_, fy_, dz_, fz_, -1);
       }
-      if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = (uint32_t)i;
+      if (o.cand) A.cand[be + atomicAdd(&s_cand, 1u)] = cand_rec(o, i);
     }
     sink_m(A.pe, i, 0, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
   }
@@ -1211,7 +1224,7 @@ template <int SP>
 __global__ void __launch_bounds__(kT) k_push_list_m(
     PartsM p, long long first, uint32_t* __restrict__ key,
     const float* __restrict__ E, long long nn, GridC g, float qm, float dtdx,
-    int* __restrict__ ncount, uint32_t* __restrict__ cand, MccC m,
+    int* __restrict__ ncount, CandRec* __restrict__ cand, MccC m,
     uint32_t step, uint64_t seed, Rec* __restrict__ ab_rec,
     double* __restrict__ ab_pos, double* __restrict__ ab_vel, long long ab_cap,
     Counters* dc, double* __restrict__ part, long long* __restrict__ dep) {
@@ -1236,7 +1249,7 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
   sink_m(p, i, SP, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
   if (SP == 0) {
     const unsigned long long cs = wave_append(o.cand, &dc->n_tail_cand);
-    if (o.cand) cand[first + cs] = (uint32_t)i;
+    if (o.cand) cand[first + cs] = cand_rec(o, i);
   }
   const double s = block_sum(live ? o.ke : 0.0, sk);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -1434,45 +1447,73 @@ __device__ __forceinline__ double sigma_ion(const MccC& m, double E_eV) {
 // Null-collision candidates: second draw U2 against the cumulative process
 // probabilities (ionisation, then elastic).  Elastic scattering is applied
 // at once; ionisation events are recorded as (cell, electron id) for
-// matching.  One wave per chunk of binned electrons (its candidates sit in
-// the chunk's own segment of the candidate list), then waves of kMccPiece
-// candidates over the unbinned electrons' ones.
+// matching.  A wave takes kMccChunks consecutive chunks of binned electrons
+// and walks their candidates (each chunk's sit in its own segment of the
+// candidate list) as one list; then waves of kMccPiece candidates cover the
+// unbinned electrons' ones.
 constexpr int kMccPiece = 512;
+constexpr int kMccChunks = 8;
 
 template <class PT>
 __global__ void __launch_bounds__(kT) k_mcc(
-    PT p, const uint32_t* __restrict__ key, const uint32_t* __restrict__ cand,
+    PT p, const uint32_t* __restrict__ key, const CandRec* __restrict__ cand,
     const uint32_t* __restrict__ tse, const uint32_t* __restrict__ cand_cnt,
     const uint2* __restrict__ chunks, const unsigned* __restrict__ nchunks,
     long long tail_first, MccC m, uint32_t step,
-    uint64_t seed, Rec* __restrict__ ev, uint8_t* __restrict__ flag,
+    uint64_t seed, Rec* __restrict__ ev, uint32_t* __restrict__ flag,
     long long ev_cap, uint32_t* __restrict__ el_cnt, Counters* dc) {
   const long long nch = *nchunks;
-  const long long t = blockIdx.x * (long long)(kT / 64) + threadIdx.x / 64;
+  const long long ngrp = (nch + kMccChunks - 1) / kMccChunks;
+  const long long w = blockIdx.x * (long long)(kT / 64) + threadIdx.x / 64;
+  // Binned: the candidate segments of chunks t0 .. t0 + kMccChunks - 1
+  // (segment k starts at sb[k] and holds pre[k + 1] - pre[k] candidates).
+  // Unbinned: one piece of the tail's candidate list.
+  long long t0 = 0, sb[kMccChunks];
+  unsigned pre[kMccChunks + 1];
   long long b, e;
-  if (t < nch) {
-    unsigned pb, pe;
-    piece(tse, chunks[t].x, chunks[t].y, pb, pe);
-    b = pb;
-    e = b + cand_cnt[t];
+  const bool binned = w < ngrp;
+  pre[0] = 0;
+  if (binned) {
+    t0 = w * kMccChunks;
+#pragma unroll
+    for (int k = 0; k < kMccChunks; ++k) {
+      const long long t = t0 + k;
+      unsigned c = 0, pb = 0, pe = 0;
+      if (t < nch) {
+        piece(tse, chunks[t].x, chunks[t].y, pb, pe);
+        c = cand_cnt[t];
+      }
+      sb[k] = pb;
+      pre[k + 1] = pre[k] + c;
+    }
+    b = 0;
+    e = pre[kMccChunks];
   } else {
     const long long te = tail_first + (long long)dc->n_tail_cand;
-    b = tail_first + (t - nch) * kMccPiece;
+    b = tail_first + (w - ngrp) * kMccPiece;
     e = b + kMccPiece < te ? b + kMccPiece : te;
     if (b >= e) return;  // whole wave
   }
   const int lane = lane_id();
   unsigned n_el = 0;  // wave-uniform
   for (long long base = b; base < e; base += 64) {
-    const long long q = base + lane;
+    long long q = base + lane;
     bool event = false, elastic = false;
     uint32_t i = 0;
     unsigned long long id = 0;
     if (q < e) {
-      i = cand[q];
-      id = p.id[i];
-      double vx, vy, vz;
-      Acc<PT>::vel(p, i, vx, vy, vz);
+      if (binned) {
+        // Combined index -> (chunk segment, offset).
+        long long at = sb[0] + q;
+#pragma unroll
+        for (int k = 1; k < kMccChunks; ++k)
+          if ((unsigned)q >= pre[k]) at = sb[k] + (q - pre[k]);
+        q = at;
+      }
+      const CandRec cr = cand[q];
+      i = cr.i;
+      id = cr.id;
+      const double vx = cr.vx, vy = cr.vy, vz = cr.vz;
       double u1, u2;
       uniform2(id, step, kTagMcc0, seed, u1, u2);
       const double v2 = (vx * vx + vy * vy) + vz * vz;
@@ -1506,17 +1547,20 @@ __global__ void __launch_bounds__(kT) k_mcc(
         Rec r;
         r.hi = cell; r.lo = id; r.val = i;
         ev[s] = r;
-        flag[cell] = 1;
+        atomicOr(&flag[cell >> 5], 1u << (cell & 31u));
       } else {
         atomicOr(&dc->err, kErrEvents);
       }
     }
   }
   if (lane == 0) {
-    if (t < nch)
-      el_cnt[t] = n_el;
-    else if (n_el)
+    if (binned) {
+      // The group's count in its first chunk's slot (only the sum is used).
+      for (int k = 0; k < kMccChunks; ++k)
+        if (t0 + k < nch) el_cnt[t0 + k] = k ? 0u : n_el;
+    } else if (n_el) {
       atomicAdd(&dc->n_el_tail, (unsigned long long)n_el);
+    }
   }
 }
 
@@ -1627,7 +1671,7 @@ constexpr int kNCChunk = kNCPer * kT;
 
 template <class PT>
 __global__ void __launch_bounds__(kT) k_neutral_cands(
-    PT p, const uint32_t* __restrict__ key, const uint8_t* __restrict__ flag,
+    PT p, const uint32_t* __restrict__ key, const uint32_t* __restrict__ flag,
     Rec* __restrict__ nc, long long cap, Counters* dc) {
   __shared__ unsigned sw[kT / 64];
   __shared__ unsigned long long sbase;
@@ -1645,7 +1689,7 @@ __global__ void __launch_bounds__(kT) k_neutral_cands(
   }
 #pragma unroll
   for (int r = 0; r < kNCPer; ++r) {
-    const bool hit = cell[r] != kDead && flag[cell[r]];
+    const bool hit = cell[r] != kDead && ((flag[cell[r] >> 5] >> (cell[r] & 31u)) & 1u);
     mk[r] = __ballot(hit);
     cnt += (unsigned)__popcll(mk[r]);
   }
@@ -1719,7 +1763,7 @@ __global__ void k_match(const Rec* __restrict__ ev, const Rec* __restrict__ nc,
 // above threshold shared uniformly, both electrons isotropic; the neutral
 // becomes the Cu+ ion (same position, velocity, id).
 template <class PT>
-__global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
+__global__ void __launch_bounds__(kT) k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
                          uint32_t* __restrict__ kn, uint32_t* __restrict__ ki,
                          const Rec* __restrict__ ok, const uint2* __restrict__ okp,
                          MccC m, uint32_t step, uint64_t seed, long long cap_e,
@@ -1777,7 +1821,7 @@ __global__ void k_ionise(PT pe, PT pn, PT pi, uint32_t* __restrict__ ke,
 // Clears the event-cell flags, adds the matched ionisations to the counts
 // and sums the per-tile elastic counts.
 __global__ void k_ionise_commit(Counters* dc, const Rec* __restrict__ ev,
-                                uint8_t* __restrict__ flag, long long cap,
+                                uint32_t* __restrict__ flag, long long cap,
                                 long long cap_e, long long cap_i,
                                 const uint32_t* __restrict__ el_cnt,
                                 const uint32_t* __restrict__ cand_cnt,
@@ -1786,7 +1830,7 @@ __global__ void k_ionise_commit(Counters* dc, const Rec* __restrict__ ev,
   __shared__ unsigned long long s[1024], s2[1024];
   long long ne = (long long)dc->n_events;
   if (ne > cap) ne = cap;
-  for (long long e = threadIdx.x; e < ne; e += blockDim.x) flag[ev[e].hi] = 0;
+  for (long long e = threadIdx.x; e < ne; e += blockDim.x) flag[ev[e].hi >> 5] = 0u;
   unsigned long long a = 0, b = 0;
   for (long long q = threadIdx.x; q < ntiles; q += blockDim.x) a += el_cnt[q];
   for (long long q = threadIdx.x; q < ntiles; q += blockDim.x) b += cand_cnt[q];
@@ -2494,7 +2538,8 @@ void push_collide_t(pic_ctx* c, double dt) {
     // Waves: one per chunk, then the unbinned electrons' candidates (at
     // most one per electron appended this step) in pieces.
     const long long tail = std::max(0ll, bound(c, 0) - c->n_binned[0]);
-    const long long waves = nch + std::max(1ll, (tail + kMccPiece - 1) / kMccPiece);
+    const long long waves = (nch + kMccChunks - 1) / kMccChunks +
+                            std::max(1ll, (tail + kMccPiece - 1) / kMccPiece);
     k_mcc<PT><<<(unsigned)((waves + kT / 64 - 1) / (kT / 64)), kT, 0, st>>>(
         cur<PT>(c, 0), c->key[0], c->cand, ts_cur(c, 0), c->cand_cnt,
         c->chunks, c->cstart + nt, c->n_binned[0], m, step, seed, c->ev,

@@ -162,8 +162,8 @@ size_t carve(pic_ctx* c, char* base) {
   c->part_n = cv.take<double>(neutral_push_blocks(f.capacity[1]));
   c->qpartials = cv.take<long long>(1024);
   c->ncount = cv.take<int>(c->ncells);
-  c->flag = cv.take<uint8_t>(c->ncells);
-  c->cand = cv.take<uint32_t>(f.capacity[0]);
+  c->flag = cv.take<uint32_t>((c->ncells + 31) / 32);
+  c->cand = cv.take<CandRec>(f.capacity[0]);
   c->cand_cnt = cv.take<uint32_t>(c->nch_cap + 1);
   c->el_cnt = cv.take<uint32_t>(c->nch_cap + 1);
   c->chunks = cv.take<uint2>(c->nch_cap);

@@ -98,8 +98,8 @@ struct pic_ctx {
   long long* acc_next;       // charge of the state the last advance left
   bool acc_next_valid;       // ... and it is the current particles'
   long long n_start1;        // neutrals at the start of the step's sources
-  uint8_t* flag;             // cells holding ionisation events
-  uint32_t* cand;            // electron indices of null-collision candidates
+  uint32_t* flag;            // cells holding ionisation events (one bit each)
+  pic::CandRec* cand;        // null-collision candidates
   uint32_t* cand_cnt;        // candidates per tile
   uint32_t* el_cnt;          // elastic collisions per tile (+ tail)
   pic::Rec *ev, *nc, *ok;    // events, neutral candidates, matched events

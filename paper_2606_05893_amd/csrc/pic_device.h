@@ -293,6 +293,15 @@ struct Rec {
   unsigned int hi, val;
 };
 
+// A null-collision candidate as the push leaves it: the electron's index,
+// id and kicked velocity, so the collision pass reads one contiguous record
+// instead of gathering from the particle arrays.
+struct CandRec {
+  double vx, vy, vz;
+  unsigned long long id;
+  unsigned int i, pad;
+};
+
 __device__ __forceinline__ bool rec_less(const Rec& a, const Rec& b) {
   return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
 }
