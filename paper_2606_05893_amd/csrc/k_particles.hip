@@ -128,11 +128,13 @@ __device__ __forceinline__ int dest_slot(unsigned cell, int tx, int ty, int tz,
 
 // Count a pushed particle's destination tile for the binning pass: per
 // neighbouring tile in LDS (sc, sd), else straight into the global counts.
-__device__ __forceinline__ void count_dest(unsigned cell, int tx, int ty,
-                                           int tz, const GridC& g,
-                                           unsigned* sc, unsigned* sd,
-                                           unsigned* __restrict__ cnt) {
-  if (cell == kDead) return;
+// Returns the slot (13: its own tile; -1: farther; -2: removed).
+constexpr int kSlotSelf = 13;
+__device__ __forceinline__ int count_dest(unsigned cell, int tx, int ty,
+                                          int tz, const GridC& g,
+                                          unsigned* sc, unsigned* sd,
+                                          unsigned* __restrict__ cnt) {
+  if (cell == kDead) return -2;
   unsigned u;
   const int d = dest_slot(cell, tx, ty, tz, g, u);
   if (d >= 0) {
@@ -141,6 +143,7 @@ __device__ __forceinline__ void count_dest(unsigned cell, int tx, int ty,
   } else {
     atomicAdd(&cnt[u], 1u);
   }
+  return d;
 }
 
 // Cell of an in-domain position (0 <= z/dx < nz): the one the MCC uses for
@@ -205,6 +208,7 @@ __global__ void k_begin(Counters* dc, unsigned long long n0,
   dc->n_cand = dc->n_elastic = dc->n_events = dc->n_ok = 0;
   dc->n_over = dc->n_near = dc->n_ab = dc->n_ncand = 0;
   dc->n_tail_cand = dc->n_el_tail = 0;
+  dc->ion_moved = dc->n_dead2 = 0;
 }
 
 // ---- sources ------------------------------------------------------------------
@@ -523,6 +527,18 @@ __device__ __forceinline__ void dep_flush(const unsigned long long* sq,
   }
 }
 
+// Deposit of the particles after the tile ranges, with global atomics.
+template <class PT>
+__global__ void __launch_bounds__(kT) k_deposit_tail(
+    PT p, long long first, const unsigned long long* __restrict__ np,
+    long long* __restrict__ acc, GridC g, long long sign) {
+  const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= (long long)*np) return;
+  int ix, fx, iy, fy, iz, fz;
+  Acc<PT>::cic(p, i, g, ix, fx, iy, fy, iz, fz);
+  dep_global(acc, g, ix, fx, iy, fy, iz, fz, sign);
+}
+
 // ---- push ---------------------------------------------------------------------
 struct MccC {
   int enabled, ion_model;
@@ -687,6 +703,15 @@ __device__ __forceinline__ CandRec cand_rec(const PushOut& o, long long i) {
   return r;
 }
 
+// Index of a removed ion into the step's list (wave-aggregated slot).  All
+// lanes must call it.
+__device__ __forceinline__ void list_dead(bool dead, long long i,
+                                          uint32_t* __restrict__ dead2,
+                                          Counters* dc) {
+  const unsigned long long slot = wave_append(dead, &dc->n_dead2);
+  if (dead && slot < (unsigned long long)kDeadList) dead2[slot] = (uint32_t)i;
+}
+
 // Cathode sink record (wave-aggregated slot).  All lanes must call it.
 template <int SP>
 __device__ __forceinline__ void sink(const Parts& p, long long i,
@@ -745,6 +770,7 @@ struct TileArgs {
   double *part_e, *part_i;
   unsigned *cnt_e, *cnt_i;   // destination-tile counts for the binning
   long long* dep;            // charge of the pushed state (int64 units)
+  uint32_t* dead2;           // removed ions' indices
 };
 
 __global__ void __launch_bounds__(kT) k_push_tile(
@@ -797,6 +823,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
     PushOut o;
     o.cathode = false;
     o.anode = false;
+    bool moved = false;
     if (live) {
       const double x = A.pi.x[i], y = A.pi.y[i], z = A.pi.z[i];
       int ix, fx, iy, fy, iz, fz;
@@ -817,7 +844,8 @@ __global__ void __launch_bounds__(kT) k_push_tile(
       finish_push<2>(A.pi, i, x, y, z, vx, vy, vz, A.dt, g, A.keyi, A.ncount, m,
                      step, seed, dc, o, 0ull);
       ke_i = ke_i + o.ke;
-      count_dest(o.cell, tx, ty, tz, g, s_nc[1], s_nd[1], A.cnt_i);
+      moved = count_dest(o.cell, tx, ty, tz, g, s_nc[1], s_nd[1], A.cnt_i) != kSlotSelf &&
+              o.cell != kDead;
       if (o.cell != kDead) {
         int dx_, fx_, dy_, fy_, dz_, fz_;
         cic_stored(Parts(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
@@ -825,6 +853,8 @@ __global__ void __launch_bounds__(kT) k_push_tile(
       }
     }
     sink<2>(A.pi, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
+    wave_count(moved, &dc->ion_moved);
+    list_dead(live && o.cell == kDead, i, A.dead2, dc);
   }
   // Electrons.
   for (unsigned base = be; base < ee; base += blockDim.x) {
@@ -889,7 +919,8 @@ __global__ void __launch_bounds__(kT) k_push_list(
     double dt, int* __restrict__ ncount, CandRec* __restrict__ cand, MccC m,
     uint32_t step, uint64_t seed, Rec* __restrict__ ab_rec,
     double* __restrict__ ab_pos, double* __restrict__ ab_vel, long long ab_cap,
-    Counters* dc, double* __restrict__ part, long long* __restrict__ dep) {
+    Counters* dc, double* __restrict__ part, long long* __restrict__ dep,
+    uint32_t* __restrict__ dead2) {
   __shared__ double sk[kT];
   const long long n = (long long)dc->n[SP];
   const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -918,6 +949,7 @@ __global__ void __launch_bounds__(kT) k_push_list(
     }
   }
   sink<SP>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+  if (SP == 2) list_dead(live && o.cell == kDead, i, dead2, dc);
   if (SP == 0) {
     const unsigned long long cs = wave_append(o.cand, &dc->n_tail_cand);
     if (o.cand) cand[first + cs] = cand_rec(o, i);
@@ -1064,6 +1096,7 @@ struct TileArgsM {
   double *part_e, *part_i;
   unsigned *cnt_e, *cnt_i;   // destination-tile counts for the binning
   long long* dep;            // charge of the pushed state (int64 units)
+  uint32_t* dead2;           // removed ions' indices
 };
 
 template <int SP>
@@ -1171,11 +1204,13 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
     PushOut o;
     o.cathode = false;
     o.anode = false;
+    bool moved = false;
     if (i < ei) {
       push_one_m<2>(A.pi, i, sx, sy, sz, x0, y0, z0, E, nn, g, A.qm_i, A.dtdx,
                     A.keyi, A.ncount, m, step, seed, dc, o);
       ke_i = ke_i + o.ke;
-      count_dest(o.cell, tx, ty, tz, g, s_nc[1], s_nd[1], A.cnt_i);
+      moved = count_dest(o.cell, tx, ty, tz, g, s_nc[1], s_nd[1], A.cnt_i) != kSlotSelf &&
+              o.cell != kDead;
       if (o.cell != kDead) {
         int dx_, fx_, dy_, fy_, dz_, fz_;
         cic_stored(PartsM(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
@@ -1183,6 +1218,8 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
       }
     }
     sink_m(A.pi, i, 2, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
+    wave_count(moved, &dc->ion_moved);
+    list_dead(i < ei && o.cell == kDead, i, A.dead2, dc);
   }
   for (unsigned base = be; base < ee; base += blockDim.x) {
     const long long i = base + threadIdx.x;
@@ -1227,7 +1264,8 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
     int* __restrict__ ncount, CandRec* __restrict__ cand, MccC m,
     uint32_t step, uint64_t seed, Rec* __restrict__ ab_rec,
     double* __restrict__ ab_pos, double* __restrict__ ab_vel, long long ab_cap,
-    Counters* dc, double* __restrict__ part, long long* __restrict__ dep) {
+    Counters* dc, double* __restrict__ part, long long* __restrict__ dep,
+    uint32_t* __restrict__ dead2) {
   __shared__ double sk[kT];
   const long long n = (long long)dc->n[SP];
   const long long i = first + blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -1247,6 +1285,7 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
     }
   }
   sink_m(p, i, SP, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+  if (SP == 2) list_dead(live && o.cell == kDead, i, dead2, dc);
   if (SP == 0) {
     const unsigned long long cs = wave_append(o.cand, &dc->n_tail_cand);
     if (o.cand) cand[first + cs] = cand_rec(o, i);
@@ -2273,6 +2312,14 @@ void deposit_t(pic_ctx* c) {
   k_deposit<PT><<<(unsigned)c->nch_bound, kT, 0, c->stream>>>(
       cur<PT>(c, 0), cur<PT>(c, 2), ts_cur(c, 0), ts_cur(c, 2), c->chunks,
       c->cstart + c->ntiles, c->acc, c->g);
+  // Particles outside the tile ranges (ions left unbinned between passes).
+  for (int s = 0; s < 3; s += 2) {
+    const long long tail = std::max(0ll, bound(c, s) - c->n_binned[s]);
+    if (tail > 0)
+      k_deposit_tail<PT><<<nblk(tail), kT, 0, c->stream>>>(
+          cur<PT>(c, s), c->n_binned[s], &c->dc->n[s], c->acc, c->g,
+          s ? 1 : -1);
+  }
 }
 
 // Queue, disk, sphere and Fowler-Nordheim particles, ids in that order.
@@ -2430,6 +2477,7 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.cnt_e = c->tcnt[0];
   A.cnt_i = c->tcnt[1];
   A.dep = c->acc_next;
+  A.dead2 = c->dead2;
   k_push_tile<<<(unsigned)c->nch_bound, kT, 0, st>>>(A, c->E, nn, c->g, m,
                                                          step, seed, c->dc);
   tmark(c, PIC_PH_PUSH_ELECTRON, false);
@@ -2439,13 +2487,13 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
   k_push_list<2><<<nbi, kT, 0, st>>>(
       cur<Parts>(c, 2), c->n_binned[2], c->key[2], c->E, nn, c->g,
       qm_dt(2, dt), dt, c->ncount, c->cand, m, step, seed, c->ab_rec,
-      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l, c->acc_next);
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l, c->acc_next, c->dead2);
   const long long tail_e = std::max(0ll, bound(c, 0) - c->n_binned[0]);
   nbe = nblk(tail_e > 0 ? tail_e : 1);
   k_push_list<0><<<nbe, kT, 0, st>>>(
       cur<Parts>(c, 0), c->n_binned[0], c->key[0], c->E, nn, c->g,
       qm_dt(0, dt), dt, c->ncount, c->cand, m, step, seed, c->ab_rec,
-      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi, c->acc_next);
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi, c->acc_next, c->dead2);
   tmark(c, PIC_PH_PUSH_ION, false);
 }
 
@@ -2485,6 +2533,7 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
   A.cnt_e = c->tcnt[0];
   A.cnt_i = c->tcnt[1];
   A.dep = c->acc_next;
+  A.dead2 = c->dead2;
   k_push_tile_m<<<(unsigned)c->nch_bound, kT, 0, st>>>(A, E, nn, c->g, m,
                                                            step, seed, c->dc);
   tmark(c, PIC_PH_PUSH_ELECTRON, false);
@@ -2494,13 +2543,13 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
   k_push_list_m<2><<<nbi, kT, 0, st>>>(
       cur<PartsM>(c, 2), c->n_binned[2], c->key[2], E, nn, c->g,
       (float)qm_dt(2, dt), dtdx, c->ncount, c->cand, m, step, seed, c->ab_rec,
-      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l, c->acc_next);
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l, c->acc_next, c->dead2);
   const long long tail_e = std::max(0ll, bound(c, 0) - c->n_binned[0]);
   nbe = nblk(tail_e > 0 ? tail_e : 1);
   k_push_list_m<0><<<nbe, kT, 0, st>>>(
       cur<PartsM>(c, 0), c->n_binned[0], c->key[0], E, nn, c->g,
       (float)qm_dt(0, dt), dtdx, c->ncount, c->cand, m, step, seed, c->ab_rec,
-      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi, c->acc_next);
+      c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi, c->acc_next, c->dead2);
   tmark(c, PIC_PH_PUSH_ION, false);
 }
 
@@ -2817,10 +2866,97 @@ void parts_chunks(pic_ctx* c, const long long hb[3]) {
 // End of a step: electrons and ions are binned by tile; the neutrals are
 // compacted in place, and binned again once the particles out of tile order
 // (moved into holes or appended since the last pass) reach half of them.
+// In-place removal of a step's few removed ions (listed by the pushes): with
+// n ions of which D are removed, each listed index below n - D is filled by
+// one of the live ions at or above it (equally many), and the tile ranges
+// are cut at n - D.  A filled slot may hold an ion of another tile; the
+// pushes and the deposit treat such ions correctly.  One workgroup.
+template <class PT>
+__global__ void __launch_bounds__(1024) k_ion_remove(
+    PT p, uint32_t* __restrict__ key, const uint32_t* __restrict__ dead2,
+    uint32_t* __restrict__ ts, long long nt, Counters* dc) {
+  __shared__ uint32_t holes[kDeadList], movers[kDeadList];
+  __shared__ unsigned nh, nm;
+  const long long n = (long long)dc->n[2];
+  const long long D = (long long)dc->n_dead2;
+  if (D <= 0 || D > kDeadList || D > n) return;
+  const long long keep = n - D;
+  if (threadIdx.x == 0) nh = nm = 0;
+  __syncthreads();
+  for (long long j = threadIdx.x; j < D; j += blockDim.x) {
+    const uint32_t q = dead2[j];
+    if ((long long)q < keep) holes[atomicAdd(&nh, 1u)] = q;
+  }
+  for (long long q = keep + threadIdx.x; q < n; q += blockDim.x)
+    if (key[q] != kDead) movers[atomicAdd(&nm, 1u)] = (uint32_t)q;
+  __syncthreads();
+  // Holes lie below keep and movers at or above it: no copy reads a slot
+  // another writes.
+  const unsigned np = nh < nm ? nh : nm;
+  for (unsigned j = threadIdx.x; j < np; j += blockDim.x) {
+    Acc<PT>::copy(p, movers[j], p, holes[j]);
+    key[holes[j]] = key[movers[j]];
+  }
+  for (long long t = threadIdx.x; t <= nt; t += blockDim.x)
+    if ((long long)ts[t] > keep) ts[t] = (uint32_t)keep;
+  if (threadIdx.x == 0) {
+    if (nh != nm) atomicOr(&dc->err, kErrCapacity);  // (cannot happen)
+    dc->n[2] = (unsigned long long)keep;
+  }
+}
+
+// Ions move about 1e-5 cells per step: binning them every step would copy
+// ten million records to file a few thousand new ones.  The ions that left
+// the domain this step (a few) are removed in place instead, and the ions
+// are binned again only when the ions out of tile order (the unbinned tail
+// of new ions, those moved into removed ones' slots, and every binned ion
+// that has crossed a tile face since the last pass) exceed kIonLazy plus
+// 1/1024 of them, or when more than kDeadList left at once.  The pushes
+// handle ions out of tile order correctly, only more slowly: the unbinned
+// tail costs about 0.7 ns per ion and step, so with a few thousand new ions
+// per step a bound of a few ten thousand balances its growth against one
+// binning pass.  The decision reads this step's counters, copied as soon as
+// the collisions are done, while the electrons bin.
+constexpr long long kIonLazy = 1 << 15;
+
 void parts_bin(pic_ctx* c) {
+  hipStream_t st = c->stream;
   tmark(c, PIC_PH_BIN, true);
+  hipMemcpyAsync(c->hmid, c->dc, sizeof(Counters), hipMemcpyDeviceToHost, st);
+  hipEventRecord(c->ev_mid, st);
   parts_bin_species(c, 0);
-  parts_bin_species(c, 2);
+  bool bin_ions = true;
+  if (hipEventSynchronize(c->ev_mid) == hipSuccess) {
+    const Counters& h = *c->hmid;
+    const long long n2 = (long long)h.n[2];
+    const long long tail = n2 - c->n_binned[2];
+    c->ion_moved_accum += (long long)h.ion_moved;
+    const long long dead = (long long)h.n_dead2;
+    const long long bound2 = kIonLazy + c->n_binned[2] / 1024;
+    bin_ions = h.err != 0 || tail < 0 || dead > kDeadList ||
+               c->ion_moved_accum + tail + dead > bound2;
+    if (!bin_ions) {
+      if (dead > 0) {
+        if (c->mixed)
+          k_ion_remove<PartsM><<<1, 1024, 0, st>>>(cur<PartsM>(c, 2), c->key[2],
+                                                   c->dead2, ts_cur(c, 2),
+                                                   c->ntiles, c->dc);
+        else
+          k_ion_remove<Parts><<<1, 1024, 0, st>>>(cur<Parts>(c, 2), c->key[2],
+                                                  c->dead2, ts_cur(c, 2),
+                                                  c->ntiles, c->dc);
+        c->ion_moved_accum += dead;
+      }
+      // Exact: nothing else changes the ions until the next step.
+      c->n[2] = n2 - dead;
+      c->n_binned[2] = std::min(c->n_binned[2], c->n[2]);
+    }
+  }
+  c->ions_binned = bin_ions;
+  if (bin_ions) {
+    parts_bin_species(c, 2);
+    c->ion_moved_accum = 0;
+  }
   c->tcounted = false;
   c->neutrals_binned = 2 * c->n_stirred >= c->n[1];
   if (c->neutrals_binned)

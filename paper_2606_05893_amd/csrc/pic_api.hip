@@ -164,6 +164,7 @@ size_t carve(pic_ctx* c, char* base) {
   c->ncount = cv.take<int>(c->ncells);
   c->flag = cv.take<uint32_t>((c->ncells + 31) / 32);
   c->cand = cv.take<CandRec>(f.capacity[0]);
+  c->dead2 = cv.take<uint32_t>(kDeadList);
   c->cand_cnt = cv.take<uint32_t>(c->nch_cap + 1);
   c->el_cnt = cv.take<uint32_t>(c->nch_cap + 1);
   c->chunks = cv.take<uint2>(c->nch_cap);
@@ -381,6 +382,10 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->ncount_valid = false;
   c->acc_next_valid = false;
   c->n_start1 = 0;
+  c->ion_moved_accum = 0;
+  c->ions_binned = true;
+  c->hmid = nullptr;
+  c->ev_mid = nullptr;
   c->n_stirred = 0;
   c->neutrals_binned = false;
   c->next_id = 0;
@@ -400,7 +405,14 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->timing = false;
   c->ev_made = false;
   if (!hip_ok(c, hipMemsetAsync(ws, 0, bytes, c->stream), "workspace clear") ||
-      !hip_ok(c, hipStreamSynchronize(c->stream), "init synchronise")) {
+      !hip_ok(c, hipStreamSynchronize(c->stream), "init synchronise") ||
+      !hip_ok(c, hipHostMalloc(reinterpret_cast<void**>(&c->hmid), sizeof(Counters),
+                               hipHostMallocDefault),
+              "pinned counters") ||
+      !hip_ok(c, hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming),
+              "event create")) {
+    if (c->hmid) hipHostFree(c->hmid);
+    if (c->ev_mid) hipEventDestroy(c->ev_mid);
     delete c;
     return PIC_ERR_HIP;
   }
@@ -410,6 +422,8 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
 
 void pic_destroy(pic_ctx* c) {
   if (!c) return;
+  if (c->hmid) hipHostFree(c->hmid);
+  if (c->ev_mid) hipEventDestroy(c->ev_mid);
   if (c->ev_made)
     for (int p = 0; p < PIC_NPHASES; ++p)
       for (int i = 0; i < pic_ctx::kTimeIv; ++i)
@@ -583,6 +597,10 @@ pic_status advance_finish(pic_ctx* c, double dt, const long long add[3],
   pic_status st = sync_counters(c);
   if (st != PIC_OK) return st;
   for (int k = 0; k < 3; ++k) {
+    if (k == 2 && !c->ions_binned) {
+      c->n[k] = (long long)c->hc.n[k];   // binned ranges kept, tail grown
+      continue;
+    }
     c->n[k] = (long long)c->hc.sorted_n[k];
     c->n_binned[k] = c->n[k];
   }
@@ -706,6 +724,7 @@ pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
   if (n > 0 && (!pos || !vel || !ids)) return PIC_ERR_ARG;
   parts_load(c, s, n, pos, vel, ids);
   if (s == 1) c->ncount_valid = false;
+  if (s == 2) c->ion_moved_accum = 0;
   c->acc_next_valid = false;
   // The new population has no tile ranges yet: all of it bins as a tail.
   hipMemsetAsync(c->tsb[s][c->tcur[s]], 0, (c->ntiles + 1) * sizeof(uint32_t),
@@ -842,6 +861,7 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
   if (st == PIC_OK) st = pic_set_sources(c, &h.src);
   if (st != PIC_OK) return st;
   c->ncount_valid = false;  // the neutrals are replaced
+  c->ion_moved_accum = 0;
   c->acc_next_valid = false;
   for (int s = 0; s < 3; ++s) c->n[s] = h.n[s];
   const char* in = static_cast<const char*>(host);

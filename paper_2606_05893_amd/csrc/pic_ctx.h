@@ -37,6 +37,8 @@ struct Level {
 // x and y (powers of two by FFT up to kSpecMaxFFT, other even sizes by a
 // direct transform up to kSpecMaxXY), unknown planes in z.
 constexpr int kSpecMaxXY = 32, kSpecMaxFFT = 64, kSpecMaxPlanes = 256;
+// Removed ions a step can list for the in-place removal (more: full binning).
+constexpr int kDeadList = 4096;
 
 struct QueueCall {
   int species;
@@ -97,6 +99,15 @@ struct pic_ctx {
   bool ncount_valid;         // ncount counts the first n_start1 neutrals
   long long* acc_next;       // charge of the state the last advance left
   bool acc_next_valid;       // ... and it is the current particles'
+  // Ions are binned again only when one left the domain, or when the
+  // ions out of tile order (unbinned tail, binned ones that crossed a tile
+  // face since the last pass) pass a bound; the decision reads this step's
+  // counters while the electrons bin.
+  long long ion_moved_accum;
+  bool ions_binned;          // this step binned them
+  pic::Counters* hmid;       // pinned copy of the counters for it
+  uint32_t* dead2;           // indices of this step's removed ions
+  hipEvent_t ev_mid;
   long long n_start1;        // neutrals at the start of the step's sources
   uint32_t* flag;            // cells holding ionisation events (one bit each)
   pic::CandRec* cand;        // null-collision candidates

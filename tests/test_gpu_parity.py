@@ -324,6 +324,51 @@ def test_absorbed_list_longer_than_a_sort_chunk(gpu_lib):
     assert np.array_equal(ab_g["vel"].cpu().numpy(), vel_o)
 
 
+def test_ions_removed_in_place_over_steps(gpu_lib):
+    """8 000 slow ions in the bulk and 600 that reach the cathode over the
+    next steps, a few per tile: each step removes the ions that left in
+    place (their slots filled from the end of the list, tile ranges cut)
+    instead of binning all ions again.  After every step the ions, by id,
+    equal the oracle's (positions and velocities exactly), and so does the
+    cathode list."""
+    p = small_c2(n_e=10, n_ion=10, n_n=10)
+    p["sources"] = {}
+    p["collisions"] = dict(p["collisions"], enabled=False)
+    g = grid_of(p)
+    gpu = make(p, cap=40000, max_events=1 << 15)
+    st = O.State(g, seed=p["seed"])
+    rng = np.random.default_rng(31)
+    L = np.array([g.lx, g.ly, g.nz * p["dx"]])
+    pos = rng.random((8600, 3)) * L
+    vel = rng.standard_normal((8600, 3)) * 1e2
+    # The last 600: within four steps' travel of the cathode, moving into it.
+    fall = 0.5 * p["dx"] / p["dt"]
+    pos[8000:, 2] = rng.random(600) * 4.0 * fall * p["dt"]
+    vel[8000:, 2] = -fall
+    ids = rng.permutation(np.arange(8600, dtype=np.uint64) * 3 + 1)
+    st.load(2, pos, vel, ids)
+    gpu.load(2, pos, vel, ids)
+    st.next_id = 10 ** 5
+    gpu.set_clock(0, 10 ** 5)
+    phi = P.solve_exact(P.add_boundary_terms(np.zeros(g.shape), g), g)
+    gpu.set_phi(phi)
+    E = O.efield(phi, g)
+    gone = 0
+    for k in range(5):
+        ab_g, dg = gpu.advance(p["dt"])
+        ab_o, do = O.advance(st, p, E, p["dt"])
+        assert ab_g["n"] == ab_o["id"].size, k
+        if ab_g["n"]:
+            assert np.array_equal(ab_g["id"].cpu().numpy().astype(np.uint64),
+                                  ab_o["id"])
+        gone += ab_g["n"]
+        ig, pg, vg = gpu_arrays(gpu, 2)
+        io, po, vo = oracle_arrays(st.sp[2])
+        assert np.array_equal(ig, io), k
+        assert np.array_equal(pg, po) and np.array_equal(vg, vo), k
+    assert 0 < gone < 4096 and gone >= 500
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_neutral_compaction_and_rebinning_over_steps(gpu_lib, precision):
     """Five advances in a fixed field with dense ionisation and a neutral
