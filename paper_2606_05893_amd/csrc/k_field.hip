@@ -845,77 +845,44 @@ inline unsigned nblocks(long long n, int t = kThreads) {
 // ---- fused smoothing ------------------------------------------------------
 // Two red-black Gauss-Seidel sweeps (red, black, red, black) in one pass over
 // the level, from uin to uout.  A workgroup owns a kSX x kSY column of nodes
-// and a segment of z planes and marches up z with a ring of kSR planes of u
-// in LDS: at step p it applies half-sweep h to plane p-h (h = 0..3), so
-// every half-sweep sees the other colour's values of the previous half-sweep
-// on the three planes it reads.  Half-sweep h updates the column widened by
-// 3-h nodes in x, y and z (the halo it leaves valid for h+1), so the final
-// values of the owned nodes are exactly those of four grid-wide colour
-// launches; the widened nodes are recomputed by the neighbouring workgroups
-// from the same old values.  The u plane and the f operands two steps
-// ahead are loaded into registers while the current step computes.  HBM traffic per pass: u and f read and u written once, against
-// about four times that for separate launches.
+// and a segment of z planes and marches up z: at step p it applies
+// half-sweep h to plane p-h (h = 0..3), so every half-sweep sees the other
+// colour's values of the previous half-sweep on the three planes it reads.
+// Half-sweep h updates the column widened by 3-h nodes in x, y and z (the
+// halo it leaves valid for h+1), so the final values of the owned nodes are
+// exactly those of four grid-wide colour launches; the widened nodes are
+// recomputed by the neighbouring workgroups from the same old values.
+//
+// Each thread owns one x-pair (2k, 2k+1) of one row of the widened column
+// for the whole march, and keeps the pair's values on the six planes in
+// flight in registers.  At step p every half-sweep updates the pair's node
+// of parity (row + p) on its own plane: its centre, its pair partner (one x
+// neighbour) and its z neighbours are the thread's registers; only the
+// other x neighbour and the two y neighbours are read from LDS, where each
+// updated value is also stored.  A plane slot in LDS holds the even-x nodes
+// of every row, then the odd-x ones, so a wave's reads are consecutive
+// words.  The half-sweeps of one step read only values written in earlier
+// steps (the z neighbours they share are one thread's registers), so one
+// barrier per step suffices.  The u pair of step p+4 and the f operands of
+// step p+2 are loaded while step p computes.  HBM traffic per pass: u and f
+// read and u written once, against about four times that for separate
+// launches.
 constexpr int kSX = 32, kSY = 8, kSH = 4;
 constexpr int kSPX = kSX + 2 * kSH, kSPY = kSY + 2 * kSH;
 constexpr int kSP = kSPX * kSPY;  // 640 nodes per plane slot
 constexpr int kSR = 6;
-constexpr int kSLoad = (kSP + 255) / 256;
-// A plane slot in LDS holds the even-x nodes of every row, then the odd-x
-// ones: a half-sweep touches one colour, i.e. every other node of a row,
-// and in this layout consecutive lanes read consecutive words (no bank
-// conflicts).
 constexpr int kHX = kSPX / 2, kHP = kHX * kSPY;
-static_assert((kSPX & 1) == 0 && (kSH & 1) == 0, "split layout needs even x");
-
-__host__ __device__ constexpr int split_idx(int lx, int ly) {
-  return (lx & 1) * kHP + ly * kHX + (lx >> 1);
-}
+constexpr int kSmoothT = kHX * kSPY;  // one x-pair per thread: 320
+static_assert((kSPX & 1) == 0 && (kSH & 1) == 0, "x-pairs need even x");
 
 __device__ __forceinline__ int wrap_n(int v, int n) {
   v = v < 0 ? v + n : v;
   return v >= n ? v - n : v;
 }
 
-// The colour nodes of half-sweep h's region that thread tid updates (at most
-// two): LDS index and in-plane global offsets for both parities of the
-// plane, and the parity of the row.
-struct HalfSlot {
-  int c0, c1, g0, g1, b;
-  bool on;
-};
-
-template <int H>
-__device__ __forceinline__ HalfSlot half_slot(int tid, int s, int x0, int y0,
-                                              int nx, int ny) {
-  constexpr int e = 3 - H;
-  constexpr int hw = (kSX + 2 * e) / 2;
-  constexpr int cnt = hw * (kSY + 2 * e);
-  HalfSlot r;
-  const int t = tid + 256 * s;
-  r.on = t < cnt;
-  const int row = t / hw, kk = t % hw;
-  const int ly = kSH - e + row, lx = kSH - e + 2 * kk;
-  r.c0 = ly * kSPX + lx;
-  r.c1 = r.c0 + 1;
-  r.g0 = r.g1 = 0;
-  if (r.on) {
-    const int gy = wrap_n(wrap_n(y0 + ly, ny), ny);
-    r.g0 = gy * nx + wrap_n(wrap_n(x0 + lx, nx), nx);
-    r.g1 = gy * nx + wrap_n(wrap_n(x0 + lx + 1, nx), nx);
-  }
-  // Node colour is (x + y + z) & 1, and x0, y0, nx, ny are even, so the
-  // local indices carry the parity: lx + d + ly + q == colour.
-  r.b = ((H & 1) + ly + lx) & 1;
-  return r;
-}
-
 template <int N>
 using IC = std::integral_constant<int, N>;
 
-// Update slots of a thread: half-sweep 0 covers up to 266 nodes (two per
-// thread), half-sweeps 1-3 at most 216 (one per thread).
-constexpr int kNS = 5;
-__host__ __device__ constexpr int slot_h(int k) { return k < 2 ? 0 : k - 1; }
 static_assert(kSR == 6, "the march below is unrolled by the ring length");
 // Ring index at step j (mod kSR) of the plane p + d.
 __host__ __device__ constexpr int ring_slot(int j, int d) {
@@ -925,9 +892,10 @@ __host__ __device__ constexpr int ring_slot(int j, int d) {
 // NEU: a z face of the level holds unknowns (Neumann condition), so face
 // planes are updated; with Dirichlet faces they never are.
 template <typename T, bool NEU>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 4 : 5)))
-k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
-          const T* __restrict__ f, LevelC L, int seg, const Counters* dc) {
+__global__ void __launch_bounds__(kSmoothT) k_smooth2(
+    const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ f,
+    LevelC L, int seg, const Counters* dc) {
+  using P2 = typename Pair2<T>::type;
   __shared__ T ring[kSR][kSP];
   if (dc->done) return;
   const int tiles_x = (L.nx + kSX - 1) / kSX;
@@ -942,32 +910,28 @@ k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
   const int x0 = tx * kSX - kSH, y0 = ty * kSY - kSH;
   const T h2 = (T)L.h2;
   const T sixth = T(1) / T(6);
-  const int tid = threadIdx.x;
 
-  // Plane loads: up to kSLoad nodes of a slot per thread.  Every global
-  // load is issued unconditionally (clamped to a valid node, its result
-  // unused where it is not needed), so the compiler waits for exactly the
-  // loads a use depends on while later ones stay in flight: the u plane of
-  // step p+4 and the f operands of step p+2 are loaded during step p.
-  int loff[kSLoad], lidx[kSLoad];
+  const int pk = threadIdx.x % kHX, ly = threadIdx.x / kHX;
+  const int lx0 = 2 * pk;
+  // x0, nx and ny are even, so the pair is one aligned 16-byte (8-byte)
+  // word of a row in memory, and the local indices carry the colour.
+  const int gy = wrap_n(wrap_n(y0 + ly, L.ny), L.ny);
+  const int gx0 = wrap_n(wrap_n(x0 + lx0, L.nx), L.nx);
+  const int goff = gy * L.nx + gx0;
+  const int s0 = ly * kHX + pk;  // even node; the odd one at s0 + kHP
+  // Bit h of inr[d]: node d of the pair lies in half-sweep h's region
+  // (widened by e = 3 - h).  Bit masks, not an array indexed by the node,
+  // which would live in scratch memory.
+  unsigned inr0 = 0u, inr1 = 0u;
 #pragma unroll
-  for (int r = 0; r < kSLoad; ++r) {
-    const int t = tid + 256 * r;
-    loff[r] = 0;
-    lidx[r] = 0;
-    if (t < kSP) {
-      const int gx = wrap_n(wrap_n(x0 + t % kSPX, L.nx), L.nx);
-      const int gy = wrap_n(wrap_n(y0 + t / kSPX, L.ny), L.ny);
-      loff[r] = gy * L.nx + gx;
-      lidx[r] = t;
-    }
+  for (int h = 0; h < 4; ++h) {
+    const int e = 3 - h;
+    const bool yin = ly >= kSH - e && ly < kSH + kSY + e;
+    if (yin && lx0 >= kSH - e && lx0 < kSH + kSX + e) inr0 |= 1u << h;
+    if (yin && lx0 + 1 >= kSH - e && lx0 + 1 < kSH + kSX + e) inr1 |= 1u << h;
   }
-  HalfSlot hs[kNS];
-  hs[0] = half_slot<0>(tid, 0, x0, y0, L.nx, L.ny);
-  hs[1] = half_slot<0>(tid, 1, x0, y0, L.nx, L.ny);
-  hs[2] = half_slot<1>(tid, 0, x0, y0, L.nx, L.ny);
-  hs[3] = half_slot<2>(tid, 0, x0, y0, L.nx, L.ny);
-  hs[4] = half_slot<3>(tid, 0, x0, y0, L.nx, L.ny);
+  const bool owned = ly >= kSH && ly < kSH + kSY && lx0 >= kSH &&
+                     lx0 < kSH + kSX && x0 + lx0 < L.nx && y0 + ly < L.ny;
 
   // Plane q takes half-sweep h when it holds unknowns and lies in h's
   // widened z range [za - e, zb - 1 + e], e = 3 - h; at step p that plane is
@@ -987,110 +951,95 @@ k_smooth2(const T* __restrict__ uin, T* __restrict__ uout,
   // Node offsets fit in 32 bits (at most 2^31 - 1 nodes per level).
   const int nxy = (int)L.nxy;
 
-  T pu[2][kSLoad];
-  T fs[2][kNS];
+  // The pair on the planes in flight: plane p + d at step j in slot
+  // ring_slot(j, d), as in LDS.
+  T v0[kSR], v1[kSR];
+  P2 pu[2];        // pairs loaded for later steps
+  T fs[2][4];      // f operands, per half-sweep, of the next two steps
+  // A plane outside the level (z < 0 or z > nz) is committed too, from the
+  // clamped loads: it is only read as the missing neighbour of a face
+  // plane, which the face update never uses.
   auto fetch_u = [&](auto U, int z) {
     constexpr int iu = decltype(U)::value;
-    const T* src = uin + clampz(z) * nxy;
+    pu[iu] = *reinterpret_cast<const P2*>(uin + clampz(z) * nxy + goff);
+  };
+  auto commit_u = [&](auto U, auto S) {
+    constexpr int iu = decltype(U)::value, sl = decltype(S)::value;
+    v0[sl] = pu[iu].x;
+    v1[sl] = pu[iu].y;
+    ring[sl][s0] = pu[iu].x;
+    ring[sl][s0 + kHP] = pu[iu].y;
+  };
+  // f operands of step p + 2 (planes p + 2 - h, node of parity d).
+  auto fetch_f = [&](auto F, int p, int d) {
+    constexpr int jf = decltype(F)::value;
 #pragma unroll
-    for (int r = 0; r < kSLoad; ++r) pu[iu][r] = src[loff[r]];
+    for (int h = 0; h < 4; ++h) fs[jf][h] = f[clampz(p + 2 - h) * nxy + goff + d];
   };
-  // A plane outside the level (z < 0 or z > nz) is committed too, from the
-  // clamped loads: its slot is only read as the missing neighbour of a face
-  // plane, which the face update never uses.
-  auto commit_u = [&](auto U, auto S, int) {
-    constexpr int iu = decltype(U)::value;
-    T* rr = ring[decltype(S)::value];
-#pragma unroll
-    for (int r = 0; r < kSLoad; ++r)
-      if (tid + 256 * r < kSP) rr[lidx[r]] = pu[iu][r];
-  };
-  // f plane pointers, kept like the u ring: plane p + d at step j in
-  // fpl[ring_slot(j, d)]; each step adds plane p + 2.
-  const T* fpl[kSR];
-  auto set_fplane = [&](auto S, int z) {
-    fpl[decltype(S)::value] = f + clampz(z) * nxy;
-  };
-  // f operands of step p + 2 (planes p + 2 - h) at step j.
-  auto fetch_f = [&](auto F, auto J, int p) {
-    constexpr int jf = decltype(F)::value, j = decltype(J)::value;
-#pragma unroll
-    for (int k = 0; k < kNS; ++k) {
-      const int q = p + 2 - slot_h(k);
-      const HalfSlot& z = hs[k];
-      fs[jf][k] = fpl[ring_slot(j, 2 - slot_h(k))][((z.b + q) & 1) ? z.g1 : z.g0];
-    }
-  };
-  // Update of slot k at step j of the unrolled march (plane q = p - h).
-  auto update = [&](auto K, auto J, int q, T fv) {
-    constexpr int k = decltype(K)::value, j = decltype(J)::value;
-    constexpr int h = slot_h(k);
-    const HalfSlot& z = hs[k];
-    if (!z.on) return;
-    const int c = z.c0 + ((z.b + q) & 1);
-    T* cur = ring[ring_slot(j, -h)];
-    const T* dn = ring[ring_slot(j, -h - 1)];
-    const T* up = ring[ring_slot(j, 1 - h)];
-    T sn = cur[c - 1] + cur[c + 1];
-    sn = sn + (cur[c - kSPX] + cur[c + kSPX]);
+  // Half-sweep h at step j (plane q = p - h) on the node of parity d.
+  auto update = [&](auto H, auto J, int p, int d, unsigned inr) {
+    constexpr int h = decltype(H)::value, j = decltype(J)::value;
+    constexpr int sc = ring_slot(j, -h), sd = ring_slot(j, -h - 1),
+                  su = ring_slot(j, 1 - h);
+    if (!(active(h, p) && ((inr >> h) & 1u))) return;
+    const int q = p - h;
+    const T* pl = ring[sc];
+    const int sn_i = s0 + d * kHP;
+    // The x neighbour outside the pair: lx0 - 1 (odd half, pair pk - 1)
+    // for the even node, lx0 + 2 (even half, pair pk + 1) for the odd one.
+    const T xo = pl[d ? s0 + 1 : s0 + kHP - 1];
+    const T xp = d ? v0[sc] : v1[sc];
+    T sn = xo + xp;
+    sn = sn + (pl[sn_i - kHX] + pl[sn_i + kHX]);
+    const T a = d ? v1[sd] : v0[sd], b = d ? v1[su] : v0[su];
     // On a Neumann face the mirror node stands in for the missing one
     // (up + up on the cathode face, dn + dn on the anode face).
-    const T a = dn[c], b = up[c];
     const T zs = NEU ? (q == 0 ? b : a) + (q == L.nz ? a : b) : a + b;
-    cur[c] = relax(cur[c], ((sn + zs) + h2 * fv) * sixth);
+    const T cu = d ? v1[sc] : v0[sc];
+    const T nv = relax(cu, ((sn + zs) + h2 * fs[j & 1][h]) * sixth);
+    if (d) v1[sc] = nv; else v0[sc] = nv;
+    ring[sc][sn_i] = nv;
   };
   // Step p (= p0 + j modulo kSR): the four half-sweeps (plane p-h), the
-  // finished plane p-3 out, plane p+2 into the ring, and the loads of later
-  // steps issued.
+  // finished plane p-3 out, the pair of plane p+2 into the ring, the loads
+  // of later steps issued, then the one barrier.
+  const int d0 = (ly + za - 3) & 1;  // parity of the updated node at p0
   auto step = [&](auto J, int p) {
     constexpr int j = decltype(J)::value, jf = j & 1;
-    if (active(0, p)) {
-      update(IC<0>(), J, p, fs[jf][0]);
-      update(IC<1>(), J, p, fs[jf][1]);
-    }
-    __syncthreads();
-    if (active(1, p)) update(IC<2>(), J, p - 1, fs[jf][2]);
-    __syncthreads();
-    if (active(2, p)) update(IC<3>(), J, p - 2, fs[jf][3]);
-    __syncthreads();
-    if (active(3, p)) update(IC<4>(), J, p - 3, fs[jf][4]);
-    __syncthreads();
+    const int d = d0 ^ jf;
+    const unsigned inr = d ? inr1 : inr0;
+    update(IC<0>(), J, p, d, inr);
+    update(IC<1>(), J, p, d, inr);
+    update(IC<2>(), J, p, d, inr);
+    update(IC<3>(), J, p, d, inr);
     const int q = p - 3;
-    if (q >= za && q < zb) {
-      const T* r = ring[ring_slot(j, -3)];
-      const int lx = kSH + tid % kSX, ly = kSH + tid / kSX;
-      const int gx = x0 + lx, gy = y0 + ly;
-      if (gx < L.nx && gy < L.ny)
-        uout[(long long)q * L.nxy + (long long)gy * L.nx + gx] = r[ly * kSPX + lx];
+    if (owned && q >= za && q < zb) {
+      constexpr int so = ring_slot(j, -3);
+      P2 w;
+      w.x = v0[so];
+      w.y = v1[so];
+      *reinterpret_cast<P2*>(uout + (long long)q * L.nxy + goff) = w;
     }
-    commit_u(IC<jf>(), IC<ring_slot(j, 2)>(), p + 2);
+    commit_u(IC<jf>(), IC<ring_slot(j, 2)>());
     fetch_u(IC<jf>(), p + 4);
-    set_fplane(IC<ring_slot(j, 2)>(), p + 2);
-    fetch_f(IC<jf>(), J, p);
+    fetch_f(IC<jf>(), p, d);
     __syncthreads();
   };
 
-  // Plane z lives in ring[(z - p0 + 1) mod kSR]; the march is unrolled by
-  // kSR, so every ring index is a constant (and the two register sets
+  // Plane z lives in slot (z - p0 + 1) mod kSR; the march is unrolled by
+  // kSR, so every slot index is a constant (and the two register sets
   // alternate with period 2, which divides kSR).
   const int p0 = za - 3, p1 = zb + 2;
   fetch_u(IC<0>(), p0 - 1);
-  commit_u(IC<0>(), IC<0>(), p0 - 1);
+  commit_u(IC<0>(), IC<0>());
   fetch_u(IC<0>(), p0);
-  commit_u(IC<0>(), IC<1>(), p0);
+  commit_u(IC<0>(), IC<1>());
   fetch_u(IC<0>(), p0 + 1);
-  commit_u(IC<0>(), IC<2>(), p0 + 1);
+  commit_u(IC<0>(), IC<2>());
   fetch_u(IC<0>(), p0 + 2);
   fetch_u(IC<1>(), p0 + 3);
-  // f planes p0 - 3 .. p0 + 1 (d = -3 .. 1 at step 0), then the operands
-  // of steps p0 and p0 + 1 (as fetched at steps p0 - 2 and p0 - 1).
-  set_fplane(IC<ring_slot(0, -3)>(), p0 - 3);
-  set_fplane(IC<ring_slot(0, -2)>(), p0 - 2);
-  set_fplane(IC<ring_slot(0, -1)>(), p0 - 1);
-  set_fplane(IC<ring_slot(0, 0)>(), p0);
-  set_fplane(IC<ring_slot(0, 1)>(), p0 + 1);
-  fetch_f(IC<0>(), IC<4>(), p0 - 2);
-  fetch_f(IC<1>(), IC<5>(), p0 - 1);
+  fetch_f(IC<0>(), p0 - 2, d0);
+  fetch_f(IC<1>(), p0 - 1, d0 ^ 1);
   __syncthreads();
   for (int p = p0;; p += kSR) {
     step(IC<0>(), p);
@@ -1816,7 +1765,7 @@ long long smooth_slots() {
   if (dev < 0 || dev >= 64) dev = 0;
   if (!cached[dev]) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth2<T, false>, 256, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth2<T, false>, kSmoothT, 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1900,9 +1849,9 @@ void vcycle(pic_ctx* c, int l) {
   auto smooth_fused = [&](const T* in, T* out) {
     if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
     if (Lc.k0 == 0 || Lc.k1 == Lc.nz)
-      k_smooth2<T, true><<<fgrid, 256, 0, st>>>(in, out, f, Lc, seg, c->dc);
+      k_smooth2<T, true><<<fgrid, kSmoothT, 0, st>>>(in, out, f, Lc, seg, c->dc);
     else
-      k_smooth2<T, false><<<fgrid, 256, 0, st>>>(in, out, f, Lc, seg, c->dc);
+      k_smooth2<T, false><<<fgrid, kSmoothT, 0, st>>>(in, out, f, Lc, seg, c->dc);
     if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
   };
   T* uc = u;  // fine values the restriction reads and the prolongation corrects
