@@ -863,8 +863,9 @@ inline unsigned nblocks(long long n, int t = kThreads) {
 // of every row, then the odd-x ones, so a wave's reads are consecutive
 // words.  The half-sweeps of one step read only values written in earlier
 // steps (the z neighbours they share are one thread's registers), so one
-// barrier per step suffices.  The u pair of step p+4 and the f operands of
-// step p+2 are loaded while step p computes.  HBM traffic per pass: u and f
+// barrier per step suffices.  The u pair of plane p+4 and the f pair of
+// plane p+2 (kept in registers for the four half-sweeps that use it) are
+// loaded while step p computes.  HBM traffic per pass: u and f
 // read and u written once, against about four times that for separate
 // launches.
 constexpr int kSX = 32, kSY = 8, kSH = 4;
@@ -954,8 +955,8 @@ __global__ void __launch_bounds__(kSmoothT) k_smooth2(
   // The pair on the planes in flight: plane p + d at step j in slot
   // ring_slot(j, d), as in LDS.
   T v0[kSR], v1[kSR];
+  T f0[kSR], f1[kSR];  // f of the pair, same slots (loaded two steps ahead)
   P2 pu[2];        // pairs loaded for later steps
-  T fs[2][4];      // f operands, per half-sweep, of the next two steps
   // A plane outside the level (z < 0 or z > nz) is committed too, from the
   // clamped loads: it is only read as the missing neighbour of a face
   // plane, which the face update never uses.
@@ -970,11 +971,12 @@ __global__ void __launch_bounds__(kSmoothT) k_smooth2(
     ring[sl][s0] = pu[iu].x;
     ring[sl][s0 + kHP] = pu[iu].y;
   };
-  // f operands of step p + 2 (planes p + 2 - h, node of parity d).
-  auto fetch_f = [&](auto F, int p, int d) {
-    constexpr int jf = decltype(F)::value;
-#pragma unroll
-    for (int h = 0; h < 4; ++h) fs[jf][h] = f[clampz(p + 2 - h) * nxy + goff + d];
+  // f pair of plane z into ring slot S (read from two steps later on).
+  auto fetch_f = [&](auto S, int z) {
+    constexpr int sl = decltype(S)::value;
+    const P2 w = *reinterpret_cast<const P2*>(f + clampz(z) * nxy + goff);
+    f0[sl] = w.x;
+    f1[sl] = w.y;
   };
   // Half-sweep h at step j (plane q = p - h) on the node of parity d.
   auto update = [&](auto H, auto J, int p, int d, unsigned inr) {
@@ -996,7 +998,8 @@ __global__ void __launch_bounds__(kSmoothT) k_smooth2(
     // (up + up on the cathode face, dn + dn on the anode face).
     const T zs = NEU ? (q == 0 ? b : a) + (q == L.nz ? a : b) : a + b;
     const T cu = d ? v1[sc] : v0[sc];
-    const T nv = relax(cu, ((sn + zs) + h2 * fs[j & 1][h]) * sixth);
+    const T fv = d ? f1[sc] : f0[sc];
+    const T nv = relax(cu, ((sn + zs) + h2 * fv) * sixth);
     if (d) v1[sc] = nv; else v0[sc] = nv;
     ring[sc][sn_i] = nv;
   };
@@ -1022,7 +1025,7 @@ __global__ void __launch_bounds__(kSmoothT) k_smooth2(
     }
     commit_u(IC<jf>(), IC<ring_slot(j, 2)>());
     fetch_u(IC<jf>(), p + 4);
-    fetch_f(IC<jf>(), p, d);
+    fetch_f(IC<ring_slot(j, 2)>(), p + 2);
     __syncthreads();
   };
 
@@ -1038,8 +1041,12 @@ __global__ void __launch_bounds__(kSmoothT) k_smooth2(
   commit_u(IC<0>(), IC<2>());
   fetch_u(IC<0>(), p0 + 2);
   fetch_u(IC<1>(), p0 + 3);
-  fetch_f(IC<0>(), p0 - 2, d0);
-  fetch_f(IC<1>(), p0 - 1, d0 ^ 1);
+  // f of planes p0 - 3 .. p0 + 1 (slots of d = -3 .. 1 at step 0).
+  fetch_f(IC<ring_slot(0, -3)>(), p0 - 3);
+  fetch_f(IC<ring_slot(0, -2)>(), p0 - 2);
+  fetch_f(IC<ring_slot(0, -1)>(), p0 - 1);
+  fetch_f(IC<ring_slot(0, 0)>(), p0);
+  fetch_f(IC<ring_slot(0, 1)>(), p0 + 1);
   __syncthreads();
   for (int p = p0;; p += kSR) {
     step(IC<0>(), p);
