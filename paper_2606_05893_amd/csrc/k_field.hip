@@ -195,25 +195,76 @@ __global__ void k_residual(const double* __restrict__ u,
                            float* __restrict__ rf, float* __restrict__ ef) {
   __shared__ double sb[kThreads];
   if (dc->done) return;
+  // Work item: an x-pair (i0, i0 + 1) of one row over a segment of the
+  // unknown planes, marched up z with the pair's z neighbours in registers
+  // (five loads per plane and pair: u above, the y-neighbour pairs, the
+  // two outer x neighbours, f).  nx is even (the configuration requires
+  // it), so a pair is one aligned
+  // 16-byte word.  The items are spread over the fixed grid in a fixed
+  // order, so the partial sums are deterministic.
+  const int hx = L.nx / 2;
+  const long long npair = (long long)hx * L.ny;
+  const int nplane = L.k1 - L.k0 + 1;
+  const long long nthr = (long long)gridDim.x * blockDim.x;
+  int nseg = (int)(nthr / npair);
+  nseg = nseg < 1 ? 1 : (nseg > nplane ? nplane : nseg);
+  const int len = (nplane + nseg - 1) / nseg;
+  const long long items = npair * nseg;
+  const int nxy = (int)L.nxy;
   double s2 = 0.0;
-  const long long nu = L.nxy * (L.k1 - L.k0 + 1);
-  // Unrolled so that several nodes' loads are in flight per thread; the
-  // partial sum keeps the loop's order.
-#pragma unroll 4
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nu;
-       t += (long long)gridDim.x * blockDim.x) {
-    const unsigned tt = (unsigned)t;
-    const int i = (int)(tt % (unsigned)L.nx);
-    const unsigned r = tt / (unsigned)L.nx;
-    const int j = (int)(r % (unsigned)L.ny);
-    const int k = L.k0 + (int)(r / (unsigned)L.ny);
-    const long long idx = ((long long)k * L.ny + j) * L.nx + i;
-    const double au = 6.0 * u[idx] - nb_sum(u, L, i, j, k);
-    const double res = f[idx] - au;
-    s2 = s2 + res * res;
-    if (rf) {
-      rf[idx] = (float)res;
-      ef[idx] = 0.0f;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < items;
+       t += nthr) {
+    const int pr = (int)(t % npair), sg = (int)(t / npair);
+    const int px = pr % hx, j = pr / hx;
+    const int i0 = 2 * px;
+    const int ka = L.k0 + sg * len;
+    const int kb = ka + len < L.k1 + 1 ? ka + len : L.k1 + 1;
+    if (ka >= kb) continue;
+    const int im = i0 ? i0 - 1 : L.nx - 1, ip = i0 + 2 < L.nx ? i0 + 2 : 0;
+    const int jm = j ? j - 1 : L.ny - 1, jp = j + 1 < L.ny ? j + 1 : 0;
+    const int r0 = j * L.nx, rm = jm * L.nx, rp = jp * L.nx;
+    auto pair = [&](int k, int row) {
+      return *reinterpret_cast<const double2*>(u + (long long)k * nxy + row + i0);
+    };
+    double2 cur = pair(ka, r0);
+    double2 dn = pair(ka > 0 ? ka - 1 : 0, r0);
+    for (int k = ka; k < kb; ++k) {
+      const long long base = (long long)k * nxy;
+      const double2 up = pair(k < L.nz ? k + 1 : k, r0);
+      const double2 ym = pair(k, rm), yp = pair(k, rp);
+      const double xl = u[base + r0 + im], xr = u[base + r0 + ip];
+      const double2 fv = *reinterpret_cast<const double2*>(f + base + r0 + i0);
+      double z0, z1;
+      if (k == 0) {
+        z0 = 2.0 * up.x;
+        z1 = 2.0 * up.y;
+      } else if (k == L.nz) {
+        z0 = 2.0 * dn.x;
+        z1 = 2.0 * dn.y;
+      } else {
+        z0 = dn.x + up.x;
+        z1 = dn.y + up.y;
+      }
+      // As the stencil sum of one node: x pair, then y pair, then z pair.
+      double n0 = xl + cur.y;
+      n0 = n0 + (ym.x + yp.x);
+      double n1 = cur.x + xr;
+      n1 = n1 + (ym.y + yp.y);
+      const double res0 = fv.x - (6.0 * cur.x - (n0 + z0));
+      const double res1 = fv.y - (6.0 * cur.y - (n1 + z1));
+      s2 = s2 + res0 * res0;
+      s2 = s2 + res1 * res1;
+      if (rf) {
+        float2 rv, zv;
+        rv.x = (float)res0;
+        rv.y = (float)res1;
+        zv.x = 0.0f;
+        zv.y = 0.0f;
+        *reinterpret_cast<float2*>(rf + base + r0 + i0) = rv;
+        *reinterpret_cast<float2*>(ef + base + r0 + i0) = zv;
+      }
+      dn = cur;
+      cur = up;
     }
   }
   sb[threadIdx.x] = s2;
