@@ -851,34 +851,71 @@ __global__ void k_efield(const double* __restrict__ phi,
                          const long long* __restrict__ acc,
                          TE* __restrict__ E, LevelC L, double h,
                          double q_unit, double* __restrict__ part) {
+  using E2 = typename Pair2<TE>::type;
   __shared__ double sb[kThreads];
   double s = 0.0;
   const long long n = L.nxy * (L.nz + 1);
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-       idx < n; idx += (long long)gridDim.x * blockDim.x) {
-    const unsigned ui = (unsigned)idx;
-    const int i = (int)(ui % (unsigned)L.nx);
-    const unsigned r = ui / (unsigned)L.nx;
-    const int j = (int)(r % (unsigned)L.ny);
-    const int k = (int)(r / (unsigned)L.ny);
-    const long long row = idx - i;
-    const int im = i ? i - 1 : L.nx - 1, ip = i + 1 < L.nx ? i + 1 : 0;
+  // Work item: an x-pair of one row over a segment of the planes, marched
+  // up z with the pair's z neighbours in registers (nx is even); the face
+  // planes load the second plane their one-sided difference needs.  Items
+  // are spread over the fixed grid in a fixed order: deterministic sums.
+  const int hx = L.nx / 2;
+  const long long npair = (long long)hx * L.ny;
+  const int nplane = L.nz + 1;
+  const long long nthr = (long long)gridDim.x * blockDim.x;
+  int nseg = (int)(nthr / npair);
+  nseg = nseg < 1 ? 1 : (nseg > nplane ? nplane : nseg);
+  const int len = (nplane + nseg - 1) / nseg;
+  const long long items = npair * nseg;
+  const int nxy = (int)L.nxy;
+  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < items;
+       t += nthr) {
+    const int pr = (int)(t % npair), sg = (int)(t / npair);
+    const int px = pr % hx, j = pr / hx;
+    const int i0 = 2 * px;
+    const int ka = sg * len;
+    const int kb = ka + len < nplane ? ka + len : nplane;
+    if (ka >= kb) continue;
+    const int im = i0 ? i0 - 1 : L.nx - 1, ip = i0 + 2 < L.nx ? i0 + 2 : 0;
     const int jm = j ? j - 1 : L.ny - 1, jp = j + 1 < L.ny ? j + 1 : 0;
-    const long long base = (long long)k * L.nxy;
-    const double ex = (phi[row + im] - phi[row + ip]) * h;
-    const double ey = (phi[base + (long long)jm * L.nx + i] -
-                       phi[base + (long long)jp * L.nx + i]) * h;
-    double ez;
-    if (k == 0)
-      ez = ((3.0 * phi[idx] - 4.0 * phi[idx + L.nxy]) + phi[idx + 2 * L.nxy]) * h;
-    else if (k == L.nz)
-      ez = ((-3.0 * phi[idx] + 4.0 * phi[idx - L.nxy]) - phi[idx - 2 * L.nxy]) * h;
-    else
-      ez = (phi[idx - L.nxy] - phi[idx + L.nxy]) * h;
-    E[idx] = (TE)ex;
-    E[n + idx] = (TE)ey;
-    E[2 * n + idx] = (TE)ez;
-    s = s + ((double)acc[idx] * q_unit) * phi[idx];
+    const int r0 = j * L.nx, rm = jm * L.nx, rp = jp * L.nx;
+    auto pair = [&](int k, int row) {
+      return *reinterpret_cast<const double2*>(phi + (long long)k * nxy + row + i0);
+    };
+    double2 cur = pair(ka, r0);
+    double2 dn = pair(ka > 0 ? ka - 1 : 0, r0);
+    for (int k = ka; k < kb; ++k) {
+      const long long idx = (long long)k * nxy + r0 + i0;
+      const double2 up = pair(k < L.nz ? k + 1 : k, r0);
+      const double2 ym = pair(k, rm), yp = pair(k, rp);
+      const double xl = phi[(long long)k * nxy + r0 + im];
+      const double xr = phi[(long long)k * nxy + r0 + ip];
+      const longlong2 ac = *reinterpret_cast<const longlong2*>(acc + idx);
+      E2 ex, ey, ez;
+      ex.x = (TE)((xl - cur.y) * h);
+      ex.y = (TE)((cur.x - xr) * h);
+      ey.x = (TE)((ym.x - yp.x) * h);
+      ey.y = (TE)((ym.y - yp.y) * h);
+      if (k == 0) {
+        const double2 u2 = pair(2, r0);
+        ez.x = (TE)(((3.0 * cur.x - 4.0 * up.x) + u2.x) * h);
+        ez.y = (TE)(((3.0 * cur.y - 4.0 * up.y) + u2.y) * h);
+      } else if (k == L.nz) {
+        const double2 d2 = pair(k - 2, r0);
+        ez.x = (TE)(((-3.0 * cur.x + 4.0 * dn.x) - d2.x) * h);
+        ez.y = (TE)(((-3.0 * cur.y + 4.0 * dn.y) - d2.y) * h);
+      } else {
+        ez.x = (TE)((dn.x - up.x) * h);
+        ez.y = (TE)((dn.y - up.y) * h);
+      }
+      *reinterpret_cast<E2*>(E + idx) = ex;
+      *reinterpret_cast<E2*>(E + n + idx) = ey;
+      *reinterpret_cast<E2*>(E + 2 * n + idx) = ez;
+      s = s + ((double)ac.x * q_unit) * cur.x;
+      s = s + ((double)ac.y * q_unit) * cur.y;
+      dn = cur;
+      cur = up;
+    }
   }
   sb[threadIdx.x] = s;
   __syncthreads();
