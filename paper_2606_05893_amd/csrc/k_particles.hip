@@ -2863,9 +2863,6 @@ void parts_chunks(pic_ctx* c, const long long hb[3]) {
   c->nch_bound = std::min<long long>(nt + (hb[0] + hb[2]) / kChunk + 2, c->nch_cap);
 }
 
-// End of a step: electrons and ions are binned by tile; the neutrals are
-// compacted in place, and binned again once the particles out of tile order
-// (moved into holes or appended since the last pass) reach half of them.
 // In-place removal of a step's few removed ions (listed by the pushes): with
 // n ions of which D are removed, each listed index below n - D is filled by
 // one of the live ions at or above it (equally many), and the tile ranges
@@ -2958,10 +2955,11 @@ void parts_bin(pic_ctx* c) {
     c->ion_moved_accum = 0;
   }
   c->tcounted = false;
-  c->neutrals_binned = 2 * c->n_stirred >= c->n[1];
-  if (c->neutrals_binned)
-    parts_bin_species(c, 1);
-  else if (c->mixed)
+  // Nothing reads the neutrals by tile (their push streams them, their
+  // cell counts are kept from step to step, the event cells are a bit mask
+  // in L2), so they are only compacted: a full binning pass of five
+  // million records through the unbinned-list path cost 2.3 ms.
+  if (c->mixed)
     compact_neutrals_t<PartsM>(c);
   else
     compact_neutrals_t<Parts>(c);

@@ -386,8 +386,6 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->ions_binned = true;
   c->hmid = nullptr;
   c->ev_mid = nullptr;
-  c->n_stirred = 0;
-  c->neutrals_binned = false;
   c->next_id = 0;
   c->step = 0;
   c->queue_used = 0;
@@ -604,9 +602,6 @@ pic_status advance_finish(pic_ctx* c, double dt, const long long add[3],
     c->n[k] = (long long)c->hc.sorted_n[k];
     c->n_binned[k] = c->n[k];
   }
-  c->n_stirred = c->neutrals_binned
-                     ? 0
-                     : c->n_stirred + add[1] + (long long)c->hc.n_holes;
   c->next_id = c->hc.next_id;
   c->step += 1;
   collect_times(c);
@@ -737,7 +732,6 @@ pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
   if (st != PIC_OK) return st;
   c->n[s] = (long long)c->hc.sorted_n[s];
   c->n_binned[s] = c->n[s];
-  if (s == 1) c->n_stirred = 0;
   const long long hb[3] = {c->n[0], c->n[1], c->n[2]};
   parts_chunks(c, hb);
   if (c->hc.err) {
@@ -904,7 +898,6 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
     c->n[s] = (long long)c->hc.sorted_n[s];
     c->n_binned[s] = c->n[s];
   }
-  c->n_stirred = 0;
   const long long hb[3] = {c->n[0], c->n[1], c->n[2]};
   parts_chunks(c, hb);
   c->step = h.step;

@@ -74,8 +74,6 @@ struct pic_ctx {
   long long nch_cap;         // capacity of the chunk list
   // Neutrals are compacted in place between full binning passes.
   uint32_t* cmp_idx;         // holes then movers, capacity[1] each
-  long long n_stirred;       // neutrals out of tile order since the last pass
-  bool neutrals_binned;      // the last step binned them (else compacted)
 
   // Node fields.
   long long* acc;            // int64 charge units

@@ -373,8 +373,8 @@ def test_ions_removed_in_place_over_steps(gpu_lib):
 def test_neutral_compaction_and_rebinning_over_steps(gpu_lib, precision):
     """Five advances in a fixed field with dense ionisation and a neutral
     source of half the initial population per step: the neutrals are
-    compacted in place on some steps and binned again on others (once the
-    neutrals out of tile order reach half of them).  After every step the
+    compacted in place every step (the ionised ones removed, the appended
+    ones kept in list order).  After every step the
     particle sets by id match the oracle's (FP64: exactly, with positions
     within 1e-12; mixed: up to collision draws that FP32 velocities move
     across a threshold, positions within 1e-4 cells), and no id repeats."""
