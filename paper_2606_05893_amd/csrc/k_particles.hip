@@ -208,7 +208,7 @@ __global__ void k_begin(Counters* dc, unsigned long long n0,
   dc->n_cand = dc->n_elastic = dc->n_events = dc->n_ok = 0;
   dc->n_over = dc->n_near = dc->n_ab = dc->n_ncand = 0;
   dc->n_tail_cand = dc->n_el_tail = 0;
-  dc->ion_moved = dc->n_dead2 = 0;
+  dc->ion_moved = dc->n_dead1 = dc->n_dead2 = 0;
 }
 
 // ---- sources ------------------------------------------------------------------
@@ -703,13 +703,14 @@ __device__ __forceinline__ CandRec cand_rec(const PushOut& o, long long i) {
   return r;
 }
 
-// Index of a removed ion into the step's list (wave-aggregated slot).  All
-// lanes must call it.
+// Index of a removed particle into the step's list of its species
+// (wave-aggregated slot; entries past kDeadList are counted, not stored).
+// All lanes must call it.
 __device__ __forceinline__ void list_dead(bool dead, long long i,
-                                          uint32_t* __restrict__ dead2,
-                                          Counters* dc) {
-  const unsigned long long slot = wave_append(dead, &dc->n_dead2);
-  if (dead && slot < (unsigned long long)kDeadList) dead2[slot] = (uint32_t)i;
+                                          uint32_t* __restrict__ list,
+                                          unsigned long long* count) {
+  const unsigned long long slot = wave_append(dead, count);
+  if (dead && slot < (unsigned long long)kDeadList) list[slot] = (uint32_t)i;
 }
 
 // Cathode sink record (wave-aggregated slot).  All lanes must call it.
@@ -854,7 +855,7 @@ __global__ void __launch_bounds__(kT) k_push_tile(
     }
     sink<2>(A.pi, i, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
     wave_count(moved, &dc->ion_moved);
-    list_dead(live && o.cell == kDead, i, A.dead2, dc);
+    list_dead(live && o.cell == kDead, i, A.dead2, &dc->n_dead2);
   }
   // Electrons.
   for (unsigned base = be; base < ee; base += blockDim.x) {
@@ -949,7 +950,7 @@ __global__ void __launch_bounds__(kT) k_push_list(
     }
   }
   sink<SP>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
-  if (SP == 2) list_dead(live && o.cell == kDead, i, dead2, dc);
+  if (SP == 2) list_dead(live && o.cell == kDead, i, dead2, &dc->n_dead2);
   if (SP == 0) {
     const unsigned long long cs = wave_append(o.cand, &dc->n_tail_cand);
     if (o.cand) cand[first + cs] = cand_rec(o, i);
@@ -1219,7 +1220,7 @@ __global__ void __launch_bounds__(kT) k_push_tile_m(
     }
     sink_m(A.pi, i, 2, o, g, A.ab_rec, A.ab_pos, A.ab_vel, A.ab_cap, dc);
     wave_count(moved, &dc->ion_moved);
-    list_dead(i < ei && o.cell == kDead, i, A.dead2, dc);
+    list_dead(i < ei && o.cell == kDead, i, A.dead2, &dc->n_dead2);
   }
   for (unsigned base = be; base < ee; base += blockDim.x) {
     const long long i = base + threadIdx.x;
@@ -1285,7 +1286,7 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
     }
   }
   sink_m(p, i, SP, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
-  if (SP == 2) list_dead(live && o.cell == kDead, i, dead2, dc);
+  if (SP == 2) list_dead(live && o.cell == kDead, i, dead2, &dc->n_dead2);
   if (SP == 0) {
     const unsigned long long cs = wave_append(o.cand, &dc->n_tail_cand);
     if (o.cand) cand[first + cs] = cand_rec(o, i);
@@ -1345,7 +1346,7 @@ __global__ void __launch_bounds__(kT) k_push_neutral(
     int* __restrict__ ncount, long long n_old, MccC m, uint32_t step,
     uint64_t seed, Rec* __restrict__ ab_rec, double* __restrict__ ab_pos,
     double* __restrict__ ab_vel, long long ab_cap, Counters* dc,
-    double* __restrict__ part) {
+    double* __restrict__ part, uint32_t* __restrict__ dead1) {
   __shared__ unsigned hk[kHist];
   __shared__ int hc[kHist];
   __shared__ double sk[kT];
@@ -1382,6 +1383,7 @@ __global__ void __launch_bounds__(kT) k_push_neutral(
         ke = ke + o.ke;
       }
       sink<1>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+      list_dead(i < n && o.cell == kDead, i, dead1, &dc->n_dead1);
     }
     if (fresh) {
       __syncthreads();
@@ -1398,7 +1400,7 @@ __global__ void __launch_bounds__(kT) k_push_neutral_m(
     int* __restrict__ ncount, long long n_old, MccC m, uint32_t step,
     uint64_t seed, Rec* __restrict__ ab_rec, double* __restrict__ ab_pos,
     double* __restrict__ ab_vel, long long ab_cap, Counters* dc,
-    double* __restrict__ part) {
+    double* __restrict__ part, uint32_t* __restrict__ dead1) {
   __shared__ unsigned hk[kHist];
   __shared__ int hc[kHist];
   __shared__ double sk[kT];
@@ -1434,6 +1436,7 @@ __global__ void __launch_bounds__(kT) k_push_neutral_m(
         ke = ke + o.ke;
       }
       sink_m(p, i, 1, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
+      list_dead(i < n && o.cell == kDead, i, dead1, &dc->n_dead1);
     }
     if (fresh) {
       __syncthreads();
@@ -1807,14 +1810,22 @@ __global__ void __launch_bounds__(kT) k_ionise(PT pe, PT pn, PT pi, uint32_t* __
                          const Rec* __restrict__ ok, const uint2* __restrict__ okp,
                          MccC m, uint32_t step, uint64_t seed, long long cap_e,
                          long long cap_i, int* __restrict__ ncount,
-                         long long* __restrict__ dep, GridC g, Counters* dc) {
+                         long long* __restrict__ dep, GridC g,
+                         uint32_t* __restrict__ dead1, Counters* dc) {
   const long long nok = (long long)dc->n_ok;
   const long long ne0 = (long long)dc->n[0], ni0 = (long long)dc->n[2];
   const unsigned long long id0 = dc->next_id;
-  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < nok;
-       r += (long long)gridDim.x * blockDim.x) {
+  // Every lane of a wave takes the same number of rounds (the list of
+  // consumed neutrals is filled per wave).
+  for (long long r0 = blockIdx.x * (long long)blockDim.x; r0 < nok;
+       r0 += (long long)gridDim.x * blockDim.x) {
+    const long long r = r0 + threadIdx.x;
+    const bool act = r < nok;
+    uint32_t in = 0;
+    if (act) {
     const uint2 pr = okp[ok[r].val];
-    const uint32_t ie = pr.x, in = pr.y;
+    const uint32_t ie = pr.x;
+    in = pr.y;
     const unsigned long long pid = ok[r].lo;
     // Charge of the new pair (the secondary at the primary's position, the
     // ion at the neutral's), taken before this event's stores.
@@ -1854,6 +1865,8 @@ __global__ void __launch_bounds__(kT) k_ionise(PT pe, PT pn, PT pi, uint32_t* __
     // The neutral leaves the per-cell counts of the next step.
     atomicSub(&ncount[kn[in]], 1);
     kn[in] = kDead;
+    }
+    list_dead(act, in, dead1, &dc->n_dead1);
   }
 }
 
@@ -2431,12 +2444,12 @@ void push_neutral_t(pic_ctx* c, double dt) {
     k_push_neutral_m<<<nb, kT, 0, st>>>(
         cur<PartsM>(c, 1), c->key[1], c->g, (float)(dt * c->g.inv_dx),
         c->ncount, n_old, m, step, seed, c->ab_rec, c->ab_raw_pos,
-        c->ab_raw_vel, ab_cap, c->dc, c->part_n);
+        c->ab_raw_vel, ab_cap, c->dc, c->part_n, c->dead1);
   else
     k_push_neutral<<<nb, kT, 0, st>>>(
         cur<Parts>(c, 1), c->key[1], c->g, dt, c->ncount, n_old, m, step,
         seed, c->ab_rec, c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc,
-        c->part_n);
+        c->part_n, c->dead1);
   c->ncount_valid = true;
   tmark(c, PIC_PH_PUSH_NEUTRAL, false);
   k_sum_partials<<<1, 1024, 0, st>>>(c->part_n, nb, nullptr, c->part_n, 0,
@@ -2603,7 +2616,7 @@ void push_collide_t(pic_ctx* c, double dt) {
                                     c->key[0], c->key[1], c->key[2], c->ok,
                                     c->okp, m, step, seed, c->cfg.capacity[0],
                                     c->cfg.capacity[2], c->ncount, c->acc_next,
-                                    c->g, c->dc);
+                                    c->g, c->dead1, c->dc);
     k_ionise_commit<<<1, 1024, 0, st>>>(c->dc, c->ev, c->flag, cap,
                                         c->cfg.capacity[0], c->cfg.capacity[2],
                                         c->el_cnt, c->cand_cnt,
@@ -2863,25 +2876,27 @@ void parts_chunks(pic_ctx* c, const long long hb[3]) {
   c->nch_bound = std::min<long long>(nt + (hb[0] + hb[2]) / kChunk + 2, c->nch_cap);
 }
 
-// In-place removal of a step's few removed ions (listed by the pushes): with
-// n ions of which D are removed, each listed index below n - D is filled by
-// one of the live ions at or above it (equally many), and the tile ranges
-// are cut at n - D.  A filled slot may hold an ion of another tile; the
-// pushes and the deposit treat such ions correctly.  One workgroup.
+// In-place removal of a step's few removed particles of species s (listed
+// as they were removed): with n particles of which D are removed, each
+// listed index below n - D is filled by one of the live particles at or
+// above it (equally many), and the tile ranges ts, if given, are cut at
+// n - D.  A filled slot may hold a particle of another tile; the pushes and
+// the deposit treat such particles correctly.  One workgroup.
 template <class PT>
-__global__ void __launch_bounds__(1024) k_ion_remove(
-    PT p, uint32_t* __restrict__ key, const uint32_t* __restrict__ dead2,
+__global__ void __launch_bounds__(1024) k_remove_listed(
+    PT p, uint32_t* __restrict__ key, const uint32_t* __restrict__ list,
+    const unsigned long long* __restrict__ ndead, int s,
     uint32_t* __restrict__ ts, long long nt, Counters* dc) {
   __shared__ uint32_t holes[kDeadList], movers[kDeadList];
   __shared__ unsigned nh, nm;
-  const long long n = (long long)dc->n[2];
-  const long long D = (long long)dc->n_dead2;
-  if (D <= 0 || D > kDeadList || D > n) return;
+  const long long n = (long long)dc->n[s];
+  const long long D = (long long)*ndead;
+  if (D > kDeadList || D > n) return;   // (the caller bins instead)
   const long long keep = n - D;
   if (threadIdx.x == 0) nh = nm = 0;
   __syncthreads();
   for (long long j = threadIdx.x; j < D; j += blockDim.x) {
-    const uint32_t q = dead2[j];
+    const uint32_t q = list[j];
     if ((long long)q < keep) holes[atomicAdd(&nh, 1u)] = q;
   }
   for (long long q = keep + threadIdx.x; q < n; q += blockDim.x)
@@ -2894,12 +2909,21 @@ __global__ void __launch_bounds__(1024) k_ion_remove(
     Acc<PT>::copy(p, movers[j], p, holes[j]);
     key[holes[j]] = key[movers[j]];
   }
-  for (long long t = threadIdx.x; t <= nt; t += blockDim.x)
-    if ((long long)ts[t] > keep) ts[t] = (uint32_t)keep;
+  if (ts)
+    for (long long t = threadIdx.x; t <= nt; t += blockDim.x)
+      if ((long long)ts[t] > keep) ts[t] = (uint32_t)keep;
   if (threadIdx.x == 0) {
     if (nh != nm) atomicOr(&dc->err, kErrCapacity);  // (cannot happen)
-    dc->n[2] = (unsigned long long)keep;
+    dc->n[s] = (unsigned long long)keep;
+    dc->sorted_n[s] = (unsigned long long)keep;
   }
+}
+
+template <class PT>
+void remove_listed_t(pic_ctx* c, int s, uint32_t* list,
+                     const unsigned long long* ndead, uint32_t* ts) {
+  k_remove_listed<PT><<<1, 1024, 0, c->stream>>>(
+      cur<PT>(c, s), c->key[s], list, ndead, s, ts, c->ntiles, c->dc);
 }
 
 // Ions move about 1e-5 cells per step: binning them every step would copy
@@ -2922,8 +2946,9 @@ void parts_bin(pic_ctx* c) {
   hipMemcpyAsync(c->hmid, c->dc, sizeof(Counters), hipMemcpyDeviceToHost, st);
   hipEventRecord(c->ev_mid, st);
   parts_bin_species(c, 0);
-  bool bin_ions = true;
+  bool bin_ions = true, listed1 = false;
   if (hipEventSynchronize(c->ev_mid) == hipSuccess) {
+    listed1 = c->hmid->err == 0 && c->hmid->n_dead1 <= (unsigned long long)kDeadList;
     const Counters& h = *c->hmid;
     const long long n2 = (long long)h.n[2];
     const long long tail = n2 - c->n_binned[2];
@@ -2935,13 +2960,9 @@ void parts_bin(pic_ctx* c) {
     if (!bin_ions) {
       if (dead > 0) {
         if (c->mixed)
-          k_ion_remove<PartsM><<<1, 1024, 0, st>>>(cur<PartsM>(c, 2), c->key[2],
-                                                   c->dead2, ts_cur(c, 2),
-                                                   c->ntiles, c->dc);
+          remove_listed_t<PartsM>(c, 2, c->dead2, &c->dc->n_dead2, ts_cur(c, 2));
         else
-          k_ion_remove<Parts><<<1, 1024, 0, st>>>(cur<Parts>(c, 2), c->key[2],
-                                                  c->dead2, ts_cur(c, 2),
-                                                  c->ntiles, c->dc);
+          remove_listed_t<Parts>(c, 2, c->dead2, &c->dc->n_dead2, ts_cur(c, 2));
         c->ion_moved_accum += dead;
       }
       // Exact: nothing else changes the ions until the next step.
@@ -2958,11 +2979,19 @@ void parts_bin(pic_ctx* c) {
   // Nothing reads the neutrals by tile (their push streams them, their
   // cell counts are kept from step to step, the event cells are a bit mask
   // in L2), so they are only compacted: a full binning pass of five
-  // million records through the unbinned-list path cost 2.3 ms.
-  if (c->mixed)
+  // million records through the unbinned-list path cost 2.3 ms.  The few
+  // thousand removed this step (ionised, absorbed) are listed, so one
+  // workgroup fills their slots; with more, the scans over all keys do.
+  if (listed1) {
+    if (c->mixed)
+      remove_listed_t<PartsM>(c, 1, c->dead1, &c->dc->n_dead1, nullptr);
+    else
+      remove_listed_t<Parts>(c, 1, c->dead1, &c->dc->n_dead1, nullptr);
+  } else if (c->mixed) {
     compact_neutrals_t<PartsM>(c);
-  else
+  } else {
     compact_neutrals_t<Parts>(c);
+  }
   long long hb[3];
   for (int s = 0; s < 3; ++s) hb[s] = bound(c, s);
   parts_chunks(c, hb);

@@ -164,6 +164,7 @@ size_t carve(pic_ctx* c, char* base) {
   c->ncount = cv.take<int>(c->ncells);
   c->flag = cv.take<uint32_t>((c->ncells + 31) / 32);
   c->cand = cv.take<CandRec>(f.capacity[0]);
+  c->dead1 = cv.take<uint32_t>(kDeadList);
   c->dead2 = cv.take<uint32_t>(kDeadList);
   c->cand_cnt = cv.take<uint32_t>(c->nch_cap + 1);
   c->el_cnt = cv.take<uint32_t>(c->nch_cap + 1);

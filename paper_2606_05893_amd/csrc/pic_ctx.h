@@ -104,6 +104,7 @@ struct pic_ctx {
   long long ion_moved_accum;
   bool ions_binned;          // this step binned them
   pic::Counters* hmid;       // pinned copy of the counters for it
+  uint32_t* dead1;           // indices of this step's removed neutrals
   uint32_t* dead2;           // indices of this step's removed ions
   hipEvent_t ev_mid;
   long long n_start1;        // neutrals at the start of the step's sources

@@ -260,6 +260,7 @@ struct Counters {
   unsigned long long n_tail_cand;   // candidates among unbinned electrons
   unsigned long long n_el_tail;     // elastic collisions among them
   unsigned long long ion_moved;     // binned ions pushed out of their tile
+  unsigned long long n_dead1;       // neutrals removed this step (listed)
   unsigned long long n_dead2;       // ions removed this step (listed)
   unsigned long long sorted_n[3];   // counts after the binning pass
   unsigned long long n_dead;        // removed neutrals (compaction)
