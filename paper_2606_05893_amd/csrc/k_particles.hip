@@ -21,8 +21,13 @@ constexpr int kT = 256;
 // Records per LDS-sorted chunk and the workgroup that sorts it.  The
 // bitonic pass is bound by LDS bandwidth (16-byte records): small chunks
 // spread a list over many CUs, at the cost of two more merge rounds.
-constexpr int kSortChunk = 1024;
+constexpr int kSortChunk = 256;
 constexpr int kSortT = kSortChunk / 2;  // one compare-exchange per thread and stage
+// Segment whose merge rounds run in LDS, in one launch (64 KB of records),
+// and its workgroup (four records per thread).
+constexpr int kMergeSeg = 4096;
+constexpr int kMergeT = 1024;
+static_assert(kMergeSeg % kSortChunk == 0 && kMergeSeg == 4 * kMergeT, "");
 constexpr int kFixedBlocks = 2048;
 
 inline unsigned nblk(long long n, int t = kT) {
@@ -1609,10 +1614,12 @@ __global__ void __launch_bounds__(kT) k_mcc(
 // Sort of a record list by (hi, lo) (keys are unique): every kSortChunk
 // chunk is sorted in LDS by its own workgroup (bitonic), then rounds of
 // pairwise merges place each record at its rank in its own run plus the
-// number of smaller keys in the partner run (binary search).  The host
-// launches the rounds for the list's capacity; the rounds whose run width
-// reaches the list's length do nothing, and a last pass brings the result
-// back into the first buffer when an odd number of rounds ran.
+// number of smaller keys in the partner run (binary search).  The rounds
+// up to kMergeSeg run in LDS, one workgroup per segment, in one launch
+// (the short lists end there); the host launches the wider rounds for the
+// list's capacity, those whose run width reaches the list's length do
+// nothing, and a last pass brings the result back into the first buffer
+// when an odd number of them ran.
 __global__ void __launch_bounds__(kSortT) k_sort_chunks(
     Rec* __restrict__ a, Rec* __restrict__ tmp,
     const unsigned long long* __restrict__ count, long long cap) {
@@ -1679,6 +1686,67 @@ __device__ __forceinline__ void merge_one(const Rec* __restrict__ src,
   dst[pos] = x;
 }
 
+// The merge rounds of widths kSortChunk .. kMergeSeg / 2 of one segment,
+// in LDS: each round reads every record and its new place (merge_one's
+// rule), then, after a barrier, writes them back.
+__global__ void __launch_bounds__(kMergeT) k_merge_lds(
+    Rec* __restrict__ a, const unsigned long long* __restrict__ count,
+    long long cap) {
+  __shared__ Rec s[kMergeSeg];
+  long long n = (long long)*count;
+  if (n > cap) n = cap;
+  const long long base = (long long)blockIdx.x * kMergeSeg;
+  if (base >= n || n - base <= kSortChunk) return;
+  const int m = (int)(n - base < kMergeSeg ? n - base : kMergeSeg);
+  const int tid = threadIdx.x;
+  constexpr int kPer = kMergeSeg / kMergeT;
+  Rec r[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = tid + k * kMergeT;
+    if (i < m) r[k] = a[base + i];
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = tid + k * kMergeT;
+    if (i < m) s[i] = r[k];
+  }
+  __syncthreads();
+  for (int w = kSortChunk; w < m; w *= 2) {
+    int pos[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int i = tid + k * kMergeT;
+      pos[k] = 0;
+      if (i >= m) continue;
+      const int a0 = i / (2 * w) * (2 * w);
+      const int a1 = a0 + w < m ? a0 + w : m;
+      const int b1 = a1 + w < m ? a1 + w : m;
+      const Rec x = s[i];
+      r[k] = x;
+      int lo, hi, own;
+      if (i < a1) { lo = a1; hi = b1; own = i - a0; }
+      else        { lo = a0; hi = a1; own = i - a1; }
+      const int first = lo;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rec_less(s[mid], x)) lo = mid + 1; else hi = mid;
+      }
+      pos[k] = a0 + own + (lo - first);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kPer; ++k)
+      if (tid + k * kMergeT < m) s[pos[k]] = r[k];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int i = tid + k * kMergeT;
+    if (i < m) a[base + i] = s[i];
+  }
+}
+
 __global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst,
                               const unsigned long long* __restrict__ count,
                               long long cap, long long w) {
@@ -1698,7 +1766,7 @@ __global__ void k_copy_recs(const Rec* __restrict__ src, Rec* __restrict__ dst,
   long long n = (long long)*count;
   if (n > cap) n = cap;
   int rounds = 0;
-  for (long long w = kSortChunk; w < n; w *= 2) ++rounds;
+  for (long long w = kMergeSeg; w < n; w *= 2) ++rounds;
   if ((rounds & 1) == 0) return;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)
@@ -2294,13 +2362,16 @@ void sort_records(pic_ctx* c, Rec* a, Rec* tmp,
   hipStream_t st = c->stream;
   const long long nchunk = (cap + kSortChunk - 1) / kSortChunk;
   k_sort_chunks<<<(unsigned)nchunk, kSortT, 0, st>>>(a, tmp, count, cap);
+  if (cap > kSortChunk)
+    k_merge_lds<<<(unsigned)((cap + kMergeSeg - 1) / kMergeSeg), kMergeT, 0, st>>>(
+        a, count, cap);
   Rec* src = a;
   Rec* dst = tmp;
-  for (long long w = kSortChunk; w < cap; w *= 2) {
+  for (long long w = kMergeSeg; w < cap; w *= 2) {
     k_merge_round<<<nblk(cap), kT, 0, st>>>(src, dst, count, cap, w);
     Rec* t = src; src = dst; dst = t;
   }
-  if (cap > kSortChunk) k_copy_recs<<<256, kT, 0, st>>>(tmp, a, count, cap);
+  if (cap > kMergeSeg) k_copy_recs<<<256, kT, 0, st>>>(tmp, a, count, cap);
 }
 
 double qm_dt(int s, double dt) {

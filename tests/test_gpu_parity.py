@@ -285,9 +285,10 @@ def test_out_of_domain_load_rejected(gpu_lib):
 
 def test_absorbed_list_longer_than_a_sort_chunk(gpu_lib):
     """About 20 000 electrons and ions cross the cathode in one step: the
-    cathode list (many times longer than one 1024-record sort chunk, so the merge
-    rounds run) comes back sorted by (species, id) and equal to the
-    oracle's, crossing points and velocities included."""
+    cathode list (several 4096-record segments, the last one ragged, so the
+    LDS merge rounds and the global ones both run) comes back sorted by
+    (species, id) and equal to the oracle's, crossing points and
+    velocities included."""
     p = small_c2(n_e=10, n_ion=10, n_n=10)
     p["sources"] = {}
     p["collisions"] = dict(p["collisions"], enabled=False)
