@@ -2952,17 +2952,21 @@ void parts_chunks(pic_ctx* c, const long long hb[3]) {
 // listed index below n - D is filled by one of the live particles at or
 // above it (equally many), and the tile ranges ts, if given, are cut at
 // n - D.  A filled slot may hold a particle of another tile; the pushes and
-// the deposit treat such particles correctly.  One workgroup.
-template <class PT>
+// the deposit treat such particles correctly.  One workgroup pairs the
+// holes with the movers; the copies are k_remove_pairs'.
 __global__ void __launch_bounds__(1024) k_remove_listed(
-    PT p, uint32_t* __restrict__ key, const uint32_t* __restrict__ list,
+    const uint32_t* __restrict__ key, const uint32_t* __restrict__ list,
     const unsigned long long* __restrict__ ndead, int s,
-    uint32_t* __restrict__ ts, long long nt, Counters* dc) {
+    uint32_t* __restrict__ ts, long long nt, uint2* __restrict__ pairs,
+    Counters* dc) {
   __shared__ uint32_t holes[kDeadList], movers[kDeadList];
   __shared__ unsigned nh, nm;
   const long long n = (long long)dc->n[s];
   const long long D = (long long)*ndead;
-  if (D > kDeadList || D > n) return;   // (the caller bins instead)
+  if (D > kDeadList || D > n) {   // (the caller bins instead)
+    if (threadIdx.x == 0) dc->n_pairs = 0;
+    return;
+  }
   const long long keep = n - D;
   if (threadIdx.x == 0) nh = nm = 0;
   __syncthreads();
@@ -2973,13 +2977,10 @@ __global__ void __launch_bounds__(1024) k_remove_listed(
   for (long long q = keep + threadIdx.x; q < n; q += blockDim.x)
     if (key[q] != kDead) movers[atomicAdd(&nm, 1u)] = (uint32_t)q;
   __syncthreads();
-  // Holes lie below keep and movers at or above it: no copy reads a slot
-  // another writes.
+  // The copies run in k_remove_pairs, spread over the GPU.
   const unsigned np = nh < nm ? nh : nm;
-  for (unsigned j = threadIdx.x; j < np; j += blockDim.x) {
-    Acc<PT>::copy(p, movers[j], p, holes[j]);
-    key[holes[j]] = key[movers[j]];
-  }
+  for (unsigned j = threadIdx.x; j < np; j += blockDim.x)
+    pairs[j] = make_uint2(holes[j], movers[j]);
   if (ts)
     for (long long t = threadIdx.x; t <= nt; t += blockDim.x)
       if ((long long)ts[t] > keep) ts[t] = (uint32_t)keep;
@@ -2987,14 +2988,30 @@ __global__ void __launch_bounds__(1024) k_remove_listed(
     if (nh != nm) atomicOr(&dc->err, kErrCapacity);  // (cannot happen)
     dc->n[s] = (unsigned long long)keep;
     dc->sorted_n[s] = (unsigned long long)keep;
+    dc->n_pairs = np;
   }
+}
+
+// Mover j into hole j.  Holes lie below the new count and movers at or
+// above it: no copy reads a slot another writes.
+template <class PT>
+__global__ void k_remove_pairs(PT p, uint32_t* __restrict__ key,
+                               const uint2* __restrict__ pairs,
+                               const Counters* __restrict__ dc) {
+  const unsigned j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= dc->n_pairs) return;
+  const uint2 hm = pairs[j];
+  Acc<PT>::copy(p, hm.y, p, hm.x);
+  key[hm.x] = key[hm.y];
 }
 
 template <class PT>
 void remove_listed_t(pic_ctx* c, int s, uint32_t* list,
                      const unsigned long long* ndead, uint32_t* ts) {
-  k_remove_listed<PT><<<1, 1024, 0, c->stream>>>(
-      cur<PT>(c, s), c->key[s], list, ndead, s, ts, c->ntiles, c->dc);
+  k_remove_listed<<<1, 1024, 0, c->stream>>>(c->key[s], list, ndead, s, ts,
+                                             c->ntiles, c->rm_pairs, c->dc);
+  k_remove_pairs<PT><<<kDeadList / 64, 64, 0, c->stream>>>(
+      cur<PT>(c, s), c->key[s], c->rm_pairs, c->dc);
 }
 
 // Ions move about 1e-5 cells per step: binning them every step would copy

@@ -166,6 +166,7 @@ size_t carve(pic_ctx* c, char* base) {
   c->cand = cv.take<CandRec>(f.capacity[0]);
   c->dead1 = cv.take<uint32_t>(kDeadList);
   c->dead2 = cv.take<uint32_t>(kDeadList);
+  c->rm_pairs = cv.take<uint2>(kDeadList);
   c->cand_cnt = cv.take<uint32_t>(c->nch_cap + 1);
   c->el_cnt = cv.take<uint32_t>(c->nch_cap + 1);
   c->chunks = cv.take<uint2>(c->nch_cap);

@@ -106,6 +106,7 @@ struct pic_ctx {
   pic::Counters* hmid;       // pinned copy of the counters for it
   uint32_t* dead1;           // indices of this step's removed neutrals
   uint32_t* dead2;           // indices of this step's removed ions
+  uint2* rm_pairs;           // (hole, mover) slots of a listed removal
   hipEvent_t ev_mid;
   long long n_start1;        // neutrals at the start of the step's sources
   uint32_t* flag;            // cells holding ionisation events (one bit each)

@@ -262,6 +262,7 @@ struct Counters {
   unsigned long long ion_moved;     // binned ions pushed out of their tile
   unsigned long long n_dead1;       // neutrals removed this step (listed)
   unsigned long long n_dead2;       // ions removed this step (listed)
+  unsigned long long n_pairs;       // (hole, mover) pairs of a listed removal
   unsigned long long sorted_n[3];   // counts after the binning pass
   unsigned long long n_dead;        // removed neutrals (compaction)
   unsigned long long n_holes;       // ... of them below the new count
