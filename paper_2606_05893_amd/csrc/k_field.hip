@@ -8,6 +8,7 @@
 // matrix cores.  The red-black Gauss-Seidel smoother is generic in the
 // precision (FP64, or FP32 for the correction solve of the mixed form).
 #include <algorithm>
+#include <cstring>
 #include <type_traits>
 
 #include "pic_ctx.h"
@@ -2075,10 +2076,14 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
       k_final<<<1, 1024, 0, st>>>(c->partials, c->qpartials, kRedBlocks,
                                   c->dc, 1, c->cfg.rel_tol);
     }
-    hipMemcpyAsync(&c->hc.vcycles, &c->dc->vcycles,
-                   sizeof(Counters) - offsetof(Counters, vcycles),
-                   hipMemcpyDeviceToHost, st);
-    hipStreamSynchronize(st);
+    constexpr size_t kOff = offsetof(Counters, vcycles);
+    hipMemcpyAsync(reinterpret_cast<char*>(c->hpin) + kOff,
+                   reinterpret_cast<const char*>(c->dc) + kOff,
+                   sizeof(Counters) - kOff, hipMemcpyDeviceToHost, st);
+    stream_wait(c);
+    std::memcpy(reinterpret_cast<char*>(&c->hc) + kOff,
+                reinterpret_cast<const char*>(c->hpin) + kOff,
+                sizeof(Counters) - kOff);
     if (c->hc.done || launched >= c->cfg.max_vcycles) break;
     batch = 1;
   }

@@ -251,12 +251,12 @@ void derive(pic_ctx* c) {
 }
 
 pic_status sync_counters(pic_ctx* c) {
-  if (!hip_ok(c, hipMemcpyAsync(&c->hc, c->dc, sizeof(Counters),
+  if (!hip_ok(c, hipMemcpyAsync(c->hpin, c->dc, sizeof(Counters),
                                 hipMemcpyDeviceToHost, c->stream),
               "counter readback"))
     return PIC_ERR_HIP;
-  if (!hip_ok(c, hipStreamSynchronize(c->stream), "stream synchronise"))
-    return PIC_ERR_HIP;
+  if (!hip_ok(c, stream_wait(c), "stream synchronise")) return PIC_ERR_HIP;
+  c->hc = *c->hpin;
   return PIC_OK;
 }
 
@@ -388,6 +388,8 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->ions_binned = true;
   c->hmid = nullptr;
   c->ev_mid = nullptr;
+  c->hpin = nullptr;
+  c->ev_sync = nullptr;
   c->next_id = 0;
   c->step = 0;
   c->queue_used = 0;
@@ -409,10 +411,17 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
       !hip_ok(c, hipHostMalloc(reinterpret_cast<void**>(&c->hmid), sizeof(Counters),
                                hipHostMallocDefault),
               "pinned counters") ||
+      !hip_ok(c, hipHostMalloc(reinterpret_cast<void**>(&c->hpin), sizeof(Counters),
+                               hipHostMallocDefault),
+              "pinned counters") ||
       !hip_ok(c, hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming),
+              "event create") ||
+      !hip_ok(c, hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming),
               "event create")) {
     if (c->hmid) hipHostFree(c->hmid);
+    if (c->hpin) hipHostFree(c->hpin);
     if (c->ev_mid) hipEventDestroy(c->ev_mid);
+    if (c->ev_sync) hipEventDestroy(c->ev_sync);
     delete c;
     return PIC_ERR_HIP;
   }
@@ -423,7 +432,9 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
 void pic_destroy(pic_ctx* c) {
   if (!c) return;
   if (c->hmid) hipHostFree(c->hmid);
+  if (c->hpin) hipHostFree(c->hpin);
   if (c->ev_mid) hipEventDestroy(c->ev_mid);
+  if (c->ev_sync) hipEventDestroy(c->ev_sync);
   if (c->ev_made)
     for (int p = 0; p < PIC_NPHASES; ++p)
       for (int i = 0; i < pic_ctx::kTimeIv; ++i)

@@ -108,6 +108,8 @@ struct pic_ctx {
   uint32_t* dead2;           // indices of this step's removed ions
   uint2* rm_pairs;           // (hole, mover) slots of a listed removal
   hipEvent_t ev_mid;
+  pic::Counters* hpin;       // pinned landing buffer of the counter readbacks
+  hipEvent_t ev_sync;        // polled by stream_wait
   long long n_start1;        // neutrals at the start of the step's sources
   uint32_t* flag;            // cells holding ionisation events (one bit each)
   pic::CandRec* cand;        // null-collision candidates
@@ -168,6 +170,17 @@ struct pic_ctx {
 };
 
 namespace pic {
+
+// Wait for everything queued on the context's stream by polling an event:
+// a blocking wait wakes the host some ten microseconds after the GPU is
+// done, and the GPU stays idle until the host queues more work.
+inline hipError_t stream_wait(pic_ctx* c) {
+  hipError_t e = hipEventRecord(c->ev_sync, c->stream);
+  if (e != hipSuccess) return e;
+  while ((e = hipEventQuery(c->ev_sync)) == hipErrorNotReady) {
+  }
+  return e;
+}
 
 // Record the start (begin = true) or end of a timed phase.
 inline void tmark(pic_ctx* c, int ph, bool begin) {
