@@ -322,10 +322,11 @@ class Pic:
         n = ab.n
         out = {"n": n}
         if n > 0:
-            out["species"] = _wrap_dev(ab.species, n, torch.int32)
-            out["id"] = _wrap_dev(ab.id, n, torch.int64)
-            out["pos"] = _wrap_dev(ab.pos, 3 * n, torch.float64).reshape(3, n).t()
-            out["vel"] = _wrap_dev(ab.vel, 3 * n, torch.float64).reshape(3, n).t()
+            st = self.stream.cuda_stream
+            out["species"] = _wrap_dev(ab.species, n, torch.int32, st)
+            out["id"] = _wrap_dev(ab.id, n, torch.int64, st)
+            out["pos"] = _wrap_dev(ab.pos, 3 * n, torch.float64, st).reshape(3, n).t()
+            out["vel"] = _wrap_dev(ab.vel, 3 * n, torch.float64, st).reshape(3, n).t()
         return out
 
     def advance(self, dt):
@@ -404,27 +405,31 @@ def _struct_dict(s):
     return d
 
 
-def _wrap_dev(ptr, n, dtype):
-    """Copy n elements of library-owned device memory into a torch tensor."""
+def _wrap_dev(ptr, n, dtype, stream):
+    """Copy n elements of library-owned device memory into a torch tensor,
+    queued on the context's stream (so before the next step overwrites
+    them, and before any later torch work on that stream reads them)."""
     out = torch.empty(n, dtype=dtype, device="cuda")
     nbytes = n * out.element_size()
-    _hip_d2d(out.data_ptr(), ptr, nbytes)
+    _hip_d2d(out.data_ptr(), ptr, nbytes, stream)
     return out
 
 
 _hip = None
 
 
-def _hip_d2d(dst, src, nbytes):
+def _hip_d2d(dst, src, nbytes, stream):
     global _hip
     if _hip is None:
         _hip = ctypes.CDLL("libamdhip64.so")
-        _hip.hipMemcpy.restype = ctypes.c_int
-        _hip.hipMemcpy.argtypes = [_c_p, _c_p, ctypes.c_size_t, ctypes.c_int]
-    rc = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src),
-                        ctypes.c_size_t(nbytes), 3)   # hipMemcpyDeviceToDevice
+        _hip.hipMemcpyAsync.restype = ctypes.c_int
+        _hip.hipMemcpyAsync.argtypes = [_c_p, _c_p, ctypes.c_size_t,
+                                        ctypes.c_int, _c_p]
+    rc = _hip.hipMemcpyAsync(ctypes.c_void_p(dst), ctypes.c_void_p(src),
+                             ctypes.c_size_t(nbytes), 3,  # device to device
+                             ctypes.c_void_p(stream))
     if rc != 0:
-        raise RuntimeError(f"hipMemcpy failed: {rc}")
+        raise RuntimeError(f"hipMemcpyAsync failed: {rc}")
 
 
 UNET_EXPORTS = {
