@@ -329,37 +329,71 @@ __global__ void k_fn_count(const TE* __restrict__ Ez, unsigned* __restrict__ cnt
   cnt[t] = c;
 }
 
-// Exclusive scan of n values in one workgroup (n <= 1024 * 256); writes
-// out[0..n] with out[n] = total.
-__global__ void k_scan1(const unsigned* __restrict__ in, unsigned* __restrict__ out,
-                        long long n) {
-  __shared__ unsigned s[1024];
-  const int tid = threadIdx.x;
-  const long long per = (n + 1023) / 1024;
-  const long long b0 = tid * per;
-  unsigned sum = 0;
-  for (long long q = 0; q < per; ++q) {
-    const long long i = b0 + q;
-    if (i < n) sum += in[i];
+// Exclusive scan of n values in one workgroup of 1024 threads; writes
+// out[0..n] with out[n] = total.  Wave w takes the values [w * span,
+// (w + 1) * span), span a multiple of 64: a first pass sums them, the
+// waves' totals give each wave its offset, and a second pass scans them
+// 64 at a time (shuffles) with a running carry.  Every access is
+// coalesced, and the loads of each pass go out kScanB at a time (clamped
+// to a valid index), not as a chain.
+constexpr int kScanB = 16;
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
   }
-  s[tid] = sum;
+  return v;
+}
+
+__global__ void __launch_bounds__(1024) k_scan1(const unsigned* __restrict__ in,
+                                                unsigned* __restrict__ out,
+                                                long long n) {
+  __shared__ unsigned wsum[16];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const long long span = ((n + 15) / 16 + 63) / 64 * 64;
+  const long long w0 = w * span < n ? w * span : n;
+  const long long w1 = w0 + span < n ? w0 + span : n;
+  unsigned tot = 0;
+  for (long long q0 = w0; q0 < w1; q0 += 64 * kScanB) {
+    unsigned v[kScanB];
+#pragma unroll
+    for (int k = 0; k < kScanB; ++k) {
+      const long long q = q0 + 64 * k + lane;
+      v[k] = in[q < w1 ? q : w1 - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kScanB; ++k)
+      tot += q0 + 64 * k + lane < w1 ? v[k] : 0u;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+  if (lane == 0) wsum[w] = tot;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const unsigned v = tid >= o ? s[tid - o] : 0u;
-    __syncthreads();
-    s[tid] += v;
-    __syncthreads();
+  unsigned carry = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    carry += k < w ? wsum[k] : 0u;
+    all += wsum[k];
   }
-  unsigned run = tid ? s[tid - 1] : 0u;
-  for (long long q = 0; q < per; ++q) {
-    const long long i = b0 + q;
-    if (i < n) {
-      const unsigned v = in[i];
-      out[i] = run;
-      run += v;
+  for (long long q0 = w0; q0 < w1; q0 += 64 * kScanB) {
+    unsigned v[kScanB];
+#pragma unroll
+    for (int k = 0; k < kScanB; ++k) {
+      const long long q = q0 + 64 * k + lane;
+      v[k] = in[q < w1 ? q : w1 - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kScanB; ++k) {
+      if (q0 + 64 * k >= w1) break;  // (wave-uniform)
+      const long long q = q0 + 64 * k + lane;
+      const unsigned x = q < w1 ? v[k] : 0u;
+      const unsigned incl = wave_incl_scan(x, lane);
+      if (q < w1) out[q] = carry + incl - x;
+      carry += __shfl(incl, 63, 64);
     }
   }
-  if (tid == 1023) out[n] = s[1023];
+  if (tid == 0) out[n] = all;
 }
 
 template <class PT>
