@@ -1488,16 +1488,33 @@ __global__ void __launch_bounds__(kT) k_push_neutral_m(
 }
 
 // Sum of two partial arrays (fixed order), times a factor; the first holds
-// *na_dev entries when na_dev is given (chunk partials), else na.
-__global__ void k_sum_partials(const double* __restrict__ a, long long na,
-                               const unsigned* __restrict__ na_dev,
-                               const double* __restrict__ b, long long nb,
-                               double factor, double* out) {
+// *na_dev entries when na_dev is given (chunk partials), else na.  Thread t
+// adds entries t, t + 1024, ... in that order; the loads go out kScanB at a
+// time (clamped to a valid entry), so they are not a chain.
+__device__ __forceinline__ double strided_sum(const double* __restrict__ a,
+                                              long long n, double acc) {
+  for (long long q0 = threadIdx.x; q0 < n; q0 += (long long)kScanB * 1024) {
+    double v[kScanB];
+#pragma unroll
+    for (int k = 0; k < kScanB; ++k) {
+      const long long q = q0 + (long long)k * 1024;
+      v[k] = a[q < n ? q : n - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kScanB; ++k)
+      if (q0 + (long long)k * 1024 < n) acc = acc + v[k];
+  }
+  return acc;
+}
+
+__global__ void __launch_bounds__(1024) k_sum_partials(
+    const double* __restrict__ a, long long na,
+    const unsigned* __restrict__ na_dev, const double* __restrict__ b,
+    long long nb, double factor, double* out) {
   __shared__ double s[1024];
   if (na_dev) na = *na_dev;
-  double acc = 0.0;
-  for (long long q = threadIdx.x; q < na; q += blockDim.x) acc = acc + a[q];
-  for (long long q = threadIdx.x; q < nb; q += blockDim.x) acc = acc + b[q];
+  double acc = strided_sum(a, na, 0.0);
+  acc = strided_sum(b, nb, acc);
   s[threadIdx.x] = acc;
   __syncthreads();
   for (int o = 512; o > 0; o >>= 1) {
