@@ -1507,6 +1507,24 @@ __device__ __forceinline__ double strided_sum(const double* __restrict__ a,
   return acc;
 }
 
+// Integer counterpart: thread t's share of the sum of n counts.
+__device__ __forceinline__ unsigned long long strided_count(
+    const uint32_t* __restrict__ a, long long n) {
+  unsigned long long acc = 0;
+  for (long long q0 = threadIdx.x; q0 < n; q0 += (long long)kScanB * 1024) {
+    uint32_t v[kScanB];
+#pragma unroll
+    for (int k = 0; k < kScanB; ++k) {
+      const long long q = q0 + (long long)k * 1024;
+      v[k] = a[q < n ? q : n - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kScanB; ++k)
+      acc += q0 + (long long)k * 1024 < n ? v[k] : 0u;
+  }
+  return acc;
+}
+
 __global__ void __launch_bounds__(1024) k_sum_partials(
     const double* __restrict__ a, long long na,
     const unsigned* __restrict__ na_dev, const double* __restrict__ b,
@@ -1991,7 +2009,7 @@ __global__ void __launch_bounds__(kT) k_ionise(PT pe, PT pn, PT pi, uint32_t* __
 
 // Clears the event-cell flags, adds the matched ionisations to the counts
 // and sums the per-tile elastic counts.
-__global__ void k_ionise_commit(Counters* dc, const Rec* __restrict__ ev,
+__global__ void __launch_bounds__(1024) k_ionise_commit(Counters* dc, const Rec* __restrict__ ev,
                                 uint32_t* __restrict__ flag, long long cap,
                                 long long cap_e, long long cap_i,
                                 const uint32_t* __restrict__ el_cnt,
@@ -2002,9 +2020,8 @@ __global__ void k_ionise_commit(Counters* dc, const Rec* __restrict__ ev,
   long long ne = (long long)dc->n_events;
   if (ne > cap) ne = cap;
   for (long long e = threadIdx.x; e < ne; e += blockDim.x) flag[ev[e].hi >> 5] = 0u;
-  unsigned long long a = 0, b = 0;
-  for (long long q = threadIdx.x; q < ntiles; q += blockDim.x) a += el_cnt[q];
-  for (long long q = threadIdx.x; q < ntiles; q += blockDim.x) b += cand_cnt[q];
+  const unsigned long long a = strided_count(el_cnt, ntiles);
+  const unsigned long long b = strided_count(cand_cnt, ntiles);
   s[threadIdx.x] = a;
   s2[threadIdx.x] = b;
   __syncthreads();
