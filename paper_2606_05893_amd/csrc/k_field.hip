@@ -822,14 +822,14 @@ __global__ void __launch_bounds__(1024) k_mg_tail(TailLevels A,
 // every node (the Dirichlet face values are the same in both, so they stay),
 // and the history becomes phi_{n-1}.  Without a valid history the history
 // is only filled.
-__global__ void k_extrap(double* __restrict__ u, double* __restrict__ hist,
-                         long long n, int valid) {
+// hist <- 2 u - hist, the extrapolated start; the host then swaps the two
+// buffers, so the old potential becomes the history (two arrays read and
+// one written, where updating both in place writes two).
+__global__ void k_extrap(const double* __restrict__ u, double* __restrict__ hist,
+                         long long n) {
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n;
-       t += (long long)gridDim.x * blockDim.x) {
-    const double a = u[t];
-    if (valid) u[t] = 2.0 * a - hist[t];
-    hist[t] = a;
-  }
+       t += (long long)gridDim.x * blockDim.x)
+    hist[t] = 2.0 * u[t] - hist[t];
 }
 
 // u += e on the level-0 unknowns (mixed form: FP64 correction accumulation).
@@ -2100,8 +2100,14 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
 }
 
 void field_extrapolate(pic_ctx* c) {
-  k_extrap<<<kRedBlocks, kThreads, 0, c->stream>>>(
-      c->lev[0].u, c->phi_hist, c->nnodes, c->hist_valid ? 1 : 0);
+  if (c->hist_valid) {
+    k_extrap<<<kRedBlocks, kThreads, 0, c->stream>>>(c->lev[0].u, c->phi_hist,
+                                                     c->nnodes);
+    std::swap(c->lev[0].u, c->phi_hist);
+  } else {
+    hipMemcpyAsync(c->phi_hist, c->lev[0].u, c->nnodes * sizeof(double),
+                   hipMemcpyDeviceToDevice, c->stream);
+  }
 }
 
 void field_warm_target(pic_ctx* c, float* t) {
