@@ -75,46 +75,65 @@ __global__ void k_rhs(const long long* __restrict__ acc,
   double s2 = 0.0;
   long long sqs = 0;
   const long long n = L.nxy * (L.nz + 1);
-  for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-       idx < n; idx += (long long)gridDim.x * blockDim.x) {
-    const int k = (int)(idx / L.nxy);
-    double v = 0.0;
-    if (from_rho) {
-      v = rho[idx] * scale;
-    } else {
-      const long long a = acc[idx];
-      sqs += a;
-      if (field_solve) v = (double)a * scale;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  // Node indices fit 32 bits: the plane index by 32-bit division.
+  const unsigned nxy = (unsigned)L.nxy;
+  // Four nodes per round, their loads issued together (clamped), then
+  // processed in index order as a plain strided loop would.
+  constexpr int kU = 4;
+  for (long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+       i0 < n; i0 += kU * stride) {
+    long long av[kU];
+    double rv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      long long q = i0 + u * stride;
+      q = q < n ? q : n - 1;
+      if (from_rho) rv[u] = rho[q]; else av[u] = acc[q];
     }
-    bool unknown = true;
-    if (k == 0) {
-      if (L.bc_lo == PIC_BC_DIRICHLET) {
-        unknown = false;
-        phi[idx] = v_lo;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const long long idx = i0 + u * stride;
+      if (idx >= n) break;
+      const int k = (int)((unsigned)idx / nxy);
+      double v = 0.0;
+      if (from_rho) {
+        v = rv[u] * scale;
       } else {
-        if (!from_rho) v = v * 2.0;
-        v = v - (2.0 * dx) * v_lo;
+        const long long a = av[u];
+        sqs += a;
+        if (field_solve) v = (double)a * scale;
       }
-    }
-    if (k == L.nz) {
-      if (L.bc_hi == PIC_BC_DIRICHLET) {
-        unknown = false;
-        phi[idx] = v_hi;
-      } else {
-        if (!from_rho) v = v * 2.0;
-        v = v + (2.0 * dx) * v_hi;
+      bool unknown = true;
+      if (k == 0) {
+        if (L.bc_lo == PIC_BC_DIRICHLET) {
+          unknown = false;
+          phi[idx] = v_lo;
+        } else {
+          if (!from_rho) v = v * 2.0;
+          v = v - (2.0 * dx) * v_lo;
+        }
       }
+      if (k == L.nz) {
+        if (L.bc_hi == PIC_BC_DIRICHLET) {
+          unknown = false;
+          phi[idx] = v_hi;
+        } else {
+          if (!from_rho) v = v * 2.0;
+          v = v + (2.0 * dx) * v_hi;
+        }
+      }
+      if (!unknown) v = 0.0;
+      // The Dirichlet face values sit in phi's face planes, where the stencil
+      // reads them, so they stay out of the stored right-hand side; ||b|| is
+      // the norm of the system with them moved to the right (the relative
+      // residual's denominator).
+      b[idx] = v;
+      double vb = v;
+      if (k == 1 && L.bc_lo == PIC_BC_DIRICHLET) vb = vb + v_lo;
+      if (k == L.nz - 1 && L.bc_hi == PIC_BC_DIRICHLET) vb = vb + v_hi;
+      s2 = s2 + vb * vb;
     }
-    if (!unknown) v = 0.0;
-    // The Dirichlet face values sit in phi's face planes, where the stencil
-    // reads them, so they stay out of the stored right-hand side; ||b|| is
-    // the norm of the system with them moved to the right (the relative
-    // residual's denominator).
-    b[idx] = v;
-    double vb = v;
-    if (k == 1 && L.bc_lo == PIC_BC_DIRICHLET) vb = vb + v_lo;
-    if (k == L.nz - 1 && L.bc_hi == PIC_BC_DIRICHLET) vb = vb + v_hi;
-    s2 = s2 + vb * vb;
   }
   sb[threadIdx.x] = s2;
   sq[threadIdx.x] = sqs;
