@@ -259,7 +259,21 @@ class Pic:
             raise PicError(status, msg)
 
     def _call(self, name, *args):
+        # Inputs prepared on the caller's current stream are complete before
+        # the context's stream reads them.
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
         self._check(getattr(self.lib, name)(self.ctx, *args), self.ctx)
+
+    def _hand_over(self, *tensors):
+        """Tensors allocated and filled on the context's stream become safe
+        to use (and to free) on the caller's current stream."""
+        cur = torch.cuda.current_stream()
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+            for t in tensors:
+                t.record_stream(cur)
 
     def set_collisions(self, d):
         self._coll = make_collisions(d)
@@ -288,21 +302,26 @@ class Pic:
 
     def read(self, species):
         n = self.count(species)
-        pos = torch.empty((3, max(n, 1)), dtype=torch.float64, device="cuda")
-        vel = torch.empty_like(pos)
-        ids = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+        with torch.cuda.stream(self.stream):
+            pos = torch.empty((3, max(n, 1)), dtype=torch.float64,
+                              device="cuda")
+            vel = torch.empty_like(pos)
+            ids = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
         got = _c_i64()
         self._call("pic_read_particles", int(species), n, _ptr(pos), _ptr(vel),
                    _ptr(ids), ctypes.byref(got))
+        self._hand_over(pos, vel, ids)
         return (pos[:, :n].t().contiguous(), vel[:, :n].t().contiguous(),
                 ids[:n])
 
     def read_fields(self):
         shp = self.grid_shape
-        acc = torch.empty(shp, dtype=torch.int64, device="cuda")
-        phi = torch.empty(shp, dtype=torch.float64, device="cuda")
-        E = torch.empty((3,) + shp, dtype=torch.float64, device="cuda")
+        with torch.cuda.stream(self.stream):
+            acc = torch.empty(shp, dtype=torch.int64, device="cuda")
+            phi = torch.empty(shp, dtype=torch.float64, device="cuda")
+            E = torch.empty((3,) + shp, dtype=torch.float64, device="cuda")
         self._call("pic_read_fields", _ptr(acc), _ptr(phi), _ptr(E))
+        self._hand_over(acc, phi, E)
         return acc, phi, E.permute(1, 2, 3, 0).contiguous()
 
     def deposit(self):
@@ -323,10 +342,16 @@ class Pic:
         out = {"n": n}
         if n > 0:
             st = self.stream.cuda_stream
-            out["species"] = _wrap_dev(ab.species, n, torch.int32, st)
-            out["id"] = _wrap_dev(ab.id, n, torch.int64, st)
-            out["pos"] = _wrap_dev(ab.pos, 3 * n, torch.float64, st).reshape(3, n).t()
-            out["vel"] = _wrap_dev(ab.vel, 3 * n, torch.float64, st).reshape(3, n).t()
+            with torch.cuda.stream(self.stream):
+                sp = _wrap_dev(ab.species, n, torch.int32, st)
+                ids = _wrap_dev(ab.id, n, torch.int64, st)
+                pos = _wrap_dev(ab.pos, 3 * n, torch.float64, st)
+                vel = _wrap_dev(ab.vel, 3 * n, torch.float64, st)
+            self._hand_over(sp, ids, pos, vel)
+            out["species"] = sp
+            out["id"] = ids
+            out["pos"] = pos.reshape(3, n).t()
+            out["vel"] = vel.reshape(3, n).t()
         return out
 
     def advance(self, dt):
@@ -372,9 +397,12 @@ class Pic:
         """(input (nz, ny, nx, 2), target (nz, ny, nx)) FP32 of the last
         recorded solve."""
         nz, ny, nx = self.p["nz"], self.p["ny"], self.p["nx"]
-        x = torch.empty((nz, ny, nx, 2), dtype=torch.float32, device="cuda")
-        t = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+        with torch.cuda.stream(self.stream):
+            x = torch.empty((nz, ny, nx, 2), dtype=torch.float32,
+                            device="cuda")
+            t = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
         self._call("pic_warm_pair", _ptr(x), _ptr(t))
+        self._hand_over(x, t)
         return x, t
 
     def checkpoint(self):
@@ -408,7 +436,8 @@ def _struct_dict(s):
 def _wrap_dev(ptr, n, dtype, stream):
     """Copy n elements of library-owned device memory into a torch tensor,
     queued on the context's stream (so before the next step overwrites
-    them, and before any later torch work on that stream reads them)."""
+    them).  The caller allocates under that stream (torch.cuda.stream) and
+    hands the tensor over to its own stream afterwards."""
     out = torch.empty(n, dtype=dtype, device="cuda")
     nbytes = n * out.element_size()
     _hip_d2d(out.data_ptr(), ptr, nbytes, stream)
