@@ -396,9 +396,75 @@ def qm_dt(species, dt):
     return (q / C.MASS[species]) * dt
 
 
-def push(sp, species, E, grid, dt):
-    """Leapfrog push of one species in place; returns (cathode, anode) masks
-    and the cathode crossing points (x, y) of absorbed particles.
+def sphere_hit(x0, y0, z0, vx, vy, vz, dt, sph, grid):
+    """Does the straight path x0 + v t, 0 <= t <= dt, of a particle touch
+    the closed ball of a nanoparticle (Appendix A: electrons that hit an NP
+    heat it)?  x and y use the nearest periodic image of the centre.
+
+    With d = x0 - c and s = v dt the path is d + tau s, tau in [0, 1]; it
+    touches the ball if it starts inside (|d|^2 <= R^2), or moves towards
+    the centre (d.s < 0) with a real root of |d + tau s|^2 = R^2 whose
+    smaller value tau_in = (-(d.s) - sqrt((d.s)^2 - |s|^2 (|d|^2 - R^2)))
+    / |s|^2 is at most 1.
+    """
+    dxx = x0 - sph["cx"]
+    dyy = y0 - sph["cy"]
+    hx, hy = 0.5 * grid.lx, 0.5 * grid.ly
+    dxx = np.where(dxx > hx, dxx - grid.lx, np.where(dxx < -hx, dxx + grid.lx, dxx))
+    dyy = np.where(dyy > hy, dyy - grid.ly, np.where(dyy < -hy, dyy + grid.ly, dyy))
+    dzz = z0 - sph["cz"]
+    sx, sy, sz = vx * dt, vy * dt, vz * dt
+    r2 = sph["radius"] * sph["radius"]
+    c0 = ((dxx * dxx + dyy * dyy) + dzz * dzz) - r2
+    b = (dxx * sx + dyy * sy) + dzz * sz
+    a = (sx * sx + sy * sy) + sz * sz
+    disc = b * b - a * c0
+    with np.errstate(invalid="ignore", divide="ignore"):
+        tau = (-b - np.sqrt(np.where(disc >= 0.0, disc, 0.0))) / np.where(
+            a > 0.0, a, 1.0)
+    moving_in = (b < 0.0) & (disc >= 0.0) & (a > 0.0) & (tau <= 1.0)
+    return (c0 <= 0.0) | moving_in
+
+
+def alpha_eh(R, d, ell, phi_w_eV, E_e_eV):
+    """Electron energy-loss fraction of a nanoparticle (Appendix A, NP
+    electron heating): not reflected (1 - R), stopped inside the particle
+    (1 - exp(-d / ell), the complement of passing through it within an
+    inelastic mean free path), and leaving with the work function
+    (1 - phi / E_e).  The paper prints the middle factor as exp(-d/ell) but
+    evaluates it as 0.76 = 1 - exp(-1 nm / 0.7 nm); this reading follows
+    the value."""
+    return (1.0 - R) * (1.0 - np.exp(-d / ell)) * (1.0 - phi_w_eV / E_e_eV)
+
+
+def md_return(ab, lattice_a, grid=None, species=(C.ION,)):
+    """Atoms handed back to MD from the cathode-absorbed list (Appendix A,
+    transfer of bombarding ions): each selected particle's crossing point
+    offset backwards along its velocity by three lattice constants,
+    x_MD = x_c - 3 a v / |v| (x, y wrapped into the periodic box when grid
+    is given), with its velocity and id, in the list's (species, id)
+    order."""
+    sel = np.isin(ab["species"], np.asarray(species))
+    vx, vy, vz = ab["vx"][sel], ab["vy"][sel], ab["vz"][sel]
+    inv = 1.0 / np.sqrt((vx * vx + vy * vy) + vz * vz)
+    off = (3.0 * lattice_a) * inv
+    x = ab["x"][sel] - off * vx
+    y = ab["y"][sel] - off * vy
+    if grid is not None:
+        x, y = _wrap(x, grid.lx), _wrap(y, grid.ly)
+    return dict(species=ab["species"][sel], id=ab["id"][sel], x=x, y=y,
+                z=ab["z"][sel] - off * vz, vx=vx.copy(), vy=vy.copy(),
+                vz=vz.copy())
+
+
+def push(sp, species, E, grid, dt, sphere=None):
+    """Leapfrog push of one species in place; returns (cathode, anode)
+    masks and the cathode crossing points (x, y) of absorbed particles.
+    With sphere (an electron-absorbing nanoparticle, electrons only) the
+    returned cathode and anode masks exclude the electrons whose path
+    touched the ball, and sp gains the mask "np_hit" of them (they are
+    removed like the absorbed ones; the ball lies inside the domain, so a
+    straight path that leaves through a face cannot meet it afterwards).
     """
     if species != C.NEUTRAL and sp["x"].size:
         ex, ey, ez = gather(sp, E, grid)
@@ -406,12 +472,19 @@ def push(sp, species, E, grid, dt):
         sp["vx"] = sp["vx"] + k * ex
         sp["vy"] = sp["vy"] + k * ey
         sp["vz"] = sp["vz"] + k * ez
+    x0, y0, z0 = sp["x"], sp["y"], sp["z"]
     x = sp["x"] + sp["vx"] * dt
     y = sp["y"] + sp["vy"] * dt
     z = sp["z"] + sp["vz"] * dt
     gz = z * grid.inv_dx
     cath = gz < 0.0
     anode = gz >= float(grid.nz)
+    if sphere is not None and species == C.ELECTRON:
+        hit = sphere_hit(x0, y0, z0, sp["vx"], sp["vy"], sp["vz"], dt,
+                         sphere, grid)
+        cath = cath & ~hit
+        anode = anode & ~hit
+        sp["np_hit"] = hit
     with np.errstate(divide="ignore", invalid="ignore"):
         tc = np.where(cath, -z / np.where(cath, sp["vz"], 1.0), 0.0)
     xc = _wrap(x + sp["vx"] * tc, grid.lx)
@@ -619,10 +692,24 @@ def advance(state, params, E, dt):
     anode = [0, 0, 0]
     cath_count = [0, 0, 0]
     ke = [0.0, 0.0, 0.0]
+    sph = params.get("sources", {}).get("sphere")
+    absorber = sph if (sph and sph.get("absorb")) else None
+    np_hits, np_heat = 0, 0.0
     for s in (C.NEUTRAL, C.ION, C.ELECTRON):
         sp = state.sp[s]
-        cath, an, xc, yc = push(sp, s, E, g, dt)
+        cath, an, xc, yc = push(sp, s, E, g, dt, absorber)
         ke[s] = kinetic_energy(sp, s)
+        hit = sp.pop("np_hit", None)
+        if hit is None:
+            hit = np.zeros(sp["x"].size, dtype=bool)
+        elif np.any(hit):
+            # Heat of the nanoparticle: alpha_EH E_e per electron, E_e the
+            # kinetic energy of the half-step velocity it arrives with.
+            v2 = ((sp["vx"][hit] * sp["vx"][hit] + sp["vy"][hit] * sp["vy"][hit])
+                  + sp["vz"][hit] * sp["vz"][hit])
+            np_hits = int(np.count_nonzero(hit))
+            np_heat = float(absorber.get("alpha_eh", 0.5)
+                            * np.sum((0.5 * C.M_E) * v2))
         if np.any(cath):
             absorbed.append(dict(species=np.full(int(cath.sum()), s),
                                  id=sp["id"][cath], x=xc[cath], y=yc[cath],
@@ -631,7 +718,7 @@ def advance(state, params, E, dt):
                                  vz=sp["vz"][cath]))
         cath_count[s] = int(cath.sum())
         anode[s] = int(an.sum())
-        state.sp[s] = _select(sp, ~(cath | an))
+        state.sp[s] = _select(sp, ~(cath | an | hit))
     ncell_neutral = cell_index(state.sp[C.NEUTRAL], g)
     ncount = np.bincount(ncell_neutral,
                          minlength=g.nx * g.ny * g.nz).astype(np.int64)
@@ -654,6 +741,7 @@ def advance(state, params, E, dt):
                   vx=np.zeros(0), vy=np.zeros(0), vz=np.zeros(0))
     diag.update(near=near, emitted=emitted, fn_emitted=n_fn,
                 cathode=cath_count, anode=anode, kinetic=ke,
+                np_hits=np_hits, np_heat=np_heat,
                 counts=[state.count(s) for s in range(3)])
     state.step += 1
     return ab, diag
