@@ -44,6 +44,11 @@ MEASURED_TRAFFIC = {
 }
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,10 +67,10 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(p_full):
-    """The oracle, as it stands, on a bounded sample of the workload: four
-    steps on the same workload scaled to 1/8 of the grid and particles."""
-    import numpy as np  # noqa: F401
+def _oracle_sample(args):
+    """Four oracle steps of the workload scaled to 1/8 of the grid and
+    particles (one process, one thread): (particle-steps, seconds)."""
+    p_full, seed = args
     import workloads as W
     from oracle import pic as O
     from oracle import poisson as P
@@ -75,28 +80,69 @@ def cpu_baseline(p_full):
                  n_ion=pl["n_ion"] // 8, n_n=pl["n_n"] // 8)
     if "disk" in p["sources"]:
         p["sources"]["disk"]["n_n"] = p_full["sources"]["disk"]["n_n"] // 8
+    p["seed"] = seed
     g = P.Grid(p["nx"], p["ny"], p["nz"], p["dx"], p["bc_lo"], p["bc_hi"],
                p["v_lo"], p["v_hi"])
     st = O.State(g, seed=p["seed"], w_sp=p["w_sp"])
     n0 = 0
-    for s, (pos, vel, ids) in W.preload(p, seed=1).items():
+    for s, (pos, vel, ids) in W.preload(p, seed=1 + seed).items():
         st.load(s, pos, vel, ids)
         n0 += pos.shape[0]
     st.next_id = n0
-    steps = 4
     psteps = 0
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for _ in range(4):
         psteps += sum(st.count(s) for s in range(3))
         O.step(st, p, p["dt"])
-    el = time.perf_counter() - t0
-    return {"value": psteps / el, "unit": "particle-steps/s", "cores": 1,
+    return psteps, time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p_full):
+    """The oracle, as it stands, on a bounded sample of the workload: four
+    steps of the workload scaled to 1/8 of the grid and particles, once on
+    one core and then as independent seeds on every core of the host share
+    (at most 16 processes, one thread each).  Runs before the GPU is
+    touched, so the worker processes fork from a process without GPU
+    state."""
+    import multiprocessing as mp
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    pl = p_full["preload"]
+    ps1, el1 = _oracle_sample((p_full, 0))
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    n = max(1, min(16, avail))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(n) as pool:
+        res = pool.map(_oracle_sample, [(p_full, k) for k in range(n)])
+    wall = time.perf_counter() - t0
+    psn = sum(r[0] for r in res)
+    nx, ny, nz = p_full["nx"] // 2, p_full["ny"] // 2, p_full["nz"] // 2
+    return {"value": psn / wall, "unit": "particle-steps/s", "cores": n,
             "kind": "oracle",
-            "sample": f"{steps} oracle steps of the workload scaled to "
+            "sample": f"4 oracle steps of the workload scaled to "
                       f"{nx}x{ny}x{nz} cells with 1/8 of the preload "
                       f"({pl['n_e'] // 8} e, {pl['n_ion'] // 8} Cu+, "
-                      f"{pl['n_n'] // 8} Cu), numpy float64, one thread",
-            "seconds": el}
+                      f"{pl['n_n'] // 8} Cu), numpy float64; {n} independent "
+                      f"seeds in {n} processes of one thread each, "
+                      f"aggregate over the wall time",
+            "seconds": round(wall, 3),
+            "one_core": {"value": ps1 / el1, "cores": 1,
+                         "seconds": round(el1, 3)},
+            "host": {"nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+                     "processes": n}}
 
 
 UNET_LAYERS = ((2, 16, 0), (16, 16, 0), (16, 32, 1), (32, 32, 1), (32, 64, 2),
@@ -229,6 +275,70 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
     return out
 
 
+def variant_rooflines(p, r, workload):
+    """Algorithmic-bytes rooflines of one variant's dominant kernels, from
+    its HIP-event-timed phases.
+
+    push (k_push_tile / k_push_tile_m): per electron x, y, z, vx, vy, vz
+    read and written (96 B FP64; 56 B mixed as cell + FP32 offsets and
+    velocities), id read (8 B), cell key written (4 B); per ion the same
+    without the id; per node the three E components read once (24 B FP64,
+    12 B mixed) and the int64 charge of the pushed state read and written
+    once (16 B); per cell the neutral count read once (4 B).
+
+    smooth (finest level): with two sweeps before and after the coarse
+    correction on a grid at least 32 x 8 in x, y it is k_smooth2, one launch
+    per two red-black sweeps, whose algorithmic bytes are u and f read and u
+    written once: 24 B per unknown in FP64, 12 B in FP32 (the mixed form's
+    correction solve).  Otherwise it is k_rbgs, one launch per colour: u
+    read once, f of the colour's half read and u of that half written, 16 B
+    (8 B) per unknown.  Launches that only find the solve converged are
+    timed but not counted as work."""
+    mixed = r["precision"] == "mixed"
+    prec = r["precision"]
+    ph = r["_phases"]
+    nodes = p["nx"] * p["ny"] * (p["nz"] + 1)
+    cells = p["nx"] * p["ny"] * p["nz"]
+    unknowns = p["nx"] * p["ny"] * (p["nz"] - 1)
+    ms_push, n_push = ph["push_electron"]
+    per_e = (56 + 8 + 4) if mixed else (96 + 8 + 4)
+    per_i = (56 + 4) if mixed else (96 + 4)
+    per_node = (12 if mixed else 24) + 16
+    alg = (r["_electrons_i"] * per_e + r["_ions_i"] * per_i
+           + nodes * per_node + cells * 4)
+    t_push = ms_push / max(n_push, 1) * 1e-3
+    ach = alg / t_push / 1e9 if t_push > 0 else 0.0
+    kname = "k_push_tile_m" if mixed else "k_push_tile"
+    push = {"bound": "hbm", "kernel": kname,
+            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": MEASURED_TRAFFIC.get((workload, prec, "k_push_tile")),
+            "bytes_per_launch": int(alg),
+            "avg_launch_ms": round(t_push * 1e3, 5)}
+    ms_sm, n_sm = ph["smooth_l0"]
+    fused = p["nx"] >= 32 and p["ny"] >= 8 and r["_nu"] == 4
+    if fused:
+        n_eff = 2 * r["_vcycles_total"]
+        per_u = 12 if mixed else 24
+        sname = "k_smooth2<%s> (finest level, two red-black sweeps per launch)" % (
+            "float" if mixed else "double")
+    else:
+        n_eff = 2 * r["_nu"] * r["_vcycles_total"]
+        per_u = 8 if mixed else 16
+        sname = "k_rbgs (finest level, one colour)"
+    sm_bytes = unknowns * per_u
+    ach_s = sm_bytes * n_eff / (ms_sm * 1e-3) / 1e9 if ms_sm > 0 else 0.0
+    smooth = {"bound": "hbm", "kernel": sname,
+              "achieved": round(ach_s, 1), "peak": HBM_PEAK_GBS,
+              "unit": "GB/s", "frac": round(ach_s / HBM_PEAK_GBS, 4),
+              "traffic": (MEASURED_TRAFFIC.get((workload, prec, "k_smooth2"))
+                          if fused else None),
+              "bytes_per_launch": int(sm_bytes),
+              "launches_timed": int(n_sm), "launches_with_work": int(n_eff),
+              "avg_launch_ms": round(ms_sm / max(n_eff, 1), 5)}
+    return {"push": push, "smooth": smooth}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -244,6 +354,11 @@ def main():
 
     p = W.config(a.workload)
     pl = p["preload"]
+    # The oracle's CPU leg first, before anything touches the GPU.
+    cpu = None if a.no_cpu_baseline else cpu_baseline(p)
+    if cpu is not None:
+        progress(f"cpu baseline: {cpu['value']:.3e} particle-steps/s on "
+                 f"{cpu['cores']} cores")
     variants = (["fp64", "mixed", "learned_mixed", "fp64_prev"]
                 if a.variant == "all" else [a.variant])
     cap, per_step_n = capacities(p, a.warmup + 2 * a.steps)
@@ -251,6 +366,8 @@ def main():
     net, train_info = None, None
     if "learned_mixed" in variants:
         net, train_info = train_warm_start(G, W, WS, p, cap)
+        progress(f"warm-start network trained: {train_info['pairs']} pairs, "
+                 f"{train_info['train_s']} s")
     pre = W.preload(p, seed=1)
     n0 = sum(v[0].shape[0] for v in pre.values())
     res = {}
@@ -259,63 +376,19 @@ def main():
         res[v] = run_variant(G, p, prec, pre, n0, cap, a.steps, a.warmup,
                              net if v == "learned_mixed" else None,
                              warm="prev" if v == "fp64_prev" else "extrap")
+        progress(f"{v}: {res[v]['ms_per_step']:.3f} ms/step")
     del pre
     head = res[variants[0]]
     mixed = head["precision"] == "mixed"
-    ph = head["_phases"]
-    nodes = p["nx"] * p["ny"] * (p["nz"] + 1)
-    cells = p["nx"] * p["ny"] * p["nz"]
-    unknowns = p["nx"] * p["ny"] * (p["nz"] - 1)
-
-    # Dominant kernel: the finest-level smoother.  With two sweeps before
-    # and after the coarse correction on a grid at least 32 x 8 in x, y it
-    # is k_smooth2, one launch per two red-black sweeps, whose algorithmic
-    # bytes are u and f read and u written once: 24 B per unknown in FP64,
-    # 12 B in FP32.  Otherwise it is k_rbgs, one launch per colour: u read
-    # once, f of the colour's half read and u of that half written, 16 B
-    # (8 B) per unknown.  Launches that only find the solve converged are
-    # timed but not counted as work.
-    ms_sm, n_sm = ph["smooth_l0"]
-    fused = p["nx"] >= 32 and p["ny"] >= 8 and head["_nu"] == 4
-    if fused:
-        n_eff = 2 * head["_vcycles_total"]
-        per_u = 12 if mixed else 24
-        kname = "k_smooth2 (finest level, two red-black sweeps per launch)"
+    rooflines = {}
+    for v, r in res.items():
+        if v in ("fp64", "mixed"):
+            rooflines[v] = variant_rooflines(p, r, a.workload)
+    if variants[0] in rooflines:
+        hr = rooflines[variants[0]]
     else:
-        n_eff = 2 * head["_nu"] * head["_vcycles_total"]
-        per_u = 8 if mixed else 16
-        kname = "k_rbgs (finest level, one colour)"
-    sm_bytes = unknowns * per_u
-    achieved = sm_bytes * n_eff / (ms_sm * 1e-3) / 1e9 if ms_sm > 0 else 0.0
-    prec = head["precision"]
-    tr = MEASURED_TRAFFIC.get((a.workload, prec, "k_smooth2")) if fused else None
-    roofline = {"bound": "hbm", "kernel": kname,
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": tr, "bytes_per_launch": int(sm_bytes),
-                "launches_timed": int(n_sm), "launches_with_work": int(n_eff),
-                "avg_launch_ms": round(ms_sm / max(n_eff, 1), 5)}
-
-    # Charged-particle push (k_push_tile): per electron x, y, z, vx, vy, vz
-    # read and written (96 B FP64; 56 B mixed as cell + FP32 offsets and
-    # velocities), id read (8 B), cell key written (4 B); per ion the same
-    # without the id; per node the three E components read once (24 B FP64,
-    # 12 B mixed) and the int64 charge of the pushed state read and written
-    # once (16 B); per cell the neutral count read once (4 B).
-    ms_push, n_push = ph["push_electron"]
-    per_e = (56 + 8 + 4) if mixed else (96 + 8 + 4)
-    per_i = (56 + 4) if mixed else (96 + 4)
-    per_node = (12 if mixed else 24) + 16
-    alg_bytes = (head["_electrons_i"] * per_e + head["_ions_i"] * per_i
-                 + nodes * per_node + cells * 4)
-    t_push = ms_push / max(n_push, 1) * 1e-3
-    ach_p = alg_bytes / t_push / 1e9
-    roofline_push = {"bound": "hbm", "kernel": "k_push_tile",
-                     "achieved": round(ach_p, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach_p / HBM_PEAK_GBS, 4),
-                     "traffic": MEASURED_TRAFFIC.get((a.workload, prec, "k_push_tile")),
-                     "bytes_per_launch": int(alg_bytes),
-                     "avg_launch_ms": round(t_push * 1e3, 5)}
+        hr = variant_rooflines(p, head, a.workload)
+    roofline = hr["push"]
     out = {
         "metric": "particle-steps/s + ms/PIC step at 10M particles; "
                   "learned+mixed vs plain MG",
@@ -332,7 +405,7 @@ def main():
                                f"{per_step_n} Cu/step, Poisson to 1e-10",
                    "variant": variants[0]},
         "roofline": roofline,
-        "roofline_push": roofline_push,
+        "rooflines": rooflines,
         "variants": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")}
                      for k, v in res.items()},
     }
@@ -354,8 +427,8 @@ def main():
         if "mixed" in res:
             out["learned_mixed_vs_mixed_step_time"] = round(
                 lm["ms_per_step"] / res["mixed"]["ms_per_step"], 4)
-    if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     if a.phases:
         print(json.dumps(out["variants"], indent=1), file=sys.stderr)
     print(json.dumps(out), flush=True)

@@ -144,8 +144,8 @@ def _advance_case(seed, with_sources=True, dense=True):
                  n_n=20000 if dense else 2000)
     p["collisions"] = dict(p["collisions"])
     if dense:
-        # Large cross sections so ionisation, starvation and elastic events
-        # all occur in a single step.
+        # Large cross sections so ionisation and elastic events both occur
+        # in a single step (starvation: test_crowded_cells_*).
         p["collisions"].update(sigma_el=3e-17, lotz_a=4.5e-15)
     p["seed"] = seed
     if not with_sources:
@@ -168,12 +168,15 @@ def test_advance_bit_exact(gpu_lib, seed):
     st = O.State(g, seed=seed)
     load_both(p, gpu, st, seed=seed + 1)
     rng = np.random.default_rng(seed + 2)
-    # A field with structure: parallel plate plus noise, so the FN source
-    # emits at some surface nodes.
+    # A field with structure: parallel plate plus noise, and the first plane
+    # raised by 40-60 V so the surface field -E_z(0) = (4 phi_1 - phi_2) /
+    # (2 dx) reaches 40-60 V/nm over the emitting disk, where elementary
+    # Fowler-Nordheim emission (4.5 eV) gives about one electron per node
+    # and step.
     phi = P.solve_exact(P.add_boundary_terms(np.zeros(g.shape), g), g)
     phi = phi + rng.standard_normal(g.shape) * 2.0
     phi[0] = 0.0
-    phi[1] = phi[1] - 60.0 * rng.random(phi[1].shape)
+    phi[1] = phi[1] + 40.0 + 20.0 * rng.random(phi[1].shape)
     gpu.set_phi(phi)
     E = O.efield(phi, g)
     # The caller queue: a few particles of every species.
@@ -186,6 +189,9 @@ def test_advance_bit_exact(gpu_lib, seed):
     near = sum(do["near"].values())
     assert dg["near_threshold"] == near
     assert do["ionisations"] > 0 and do["elastic"] > 0, do
+    # The Fowler-Nordheim spawn is exercised: its electrons (ids after the
+    # other sources, node order) are compared one by one below.
+    assert do["fn_emitted"] >= 100, do["fn_emitted"]
     if near == 0:
         assert dg["ionisations"] == do["ionisations"]
         assert dg["starved"] == do["starved"]
@@ -219,10 +225,16 @@ def test_advance_bit_exact(gpu_lib, seed):
         assert np.isclose(dg["kinetic"][s], do["kinetic"][s], rtol=1e-12)
 
 
-def test_step_tolerance_and_charge(gpu_lib):
+@pytest.mark.parametrize("bc", ["dirichlet", "neumann_cathode"])
+def test_step_tolerance_and_charge(gpu_lib, bc):
     """A full step (MG solve vs exact): phi within 1e-6, positions and
-    velocities within 1e-6, exact total charge."""
+    velocities within 1e-6, exact total charge.  With a Neumann cathode
+    (prescribed dphi/dz = 1 GV/m at z = 0) the step's deposit, the doubled
+    density of the face node, the mirror-ghost solve, E and the push all
+    follow the Neumann path."""
     p = _advance_case(3, dense=False)
+    if bc == "neumann_cathode":
+        p.update(bc_lo=1, v_lo=p["v_hi"] / (p["nz"] * p["dx"]))
     gpu = make(p)
     g = grid_of(p)
     st = O.State(g, seed=3)
@@ -418,3 +430,63 @@ def test_neutral_compaction_and_rebinning_over_steps(gpu_lib, precision):
                     d[:, a] = np.minimum(d[:, a], L - d[:, a])
                 assert np.max(d) <= 1e-4 * p["dx"], s
     assert ionised > 0
+
+
+def test_crowded_cells_ionisation_and_starvation(gpu_lib):
+    """About fifteen 30 eV electrons and one or two neutrals per cell with
+    large cross sections: several ionisation events per cell, most of them
+    starved.  Counts, ids (Cu+ from neutral ids, secondaries from next_id)
+    and kinematics equal the oracle's; and on the GPU's own result the
+    neutrals each cell lost are the lowest ids of that cell, and the
+    secondaries' ids are the block next_id .. next_id + n - 1."""
+    p = small_c2(nx=16, ny=16, nz=16, n_e=60000, n_ion=100, n_n=5000)
+    p["preload"]["kT_e_eV"] = 30.0
+    p["sources"] = {}
+    p["collisions"] = dict(p["collisions"], sigma_el=3e-17, lotz_a=4.5e-15)
+    gpu = make(p, cap=100000)
+    g = grid_of(p)
+    st = O.State(g, seed=p["seed"])
+    pre = load_both(p, gpu, st, seed=42)   # a seed with no near-threshold draw
+    id0 = st.next_id
+    neutral_ids0 = pre[1][2].astype(np.uint64)
+    phi = P.solve_exact(P.add_boundary_terms(np.zeros(g.shape), g), g)
+    gpu.set_phi(phi)
+    ab_g, dg = gpu.advance(p["dt"])
+    ab_o, do = O.advance(st, p, O.efield(phi, g), p["dt"])
+    print("events:", do["ionisations"], "ionised,", do["starved"], "starved,",
+          do["elastic"], "elastic", flush=True)
+    assert do["starved"] >= 50 and do["ionisations"] >= 50, do
+    assert dg["near_threshold"] == sum(do["near"].values())
+    if dg["near_threshold"] == 0:
+        for k in ("ionisations", "starved", "elastic", "candidates"):
+            assert dg[k] == do[k], k
+    for s in range(3):
+        ig, pg, vg = gpu_arrays(gpu, s)
+        io, po, vo = oracle_arrays(st.sp[s])
+        assert np.array_equal(ig, io), s
+        sc = np.maximum(np.abs(vo), np.sqrt(np.mean(vo ** 2)))
+        assert np.all(np.abs(vg - vo) <= 1e-12 * sc), s
+        assert np.all(np.abs(pg - po) <= 1e-12 * np.maximum(np.abs(po), p["dx"]))
+    # Rank rule on the GPU result itself.
+    ii, ip, _ = gpu_arrays(gpu, 2)
+    new_ion = np.isin(ii, neutral_ids0)
+    assert new_ion.sum() == dg["ionisations"]
+    ni, npos, _ = gpu_arrays(gpu, 1)
+
+    def cells(pos):
+        c = np.floor(pos * g.inv_dx).astype(np.int64)
+        return (c[:, 2] * g.ny + c[:, 1]) * g.nx + c[:, 0]
+    c_ion, c_left = cells(ip[new_ion]), cells(npos)
+    lost_max = {}
+    for c, i in zip(c_ion, ii[new_ion]):
+        lost_max[c] = max(lost_max.get(c, 0), int(i))
+    left_min = {}
+    for c, i in zip(c_left, ni):
+        left_min[c] = min(left_min.get(c, 1 << 63), int(i))
+    for c, m in lost_max.items():
+        assert m < left_min.get(c, 1 << 63), c
+    # Secondaries: the next ids in one block.
+    ie, _, _ = gpu_arrays(gpu, 0)
+    sec = np.sort(ie[ie >= np.uint64(id0)])
+    assert np.array_equal(sec, np.arange(id0, id0 + dg["ionisations"],
+                                         dtype=np.uint64))
