@@ -344,6 +344,31 @@ const char* pic_unet_last_error(const pic_unet* u);
  * else PIC_ERR_ARG. */
 pic_status pic_set_warm_start(pic_ctx* ctx, int32_t mode, pic_unet* net);
 
+/* ---- Allocation-free Poisson solve ----------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as poisson_solve (rho -> phi with cfg's grid, boundary data,
+ * precision, multigrid settings and rel_tol; cfg's capacities are ignored)
+ * without a context or a workspace: the multigrid state lives in a fixed
+ * device buffer of the library, PIC_STATIC_SCRATCH_BYTES large, one per GPU
+ * it runs on, held until the process ends.  Nothing is allocated: no
+ * hipMalloc, hipFree or host allocation.  rho and phi are caller-owned
+ * device arrays of nx*ny*(nz+1) FP64 values (x fastest); phi is read as the
+ * initial guess when warm == PIC_WARM_GIVEN.  Enqueued on hip_stream (a
+ * hipStream_t, NULL = default), which is synchronised before returning.
+ * Every call on one GPU shares that GPU's buffer and clears it first:
+ * calls that overlap on one GPU (several host threads or streams) race.
+ * Errors: PIC_ERR_ARG (invalid cfg or arguments), PIC_ERR_CAPACITY (the
+ * grid's multigrid state, about 27 bytes per node in FP64 plus the exact
+ * coarse level, exceeds the buffer: roughly above 2 M nodes), PIC_ERR_HIP,
+ * PIC_ERR_NOCONV. */
+#define PIC_STATIC_SCRATCH_BYTES (64u << 20)
+pic_status poisson_solve_static(const pic_config* cfg,
+                                const double* rho_device, double* phi_device,
+                                int32_t warm, pic_solve_info* info,
+                                void* hip_stream);
+
+
 /* The last recorded solve's network input (nz, ny, nx, 2) and target
  * (phi - phi_prev) / sigma (nz, ny, nx), FP32 device buffers: the learned
  * start's training pair.  PIC_ERR_STATE if no solve has been recorded. */

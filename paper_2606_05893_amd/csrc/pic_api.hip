@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "pic_ctx.h"
@@ -191,6 +192,39 @@ size_t carve(pic_ctx* c, char* base) {
   c->warm_x = cv.take<float>(2 * c->g.nxy * f.nz);
   c->warm_prev = cv.take<double>(c->nnodes);
   c->phi_hist = cv.take<double>(c->nnodes);
+  return cv.off + kAlign;
+}
+
+// The arrays the field solve alone uses (allocation-free poisson solve):
+// the multigrid levels, the reduction partials, the exact coarse level and
+// the counters.
+size_t carve_field(pic_ctx* c, char* base) {
+  Carver cv{base, 0};
+  const bool mixed = c->cfg.precision == PIC_MIXED;
+  for (int l = 0; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    L.u = L.f = L.us = nullptr;
+    L.uf = L.ff = L.usf = nullptr;
+    if (l == 0 || !mixed) {
+      L.u = cv.take<double>(L.nnodes);
+      L.f = cv.take<double>(L.nnodes);
+      if (!mixed) L.us = cv.take<double>(L.nnodes);
+    }
+    if (mixed) {
+      L.uf = cv.take<float>(L.nnodes);
+      L.ff = cv.take<float>(L.nnodes);
+      L.usf = cv.take<float>(L.nnodes);
+    }
+  }
+  c->partials = cv.take<double>(c->npartials);
+  {
+    const long long es = mixed ? 4 : 8;
+    const long long pm = (long long)c->spec_planes * c->spec_modes;
+    c->spec_s = cv.take<char>(2 * pm * es);
+    c->spec_m = cv.take<char>(pm * es);
+  }
+  c->qpartials = cv.take<long long>(1024);
+  c->dc = cv.take<Counters>(1);
   return cv.off + kAlign;
 }
 
@@ -685,6 +719,94 @@ pic_status poisson_solve(pic_ctx* c, const double* rho, double* phi,
   if (st != PIC_OK)
     return set_err(c, (pic_status)st, "Poisson solve did not converge");
   return PIC_OK;
+}
+
+// ---- allocation-free Poisson solve ------------------------------------------
+}  // extern "C"
+
+// The fixed device buffer of poisson_solve_static: one per GPU the library
+// runs on, held until the process ends.  Host code never passes the array's
+// name to a kernel or a copy (on the host it is only a stand-in for the
+// symbol): it uses the device address hipGetSymbolAddress returns, looked up
+// once per device.
+static __device__ __align__(256) char scratch[PIC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+// Counter readbacks of the allocation-free solve land here (pageable host
+// memory, one slot per device).
+Counters g_scratch_counters[kMaxDevices];
+
+__global__ void k_zero16(uint4* __restrict__ p, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += stride)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+}  // namespace
+
+extern "C" {
+
+pic_status poisson_solve_static(const pic_config* cfg, const double* rho,
+                                double* phi, int32_t warm,
+                                pic_solve_info* info, void* stream) {
+  if (!cfg || !rho || !phi) return PIC_ERR_ARG;
+  if (warm != PIC_WARM_ZERO && warm != PIC_WARM_GIVEN) return PIC_ERR_ARG;
+  if (validate(cfg) != PIC_OK) return PIC_ERR_ARG;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return PIC_ERR_HIP;
+  char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void* ptr = nullptr;
+      if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+        return PIC_ERR_HIP;
+      g_scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    base = g_scratch_ptr[dev];
+  }
+  // A field-only context on the stack: the particle capacities are zero and
+  // every device array comes from the fixed buffer.
+  pic_ctx c{};
+  c.cfg = *cfg;
+  for (int s = 0; s < 3; ++s) c.cfg.capacity[s] = 0;
+  c.cfg.queue_capacity = 0;
+  c.cfg.max_events = 1;
+  c.stream = reinterpret_cast<hipStream_t>(stream);
+  derive(&c);
+  const size_t need = carve_field(&c, nullptr);
+  if (need > (size_t)PIC_STATIC_SCRATCH_BYTES) return PIC_ERR_CAPACITY;
+  carve_field(&c, base);
+  c.hpin = &g_scratch_counters[dev];
+  c.ev_sync = nullptr;
+  c.warm_mode = PIC_WS_PREV;
+  c.last_vcycles = 0;
+  c.spec_ready = false;
+  c.timing = false;
+  // Every array starts at zero, whatever the last call on this GPU left.
+  const long long n16 = (long long)(need / 16);
+  k_zero16<<<1024, 256, 0, c.stream>>>(reinterpret_cast<uint4*>(base), n16);
+  if (hipGetLastError() != hipSuccess) return PIC_ERR_HIP;
+  if (warm == PIC_WARM_GIVEN &&
+      hipMemcpyAsync(c.lev[0].u, phi, c.nnodes * sizeof(double),
+                     hipMemcpyDeviceToDevice, c.stream) != hipSuccess)
+    return PIC_ERR_HIP;
+  field_rhs(&c, rho);
+  int st = PIC_OK;
+  pic_solve_info loc;
+  field_solve(&c, warm == PIC_WARM_GIVEN, &loc, &st);
+  if (info) *info = loc;
+  if (hipMemcpyAsync(phi, c.lev[0].u, c.nnodes * sizeof(double),
+                     hipMemcpyDeviceToDevice, c.stream) != hipSuccess ||
+      hipStreamSynchronize(c.stream) != hipSuccess)
+    return PIC_ERR_HIP;
+  return (pic_status)st;
 }
 
 pic_status pic_set_warm_start(pic_ctx* c, int32_t mode, pic_unet* net) {

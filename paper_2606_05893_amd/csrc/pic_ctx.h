@@ -175,6 +175,8 @@ namespace pic {
 // a blocking wait wakes the host some ten microseconds after the GPU is
 // done, and the GPU stays idle until the host queues more work.
 inline hipError_t stream_wait(pic_ctx* c) {
+  // A context without its event (the allocation-free solve) waits plainly.
+  if (!c->ev_sync) return hipStreamSynchronize(c->stream);
   hipError_t e = hipEventRecord(c->ev_sync, c->stream);
   if (e != hipSuccess) return e;
   while ((e = hipEventQuery(c->ev_sync)) == hipErrorNotReady) {

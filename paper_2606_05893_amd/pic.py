@@ -121,6 +121,9 @@ EXPORTS = {
     "pic_enable_timing": (_c_i32, [_c_p, _c_i32]),
     "pic_phase_times": (_c_i32, [_c_p, ctypes.POINTER(_c_d),
                                  ctypes.POINTER(_c_i64)]),
+    "poisson_solve_static": (_c_i32, [ctypes.POINTER(Config), _c_p, _c_p,
+                                      _c_i32, ctypes.POINTER(SolveInfo),
+                                      _c_p]),
 }
 
 PHASES = ("deposit", "rhs", "poisson", "efield", "sources", "push_neutral",
@@ -419,6 +422,27 @@ class Pic:
 
     def set_clock(self, step, next_id):
         self._call("pic_set_clock", int(step), int(next_id))
+
+
+def poisson_solve_static(p, rho, phi=None, **kw):
+    """rho -> phi through the allocation-free entry point (no context, no
+    workspace) on the current stream; kw as for make_config."""
+    lib = load_library()
+    cfg = make_config(p, capacity=(0, 0, 0), queue_capacity=0, max_events=1,
+                      **kw)
+    shape = (p["nz"] + 1, p["ny"], p["nx"])
+    rho = torch.as_tensor(rho, dtype=torch.float64, device="cuda").contiguous()
+    warm = phi is not None
+    out = (torch.as_tensor(phi, dtype=torch.float64, device="cuda").clone()
+           if warm else torch.zeros(shape, dtype=torch.float64, device="cuda"))
+    info = SolveInfo()
+    st = lib.poisson_solve_static(
+        ctypes.byref(cfg), _ptr(rho), _ptr(out), 1 if warm else 0,
+        ctypes.byref(info),
+        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != 0:
+        raise PicError(st, "poisson_solve_static")
+    return out, _struct_dict(info)
 
 
 def _struct_dict(s):
