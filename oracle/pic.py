@@ -755,3 +755,65 @@ def step(state, params, dt):
     diag["total_charge_units"] = int(acc.sum())
     diag["field_energy"] = field_energy(acc, phi, state.grid, state.w_sp)
     return ab, diag, phi
+
+
+# --------------------------------------------------------------------------
+# Resolution check against the Debye length
+# --------------------------------------------------------------------------
+def debye_check(state, block=1, alpha_D=0.5):
+    """Debye length of the electrons and ions per block of block^3 cells
+    and the mesh criterion the paper applies to its elements (Appendix A:
+    maximum element size d_max = 3.4 lambda_D alpha_D, alpha_D = 0.5).
+
+    Per block and charged species s with N_s >= 2 particles: density
+    n_s = N_s w / (block dx)^3, temperature k T_s = m_s S_s / (3 (N_s - 1))
+    with S_s the sum over the block's particles of |v - mean v|^2 (the
+    unbiased variance of the three velocity components, drift removed), and
+    1 / lambda_D^2 = sum_s n_s e^2 / (eps0 k T_s) over the species with
+    N_s >= 2 and T_s > 0.  A block where no species qualifies has no Debye
+    length (infinite: nothing to resolve).  The grid resolves a block when
+    dx <= d_max.
+
+    Returns dict(lambda_D (bz, by, bx) array, checked = blocks with a finite
+    lambda_D, unresolved = of them with dx > d_max, lambda_min, ratio_max =
+    largest dx / d_max).
+    """
+    g = state.grid
+    if g.nx % block or g.ny % block or g.nz % block:
+        raise ValueError("block must divide the grid")
+    bx, by, bz = g.nx // block, g.ny // block, g.nz // block
+    nb = bx * by * bz
+    vol = (float(block) * g.dx) ** 3
+    inv_l2 = np.zeros(nb)
+    for s in (C.ELECTRON, C.ION):
+        sp = state.sp[s]
+        if sp["x"].size == 0:
+            continue
+        i = (np.floor(sp["x"] * g.inv_dx).astype(np.int64) % g.nx) // block
+        j = (np.floor(sp["y"] * g.inv_dx).astype(np.int64) % g.ny) // block
+        k = np.floor(sp["z"] * g.inv_dx).astype(np.int64) // block
+        key = (k * by + j) * bx + i
+        N = np.bincount(key, minlength=nb).astype(np.float64)
+        Nq = np.where(N > 0, N, 1.0)
+        ss = np.zeros(nb)
+        for comp in ("vx", "vy", "vz"):
+            mean = np.bincount(key, sp[comp], minlength=nb) / Nq
+            dev = sp[comp] - mean[key]
+            ss += np.bincount(key, dev * dev, minlength=nb)
+        ok = N >= 2
+        kT = np.where(ok, (C.MASS[s] * ss) / (3.0 * np.where(ok, N - 1.0, 1.0)),
+                      0.0)
+        n = (N * float(state.w_sp)) / vol
+        use = ok & (kT > 0.0)
+        term = np.where(use, (n * (C.E_CHARGE * C.E_CHARGE))
+                        / (C.EPS0 * np.where(use, kT, 1.0)), 0.0)
+        inv_l2 += term
+    has = inv_l2 > 0.0
+    lam = np.full(nb, np.inf)
+    lam[has] = 1.0 / np.sqrt(inv_l2[has])
+    dmax = (3.4 * alpha_D) * lam
+    ratio = np.where(has, g.dx / dmax, 0.0)
+    return dict(lambda_D=lam.reshape(bz, by, bx), checked=int(has.sum()),
+                unresolved=int(np.count_nonzero(ratio > 1.0)),
+                lambda_min=float(lam[has].min()) if has.any() else np.inf,
+                ratio_max=float(ratio.max()) if nb else 0.0)
