@@ -56,7 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--variant", default="all",
-                    choices=["all", "fp64", "mixed", "learned_mixed", "fp64_prev"],
+                    choices=["all", "fp64", "mixed", "learned_mixed", "fp64_prev",
+                             "fp64_np"],
                     help="fp64: plain FP64 multigrid; mixed: FP32 particles and "
                          "smoothing with FP64 refinement; learned_mixed: mixed "
                          "with the U-Net warm start (trained first on pairs "
@@ -212,7 +213,7 @@ WARM_LABEL = {"prev": "previous phi", "extrap": "extrapolated phi",
 
 
 def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
-                warm="extrap"):
+                warm="extrap", diagnostics=False):
     import numpy as np
     import torch
     gpu = new_context(G, p, precision, pre, n0, cap)
@@ -225,11 +226,13 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
     for _ in range(warmup):
         gpu.step(dt)
     counts = [gpu.count(s) for s in range(3)]
+    nps = []
 
     def timed(k):
         nonlocal counts
         psteps = 0
         solves, electrons, ions = [], [], []
+        nps.clear()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(k):
@@ -239,6 +242,7 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
             _, d = gpu.step(dt)
             counts = d["counts"]
             solves.append(d["solve"])
+            nps.append((d["np_absorbed"], d["np_heat"]))
         torch.cuda.synchronize()
         return time.perf_counter() - t0, psteps, solves, electrons, ions
 
@@ -250,6 +254,31 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
     el_i, _, solves_i, electrons_i, ions_i = timed(steps)
     ph = gpu.phase_times()
     nu = gpu.p.get("nu_pre", 2) + gpu.p.get("nu_post", 2)
+    diag = None
+    if diagnostics:
+        # The Debye-length check on the state the run left, per cell and per
+        # tile-sized block, timed with HIP events like the step's phases.
+        diag = {}
+        n_charged = gpu.count(0) + gpu.count(2)
+        for block in (1, 8):
+            gpu.enable_timing(True)
+            for _ in range(5):
+                info, _ = gpu.debye_check(block, 0.5, with_lambda=False)
+            ms, calls = gpu.phase_times()["debye"]
+            nb = info["blocks"]
+            # 48 B per charged particle (x, y, z, vx, vy, vz read); per block
+            # the 80-byte moment record cleared, updated once and read once.
+            alg = 48 * n_charged + 240 * nb
+            t = ms / max(calls, 1) * 1e-3
+            diag[f"debye_block{block}"] = {
+                "ms": round(t * 1e3, 4), "blocks": nb,
+                "checked": info["checked"], "unresolved": info["unresolved"],
+                "lambda_min_m": info["lambda_min"],
+                "ratio_max": round(info["ratio_max"], 4),
+                "roofline": {"bound": "hbm", "achieved": round(alg / t / 1e9, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(alg / t / 1e9 / HBM_PEAK_GBS, 4),
+                             "bytes_per_call": int(alg)}}
     del gpu
     torch.cuda.empty_cache()
     out = {"precision": precision,
@@ -267,6 +296,11 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
     if net is not None:
         out["warm_ratio_avg"] = float(np.mean([d["warm_ratio"] for d in solves]))
         out["fallback_rate"] = float(np.mean([d["warm_rejected"] for d in solves]))
+    if diag is not None:
+        out["debye_check"] = diag
+    if any(h for h, _ in nps):
+        out["np_absorbed_avg"] = float(np.mean([h for h, _ in nps]))
+        out["np_heat_J_avg"] = float(np.mean([e for _, e in nps]))
     out["_phases"] = ph
     out["_vcycles_total"] = sum(d["vcycles"] for d in solves_i)
     out["_electrons_i"] = float(np.mean(electrons_i))
@@ -359,7 +393,7 @@ def main():
     if cpu is not None:
         progress(f"cpu baseline: {cpu['value']:.3e} particle-steps/s on "
                  f"{cpu['cores']} cores")
-    variants = (["fp64", "mixed", "learned_mixed", "fp64_prev"]
+    variants = (["fp64", "mixed", "learned_mixed", "fp64_prev", "fp64_np"]
                 if a.variant == "all" else [a.variant])
     cap, per_step_n = capacities(p, a.warmup + 2 * a.steps)
     torch.cuda.set_device(0)
@@ -373,9 +407,20 @@ def main():
     res = {}
     for v in variants:
         prec = "fp64" if v.startswith("fp64") else "mixed"
-        res[v] = run_variant(G, p, prec, pre, n0, cap, a.steps, a.warmup,
+        pv = p
+        if v == "fp64_np":
+            # A nanoparticle of 5 nm radius at z = 200 nm over the disk
+            # centre absorbing electrons (alpha_EH = 0.5); no extra source.
+            pv = dict(p)
+            pv["sources"] = dict(p["sources"])
+            pv["sources"]["sphere"] = dict(
+                cx=p["nx"] * p["dx"] / 2, cy=p["ny"] * p["dx"] / 2,
+                cz=200e-9, radius=5e-9, n=0, T_K=3500.0, absorb=True,
+                alpha_eh=0.5)
+        res[v] = run_variant(G, pv, prec, pre, n0, cap, a.steps, a.warmup,
                              net if v == "learned_mixed" else None,
-                             warm="prev" if v == "fp64_prev" else "extrap")
+                             warm="prev" if v == "fp64_prev" else "extrap",
+                             diagnostics=(v == "fp64"))
         progress(f"{v}: {res[v]['ms_per_step']:.3f} ms/step")
     del pre
     head = res[variants[0]]

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 3
+#define PIC_ABI_VERSION 4
 
 typedef enum {
   PIC_OK = 0,
@@ -115,9 +115,16 @@ typedef struct {
   double E_max_eV;         /* majorant energy of the null-collision method */
 } pic_collisions;
 
-/* Per-step particle sources at the cathode and in the gap. */
+/* Per-step particle sources at the cathode and in the gap, and the
+ * nanoparticle as an electron sink. */
 typedef struct {
-  int32_t disk_on, fn_on, sphere_on, reserved;
+  int32_t disk_on, fn_on, sphere_on;
+  /* sph_absorb: the sphere (a nanoparticle) absorbs every electron whose
+   * straight path in a step touches it, and tallies alpha_EH times the
+   * electron's kinetic energy as the particle's heat (Appendix A, electron
+   * heating of NPs); ions and neutrals pass through.  Independent of
+   * sphere_on (the neutral source). */
+  int32_t sph_absorb;
   /* Disk at z = 0: electrons with a flux-weighted half-Maxwellian normal
    * speed at kT_e, neutrals with a half-space Maxwellian at T_n. */
   double disk_cx, disk_cy, disk_radius;
@@ -133,6 +140,8 @@ typedef struct {
   double sph_cx, sph_cy, sph_cz, sph_radius;
   int64_t sph_n;
   double sph_T_K;
+  double sph_alpha_eh;     /* energy fraction an absorbed electron leaves
+                              as heat, 0..1 (the paper's estimate: 0.5)   */
 } pic_sources;
 
 typedef struct {
@@ -167,6 +176,8 @@ typedef struct {
   pic_solve_info solve;
   int64_t step;               /* steps completed                           */
   uint64_t next_id;           /* next particle id to assign                */
+  int64_t np_absorbed;        /* electrons absorbed by the nanoparticle    */
+  double np_heat;             /* alpha_EH * sum of their energies, J       */
 } pic_diag;
 
 /* Particles absorbed at the cathode in the last step, sorted by
@@ -180,6 +191,52 @@ typedef struct {
   const double* pos;       /* device, 3n SoA: crossing point, z = 0        */
   const double* vel;       /* device, 3n SoA: half-step velocity           */
 } pic_absorbed;
+
+/* Atoms handed back to MD from the last step's cathode list (Appendix A,
+ * transfer of bombarding ions): each particle of a species selected by
+ * species_mask (bit s for species s; the paper hands back the ions,
+ * 1u << PIC_ION) is placed at its crossing point offset backwards along its
+ * velocity by three lattice constants, x_MD = x_c - 3 a v / |v|, x and y
+ * wrapped into the periodic box, so the atom starts above the surface and
+ * clear of its atoms.  Outputs (caller-owned device buffers of at least cap
+ * entries; species may be NULL) keep the list's (species, id) order:
+ * pos3n and vel3n SoA (m, m/s), ids, species; *n receives the count.
+ * PIC_ERR_CAPACITY (with *n set) if cap is too small; PIC_ERR_STATE before
+ * the first step.  Synchronises the context's stream. */
+pic_status pic_md_return(pic_ctx* ctx, double lattice_a, uint32_t species_mask,
+                         int64_t cap, double* pos3n_device,
+                         double* vel3n_device, uint64_t* ids_device,
+                         int32_t* species_device, int64_t* n);
+
+/* Resolution of the grid against the Debye length of the electrons and ions
+ * (Appendix A: mesh criterion d_max = 3.4 lambda_D alpha_D, the paper uses
+ * alpha_D = 0.5).  Per block of block^3 cells (block = 1, 2, 4 or 8,
+ * dividing nx, ny, nz; blocks x fastest) and charged species with N >= 2
+ * particles: n = N w_sp / (block dx)^3 and k T = m S / (3 (N - 1)), S the
+ * sum of |v - mean v|^2 over the block's particles; 1 / lambda_D^2 = sum
+ * over those species of n e^2 / (eps0 k T).  A block with no such species
+ * has no Debye length (lambda = +inf).  The grid resolves a block when
+ * dx <= d_max.  lambda_device (may be NULL): nx*ny*nz / block^3 values, m.
+ * Moments are summed with atomics, so lambda_D is reproducible to rounding
+ * (not bit for bit).  Synchronises the context's stream. */
+typedef struct {
+  int64_t blocks;          /* blocks of the grid                           */
+  int64_t checked;         /* with a finite Debye length                   */
+  int64_t unresolved;      /* of them with dx > d_max                      */
+  double lambda_min;       /* smallest Debye length, m (inf: none)         */
+  double ratio_max;        /* largest dx / d_max (0: none)                 */
+} pic_debye_info;
+pic_status pic_debye_check(pic_ctx* ctx, int32_t block, double alpha_D,
+                           double* lambda_device, pic_debye_info* info);
+
+/* The nanoparticle's electron energy-loss fraction (Appendix A):
+ * (1 - R)(1 - exp(-d / ell))(1 - phi_w / E_e) for reflection probability R,
+ * particle diameter d and inelastic mean free path ell (same length unit),
+ * work function phi_w and electron energy E_e (eV).  The paper prints the
+ * middle factor as exp(-d/ell) but evaluates it as 0.76 = 1 - exp(-1/0.7);
+ * this follows the value (0.85 * 0.76 * 0.775 = 0.50). */
+double pic_alpha_eh(double R, double d, double ell, double phi_w_eV,
+                    double E_e_eV);
 
 /* Workspace size for a configuration; the caller allocates it (e.g. with
  * torch) with at least 256-byte alignment. */
@@ -262,14 +319,18 @@ pic_status pic_get_diag(pic_ctx* ctx, pic_diag* diag);
  * of a phase per step are timed).  ms[PIC_NPHASES] receives the time
  * accumulated since timing was enabled, calls[] (may be NULL) the number of
  * timed intervals of each phase. */
-#define PIC_NPHASES 13
+#define PIC_NPHASES 16
 enum {
   PIC_PH_DEPOSIT = 0, PIC_PH_RHS, PIC_PH_POISSON, PIC_PH_EFIELD,
   PIC_PH_SOURCES, PIC_PH_PUSH_NEUTRAL, PIC_PH_PUSH_ION, PIC_PH_PUSH_ELECTRON,
   PIC_PH_COLLIDE, PIC_PH_ABSORBED, PIC_PH_BIN,
   PIC_PH_WARM,    /* warm-start stage of the solve (inside PIC_PH_POISSON) */
-  PIC_PH_SMOOTH0  /* each finest-level smoothing launch (inside the solve;
+  PIC_PH_SMOOTH0, /* each finest-level smoothing launch (inside the solve;
                      calls counts launches)                               */
+  PIC_PH_DEBYE,   /* pic_debye_check                                      */
+  PIC_PH_COULOMB, /* Coulomb binary collisions (inside PIC_PH_COLLIDE)    */
+  PIC_PH_ION_COLL /* ion-neutral and recombination collisions (inside
+                     PIC_PH_COLLIDE)                                      */
 };
 pic_status pic_enable_timing(pic_ctx* ctx, int32_t on);
 pic_status pic_phase_times(pic_ctx* ctx, double* ms, int64_t* calls);

@@ -13,7 +13,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["pic_api.hip", "k_field.hip", "k_particles.hip", "k_unet.hip"]
+SOURCES = ["pic_api.hip", "k_field.hip", "k_particles.hip", "k_unet.hip",
+           "k_debye.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",

@@ -214,6 +214,8 @@ __global__ void k_begin(Counters* dc, unsigned long long n0,
   dc->n_over = dc->n_near = dc->n_ab = dc->n_ncand = 0;
   dc->n_tail_cand = dc->n_el_tail = 0;
   dc->ion_moved = dc->n_dead1 = dc->n_dead2 = 0;
+  dc->np_hits = 0;
+  dc->np_heat = 0.0;
 }
 
 // ---- sources ------------------------------------------------------------------
@@ -585,7 +587,41 @@ struct MccC {
   double inv_gmax, sigma_el, lotz_a, ion_I, sigma_const, E_max;
   double half_me, ratio;  // 0.5 m_e; 2 m_e / M
   double two_e_me;        // 2 e / m_e
+  // Electron-absorbing nanoparticle (sph_on = 0: none).
+  int sph_on;
+  double sph_cx, sph_cy, sph_cz, sph_r2, sph_alpha, dt;
 };
+
+// Does the straight path (x0, y0, z0) + v t, 0 <= t <= dt, touch the closed
+// ball of the nanoparticle (x, y: nearest periodic image of its centre)?
+// With d = x0 - c and s = v dt the path is d + tau s, tau in [0, 1]: it
+// touches the ball if it starts inside, or moves towards the centre with
+// the smaller root of |d + tau s|^2 = R^2 at most 1.
+__device__ __forceinline__ bool sphere_hit(const MccC& m, const GridC& g,
+                                           double x0, double y0, double z0,
+                                           double vx, double vy, double vz) {
+  double dxx = x0 - m.sph_cx, dyy = y0 - m.sph_cy;
+  const double hx = 0.5 * g.lx, hy = 0.5 * g.ly;
+  if (dxx > hx) dxx = dxx - g.lx; else if (dxx < -hx) dxx = dxx + g.lx;
+  if (dyy > hy) dyy = dyy - g.ly; else if (dyy < -hy) dyy = dyy + g.ly;
+  const double dzz = z0 - m.sph_cz;
+  const double sx = vx * m.dt, sy = vy * m.dt, sz = vz * m.dt;
+  const double c0 = ((dxx * dxx + dyy * dyy) + dzz * dzz) - m.sph_r2;
+  if (c0 <= 0.0) return true;
+  const double b = (dxx * sx + dyy * sy) + dzz * sz;
+  const double a = (sx * sx + sy * sy) + sz * sz;
+  const double disc = b * b - a * c0;
+  if (!(b < 0.0) || !(disc >= 0.0) || !(a > 0.0)) return false;
+  return (-b - sqrt(disc)) / a <= 1.0;
+}
+
+// An electron absorbed by the nanoparticle: counted, and alpha_EH times its
+// kinetic energy (|v|^2 = ke) added to the particle's heat.
+__device__ __forceinline__ void np_absorb(const MccC& m, double ke,
+                                          Counters* dc) {
+  atomicAdd(&dc->np_hits, 1ull);
+  atomicAdd(&dc->np_heat, m.sph_alpha * (m.half_me * ke));
+}
 
 // Field at a particle from the node arrays (Ex, Ey, Ez blocks of nn nodes),
 // with the deposit's quantised weights, accumulated in the fixed order
@@ -688,6 +724,7 @@ __device__ __forceinline__ void finish_push(Parts& p, long long i, double x,
                                             uint32_t step, uint64_t seed,
                                             Counters* dc, PushOut& o,
                                             uint64_t idv) {
+  const bool np = SP == 0 && m.sph_on && sphere_hit(m, g, x, y, z, vx, vy, vz);
   x = x + vx * dt;
   y = y + vy * dt;
   z = z + vz * dt;
@@ -703,6 +740,10 @@ __device__ __forceinline__ void finish_push(Parts& p, long long i, double x,
     // Non-finite, or moved more than one period in a step: removed and
     // reported.
     atomicOr(&dc->err, kErrNonFinite);
+  } else if (np) {
+    // Absorbed by the nanoparticle (which lies inside the domain, so a
+    // path that leaves through a face cannot reach it afterwards).
+    np_absorb(m, o.ke, dc);
   } else if (gz < 0.0) {
     o.cathode = true;
   } else if (gz >= (double)g.nz) {
@@ -1019,6 +1060,12 @@ __device__ __forceinline__ void finish_push_m(PartsM& p, long long i, PushM q,
                                               const MccC& m, uint32_t step,
                                               uint64_t seed, Counters* dc,
                                               PushOut& o) {
+  bool np = false;
+  if (SP == 0 && m.sph_on)
+    np = sphere_hit(m, g, ((double)q.ix + (double)q.ox) * g.dx,
+                    ((double)q.iy + (double)q.oy) * g.dx,
+                    ((double)q.iz + (double)q.oz) * g.dx, (double)q.vx,
+                    (double)q.vy, (double)q.vz);
   q.ox = q.ox + q.vx * dtdx;
   q.oy = q.oy + q.vy * dtdx;
   q.oz = q.oz + q.vz * dtdx;
@@ -1043,6 +1090,8 @@ __device__ __forceinline__ void finish_push_m(PartsM& p, long long i, PushM q,
       !(q.oy == q.oy) || !(q.oz == q.oz) || !isfinite(q.vx) ||
       !isfinite(q.vy) || !isfinite(q.vz)) {
     atomicOr(&dc->err, kErrNonFinite);
+  } else if (np) {
+    np_absorb(m, o.ke, dc);
   } else if (iz < 0) {
     o.cathode = true;
   } else if (iz >= g.nz) {
@@ -2066,6 +2115,34 @@ __global__ void k_ab_gather(const Rec* __restrict__ rec,
   }
 }
 
+// Atoms handed back to MD: records [first, first + n) of the sorted cathode
+// list to outputs [out0, out0 + n) of SoA arrays of stride nout, each
+// crossing point offset backwards along the velocity by off = 3 a.
+__global__ void k_md_return(const int32_t* __restrict__ sp,
+                            const uint64_t* __restrict__ id,
+                            const double* __restrict__ pos,
+                            const double* __restrict__ vel, long long nab,
+                            long long first, long long n, double off3a,
+                            GridC g, double* __restrict__ opos,
+                            double* __restrict__ ovel,
+                            uint64_t* __restrict__ oid,
+                            int32_t* __restrict__ osp, long long out0,
+                            long long nout) {
+  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < n;
+       r += (long long)gridDim.x * blockDim.x) {
+    const long long q = first + r, o = out0 + r;
+    const double vx = vel[q], vy = vel[nab + q], vz = vel[2 * nab + q];
+    const double inv = 1.0 / sqrt((vx * vx + vy * vy) + vz * vz);
+    const double off = off3a * inv;
+    opos[o] = wrap_coord(pos[q] - off * vx, g.lx);
+    opos[nout + o] = wrap_coord(pos[nab + q] - off * vy, g.ly);
+    opos[2 * nout + o] = pos[2 * nab + q] - off * vz;
+    ovel[o] = vx; ovel[nout + o] = vy; ovel[2 * nout + o] = vz;
+    oid[o] = id[q];
+    if (osp) osp[o] = sp[q];
+  }
+}
+
 // ---- binning ------------------------------------------------------------------
 // Particles of a binned tile move at most one tile per axis per step, so a
 // tile's particles go to one of its 27 neighbours (slot d of dest_slot);
@@ -2410,6 +2487,14 @@ MccC mcc_constants(const pic_ctx* c, double dt) {
   m.half_me = 0.5 * kMe;
   m.ratio = (2.0 * kMe) / kMcu;
   m.two_e_me = (2.0 * kE) / kMe;
+  const pic_sources& s = c->src;
+  m.sph_on = s.sph_absorb ? 1 : 0;
+  m.sph_cx = s.sph_cx;
+  m.sph_cy = s.sph_cy;
+  m.sph_cz = s.sph_cz;
+  m.sph_r2 = s.sph_radius * s.sph_radius;
+  m.sph_alpha = s.sph_alpha_eh;
+  m.dt = dt;
   return m;
 }
 
@@ -2937,6 +3022,27 @@ void compact_neutrals_t(pic_ctx* c) {
 }
 
 }  // namespace
+
+void parts_md_return(pic_ctx* c, double lattice_a, unsigned mask,
+                     double* pos, double* vel, uint64_t* ids, int32_t* sp,
+                     long long nout) {
+  long long nab = (long long)c->hc.n_ab;
+  if (nab > c->cfg.max_events) nab = c->cfg.max_events;
+  const double off3a = 3.0 * lattice_a;
+  long long first = 0, out0 = 0;
+  for (int s = 0; s < 3; ++s) {
+    const long long n = (long long)c->hc.cathode[s];
+    if ((mask >> s) & 1u) {
+      if (n > 0)
+        k_md_return<<<(unsigned)std::min<long long>((n + kT - 1) / kT, 1024),
+                      kT, 0, c->stream>>>(c->ab_species, c->ab_id, c->ab_pos,
+                                          c->ab_vel, nab, first, n, off3a,
+                                          c->g, pos, vel, ids, sp, out0, nout);
+      out0 += n;
+    }
+    first += n;
+  }
+}
 
 void parts_deposit(pic_ctx* c) {
   tmark(c, PIC_PH_DEPOSIT, true);

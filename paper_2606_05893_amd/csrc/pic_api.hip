@@ -189,6 +189,10 @@ size_t carve(pic_ctx* c, char* base) {
   c->q_vel = cv.take<double>(3 * f.queue_capacity);
   c->fn_scan = cv.take<unsigned>(2 * c->g.nxy + 2);
   c->dc = cv.take<Counters>(1);
+  c->dbg_mom = cv.take<double>(debye_moment_doubles(c->ncells));
+  c->dbg_qpart = cv.take<long long>(2048);
+  c->dbg_part = cv.take<double>(2048);
+  c->dbg_out = cv.take<double>(4);
   c->warm_x = cv.take<float>(2 * c->g.nxy * f.nz);
   c->warm_prev = cv.take<double>(c->nnodes);
   c->phi_hist = cv.take<double>(c->nnodes);
@@ -357,6 +361,8 @@ void fill_diag(pic_ctx* c, pic_diag* d) {
   d->near_threshold = (long long)h.n_near;
   d->total_charge_units = h.total_charge;
   d->field_energy = h.field_energy;
+  d->np_absorbed = (long long)h.np_hits;
+  d->np_heat = h.np_heat;
   d->solve = c->last_solve;
   d->step = c->step;
   d->next_id = c->next_id;
@@ -533,7 +539,12 @@ pic_status pic_set_sources(pic_ctx* c, const pic_sources* s) {
        (s->sph_n < 0 || !(s->sph_radius >= 0.0) || !(s->sph_radius < lmin) ||
         !in_xy(s->sph_cx, s->sph_cy) || !(s->sph_cz - s->sph_radius >= 0.0) ||
         !((s->sph_cz + s->sph_radius) * c->g.inv_dx < (double)c->g.nz))) ||
-      (s->fn_on && !(s->fn_phi_w_eV > 0.0)))
+      (s->fn_on && !(s->fn_phi_w_eV > 0.0)) ||
+      (s->sph_absorb &&
+       (!(s->sph_radius > 0.0) || !(s->sph_radius < 0.5 * lmin) ||
+        !in_xy(s->sph_cx, s->sph_cy) || !(s->sph_cz - s->sph_radius >= 0.0) ||
+        !((s->sph_cz + s->sph_radius) * c->g.inv_dx < (double)c->g.nz) ||
+        !(s->sph_alpha_eh >= 0.0 && s->sph_alpha_eh <= 1.0))))
     return set_err(c, PIC_ERR_ARG, "invalid source parameters");
   (void)lz;
   c->src = *s;
@@ -1045,6 +1056,57 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
     return set_err(c, PIC_ERR_ARG, "checkpoint holds particles outside the domain");
   }
   return hip_ok(c, hipStreamSynchronize(c->stream), "synchronise") ? PIC_OK : PIC_ERR_HIP;
+}
+
+pic_status pic_md_return(pic_ctx* c, double lattice_a, uint32_t mask,
+                         int64_t cap, double* pos, double* vel, uint64_t* ids,
+                         int32_t* species, int64_t* n) {
+  if (!c || !n || !(lattice_a >= 0.0) || (mask & ~7u)) return PIC_ERR_ARG;
+  if (c->step == 0) return set_err(c, PIC_ERR_STATE, "no step taken yet");
+  long long tot = 0;
+  for (int s = 0; s < 3; ++s)
+    if ((mask >> s) & 1u) tot += (long long)c->hc.cathode[s];
+  *n = tot;
+  if (cap < tot) return set_err(c, PIC_ERR_CAPACITY, "output buffers too small");
+  if (tot == 0) return PIC_OK;
+  if (!pos || !vel || !ids) return PIC_ERR_ARG;
+  parts_md_return(c, lattice_a, mask, pos, vel, ids, species, cap);
+  if (!hip_ok(c, hipGetLastError(), "md return launch") ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "synchronise"))
+    return PIC_ERR_HIP;
+  return PIC_OK;
+}
+
+pic_status pic_debye_check(pic_ctx* c, int32_t block, double alpha_D,
+                           double* lambda, pic_debye_info* info) {
+  if (!c || !info) return PIC_ERR_ARG;
+  if ((block != 1 && block != 2 && block != 4 && block != 8) ||
+      c->cfg.nx % block || c->cfg.ny % block || c->cfg.nz % block ||
+      !(alpha_D > 0.0) || !std::isfinite(alpha_D))
+    return set_err(c, PIC_ERR_ARG, "block must be 1, 2, 4 or 8 and divide the grid");
+  tmark(c, PIC_PH_DEBYE, true);
+  parts_debye(c, block, alpha_D, lambda, c->dbg_out);
+  tmark(c, PIC_PH_DEBYE, false);
+  double out[4];
+  if (!hip_ok(c, hipGetLastError(), "debye launch") ||
+      !hip_ok(c, hipMemcpyAsync(out, c->dbg_out, sizeof(out),
+                                hipMemcpyDeviceToHost, c->stream),
+              "debye readback") ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "synchronise"))
+    return PIC_ERR_HIP;
+  collect_times(c);
+  info->blocks = (int64_t)(c->cfg.nx / block) * (c->cfg.ny / block) *
+                 (c->cfg.nz / block);
+  info->checked = (int64_t)out[0];
+  info->unresolved = (int64_t)out[1];
+  info->lambda_min = out[2];
+  info->ratio_max = out[3];
+  return PIC_OK;
+}
+
+double pic_alpha_eh(double R, double d, double ell, double phi_w_eV,
+                    double E_e_eV) {
+  return ((1.0 - R) * (1.0 - std::exp(-d / ell))) * (1.0 - phi_w_eV / E_e_eV);
 }
 
 pic_status pic_count(pic_ctx* c, int32_t s, int64_t* n) {

@@ -131,6 +131,13 @@ struct pic_ctx {
   double *q_pos, *q_vel;
   unsigned* fn_scan;         // nx*ny + 1
 
+  // Debye-length check: per-block moments of electrons and ions, block
+  // partials of its reductions and its four results.
+  double* dbg_mom;
+  long long* dbg_qpart;
+  double* dbg_part;
+  double* dbg_out;
+
   pic::Counters* dc;         // device counters
   pic::Counters hc;          // host copy after the last sync
 
@@ -205,7 +212,21 @@ void field_phi_to_level0(pic_ctx* c);
 void field_extrapolate(pic_ctx* c);
 
 // ---- particles (k_particles.hip) -------------------------------------------
+// ---- diagnostics (k_debye.hip) ---------------------------------------------
+// Doubles of the per-block moment records for ncells cells (block = 1).
+long long debye_moment_doubles(long long ncells);
+// Debye-length check over blocks of block^3 cells; lam_out (may be null):
+// lambda_D per block; out (device, 4 doubles): checked, unresolved,
+// lambda_min, ratio_max.
+void parts_debye(pic_ctx* c, int block, double alpha_D, double* lam_out,
+                 double* out);
+
 void parts_deposit(pic_ctx* c);
+// The last step's cathode records of the species in mask, offset back along
+// their velocity by 3 lattice_a, into SoA outputs of stride nout.
+void parts_md_return(pic_ctx* c, double lattice_a, unsigned mask,
+                     double* pos, double* vel, uint64_t* ids, int32_t* sp,
+                     long long nout);
 // One step's particle work: host-known sources (and the counter reset) and
 // the neutral push need no field; the Fowler-Nordheim source, the charged
 // pushes and the collisions do.

@@ -267,6 +267,7 @@ struct Counters {
   unsigned long long n_dead;        // removed neutrals (compaction)
   unsigned long long n_holes;       // ... of them below the new count
   unsigned long long n_movers;      // live neutrals above it (= n_holes)
+  unsigned long long np_hits;       // electrons absorbed by the nanoparticle
   long long total_charge;
   unsigned int err;                 // sticky error bits (kErr*)
   int vcycles;
@@ -276,6 +277,7 @@ struct Counters {
   double b_norm;
   double kinetic[3];
   double field_energy;
+  double np_heat;                   // alpha_EH * their kinetic energy, J
   // Warm start of the field solve.
   double warm_r0;                   // ||r|| of the previous potential
   double sigma;                     // RMS of that residual over unknowns

@@ -53,14 +53,14 @@ class Collisions(ctypes.Structure):
 
 class Sources(ctypes.Structure):
     _fields_ = [("disk_on", _c_i32), ("fn_on", _c_i32), ("sphere_on", _c_i32),
-                ("reserved", _c_i32), ("disk_cx", _c_d), ("disk_cy", _c_d),
+                ("sph_absorb", _c_i32), ("disk_cx", _c_d), ("disk_cy", _c_d),
                 ("disk_radius", _c_d), ("disk_n_e", _c_i64),
                 ("disk_kT_e_eV", _c_d), ("disk_n_n", _c_i64),
                 ("disk_T_n_K", _c_d), ("fn_cx", _c_d), ("fn_cy", _c_d),
                 ("fn_radius", _c_d), ("fn_phi_w_eV", _c_d),
                 ("fn_kT_e_eV", _c_d), ("sph_cx", _c_d), ("sph_cy", _c_d),
                 ("sph_cz", _c_d), ("sph_radius", _c_d), ("sph_n", _c_i64),
-                ("sph_T_K", _c_d)]
+                ("sph_T_K", _c_d), ("sph_alpha_eh", _c_d)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -78,7 +78,14 @@ class Diag(ctypes.Structure):
                 ("starved", _c_i64), ("over_majorant", _c_i64),
                 ("near_threshold", _c_i64), ("total_charge_units", _c_i64),
                 ("kinetic", _c_d * 3), ("field_energy", _c_d),
-                ("solve", SolveInfo), ("step", _c_i64), ("next_id", _c_u64)]
+                ("solve", SolveInfo), ("step", _c_i64), ("next_id", _c_u64),
+                ("np_absorbed", _c_i64), ("np_heat", _c_d)]
+
+
+class DebyeInfo(ctypes.Structure):
+    _fields_ = [("blocks", _c_i64), ("checked", _c_i64),
+                ("unresolved", _c_i64), ("lambda_min", _c_d),
+                ("ratio_max", _c_d)]
 
 
 class Absorbed(ctypes.Structure):
@@ -121,6 +128,11 @@ EXPORTS = {
     "pic_enable_timing": (_c_i32, [_c_p, _c_i32]),
     "pic_phase_times": (_c_i32, [_c_p, ctypes.POINTER(_c_d),
                                  ctypes.POINTER(_c_i64)]),
+    "pic_md_return": (_c_i32, [_c_p, _c_d, _c_u32, _c_i64, _c_p, _c_p, _c_p,
+                               _c_p, ctypes.POINTER(_c_i64)]),
+    "pic_alpha_eh": (_c_d, [_c_d, _c_d, _c_d, _c_d, _c_d]),
+    "pic_debye_check": (_c_i32, [_c_p, _c_i32, _c_d, _c_p,
+                                 ctypes.POINTER(DebyeInfo)]),
     "poisson_solve_static": (_c_i32, [ctypes.POINTER(Config), _c_p, _c_p,
                                       _c_i32, ctypes.POINTER(SolveInfo),
                                       _c_p]),
@@ -128,7 +140,7 @@ EXPORTS = {
 
 PHASES = ("deposit", "rhs", "poisson", "efield", "sources", "push_neutral",
           "push_ion", "push_electron", "collide", "absorbed", "bin", "warm",
-          "smooth_l0")
+          "smooth_l0", "debye", "coulomb", "ion_coll")
 WARM_MODES = {"prev": 0, "record": 1, "unet": 2, "extrap": 3}
 
 _lib = None
@@ -221,6 +233,8 @@ def make_sources(d):
         s.sphere_on = 1
         s.sph_cx, s.sph_cy, s.sph_cz = q["cx"], q["cy"], q["cz"]
         s.sph_radius, s.sph_n, s.sph_T_K = q["radius"], int(q["n"]), q["T_K"]
+        s.sph_absorb = int(bool(q.get("absorb", False)))
+        s.sph_alpha_eh = float(q.get("alpha_eh", 0.5))
     return s
 
 
@@ -419,6 +433,47 @@ class Pic:
     def restore(self, data):
         buf = ctypes.create_string_buffer(bytes(data), len(data))
         self._call("pic_checkpoint_load", buf, len(data))
+
+    def md_return(self, lattice_a, species=(ION,)):
+        """Atoms handed back to MD from the last step's cathode list: dict
+        of species, id, pos (n, 3), vel (n, 3) device tensors."""
+        mask = 0
+        for sp in species:
+            mask |= 1 << int(sp)
+        n = _c_i64()
+        # First call with no room: the count (PIC_ERR_CAPACITY if non-zero).
+        st = self.lib.pic_md_return(self.ctx, float(lattice_a), mask, 0, None,
+                                    None, None, None, ctypes.byref(n))
+        if st not in (0, -2):
+            self._check(st, self.ctx)
+        k = n.value
+        with torch.cuda.stream(self.stream):
+            pos = torch.empty((3, max(k, 1)), dtype=torch.float64,
+                              device="cuda")
+            vel = torch.empty_like(pos)
+            ids = torch.empty(max(k, 1), dtype=torch.int64, device="cuda")
+            sp_t = torch.empty(max(k, 1), dtype=torch.int32, device="cuda")
+        self._call("pic_md_return", float(lattice_a), mask, k, _ptr(pos),
+                   _ptr(vel), _ptr(ids), _ptr(sp_t), ctypes.byref(n))
+        self._hand_over(pos, vel, ids, sp_t)
+        return {"species": sp_t[:k], "id": ids[:k],
+                "pos": pos[:, :k].t(), "vel": vel[:, :k].t()}
+
+    def debye_check(self, block=1, alpha_D=0.5, with_lambda=True):
+        """(info dict, lambda_D per block (bz, by, bx) device tensor or
+        None)."""
+        lam = None
+        if with_lambda:
+            shp = (self.p["nz"] // block, self.p["ny"] // block,
+                   self.p["nx"] // block)
+            with torch.cuda.stream(self.stream):
+                lam = torch.empty(shp, dtype=torch.float64, device="cuda")
+        info = DebyeInfo()
+        self._call("pic_debye_check", int(block), float(alpha_D), _ptr(lam),
+                   ctypes.byref(info))
+        if lam is not None:
+            self._hand_over(lam)
+        return _struct_dict(info), lam
 
     def set_clock(self, step, next_id):
         self._call("pic_set_clock", int(step), int(next_id))
