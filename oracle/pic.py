@@ -731,6 +731,9 @@ def advance(state, params, E, dt):
         _append(state.sp[C.ION], ions["x"], ions["y"], ions["z"],
                 ions["vx"], ions["vy"], ions["vz"], ions["id"])
         state.sp[C.NEUTRAL] = _select(state.sp[C.NEUTRAL], ~consumed)
+    # Coulomb collisions of the charged particles the step leaves.
+    from .coulomb import coulomb
+    diag["coulomb_like"], diag["coulomb_ei"] = coulomb(state, params, dt)
     if absorbed:
         ab = {k: np.concatenate([a[k] for a in absorbed]) for k in absorbed[0]}
         order = np.lexsort((ab["id"], ab["species"]))
