@@ -17,7 +17,9 @@ M_CU = M_CU_AMU * AMU               # Cu atom and Cu+ ion mass (electron mass
 TWO_PI = 6.283185307179586          # 2*pi rounded to binary64
 E_EULER = 2.718281828459045         # e rounded to binary64
 
-# Species indices.
-ELECTRON, NEUTRAL, ION = 0, 1, 2
-CHARGE_SIGN = (-1, 0, +1)
-MASS = (M_E, M_CU, M_CU)
+# Species indices: electron, Cu atom, Cu+ and Cu2+ (a higher charge state
+# made by electron-impact ionisation of Cu+).
+ELECTRON, NEUTRAL, ION, ION2 = 0, 1, 2, 3
+NSPECIES = 4
+CHARGE_SIGN = (-1, 0, +1, +2)
+MASS = (M_E, M_CU, M_CU, M_CU)

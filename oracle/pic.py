@@ -71,7 +71,7 @@ class State:
         self.grid = grid
         self.seed = int(seed)
         self.w_sp = int(w_sp)
-        self.sp = [empty_species() for _ in range(3)]
+        self.sp = [empty_species() for _ in range(C.NSPECIES)]
         self.step = 0
         self.next_id = 0
         self.queue = []                 # (species, pos (n,3), vel (n,3))
@@ -123,12 +123,13 @@ def deposit(state):
     """int64 node charges: sum over charged particles of s * Wa * Wb * Wc.
 
     One unit is 2^-39 of a superparticle's charge (times w_sp, applied in the
-    right-hand side).  Sum over all nodes = 2^39 * (N_ion - N_electron).
+    right-hand side).  Sum over all nodes =
+    2^39 * (N_ion + 2 N_ion2 - N_electron).
     """
     g = state.grid
     acc = np.zeros(g.shape, dtype=np.int64)
     flat = acc.reshape(-1)
-    for s, sign in ((C.ELECTRON, -1), (C.ION, +1)):
+    for s, sign in ((C.ELECTRON, -1), (C.ION, +1), (C.ION2, +2)):
         sp = state.sp[s]
         if sp["x"].size == 0:
             continue
@@ -254,7 +255,7 @@ def sources(state, params, E, dt, near):
     """
     g = state.grid
     step, seed = state.step, state.seed
-    new = {s: [] for s in range(3)}
+    new = {s: [] for s in range(C.NSPECIES)}
     nid = state.next_id
 
     def take(n):
@@ -683,19 +684,19 @@ def advance(state, params, E, dt):
     diag = {"candidates": 0, "elastic": 0, "ionisations": 0, "starved": 0,
             "over_majorant": 0}
     new, n_fn = sources(state, params, E, dt, near)
-    emitted = {s: 0 for s in range(3)}
-    for s in range(3):
+    emitted = {s: 0 for s in range(C.NSPECIES)}
+    for s in range(C.NSPECIES):
         for parts in new[s]:
             _append(state.sp[s], *parts)
             emitted[s] += parts[0].size
     absorbed = []
-    anode = [0, 0, 0]
-    cath_count = [0, 0, 0]
-    ke = [0.0, 0.0, 0.0]
+    anode = [0] * C.NSPECIES
+    cath_count = [0] * C.NSPECIES
+    ke = [0.0] * C.NSPECIES
     sph = params.get("sources", {}).get("sphere")
     absorber = sph if (sph and sph.get("absorb")) else None
     np_hits, np_heat = 0, 0.0
-    for s in (C.NEUTRAL, C.ION, C.ELECTRON):
+    for s in (C.NEUTRAL, C.ION, C.ION2, C.ELECTRON):
         sp = state.sp[s]
         cath, an, xc, yc = push(sp, s, E, g, dt, absorber)
         ke[s] = kinetic_energy(sp, s)
@@ -734,6 +735,9 @@ def advance(state, params, E, dt):
     # Coulomb collisions of the charged particles the step leaves.
     from .coulomb import coulomb
     diag["coulomb_like"], diag["coulomb_ei"] = coulomb(state, params, dt)
+    # Recombination, ionisation of Cu+ and charge exchange.
+    from .ionproc import ion_processes
+    ion_processes(state, params, dt, near, diag)
     if absorbed:
         ab = {k: np.concatenate([a[k] for a in absorbed]) for k in absorbed[0]}
         order = np.lexsort((ab["id"], ab["species"]))
@@ -745,7 +749,7 @@ def advance(state, params, E, dt):
     diag.update(near=near, emitted=emitted, fn_emitted=n_fn,
                 cathode=cath_count, anode=anode, kinetic=ke,
                 np_hits=np_hits, np_heat=np_heat,
-                counts=[state.count(s) for s in range(3)])
+                counts=[state.count(s) for s in range(C.NSPECIES)])
     state.step += 1
     return ab, diag
 
