@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--variant", default="all",
                     choices=["all", "fp64", "mixed", "learned_mixed", "fp64_prev",
-                             "fp64_np"],
+                             "fp64_np", "fp64_coulomb"],
                     help="fp64: plain FP64 multigrid; mixed: FP32 particles and "
                          "smoothing with FP64 refinement; learned_mixed: mixed "
                          "with the U-Net warm start (trained first on pairs "
@@ -171,7 +171,9 @@ def capacities(p, total_steps):
 def new_context(G, p, precision, pre, n0, cap):
     q = dict(p)
     q["precision"] = precision
-    gpu = G.Pic(q, capacity=cap, max_events=1 << 17, queue_capacity=1 << 10)
+    flags = G.FLAG_CELL_GROUPS if q.get("coulomb") else 0
+    gpu = G.Pic(q, capacity=cap, max_events=1 << 17, queue_capacity=1 << 10,
+                flags=flags)
     for s, (pos, vel, ids) in pre.items():
         gpu.load(s, pos, vel, ids)
     gpu.set_clock(0, n0)
@@ -227,12 +229,14 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
         gpu.step(dt)
     counts = [gpu.count(s) for s in range(3)]
     nps = []
+    couls = []
 
     def timed(k):
         nonlocal counts
         psteps = 0
         solves, electrons, ions = [], [], []
         nps.clear()
+        couls.clear()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(k):
@@ -243,6 +247,7 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
             counts = d["counts"]
             solves.append(d["solve"])
             nps.append((d["np_absorbed"], d["np_heat"]))
+            couls.append((d["coulomb_like"], d["coulomb_ei"]))
         torch.cuda.synchronize()
         return time.perf_counter() - t0, psteps, solves, electrons, ions
 
@@ -298,6 +303,9 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
         out["fallback_rate"] = float(np.mean([d["warm_rejected"] for d in solves]))
     if diag is not None:
         out["debye_check"] = diag
+    if any(a + b for a, b in couls):
+        out["coulomb_like_avg"] = float(np.mean([a for a, _ in couls]))
+        out["coulomb_ei_avg"] = float(np.mean([b for _, b in couls]))
     if any(h for h, _ in nps):
         out["np_absorbed_avg"] = float(np.mean([h for h, _ in nps]))
         out["np_heat_J_avg"] = float(np.mean([e for _, e in nps]))
@@ -393,7 +401,8 @@ def main():
     if cpu is not None:
         progress(f"cpu baseline: {cpu['value']:.3e} particle-steps/s on "
                  f"{cpu['cores']} cores")
-    variants = (["fp64", "mixed", "learned_mixed", "fp64_prev", "fp64_np"]
+    variants = (["fp64", "mixed", "learned_mixed", "fp64_prev", "fp64_np",
+                 "fp64_coulomb"]
                 if a.variant == "all" else [a.variant])
     cap, per_step_n = capacities(p, a.warmup + 2 * a.steps)
     torch.cuda.set_device(0)
@@ -417,6 +426,10 @@ def main():
                 cx=p["nx"] * p["dx"] / 2, cy=p["ny"] * p["dx"] / 2,
                 cz=200e-9, radius=5e-9, n=0, T_K=3500.0, absorb=True,
                 alpha_eh=0.5)
+        if v == "fp64_coulomb":
+            # Coulomb binary collisions of all charged particles each step.
+            pv = dict(p)
+            pv["coulomb"] = dict(enabled=True, ln_lambda=10.0)
         res[v] = run_variant(G, pv, prec, pre, n0, cap, a.steps, a.warmup,
                              net if v == "learned_mixed" else None,
                              warm="prev" if v == "fp64_prev" else "extrap",

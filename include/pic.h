@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define PIC_ABI_VERSION 4
+#define PIC_ABI_VERSION 5
 
 typedef enum {
   PIC_OK = 0,
@@ -54,17 +54,24 @@ typedef enum {
   PIC_ERR_STATE = -6      /* call not valid in the current state          */
 } pic_status;
 
-enum { PIC_ELECTRON = 0, PIC_NEUTRAL = 1, PIC_ION = 2 };
+/* Species: electrons, Cu atoms, Cu+ and Cu2+ (the higher charge state made
+ * by electron-impact ionisation of Cu+, see pic_set_ion_processes). */
+enum { PIC_ELECTRON = 0, PIC_NEUTRAL = 1, PIC_ION = 2, PIC_ION2 = 3 };
+#define PIC_NSPECIES 4
 enum { PIC_BC_DIRICHLET = 0, PIC_BC_NEUMANN = 1 };
 enum { PIC_FP64 = 0, PIC_MIXED = 1 };
 enum { PIC_ION_LOTZ = 0, PIC_ION_CONST = 1 };
-/* PIC_FLAG_PLAIN_SMOOTHER: smooth with one launch per colour and sweep
+/* PIC_FLAG_CELL_GROUPS: reserve the workspace that groups the charged
+ * particles by cell each step (about 16 bytes per particle of capacity and
+ * 8 per cell), needed by the Coulomb collisions (pic_set_coulomb).
+ * PIC_FLAG_PLAIN_SMOOTHER: smooth with one launch per colour and sweep
  * instead of the fused two-sweep pass (same arithmetic, same results).
  * PIC_FLAG_MG_ALL_LEVELS: run the V-cycle down to the coarsest level
  * instead of solving the first coarse level small enough exactly (at most
  * 64 x 64 nodes per plane if both are powers of two, else 32 x 32, and 256
  * unknown planes: 2-D DFT in x, y, tridiagonal solve in z per mode). */
-enum { PIC_FLAG_PLAIN_SMOOTHER = 1, PIC_FLAG_MG_ALL_LEVELS = 2 };
+enum { PIC_FLAG_PLAIN_SMOOTHER = 1, PIC_FLAG_MG_ALL_LEVELS = 2,
+       PIC_FLAG_CELL_GROUPS = 4 };
 enum { PIC_WARM_ZERO = 0, PIC_WARM_GIVEN = 1 };
 /* Warm start of the field solve in pic_step / pic_field (and of
  * poisson_solve with PIC_WARM_GIVEN): the previous potential; the same
@@ -97,7 +104,8 @@ typedef struct {
   uint64_t seed;           /* Philox key                                   */
   uint32_t w_sp;           /* superparticle weight (all species), >= 1     */
   uint32_t flags;          /* PIC_FLAG_* (0 by default)                    */
-  int64_t capacity[3];     /* particles per species (electron, Cu, Cu+)    */
+  int64_t capacity[PIC_NSPECIES]; /* particles per species (electron, Cu,
+                              Cu+, Cu2+)                                   */
   int64_t queue_capacity;  /* particles pic_inject may queue per step      */
   int64_t max_events;      /* ionisation events / cathode absorptions /
                               Fowler-Nordheim electrons per step           */
@@ -114,6 +122,58 @@ typedef struct {
   double sigma_ion_const;  /* PIC_ION_CONST cross section above I, m^2     */
   double E_max_eV;         /* majorant energy of the null-collision method */
 } pic_collisions;
+
+/* Coulomb collisions by binary pairing within cells (the paper's Monte
+ * Carlo collisions, after Takizuka & Abe), applied each step after the
+ * electron-neutral collisions to the charged particles of every cell.  A
+ * cell's electrons and its ions are each put in a random order (ascending
+ * 53-bit Philox draw of (id, step), then id); consecutive particles pair,
+ * an odd count N >= 3 starts with a triplet (0,1), (1,2), (2,0) of
+ * half-variance collisions; then max(N_e, N_i) electron-ion collisions,
+ * collision k between electron k mod N_e and ion k mod N_i in ascending k,
+ * at the lower density.  Each collision turns the relative velocity u by
+ * theta with tan(theta/2) normal of variance
+ * e^4 n lnL dt / (8 pi eps0^2 m_r^2 |u|^3) and a uniform azimuth, keeping
+ * momentum and energy.  Cells with more than 2048 charged particles set
+ * the event error (PIC_ERR_CAPACITY).  Needs PIC_FLAG_CELL_GROUPS. */
+typedef struct {
+  int32_t enabled;         /* 0: off (default)                             */
+  int32_t reserved;
+  double ln_lambda;        /* Coulomb logarithm lnL, e.g. 10               */
+} pic_coulomb;
+pic_status pic_set_coulomb(pic_ctx* ctx, const pic_coulomb* c);
+
+/* Recombination, electron-impact ionisation of Cu+ and resonant charge
+ * exchange (the paper's Monte Carlo collisions include charge exchange and
+ * recombination, and its ions reach several charge levels), applied each
+ * step after the Coulomb collisions.  The paper gives no cross sections;
+ * they are parameters:
+ *   sigma_rec(E) = sigma_rec_1eV * (1 eV / max(E, 1e-3 eV)),
+ *   sigma_ion2(E) = lotz_a2 ln(E / I2) / (E I2) for E > I2, else 0,
+ *   sigma_cx(eps) = max(cx_a - cx_b ln(max(eps, 1e-6 eV) / 1 eV), 0)^2
+ *     with eps = m_r u^2 / 2 of the Cu+ / Cu pair (eV).
+ * Per cell, electrons, Cu+ and Cu each in a random order (53-bit Philox
+ * draw of (id, step), then id): each electron collides with probability
+ * 1 - exp(-n_i (sigma_rec + sigma_ion2) v dt) (Eq. 4, n_i the cell's Cu+
+ * density), the r-th colliding one with the r-th Cu+ (none left:
+ * starved); recombination leaves a Cu atom with the ion's position and id
+ * and the pair's centre-of-mass velocity; ionisation shares the energy
+ * above I2 uniformly between two isotropic electrons (the secondary at the
+ * primary's position, ids next_id + rank by primary id) and makes the ion
+ * a Cu2+.  Then each Cu+ left meets atom k mod N_n of the cell's atoms with
+ * probability 1 - exp(-n_n sigma_cx u dt) (u the pair's relative speed):
+ * the two records exchange position, velocity and id.  Crowded cells
+ * (more than 2048 particles) set the event error.  Needs
+ * PIC_FLAG_CELL_GROUPS (its records then cover electrons, Cu and Cu+). */
+typedef struct {
+  int32_t enabled;         /* 0: off (default)                             */
+  int32_t reserved;
+  double sigma_rec_1eV;    /* m^2                                          */
+  double lotz_a2;          /* m^2 eV^2                                     */
+  double ion2_I_eV;        /* Cu+ -> Cu2+ threshold, eV (20.29)            */
+  double cx_a, cx_b;       /* m                                            */
+} pic_ion_processes;
+pic_status pic_set_ion_processes(pic_ctx* ctx, const pic_ion_processes* p);
 
 /* Per-step particle sources at the cathode and in the gap, and the
  * nanoparticle as an electron sink. */
@@ -158,11 +218,11 @@ typedef struct {
 } pic_solve_info;
 
 typedef struct {
-  int64_t counts[3];          /* live particles after the step             */
-  int64_t emitted[3];         /* particles added by queue and sources      */
+  int64_t counts[PIC_NSPECIES];          /* live particles after the step             */
+  int64_t emitted[PIC_NSPECIES];         /* particles added by queue and sources      */
   int64_t fn_emitted;         /* of which Fowler-Nordheim electrons        */
-  int64_t cathode[3];         /* absorbed at z = 0                         */
-  int64_t anode[3];           /* absorbed at z = nz*dx                     */
+  int64_t cathode[PIC_NSPECIES];         /* absorbed at z = 0                         */
+  int64_t anode[PIC_NSPECIES];           /* absorbed at z = nz*dx                     */
   int64_t candidates;         /* null-collision candidates                 */
   int64_t elastic;
   int64_t ionisations;        /* successful (matched) ionisations          */
@@ -171,13 +231,19 @@ typedef struct {
   int64_t near_threshold;     /* draws within 1e-6 of a threshold that
                                  involves a transcendental function        */
   int64_t total_charge_units; /* sum of node charges, 2^-39 w_sp e units   */
-  double kinetic[3];          /* kinetic energy after the push, J          */
+  double kinetic[PIC_NSPECIES]; /* kinetic energy after the push, J        */
   double field_energy;        /* 1/2 sum q phi over nodes, J               */
   pic_solve_info solve;
   int64_t step;               /* steps completed                           */
   uint64_t next_id;           /* next particle id to assign                */
   int64_t np_absorbed;        /* electrons absorbed by the nanoparticle    */
   double np_heat;             /* alpha_EH * sum of their energies, J       */
+  int64_t coulomb_like;       /* Coulomb collisions of like pairs          */
+  int64_t coulomb_ei;         /* ... and electron-ion                      */
+  int64_t recombinations;     /* e + Cu+ -> Cu                             */
+  int64_t ionisations2;       /* e + Cu+ -> 2e + Cu2+                      */
+  int64_t charge_exchanges;   /* Cu+ + Cu -> Cu + Cu+                      */
+  int64_t ion_starved;        /* electron-ion events without a Cu+ left    */
 } pic_diag;
 
 /* Particles absorbed at the cathode in the last step, sorted by

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
 SOURCES = ["pic_api.hip", "k_field.hip", "k_particles.hip", "k_unet.hip",
-           "k_debye.hip"]
+           "k_debye.hip", "k_coulomb.hip", "k_ionproc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",

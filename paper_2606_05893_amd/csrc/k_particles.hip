@@ -201,11 +201,11 @@ __global__ void k_chunk_fill(const unsigned* __restrict__ cstart, long long nt,
 // ---- step bookkeeping ---------------------------------------------------------
 __global__ void k_begin(Counters* dc, unsigned long long n0,
                         unsigned long long n1, unsigned long long n2,
-                        unsigned long long next_id) {
-  dc->n[0] = n0; dc->n[1] = n1; dc->n[2] = n2;
+                        unsigned long long n3, unsigned long long next_id) {
+  dc->n[0] = n0; dc->n[1] = n1; dc->n[2] = n2; dc->n[3] = n3;
   dc->next_id = next_id;
   dc->fn_total = 0;
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < 4; ++s) {
     dc->cathode[s] = 0; dc->anode[s] = 0; dc->kinetic[s] = 0.0;
     dc->sorted_n[s] = 0;
   }
@@ -216,6 +216,8 @@ __global__ void k_begin(Counters* dc, unsigned long long n0,
   dc->ion_moved = dc->n_dead1 = dc->n_dead2 = 0;
   dc->np_hits = 0;
   dc->np_heat = 0.0;
+  dc->coul_like = dc->coul_ei = 0;
+  dc->f3_rec = dc->f3_ion2 = dc->f3_cx = dc->f3_starved = 0;
 }
 
 // ---- sources ------------------------------------------------------------------
@@ -1026,7 +1028,8 @@ __global__ void __launch_bounds__(kT) k_push_list(
     if (SP != 1 && o.cell != kDead) {
       int dx_, fx_, dy_, fy_, dz_, fz_;
       cic_stored(Parts(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
-      dep_global(dep, g, dx_, fx_, dy_, fy_, dz_, fz_, SP == 2 ? 1 : -1);
+      dep_global(dep, g, dx_, fx_, dy_, fy_, dz_, fz_,
+                 SP == 0 ? -1 : (SP == 3 ? 2 : 1));
     }
   }
   sink<SP>(p, i, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
@@ -1370,7 +1373,8 @@ __global__ void __launch_bounds__(kT) k_push_list_m(
     if (SP != 1 && o.cell != kDead) {
       int dx_, fx_, dy_, fy_, dz_, fz_;
       cic_stored(PartsM(), o, g, dx_, fx_, dy_, fy_, dz_, fz_);
-      dep_global(dep, g, dx_, fx_, dy_, fy_, dz_, fz_, SP == 2 ? 1 : -1);
+      dep_global(dep, g, dx_, fx_, dy_, fy_, dz_, fz_,
+                 SP == 0 ? -1 : (SP == 3 ? 2 : 1));
     }
   }
   sink_m(p, i, SP, o, g, ab_rec, ab_pos, ab_vel, ab_cap, dc);
@@ -2528,7 +2532,7 @@ void sort_records(pic_ctx* c, Rec* a, Rec* tmp,
 }
 
 double qm_dt(int s, double dt) {
-  const double q = s == 0 ? -kE : (s == 2 ? kE : 0.0);
+  const double q = s == 0 ? -kE : (s == 2 ? kE : (s == 3 ? 2.0 * kE : 0.0));
   const double mass = s == 0 ? kMe : kMcu;
   return (q / mass) * dt;
 }
@@ -2557,6 +2561,11 @@ void deposit_t(pic_ctx* c) {
           cur<PT>(c, s), c->n_binned[s], &c->dc->n[s], c->acc, c->g,
           s ? 1 : -1);
   }
+  // Cu2+ (a list species, two charges each).
+  const long long n3 = bound(c, 3);
+  if (n3 > 0)
+    k_deposit_tail<PT><<<nblk(n3), kT, 0, c->stream>>>(
+        cur<PT>(c, 3), 0, &c->dc->n[3], c->acc, c->g, 2);
 }
 
 // Queue, disk, sphere and Fowler-Nordheim particles, ids in that order.
@@ -2567,7 +2576,7 @@ void sources_host_t(pic_ctx* c) {
   hipStream_t st = c->stream;
   const uint32_t step = (uint32_t)c->step;
   const uint64_t seed = c->cfg.seed;
-  long long n[3] = {c->n[0], c->n[1], c->n[2]};
+  long long n[4] = {c->n[0], c->n[1], c->n[2], c->n[3]};
   c->n_start1 = c->n[1];
   unsigned long long nid = c->next_id;
   for (const QueueCall& q : c->queue) {
@@ -2607,8 +2616,8 @@ void sources_host_t(pic_ctx* c) {
     n[1] += s.sph_n;
     nid += s.sph_n;
   }
-  k_begin<<<1, 1, 0, st>>>(c->dc, n[0], n[1], n[2], nid);
-  for (int k = 0; k < 3; ++k) c->n[k] = n[k];
+  k_begin<<<1, 1, 0, st>>>(c->dc, n[0], n[1], n[2], n[3], nid);
+  for (int k = 0; k < 4; ++k) c->n[k] = n[k];
   c->next_id_src = nid;
 }
 
@@ -2682,7 +2691,8 @@ void push_neutral_t(pic_ctx* c, double dt) {
 
 // Pushes of the FP64 layout.
 void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
-               double* part_i, double* part_l, long long& nbi, long long& nbe) {
+               double* part_i, double* part_l, long long& nbi, long long& nbe,
+               long long& nb3) {
   hipStream_t st = c->stream;
   const uint32_t step = (uint32_t)c->step;
   const uint64_t seed = c->cfg.seed;
@@ -2731,12 +2741,22 @@ void push_fp64(pic_ctx* c, double dt, const MccC& m, double* part_e,
       cur<Parts>(c, 0), c->n_binned[0], c->key[0], c->E, nn, c->g,
       qm_dt(0, dt), dt, c->ncount, c->cand, m, step, seed, c->ab_rec,
       c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi, c->acc_next, c->dead2);
+  // Cu2+: the whole list, field from global memory.
+  const long long n3 = bound(c, 3);
+  nb3 = n3 > 0 ? nblk(n3) : 0;
+  if (n3 > 0)
+    k_push_list<3><<<nb3, kT, 0, st>>>(
+        cur<Parts>(c, 3), 0, c->key[3], c->E, nn, c->g, qm_dt(3, dt), dt,
+        c->ncount, c->cand, m, step, seed, c->ab_rec, c->ab_raw_pos,
+        c->ab_raw_vel, ab_cap, c->dc, part_l + nbi + nbe, c->acc_next,
+        c->dead2);
   tmark(c, PIC_PH_PUSH_ION, false);
 }
 
 // Pushes of the mixed layout (FP32 field, kick and drift).
 void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
-                double* part_i, double* part_l, long long& nbi, long long& nbe) {
+                double* part_i, double* part_l, long long& nbi, long long& nbe,
+                long long& nb3) {
   hipStream_t st = c->stream;
   const uint32_t step = (uint32_t)c->step;
   const uint64_t seed = c->cfg.seed;
@@ -2787,6 +2807,14 @@ void push_mixed(pic_ctx* c, double dt, const MccC& m, double* part_e,
       cur<PartsM>(c, 0), c->n_binned[0], c->key[0], E, nn, c->g,
       (float)qm_dt(0, dt), dtdx, c->ncount, c->cand, m, step, seed, c->ab_rec,
       c->ab_raw_pos, c->ab_raw_vel, ab_cap, c->dc, part_l + nbi, c->acc_next, c->dead2);
+  const long long n3 = bound(c, 3);
+  nb3 = n3 > 0 ? nblk(n3) : 0;
+  if (n3 > 0)
+    k_push_list_m<3><<<nb3, kT, 0, st>>>(
+        cur<PartsM>(c, 3), 0, c->key[3], E, nn, c->g, (float)qm_dt(3, dt),
+        dtdx, c->ncount, c->cand, m, step, seed, c->ab_rec, c->ab_raw_pos,
+        c->ab_raw_vel, ab_cap, c->dc, part_l + nbi + nbe, c->acc_next,
+        c->dead2);
   tmark(c, PIC_PH_PUSH_ION, false);
 }
 
@@ -2804,20 +2832,24 @@ void push_collide_t(pic_ctx* c, double dt) {
   double* part_e = c->partials;
   double* part_i = c->partials + c->nch_cap;
   double* part_l = c->partials + 2 * c->nch_cap;
-  long long nbi = 1, nbe = 1;
+  long long nbi = 1, nbe = 1, nb3 = 0;
   // The pushes and the ionisations add the charge of the state this step
   // leaves; the next deposit takes it instead of a pass of its own.
   hipMemsetAsync(c->acc_next, 0, c->nnodes * sizeof(long long), st);
   if (c->mixed)
-    push_mixed(c, dt, m, part_e, part_i, part_l, nbi, nbe);
+    push_mixed(c, dt, m, part_e, part_i, part_l, nbi, nbe, nb3);
   else
-    push_fp64(c, dt, m, part_e, part_i, part_l, nbi, nbe);
+    push_fp64(c, dt, m, part_e, part_i, part_l, nbi, nbe, nb3);
   const long long nch = c->nch_bound;
   k_sum_partials<<<1, 1024, 0, st>>>(part_i, nch, c->cstart + nt, part_l,
                                      nbi, 0.5 * kMcu, &c->dc->kinetic[2]);
   k_sum_partials<<<1, 1024, 0, st>>>(part_e, nch, c->cstart + nt,
                                      part_l + nbi, nbe, 0.5 * kMe,
                                      &c->dc->kinetic[0]);
+  if (nb3 > 0)
+    k_sum_partials<<<1, 1024, 0, st>>>(part_l + nbi + nbe, nb3, nullptr,
+                                       part_l + nbi + nbe, 0, 0.5 * kMcu,
+                                       &c->dc->kinetic[3]);
   const long long cap = c->cfg.max_events;
   tmark(c, PIC_PH_COLLIDE, true);
   if (m.enabled) {
@@ -2848,6 +2880,21 @@ void push_collide_t(pic_ctx* c, double dt) {
     c->n[0] += cap;  // bound: secondaries
     c->n[2] += cap;
   }
+  if (c->coul.enabled) {
+    // Coulomb collisions of the charged particles the step leaves.
+    tmark(c, PIC_PH_COULOMB, true);
+    parts_coulomb(c, dt);
+    tmark(c, PIC_PH_COULOMB, false);
+  }
+  if (c->ionp.enabled) {
+    // Recombination, ionisation of Cu+ and charge exchange.
+    tmark(c, PIC_PH_ION_COLL, true);
+    parts_ion_processes(c, dt);
+    tmark(c, PIC_PH_ION_COLL, false);
+    c->n[0] += cap;  // bounds: secondaries, atoms, Cu2+
+    c->n[1] += cap;
+    c->n[3] += cap;
+  }
   tmark(c, PIC_PH_COLLIDE, false);
   // Cathode list sorted by (species, id).
   tmark(c, PIC_PH_ABSORBED, true);
@@ -2867,7 +2914,8 @@ template <class PT>
 void bin_species_t(pic_ctx* c, int s) {
   hipStream_t st = c->stream;
   const long long nt = c->ntiles;
-  const bool tiled = s != 1;
+  // Electrons and Cu+ keep tile ranges; Cu atoms and Cu2+ bin as one list.
+  const bool tiled = s == 0 || s == 2;
   uint32_t* ts_old = ts_cur(c, s);
   uint32_t* ts_new = c->tsb[s][c->tcur[s] ^ 1];
   const long long first = tiled ? c->n_binned[s] : 0;
@@ -3023,6 +3071,10 @@ void compact_neutrals_t(pic_ctx* c) {
 
 }  // namespace
 
+void sort_event_records(pic_ctx* c, Rec* a, unsigned long long* count) {
+  sort_records(c, a, c->rec_tmp, count, c->cfg.max_events);
+}
+
 void parts_md_return(pic_ctx* c, double lattice_a, unsigned mask,
                      double* pos, double* vel, uint64_t* ids, int32_t* sp,
                      long long nout) {
@@ -3030,7 +3082,7 @@ void parts_md_return(pic_ctx* c, double lattice_a, unsigned mask,
   if (nab > c->cfg.max_events) nab = c->cfg.max_events;
   const double off3a = 3.0 * lattice_a;
   long long first = 0, out0 = 0;
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < 4; ++s) {
     const long long n = (long long)c->hc.cathode[s];
     if ((mask >> s) & 1u) {
       if (n > 0)
@@ -3237,6 +3289,8 @@ void parts_bin(pic_ctx* c) {
     parts_bin_species(c, 2);
     c->ion_moved_accum = 0;
   }
+  // Cu2+ (few): binned as one list every step, which drops the removed.
+  if (bound(c, 3) > 0) parts_bin_species(c, 3);
   c->tcounted = false;
   // Nothing reads the neutrals by tile (their push streams them, their
   // cell counts are kept from step to step, the event cells are a bit mask

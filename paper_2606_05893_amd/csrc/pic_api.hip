@@ -93,7 +93,7 @@ pic_status validate(const pic_config* c) {
     return PIC_ERR_ARG;
   if (c->sort_every != 1) return PIC_ERR_ARG;
   if (c->w_sp < 1) return PIC_ERR_ARG;
-  for (int s = 0; s < 3; ++s)
+  for (int s = 0; s < PIC_NSPECIES; ++s)
     if (c->capacity[s] < 0 || c->capacity[s] > 0xFFFFFFF0ll) return PIC_ERR_ARG;
   if (c->queue_capacity < 0 || c->max_events < 1) return PIC_ERR_ARG;
   const long long nodes = (long long)c->nx * c->ny * (c->nz + 1);
@@ -107,7 +107,7 @@ size_t carve(pic_ctx* c, char* base) {
   Carver cv{base, 0};
   const pic_config& f = c->cfg;
   const bool mixed = f.precision == PIC_MIXED;
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < PIC_NSPECIES; ++s) {
     const long long cap = f.capacity[s];
     for (int b = 0; b < 2; ++b) {
       if (!mixed) {
@@ -189,6 +189,22 @@ size_t carve(pic_ctx* c, char* base) {
   c->q_vel = cv.take<double>(3 * f.queue_capacity);
   c->fn_scan = cv.take<unsigned>(2 * c->g.nxy + 2);
   c->dc = cv.take<Counters>(1);
+  c->cg_cnt = c->cg_off = c->cg_bsum = c->cg_big = c->cg_nbig = nullptr;
+  c->cg_rec = nullptr;
+  c->ip_ev = nullptr;
+  c->ip_evp = nullptr;
+  c->cg_big_cap = 0;
+  if (f.flags & PIC_FLAG_CELL_GROUPS) {
+    c->cg_cnt = cv.take<unsigned>(c->ncells);
+    c->cg_off = cv.take<unsigned>(c->ncells + 1);
+    c->cg_bsum = cv.take<unsigned>(coulomb_scan_blocks(c->ncells));
+    c->cg_big_cap = std::min<long long>(c->ncells, 1ll << 16);
+    c->cg_big = cv.take<unsigned>(c->cg_big_cap);
+    c->cg_nbig = cv.take<unsigned>(1);
+    c->cg_rec = cv.take<Rec>(f.capacity[0] + f.capacity[1] + f.capacity[2]);
+    c->ip_ev = cv.take<Rec>(c->ev_cap_p2);
+    c->ip_evp = cv.take<uint2>(c->ev_cap_p2);
+  }
   c->dbg_mom = cv.take<double>(debye_moment_doubles(c->ncells));
   c->dbg_qpart = cv.take<long long>(2048);
   c->dbg_part = cv.take<double>(2048);
@@ -279,7 +295,8 @@ void derive(pic_ctx* c) {
       }
     }
   }
-  long long maxcap = std::max(f.capacity[0], std::max(f.capacity[1], f.capacity[2]));
+  long long maxcap = std::max(std::max(f.capacity[0], f.capacity[3]),
+                              std::max(f.capacity[1], f.capacity[2]));
   // Chunk list of the charged species: at most one chunk per tile plus one
   // per 2048 particles.
   c->nch_cap = c->ntiles + (f.capacity[0] + f.capacity[2]) / 2048 + 4;
@@ -346,7 +363,7 @@ void collect_times(pic_ctx* c) {
 void fill_diag(pic_ctx* c, pic_diag* d) {
   if (!d) return;
   const Counters& h = c->hc;
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < PIC_NSPECIES; ++s) {
     d->counts[s] = c->n[s];
     d->cathode[s] = (long long)h.cathode[s];
     d->anode[s] = (long long)h.anode[s];
@@ -363,6 +380,12 @@ void fill_diag(pic_ctx* c, pic_diag* d) {
   d->field_energy = h.field_energy;
   d->np_absorbed = (long long)h.np_hits;
   d->np_heat = h.np_heat;
+  d->coulomb_like = (long long)h.coul_like;
+  d->coulomb_ei = (long long)h.coul_ei;
+  d->recombinations = (long long)h.f3_rec;
+  d->ionisations2 = (long long)h.f3_ion2;
+  d->charge_exchanges = (long long)h.f3_cx;
+  d->ion_starved = (long long)h.f3_starved;
   d->solve = c->last_solve;
   d->step = c->step;
   d->next_id = c->next_id;
@@ -413,7 +436,7 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->ws = reinterpret_cast<char*>(ws);
   c->ws_bytes = bytes;
   carve(c, base);
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < PIC_NSPECIES; ++s) {
     c->cur[s] = 0;
     c->tcur[s] = 0;
     c->n[s] = 0;
@@ -441,6 +464,8 @@ pic_status pic_init(const pic_config* cfg, void* ws, size_t bytes,
   c->net = nullptr;
   c->warm_recorded = false;
   std::memset(&c->coll, 0, sizeof(c->coll));
+  std::memset(&c->coul, 0, sizeof(c->coul));
+  std::memset(&c->ionp, 0, sizeof(c->ionp));
   std::memset(&c->src, 0, sizeof(c->src));
   std::memset(&c->last_solve, 0, sizeof(c->last_solve));
   std::memset(&c->hc, 0, sizeof(c->hc));
@@ -523,6 +548,34 @@ pic_status pic_set_collisions(pic_ctx* c, const pic_collisions* k) {
   return PIC_OK;
 }
 
+pic_status pic_set_coulomb(pic_ctx* c, const pic_coulomb* k) {
+  if (!c || !k) return PIC_ERR_ARG;
+  if (k->enabled) {
+    if (!c->cg_rec)
+      return set_err(c, PIC_ERR_STATE,
+                     "Coulomb collisions need PIC_FLAG_CELL_GROUPS at init");
+    if (!(k->ln_lambda > 0.0) || !std::isfinite(k->ln_lambda))
+      return set_err(c, PIC_ERR_ARG, "invalid Coulomb logarithm");
+  }
+  c->coul = *k;
+  return PIC_OK;
+}
+
+pic_status pic_set_ion_processes(pic_ctx* c, const pic_ion_processes* k) {
+  if (!c || !k) return PIC_ERR_ARG;
+  if (k->enabled) {
+    if (!c->cg_rec)
+      return set_err(c, PIC_ERR_STATE,
+                     "ion processes need PIC_FLAG_CELL_GROUPS at init");
+    if (!(k->sigma_rec_1eV >= 0.0) || !(k->lotz_a2 >= 0.0) ||
+        !(k->ion2_I_eV > 0.0) || !std::isfinite(k->cx_a) ||
+        !std::isfinite(k->cx_b) || !std::isfinite(k->sigma_rec_1eV))
+      return set_err(c, PIC_ERR_ARG, "invalid ion-process parameters");
+  }
+  c->ionp = *k;
+  return PIC_OK;
+}
+
 pic_status pic_set_sources(pic_ctx* c, const pic_sources* s) {
   if (!c || !s) return PIC_ERR_ARG;
   const double lx = c->g.lx, ly = c->g.ly, lmin = std::min(lx, ly);
@@ -553,7 +606,7 @@ pic_status pic_set_sources(pic_ctx* c, const pic_sources* s) {
 
 pic_status pic_inject(pic_ctx* c, int32_t species, int64_t n,
                       const double* pos, const double* vel) {
-  if (!c || species < 0 || species > 2 || n < 0) return PIC_ERR_ARG;
+  if (!c || species < 0 || species >= PIC_NSPECIES || n < 0) return PIC_ERR_ARG;
   if (n == 0) return PIC_OK;
   if (!pos || !vel) return set_err(c, PIC_ERR_ARG, "null particle buffer");
   if (c->queue_used + n > c->cfg.queue_capacity)
@@ -625,9 +678,9 @@ pic_status pic_set_phi(pic_ctx* c, const double* phi) {
 namespace {
 
 // Host-known additions of the next step (queue, disk, sphere) must fit.
-pic_status advance_check(pic_ctx* c, double dt, long long add[3]) {
+pic_status advance_check(pic_ctx* c, double dt, long long add[PIC_NSPECIES]) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return set_err(c, PIC_ERR_ARG, "dt");
-  add[0] = add[1] = add[2] = 0;
+  for (int k = 0; k < PIC_NSPECIES; ++k) add[k] = 0;
   for (const QueueCall& q : c->queue) add[q.species] += q.n;
   const pic_sources& s = c->src;
   if (s.disk_on) {
@@ -635,7 +688,7 @@ pic_status advance_check(pic_ctx* c, double dt, long long add[3]) {
     add[1] += s.disk_n_n;
   }
   if (s.sphere_on) add[1] += s.sph_n;
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < PIC_NSPECIES; ++k)
     if (c->n[k] + add[k] > c->cfg.capacity[k])
       return set_err(c, PIC_ERR_CAPACITY, "sources exceed particle capacity");
   return PIC_OK;
@@ -644,7 +697,8 @@ pic_status advance_check(pic_ctx* c, double dt, long long add[3]) {
 // The field-dependent rest of a step (after the host-known sources and the
 // neutral push), the binning pass, the synchronisation and the host
 // bookkeeping.
-pic_status advance_finish(pic_ctx* c, double dt, const long long add[3],
+pic_status advance_finish(pic_ctx* c, double dt,
+                          const long long add[PIC_NSPECIES],
                           pic_absorbed* out, pic_diag* diag) {
   parts_sources_fn(c, dt);
   parts_push_collide(c, dt);
@@ -652,7 +706,7 @@ pic_status advance_finish(pic_ctx* c, double dt, const long long add[3],
   if (!hip_ok(c, hipGetLastError(), "advance launch")) return PIC_ERR_HIP;
   pic_status st = sync_counters(c);
   if (st != PIC_OK) return st;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < PIC_NSPECIES; ++k) {
     if (k == 2 && !c->ions_binned) {
       c->n[k] = (long long)c->hc.n[k];   // binned ranges kept, tail grown
       continue;
@@ -665,7 +719,7 @@ pic_status advance_finish(pic_ctx* c, double dt, const long long add[3],
   collect_times(c);
   if (diag) {
     fill_diag(c, diag);
-    for (int k = 0; k < 3; ++k) diag->emitted[k] = add[k];
+    for (int k = 0; k < PIC_NSPECIES; ++k) diag->emitted[k] = add[k];
     diag->emitted[0] += (long long)c->hc.fn_total;
   }
   if (out) {
@@ -685,7 +739,7 @@ pic_status advance_finish(pic_ctx* c, double dt, const long long add[3],
 pic_status pic_advance(pic_ctx* c, double dt, pic_absorbed* out,
                        pic_diag* diag) {
   if (!c) return PIC_ERR_ARG;
-  long long add[3];
+  long long add[PIC_NSPECIES];
   const pic_status v = advance_check(c, dt, add);
   if (v != PIC_OK) return v;
   parts_sources_host(c);
@@ -786,7 +840,7 @@ pic_status poisson_solve_static(const pic_config* cfg, const double* rho,
   // every device array comes from the fixed buffer.
   pic_ctx c{};
   c.cfg = *cfg;
-  for (int s = 0; s < 3; ++s) c.cfg.capacity[s] = 0;
+  for (int s = 0; s < PIC_NSPECIES; ++s) c.cfg.capacity[s] = 0;
   c.cfg.queue_capacity = 0;
   c.cfg.max_events = 1;
   c.stream = reinterpret_cast<hipStream_t>(stream);
@@ -859,7 +913,7 @@ pic_status pic_warm_pair(pic_ctx* c, float* input, float* target) {
 pic_status pic_load_particles(pic_ctx* c, int32_t s, int64_t n,
                               const double* pos, const double* vel,
                               const uint64_t* ids) {
-  if (!c || s < 0 || s > 2 || n < 0) return PIC_ERR_ARG;
+  if (!c || s < 0 || s >= PIC_NSPECIES || n < 0) return PIC_ERR_ARG;
   if (n > c->cfg.capacity[s])
     return set_err(c, PIC_ERR_CAPACITY, "load exceeds capacity");
   if (n > 0 && (!pos || !vel || !ids)) return PIC_ERR_ARG;
@@ -900,7 +954,7 @@ struct CkptHeader {
   uint32_t w_sp, pad;
   int64_t step;
   uint64_t next_id;
-  int64_t n[3];
+  int64_t n[PIC_NSPECIES];
   int32_t last_vcycles, hist_valid;  // bit 0: history, bit 1: u solved
   pic_collisions coll;
   pic_sources src;
@@ -912,7 +966,7 @@ size_t record_bytes(const pic_ctx* c) { return c->mixed ? 36 : 56; }
 
 size_t ckpt_bytes(const pic_ctx* c) {
   size_t b = sizeof(CkptHeader);
-  for (int s = 0; s < 3; ++s) b += (size_t)c->n[s] * record_bytes(c);
+  for (int s = 0; s < PIC_NSPECIES; ++s) b += (size_t)c->n[s] * record_bytes(c);
   // The potential and the one before it (extrapolated start).
   return b + 2 * (size_t)c->nnodes * sizeof(double);
 }
@@ -944,7 +998,7 @@ pic_status pic_checkpoint_save(pic_ctx* c, void* host, size_t bytes) {
   h.w_sp = c->cfg.w_sp;
   h.step = c->step;
   h.next_id = c->next_id;
-  for (int s = 0; s < 3; ++s) h.n[s] = c->n[s];
+  for (int s = 0; s < PIC_NSPECIES; ++s) h.n[s] = c->n[s];
   h.last_vcycles = c->last_vcycles;
   h.hist_valid = (c->hist_valid ? 1 : 0) | (c->u_solved ? 2 : 0);
   h.coll = c->coll;
@@ -953,7 +1007,7 @@ pic_status pic_checkpoint_save(pic_ctx* c, void* host, size_t bytes) {
   char* out = static_cast<char*>(host);
   std::memcpy(out, &h, sizeof(h));
   size_t off = sizeof(h);
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < PIC_NSPECIES; ++s) {
     void* ptr[8];
     size_t elem[8];
     const int na = parts_arrays(c, s, ptr, elem);
@@ -991,11 +1045,11 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
       h.v_hi != f.v_hi || h.seed != f.seed || h.w_sp != f.w_sp ||
       h.nnodes != c->nnodes)
     return set_err(c, PIC_ERR_ARG, "checkpoint of another configuration");
-  for (int s = 0; s < 3; ++s)
+  for (int s = 0; s < PIC_NSPECIES; ++s)
     if (h.n[s] < 0 || h.n[s] > f.capacity[s])
       return set_err(c, PIC_ERR_CAPACITY, "checkpoint exceeds capacity");
   size_t need = sizeof(CkptHeader) + 2 * (size_t)c->nnodes * sizeof(double);
-  for (int s = 0; s < 3; ++s) need += (size_t)h.n[s] * record_bytes(c);
+  for (int s = 0; s < PIC_NSPECIES; ++s) need += (size_t)h.n[s] * record_bytes(c);
   if (bytes < need) return set_err(c, PIC_ERR_ARG, "checkpoint truncated");
   pic_status st = pic_set_collisions(c, &h.coll);
   if (st == PIC_OK) st = pic_set_sources(c, &h.src);
@@ -1003,10 +1057,10 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
   c->ncount_valid = false;  // the neutrals are replaced
   c->ion_moved_accum = 0;
   c->acc_next_valid = false;
-  for (int s = 0; s < 3; ++s) c->n[s] = h.n[s];
+  for (int s = 0; s < PIC_NSPECIES; ++s) c->n[s] = h.n[s];
   const char* in = static_cast<const char*>(host);
   size_t off = sizeof(h);
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < PIC_NSPECIES; ++s) {
     void* ptr[8];
     size_t elem[8];
     const int na = parts_arrays(c, s, ptr, elem);
@@ -1030,7 +1084,7 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
   c->hist_valid = (h.hist_valid & 1) != 0;
   c->u_solved = (h.hist_valid & 2) != 0;
   // Keys from the restored layout, then the binning pass as for a load.
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < PIC_NSPECIES; ++s) {
     parts_restore_keys(c, s, h.n[s]);
     hipMemsetAsync(c->tsb[s][c->tcur[s]], 0, (c->ntiles + 1) * sizeof(uint32_t),
                    c->stream);
@@ -1040,7 +1094,7 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
   }
   st = sync_counters(c);
   if (st != PIC_OK) return st;
-  for (int s = 0; s < 3; ++s) {
+  for (int s = 0; s < PIC_NSPECIES; ++s) {
     c->n[s] = (long long)c->hc.sorted_n[s];
     c->n_binned[s] = c->n[s];
   }
@@ -1061,10 +1115,10 @@ pic_status pic_checkpoint_load(pic_ctx* c, const void* host, size_t bytes) {
 pic_status pic_md_return(pic_ctx* c, double lattice_a, uint32_t mask,
                          int64_t cap, double* pos, double* vel, uint64_t* ids,
                          int32_t* species, int64_t* n) {
-  if (!c || !n || !(lattice_a >= 0.0) || (mask & ~7u)) return PIC_ERR_ARG;
+  if (!c || !n || !(lattice_a >= 0.0) || (mask & ~15u)) return PIC_ERR_ARG;
   if (c->step == 0) return set_err(c, PIC_ERR_STATE, "no step taken yet");
   long long tot = 0;
-  for (int s = 0; s < 3; ++s)
+  for (int s = 0; s < PIC_NSPECIES; ++s)
     if ((mask >> s) & 1u) tot += (long long)c->hc.cathode[s];
   *n = tot;
   if (cap < tot) return set_err(c, PIC_ERR_CAPACITY, "output buffers too small");
@@ -1110,14 +1164,14 @@ double pic_alpha_eh(double R, double d, double ell, double phi_w_eV,
 }
 
 pic_status pic_count(pic_ctx* c, int32_t s, int64_t* n) {
-  if (!c || s < 0 || s > 2 || !n) return PIC_ERR_ARG;
+  if (!c || s < 0 || s >= PIC_NSPECIES || !n) return PIC_ERR_ARG;
   *n = c->n[s];
   return PIC_OK;
 }
 
 pic_status pic_read_particles(pic_ctx* c, int32_t s, int64_t cap, double* pos,
                               double* vel, uint64_t* ids, int64_t* n) {
-  if (!c || s < 0 || s > 2) return PIC_ERR_ARG;
+  if (!c || s < 0 || s >= PIC_NSPECIES) return PIC_ERR_ARG;
   if (n) *n = c->n[s];
   if (cap < c->n[s]) return set_err(c, PIC_ERR_CAPACITY, "read buffer small");
   if (c->n[s] > 0 && (!pos || !vel || !ids)) return PIC_ERR_ARG;

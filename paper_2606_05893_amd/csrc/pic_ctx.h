@@ -57,17 +57,17 @@ struct pic_ctx {
   bool mixed;
 
   // Particles: two buffers per species (binning ping-pong).
-  pic::Parts P[3][2];
-  pic::PartsM PM[3][2];
-  int cur[3];
-  uint32_t* key[3];          // cell index of each particle, or kDead
-  uint32_t* tsb[3][2];       // ntiles + 1 offsets of the binned order
-  int tcur[3];               // which tsb buffer holds the current order
+  pic::Parts P[4][2];
+  pic::PartsM PM[4][2];
+  int cur[4];
+  uint32_t* key[4];          // cell index of each particle, or kDead
+  uint32_t* tsb[4][2];       // ntiles + 1 offsets of the binned order
+  int tcur[4];               // which tsb buffer holds the current order
   uint32_t* tile_cursor;     // scatter cursors
   uint32_t* tcnt[2];         // destination-tile counts of the tile push (e, ion)
   bool tcounted;             // tcnt holds this step's counts
   uint32_t* scan_block;      // block sums of the tile scan
-  long long n_binned[3];     // particles covered by the tile ranges
+  long long n_binned[4];     // particles covered by the tile ranges
   uint2* chunks;             // (tile, piece) work list of the charged species
   uint32_t* cstart;          // ntiles + 1 chunk offsets
   long long nch_bound;       // host bound of the chunk count
@@ -131,6 +131,19 @@ struct pic_ctx {
   double *q_pos, *q_vel;
   unsigned* fn_scan;         // nx*ny + 1
 
+  // Coulomb collisions (buffers only with PIC_FLAG_CELL_GROUPS): charged
+  // particles per cell, segment offsets, scan block sums, one record per
+  // charged particle, the list of crowded cells and its counter.
+  pic_coulomb coul;
+  unsigned *cg_cnt, *cg_off, *cg_bsum, *cg_big, *cg_nbig;
+  pic::Rec* cg_rec;
+  long long cg_big_cap;
+  // Recombination, Cu+ ionisation, charge exchange: settings and the listed
+  // Cu+ ionisations (sort records, (electron, ion) index pairs).
+  pic_ion_processes ionp;
+  pic::Rec* ip_ev;
+  uint2* ip_evp;
+
   // Debye-length check: per-block moments of electrons and ions, block
   // partials of its reductions and its four results.
   double* dbg_mom;
@@ -142,7 +155,7 @@ struct pic_ctx {
   pic::Counters hc;          // host copy after the last sync
 
   // Host mirrors (exact after each synchronising call).
-  long long n[3];
+  long long n[4];
   unsigned long long next_id;
   unsigned long long next_id_src;  // first id after the host-known sources
   long long step;
@@ -220,6 +233,14 @@ long long debye_moment_doubles(long long ncells);
 // lambda_min, ratio_max.
 void parts_debye(pic_ctx* c, int block, double alpha_D, double* lam_out,
                  double* out);
+
+// ---- Coulomb collisions (k_coulomb.hip) ----------------------------------
+long long coulomb_scan_blocks(long long ncells);
+void parts_coulomb(pic_ctx* c, double dt);
+// ---- ion processes (k_ionproc.hip) ----------------------------------------
+void parts_ion_processes(pic_ctx* c, double dt);
+// Sort an event record list of at most max_events entries by (hi, lo).
+void sort_event_records(pic_ctx* c, Rec* a, unsigned long long* count);
 
 void parts_deposit(pic_ctx* c);
 // The last step's cathode records of the species in mask, offset back along

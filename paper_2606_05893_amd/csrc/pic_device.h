@@ -245,10 +245,10 @@ struct Acc<PartsM> {
 // Device-resident counters of one step.  All are updated with atomics or by
 // single-thread kernels and copied to the host once at the end of a step.
 struct Counters {
-  unsigned long long n[3];          // live particles
+  unsigned long long n[4];          // live particles
   unsigned long long next_id;
   unsigned long long fn_total;      // Fowler-Nordheim electrons this step
-  unsigned long long cathode[3], anode[3];
+  unsigned long long cathode[4], anode[4];
   unsigned long long n_cand;        // null-collision candidates
   unsigned long long n_elastic;
   unsigned long long n_events;      // ionisation events before matching
@@ -263,11 +263,17 @@ struct Counters {
   unsigned long long n_dead1;       // neutrals removed this step (listed)
   unsigned long long n_dead2;       // ions removed this step (listed)
   unsigned long long n_pairs;       // (hole, mover) pairs of a listed removal
-  unsigned long long sorted_n[3];   // counts after the binning pass
+  unsigned long long sorted_n[4];   // counts after the binning pass
   unsigned long long n_dead;        // removed neutrals (compaction)
   unsigned long long n_holes;       // ... of them below the new count
   unsigned long long n_movers;      // live neutrals above it (= n_holes)
   unsigned long long np_hits;       // electrons absorbed by the nanoparticle
+  unsigned long long coul_like;     // Coulomb collisions: like pairs
+  unsigned long long coul_ei;       // ... electron-ion
+  unsigned long long f3_rec;        // recombinations
+  unsigned long long f3_ion2;       // ionisations of Cu+ (listed)
+  unsigned long long f3_cx;         // charge exchanges
+  unsigned long long f3_starved;    // electron-ion events without an ion
   long long total_charge;
   unsigned int err;                 // sticky error bits (kErr*)
   int vcycles;
@@ -275,7 +281,7 @@ struct Counters {
   int pad;
   double rel_res;
   double b_norm;
-  double kinetic[3];
+  double kinetic[4];
   double field_energy;
   double np_heat;                   // alpha_EH * their kinetic energy, J
   // Warm start of the field solve.

@@ -13,12 +13,14 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpic.so")
 
-ELECTRON, NEUTRAL, ION = 0, 1, 2
+ELECTRON, NEUTRAL, ION, ION2 = 0, 1, 2, 3
+NSPECIES = 4
 DIRICHLET, NEUMANN = 0, 1
 FP64, MIXED = 0, 1
 ION_LOTZ, ION_CONST = 0, 1
 FLAG_PLAIN_SMOOTHER = 1
 FLAG_MG_ALL_LEVELS = 2
+FLAG_CELL_GROUPS = 4
 
 STATUS = {0: "PIC_OK", -1: "PIC_ERR_ARG", -2: "PIC_ERR_CAPACITY",
           -3: "PIC_ERR_NOCONV", -4: "PIC_ERR_NONFINITE", -5: "PIC_ERR_HIP",
@@ -41,7 +43,7 @@ class Config(ctypes.Structure):
                 ("nu_post", _c_i32), ("coarse_sweeps", _c_i32),
                 ("sort_every", _c_i32), ("rel_tol", _c_d), ("seed", _c_u64),
                 ("w_sp", _c_u32), ("flags", _c_u32),
-                ("capacity", _c_i64 * 3), ("queue_capacity", _c_i64),
+                ("capacity", _c_i64 * 4), ("queue_capacity", _c_i64),
                 ("max_events", _c_i64)]
 
 
@@ -71,15 +73,29 @@ class SolveInfo(ctypes.Structure):
 
 
 class Diag(ctypes.Structure):
-    _fields_ = [("counts", _c_i64 * 3), ("emitted", _c_i64 * 3),
-                ("fn_emitted", _c_i64), ("cathode", _c_i64 * 3),
-                ("anode", _c_i64 * 3), ("candidates", _c_i64),
+    _fields_ = [("counts", _c_i64 * 4), ("emitted", _c_i64 * 4),
+                ("fn_emitted", _c_i64), ("cathode", _c_i64 * 4),
+                ("anode", _c_i64 * 4), ("candidates", _c_i64),
                 ("elastic", _c_i64), ("ionisations", _c_i64),
                 ("starved", _c_i64), ("over_majorant", _c_i64),
                 ("near_threshold", _c_i64), ("total_charge_units", _c_i64),
-                ("kinetic", _c_d * 3), ("field_energy", _c_d),
+                ("kinetic", _c_d * 4), ("field_energy", _c_d),
                 ("solve", SolveInfo), ("step", _c_i64), ("next_id", _c_u64),
-                ("np_absorbed", _c_i64), ("np_heat", _c_d)]
+                ("np_absorbed", _c_i64), ("np_heat", _c_d),
+                ("coulomb_like", _c_i64), ("coulomb_ei", _c_i64),
+                ("recombinations", _c_i64), ("ionisations2", _c_i64),
+                ("charge_exchanges", _c_i64), ("ion_starved", _c_i64)]
+
+
+class Coulomb(ctypes.Structure):
+    _fields_ = [("enabled", _c_i32), ("reserved", _c_i32),
+                ("ln_lambda", _c_d)]
+
+
+class IonProcesses(ctypes.Structure):
+    _fields_ = [("enabled", _c_i32), ("reserved", _c_i32),
+                ("sigma_rec_1eV", _c_d), ("lotz_a2", _c_d),
+                ("ion2_I_eV", _c_d), ("cx_a", _c_d), ("cx_b", _c_d)]
 
 
 class DebyeInfo(ctypes.Structure):
@@ -131,6 +147,8 @@ EXPORTS = {
     "pic_md_return": (_c_i32, [_c_p, _c_d, _c_u32, _c_i64, _c_p, _c_p, _c_p,
                                _c_p, ctypes.POINTER(_c_i64)]),
     "pic_alpha_eh": (_c_d, [_c_d, _c_d, _c_d, _c_d, _c_d]),
+    "pic_set_coulomb": (_c_i32, [_c_p, ctypes.POINTER(Coulomb)]),
+    "pic_set_ion_processes": (_c_i32, [_c_p, ctypes.POINTER(IonProcesses)]),
     "pic_debye_check": (_c_i32, [_c_p, _c_i32, _c_d, _c_p,
                                  ctypes.POINTER(DebyeInfo)]),
     "poisson_solve_static": (_c_i32, [ctypes.POINTER(Config), _c_p, _c_p,
@@ -195,8 +213,12 @@ def make_config(p, capacity=(1 << 16,) * 3, queue_capacity=1 << 16,
     c.seed = int(p.get("seed", 0))
     c.w_sp = int(p.get("w_sp", 1))
     c.flags = int(flags)
-    for s in range(3):
-        c.capacity[s] = int(capacity[s])
+    # A fourth capacity (Cu2+) defaults to at most 65536.
+    caps = list(capacity)
+    if len(caps) == 3:
+        caps.append(min(int(caps[2]), 1 << 16))
+    for s in range(NSPECIES):
+        c.capacity[s] = int(caps[s])
     c.queue_capacity, c.max_events = int(queue_capacity), int(max_events)
     return c
 
@@ -264,6 +286,10 @@ class Pic:
         self.grid_shape = (p["nz"] + 1, p["ny"], p["nx"])
         self.set_collisions(p.get("collisions"))
         self.set_sources(p.get("sources"))
+        if p.get("coulomb"):
+            self.set_coulomb(p["coulomb"])
+        if p.get("ion_processes"):
+            self.set_ion_processes(p["ion_processes"])
 
     def __del__(self):
         if getattr(self, "ctx", None) and self.lib is not None:
@@ -295,6 +321,26 @@ class Pic:
     def set_collisions(self, d):
         self._coll = make_collisions(d)
         self._call("pic_set_collisions", ctypes.byref(self._coll))
+
+    def set_coulomb(self, d):
+        k = Coulomb()
+        d = d or {}
+        k.enabled = int(bool(d.get("enabled", False)))
+        k.ln_lambda = float(d.get("ln_lambda", 10.0))
+        self._coul = k
+        self._call("pic_set_coulomb", ctypes.byref(k))
+
+    def set_ion_processes(self, d):
+        k = IonProcesses()
+        d = d or {}
+        k.enabled = int(bool(d.get("enabled", False)))
+        k.sigma_rec_1eV = float(d.get("sigma_rec_1eV", 1e-24))
+        k.lotz_a2 = float(d.get("lotz_a2", 4.5e-18))
+        k.ion2_I_eV = float(d.get("I2_eV", 20.29))
+        k.cx_a = float(d.get("cx_a", 7.0710678118654755e-10))
+        k.cx_b = float(d.get("cx_b", 0.0))
+        self._ionp = k
+        self._call("pic_set_ion_processes", ctypes.byref(k))
 
     def set_sources(self, d):
         self._src = make_sources(d)
