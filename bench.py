@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--variant", default="all",
                     choices=["all", "fp64", "mixed", "learned_mixed", "fp64_prev",
-                             "fp64_np", "fp64_coulomb"],
+                             "fp64_np", "fp64_coulomb", "fp64_ionproc"],
                     help="fp64: plain FP64 multigrid; mixed: FP32 particles and "
                          "smoothing with FP64 refinement; learned_mixed: mixed "
                          "with the U-Net warm start (trained first on pairs "
@@ -171,7 +171,7 @@ def capacities(p, total_steps):
 def new_context(G, p, precision, pre, n0, cap):
     q = dict(p)
     q["precision"] = precision
-    flags = G.FLAG_CELL_GROUPS if q.get("coulomb") else 0
+    flags = G.FLAG_CELL_GROUPS if (q.get("coulomb") or q.get("ion_processes")) else 0
     gpu = G.Pic(q, capacity=cap, max_events=1 << 17, queue_capacity=1 << 10,
                 flags=flags)
     for s, (pos, vel, ids) in pre.items():
@@ -230,6 +230,7 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
     counts = [gpu.count(s) for s in range(3)]
     nps = []
     couls = []
+    ips = []
 
     def timed(k):
         nonlocal counts
@@ -237,6 +238,7 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
         solves, electrons, ions = [], [], []
         nps.clear()
         couls.clear()
+        ips.clear()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(k):
@@ -248,6 +250,8 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
             solves.append(d["solve"])
             nps.append((d["np_absorbed"], d["np_heat"]))
             couls.append((d["coulomb_like"], d["coulomb_ei"]))
+            ips.append((d["recombinations"], d["ionisations2"],
+                        d["charge_exchanges"]))
         torch.cuda.synchronize()
         return time.perf_counter() - t0, psteps, solves, electrons, ions
 
@@ -303,6 +307,10 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
         out["fallback_rate"] = float(np.mean([d["warm_rejected"] for d in solves]))
     if diag is not None:
         out["debye_check"] = diag
+    if any(sum(t) for t in ips):
+        out["recombinations_avg"] = float(np.mean([t[0] for t in ips]))
+        out["ionisations2_avg"] = float(np.mean([t[1] for t in ips]))
+        out["charge_exchanges_avg"] = float(np.mean([t[2] for t in ips]))
     if any(a + b for a, b in couls):
         out["coulomb_like_avg"] = float(np.mean([a for a, _ in couls]))
         out["coulomb_ei_avg"] = float(np.mean([b for _, b in couls]))
@@ -402,7 +410,7 @@ def main():
         progress(f"cpu baseline: {cpu['value']:.3e} particle-steps/s on "
                  f"{cpu['cores']} cores")
     variants = (["fp64", "mixed", "learned_mixed", "fp64_prev", "fp64_np",
-                 "fp64_coulomb"]
+                 "fp64_coulomb", "fp64_ionproc"]
                 if a.variant == "all" else [a.variant])
     cap, per_step_n = capacities(p, a.warmup + 2 * a.steps)
     torch.cuda.set_device(0)
@@ -430,6 +438,13 @@ def main():
             # Coulomb binary collisions of all charged particles each step.
             pv = dict(p)
             pv["coulomb"] = dict(enabled=True, ln_lambda=10.0)
+        if v == "fp64_ionproc":
+            # Recombination (1e-24 m^2 at 1 eV), Cu+ ionisation (Lotz,
+            # 20.29 eV) and charge exchange (5e-19 m^2) each step.
+            pv = dict(p)
+            pv["ion_processes"] = dict(enabled=True, sigma_rec_1eV=1e-24,
+                                       lotz_a2=4.5e-18, I2_eV=20.29,
+                                       cx_a=7.0710678118654755e-10, cx_b=0.0)
         res[v] = run_variant(G, pv, prec, pre, n0, cap, a.steps, a.warmup,
                              net if v == "learned_mixed" else None,
                              warm="prev" if v == "fp64_prev" else "extrap",

@@ -6,10 +6,10 @@
 // Electrons, Cu+ and Cu atoms are grouped by cell as for the Coulomb
 // collisions (count, scan, scatter of 16-byte records keyed by species and
 // a random order draw, then a sort inside each cell).  Every cell is then
-// processed in sequence by one thread (a workgroup sorts the crowded
-// ones): first each electron in turn against the cell's Cu+ (Eq. 4
-// evaluated per electron; the r-th colliding electron takes the r-th ion),
-// then the Cu+ left against the cell's atoms (ion k with atom k mod N_n,
+// processed in sequence by one thread (a workgroup sorts the crowded ones,
+// their atoms a window at a time): first each electron in turn against the
+// cell's Cu+ (Eq. 4 evaluated per electron; the r-th colliding electron
+// takes the r-th ion), then the Cu+ left against the cell's atoms (ion k with atom k mod N_n,
 // the real relative speed).  Recombinations and charge exchanges are applied
 // in place (records swapped, atoms appended, the charge of the pushed state
 // corrected); Cu+ ionisations are listed, sorted by primary id and
@@ -23,7 +23,9 @@ namespace {
 
 constexpr int kT = 256;
 constexpr int kSmall = 32;
-constexpr int kBigCell = 2048;
+constexpr int kBigCell = 2048;        // charged records of a crowded cell
+constexpr int kWin = 1024;            // atoms per selection window
+constexpr unsigned long long kOrdMask = (1ull << 53) - 1ull;
 constexpr int kScanB = 1024;
 constexpr double kNear = 1e-6;
 
@@ -233,20 +235,16 @@ struct Tally {
   unsigned long long rec = 0, cx = 0, starved = 0, near = 0;
 };
 
-// One cell's processes on records r[0..n) in (key, id) order.
+// Electrons re[0..ne) against the cell's Cu+ ri[0..ni), both in their
+// random order; returns the number of Cu+ taken.
 template <class PT>
-__device__ void ip_cell(const Sp3<PT>& S, const Rec* r, int n, unsigned cell,
-                        const IonC& k, const GridC& g, int* __restrict__ ncount,
-                        long long* __restrict__ acc, uint32_t* __restrict__ dead2,
-                        Rec* __restrict__ ev, uint2* __restrict__ evp,
-                        Counters* dc, Tally& t) {
-  int ne = 0, ni = 0;
-  while (ne < n && r[ne].hi == 0u) ++ne;
-  while (ne + ni < n && r[ne + ni].hi == 1u) ++ni;
-  const int nn = n - ne - ni;
-  const Rec* re = r;
-  const Rec* ri = r + ne;
-  const Rec* rn = r + ne + ni;
+__device__ int ip_electrons(const Sp3<PT>& S, const Rec* re, int ne,
+                            const Rec* ri, int ni, unsigned cell,
+                            const IonC& k, const GridC& g,
+                            int* __restrict__ ncount,
+                            long long* __restrict__ acc,
+                            uint32_t* __restrict__ dead2, Rec* __restrict__ ev,
+                            uint2* __restrict__ evp, Counters* dc, Tally& t) {
   int used = 0;                                     // Cu+ taken by electrons
   if (ni > 0) {
     const double dens = (double)ni * k.w_dx3;
@@ -315,32 +313,57 @@ __device__ void ip_cell(const Sp3<PT>& S, const Rec* r, int n, unsigned cell,
       }
     }
   }
-  // Charge exchange of the Cu+ left with the cell's atoms.
-  if (nn > 0 && used < ni) {
-    const double dens = (double)nn * k.w_dx3;
-    const double mr = 0.5 * kMcu;
-    for (int a = used; a < ni; ++a) {
-      const unsigned ion = ri[a].val;
-      const unsigned at = rn[(a - used) % nn].val;
-      double ix, iy, iz, nx, ny, nz;
-      Acc<PT>::vel(S.i, ion, ix, iy, iz);
-      Acc<PT>::vel(S.n, at, nx, ny, nz);
-      const double ux = ix - nx, uy = iy - ny, uz = iz - nz;
-      const double u2 = (ux * ux + uy * uy) + uz * uz;
-      const double u = sqrt(u2);
-      const double eps = ((0.5 * mr) * u2) / kE;
-      const double P = 1.0 - exp(-(((dens * sigma_cx(k, eps)) * u) * k.dt));
-      double u1, u1b;
-      uniform2(S.i.id[ion], k.step, kTagCX, k.seed, u1, u1b);
-      if (fabs(u1 - P) < kNear) t.near += 1;
-      if (u1 < P) {
-        dep_add(S.i, ion, g, acc, -1);
-        swap_records(S.i, ion, S.n, at);
-        dep_add(S.i, ion, g, acc, 1);
-        t.cx += 1;
-      }
-    }
+  return used;
+}
+
+// Charge exchange trial of one Cu+ with one atom of its cell (nn atoms).
+template <class PT>
+__device__ void cx_pair(const Sp3<PT>& S, unsigned ion, unsigned at, int nn,
+                        const IonC& k, const GridC& g,
+                        long long* __restrict__ acc, Tally& t) {
+  const double dens = (double)nn * k.w_dx3;
+  const double mr = 0.5 * kMcu;
+  double ix, iy, iz, nx, ny, nz;
+  Acc<PT>::vel(S.i, ion, ix, iy, iz);
+  Acc<PT>::vel(S.n, at, nx, ny, nz);
+  const double ux = ix - nx, uy = iy - ny, uz = iz - nz;
+  const double u2 = (ux * ux + uy * uy) + uz * uz;
+  const double u = sqrt(u2);
+  const double eps = ((0.5 * mr) * u2) / kE;
+  const double P = 1.0 - exp(-(((dens * sigma_cx(k, eps)) * u) * k.dt));
+  double u1, u1b;
+  uniform2(S.i.id[ion], k.step, kTagCX, k.seed, u1, u1b);
+  if (fabs(u1 - P) < kNear) t.near += 1;
+  if (u1 < P) {
+    dep_add(S.i, ion, g, acc, -1);
+    swap_records(S.i, ion, S.n, at);
+    dep_add(S.i, ion, g, acc, 1);
+    t.cx += 1;
   }
+}
+
+// One small cell's processes on records r[0..n) in (key, id) order:
+// electrons, then Cu+, then atoms.
+template <class PT>
+__device__ void ip_cell(const Sp3<PT>& S, const Rec* r, int n, unsigned cell,
+                        const IonC& k, const GridC& g, int* __restrict__ ncount,
+                        long long* __restrict__ acc, uint32_t* __restrict__ dead2,
+                        Rec* __restrict__ ev, uint2* __restrict__ evp,
+                        Counters* dc, Tally& t) {
+  int ne = 0, ni = 0;
+  while (ne < n && r[ne].hi == 0u) ++ne;
+  while (ne + ni < n && r[ne + ni].hi == 1u) ++ni;
+  const int nn = n - ne - ni;
+  const Rec* ri = r + ne;
+  const Rec* rn = r + ne + ni;
+  int used = 0;
+  if (ni > 0)
+    used = ip_electrons(S, r, ne, ri, ni, cell, k, g, ncount, acc, dead2, ev,
+                        evp, dc, t);
+  // Charge exchange of the Cu+ left with the cell's atoms.
+  if (nn > 0)
+    for (int a = used; a < ni; ++a)
+      cx_pair(S, ri[a].val, rn[(a - used) % nn].val, nn, k, g, acc, t);
 }
 
 template <class PT>
@@ -397,8 +420,114 @@ __global__ void __launch_bounds__(kT) k_ip_small(
   flush_tally<PT>(t, dc);
 }
 
-// Crowded cells: the records sorted in LDS by one workgroup, the processes
-// run by its first thread (they are sequential by definition).
+// Block-wide sort of s[0..n) (n <= cap, cap a power of two) by key, then
+// equal keys by id.  Called by every thread of the workgroup.
+template <class PT>
+__device__ void wg_sort(const Sp3<PT>& S, Rec* s, int n) {
+  int np2 = 1;
+  while (np2 < n) np2 <<= 1;
+  for (int j = n + threadIdx.x; j < np2; j += kT) {
+    Rec x;
+    x.lo = ~0ull;
+    x.hi = 3u;
+    x.val = 0u;
+    s[j] = x;
+  }
+  __syncthreads();
+  for (int size = 2; size <= np2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int j = threadIdx.x; j < np2; j += kT) {
+        const int p = j ^ stride;
+        if (p > j) {
+          const bool up = (j & size) == 0;
+          const bool sw = up ? s[j].lo > s[p].lo : s[j].lo < s[p].lo;
+          if (sw) {
+            const Rec x = s[j];
+            s[j] = s[p];
+            s[p] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (int j = 1; j < n; ++j) {
+      int m = j;
+      while (m > 0 && s[m].lo == s[m - 1].lo && rid(S, s[m]) < rid(S, s[m - 1])) {
+        const Rec x = s[m];
+        s[m] = s[m - 1];
+        s[m - 1] = x;
+        --m;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+struct Sel {
+  unsigned long long T;              // inclusive upper bound of the window
+  int state;                         // 0 refine, 1 done, 2 too many equal keys
+  int chosen, below;
+};
+
+// The next window of a crowded cell's atoms in their random order: those
+// whose order draw lies in (lb, T], with T the smallest bound that holds
+// `want` of them, found by radix selection over the 53-bit draw (8 bits a
+// pass), relaxed to the end of a digit bin while the window fits kWin.
+// Called by every thread; the result is left in *sel (state 2: error).
+__device__ void select_window(const Rec* __restrict__ r, int n, long long lb,
+                              int want, unsigned* hist, Sel* sel) {
+  unsigned long long pv = 0, pm = 0;
+  int below = 0;
+  for (int sh = 45;; sh = sh >= 8 ? sh - 8 : 0) {
+    for (int i = threadIdx.x; i < 256; i += kT) hist[i] = 0u;
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += kT) {
+      const Rec x = r[j];
+      if (x.hi != 2u) continue;
+      const unsigned long long o = x.lo & kOrdMask;
+      if ((long long)o <= lb || (o & pm) != pv) continue;
+      atomicAdd(&hist[(o >> sh) & 0xFFu], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int cum = below, chosen = -1;
+      for (int b = 0; b < 256; ++b) {
+        if (cum + (int)hist[b] >= want) {
+          chosen = b;
+          break;
+        }
+        cum += (int)hist[b];
+      }
+      Sel d;
+      d.chosen = chosen;
+      d.below = cum;
+      if (chosen < 0) {                  // fewer than want left: take them all
+        d.state = 1;
+        d.T = kOrdMask;
+      } else {
+        const int through = cum + (int)hist[chosen];
+        d.T = pv | ((unsigned long long)chosen << sh) | ((1ull << sh) - 1ull);
+        d.state = through <= kWin ? 1 : (sh == 0 ? 2 : 0);
+      }
+      *sel = d;
+    }
+    __syncthreads();
+    const Sel d = *sel;
+    if (d.state != 0) return;
+    pv |= (unsigned long long)d.chosen << sh;
+    pm |= 0xFFull << sh;
+    below = d.below;
+  }
+}
+
+// Crowded cells, one workgroup each.  The charged records are gathered and
+// sorted in LDS and the electrons run against the Cu+ by the first thread
+// (sequential by definition).  The atoms, however many, are never sorted as
+// a whole: the live Cu+ take them window by window of the atoms' random
+// order, each window selected by radix selection and sorted in LDS, the
+// order starting again from the first atom when the ions outnumber them.
 template <class PT>
 __global__ void __launch_bounds__(kT) k_ip_big(
     Sp3<PT> S, const unsigned* __restrict__ off, const Rec* __restrict__ rec,
@@ -407,6 +536,10 @@ __global__ void __launch_bounds__(kT) k_ip_big(
     long long* __restrict__ acc, uint32_t* __restrict__ dead2,
     Rec* __restrict__ ev, uint2* __restrict__ evp, Counters* dc) {
   __shared__ Rec sr[kBigCell];
+  __shared__ Rec sn[kWin];
+  __shared__ unsigned hist[256];
+  __shared__ Sel sel;
+  __shared__ int s_nc, s_ni, s_w, s_used;
   long long nlist = (long long)*nbig;
   if (nlist > big_cap) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&dc->err, kErrEvents);
@@ -417,54 +550,71 @@ __global__ void __launch_bounds__(kT) k_ip_big(
     const unsigned c = big[q];
     const unsigned b = off[c];
     const int n = (int)(off[c + 1] - b);
-    if (n > kBigCell) {
+    const Rec* r = rec + b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_nc = 0;
+      s_ni = 0;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += kT) {
+      const Rec x = r[j];
+      if (x.hi >= 2u) continue;
+      const int slot = atomicAdd(&s_nc, 1);
+      if (slot < kBigCell) sr[slot] = x;
+      if (x.hi == 1u) atomicAdd(&s_ni, 1);
+    }
+    __syncthreads();
+    const int nc = s_nc, ni = s_ni, nn = n - nc, ne = nc - ni;
+    if (ni == 0) continue;
+    if (nc > kBigCell) {
       if (threadIdx.x == 0) atomicOr(&dc->err, kErrEvents);
       continue;
     }
-    int np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    for (int j = threadIdx.x; j < np2; j += kT) {
-      if (j < n) {
-        sr[j] = rec[b + j];
-      } else {
-        Rec x;
-        x.lo = ~0ull;
-        x.hi = 3u;
-        x.val = 0u;
-        sr[j] = x;
-      }
-    }
+    wg_sort(S, sr, nc);
+    if (threadIdx.x == 0)
+      s_used = ip_electrons(S, sr, ne, sr + ne, ni, c, k, g, ncount, acc, dead2,
+                            ev, evp, dc, t);
     __syncthreads();
-    for (int size = 2; size <= np2; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int j = threadIdx.x; j < np2; j += kT) {
-          const int p = j ^ stride;
-          if (p > j) {
-            const bool up = (j & size) == 0;
-            const bool sw = up ? sr[j].lo > sr[p].lo : sr[j].lo < sr[p].lo;
-            if (sw) {
-              const Rec x = sr[j];
-              sr[j] = sr[p];
-              sr[p] = x;
-            }
-          }
-        }
-        __syncthreads();
+    const int used = s_used;
+    const int live = ni - used;
+    const Rec* ri = sr + ne + used;
+    int m = 0, rank = 0;
+    long long lb = -1;
+    while (nn > 0 && m < live) {
+      const int want = min(min(nn - rank, live - m), kWin);
+      select_window(r, n, lb, want, hist, &sel);
+      const Sel d = sel;
+      if (d.state == 2) {
+        if (threadIdx.x == 0) atomicOr(&dc->err, kErrEvents);
+        break;
       }
-    }
-    if (threadIdx.x == 0) {
-      for (int j = 1; j < n; ++j) {
-        int m = j;
-        while (m > 0 && sr[m].lo == sr[m - 1].lo && rid(S, sr[m]) < rid(S, sr[m - 1])) {
-          const Rec x = sr[m];
-          sr[m] = sr[m - 1];
-          sr[m - 1] = x;
-          --m;
-        }
+      if (threadIdx.x == 0) s_w = 0;
+      __syncthreads();
+      for (int j = threadIdx.x; j < n; j += kT) {
+        const Rec x = r[j];
+        if (x.hi != 2u) continue;
+        const unsigned long long o = x.lo & kOrdMask;
+        if ((long long)o <= lb || o > d.T) continue;
+        const int slot = atomicAdd(&s_w, 1);
+        if (slot < kWin) sn[slot] = x;
       }
-      ip_cell(S, sr, n, c, k, g, ncount, acc, dead2, ev, evp, dc, t);
+      __syncthreads();
+      const int w = min(s_w, kWin);
+      wg_sort(S, sn, w);
+      const int take = min(w, live - m);
+      if (threadIdx.x == 0)
+        for (int a = 0; a < take; ++a)
+          cx_pair(S, ri[m + a].val, sn[a].val, nn, k, g, acc, t);
+      m += take;
+      rank += w;
+      lb = (long long)d.T;
+      if (rank >= nn) {                  // every atom met: the order restarts
+        rank = 0;
+        lb = -1;
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   flush_tally<PT>(t, dc);
 }

@@ -141,3 +141,78 @@ def test_ion_processes_mixed_tracks_oracle(gpu_lib):
     for key in ("recombinations", "ionisations2", "charge_exchanges"):
         assert abs(dg[key] - do[key]) <= max(3, 0.02 * do[key]), key
     assert abs(dg["counts"][3] - do["counts"][3]) <= max(3, 0.02 * do["counts"][3])
+
+
+def crowded_load(p, gpu, st, seed, cells):
+    """A thin base population plus crowded cells, each given as
+    ((i, j, k), electrons, Cu+, atoms), particles well inside the cell."""
+    pre = W.preload(p, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    sig = {C.ELECTRON: np.sqrt(40.0 * C.E_CHARGE / C.M_E),
+           C.ION: np.sqrt(C.K_B * 3000.0 / C.M_CU)}
+    sig[C.NEUTRAL] = sig[C.ION]
+    nid = sum(v[0].shape[0] for v in pre.values())
+    out = {s: list(v) for s, v in pre.items()}
+    for ijk, *counts in cells:
+        for s, n in zip((C.ELECTRON, C.ION, C.NEUTRAL), counts):
+            if n == 0:
+                continue
+            pos = (np.array(ijk) + 0.3 + 0.4 * rng.random((n, 3))) * p["dx"]
+            vel = rng.standard_normal((n, 3)) * sig[s]
+            ids = np.arange(nid, nid + n, dtype=np.uint64)
+            nid += n
+            out[s] = [np.concatenate([out[s][0], pos]),
+                      np.concatenate([out[s][1], vel]),
+                      np.concatenate([out[s][2], ids])]
+    for s, (pos, vel, ids) in out.items():
+        st.load(s, pos, vel, ids)
+        gpu.load(s, pos, vel, ids)
+    st.next_id = nid
+    gpu.set_clock(0, nid)
+
+
+def test_crowded_cells_windows_of_atoms(gpu_lib):
+    """Cells of thousands of atoms: the charge exchanges take the atoms a
+    window at a time, the order restarting when the Cu+ outnumber them."""
+    p = W.scaled(W.config("c2"), 16, 16, 16, n_e=2000, n_ion=2000, n_n=2000)
+    p["seed"] = 12
+    p["sources"] = {}
+    p["ion_processes"] = dict(IONP, cx_a=3e-9)
+    g = grid_of(p)
+    gpu = make(p)
+    st = O.State(g, seed=p["seed"])
+    cells = [((3, 4, 5), 200, 1500, 3000),    # several windows of atoms
+             ((10, 10, 10), 0, 1300, 1100),   # windows, then the order restarts
+             ((5, 12, 2), 5, 40, 30),          # restarts within one window
+             ((8, 8, 8), 0, 600, 2500)]
+    crowded_load(p, gpu, st, 71, cells)
+    phi = P.solve_exact(P.add_boundary_terms(np.zeros(g.shape), g), g)
+    gpu.set_phi(phi)
+    E = O.efield(phi, g)
+    for k in range(2):
+        ab_g, dg = gpu.advance(p["dt"])
+        ab_o, do = O.advance(st, p, E, p["dt"])
+        print("step", k, do["charge_exchanges"], do["recombinations"],
+              do["ionisations2"], flush=True)
+        assert dg["near_threshold"] == sum(do["near"].values())
+        for key in ("recombinations", "ionisations2", "charge_exchanges"):
+            assert dg[key] == do[key], (k, key)
+        assert dg["ion_starved"] == do["f3_starved"]
+        compare_all(gpu, st, p, 1e-12, k)
+    assert do["charge_exchanges"] >= 500
+
+
+def test_crowded_cell_beyond_lds_is_reported(gpu_lib):
+    from paper_2606_05893_amd import pic as G
+    p = W.scaled(W.config("c2"), 16, 16, 16, n_e=10, n_ion=10, n_n=10)
+    p["sources"] = {}
+    p["collisions"] = dict(p["collisions"], enabled=False)
+    p["ion_processes"] = IONP
+    g = grid_of(p)
+    gpu = make(p)
+    st = O.State(g, seed=p["seed"])
+    crowded_load(p, gpu, st, 72, [((8, 8, 8), 1000, 1100, 10)])
+    gpu.set_phi(np.zeros(g.shape))
+    with pytest.raises(G.PicError) as e:
+        gpu.advance(1e-18)
+    assert e.value.status == -2
