@@ -61,9 +61,12 @@ enum { PIC_ELECTRON = 0, PIC_NEUTRAL = 1, PIC_ION = 2, PIC_ION2 = 3 };
 enum { PIC_BC_DIRICHLET = 0, PIC_BC_NEUMANN = 1 };
 enum { PIC_FP64 = 0, PIC_MIXED = 1 };
 enum { PIC_ION_LOTZ = 0, PIC_ION_CONST = 1 };
-/* PIC_FLAG_CELL_GROUPS: reserve the workspace that groups the charged
- * particles by cell each step (about 16 bytes per particle of capacity and
- * 8 per cell), needed by the Coulomb collisions (pic_set_coulomb).
+/* PIC_FLAG_CELL_GROUPS: reserve the workspace that groups the particles
+ * by cell each step (48 bytes per particle of capacity of electrons, Cu
+ * and Cu+ together, and 8 per cell), needed by the Coulomb collisions
+ * (pic_set_coulomb) and the ion processes (pic_set_ion_processes); the
+ * grid must then have fewer than 2^30 cells and those three capacities
+ * must sum to at most 0xFFFFFFF0 (else PIC_ERR_ARG).
  * PIC_FLAG_PLAIN_SMOOTHER: smooth with one launch per colour and sweep
  * instead of the fused two-sweep pass (same arithmetic, same results).
  * PIC_FLAG_MG_ALL_LEVELS: run the V-cycle down to the coarsest level
@@ -163,7 +166,8 @@ pic_status pic_set_coulomb(pic_ctx* ctx, const pic_coulomb* c);
  * a Cu2+.  Then each Cu+ left meets atom k mod N_n of the cell's atoms with
  * probability 1 - exp(-n_n sigma_cx u dt) (u the pair's relative speed):
  * the two records exchange position, velocity and id.  Crowded cells
- * (more than 2048 particles) set the event error.  Needs
+ * (more than 2048 electrons and Cu+ together; any number of atoms) set the
+ * event error.  Needs
  * PIC_FLAG_CELL_GROUPS (its records then cover electrons, Cu and Cu+). */
 typedef struct {
   int32_t enabled;         /* 0: off (default)                             */

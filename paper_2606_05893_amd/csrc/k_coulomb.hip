@@ -11,13 +11,18 @@
 // collisions, and the electrons and ions of the cell collide in a sequence
 // of max(N_e, N_i) collisions.
 //
-// Most cells hold a few charged particles: one thread per cell sorts its
-// segment in place and runs the collisions in order.  Crowded cells (more
-// than kSmallCell records) go to a list served by one workgroup each: an
-// LDS sort, the like pairs in parallel, and the electron-ion sequence in
-// rounds of min(N_e, N_i) collisions, each round touching every particle
-// at most once (so the rounds equal the sequence).  The result is the same
-// either way, and the same as the sequence of the definition.
+// Most cells hold a few charged particles.  There a thread per record
+// finds the record's rank in its cell's order (by comparison with the
+// others of the segment), and writes it, with the work it leads (a like
+// pair or triplet, or an electron-ion chain), to its sorted place.  The
+// like collisions then run a thread per pair, and after them the electron-
+// ion collisions a thread per chain (the t-th particle of the smaller group
+// with the larger group's t-th, (t+m)-th, ... particles; the chains share
+// no particle, so they equal the sequence of the definition).  Crowded
+// cells (more than kSmallCell records) go to a list served by one
+// workgroup each: an LDS sort, the like pairs in parallel, and the
+// electron-ion sequence in rounds of min(N_e, N_i) collisions, each round
+// touching every particle at most once.
 #include <cmath>
 
 #include "pic_ctx.h"
@@ -114,10 +119,14 @@ __device__ void collide(const Sp2<PT>& S, int sa, unsigned a, int sb,
   set_v(S, sb, b, v2x - a2 * dux, v2y - a2 * duy, v2z - a2 * duz);
 }
 
+// A record's hi word holds its cell above two species bits.
+__device__ __forceinline__ unsigned rec_sp(const Rec& r) { return r.hi & 3u; }
+__device__ __forceinline__ unsigned rec_cell(const Rec& r) { return r.hi >> 2; }
+
 template <class PT>
 __device__ __forceinline__ unsigned long long rec_id(const Sp2<PT>& S,
                                                      const Rec& r) {
-  return S.p[r.hi].id[r.val];
+  return S.p[rec_sp(r)].id[r.val];
 }
 
 template <class PT>
@@ -208,93 +217,148 @@ __global__ void k_cg_scatter(Sp2<PT> S, const uint32_t* __restrict__ ke,
     const unsigned slot = off[c] + atomicSub(&cnt[c], 1u) - 1u;
     Rec r;
     r.lo = (s ? kSpBit : 0ull) | order_key(S.p[s].id[i], step, seed);
-    r.hi = (unsigned)s;
+    r.hi = (c << 2) | (unsigned)s;
     r.val = i;
     rec[slot] = r;
   }
 }
 
-// The collisions of one cell whose records r[0..n) are in (key, id) order:
-// electrons first, then ions.  Like pairs, then the electron-ion sequence
-// (serial).  Returns the like and electron-ion collisions formed.
+// Workgroups are dispatched to the eight XCDs in turn; this numbering gives
+// each XCD a contiguous run of them (grid a multiple of 8), so that a range
+// of cells, and the particles of their tiles, stays in one XCD's L2.
+__device__ __forceinline__ long long xcd_block() {
+  return (long long)(blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
+}
+
+// The contiguous range [lo, hi) of n items this workgroup serves.
+__device__ __forceinline__ void block_range(long long n, long long& lo,
+                                            long long& hi) {
+  const long long per = (n + gridDim.x - 1) / gridDim.x;
+  lo = xcd_block() * per;
+  hi = lo + per < n ? lo + per : n;
+}
+
+// Cells of at most kSmallCell records, one thread per record: the record's
+// rank in its cell's (key, id) order places it in the sorted array, and at
+// that place goes the work it leads, if any.  Like collisions: the first of
+// each consecutive pair of its species (after a leading triplet when the
+// species count is odd; the triplet's first leads it).  Electron-ion
+// collisions: K = max(N_e, N_i) in sequence, collision j between electron
+// j mod N_e and ion j mod N_i.  Every particle of the larger group takes
+// part once, the t-th of the smaller group (m of them) in collisions t,
+// t + m, ...: m independent chains, each led by its smaller-group record.
+// Every place of the sorted array gets its two work words (zero: none); the
+// first record of a crowded cell lists the cell for the workgroup pass.
 template <class PT>
-__device__ void cell_collisions(const Sp2<PT>& S, const Rec* r, int n,
-                                const CoulC& k, unsigned long long& nl,
-                                unsigned long long& nei) {
-  int ne = 0;
-  while (ne < n && r[ne].hi == 0u) ++ne;
-  const int ni = n - ne;
-  for (int s = 0; s < 2; ++s) {
-    const Rec* q = s ? r + ne : r;
-    const int N = s ? ni : ne;
-    if (N < 2) continue;
-    const double dens = (double)N * k.w_dx3;
-    int start = 0;
-    if (N & 1) {
-      const Rec a = q[0], b = q[1], c = q[2];
-      collide(S, s, a.val, s, b.val, dens, true, rec_id(S, a), kTagDelta, kTagPhi, k);
-      collide(S, s, b.val, s, c.val, dens, true, rec_id(S, b), kTagDelta, kTagPhi, k);
-      collide(S, s, c.val, s, a.val, dens, true, rec_id(S, c), kTagDelta, kTagPhi, k);
-      start = 3;
-      nl += 3;
+__global__ void __launch_bounds__(kT) k_cg_rank(
+    Sp2<PT> S, const unsigned* __restrict__ off, long long ncells,
+    const Rec* __restrict__ rec, Rec* __restrict__ srt,
+    unsigned* __restrict__ big, long long big_cap, unsigned* __restrict__ nbig,
+    uint2* __restrict__ like_w, uint2* __restrict__ ei_w) {
+  long long lo, hi;
+  block_range((long long)off[ncells], lo, hi);
+  for (long long p = lo + threadIdx.x; p < hi; p += kT) {
+    const Rec r = rec[p];
+    const unsigned c = rec_cell(r);
+    const unsigned b = off[c];
+    const int n = (int)(off[c + 1] - b);
+    uint2 li = make_uint2(0u, 0u), eit = make_uint2(0u, 0u);
+    long long place = p;
+    if (n > kSmallCell) {
+      if ((unsigned)p == b) {
+        const unsigned slot = atomicAdd(nbig, 1u);
+        if ((long long)slot < big_cap) big[slot] = c;
+      }
+    } else if (n >= 2) {
+      int rank = 0, ne = 0;
+      for (int j = 0; j < n; ++j) {
+        const Rec x = rec[b + j];
+        ne += rec_sp(x) == 0u;
+        rank += rec_before(S, x, r);
+      }
+      place = (long long)b + rank;
+      srt[place] = r;
+      const unsigned s = rec_sp(r);
+      const int ni = n - ne;
+      const int q = s ? rank - ne : rank;           // rank within the species
+      const int N = s ? ni : ne;
+      const int start = (N & 1) ? 3 : 0;
+      const bool trip = (N & 1) && q == 0;
+      const bool lead =
+          N >= 2 && (trip || (q >= start && ((q - start) & 1) == 0 && q + 1 < N));
+      const bool chain = ne > 0 && ni > 0 && s == (ne <= ni ? 0u : 1u);
+      // Both words by selection, not by a branch around the assignment: the
+      // branch form of this code was compiled to a wrong first word.
+      li.x = lead ? (unsigned)place : 0u;
+      li.y = lead ? ((unsigned)N | (trip ? 1u << 30 : 0u) | (s << 31)) : 0u;
+      eit.x = chain ? b : 0u;
+      eit.y = chain ? ((unsigned)q | ((unsigned)ne << 8) | ((unsigned)ni << 16)) : 0u;
     }
-    for (int j = start; j + 1 < N; j += 2) {
-      collide(S, s, q[j].val, s, q[j + 1].val, dens, false, rec_id(S, q[j]),
-              kTagDelta, kTagPhi, k);
-      nl += 1;
-    }
-  }
-  if (ne > 0 && ni > 0) {
-    const int K = ne > ni ? ne : ni;
-    const double dens = (double)(ne < ni ? ne : ni) * k.w_dx3;
-    for (int j = 0; j < K; ++j) {
-      const Rec& a = r[j % ne];
-      const Rec& b = r[ne + j % ni];
-      const unsigned long long idc = ne >= ni ? rec_id(S, a) : rec_id(S, b);
-      collide(S, 0, a.val, 1, b.val, dens, false, idc, kTagDeltaEI, kTagPhiEI, k);
-    }
-    nei += (unsigned long long)K;
+    like_w[place] = li;
+    ei_w[place] = eit;
   }
 }
 
-// Cells of at most kSmallCell records: one thread each; larger ones are
-// listed for the workgroup pass.
+// Like collisions of the small cells, one thread per pair or triplet.
 template <class PT>
-__global__ void __launch_bounds__(kT) k_cg_small(Sp2<PT> S,
-                                                 const unsigned* __restrict__ off,
-                                                 long long ncells,
-                                                 Rec* __restrict__ rec,
-                                                 unsigned* __restrict__ big,
-                                                 unsigned* __restrict__ nbig,
-                                                 long long big_cap, CoulC k,
-                                                 Counters* dc) {
-  unsigned long long nl = 0, nei = 0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-       c < ncells; c += stride) {
-    const unsigned b = off[c], e = off[c + 1];
-    const int n = (int)(e - b);
-    if (n < 2) continue;
-    if (n > kSmallCell) {
-      const unsigned slot = atomicAdd(nbig, 1u);
-      if (slot < (unsigned long long)big_cap) big[slot] = (unsigned)c;
-      continue;
+__global__ void __launch_bounds__(kT) k_cg_like(Sp2<PT> S,
+                                                const Rec* __restrict__ srt,
+                                                const unsigned* __restrict__ off,
+                                                long long ncells,
+                                                const uint2* __restrict__ work,
+                                                CoulC k, Counters* dc) {
+  long long lo, hi;
+  block_range((long long)off[ncells], lo, hi);
+  unsigned long long nl = 0;
+  for (long long w = lo + threadIdx.x; w < hi; w += kT) {
+    const uint2 it = work[w];
+    if (it.y == 0u) continue;
+    const int s = (int)(it.y >> 31);
+    const bool trip = (it.y >> 30) & 1u;
+    const int N = (int)(it.y & 0x3FFFFFFFu);
+    const double dens = (double)N * k.w_dx3;
+    const PT& P = S.p[s];
+    const unsigned a = srt[it.x].val, b = srt[it.x + 1].val;
+    if (trip) {
+      const unsigned c = srt[it.x + 2].val;
+      collide(S, s, a, s, b, dens, true, P.id[a], kTagDelta, kTagPhi, k);
+      collide(S, s, b, s, c, dens, true, P.id[b], kTagDelta, kTagPhi, k);
+      collide(S, s, c, s, a, dens, true, P.id[c], kTagDelta, kTagPhi, k);
+      nl += 3;
+    } else {
+      collide(S, s, a, s, b, dens, false, P.id[a], kTagDelta, kTagPhi, k);
+      nl += 1;
     }
-    Rec r[kSmallCell];
-    for (int j = 0; j < n; ++j) r[j] = rec[b + j];
-    // Insertion sort by (key, id).
-    for (int j = 1; j < n; ++j) {
-      const Rec x = r[j];
-      int m = j - 1;
-      while (m >= 0 && rec_before(S, x, r[m])) {
-        r[m + 1] = r[m];
-        --m;
-      }
-      r[m + 1] = x;
-    }
-    cell_collisions(S, r, n, k, nl, nei);
   }
   if (nl) atomicAdd(&dc->coul_like, nl);
+}
+
+// Electron-ion chains of the small cells, one thread per chain.
+template <class PT>
+__global__ void __launch_bounds__(kT) k_cg_ei(Sp2<PT> S,
+                                              const Rec* __restrict__ srt,
+                                              const unsigned* __restrict__ off,
+                                              long long ncells,
+                                              const uint2* __restrict__ work,
+                                              CoulC k, Counters* dc) {
+  long long lo, hi;
+  block_range((long long)off[ncells], lo, hi);
+  unsigned long long nei = 0;
+  for (long long w = lo + threadIdx.x; w < hi; w += kT) {
+    const uint2 it = work[w];
+    if (it.y == 0u) continue;
+    const unsigned b = it.x;
+    const int t = (int)(it.y & 0xFFu), ne = (int)((it.y >> 8) & 0xFFu),
+              ni = (int)(it.y >> 16);
+    const int K = ne > ni ? ne : ni, m = ne < ni ? ne : ni;
+    const double dens = (double)m * k.w_dx3;
+    for (int j = t; j < K; j += m) {
+      const unsigned a = srt[b + j % ne].val, bi = srt[b + ne + j % ni].val;
+      const unsigned long long idc = ne >= ni ? S.p[0].id[a] : S.p[1].id[bi];
+      collide(S, 0, a, 1, bi, dens, false, idc, kTagDeltaEI, kTagPhiEI, k);
+      nei += 1;
+    }
+  }
   if (nei) atomicAdd(&dc->coul_ei, nei);
 }
 
@@ -332,7 +396,7 @@ __global__ void __launch_bounds__(kBigT) k_cg_big(Sp2<PT> S,
         const Rec r = rec[b + j];
         sk[j] = r.lo;
         sv[j] = r.val;
-        ss[j] = (unsigned char)r.hi;
+        ss[j] = (unsigned char)rec_sp(r);
       } else {
         sk[j] = ~0ull;
         sv[j] = 0u;
@@ -458,9 +522,14 @@ void coulomb_t(pic_ctx* c, double dt) {
   k_cg_scatter<PT><<<nblk, kT, 0, st>>>(S, c->key[0], c->key[2], c->dc,
                                         c->cg_off, c->cg_cnt, c->cg_rec,
                                         k.step, k.seed);
-  k_cg_small<PT><<<(unsigned)std::min<long long>((nc + kT - 1) / kT, 8192), kT,
-                   0, st>>>(S, c->cg_off, nc, c->cg_rec, c->cg_big,
-                            c->cg_nbig, c->cg_big_cap, k, c->dc);
+  // Grids of a multiple of 8 workgroups (see xcd_block).
+  k_cg_rank<PT><<<8192, kT, 0, st>>>(S, c->cg_off, nc, c->cg_rec, c->cg_srt,
+                                     c->cg_big, c->cg_big_cap, c->cg_nbig,
+                                     c->cg_work, c->cg_work + c->cg_work_cap);
+  k_cg_like<PT><<<8192, kT, 0, st>>>(S, c->cg_srt, c->cg_off, nc, c->cg_work,
+                                     k, c->dc);
+  k_cg_ei<PT><<<8192, kT, 0, st>>>(S, c->cg_srt, c->cg_off, nc,
+                                   c->cg_work + c->cg_work_cap, k, c->dc);
   k_cg_big<PT><<<512, kBigT, 0, st>>>(S, c->cg_off, c->cg_rec, c->cg_big,
                                       c->cg_nbig, c->cg_big_cap, k, c->dc);
 }

@@ -98,6 +98,14 @@ pic_status validate(const pic_config* c) {
   if (c->queue_capacity < 0 || c->max_events < 1) return PIC_ERR_ARG;
   const long long nodes = (long long)c->nx * c->ny * (c->nz + 1);
   if (nodes > 0x7FFFFFFFll) return PIC_ERR_ARG;
+  // Cell records keep the cell index above two species bits.
+  if ((c->flags & PIC_FLAG_CELL_GROUPS) &&
+      (long long)c->nx * c->ny * c->nz >= (1ll << 30))
+    return PIC_ERR_ARG;
+  // Their counts and offsets are 32-bit.
+  if ((c->flags & PIC_FLAG_CELL_GROUPS) &&
+      c->capacity[0] + c->capacity[1] + c->capacity[2] > 0xFFFFFFF0ll)
+    return PIC_ERR_ARG;
   return PIC_OK;
 }
 
@@ -190,7 +198,9 @@ size_t carve(pic_ctx* c, char* base) {
   c->fn_scan = cv.take<unsigned>(2 * c->g.nxy + 2);
   c->dc = cv.take<Counters>(1);
   c->cg_cnt = c->cg_off = c->cg_bsum = c->cg_big = c->cg_nbig = nullptr;
-  c->cg_rec = nullptr;
+  c->cg_rec = c->cg_srt = nullptr;
+  c->cg_work = nullptr;
+  c->cg_work_cap = 0;
   c->ip_ev = nullptr;
   c->ip_evp = nullptr;
   c->cg_big_cap = 0;
@@ -200,8 +210,11 @@ size_t carve(pic_ctx* c, char* base) {
     c->cg_bsum = cv.take<unsigned>(coulomb_scan_blocks(c->ncells));
     c->cg_big_cap = std::min<long long>(c->ncells, 1ll << 16);
     c->cg_big = cv.take<unsigned>(c->cg_big_cap);
-    c->cg_nbig = cv.take<unsigned>(1);
-    c->cg_rec = cv.take<Rec>(f.capacity[0] + f.capacity[1] + f.capacity[2]);
+    c->cg_nbig = cv.take<unsigned>(4);
+    c->cg_work_cap = f.capacity[0] + f.capacity[1] + f.capacity[2];
+    c->cg_rec = cv.take<Rec>(c->cg_work_cap);
+    c->cg_srt = cv.take<Rec>(c->cg_work_cap);
+    c->cg_work = cv.take<uint2>(2 * c->cg_work_cap);
     c->ip_ev = cv.take<Rec>(c->ev_cap_p2);
     c->ip_evp = cv.take<uint2>(c->ev_cap_p2);
   }

@@ -137,6 +137,9 @@ struct pic_ctx {
   pic_coulomb coul;
   unsigned *cg_cnt, *cg_off, *cg_bsum, *cg_big, *cg_nbig;
   pic::Rec* cg_rec;
+  pic::Rec* cg_srt;                 // records in (cell, key, id) order
+  uint2* cg_work;                   // two work lists of cg_work_cap items
+  long long cg_work_cap;
   long long cg_big_cap;
   // Recombination, Cu+ ionisation, charge exchange: settings and the listed
   // Cu+ ionisations (sort records, (electron, ion) index pairs).
