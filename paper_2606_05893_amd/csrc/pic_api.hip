@@ -98,9 +98,10 @@ pic_status validate(const pic_config* c) {
   if (c->queue_capacity < 0 || c->max_events < 1) return PIC_ERR_ARG;
   const long long nodes = (long long)c->nx * c->ny * (c->nz + 1);
   if (nodes > 0x7FFFFFFFll) return PIC_ERR_ARG;
-  // Cell records keep the cell index above two species bits.
+  // Cell records keep the (tile-major) cell number above two species bits.
   if ((c->flags & PIC_FLAG_CELL_GROUPS) &&
-      (long long)c->nx * c->ny * c->nz >= (1ll << 30))
+      (long long)((c->nx + 7) / 8) * ((c->ny + 7) / 8) * ((c->nz + 7) / 8) * 512 >=
+          (1ll << 30))
     return PIC_ERR_ARG;
   // Their counts and offsets are 32-bit.
   if ((c->flags & PIC_FLAG_CELL_GROUPS) &&
@@ -198,23 +199,37 @@ size_t carve(pic_ctx* c, char* base) {
   c->fn_scan = cv.take<unsigned>(2 * c->g.nxy + 2);
   c->dc = cv.take<Counters>(1);
   c->cg_cnt = c->cg_off = c->cg_bsum = c->cg_big = c->cg_nbig = nullptr;
-  c->cg_rec = c->cg_srt = nullptr;
-  c->cg_work = nullptr;
+  c->cg_rec = nullptr;
+  c->cg_work = c->cg_list = nullptr;
+  c->cg_pv = c->cg_pvu = nullptr;
+  c->cg_slot = c->cg_place = nullptr;
+  c->cg_wcnt = c->cg_woff = c->cg_wbsum = nullptr;
+  c->cg_wblocks = 0;
   c->cg_work_cap = 0;
   c->ip_ev = nullptr;
   c->ip_evp = nullptr;
   c->cg_big_cap = 0;
+  c->cg_nkeys = c->ntiles * kTile * kTile * kTile;
   if (f.flags & PIC_FLAG_CELL_GROUPS) {
-    c->cg_cnt = cv.take<unsigned>(c->ncells);
-    c->cg_off = cv.take<unsigned>(c->ncells + 1);
-    c->cg_bsum = cv.take<unsigned>(coulomb_scan_blocks(c->ncells));
+    c->cg_cnt = cv.take<unsigned>(c->cg_nkeys);
+    c->cg_off = cv.take<unsigned>(c->cg_nkeys + 1);
+    c->cg_bsum = cv.take<unsigned>(coulomb_scan_blocks(c->cg_nkeys));
     c->cg_big_cap = std::min<long long>(c->ncells, 1ll << 16);
     c->cg_big = cv.take<unsigned>(c->cg_big_cap);
     c->cg_nbig = cv.take<unsigned>(4);
     c->cg_work_cap = f.capacity[0] + f.capacity[1] + f.capacity[2];
     c->cg_rec = cv.take<Rec>(c->cg_work_cap);
-    c->cg_srt = cv.take<Rec>(c->cg_work_cap);
     c->cg_work = cv.take<uint2>(2 * c->cg_work_cap);
+    c->cg_list = cv.take<uint2>(2 * c->cg_work_cap);
+    c->cg_pv = cv.take<double>(4 * c->cg_work_cap);
+    c->cg_pvu = cv.take<double>(4 * c->cg_work_cap);
+    c->cg_slot = cv.take<unsigned>(c->cg_work_cap);
+    c->cg_place = cv.take<unsigned>(c->cg_work_cap);
+    c->cg_wblocks = (int)coulomb_work_blocks(c->cg_work_cap);
+    const long long nw = coulomb_work_counts(c->cg_work_cap);
+    c->cg_wcnt = cv.take<unsigned>(nw);
+    c->cg_woff = cv.take<unsigned>(nw + 1);
+    c->cg_wbsum = cv.take<unsigned>(coulomb_scan_blocks(nw));
     c->ip_ev = cv.take<Rec>(c->ev_cap_p2);
     c->ip_evp = cv.take<uint2>(c->ev_cap_p2);
   }

@@ -137,10 +137,17 @@ struct pic_ctx {
   pic_coulomb coul;
   unsigned *cg_cnt, *cg_off, *cg_bsum, *cg_big, *cg_nbig;
   pic::Rec* cg_rec;
-  pic::Rec* cg_srt;                 // records in (cell, key, id) order
-  uint2* cg_work;                   // two work lists of cg_work_cap items
+  uint2* cg_work;                   // two work words per record place
   long long cg_work_cap;
+  uint2* cg_list;                   // the work in class order (2 per place)
+  double* cg_pv;                    // velocity and id copies (4 words a place)
+  double* cg_pvu;                   // the same in scatter order
+  unsigned* cg_slot;                // each particle's record slot
+  unsigned* cg_place;               // each slot's sorted place
+  unsigned *cg_wcnt, *cg_woff, *cg_wbsum;
+  int cg_wblocks;
   long long cg_big_cap;
+  long long cg_nkeys;               // tile-major cell numbers (tiles x 512)
   // Recombination, Cu+ ionisation, charge exchange: settings and the listed
   // Cu+ ionisations (sort records, (electron, ion) index pairs).
   pic_ion_processes ionp;
@@ -239,6 +246,8 @@ void parts_debye(pic_ctx* c, int block, double alpha_D, double* lam_out,
 
 // ---- Coulomb collisions (k_coulomb.hip) ----------------------------------
 long long coulomb_scan_blocks(long long ncells);
+long long coulomb_work_blocks(long long records);
+long long coulomb_work_counts(long long records);
 void parts_coulomb(pic_ctx* c, double dt);
 // ---- ion processes (k_ionproc.hip) ----------------------------------------
 void parts_ion_processes(pic_ctx* c, double dt);
