@@ -1,0 +1,52 @@
+// Helpers shared by the passes that group particles by cell (Coulomb
+// collisions, ion processes): the XCD-aware split of a range over the
+// workgroups and the tile-major numbering of cells.
+#pragma once
+
+#include "pic_device.h"
+
+namespace pic {
+
+// Workgroups are dispatched to the eight XCDs in turn; this numbering gives
+// each XCD a contiguous run of them (grid a multiple of 8), so that a range
+// of cells, and the particles of their tiles, stays in one XCD's L2.
+__device__ __forceinline__ long long xcd_block() {
+  return (long long)(blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
+}
+
+// The contiguous range [lo, hi) of n items this workgroup serves.
+__device__ __forceinline__ void block_range(long long n, long long& lo,
+                                            long long& hi) {
+  const long long per = (n + gridDim.x - 1) / gridDim.x;
+  lo = xcd_block() * per;
+  hi = lo + per < n ? lo + per : n;
+}
+
+// Cells are numbered tile by tile (512 to a tile, x fastest inside), so that
+// the cells of one tile, whose particles share one range of the tile-binned
+// arrays, are served together.
+__device__ __forceinline__ unsigned tile_major(unsigned c, const GridC& g) {
+  const unsigned i = c % (unsigned)g.nx;
+  const unsigned r = c / (unsigned)g.nx;
+  const unsigned j = r % (unsigned)g.ny;
+  const unsigned k = r / (unsigned)g.ny;
+  const unsigned t = ((k / kTile) * (unsigned)g.tny + j / kTile) * (unsigned)g.tnx + i / kTile;
+  return (t * kTile + k % kTile) * (kTile * kTile) + (j % kTile) * kTile + i % kTile;
+}
+
+// The cell (x fastest, then y, then z) of a tile-major number.
+__device__ __forceinline__ unsigned cell_of_tile_major(unsigned key,
+                                                       const GridC& g) {
+  const unsigned t = key / (kTile * kTile * kTile);
+  const unsigned w = key % (kTile * kTile * kTile);
+  const unsigned ti = t % (unsigned)g.tnx;
+  const unsigned tr = t / (unsigned)g.tnx;
+  const unsigned tj = tr % (unsigned)g.tny;
+  const unsigned tk = tr / (unsigned)g.tny;
+  const unsigned i = ti * kTile + w % kTile;
+  const unsigned j = tj * kTile + (w / kTile) % kTile;
+  const unsigned k = tk * kTile + w / (kTile * kTile);
+  return (k * (unsigned)g.ny + j) * (unsigned)g.nx + i;
+}
+
+}  // namespace pic

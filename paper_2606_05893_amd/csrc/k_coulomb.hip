@@ -30,6 +30,7 @@
 // collisions, each round touching every particle at most once.
 #include <cmath>
 
+#include "cell_groups.h"
 #include "pic_ctx.h"
 
 namespace pic {
@@ -183,33 +184,6 @@ __device__ __forceinline__ bool rec_before(const Sp2<PT>& S, const Rec& a,
 }
 
 // ---- grouping ----------------------------------------------------------------
-// Workgroups are dispatched to the eight XCDs in turn; this numbering gives
-// each XCD a contiguous run of them (grid a multiple of 8), so that a range
-// of cells, and the particles of their tiles, stays in one XCD's L2.
-__device__ __forceinline__ long long xcd_block() {
-  return (long long)(blockIdx.x % 8u) * (gridDim.x / 8u) + blockIdx.x / 8u;
-}
-
-// The contiguous range [lo, hi) of n items this workgroup serves.
-__device__ __forceinline__ void block_range(long long n, long long& lo,
-                                            long long& hi) {
-  const long long per = (n + gridDim.x - 1) / gridDim.x;
-  lo = xcd_block() * per;
-  hi = lo + per < n ? lo + per : n;
-}
-
-// Cells are numbered tile by tile (512 to a tile, x fastest inside), so that
-// the cells of one tile, whose particles share one range of the tile-binned
-// arrays, are served together.
-__device__ __forceinline__ unsigned tile_major(unsigned c, const GridC& g) {
-  const unsigned i = c % (unsigned)g.nx;
-  const unsigned r = c / (unsigned)g.nx;
-  const unsigned j = r % (unsigned)g.ny;
-  const unsigned k = r / (unsigned)g.ny;
-  const unsigned t = ((k / kTile) * (unsigned)g.tny + j / kTile) * (unsigned)g.tnx + i / kTile;
-  return (t * kTile + k % kTile) * (kTile * kTile) + (j % kTile) * kTile + i % kTile;
-}
-
 __global__ void k_cg_count(const uint32_t* __restrict__ ke,
                            const uint32_t* __restrict__ ki,
                            const Counters* dc, GridC g,

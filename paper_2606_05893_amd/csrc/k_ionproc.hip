@@ -16,6 +16,7 @@
 // committed in that order, which fixes the secondaries' ids.
 #include <cmath>
 
+#include "cell_groups.h"
 #include "pic_ctx.h"
 
 namespace pic {
@@ -61,10 +62,15 @@ struct Sp3 {
   uint32_t *ke, *ki, *kn;            // their keys
 };
 
+// A record's hi word holds its tile-major cell number above two species
+// bits (0 electron, 1 Cu+, 2 Cu).
+__device__ __forceinline__ unsigned ip_sp(const Rec& r) { return r.hi & 3u; }
+
 template <class PT>
 __device__ __forceinline__ unsigned long long rid(const Sp3<PT>& S,
                                                   const Rec& r) {
-  return r.hi == 0 ? S.e.id[r.val] : (r.hi == 1 ? S.i.id[r.val] : S.n.id[r.val]);
+  const unsigned s = ip_sp(r);
+  return s == 0 ? S.e.id[r.val] : (s == 1 ? S.i.id[r.val] : S.n.id[r.val]);
 }
 
 __device__ __forceinline__ unsigned long long ord_key(unsigned long long id,
@@ -149,14 +155,15 @@ __device__ void swap_records<PartsM>(const PartsM& a, unsigned i,
 __global__ void k_ig_count(const uint32_t* __restrict__ ke,
                            const uint32_t* __restrict__ ki,
                            const uint32_t* __restrict__ kn,
-                           const Counters* dc, unsigned* __restrict__ cnt) {
+                           const Counters* dc, GridC g,
+                           unsigned* __restrict__ cnt) {
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2],
                   nn = (long long)dc->n[1];
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-       t < ne + ni + nn; t += stride) {
+  long long lo, hi;
+  block_range(ne + ni + nn, lo, hi);
+  for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
     const uint32_t c = t < ne ? ke[t] : (t < ne + ni ? ki[t - ne] : kn[t - ne - ni]);
-    if (c != kDead) atomicAdd(&cnt[c], 1u);
+    if (c != kDead) atomicAdd(&cnt[tile_major(c, g)], 1u);
   }
 }
 
@@ -208,26 +215,59 @@ __global__ void __launch_bounds__(kScanB) k_ig_scan_apply(
 }
 
 template <class PT>
-__global__ void k_ig_scatter(Sp3<PT> S, const Counters* dc,
+__global__ void k_ig_scatter(Sp3<PT> S, const Counters* dc, GridC g,
                              const unsigned* __restrict__ off,
                              unsigned* __restrict__ cnt, Rec* __restrict__ rec,
                              unsigned step, unsigned long long seed) {
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2],
                   nn = (long long)dc->n[1];
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-       t < ne + ni + nn; t += stride) {
+  long long lo, hi;
+  block_range(ne + ni + nn, lo, hi);
+  for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
     const unsigned s = t < ne ? 0u : (t < ne + ni ? 1u : 2u);
     const unsigned i = (unsigned)(s == 0 ? t : (s == 1 ? t - ne : t - ne - ni));
-    const uint32_t c = s == 0 ? S.ke[i] : (s == 1 ? S.ki[i] : S.kn[i]);
-    if (c == kDead) continue;
+    const uint32_t c0 = s == 0 ? S.ke[i] : (s == 1 ? S.ki[i] : S.kn[i]);
+    if (c0 == kDead) continue;
+    const unsigned c = tile_major(c0, g);
     const unsigned long long id = s == 0 ? S.e.id[i] : (s == 1 ? S.i.id[i] : S.n.id[i]);
     const unsigned slot = off[c] + atomicSub(&cnt[c], 1u) - 1u;
     Rec r;
     r.lo = ((unsigned long long)s << 62) | ord_key(id, step, seed);
-    r.hi = s;
+    r.hi = (c << 2) | s;
     r.val = i;
     rec[slot] = r;
+  }
+}
+
+// Cells of at most kSmall records, one thread per record: its rank in the
+// cell's (key, id) order places it in the sorted array.  The first record
+// of a crowded cell lists the cell for the workgroup pass.
+template <class PT>
+__global__ void __launch_bounds__(kT) k_ig_rank(
+    Sp3<PT> S, const unsigned* __restrict__ off, long long nkeys,
+    const Rec* __restrict__ rec, Rec* __restrict__ srt,
+    unsigned* __restrict__ big, unsigned* __restrict__ nbig, long long big_cap) {
+  long long lo, hi;
+  block_range((long long)off[nkeys], lo, hi);
+  for (long long p = lo + threadIdx.x; p < hi; p += kT) {
+    const Rec r = rec[p];
+    const unsigned c = r.hi >> 2;
+    const unsigned b = off[c];
+    const int n = (int)(off[c + 1] - b);
+    if (n > kSmall) {
+      if ((unsigned)p == b) {
+        const unsigned slot = atomicAdd(nbig, 1u);
+        if ((long long)slot < big_cap) big[slot] = c;
+      }
+    } else if (n >= 2) {
+      int rank = 0;
+      for (int j = 0; j < n; ++j) {
+        const Rec x = rec[b + j];
+        rank += (b + (unsigned)j != (unsigned)p) &&
+                (x.lo < r.lo || (x.lo == r.lo && rid(S, x) < rid(S, r)));
+      }
+      srt[b + rank] = r;
+    }
   }
 }
 
@@ -351,8 +391,8 @@ __device__ void ip_cell(const Sp3<PT>& S, const Rec* r, int n, unsigned cell,
                         Rec* __restrict__ ev, uint2* __restrict__ evp,
                         Counters* dc, Tally& t) {
   int ne = 0, ni = 0;
-  while (ne < n && r[ne].hi == 0u) ++ne;
-  while (ne + ni < n && r[ne + ni].hi == 1u) ++ni;
+  while (ne < n && ip_sp(r[ne]) == 0u) ++ne;
+  while (ne + ni < n && ip_sp(r[ne + ni]) == 1u) ++ni;
   const int nn = n - ne - ni;
   const Rec* ri = r + ne;
   const Rec* rn = r + ne + ni;
@@ -367,12 +407,6 @@ __device__ void ip_cell(const Sp3<PT>& S, const Rec* r, int n, unsigned cell,
 }
 
 template <class PT>
-__device__ __forceinline__ bool rec_before(const Sp3<PT>& S, const Rec& a,
-                                           const Rec& b) {
-  return a.lo < b.lo || (a.lo == b.lo && rid(S, a) < rid(S, b));
-}
-
-template <class PT>
 __device__ void flush_tally(const Tally& t, Counters* dc) {
   if (t.rec) atomicAdd(&dc->f3_rec, t.rec);
   if (t.cx) atomicAdd(&dc->f3_cx, t.cx);
@@ -380,42 +414,28 @@ __device__ void flush_tally(const Tally& t, Counters* dc) {
   if (t.near) atomicAdd(&dc->n_near, t.near);
 }
 
+// Small cells with a Cu+, one thread each, on the sorted records.
 template <class PT>
 __global__ void __launch_bounds__(kT) k_ip_small(
-    Sp3<PT> S, const unsigned* __restrict__ off, long long ncells,
-    Rec* __restrict__ rec, unsigned* __restrict__ big,
-    unsigned* __restrict__ nbig, long long big_cap, IonC k, GridC g,
+    Sp3<PT> S, const unsigned* __restrict__ off, long long nkeys,
+    const Rec* __restrict__ srt, IonC k, GridC g,
     int* __restrict__ ncount, long long* __restrict__ acc,
     uint32_t* __restrict__ dead2, Rec* __restrict__ ev,
     uint2* __restrict__ evp, Counters* dc) {
   Tally t;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-       c < ncells; c += stride) {
+  long long lo, hi;
+  block_range(nkeys, lo, hi);
+  for (long long c = lo + threadIdx.x; c < hi; c += kT) {
     const unsigned b = off[c], e = off[c + 1];
     const int n = (int)(e - b);
-    if (n < 2) continue;
-    if (n > kSmall) {
-      const unsigned slot = atomicAdd(nbig, 1u);
-      if ((long long)slot < big_cap) big[slot] = (unsigned)c;
-      continue;
-    }
-    Rec r[kSmall];
-    for (int j = 0; j < n; ++j) r[j] = rec[b + j];
-    for (int j = 1; j < n; ++j) {
-      const Rec x = r[j];
-      int m = j - 1;
-      while (m >= 0 && rec_before(S, x, r[m])) {
-        r[m + 1] = r[m];
-        --m;
-      }
-      r[m + 1] = x;
-    }
+    if (n < 2 || n > kSmall) continue;
+    const Rec* r = srt + b;
     // Nothing to do without a Cu+.
     bool has_ion = false;
-    for (int j = 0; j < n; ++j) has_ion = has_ion || r[j].hi == 1u;
+    for (int j = 0; j < n; ++j) has_ion = has_ion || ip_sp(r[j]) == 1u;
     if (has_ion)
-      ip_cell(S, r, n, (unsigned)c, k, g, ncount, acc, dead2, ev, evp, dc, t);
+      ip_cell(S, r, n, cell_of_tile_major((unsigned)c, g), k, g, ncount, acc,
+              dead2, ev, evp, dc, t);
   }
   flush_tally<PT>(t, dc);
 }
@@ -485,7 +505,7 @@ __device__ void select_window(const Rec* __restrict__ r, int n, long long lb,
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += kT) {
       const Rec x = r[j];
-      if (x.hi != 2u) continue;
+      if (ip_sp(x) != 2u) continue;
       const unsigned long long o = x.lo & kOrdMask;
       if ((long long)o <= lb || (o & pm) != pv) continue;
       atomicAdd(&hist[(o >> sh) & 0xFFu], 1u);
@@ -547,9 +567,10 @@ __global__ void __launch_bounds__(kT) k_ip_big(
   }
   Tally t;
   for (long long q = blockIdx.x; q < nlist; q += gridDim.x) {
-    const unsigned c = big[q];
-    const unsigned b = off[c];
-    const int n = (int)(off[c + 1] - b);
+    const unsigned key = big[q];
+    const unsigned c = cell_of_tile_major(key, g);
+    const unsigned b = off[key];
+    const int n = (int)(off[key + 1] - b);
     const Rec* r = rec + b;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -559,10 +580,10 @@ __global__ void __launch_bounds__(kT) k_ip_big(
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += kT) {
       const Rec x = r[j];
-      if (x.hi >= 2u) continue;
+      if (ip_sp(x) >= 2u) continue;
       const int slot = atomicAdd(&s_nc, 1);
       if (slot < kBigCell) sr[slot] = x;
-      if (x.hi == 1u) atomicAdd(&s_ni, 1);
+      if (ip_sp(x) == 1u) atomicAdd(&s_ni, 1);
     }
     __syncthreads();
     const int nc = s_nc, ni = s_ni, nn = n - nc, ne = nc - ni;
@@ -593,7 +614,7 @@ __global__ void __launch_bounds__(kT) k_ip_big(
       __syncthreads();
       for (int j = threadIdx.x; j < n; j += kT) {
         const Rec x = r[j];
-        if (x.hi != 2u) continue;
+        if (ip_sp(x) != 2u) continue;
         const unsigned long long o = x.lo & kOrdMask;
         if ((long long)o <= lb || o > d.T) continue;
         const int slot = atomicAdd(&s_w, 1);
@@ -708,7 +729,7 @@ PartsM sp_cur<PartsM>(pic_ctx* c, int s) { return c->PM[s][c->cur[s]]; }
 template <class PT>
 void ionproc_t(pic_ctx* c, double dt) {
   hipStream_t st = c->stream;
-  const long long nc = c->ncells;
+  const long long nc = c->cg_nkeys;          // tile-major cell numbers
   const pic_ion_processes& q = c->ionp;
   IonC k;
   k.s_rec = q.sigma_rec_1eV;
@@ -732,20 +753,21 @@ void ionproc_t(pic_ctx* c, double dt) {
   const Sp3<PT> S = sp3<PT>(c);
   hipMemsetAsync(c->cg_cnt, 0, nc * sizeof(unsigned), st);
   hipMemsetAsync(c->cg_nbig, 0, sizeof(unsigned), st);
-  k_ig_count<<<4096, kT, 0, st>>>(c->key[0], c->key[2], c->key[1], c->dc,
+  // Grids of a multiple of 8 workgroups (see xcd_block).
+  k_ig_count<<<4096, kT, 0, st>>>(c->key[0], c->key[2], c->key[1], c->dc, c->g,
                                   c->cg_cnt);
   const long long nb = (nc + kScanB - 1) / kScanB;
   k_ig_scan_blocks<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_cnt, nc, c->cg_off,
                                                    c->cg_bsum);
   k_ig_scan_sums<<<1, 1024, 0, st>>>(c->cg_bsum, (int)nb);
   k_ig_scan_apply<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_off, nc, c->cg_bsum);
-  k_ig_scatter<PT><<<4096, kT, 0, st>>>(S, c->dc, c->cg_off, c->cg_cnt,
+  k_ig_scatter<PT><<<4096, kT, 0, st>>>(S, c->dc, c->g, c->cg_off, c->cg_cnt,
                                         c->cg_rec, k.step, k.seed);
-  k_ip_small<PT><<<(unsigned)std::min<long long>((nc + kT - 1) / kT, 8192), kT,
-                   0, st>>>(S, c->cg_off, nc, c->cg_rec, c->cg_big,
-                            c->cg_nbig, c->cg_big_cap, k, c->g, c->ncount,
-                            c->acc_next, c->dead2, c->ip_ev, c->ip_evp,
-                            c->dc);
+  k_ig_rank<PT><<<8192, kT, 0, st>>>(S, c->cg_off, nc, c->cg_rec, c->cg_srt,
+                                     c->cg_big, c->cg_nbig, c->cg_big_cap);
+  k_ip_small<PT><<<8192, kT, 0, st>>>(S, c->cg_off, nc, c->cg_srt, k, c->g,
+                                      c->ncount, c->acc_next, c->dead2,
+                                      c->ip_ev, c->ip_evp, c->dc);
   k_ip_big<PT><<<512, kT, 0, st>>>(S, c->cg_off, c->cg_rec, c->cg_big,
                                    c->cg_nbig, c->cg_big_cap, k, c->g,
                                    c->ncount, c->acc_next, c->dead2, c->ip_ev,

@@ -199,7 +199,7 @@ size_t carve(pic_ctx* c, char* base) {
   c->fn_scan = cv.take<unsigned>(2 * c->g.nxy + 2);
   c->dc = cv.take<Counters>(1);
   c->cg_cnt = c->cg_off = c->cg_bsum = c->cg_big = c->cg_nbig = nullptr;
-  c->cg_rec = nullptr;
+  c->cg_rec = c->cg_srt = nullptr;
   c->cg_work = c->cg_list = nullptr;
   c->cg_pv = c->cg_pvu = nullptr;
   c->cg_slot = c->cg_place = nullptr;
@@ -219,6 +219,7 @@ size_t carve(pic_ctx* c, char* base) {
     c->cg_nbig = cv.take<unsigned>(4);
     c->cg_work_cap = f.capacity[0] + f.capacity[1] + f.capacity[2];
     c->cg_rec = cv.take<Rec>(c->cg_work_cap);
+    c->cg_srt = cv.take<Rec>(c->cg_work_cap);
     c->cg_work = cv.take<uint2>(2 * c->cg_work_cap);
     c->cg_list = cv.take<uint2>(2 * c->cg_work_cap);
     c->cg_pv = cv.take<double>(4 * c->cg_work_cap);

@@ -144,6 +144,7 @@ struct pic_ctx {
   double* cg_pvu;                   // the same in scatter order
   unsigned* cg_slot;                // each particle's record slot
   unsigned* cg_place;               // each slot's sorted place
+  pic::Rec* cg_srt;                 // records in cell order (ion processes)
   unsigned *cg_wcnt, *cg_woff, *cg_wbsum;
   int cg_wblocks;
   long long cg_big_cap;
