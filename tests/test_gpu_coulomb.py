@@ -3,7 +3,9 @@
 * A populated grid (one or two electrons and ions per cell) through full
   advances with sources and electron-neutral collisions on: the collision
   counts exactly, the particle sets by id, positions bit for bit and
-  velocities within 1e-12 (the collisions call log, sqrt, sin, cos).
+  velocities within 1e-12 (the collisions call log and sqrt, and the GPU
+  takes cos(2 pi u) and the azimuth's sine and cosine from cospi and
+  sincospi, which round differently from the oracle's cos and sin).
 * Crowded cells (16 and 17 particles, the switch to one workgroup per
   cell, and a few hundred electrons against a hundred ions, so the
   electron-ion sequence runs in rounds): the same.
