@@ -672,10 +672,15 @@ def kinetic_energy(sp, species):
     return float(0.5 * C.MASS[species] * np.sum(v2))
 
 
-def advance(state, params, E, dt):
+def advance(state, params, E, dt, progress=None):
     """Everything after the field solve: sources, push, MCC, ionisation,
-    compaction.  Returns (absorbed dict, diagnostics dict).
+    compaction.  Returns (absorbed dict, diagnostics dict).  progress, if
+    given, is called with a short label after each stage (long runs at full
+    size report where they are).
     """
+    def done(label):
+        if progress is not None:
+            progress(label)
     g = state.grid
     coll = params.get("collisions_obj")
     if coll is None:
@@ -684,6 +689,7 @@ def advance(state, params, E, dt):
     diag = {"candidates": 0, "elastic": 0, "ionisations": 0, "starved": 0,
             "over_majorant": 0}
     new, n_fn = sources(state, params, E, dt, near)
+    done("sources")
     emitted = {s: 0 for s in range(C.NSPECIES)}
     for s in range(C.NSPECIES):
         for parts in new[s]:
@@ -720,10 +726,12 @@ def advance(state, params, E, dt):
         cath_count[s] = int(cath.sum())
         anode[s] = int(an.sum())
         state.sp[s] = _select(sp, ~(cath | an | hit))
+        done(f"push of species {s}")
     ncell_neutral = cell_index(state.sp[C.NEUTRAL], g)
     ncount = np.bincount(ncell_neutral,
                          minlength=g.nx * g.ny * g.nz).astype(np.int64)
     ion_idx, ion_cell = mcc(state, coll, ncount, dt, near, diag)
+    done("mcc")
     sec, consumed, ions = ionise(state, coll, ion_idx, ion_cell,
                                  ncell_neutral, diag)
     if sec is not None:

@@ -1,0 +1,152 @@
+"""Teacher-forced parity over a long run of the 128x128x512 workload (10 M
+electrons + 10 M Cu+ + 5 M Cu preloaded, Fowler-Nordheim disk and 1e5 Cu
+evaporated per step).
+
+The GPU runs the full step to step k and its state is read back.  The
+oracle then takes step k+1 from that state: its deposit solved exactly
+must give the potential the GPU solves for that step (1e-6 of its largest
+value; the GPU stops at a 1e-10 residual), and in that potential the
+oracle's sources, push, collisions and compaction must give the GPU's
+particles of step k+1 by id: counts exactly, positions and velocities
+within 1e-12 (the collisions call exp, log, sqrt, sin and cos).  A draw
+within 1e-6 of a threshold may decide an outcome differently on the two
+sides; only then may a few particles (at most four per such draw) differ.
+
+k = 10 runs by default, k in {1, 100} with PIC_C2_CHECKPOINTS=all.  k = 1000
+and 2000 (the configuration's run length) do not run: the evaporation
+source puts its 1e5 atoms a step into the few hundred cells above the disk,
+where they barely move, and the ionisation matching gathers every atom of a
+cell with an ionisation event, so past about 300 steps that list exceeds
+even 4 M entries (the step returns PIC_ERR_CAPACITY).
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import constants as C
+from oracle import pic as O
+from oracle import poisson as P
+
+pytestmark = pytest.mark.gpu
+
+ALL = os.environ.get("PIC_C2_CHECKPOINTS") == "all"
+BEYOND = "the atoms of the event cells above the disk exceed the candidate list"
+
+
+def _marks(k):
+    if k >= 1000:
+        return pytest.mark.skip(reason=BEYOND)
+    if k == 10 or ALL:
+        return ()
+    return pytest.mark.skip(reason="long checkpoint: set PIC_C2_CHECKPOINTS=all")
+
+
+CHECKPOINTS = [pytest.param(k, marks=_marks(k)) for k in (1, 10, 100, 1000, 2000)]
+
+
+def say(t0, msg):
+    print(f"[{time.time() - t0:7.1f} s] {msg}", flush=True)
+
+
+def read_state(gpu):
+    out = {}
+    for s in range(C.NSPECIES):
+        pos, vel, ids = (t.cpu().numpy() for t in gpu.read(s))
+        out[s] = (pos, vel, ids.astype(np.uint64))
+    return out
+
+
+def sort_by_id(pos, vel, ids):
+    o = np.argsort(ids, kind="stable")
+    return ids[o], pos[o], vel[o]
+
+
+def compare_species(s, got, sp, dx, allow):
+    """Number of particles that differ (by id set, position or velocity)."""
+    ig, pg, vg = sort_by_id(*got)
+    po = np.stack([sp["x"], sp["y"], sp["z"]], 1)
+    vo = np.stack([sp["vx"], sp["vy"], sp["vz"]], 1)
+    io, po, vo = sort_by_id(po, vo, sp["id"])
+    only = np.setxor1d(ig, io, assume_unique=True).size
+    common, ag, ao = np.intersect1d(ig, io, assume_unique=True,
+                                    return_indices=True)
+    if common.size == 0:
+        return only
+    pg, vg, po, vo = pg[ag], vg[ag], po[ao], vo[ao]
+    vs = max(float(np.sqrt(np.mean(vo ** 2))), 1e-300)
+    bad_p = np.any(np.abs(pg - po) > 1e-12 * np.maximum(np.abs(po), dx), axis=1)
+    bad_v = np.any(np.abs(vg - vo) > 1e-12 * np.maximum(np.abs(vo), vs), axis=1)
+    bad = int(np.count_nonzero(bad_p | bad_v))
+    assert only + bad <= allow, (s, only, bad, allow)
+    return only + bad
+
+
+@pytest.mark.parametrize("k", CHECKPOINTS)
+def test_c2_teacher_forced_step(gpu_lib, k):
+    from paper_2606_05893_amd import pic as G
+    t0 = time.time()
+    p = W.config("c2")
+    g = P.Grid(p["nx"], p["ny"], p["nz"], p["dx"], p["bc_lo"], p["bc_hi"],
+               p["v_lo"], p["v_hi"])
+    pl = p["preload"]
+    per_step = p["sources"]["disk"]["n_n"]
+    cap = (pl["n_e"] + 2_000_000, pl["n_n"] + per_step * (k + 3) + 1_000_000,
+           pl["n_ion"] + 2_000_000)
+    # The evaporated atoms pile up above the disk, and the collisions there
+    # with them: the per-step event lists grow with the run.
+    gpu = G.Pic(p, capacity=cap, max_events=1 << 22, queue_capacity=1 << 10)
+    pre = W.preload(p, seed=1)
+    n0 = 0
+    for s, (pos, vel, ids) in pre.items():
+        gpu.load(s, pos, vel, ids)
+        n0 += pos.shape[0]
+    del pre
+    gpu.set_clock(0, n0)
+    d = None
+    for i in range(k):
+        _, d = gpu.step(p["dt"])
+        if (i + 1) % 250 == 0:
+            say(t0, f"GPU step {i + 1} of {k}")
+    step_k, next_k = int(d["step"]), int(d["next_id"])
+    assert step_k == k
+    before = read_state(gpu)
+    say(t0, f"state of step {k} read: counts {[v[2].size for v in before.values()]}")
+
+    _, dg = gpu.step(p["dt"])
+    _, phi_g, _ = gpu.read_fields()
+    phi_g = phi_g.cpu().numpy()
+    after = read_state(gpu)
+    del gpu
+    say(t0, f"GPU step {k + 1}: near-threshold draws {dg['near_threshold']}")
+
+    st = O.State(g, seed=p["seed"], w_sp=p["w_sp"])
+    for s, v in before.items():
+        st.load(s, *v)
+    del before
+    st.step, st.next_id = step_k, next_k
+    acc = O.deposit(st)
+    phi_o = P.solve_exact(O.rhs(acc, g, p["w_sp"]), g)
+    assert np.max(np.abs(phi_g - phi_o)) <= 1e-6 * np.max(np.abs(phi_o))
+    assert int(acc.sum()) == int(dg["total_charge_units"])
+    say(t0, "potential within 1e-6 of the oracle's exact solve")
+
+    _, do = O.advance(st, p, O.efield(phi_g, g), p["dt"],
+                      progress=lambda m: say(t0, "oracle " + m))
+    near = int(dg["near_threshold"])
+    assert near == sum(do["near"].values())
+    allow = 4 * near
+    for key in ("elastic", "ionisations", "starved", "fn_emitted"):
+        if near == 0:
+            assert dg[key] == do[key], key
+        else:
+            assert abs(dg[key] - do[key]) <= near, key
+    differ = 0
+    for s in range(C.NSPECIES):
+        differ += compare_species(s, after[s], st.sp[s], p["dx"], allow - differ)
+        say(t0, f"species {s}: {st.count(s)} particles compared")
+    print("step", k + 1, {key: do[key] for key in
+                          ("elastic", "ionisations", "starved", "fn_emitted")},
+          "near", near, "differ", differ, flush=True)
