@@ -1,10 +1,27 @@
 """The BF16-MFMA U-Net kernels against the FP64 oracle: forward output and
-the parameter gradient of the MSE loss (the GPU runs BF16 activations and
-weights with FP32 accumulation, so agreement is to BF16 precision), and an
-Adam training run that lowers the loss."""
+the parameter gradient of the MSE loss, and an Adam training run that
+lowers the loss.
+
+The GPU stores activations, weights and gradients in BF16 and sums in FP32,
+so its distance from FP64 is judged against a model of that number format
+(`unet_bf16.py`: the same network in float32 with BF16 rounding where the
+kernels store BF16).  The model is as far from FP64 as the GPU (forward
+1 %, gradients 1-9 % per tensor), and its output moves by the same 0.7 %
+under a 1e-7 relative change of the weights: with BF16 storage the network
+amplifies rounding, so the GPU and the model cannot agree element by
+element more closely than that; each is instead held to the model's
+distance from FP64, element by element (every element within twice the
+model's largest deviation in that tensor) and per tensor.  The worst
+tensor is the first layer's weight gradient (e0a W, 9 % in relative L2):
+the model gives 8.7 % with BF16 activations and weights whether its
+gradients are stored in BF16 or FP32, and 0.3 % with FP32 activations and
+BF16 gradients, so that error comes from the forward pass's BF16 storage,
+not from the gradients' storage.
+"""
 import numpy as np
 import pytest
 
+from . import unet_bf16 as B
 import workloads as W
 from oracle import unet as U
 
@@ -42,9 +59,43 @@ def test_unet_forward_matches_oracle(gpu_lib):
     x, _ = sample(1)
     out = net.forward(x).cpu().numpy()
     ref, _ = U.forward(p.astype(np.float64), x.astype(np.float64))
-    err = rel(out, ref)
-    print("forward rel L2 error vs FP64:", err)
-    assert err < 0.03
+    model, _ = B.forward(p, x)
+    err, err_m = rel(out, ref), rel(model, ref)
+    worst, worst_m = np.max(np.abs(out - ref)), np.max(np.abs(model - ref))
+    print("forward rel L2 vs FP64: GPU", err, "BF16 model", err_m,
+          "; largest element error: GPU", worst, "model", worst_m)
+    assert err < 0.03 and err <= 1.5 * err_m
+    assert worst <= 2.0 * worst_m
+
+
+def model_samples(p, fn, n=4):
+    """n runs of the BF16 model, the weights nudged by 1e-7 (relative) in
+    all but the first: the spread of the BF16 format's rounding noise."""
+    out = []
+    for k in range(n):
+        q = p if k == 0 else (p * (1.0 + 1e-7 * np.random.default_rng(k).standard_normal(p.size))).astype(np.float32)
+        out.append(np.asarray(fn(q), np.float64))
+    return out
+
+
+def grad_checks(g, g_o, g_ms, tag):
+    """Per tensor: cosine and relative L2 against FP64 within reach of the
+    BF16 model's worst sample, and every element within twice the largest
+    deviation of any model sample.  Returns the worst tensor (relative L2,
+    name)."""
+    lay, n = U.param_layout()
+    worst = (0.0, "")
+    for name, kind, off, shape in lay:
+        sl = slice(off, off + int(np.prod(shape)))
+        a, b = g[sl], g_o[sl]
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
+        e = rel(a, b)
+        e_m = max(rel(m[sl], b) for m in g_ms)
+        dev_m = max(np.max(np.abs(m[sl] - b)) for m in g_ms)
+        worst = max(worst, (e, f"{name} {kind}"))
+        assert cos > 0.98 and e <= 1.5 * e_m + 0.005, (tag, name, kind, cos, e, e_m)
+        assert np.max(np.abs(a - b)) <= 2.0 * dev_m, (tag, name, kind, np.max(np.abs(a - b)), dev_m)
+    return worst
 
 
 def test_unet_gradients_match_oracle(gpu_lib):
@@ -53,26 +104,25 @@ def test_unet_gradients_match_oracle(gpu_lib):
     net = UNet(*SHAPE, params=p)
     x, t = sample(4)
     g, loss = net.gradients(x, t)
-    g = g.cpu().numpy()
+    g = g.cpu().numpy().astype(np.float64)
     loss_o, g_o, _ = U.loss_and_grad(p.astype(np.float64), x.astype(np.float64),
                                      t.astype(np.float64))
+    g_ms = model_samples(p, lambda q: B.loss_and_grad(q, x, t)[1])
     assert abs(loss - loss_o) <= 0.02 * loss_o
-    lay, n = U.param_layout()
-    worst = 0.0
-    for name, kind, off, shape in lay:
-        k = int(np.prod(shape))
-        a, b = g[off:off + k], g_o[off:off + k]
-        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
-        e = rel(a, b)
-        worst = max(worst, e)
-        assert cos > 0.99 and e < 0.1, (name, kind, cos, e)
+    worst = grad_checks(g, g_o, g_ms, "mse")
     print("worst per-tensor gradient rel L2 error vs FP64:", worst)
 
 
 def test_unet_adam_tracks_oracle(gpu_lib):
     """Ten Adam steps on the GPU (BF16 kernels, FP32 master weights and
     moments) against ten FP64 oracle steps from the same parameters: the
-    loss trajectory and the parameter update agree to BF16 precision."""
+    loss trajectory agrees to 2 %, and the parameter update points the
+    FP64 way (cosine >= 0.95) over the elements whose gradient stands above
+    the BF16 noise floor (five times the RMS deviation of the BF16 model's
+    first gradient from FP64 in that tensor; below it Adam, which scales
+    each element by its own gradient RMS, takes full-size steps whose sign
+    BF16 rounding decides).  Over all elements the GPU's update is as close
+    to FP64 as the BF16 model's own ten steps."""
     from paper_2606_05893_amd.pic import UNet
     p0 = W.unet_init(7)
     net = UNet(*SHAPE, params=p0)
@@ -81,26 +131,41 @@ def test_unet_adam_tracks_oracle(gpu_lib):
     steps, lr = 10, 3e-4
     lg = [net.train_step(x, t, lr=lr) for _ in range(steps)]
     pg = net.get_params().cpu().numpy().astype(np.float64)
-    po = p0.astype(np.float64).copy()
-    m, v = np.zeros_like(po), np.zeros_like(po)
-    lo = []
+    po, pm = p0.astype(np.float64).copy(), p0.astype(np.float64).copy()
+    mo, vo, mm, vm = (np.zeros_like(po) for _ in range(4))
+    lo, first = [], None
     for k in range(1, steps + 1):
         loss, g, _ = U.loss_and_grad(po, x.astype(np.float64), t.astype(np.float64))
+        _, gm, _ = B.loss_and_grad(pm.astype(np.float32), x, t)
+        gm = gm.astype(np.float64)
+        if first is None:
+            first = (g.copy(), gm.copy())
         lo.append(loss)
-        U.adam_step(po, m, v, g, k, lr)
+        U.adam_step(po, mo, vo, g, k, lr)
+        U.adam_step(pm, mm, vm, gm, k, lr)
     print("GPU losses:", lg)
     print("oracle losses:", lo)
     for a, b in zip(lg, lo):
         assert abs(a - b) <= 0.02 * b, (a, b)
     assert lg[-1] < 0.9 * lg[0]
-    dg, do = pg - p0, po - p0
-    cos = float(dg @ do / (np.linalg.norm(dg) * np.linalg.norm(do)))
-    print("update cosine:", cos)
-    # Adam scales each element by its own gradient RMS, so elements whose
-    # gradient is near zero take full-size steps whose sign BF16 rounding
-    # decides; those lower the cosine without changing the loss.
-    assert cos > 0.8
+    dg, do, dm = pg - p0, po - p0, pm - p0
 
+    def cos(a, b):
+        return float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-300))
+
+    lay, n = U.param_layout()
+    mask = np.zeros(n, bool)
+    g1, g1m = first
+    for name, kind, off, shape in lay:
+        sl = slice(off, off + int(np.prod(shape)))
+        floor = np.sqrt(np.mean((g1m[sl] - g1[sl]) ** 2))
+        mask[sl] = np.abs(g1[sl]) > 5.0 * floor
+    c_all, c_all_m = cos(dg, do), cos(dm, do)
+    c, c_m = cos(dg[mask], do[mask]), cos(dm[mask], do[mask])
+    print("update cosine vs FP64: all elements GPU", c_all, "model", c_all_m,
+          "; above the BF16 floor (", mask.mean(), "of them) GPU", c, "model", c_m)
+    assert c >= 0.95
+    assert c_all >= c_all_m - 0.02
 
 @pytest.mark.parametrize("k0", [0, 1])
 def test_unet_residual_loss_gradients_match_oracle(gpu_lib, k0):
@@ -119,16 +184,16 @@ def test_unet_residual_loss_gradients_match_oracle(gpu_lib, k0):
     # directly: tight.
     off = [o for name, kind, o, sh in lay if name == "head" and kind == "W"][0]
     assert rel(g[off:off + 16], g_o[off:off + 16]) < 0.02
-    worst = 0.0
-    for name, kind, off, shape in lay:
-        k = int(np.prod(shape))
-        a, b = g[off:off + k], g_o[off:off + k]
-        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))
-        e = rel(a, b)
-        worst = max(worst, e)
-        # Deeper tensors: the A^T A-weighted gradient is mostly high
-        # frequency and largely cancels under pooling on its way to the
-        # coarse levels, which magnifies the BF16 rounding of activations
-        # and gradients (the smooth MSE gradient is held to 0.1).
-        assert cos > 0.98 and e < 0.2, (name, kind, cos, e)
+    # The BF16 model with the output gradient formed in float32 from its
+    # own output, as the kernels form it.
+    def model(q):
+        out_m, cache_m = B.forward(q, x)
+        return B.backward(q, cache_m, B.residual_output_grad(out_m, t, k0))
+
+    g_ms = model_samples(p, model)
+    # Deeper tensors: the A^T A-weighted gradient is mostly high frequency
+    # and largely cancels under pooling on its way to the coarse levels,
+    # which magnifies the BF16 rounding; the model shows the same.
+    worst = grad_checks(g.astype(np.float64), g_o, g_ms, f"residual k0={k0}")
+    assert worst[0] < 0.2
     print("residual loss, k0 =", k0, ": worst per-tensor gradient rel L2 error:", worst)
