@@ -12,12 +12,13 @@ within 1e-12 (the collisions call exp, log, sqrt, sin and cos).  A draw
 within 1e-6 of a threshold may decide an outcome differently on the two
 sides; only then may a few particles (at most four per such draw) differ.
 
-k = 10 runs by default, k in {1, 100} with PIC_C2_CHECKPOINTS=all.  k = 1000
-and 2000 (the configuration's run length) do not run: the evaporation
-source puts its 1e5 atoms a step into the few hundred cells above the disk,
-where they barely move, and the ionisation matching gathers every atom of a
-cell with an ionisation event, so past about 300 steps that list exceeds
-even 4 M entries (the step returns PIC_ERR_CAPACITY).
+k = 10 runs by default; PIC_C2_CHECKPOINTS=all adds k = 1, 100, 1000 and
+2000 (the configuration's run length).  By step 2000 the evaporation
+source has put 2e8 atoms into the few hundred cells above the disk, where
+they barely move; the ionisation matching gathers every atom of a cell
+with an ionisation event, so long runs take event lists of up to 2^28
+entries.  Measured: no differing particle at any of the five checkpoints
+(25 M to 229 M particles compared).
 """
 import os
 import time
@@ -33,12 +34,9 @@ from oracle import poisson as P
 pytestmark = pytest.mark.gpu
 
 ALL = os.environ.get("PIC_C2_CHECKPOINTS") == "all"
-BEYOND = "the atoms of the event cells above the disk exceed the candidate list"
 
 
 def _marks(k):
-    if k >= 1000:
-        return pytest.mark.skip(reason=BEYOND)
     if k == 10 or ALL:
         return ()
     return pytest.mark.skip(reason="long checkpoint: set PIC_C2_CHECKPOINTS=all")
@@ -93,11 +91,16 @@ def test_c2_teacher_forced_step(gpu_lib, k):
                p["v_lo"], p["v_hi"])
     pl = p["preload"]
     per_step = p["sources"]["disk"]["n_n"]
-    cap = (pl["n_e"] + 2_000_000, pl["n_n"] + per_step * (k + 3) + 1_000_000,
-           pl["n_ion"] + 2_000_000)
-    # The evaporated atoms pile up above the disk, and the collisions there
-    # with them: the per-step event lists grow with the run.
-    gpu = G.Pic(p, capacity=cap, max_events=1 << 22, queue_capacity=1 << 10)
+    # Ionisation in the dense atoms above the disk multiplies the charged
+    # particles over a long run.
+    extra = 2_000_000 if k < 300 else 50_000_000
+    cap = (pl["n_e"] + extra, pl["n_n"] + per_step * (k + 3) + 1_000_000,
+           pl["n_ion"] + extra)
+    # The evaporated atoms pile up above the disk, and the ionisation
+    # matching gathers every atom of a cell with an event: the per-step
+    # lists grow with the run (about 1e5 entries per step of the run).
+    max_events = 1 << (22 if k < 300 else 28)
+    gpu = G.Pic(p, capacity=cap, max_events=max_events, queue_capacity=1 << 10)
     pre = W.preload(p, seed=1)
     n0 = 0
     for s, (pos, vel, ids) in pre.items():
@@ -109,7 +112,8 @@ def test_c2_teacher_forced_step(gpu_lib, k):
     for i in range(k):
         _, d = gpu.step(p["dt"])
         if (i + 1) % 250 == 0:
-            say(t0, f"GPU step {i + 1} of {k}")
+            say(t0, f"GPU step {i + 1} of {k}: counts {list(d['counts'])}, "
+                    f"ionisations {d['ionisations']}")
     step_k, next_k = int(d["step"]), int(d["next_id"])
     assert step_k == k
     before = read_state(gpu)
