@@ -952,7 +952,7 @@ inline unsigned nblocks(long long n, int t = kThreads) {
 
 // ---- fused smoothing ------------------------------------------------------
 // Two red-black Gauss-Seidel sweeps (red, black, red, black) in one pass over
-// the level, from uin to uout.  A workgroup owns a kSX x kSY column of nodes
+// the level, from uin to uout.  A workgroup owns an SX x SY column of nodes
 // and a segment of z planes and marches up z: at step p it applies
 // half-sweep h to plane p-h (h = 0..3), so every half-sweep sees the other
 // colour's values of the previous half-sweep on the three planes it reads.
@@ -976,13 +976,31 @@ inline unsigned nblocks(long long n, int t = kThreads) {
 // loaded while step p computes.  HBM traffic per pass: u and f
 // read and u written once, against about four times that for separate
 // launches.
-constexpr int kSX = 32, kSY = 8, kSH = 4;
-constexpr int kSPX = kSX + 2 * kSH, kSPY = kSY + 2 * kSH;
-constexpr int kSP = kSPX * kSPY;  // 640 nodes per plane slot
+//
+// The owned column is SX x SY nodes and the widened one (SX + 8) x (SY + 8),
+// so a workgroup recomputes (SX + 8)(SY + 8) / (SX SY) nodes per owned node:
+// 2.5 at 32 x 8, 1.69 at 64 x 16.  The march is bound by instruction issue,
+// so the larger column pays; FP64 takes 64 x 16 (864 threads, 83 KB of
+// LDS ring), FP32 32 x 16 (480 threads), which measured faster than 64 x 16
+// in FP32 (more resident workgroups per CU for the latency of the march).
+template <typename T>
+struct SmoothTile;
+template <>
+struct SmoothTile<double> {
+  static constexpr int SX = 64, SY = 16;
+};
+template <>
+struct SmoothTile<float> {
+  static constexpr int SX = 32, SY = 16;
+};
+constexpr int kSH = 4;
 constexpr int kSR = 6;
-constexpr int kHX = kSPX / 2, kHP = kHX * kSPY;
-constexpr int kSmoothT = kHX * kSPY;  // one x-pair per thread: 320
-static_assert((kSPX & 1) == 0 && (kSH & 1) == 0, "x-pairs need even x");
+// One x-pair of the widened column per thread.
+template <typename T>
+__host__ __device__ constexpr int smooth_threads() {
+  return (SmoothTile<T>::SX + 2 * kSH) / 2 * (SmoothTile<T>::SY + 2 * kSH);
+}
+static_assert((kSH & 1) == 0, "x-pairs need even x");
 
 __device__ __forceinline__ int wrap_n(int v, int n) {
   v = v < 0 ? v + n : v;
@@ -1001,10 +1019,15 @@ __host__ __device__ constexpr int ring_slot(int j, int d) {
 // NEU: a z face of the level holds unknowns (Neumann condition), so face
 // planes are updated; with Dirichlet faces they never are.
 template <typename T, bool NEU>
-__global__ void __launch_bounds__(kSmoothT) k_smooth2(
+__global__ void __launch_bounds__(smooth_threads<T>()) k_smooth2(
     const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ f,
     LevelC L, int seg, const Counters* dc) {
   using P2 = typename Pair2<T>::type;
+  constexpr int kSX = SmoothTile<T>::SX, kSY = SmoothTile<T>::SY;
+  constexpr int kSPX = kSX + 2 * kSH, kSPY = kSY + 2 * kSH;
+  constexpr int kSP = kSPX * kSPY;  // nodes per plane slot
+  constexpr int kHX = kSPX / 2, kHP = kHX * kSPY;
+  static_assert((kSX & 1) == 0 && kHX * kSPY == smooth_threads<T>(), "tile");
   __shared__ T ring[kSR][kSP];
   if (dc->done) return;
   const int tiles_x = (L.nx + kSX - 1) / kSX;
@@ -1880,7 +1903,8 @@ long long smooth_slots() {
   if (dev < 0 || dev >= 64) dev = 0;
   if (!cached[dev]) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth2<T, false>, kSmoothT, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth2<T, false>,
+                                                     smooth_threads<T>(), 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -1939,12 +1963,13 @@ void vcycle(pic_ctx* c, int l) {
   T* sp = lev_s<T>(L);
   const bool fused = sp && !(c->cfg.flags & PIC_FLAG_PLAIN_SMOOTHER) &&
                      c->cfg.nu_pre == 2 && c->cfg.nu_post == 2 &&
-                     L.nx >= kSX && L.ny >= kSY;
+                     L.nx >= SmoothTile<T>::SX && L.ny >= SmoothTile<T>::SY;
   unsigned fgrid = 0;
   int seg = 0;
   if (fused) {
     // One round of workgroups: as many z segments as the device keeps
     // resident, since each segment's march is a latency-bound chain.
+    constexpr int kSX = SmoothTile<T>::SX, kSY = SmoothTile<T>::SY;
     const long long nxy_t = (long long)((L.nx + kSX - 1) / kSX) * ((L.ny + kSY - 1) / kSY);
     const long long slots = smooth_slots<T>();
     seg = (int)(((long long)(L.nz + 1) * nxy_t + slots - 1) / slots);
@@ -1964,9 +1989,9 @@ void vcycle(pic_ctx* c, int l) {
   auto smooth_fused = [&](const T* in, T* out) {
     if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
     if (Lc.k0 == 0 || Lc.k1 == Lc.nz)
-      k_smooth2<T, true><<<fgrid, kSmoothT, 0, st>>>(in, out, f, Lc, seg, c->dc);
+      k_smooth2<T, true><<<fgrid, smooth_threads<T>(), 0, st>>>(in, out, f, Lc, seg, c->dc);
     else
-      k_smooth2<T, false><<<fgrid, kSmoothT, 0, st>>>(in, out, f, Lc, seg, c->dc);
+      k_smooth2<T, false><<<fgrid, smooth_threads<T>(), 0, st>>>(in, out, f, Lc, seg, c->dc);
     if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
   };
   T* uc = u;  // fine values the restriction reads and the prolongation corrects
