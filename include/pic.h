@@ -219,6 +219,9 @@ typedef struct {
   int32_t warm_used;       /* the network ran in this solve                */
   int32_t warm_rejected;   /* ... and its start was rejected (non-finite,
                               or a larger residual than phi_prev's)        */
+  int32_t refinements;     /* mixed form: refinement rounds (FP32 V-cycles
+                              on the correction, then the FP64 residual);
+                              0 in FP64                                    */
 } pic_solve_info;
 
 typedef struct {

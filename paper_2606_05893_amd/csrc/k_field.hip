@@ -154,13 +154,15 @@ __global__ void k_rhs(const long long* __restrict__ acc,
 // Fixed-tree sum of the block partials.  mode 0: ||b|| (and the integer
 // charge); mode 1: residual check after a V-cycle (counts the cycle, sets
 // done when converged); mode 2: initial residual check of the warm start;
-// mode 3: field energy.
+// mode 3: field energy; mode 4: as mode 1, after a refinement round of the
+// mixed form (also counts the round).  Modes 1 and 4 count 'cycles' V-cycles
+// (those run since the last check).
 __global__ void k_final(const double* __restrict__ part,
                         const long long* __restrict__ qpart, int n,
-                        Counters* dc, int mode, double tol) {
+                        Counters* dc, int mode, double tol, int cycles = 1) {
   __shared__ double s[1024];
   __shared__ long long q[1024];
-  if ((mode == 1) && dc->done) return;
+  if ((mode == 1 || mode == 4) && dc->done) return;
   double a = 0.0;
   long long qa = 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -184,8 +186,10 @@ __global__ void k_final(const double* __restrict__ part,
     dc->done = 0;
     dc->vcycles = 0;
     dc->rel_res = 1.0;
-  } else if (mode == 1 || mode == 2) {
-    if (mode == 1) dc->vcycles += 1;
+    dc->refinements = 0;
+  } else if (mode == 1 || mode == 2 || mode == 4) {
+    if (mode == 1 || mode == 4) dc->vcycles += cycles;
+    if (mode == 4) dc->refinements += 1;
     const double bn = dc->b_norm;
     const double rr = bn > 0.0 ? sqrt(s[0]) / bn : 0.0;
     dc->rel_res = rr;
@@ -201,14 +205,12 @@ __global__ void k_final(const double* __restrict__ part,
   }
 }
 
-// A V-cycle run without a residual check.
-__global__ void k_count_cycle(Counters* dc) {
-  if (!dc->done) dc->vcycles += 1;
-}
 
 // Residual r = f - A u / h2 on level 0 (FP64): block partials of sum(r^2).
 // With rf != nullptr (mixed form) also writes r in FP32 as the right-hand
-// side of the correction solve and zeroes the FP32 correction.
+// side of the correction solve, and with ef != nullptr zeroes the FP32
+// correction (the start of the next correction solve, unless its first
+// smoothing pass starts from zero by itself).
 __global__ void k_residual(const double* __restrict__ u,
                            const double* __restrict__ f, LevelC L,
                            double* __restrict__ part, const Counters* dc,
@@ -275,14 +277,12 @@ __global__ void k_residual(const double* __restrict__ u,
       s2 = s2 + res0 * res0;
       s2 = s2 + res1 * res1;
       if (rf) {
-        float2 rv, zv;
+        float2 rv;
         rv.x = (float)res0;
         rv.y = (float)res1;
-        zv.x = 0.0f;
-        zv.y = 0.0f;
         *reinterpret_cast<float2*>(rf + base + r0 + i0) = rv;
-        *reinterpret_cast<float2*>(ef + base + r0 + i0) = zv;
       }
+      if (ef) *reinterpret_cast<float2*>(ef + base + r0 + i0) = make_float2(0.0f, 0.0f);
       dn = cur;
       cur = up;
     }
@@ -625,29 +625,50 @@ __global__ void __launch_bounds__(256) k_prolong_pairs(
 }
 
 // Restriction with the fine residual staged in LDS: a workgroup takes an
-// 8x8x4 block of coarse nodes.  It stages the 19x19x11 fine u nodes the
-// block's residuals read (coalesced, each node once), computes the residual
-// of the 17x17x9 fine nodes under the block from LDS (same stencil and
-// order as nb_sum), then applies the 27-point full weighting from LDS.
-constexpr int kRX = 8, kRY = 8, kRZ = 4;
-constexpr int kFX = 2 * kRX + 1, kFY = 2 * kRY + 1, kFZ = 2 * kRZ + 1;
-constexpr int kUX = kFX + 2, kUY = kFY + 2, kUZ = kFZ + 2;
-constexpr int kUXY = kUX * kUY;
+// RX x RY x RZ block of coarse nodes, one per thread.  It stages the
+// (2RX+3)(2RY+3)(2RZ+3) fine u nodes the block's residuals read (coalesced,
+// each node once), computes the residual of the (2RX+1)(2RY+1)(2RZ+1) fine
+// nodes under the block from LDS (same stencil and order as nb_sum), then
+// applies the 27-point full weighting from LDS.  FP64 takes 8x8x4 blocks
+// (31.8 KB of LDS); FP32 16x8x4 on 512 threads (29.3 KB), which stages 1.79
+// fine nodes per owned one against 1.94 and halves the blocks, the pass
+// being bound by its load and LDS instructions rather than by bytes.
+template <typename T>
+struct RTile {
+  static constexpr int RX = 8, RY = 8, RZ = 4;
+};
+template <>
+struct RTile<float> {
+  static constexpr int RX = 16, RY = 8, RZ = 4;
+};
+template <typename T>
+__host__ __device__ constexpr int restrict_threads() {
+  return RTile<T>::RX * RTile<T>::RY * RTile<T>::RZ;
+}
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_restrict_tiled(
+__global__ void __launch_bounds__(restrict_threads<T>()) k_restrict_tiled(
     const T* __restrict__ uf, const T* __restrict__ ff, T* __restrict__ uc,
     T* __restrict__ fc, LevelC F, LevelC Cc, const Counters* dc) {
-  // The staged u block, then (reused) the residuals: 31.8 KB in FP64.
+  constexpr int kRX = RTile<T>::RX, kRY = RTile<T>::RY, kRZ = RTile<T>::RZ;
+  constexpr int kNT = restrict_threads<T>();
+  constexpr int kFX = 2 * kRX + 1, kFY = 2 * kRY + 1, kFZ = 2 * kRZ + 1;
+  constexpr int kUX = kFX + 2, kUY = kFY + 2, kUZ = kFZ + 2;
+  constexpr int kUXY = kUX * kUY;
+  // The staged u block, then (reused) the residuals.
   __shared__ T su[kUZ * kUXY];
   static_assert(kFZ * kFY * kFX <= kUZ * kUXY, "residuals reuse the u block");
-  constexpr int kRPer = (kFZ * kFY * kFX + 255) / 256;
+  constexpr int kRPer = (kFZ * kFY * kFX + kNT - 1) / kNT;
   if (dc->done) return;
   const int tnx = (Cc.nx + kRX - 1) / kRX, tny = (Cc.ny + kRY - 1) / kRY;
   // Neighbouring tiles share halo nodes: keep them on one XCD's L2.
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   const int bx = blk % tnx, by = (blk / tnx) % tny, bz = blk / (tnx * tny);
-  const int cx0 = bx * kRX, cy0 = by * kRY, cz0 = bz * kRZ;
+  // The blocks cover the unknown coarse planes k0..k1 (the face planes of a
+  // Dirichlet level are zeroed by the blocks next to them): with 2^m + 1
+  // planes a level has 2^m - 1 unknown ones, so the blocks fill whole
+  // rounds of resident workgroups instead of leaving a round for one plane.
+  const int cx0 = bx * kRX, cy0 = by * kRY, cz0 = Cc.k0 + bz * kRZ;
   const T inv_h2 = T(1) / (T)F.h2;
   // Staged node (sx, sy, sz) is fine node (2cx0 - 2 + sx, 2cy0 - 2 + sy,
   // 2cz0 - 2 + sz), x and y wrapped; planes outside [0, nz] are loaded
@@ -657,11 +678,11 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
   // Every global load of the block is issued before the first use (clamped
   // to a valid node where the slot is unused), so they are all in flight
   // together: the u block, then the f values of this thread's residuals.
-  constexpr int kSPer = (kUZ * kUXY + 255) / 256;
+  constexpr int kSPer = (kUZ * kUXY + kNT - 1) / kNT;
   T uv[kSPer];
 #pragma unroll
   for (int m = 0; m < kSPer; ++m) {
-    int q = threadIdx.x + 256 * m;
+    int q = threadIdx.x + kNT * m;
     q = q < kUZ * kUXY ? q : kUZ * kUXY - 1;
     const int sx = q % kUX, sy = (q / kUX) % kUY, sz = q / kUXY;
     const int i = wrap_index(2 * cx0 - 2 + sx, F.nx);
@@ -674,7 +695,7 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
   int rk[kRPer], rc[kRPer];
 #pragma unroll
   for (int m = 0; m < kRPer; ++m) {
-    int q = threadIdx.x + 256 * m;
+    int q = threadIdx.x + kNT * m;
     q = q < kFZ * kFY * kFX ? q : kFZ * kFY * kFX - 1;
     const int lx = q % kFX, ly = (q / kFX) % kFY, lz = q / (kFX * kFY);
     int k = 2 * cz0 - 1 + lz;
@@ -689,7 +710,7 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
   }
 #pragma unroll
   for (int m = 0; m < kSPer; ++m) {
-    const int q = threadIdx.x + 256 * m;
+    const int q = threadIdx.x + kNT * m;
     if (q < kUZ * kUXY) su[q] = uv[m];
   }
   __syncthreads();
@@ -698,7 +719,7 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
   for (int m = 0; m < kRPer; ++m) {
     const int k = rk[m], c = rc[m];
     T res = T(0);
-    if (threadIdx.x + 256 * m < kFZ * kFY * kFX && k >= F.k0 && k <= F.k1) {
+    if (threadIdx.x + kNT * m < kFZ * kFY * kFX && k >= F.k0 && k <= F.k1) {
       T sn = su[c - 1] + su[c + 1];
       sn = sn + (su[c - kUX] + su[c + kUX]);
       T zs;
@@ -716,7 +737,7 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
   T* r = su;
 #pragma unroll
   for (int m = 0; m < kRPer; ++m) {
-    const int q = threadIdx.x + 256 * m;
+    const int q = threadIdx.x + kNT * m;
     if (q < kFZ * kFY * kFX) r[q] = rv[m];
   }
   __syncthreads();
@@ -729,6 +750,14 @@ __global__ void __launch_bounds__(256) k_restrict_tiled(
   if (kc < Cc.k0 || kc > Cc.k1) {
     fc[t] = T(0);
     return;
+  }
+  if (kc == Cc.k0 && Cc.k0 > 0) {
+    uc[t - Cc.nxy] = T(0);
+    fc[t - Cc.nxy] = T(0);
+  }
+  if (kc == Cc.k1 && Cc.k1 < Cc.nz) {
+    uc[t + Cc.nxy] = T(0);
+    fc[t + Cc.nxy] = T(0);
   }
   T acc = T(0);
   for (int dk = 0; dk < 3; ++dk) {
@@ -1016,12 +1045,21 @@ __host__ __device__ constexpr int ring_slot(int j, int d) {
   return ((1 + j + d) % kSR + kSR) % kSR;
 }
 
+// Level-0 pass modes of the mixed form's FP32 correction solve: the first
+// pass of a refinement round starts from a zero correction without reading
+// one (kSmZeroIn); the last adds its correction to the FP64 potential u64 on
+// the unknown planes instead of storing it (kSmAcc64: u64 + (double)e, the
+// FP64 accumulation of the refinement).
+enum : int { kSmPlain = 0, kSmZeroIn = 1, kSmAcc64 = 2 };
+
 // NEU: a z face of the level holds unknowns (Neumann condition), so face
 // planes are updated; with Dirichlet faces they never are.
-template <typename T, bool NEU>
+template <typename T, bool NEU, int MODE>
 __global__ void __launch_bounds__(smooth_threads<T>()) k_smooth2(
     const T* __restrict__ uin, T* __restrict__ uout, const T* __restrict__ f,
-    LevelC L, int seg, const Counters* dc) {
+    LevelC L, int seg, const Counters* dc, double* __restrict__ u64) {
+  static_assert(MODE == kSmPlain || std::is_same<T, float>::value,
+                "pass modes of the FP32 correction solve");
   using P2 = typename Pair2<T>::type;
   constexpr int kSX = SmoothTile<T>::SX, kSY = SmoothTile<T>::SY;
   constexpr int kSPX = kSX + 2 * kSH, kSPY = kSY + 2 * kSH;
@@ -1093,7 +1131,21 @@ __global__ void __launch_bounds__(smooth_threads<T>()) k_smooth2(
   // plane, which the face update never uses.
   auto fetch_u = [&](auto U, int z) {
     constexpr int iu = decltype(U)::value;
-    pu[iu] = *reinterpret_cast<const P2*>(uin + clampz(z) * nxy + goff);
+    if constexpr ((MODE & kSmZeroIn) != 0) {
+      pu[iu].x = T(0);
+      pu[iu].y = T(0);
+    } else {
+      pu[iu] = *reinterpret_cast<const P2*>(uin + clampz(z) * nxy + goff);
+    }
+  };
+  // kSmAcc64: the FP64 pair of the plane stored two steps later, loaded
+  // into slot (step & 1) once that slot's previous pair is stored.
+  double2 pa[2];
+  auto fetch_acc = [&](auto A, int z) {
+    if constexpr ((MODE & kSmAcc64) != 0) {
+      constexpr int ia = decltype(A)::value;
+      pa[ia] = *reinterpret_cast<const double2*>(u64 + (long long)clampz(z) * nxy + goff);
+    }
   };
   auto commit_u = [&](auto U, auto S) {
     constexpr int iu = decltype(U)::value, sl = decltype(S)::value;
@@ -1149,11 +1201,21 @@ __global__ void __launch_bounds__(smooth_threads<T>()) k_smooth2(
     const int q = p - 3;
     if (owned && q >= za && q < zb) {
       constexpr int so = ring_slot(j, -3);
-      P2 w;
-      w.x = v0[so];
-      w.y = v1[so];
-      *reinterpret_cast<P2*>(uout + (long long)q * L.nxy + goff) = w;
+      if constexpr ((MODE & kSmAcc64) != 0) {
+        if (q >= L.k0 && q <= L.k1) {
+          double2 w = pa[jf];
+          w.x = w.x + (double)v0[so];
+          w.y = w.y + (double)v1[so];
+          *reinterpret_cast<double2*>(u64 + (long long)q * L.nxy + goff) = w;
+        }
+      } else {
+        P2 w;
+        w.x = v0[so];
+        w.y = v1[so];
+        *reinterpret_cast<P2*>(uout + (long long)q * L.nxy + goff) = w;
+      }
     }
+    fetch_acc(IC<jf>(), p - 1);
     commit_u(IC<jf>(), IC<ring_slot(j, 2)>());
     fetch_u(IC<jf>(), p + 4);
     fetch_f(IC<ring_slot(j, 2)>(), p + 2);
@@ -1178,6 +1240,8 @@ __global__ void __launch_bounds__(smooth_threads<T>()) k_smooth2(
   fetch_f(IC<ring_slot(0, -1)>(), p0 - 1);
   fetch_f(IC<ring_slot(0, 0)>(), p0);
   fetch_f(IC<ring_slot(0, 1)>(), p0 + 1);
+  fetch_acc(IC<0>(), p0 - 3);
+  fetch_acc(IC<1>(), p0 - 2);
   __syncthreads();
   for (int p = p0;; p += kSR) {
     step(IC<0>(), p);
@@ -1903,7 +1967,7 @@ long long smooth_slots() {
   if (dev < 0 || dev >= 64) dev = 0;
   if (!cached[dev]) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth2<T, false>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_smooth2<T, false, kSmPlain>,
                                                      smooth_threads<T>(), 0) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
@@ -1915,10 +1979,46 @@ long long smooth_slots() {
   return cached[dev];
 }
 
-// One V(nu_pre, nu_post) cycle from level l down.  Level 0 of an FP32
-// cycle is the correction equation of the mixed form.
+// Level l is smoothed by the fused two-sweep pass (it is neither the exact
+// coarse level, the coarsest, nor in the single-workgroup tail).
 template <typename T>
-void vcycle(pic_ctx* c, int l) {
+bool level_fused(pic_ctx* c, int l) {
+  if (l == c->spec_level || l >= c->nlev - 1 || l >= tail_first<T>(c)) return false;
+  const Level& L = c->lev[l];
+  return lev_s<T>(c->lev[l]) && !(c->cfg.flags & PIC_FLAG_PLAIN_SMOOTHER) &&
+         c->cfg.nu_pre == 2 && c->cfg.nu_post == 2 && L.nx >= SmoothTile<T>::SX &&
+         L.ny >= SmoothTile<T>::SY;
+}
+
+template <typename T, bool NEU>
+void launch_smooth(unsigned grid, hipStream_t st, const T* in, T* out,
+                   const T* f, LevelC L, int seg, const Counters* dc, int mode,
+                   double* u64) {
+  constexpr int nt = smooth_threads<T>();
+  if constexpr (std::is_same<T, float>::value) {
+    switch (mode) {
+      case kSmZeroIn:
+        k_smooth2<T, NEU, kSmZeroIn><<<grid, nt, 0, st>>>(in, out, f, L, seg, dc, u64);
+        return;
+      case kSmAcc64:
+        k_smooth2<T, NEU, kSmAcc64><<<grid, nt, 0, st>>>(in, out, f, L, seg, dc, u64);
+        return;
+      case kSmZeroIn | kSmAcc64:
+        k_smooth2<T, NEU, kSmZeroIn | kSmAcc64><<<grid, nt, 0, st>>>(in, out, f, L, seg, dc, u64);
+        return;
+      default:
+        break;
+    }
+  }
+  k_smooth2<T, NEU, kSmPlain><<<grid, nt, 0, st>>>(in, out, f, L, seg, dc, u64);
+}
+
+// One V(nu_pre, nu_post) cycle from level l down.  Level 0 of an FP32
+// cycle is the correction equation of the mixed form; l0_mode gives the
+// pass modes of its fused smoothing (kSmZeroIn for the pre-smoothing pass,
+// kSmAcc64 for the post-smoothing one).
+template <typename T>
+void vcycle(pic_ctx* c, int l, int l0_mode = kSmPlain) {
   hipStream_t st = c->stream;
   if (l == c->spec_level) {
     spectral_solve<T>(c, l);
@@ -1961,9 +2061,7 @@ void vcycle(pic_ctx* c, int l) {
   // Fused pass (two sweeps each way): u -> spare before the restriction,
   // the coarse correction is added to the spare, spare -> u after.
   T* sp = lev_s<T>(L);
-  const bool fused = sp && !(c->cfg.flags & PIC_FLAG_PLAIN_SMOOTHER) &&
-                     c->cfg.nu_pre == 2 && c->cfg.nu_post == 2 &&
-                     L.nx >= SmoothTile<T>::SX && L.ny >= SmoothTile<T>::SY;
+  const bool fused = level_fused<T>(c, l);
   unsigned fgrid = 0;
   int seg = 0;
   if (fused) {
@@ -1986,27 +2084,30 @@ void vcycle(pic_ctx* c, int l) {
         if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
       }
   };
-  auto smooth_fused = [&](const T* in, T* out) {
+  auto smooth_fused = [&](const T* in, T* out, int mode) {
     if (l == 0) tmark(c, PIC_PH_SMOOTH0, true);
     if (Lc.k0 == 0 || Lc.k1 == Lc.nz)
-      k_smooth2<T, true><<<fgrid, smooth_threads<T>(), 0, st>>>(in, out, f, Lc, seg, c->dc);
+      launch_smooth<T, true>(fgrid, st, in, out, f, Lc, seg, c->dc, mode, c->lev[0].u);
     else
-      k_smooth2<T, false><<<fgrid, smooth_threads<T>(), 0, st>>>(in, out, f, Lc, seg, c->dc);
+      launch_smooth<T, false>(fgrid, st, in, out, f, Lc, seg, c->dc, mode, c->lev[0].u);
     if (l == 0) tmark(c, PIC_PH_SMOOTH0, false);
   };
+  const int pre_mode = l == 0 ? (l0_mode & kSmZeroIn) : kSmPlain;
+  const int post_mode = l == 0 ? (l0_mode & kSmAcc64) : kSmPlain;
   T* uc = u;  // fine values the restriction reads and the prolongation corrects
   if (fused) {
-    smooth_fused(u, sp);
+    smooth_fused(u, sp, pre_mode);
     uc = sp;
   } else {
     smooth_plain(c->cfg.nu_pre);
   }
   Level& N = c->lev[l + 1];
   LevelC Nc = level_c(c, l + 1);
+  constexpr int kRX = RTile<T>::RX, kRY = RTile<T>::RY, kRZ = RTile<T>::RZ;
   if (N.nx >= kRX && N.ny >= kRY) {
     const long long nb = (long long)((N.nx + kRX - 1) / kRX) *
-                         ((N.ny + kRY - 1) / kRY) * ((N.nz + 1 + kRZ - 1) / kRZ);
-    k_restrict_tiled<T><<<(unsigned)nb, 256, 0, st>>>(
+                         ((N.ny + kRY - 1) / kRY) * ((Nc.k1 - Nc.k0 + kRZ) / kRZ);
+    k_restrict_tiled<T><<<(unsigned)nb, restrict_threads<T>(), 0, st>>>(
         uc, f, lev_u<T>(N), lev_f<T>(N), Lc, Nc, c->dc);
   } else {
     k_restrict<T><<<nblocks(N.nnodes), kThreads, 0, st>>>(
@@ -2020,7 +2121,7 @@ void vcycle(pic_ctx* c, int l) {
         uc, lev_u<T>(N), Lc, Nc, nbx, c->dc);
   }
   if (fused)
-    smooth_fused(sp, u);
+    smooth_fused(sp, u, post_mode);
   else
     smooth_plain(c->cfg.nu_post);
 }
@@ -2057,8 +2158,12 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
                    st);
   }
   const long long nu = Lc.nxy * (Lc.k1 - Lc.k0 + 1);
+  // Mixed form: with a fused level-0 pass the correction solve starts from
+  // zero and ends in the FP64 potential by itself; otherwise the FP32
+  // correction is zeroed with each residual and added by k_correct.
+  const bool mixed_fused = c->mixed && level_fused<float>(c, 0);
   float* rf = c->mixed ? L0.ff : nullptr;
-  float* ef = c->mixed ? L0.uf : nullptr;
+  float* ef = c->mixed && !mixed_fused ? L0.uf : nullptr;
   bool used_net = false;
   if (warm && (c->warm_mode == PIC_WS_RECORD || c->warm_mode == PIC_WS_UNET)) {
     tmark(c, PIC_PH_WARM, true);
@@ -2096,29 +2201,54 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
   k_final<<<1, 1024, 0, st>>>(c->partials, c->qpartials, kRedBlocks, c->dc, 2,
                               c->cfg.rel_tol);
   int launched = 0;
-  int batch = c->last_vcycles > 0 ? c->last_vcycles : 4;
-  // An FP64 V-cycle needs no residual: the check only decides when to stop,
-  // so the cycles the last solve says will not suffice run unchecked (a
-  // solve that converges sooner just ends more accurate).  The mixed form's
-  // correction equation needs the FP64 residual after every cycle.
+  // FP64: a V-cycle needs no residual, since the check only decides when to
+  // stop, so the cycles the last solve says will not suffice run unchecked
+  // (a solve that converges sooner just ends more accurate).  Mixed:
+  // refinement rounds of kInner FP32 V-cycles on the correction equation
+  // A e = r (r the FP64 residual rounded to FP32; two over-relaxed cycles cut
+  // its error about 10^4-fold, to near FP32 accuracy), the correction added
+  // to phi in FP64, then the FP64 residual: the convergence check and the
+  // next round's right-hand side.  Batches count cycles in FP64 and rounds
+  // in the mixed form.
+  constexpr int kInner = 2;
+  const int last = c->last_vcycles > 0 ? c->last_vcycles : 4;
+  int batch = c->mixed ? (last + kInner - 1) / kInner : last;
   const int unchecked = c->mixed ? 0 : std::max(0, batch - 2);
+  int pending = 0;  // FP64 cycles run since the last check
   *status = PIC_OK;
   while (true) {
-    for (int b = 0; b < batch && launched < c->cfg.max_vcycles; ++b, ++launched) {
+    for (int b = 0; b < batch && launched < c->cfg.max_vcycles; ++b) {
       if (c->mixed) {
-        vcycle<float>(c, 0);
-        k_correct<<<nblocks(nu), kThreads, 0, st>>>(L0.u, L0.uf, Lc, c->dc);
-      } else {
-        vcycle<double>(c, 0);
-      }
-      if (launched < unchecked) {
-        k_count_cycle<<<1, 1, 0, st>>>(c->dc);
+        const int n_in = std::min(kInner, c->cfg.max_vcycles - launched);
+        for (int i = 0; i < n_in; ++i, ++launched) {
+          int mode = kSmPlain;
+          if (mixed_fused && i == 0) mode |= kSmZeroIn;
+          if (mixed_fused && i == n_in - 1) mode |= kSmAcc64;
+          vcycle<float>(c, 0, mode);
+        }
+        if (!mixed_fused)
+          k_correct<<<nblocks(nu), kThreads, 0, st>>>(L0.u, L0.uf, Lc, c->dc);
+        k_residual<<<kRedBlocks, kThreads, 0, st>>>(L0.u, L0.f, Lc, c->partials,
+                                                    c->dc, rf, ef);
+        k_final<<<1, 1024, 0, st>>>(c->partials, c->qpartials, kRedBlocks,
+                                    c->dc, 4, c->cfg.rel_tol, n_in);
         continue;
       }
+      vcycle<double>(c, 0);
+      ++pending;
+      if (launched++ < unchecked) continue;
       k_residual<<<kRedBlocks, kThreads, 0, st>>>(L0.u, L0.f, Lc, c->partials,
                                                   c->dc, rf, ef);
       k_final<<<1, 1024, 0, st>>>(c->partials, c->qpartials, kRedBlocks,
-                                  c->dc, 1, c->cfg.rel_tol);
+                                  c->dc, 1, c->cfg.rel_tol, pending);
+      pending = 0;
+    }
+    if (pending) {  // the cycle limit ended the batch before its check
+      k_residual<<<kRedBlocks, kThreads, 0, st>>>(L0.u, L0.f, Lc, c->partials,
+                                                  c->dc, rf, ef);
+      k_final<<<1, 1024, 0, st>>>(c->partials, c->qpartials, kRedBlocks,
+                                  c->dc, 1, c->cfg.rel_tol, pending);
+      pending = 0;
     }
     constexpr size_t kOff = offsetof(Counters, vcycles);
     hipMemcpyAsync(reinterpret_cast<char*>(c->hpin) + kOff,
@@ -2139,6 +2269,7 @@ void field_solve(pic_ctx* c, bool warm, pic_solve_info* info, int* status) {
   info->warm_used = used_net ? 1 : 0;
   info->warm_rejected = used_net ? c->hc.warm_reject : 0;
   info->warm_ratio = used_net ? c->hc.warm_ratio : 1.0;
+  info->refinements = c->hc.refinements;
   c->last_vcycles = c->hc.vcycles > 0 ? c->hc.vcycles : 1;
   if (!info->converged) *status = PIC_ERR_NOCONV;
 }

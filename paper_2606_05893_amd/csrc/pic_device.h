@@ -278,7 +278,7 @@ struct Counters {
   unsigned int err;                 // sticky error bits (kErr*)
   int vcycles;
   int done;                         // Poisson solve converged
-  int pad;
+  int refinements;                  // FP64 residuals of the mixed form's refinement
   double rel_res;
   double b_norm;
   double kinetic[4];

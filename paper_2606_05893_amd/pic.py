@@ -69,7 +69,8 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [("vcycles", _c_i32), ("converged", _c_i32),
                 ("rel_residual", _c_d), ("b_norm", _c_d),
                 ("rel_residual0", _c_d), ("warm_ratio", _c_d),
-                ("warm_used", _c_i32), ("warm_rejected", _c_i32)]
+                ("warm_used", _c_i32), ("warm_rejected", _c_i32),
+                ("refinements", _c_i32)]
 
 
 class Diag(ctypes.Structure):
