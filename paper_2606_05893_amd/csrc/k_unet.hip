@@ -36,12 +36,17 @@ typedef unsigned short bf16;  // storage
 __device__ __forceinline__ float bf2f(bf16 h) {
   return __uint_as_float((unsigned)h << 16);
 }
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+// Round to nearest even (the CDNA4 conversion instruction, two at a time).
+__device__ __forceinline__ unsigned f2bf2(float lo, float hi) {
+  const bf16x2v h = __builtin_convertvector((f2v){lo, hi}, bf16x2v);
+  unsigned r;
+  __builtin_memcpy(&r, &h, 4);
+  return r;
+}
 __device__ __forceinline__ bf16 f2bf(float x) {
-  // Round to nearest even (inputs are finite here; NaN keeps a NaN pattern).
-  unsigned u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (bf16)(u >> 16);
+  return (bf16)(f2bf2(x, 0.0f) & 0xffffu);
 }
 
 __device__ __forceinline__ bf16x8 load8(const bf16* p) {
@@ -101,6 +106,76 @@ __device__ __forceinline__ long long nb_voxel(const Dims& d, int z, int y,
 
 constexpr int KP(int cin) { return (27 * cin + 63) / 64 * 64; }
 
+// Stage the halo of a tile for one slice of 16 input channels into LDS:
+// HV voxels of 32 B as two planes of 16-byte halves (x and y periodic, z
+// zero-padded).  The slice is channels c0 .. c0 + 15 of a tensor of C
+// channels per voxel: at the tile's dims, or (UP) at half of them, read as
+// its nearest upsampling (fine voxel (z, y, x) takes coarse (z/2, y/2,
+// x/2)).  Every global load of a thread is issued before the first LDS
+// store, so they are all in flight together.  ONE: the level is at least a
+// halo wide, so one wrap brings every coordinate into range.
+template <int HX, int HY, int HZ, int NTH, bool ONE, bool UP>
+__device__ __forceinline__ void stage_halo_w(uint4* lds, const bf16* __restrict__ in,
+                                             int C, int c0, const Dims& d, int x0,
+                                             int y0, int z0) {
+  constexpr int HV = HX * HY * HZ;
+  constexpr int PER = (2 * HV + NTH - 1) / NTH;
+  uint4 val[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int q = (int)threadIdx.x + m * NTH;
+    const int hv = q >> 1, hh = q & 1;
+    const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+    const int gz = z0 + hz - 1;
+    val[m] = make_uint4(0, 0, 0, 0);
+    if (q < 2 * HV && gz >= 0 && gz < d.D) {
+      int gy = y0 + hy - 1, gx = x0 + hx - 1;
+      if constexpr (ONE) {
+        gy = gy < 0 ? gy + d.H : (gy >= d.H ? gy - d.H : gy);
+        gx = gx < 0 ? gx + d.W : (gx >= d.W ? gx - d.W : gx);
+      } else {
+        gy = (gy + d.H) % d.H;
+        gx = (gx + d.W) % d.W;
+      }
+      size_t gv;
+      if constexpr (UP)
+        gv = ((size_t)(gz >> 1) * (d.H >> 1) + (gy >> 1)) * (d.W >> 1) + (gx >> 1);
+      else
+        gv = ((size_t)gz * d.H + gy) * d.W + gx;
+      val[m] = ld16(in + gv * C + c0 + hh * 8);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int q = (int)threadIdx.x + m * NTH;
+    if (q < 2 * HV) lds[(q & 1) * HV + (q >> 1)] = val[m];
+  }
+}
+
+// Slice sl of the input: of 'in' (CIN channels), or with CU > 0 of the
+// concatenation [up(in) (CU channels, half dims), skip (CIN - CU)].
+template <int CIN, int CU, int HX, int HY, int HZ, int NTH>
+__device__ __forceinline__ void stage_halo(uint4* lds, const bf16* __restrict__ in,
+                                           const bf16* __restrict__ skip,
+                                           const Dims& d, int x0, int y0, int z0,
+                                           int sl) {
+  const bool one = d.H >= HY && d.W >= HX;
+  if (CU > 0 && sl * 16 < CU) {
+    if (one)
+      stage_halo_w<HX, HY, HZ, NTH, true, true>(lds, in, CU, sl * 16, d, x0, y0, z0);
+    else
+      stage_halo_w<HX, HY, HZ, NTH, false, true>(lds, in, CU, sl * 16, d, x0, y0, z0);
+    return;
+  }
+  const bf16* src = CU > 0 ? skip : in;
+  const int C = CU > 0 ? CIN - CU : CIN, c0 = sl * 16 - CU;
+  if (one)
+    stage_halo_w<HX, HY, HZ, NTH, true, false>(lds, src, C, c0, d, x0, y0, z0);
+  else
+    stage_halo_w<HX, HY, HZ, NTH, false, false>(lds, src, C, c0, d, x0, y0, z0);
+}
+
+
 // out = act(conv(in) + bias), LDS-tiled.  A workgroup owns an output tile
 // of 16 (x) x TY x TZ voxels; per slice of 16 input channels it stages the
 // tile's halo (18 x (TY+2) x (TZ+2) voxels, 32 B each, x and y periodic, z
@@ -144,21 +219,7 @@ __global__ void __launch_bounds__(256) k_conv3t(const bf16* __restrict__ in,
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
   for (int sl = 0; sl < NS; ++sl) {
-    for (int q = threadIdx.x; q < HV * 2; q += 256) {
-      const int hv = q >> 1, hh = q & 1;
-      const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-      const int gz = z0 + hz - 1;
-      uint4 val = make_uint4(0, 0, 0, 0);
-      if (gz >= 0 && gz < d.D) {
-        int gy = (y0 + hy - 1) % d.H;
-        gy = gy < 0 ? gy + d.H : gy;
-        int gx = (x0 + hx - 1) % d.W;
-        gx = gx < 0 ? gx + d.W : gx;
-        const size_t gv = ((size_t)gz * d.H + gy) * d.W + gx;
-        val = ld16(in + gv * CIN + sl * 16 + hh * 8);
-      }
-      lds[hh * HV + hv] = val;
-    }
+    stage_halo<CIN, 0, HX, HY, HZ, 256>(lds, in, nullptr, d, x0, y0, z0, sl);
     __syncthreads();
     // Chunks 0..12 hold two taps; chunk 13 holds tap 26 and padding.
     auto chunk = [&](int ch, bool last) {
@@ -208,6 +269,136 @@ __global__ void __launch_bounds__(256) k_conv3t(const bf16* __restrict__ in,
         out[(((size_t)gz * d.H + gy) * d.W + x) * COUT + co] = f2bf(v);
       }
     }
+  }
+}
+
+// out = act(conv(in) + bias), register-blocked over output rows.  A
+// workgroup owns an output tile of 16 (x) x 4WY x 4WZ voxels and stages its
+// halo per slice of 16 input channels in LDS as k_conv3t does.  Each wave
+// owns one 16-channel tile of C_out and a block of 4 x 4 output rows (y, z)
+// of 16 voxels.  An input row of the halo is one MFMA operand whose K of 32
+// is two x-offsets of the row (x offsets 0 and 1, or 2 and a slot whose
+// weights are zero), so one LDS read of an input row serves every output
+// row it reaches, up to nine (three z by three y offsets), and the wave's
+// 18 weight fragments of the slice (3 z x 3 y offsets x 2 x-pairs) stay in
+// registers: per slice a wave reads 6 x 6 x 2 input fragments for 288
+// MFMAs (a quarter of the second pair's products are with zero weights),
+// against one read per MFMA when the operand is formed per tap.  The
+// product is taken as W X (rows: output channels, columns: voxels), so a
+// lane ends with four consecutive channels of one voxel, stored as one
+// 8-byte word.
+//
+// With CU > 0 the input is the decoder's concatenation [up(in), skip]
+// formed in the staging (in: CU channels at half the dims; skip: CIN - CU
+// channels), so the concatenated tensor is never written.
+template <int CIN, int COUT, int WY, int WZ, int CU = 0>
+__global__ void __launch_bounds__(64 * (COUT / 16) * WY * WZ) k_conv3r(
+    const bf16* __restrict__ in, const bf16* __restrict__ skip,
+    const bf16* __restrict__ Wk, const float* __restrict__ bias,
+    bf16* __restrict__ out, Dims d, int relu) {
+  static_assert(CU % 16 == 0 && CU < CIN, "concatenation split on slices");
+  constexpr int NTC = COUT / 16, RY = 4, RZ = 4;
+  constexpr int TX = 16, TY = WY * RY, TZ = WZ * RZ;
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+  constexpr int HV = HX * HY * HZ;
+  constexpr int NTH = 64 * NTC * WY * WZ;
+  constexpr int KPAD = KP(CIN);
+  constexpr int NS = CIN / 16;
+  static_assert(CIN % 16 == 0 && COUT % 16 == 0, "channel multiples of 16");
+  __shared__ uint4 lds[HV * 2];
+  // The wave index is uniform: scalar, so the per-row tests are scalar.
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int nt = wave % NTC, sp = wave / NTC;
+  const int wy = sp % WY, wz = sp / WY;
+  const int ntx = (d.W + TX - 1) / TX, nty = (d.H + TY - 1) / TY;
+  int bi = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int tx = bi % ntx;
+  bi /= ntx;
+  const int ty = bi % nty, tz = bi / nty;
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int kg = lane >> 4, rl = lane & 15;
+  const int half = kg & 1, slot = kg >> 1;
+  const bf16* wrow = Wk + (size_t)(nt * 16 + rl) * KPAD + half * 8;
+  f4 acc[RZ][RY];
+#pragma unroll
+  for (int zo = 0; zo < RZ; ++zo)
+#pragma unroll
+    for (int yo = 0; yo < RY; ++yo) acc[zo][yo] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int sl = 0; sl < NS; ++sl) {
+    stage_halo<CIN, CU, HX, HY, HZ, NTH>(lds, in, skip, d, x0, y0, z0, sl);
+    // Weight fragments of the slice: tap (oz, oy, ox) with ox = slot in the
+    // first x-pair and ox = 2 (slot 0 only; zero in slot 1) in the second.
+    bf16x8 wa[3][3], wb[3][3];
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+      for (int oy = 0; oy < 3; ++oy) {
+        const int t0 = oz * 9 + oy * 3;
+        wa[oz][oy] = load8(wrow + (t0 + slot) * CIN + sl * 16);
+        const bf16x8 w2 = load8(wrow + (t0 + 2) * CIN + sl * 16);
+        wb[oz][oy] = slot == 0 ? w2 : zero8();
+      }
+    __syncthreads();
+    const uint4* lh = lds + half * HV + rl;
+#pragma unroll
+    for (int iz = 0; iz < RZ + 2; ++iz)
+#pragma unroll
+      for (int iy = 0; iy < RY + 2; ++iy) {
+        const int hv = ((wz * RZ + iz) * HY + (wy * RY + iy)) * HX;
+        // Slot 1 of the second pair reads the x + 2 voxel too (its weights
+        // are zero): no divergent load.
+        bf16x8 fa, fb;
+        {
+          const uint4 w0 = lh[hv + slot], w1 = lh[hv + 2];
+          __builtin_memcpy(&fa, &w0, 16);
+          __builtin_memcpy(&fb, &w1, 16);
+        }
+        // The products of one fragment go to distinct accumulators, so the
+        // MFMAs of a pass are independent.
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+          for (int oy = 0; oy < 3; ++oy) {
+            const int zo = iz - oz, yo = iy - oy;
+            if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
+              acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[oz][oy], fa, acc[zo][yo], 0, 0, 0);
+          }
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+          for (int oy = 0; oy < 3; ++oy) {
+            const int zo = iz - oz, yo = iy - oy;
+            if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
+              acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[oz][oy], fb, acc[zo][yo], 0, 0, 0);
+          }
+      }
+    __syncthreads();
+  }
+  // Lane: voxel x0 + rl, channels nt * 16 + 4 kg .. +3.
+  const int x = x0 + rl;
+  const int c0 = nt * 16 + 4 * kg;
+  float bv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bv[j] = bias ? bias[c0 + j] : 0.0f;
+  if (x < d.W) {
+#pragma unroll
+    for (int zo = 0; zo < RZ; ++zo)
+#pragma unroll
+      for (int yo = 0; yo < RY; ++yo) {
+        const int gy = y0 + wy * RY + yo, gz = z0 + wz * RZ + zo;
+        if (gy >= d.H || gz >= d.D) continue;
+        float v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          v[j] = acc[zo][yo][j] + bv[j];
+          if (relu) v[j] = fmaxf(v[j], 0.0f);
+        }
+        uint2 w;
+        w.x = f2bf2(v[0], v[1]);
+        w.y = f2bf2(v[2], v[3]);
+        *reinterpret_cast<uint2*>(out + (((size_t)gz * d.H + gy) * d.W + x) * COUT + c0) = w;
+      }
   }
 }
 
@@ -840,16 +1031,26 @@ Dims dims_at(const pic_unet* u, int D, int H, int W, int level) {
   return d;
 }
 
-// Tile of k_conv3t for a column count: MT * COUT / 16 <= 16.
+// Tile of k_conv3t for a column count: MT * COUT / 16 <= 16; the
+// register-blocked k_conv3r for 16 and 32 output channels.
 template <int CIN, int COUT>
 void conv_launch(hipStream_t st, const bf16* in, const bf16* Wk, const float* b,
                  bf16* out, Dims d, int relu) {
-  constexpr int NT = COUT / 16;
-  constexpr int TY = NT <= 2 ? 8 : (NT <= 8 ? 4 : 2);
-  constexpr int TZ = NT <= 4 ? 4 : 2;
-  const long long nbk = (long long)((d.W + 15) / 16) * ((d.H + TY - 1) / TY) *
-                        ((d.D + TZ - 1) / TZ);
-  pic::k_conv3t<CIN, COUT, TY, TZ><<<(unsigned)nbk, 256, 0, st>>>(in, Wk, b, out, d, relu);
+  if constexpr (COUT == 16 || COUT == 32) {
+    constexpr int WY = COUT == 16 ? 2 : 1, WZ = 2;
+    constexpr int TY = 4 * WY, TZ = 4 * WZ;
+    const long long nbk = (long long)((d.W + 15) / 16) * ((d.H + TY - 1) / TY) *
+                          ((d.D + TZ - 1) / TZ);
+    pic::k_conv3r<CIN, COUT, WY, WZ><<<(unsigned)nbk, 64 * (COUT / 16) * WY * WZ, 0, st>>>(
+        in, nullptr, Wk, b, out, d, relu);
+  } else {
+    constexpr int NT = COUT / 16;
+    constexpr int TY = NT <= 2 ? 8 : (NT <= 8 ? 4 : 2);
+    constexpr int TZ = NT <= 4 ? 4 : 2;
+    const long long nbk = (long long)((d.W + 15) / 16) * ((d.H + TY - 1) / TY) *
+                          ((d.D + TZ - 1) / TZ);
+    pic::k_conv3t<CIN, COUT, TY, TZ><<<(unsigned)nbk, 256, 0, st>>>(in, Wk, b, out, d, relu);
+  }
 }
 
 // Dispatch of the (C_in, C_out) pairs the network and its backward use.
@@ -868,6 +1069,19 @@ bool conv(hipStream_t st, int cin, int cout, const bf16* in, const bf16* Wk,
   PIC_CONV(32, 96) PIC_CONV(16, 48)
 #undef PIC_CONV
   return false;
+}
+
+// Decoder convolution of [up(coarse) (CU channels), skip] without the
+// concatenated tensor (inference).
+template <int CIN, int COUT, int CU>
+void conv_upcat_launch(hipStream_t st, const bf16* coarse, const bf16* skip,
+                       const bf16* Wk, const float* b, bf16* out, Dims d) {
+  constexpr int WY = COUT == 16 ? 2 : 1, WZ = 2;
+  constexpr int TY = 4 * WY, TZ = 4 * WZ;
+  const long long nbk = (long long)((d.W + 15) / 16) * ((d.H + TY - 1) / TY) *
+                        ((d.D + TZ - 1) / TZ);
+  pic::k_conv3r<CIN, COUT, WY, WZ, CU><<<(unsigned)nbk, 64 * (COUT / 16) * WY * WZ, 0, st>>>(
+      coarse, skip, Wk, b, out, d, 1);
 }
 
 template <int CIN, int COUT>
@@ -905,7 +1119,9 @@ void pack_weights(pic_unet* u) {
 }
 
 // Forward pass of a D x H x W grid (input already in x_in); out -> u->out.
-bool unet_forward(pic_unet* u, int D, int H, int W) {
+// keep: write the decoder's concatenations (the backward pass reads them);
+// without it the level-1 and level-0 decoders form them in their staging.
+bool unet_forward(pic_unet* u, int D, int H, int W, bool keep = true) {
   hipStream_t st = u->stream;
   Dims d0 = dims_at(u, D, H, W, 0), d1 = dims_at(u, D, H, W, 1),
        d2 = dims_at(u, D, H, W, 2), d3 = dims_at(u, D, H, W, 3);
@@ -930,11 +1146,21 @@ bool unet_forward(pic_unet* u, int D, int H, int W) {
   pic::k_up_cat<<<nb(d2.V * 24), 256, 0, st>>>(u->y[BB], 128, u->y[E2B], 64, u->c2, d2);
   L(D2A, u->c2, d2);
   L(D2B, u->y[D2A], d2);
-  pic::k_up_cat<<<nb(d1.V * 12), 256, 0, st>>>(u->y[D2B], 64, u->y[E1B], 32, u->c1, d1);
-  L(D1A, u->c1, d1);
+  if (keep) {
+    pic::k_up_cat<<<nb(d1.V * 12), 256, 0, st>>>(u->y[D2B], 64, u->y[E1B], 32, u->c1, d1);
+    L(D1A, u->c1, d1);
+  } else {
+    conv_upcat_launch<96, 32, 64>(st, u->y[D2B], u->y[E1B], u->wk[D1A], P + u->boff[D1A],
+                                  u->y[D1A], d1);
+  }
   L(D1B, u->y[D1A], d1);
-  pic::k_up_cat<<<nb(d0.V * 6), 256, 0, st>>>(u->y[D1B], 32, u->y[E0B], 16, u->c0, d0);
-  L(D0A, u->c0, d0);
+  if (keep) {
+    pic::k_up_cat<<<nb(d0.V * 6), 256, 0, st>>>(u->y[D1B], 32, u->y[E0B], 16, u->c0, d0);
+    L(D0A, u->c0, d0);
+  } else {
+    conv_upcat_launch<48, 16, 32>(st, u->y[D1B], u->y[E0B], u->wk[D0A], P + u->boff[D0A],
+                                  u->y[D0A], d0);
+  }
   L(D0B, u->y[D0A], d0);
   pic::k_head<<<nb(d0.V), 256, 0, st>>>(u->y[D0B], P + u->hoff, u->out, d0.V);
   return ok;
@@ -1020,7 +1246,7 @@ bool pic_unet_infer(pic_unet* u, const float* x, int D, int H, int W,
   hipStream_t keep_st = u->stream;
   u->x_in = const_cast<float*>(x);
   u->stream = st;
-  const bool ok = unet_forward(u, D, H, W);
+  const bool ok = unet_forward(u, D, H, W, false);
   u->x_in = keep_x;
   u->stream = keep_st;
   *out = u->out;
@@ -1112,7 +1338,7 @@ pic_status pic_unet_forward(pic_unet* u, const float* input, int32_t D,
   const long long V = (long long)D * H * W;
   hipMemcpyAsync(u->x_in, input, 2 * V * sizeof(float), hipMemcpyDeviceToDevice,
                  u->stream);
-  if (!unet_forward(u, D, H, W)) return PIC_ERR_STATE;
+  if (!unet_forward(u, D, H, W, false)) return PIC_ERR_STATE;
   hipMemcpyAsync(out, u->out, V * sizeof(float), hipMemcpyDeviceToDevice, u->stream);
   return hipStreamSynchronize(u->stream) == hipSuccess ? PIC_OK : PIC_ERR_HIP;
 }
