@@ -1032,12 +1032,12 @@ Dims dims_at(const pic_unet* u, int D, int H, int W, int level) {
 }
 
 // Tile of k_conv3t for a column count: MT * COUT / 16 <= 16; the
-// register-blocked k_conv3r for 16 and 32 output channels.
+// register-blocked k_conv3r for 16 to 128 output channels.
 template <int CIN, int COUT>
 void conv_launch(hipStream_t st, const bf16* in, const bf16* Wk, const float* b,
                  bf16* out, Dims d, int relu) {
-  if constexpr (COUT == 16 || COUT == 32) {
-    constexpr int WY = COUT == 16 ? 2 : 1, WZ = 2;
+  if constexpr (COUT == 16 || COUT == 32 || COUT == 64 || COUT == 128) {
+    constexpr int WY = COUT == 16 ? 2 : 1, WZ = COUT >= 64 ? 1 : 2;
     constexpr int TY = 4 * WY, TZ = 4 * WZ;
     const long long nbk = (long long)((d.W + 15) / 16) * ((d.H + TY - 1) / TY) *
                           ((d.D + TZ - 1) / TZ);
@@ -1076,7 +1076,7 @@ bool conv(hipStream_t st, int cin, int cout, const bf16* in, const bf16* Wk,
 template <int CIN, int COUT, int CU>
 void conv_upcat_launch(hipStream_t st, const bf16* coarse, const bf16* skip,
                        const bf16* Wk, const float* b, bf16* out, Dims d) {
-  constexpr int WY = COUT == 16 ? 2 : 1, WZ = 2;
+  constexpr int WY = COUT == 16 ? 2 : 1, WZ = COUT == 64 ? 1 : 2;
   constexpr int TY = 4 * WY, TZ = 4 * WZ;
   const long long nbk = (long long)((d.W + 15) / 16) * ((d.H + TY - 1) / TY) *
                         ((d.D + TZ - 1) / TZ);
@@ -1120,7 +1120,7 @@ void pack_weights(pic_unet* u) {
 
 // Forward pass of a D x H x W grid (input already in x_in); out -> u->out.
 // keep: write the decoder's concatenations (the backward pass reads them);
-// without it the level-1 and level-0 decoders form them in their staging.
+// without it the decoders form them in their staging.
 bool unet_forward(pic_unet* u, int D, int H, int W, bool keep = true) {
   hipStream_t st = u->stream;
   Dims d0 = dims_at(u, D, H, W, 0), d1 = dims_at(u, D, H, W, 1),
@@ -1143,8 +1143,13 @@ bool unet_forward(pic_unet* u, int D, int H, int W, bool keep = true) {
   pic::k_pool<<<nb(d3.V * 8), 256, 0, st>>>(u->y[E2B], u->p2, d3, 64);
   L(BA, u->p2, d3);
   L(BB, u->y[BA], d3);
-  pic::k_up_cat<<<nb(d2.V * 24), 256, 0, st>>>(u->y[BB], 128, u->y[E2B], 64, u->c2, d2);
-  L(D2A, u->c2, d2);
+  if (keep) {
+    pic::k_up_cat<<<nb(d2.V * 24), 256, 0, st>>>(u->y[BB], 128, u->y[E2B], 64, u->c2, d2);
+    L(D2A, u->c2, d2);
+  } else {
+    conv_upcat_launch<192, 64, 128>(st, u->y[BB], u->y[E2B], u->wk[D2A], P + u->boff[D2A],
+                                    u->y[D2A], d2);
+  }
   L(D2B, u->y[D2A], d2);
   if (keep) {
     pic::k_up_cat<<<nb(d1.V * 12), 256, 0, st>>>(u->y[D2B], 64, u->y[E1B], 32, u->c1, d1);
