@@ -152,6 +152,55 @@ __device__ __forceinline__ void stage_halo_w(uint4* lds, const bf16* __restrict_
   }
 }
 
+// The same halo held in registers between its loads and its LDS stores
+// (halo_load / halo_store), so that the loads of the next slice can be in
+// flight while the current one is computed.
+template <int HX, int HY, int HZ, int NTH>
+struct HaloRegs {
+  static constexpr int HV = HX * HY * HZ;
+  static constexpr int PER = (2 * HV + NTH - 1) / NTH;
+  uint4 v[PER];
+};
+
+template <int HX, int HY, int HZ, int NTH>
+__device__ __forceinline__ void halo_load(HaloRegs<HX, HY, HZ, NTH>& r,
+                                          const bf16* __restrict__ in, int C,
+                                          const Dims& d, int x0, int y0, int z0,
+                                          int sl) {
+  constexpr int HV = HX * HY * HZ;
+  const bool one = d.H >= HY && d.W >= HX;
+#pragma unroll
+  for (int m = 0; m < r.PER; ++m) {
+    const int q = (int)threadIdx.x + m * NTH;
+    const int hv = q >> 1, hh = q & 1;
+    const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+    const int gz = z0 + hz - 1;
+    r.v[m] = make_uint4(0, 0, 0, 0);
+    if (q < 2 * HV && gz >= 0 && gz < d.D) {
+      int gy = y0 + hy - 1, gx = x0 + hx - 1;
+      if (one) {
+        gy = gy < 0 ? gy + d.H : (gy >= d.H ? gy - d.H : gy);
+        gx = gx < 0 ? gx + d.W : (gx >= d.W ? gx - d.W : gx);
+      } else {
+        gy = (gy + d.H) % d.H;
+        gx = (gx + d.W) % d.W;
+      }
+      const size_t gv = ((size_t)gz * d.H + gy) * d.W + gx;
+      r.v[m] = ld16(in + gv * C + sl * 16 + hh * 8);
+    }
+  }
+}
+
+template <int HX, int HY, int HZ, int NTH>
+__device__ __forceinline__ void halo_store(uint4* lds, const HaloRegs<HX, HY, HZ, NTH>& r) {
+  constexpr int HV = HX * HY * HZ;
+#pragma unroll
+  for (int m = 0; m < r.PER; ++m) {
+    const int q = (int)threadIdx.x + m * NTH;
+    if (q < 2 * HV) lds[(q & 1) * HV + (q >> 1)] = r.v[m];
+  }
+}
+
 // Slice sl of the input: of 'in' (CIN channels), or with CU > 0 of the
 // concatenation [up(in) (CU channels, half dims), skip (CIN - CU)].
 template <int CIN, int CU, int HX, int HY, int HZ, int NTH>
@@ -325,55 +374,119 @@ __global__ void __launch_bounds__(64 * (COUT / 16) * WY * WZ) k_conv3r(
   for (int zo = 0; zo < RZ; ++zo)
 #pragma unroll
     for (int yo = 0; yo < RY; ++yo) acc[zo][yo] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int sl = 0; sl < NS; ++sl) {
-    stage_halo<CIN, CU, HX, HY, HZ, NTH>(lds, in, skip, d, x0, y0, z0, sl);
-    // Weight fragments of the slice: tap (oz, oy, ox) with ox = slot in the
-    // first x-pair and ox = 2 (slot 0 only; zero in slot 1) in the second.
-    bf16x8 wa[3][3], wb[3][3];
+  // PF: the next slice's halo loads are issued before the current slice is
+  // computed and stored to LDS once it is done, holding the halo share in
+  // registers through the MFMAs.  That paid where the kernel still fits two
+  // waves per SIMD (32 and 64 output channels) and lost elsewhere.
+  constexpr bool PF = CU == 0 && (COUT == 32 || COUT == 64) && NS > 1;
+  if constexpr (PF) {
+    HaloRegs<HX, HY, HZ, NTH> hr;
+    halo_load(hr, in, CIN, d, x0, y0, z0, 0);
+    halo_store(lds, hr);
+    for (int sl = 0; sl < NS; ++sl) {
+      if (sl + 1 < NS) halo_load(hr, in, CIN, d, x0, y0, z0, sl + 1);
+      // Weight fragments of the slice: tap (oz, oy, ox) with ox = slot in the
+      // first x-pair and ox = 2 (slot 0 only; zero in slot 1) in the second.
+      bf16x8 wa[3][3], wb[3][3];
 #pragma unroll
-    for (int oz = 0; oz < 3; ++oz)
+      for (int oz = 0; oz < 3; ++oz)
 #pragma unroll
-      for (int oy = 0; oy < 3; ++oy) {
-        const int t0 = oz * 9 + oy * 3;
-        wa[oz][oy] = load8(wrow + (t0 + slot) * CIN + sl * 16);
-        const bf16x8 w2 = load8(wrow + (t0 + 2) * CIN + sl * 16);
-        wb[oz][oy] = slot == 0 ? w2 : zero8();
-      }
-    __syncthreads();
-    const uint4* lh = lds + half * HV + rl;
-#pragma unroll
-    for (int iz = 0; iz < RZ + 2; ++iz)
-#pragma unroll
-      for (int iy = 0; iy < RY + 2; ++iy) {
-        const int hv = ((wz * RZ + iz) * HY + (wy * RY + iy)) * HX;
-        // Slot 1 of the second pair reads the x + 2 voxel too (its weights
-        // are zero): no divergent load.
-        bf16x8 fa, fb;
-        {
-          const uint4 w0 = lh[hv + slot], w1 = lh[hv + 2];
-          __builtin_memcpy(&fa, &w0, 16);
-          __builtin_memcpy(&fb, &w1, 16);
+        for (int oy = 0; oy < 3; ++oy) {
+          const int t0 = oz * 9 + oy * 3;
+          wa[oz][oy] = load8(wrow + (t0 + slot) * CIN + sl * 16);
+          const bf16x8 w2 = load8(wrow + (t0 + 2) * CIN + sl * 16);
+          wb[oz][oy] = slot == 0 ? w2 : zero8();
         }
-        // The products of one fragment go to distinct accumulators, so the
-        // MFMAs of a pass are independent.
+      __syncthreads();
+      const uint4* lh = lds + half * HV + rl;
 #pragma unroll
-        for (int oz = 0; oz < 3; ++oz)
+      for (int iz = 0; iz < RZ + 2; ++iz)
 #pragma unroll
-          for (int oy = 0; oy < 3; ++oy) {
-            const int zo = iz - oz, yo = iy - oy;
-            if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
-              acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[oz][oy], fa, acc[zo][yo], 0, 0, 0);
+        for (int iy = 0; iy < RY + 2; ++iy) {
+          const int hv = ((wz * RZ + iz) * HY + (wy * RY + iy)) * HX;
+          // Slot 1 of the second pair reads the x + 2 voxel too (its weights
+          // are zero): no divergent load.
+          bf16x8 fa, fb;
+          {
+            const uint4 w0 = lh[hv + slot], w1 = lh[hv + 2];
+            __builtin_memcpy(&fa, &w0, 16);
+            __builtin_memcpy(&fb, &w1, 16);
           }
+          // The products of one fragment go to distinct accumulators, so the
+          // MFMAs of a pass are independent.
 #pragma unroll
-        for (int oz = 0; oz < 3; ++oz)
+          for (int oz = 0; oz < 3; ++oz)
 #pragma unroll
-          for (int oy = 0; oy < 3; ++oy) {
-            const int zo = iz - oz, yo = iy - oy;
-            if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
-              acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[oz][oy], fb, acc[zo][yo], 0, 0, 0);
-          }
+            for (int oy = 0; oy < 3; ++oy) {
+              const int zo = iz - oz, yo = iy - oy;
+              if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
+                acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[oz][oy], fa, acc[zo][yo], 0, 0, 0);
+            }
+#pragma unroll
+          for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+              const int zo = iz - oz, yo = iy - oy;
+              if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
+                acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[oz][oy], fb, acc[zo][yo], 0, 0, 0);
+            }
+        }
+      if (sl + 1 < NS) {
+        __syncthreads();
+        halo_store(lds, hr);
       }
-    __syncthreads();
+    }
+  } else {
+    for (int sl = 0; sl < NS; ++sl) {
+      stage_halo<CIN, CU, HX, HY, HZ, NTH>(lds, in, skip, d, x0, y0, z0, sl);
+      // Weight fragments of the slice: tap (oz, oy, ox) with ox = slot in the
+      // first x-pair and ox = 2 (slot 0 only; zero in slot 1) in the second.
+      bf16x8 wa[3][3], wb[3][3];
+#pragma unroll
+      for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy) {
+          const int t0 = oz * 9 + oy * 3;
+          wa[oz][oy] = load8(wrow + (t0 + slot) * CIN + sl * 16);
+          const bf16x8 w2 = load8(wrow + (t0 + 2) * CIN + sl * 16);
+          wb[oz][oy] = slot == 0 ? w2 : zero8();
+        }
+      __syncthreads();
+      const uint4* lh = lds + half * HV + rl;
+#pragma unroll
+      for (int iz = 0; iz < RZ + 2; ++iz)
+#pragma unroll
+        for (int iy = 0; iy < RY + 2; ++iy) {
+          const int hv = ((wz * RZ + iz) * HY + (wy * RY + iy)) * HX;
+          // Slot 1 of the second pair reads the x + 2 voxel too (its weights
+          // are zero): no divergent load.
+          bf16x8 fa, fb;
+          {
+            const uint4 w0 = lh[hv + slot], w1 = lh[hv + 2];
+            __builtin_memcpy(&fa, &w0, 16);
+            __builtin_memcpy(&fb, &w1, 16);
+          }
+          // The products of one fragment go to distinct accumulators, so the
+          // MFMAs of a pass are independent.
+#pragma unroll
+          for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+              const int zo = iz - oz, yo = iy - oy;
+              if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
+                acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[oz][oy], fa, acc[zo][yo], 0, 0, 0);
+            }
+#pragma unroll
+          for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy) {
+              const int zo = iz - oz, yo = iy - oy;
+              if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
+                acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[oz][oy], fb, acc[zo][yo], 0, 0, 0);
+            }
+        }
+      __syncthreads();
+    }
   }
   // Lane: voxel x0 + rl, channels nt * 16 + 4 kg .. +3.
   const int x = x0 + rl;
