@@ -162,11 +162,10 @@ struct HaloRegs {
   uint4 v[PER];
 };
 
-template <int HX, int HY, int HZ, int NTH>
-__device__ __forceinline__ void halo_load(HaloRegs<HX, HY, HZ, NTH>& r,
-                                          const bf16* __restrict__ in, int C,
-                                          const Dims& d, int x0, int y0, int z0,
-                                          int sl) {
+template <int HX, int HY, int HZ, int NTH, bool UP>
+__device__ __forceinline__ void halo_load_c(HaloRegs<HX, HY, HZ, NTH>& r,
+                                            const bf16* __restrict__ in, int C, int c0,
+                                            const Dims& d, int x0, int y0, int z0) {
   constexpr int HV = HX * HY * HZ;
   const bool one = d.H >= HY && d.W >= HX;
 #pragma unroll
@@ -185,10 +184,38 @@ __device__ __forceinline__ void halo_load(HaloRegs<HX, HY, HZ, NTH>& r,
         gy = (gy + d.H) % d.H;
         gx = (gx + d.W) % d.W;
       }
-      const size_t gv = ((size_t)gz * d.H + gy) * d.W + gx;
-      r.v[m] = ld16(in + gv * C + sl * 16 + hh * 8);
+      size_t gv;
+      if constexpr (UP)
+        gv = ((size_t)(gz >> 1) * (d.H >> 1) + (gy >> 1)) * (d.W >> 1) + (gx >> 1);
+      else
+        gv = ((size_t)gz * d.H + gy) * d.W + gx;
+      r.v[m] = ld16(in + gv * C + c0 + hh * 8);
     }
   }
+}
+
+template <int HX, int HY, int HZ, int NTH>
+__device__ __forceinline__ void halo_load(HaloRegs<HX, HY, HZ, NTH>& r,
+                                          const bf16* __restrict__ in, int C,
+                                          const Dims& d, int x0, int y0, int z0,
+                                          int sl) {
+  halo_load_c<HX, HY, HZ, NTH, false>(r, in, C, sl * 16, d, x0, y0, z0);
+}
+
+// Slice sl of 'in' (CIN channels), or with CU > 0 of the concatenation
+// [up(in) (CU channels, half dims), skip (CIN - CU)].
+template <int CIN, int CU, int HX, int HY, int HZ, int NTH>
+__device__ __forceinline__ void halo_load_cat(HaloRegs<HX, HY, HZ, NTH>& r,
+                                              const bf16* __restrict__ in,
+                                              const bf16* __restrict__ skip,
+                                              const Dims& d, int x0, int y0, int z0,
+                                              int sl) {
+  if (CU > 0 && sl * 16 < CU)
+    halo_load_c<HX, HY, HZ, NTH, true>(r, in, CU, sl * 16, d, x0, y0, z0);
+  else if (CU > 0)
+    halo_load_c<HX, HY, HZ, NTH, false>(r, skip, CIN - CU, sl * 16 - CU, d, x0, y0, z0);
+  else
+    halo_load_c<HX, HY, HZ, NTH, false>(r, in, CIN, sl * 16, d, x0, y0, z0);
 }
 
 template <int HX, int HY, int HZ, int NTH>
@@ -512,6 +539,152 @@ __global__ void __launch_bounds__(64 * (COUT / 16) * WY * WZ) k_conv3r(
         w.y = f2bf2(v[2], v[3]);
         *reinterpret_cast<uint2*>(out + (((size_t)gz * d.H + gy) * d.W + x) * COUT + c0) = w;
       }
+  }
+}
+
+// k_conv3r for 16 output channels as a persistent kernel: as many
+// workgroups as the GPU holds at once, each taking a contiguous run of
+// tiles (of one XCD's range, so that neighbouring tiles share its L2), its
+// (tile, slice) items in turn.  The halo loads of the next item are issued
+// before the current item is computed and stored to LDS after it, and with
+// one slice the weight fragments are loaded once per workgroup; a one-shot
+// workgroup otherwise waits on its halo loads with nothing to compute.
+template <int CIN, int CU = 0>
+__global__ void __launch_bounds__(256) k_conv3p(
+    const bf16* __restrict__ in, const bf16* __restrict__ skip,
+    const bf16* __restrict__ Wk, const float* __restrict__ bias,
+    bf16* __restrict__ out, Dims d, int relu) {
+  static_assert(CU % 16 == 0 && CU < CIN && CIN % 16 == 0, "channel slices");
+  constexpr int RY = 4, RZ = 4, WY = 2;
+  constexpr int TX = 16, TY = 8, TZ = 8;
+  constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+  constexpr int HV = HX * HY * HZ;
+  constexpr int NTH = 256;
+  constexpr int KPAD = KP(CIN);
+  constexpr int NS = CIN / 16;
+  __shared__ uint4 lds[HV * 2];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int wy = wave % WY, wz = wave / WY;
+  const int ntx = (d.W + TX - 1) / TX, nty = (d.H + TY - 1) / TY;
+  const int ntiles = ntx * nty * ((d.D + TZ - 1) / TZ);
+  const int per = (ntiles + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int lo = (int)xcd_block(blockIdx.x, gridDim.x) * per;
+  const int hi = lo + per < ntiles ? lo + per : ntiles;
+  if (lo >= hi) return;
+  const int nitems = (hi - lo) * NS;
+  const int kg = lane >> 4, rl = lane & 15;
+  const int half = kg & 1, slot = kg >> 1;
+  const bf16* wrow = Wk + (size_t)rl * KPAD + half * 8;
+  const int c0 = 4 * kg;
+  float bv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bv[j] = bias ? bias[c0 + j] : 0.0f;
+  auto origin = [&](int t, int& x0, int& y0, int& z0) {
+    x0 = (t % ntx) * TX;
+    y0 = ((t / ntx) % nty) * TY;
+    z0 = (t / (ntx * nty)) * TZ;
+  };
+  f4 acc[RZ][RY];
+#pragma unroll
+  for (int zo = 0; zo < RZ; ++zo)
+#pragma unroll
+    for (int yo = 0; yo < RY; ++yo) acc[zo][yo] = f4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 wa[3][3], wb[3][3];
+  auto load_w = [&](int sl) {
+#pragma unroll
+    for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+      for (int oy = 0; oy < 3; ++oy) {
+        const int t0 = oz * 9 + oy * 3;
+        wa[oz][oy] = load8(wrow + (t0 + slot) * CIN + sl * 16);
+        const bf16x8 w2 = load8(wrow + (t0 + 2) * CIN + sl * 16);
+        wb[oz][oy] = slot == 0 ? w2 : zero8();
+      }
+  };
+  if (NS == 1) load_w(0);
+  HaloRegs<HX, HY, HZ, NTH> hr;
+  {
+    int x0, y0, z0;
+    origin(lo, x0, y0, z0);
+    halo_load_cat<CIN, CU>(hr, in, skip, d, x0, y0, z0, 0);
+    halo_store(lds, hr);
+  }
+  for (int j = 0; j < nitems; ++j) {
+    const int t = lo + j / NS, sl = j % NS;
+    if (j + 1 < nitems) {
+      int x0, y0, z0;
+      origin(lo + (j + 1) / NS, x0, y0, z0);
+      halo_load_cat<CIN, CU>(hr, in, skip, d, x0, y0, z0, (j + 1) % NS);
+    }
+    if (NS > 1) load_w(sl);
+    __syncthreads();
+    const uint4* lh = lds + half * HV + rl + (wz * RZ * HY + wy * RY) * HX;
+    // The input rows in a ring of three, each read two rows ahead of its
+    // MFMAs so that the LDS latency is covered.
+    constexpr int NP = (RZ + 2) * (RY + 2);
+    uint4 ring[3][2];
+    auto fetch = [&](int p, uint4 (&r)[2]) {
+      const int hv = ((p / (RY + 2)) * HY + p % (RY + 2)) * HX;
+      r[0] = lh[hv + slot];
+      r[1] = lh[hv + 2];
+    };
+    fetch(0, ring[0]);
+    fetch(1, ring[1]);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int iz = p / (RY + 2), iy = p % (RY + 2);
+      if (p + 2 < NP) fetch(p + 2, ring[(p + 2) % 3]);
+      {
+        bf16x8 fa, fb;
+        __builtin_memcpy(&fa, &ring[p % 3][0], 16);
+        __builtin_memcpy(&fb, &ring[p % 3][1], 16);
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+          for (int oy = 0; oy < 3; ++oy) {
+            const int zo = iz - oz, yo = iy - oy;
+            if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
+              acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[oz][oy], fa, acc[zo][yo], 0, 0, 0);
+          }
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+          for (int oy = 0; oy < 3; ++oy) {
+            const int zo = iz - oz, yo = iy - oy;
+            if (zo >= 0 && zo < RZ && yo >= 0 && yo < RY)
+              acc[zo][yo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wb[oz][oy], fb, acc[zo][yo], 0, 0, 0);
+          }
+      }
+    }
+    if (sl == NS - 1) {
+      int x0, y0, z0;
+      origin(t, x0, y0, z0);
+      const int x = x0 + rl;
+#pragma unroll
+      for (int zo = 0; zo < RZ; ++zo)
+#pragma unroll
+        for (int yo = 0; yo < RY; ++yo) {
+          const int gy = y0 + wy * RY + yo, gz = z0 + wz * RZ + zo;
+          if (x < d.W && gy < d.H && gz < d.D) {
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              v[q] = acc[zo][yo][q] + bv[q];
+              if (relu) v[q] = fmaxf(v[q], 0.0f);
+            }
+            uint2 w;
+            w.x = f2bf2(v[0], v[1]);
+            w.y = f2bf2(v[2], v[3]);
+            *reinterpret_cast<uint2*>(out + (((size_t)gz * d.H + gy) * d.W + x) * 16 + c0) = w;
+          }
+          acc[zo][yo] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
+    if (j + 1 < nitems) {
+      __syncthreads();
+      halo_store(lds, hr);
+    }
   }
 }
 
@@ -1144,12 +1317,43 @@ Dims dims_at(const pic_unet* u, int D, int H, int W, int level) {
   return d;
 }
 
+// Workgroups of k_conv3p<CIN, CU> the current device holds at once.
+template <int CIN, int CU>
+unsigned conv3p_slots() {
+  static unsigned cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  if (!cached[dev]) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pic::k_conv3p<CIN, CU>, 256, 0) !=
+            hipSuccess || per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    cached[dev] = (unsigned)(per_cu * cus);
+  }
+  return cached[dev];
+}
+
+template <int CIN, int CU>
+void conv3p_launch(hipStream_t st, const bf16* in, const bf16* skip, const bf16* Wk,
+                   const float* b, bf16* out, Dims d, int relu) {
+  const long long ntiles = (long long)((d.W + 15) / 16) * ((d.H + 7) / 8) * ((d.D + 7) / 8);
+  const unsigned slots = conv3p_slots<CIN, CU>();
+  const unsigned grid = ntiles < (long long)slots ? (unsigned)ntiles : slots;
+  pic::k_conv3p<CIN, CU><<<grid, 256, 0, st>>>(in, skip, Wk, b, out, d, relu);
+}
+
 // Tile of k_conv3t for a column count: MT * COUT / 16 <= 16; the
-// register-blocked k_conv3r for 16 to 128 output channels.
+// register-blocked k_conv3r for 32 to 128 output channels, its persistent
+// form k_conv3p for 16.
 template <int CIN, int COUT>
 void conv_launch(hipStream_t st, const bf16* in, const bf16* Wk, const float* b,
                  bf16* out, Dims d, int relu) {
-  if constexpr (COUT == 16 || COUT == 32 || COUT == 64 || COUT == 128) {
+  if constexpr (COUT == 16) {
+    conv3p_launch<CIN, 0>(st, in, nullptr, Wk, b, out, d, relu);
+  } else if constexpr (COUT == 32 || COUT == 64 || COUT == 128) {
     constexpr int WY = COUT == 16 ? 2 : 1, WZ = COUT >= 64 ? 1 : 2;
     constexpr int TY = 4 * WY, TZ = 4 * WZ;
     const long long nbk = (long long)((d.W + 15) / 16) * ((d.H + TY - 1) / TY) *
@@ -1189,6 +1393,10 @@ bool conv(hipStream_t st, int cin, int cout, const bf16* in, const bf16* Wk,
 template <int CIN, int COUT, int CU>
 void conv_upcat_launch(hipStream_t st, const bf16* coarse, const bf16* skip,
                        const bf16* Wk, const float* b, bf16* out, Dims d) {
+  if constexpr (COUT == 16) {
+    conv3p_launch<CIN, CU>(st, coarse, skip, Wk, b, out, d, 1);
+    return;
+  }
   constexpr int WY = COUT == 16 ? 2 : 1, WZ = COUT == 64 ? 1 : 2;
   constexpr int TY = 4 * WY, TZ = 4 * WZ;
   const long long nbk = (long long)((d.W + 15) / 16) * ((d.H + TY - 1) / TY) *
