@@ -39,8 +39,13 @@ HBM_PEAK_GBS = 8000.0
 # profiles/c2_fp64_hbm_traffic.md.  Valid only for these kernels as built
 # when measured; set to None when they change.
 MEASURED_TRAFFIC = {
-    ("c2", "fp64", "k_smooth2"): 242.8e6,
-    ("c2", "fp64", "k_push_tile"): 2563.2e6,
+    ("c2", "fp64", "k_smooth2"): 241.2e6,
+    ("c2", "fp64", "k_push_tile"): 2562.7e6,
+    # profiles/c2_mixed_hbm_traffic.md; the smoother's figure is the mean
+    # over the four finest-level passes of a refinement round (zero start,
+    # two plain, FP64 accumulation).
+    ("c2", "mixed", "k_smooth2"): (77.2e6 + 2 * 120.7e6 + 237.0e6) / 4,
+    ("c2", "mixed", "k_push_tile"): 1625.2e6,
 }
 
 
@@ -366,10 +371,14 @@ def variant_rooflines(p, r, workload):
             "bytes_per_launch": int(alg),
             "avg_launch_ms": round(t_push * 1e3, 5)}
     ms_sm, n_sm = ph["smooth_l0"]
-    fused = p["nx"] >= 32 and p["ny"] >= 8 and r["_nu"] == 4
+    # The fused pass needs a level at least one owned column wide (64 x 16
+    # nodes in FP64, 32 x 16 in FP32).
+    fused = p["nx"] >= (32 if mixed else 64) and p["ny"] >= 16 and r["_nu"] == 4
     if fused:
         n_eff = 2 * r["_vcycles_total"]
-        per_u = 12 if mixed else 24
+        # Mixed: a refinement round's four finest-level passes move 8 (zero
+        # start), 12, 12 and 20 (FP64 accumulation) bytes per unknown.
+        per_u = 13 if mixed else 24
         sname = "k_smooth2<%s> (finest level, two red-black sweeps per launch)" % (
             "float" if mixed else "double")
     else:
