@@ -342,10 +342,12 @@ def variant_rooflines(p, r, workload):
     once (16 B); per cell the neutral count read once (4 B).
 
     smooth (finest level): with two sweeps before and after the coarse
-    correction on a grid at least 32 x 8 in x, y it is k_smooth2, one launch
-    per two red-black sweeps, whose algorithmic bytes are u and f read and u
-    written once: 24 B per unknown in FP64, 12 B in FP32 (the mixed form's
-    correction solve).  Otherwise it is k_rbgs, one launch per colour: u
+    correction on a grid at least one owned column wide (64 x 16 nodes in
+    FP64, 32 x 16 in FP32) it is k_smooth2, one launch per two red-black
+    sweeps, whose algorithmic bytes are u and f read and u written once: 24 B
+    per unknown in FP64; in the mixed form's correction solve 13 B, the mean
+    of a refinement round's four passes (8 B from a zero start, 12, 12, and
+    20 B adding the correction to the FP64 potential).  Otherwise it is k_rbgs, one launch per colour: u
     read once, f of the colour's half read and u of that half written, 16 B
     (8 B) per unknown.  Launches that only find the solve converged are
     timed but not counted as work."""
