@@ -70,6 +70,19 @@ def test_mixed_poisson_reaches_fp64_residual(gpu_lib):
     assert P.rel_residual(phi.cpu().numpy(), b, g) <= 1.5e-10
     ref = P.solve_exact(b, g)
     assert np.max(np.abs(phi.cpu().numpy() - ref)) <= 1e-6 * np.max(np.abs(ref))
+    # Refinement rounds of two FP32 V-cycles, each ended by one FP64
+    # residual: the rounds are the checks the solve made.
+    assert info["refinements"] == (info["vcycles"] + 1) // 2
+
+
+def test_fp64_poisson_reports_no_refinement(gpu_lib):
+    p = case()
+    p["precision"] = "fp64"
+    gpu = make(p)
+    g = grid_of(p)
+    rho = np.random.default_rng(5).standard_normal(g.shape) * 1e5
+    _, info = gpu.poisson_solve(rho)
+    assert info["converged"] == 1 and info["refinements"] == 0
 
 
 def test_mixed_step_against_fp64_oracle(gpu_lib):

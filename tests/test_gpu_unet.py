@@ -52,6 +52,26 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
+def test_unet_forward_equivariant_under_rolls_multi_tile(gpu_lib):
+    """At 128x128x128 the finest-level convolutions' workgroups each serve
+    several tiles in turn (the persistent kernel, with the next tile's halo
+    loaded during the current one), and the level-1 to level-3 ones cover
+    the grid with many tiles.  x and y are periodic and every output
+    voxel's sums run in the same order wherever its tile lies, so rolling
+    the input by multiples of 8 voxels (the alignment of three poolings)
+    rolls the output bit for bit; a tile served with another tile's origin,
+    halo or unreset accumulators breaks that."""
+    from paper_2606_05893_amd.pic import UNet
+    shape = (128, 128, 128)
+    net = UNet(*shape, params=params())
+    x = np.random.default_rng(5).standard_normal(shape + (2,)).astype(np.float32)
+    out = net.forward(x).cpu().numpy()
+    assert np.all(np.isfinite(out)) and np.std(out) > 0
+    for sy, sx in ((8, 0), (0, 24), (40, 16)):
+        outr = net.forward(np.roll(x, (sy, sx), axis=(1, 2))).cpu().numpy()
+        assert np.array_equal(outr, np.roll(out, (sy, sx), axis=(1, 2))), (sy, sx)
+
+
 def test_unet_forward_matches_oracle(gpu_lib):
     from paper_2606_05893_amd.pic import UNet
     p = params()
