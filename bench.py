@@ -168,17 +168,30 @@ def capacities(p, total_steps):
     pl = p["preload"]
     per_step_n = p["sources"].get("disk", {}).get("n_n", 0) + \
         p["sources"].get("sphere", {}).get("n", 0)
-    return (pl["n_e"] + 2_000_000,
-            pl["n_n"] + per_step_n * (total_steps + 2) + 1_000_000,
-            pl["n_ion"] + 2_000_000), per_step_n
+    # Margins for what the collisions add over the run (secondaries,
+    # recombined atoms, Cu2+), generous beside the measured few thousand a
+    # step.
+    extra = 50_000 * max(total_steps, 40)
+    return (pl["n_e"] + extra,
+            pl["n_n"] + per_step_n * (total_steps + 2) + extra,
+            pl["n_ion"] + extra, 1_000_000 + 10_000 * total_steps), per_step_n
 
 
-def new_context(G, p, precision, pre, n0, cap):
+def event_capacity(total_steps):
+    """Per-step event-list length for a run of total_steps: the evaporated
+    atoms pile up above the disk and the ionisation matching lists every
+    atom of a cell with an event, about 1e5 entries per step of the run."""
+    if total_steps <= 60:
+        return 1 << 17
+    return 1 << (22 if total_steps <= 300 else 26)
+
+
+def new_context(G, p, precision, pre, n0, cap, total_steps=60):
     q = dict(p)
     q["precision"] = precision
     flags = G.FLAG_CELL_GROUPS if (q.get("coulomb") or q.get("ion_processes")) else 0
-    gpu = G.Pic(q, capacity=cap, max_events=1 << 17, queue_capacity=1 << 10,
-                flags=flags)
+    gpu = G.Pic(q, capacity=cap, max_events=event_capacity(total_steps),
+                queue_capacity=1 << 10, flags=flags)
     for s, (pos, vel, ids) in pre.items():
         gpu.load(s, pos, vel, ids)
     gpu.set_clock(0, n0)
@@ -223,7 +236,7 @@ def run_variant(G, p, precision, pre, n0, cap, steps, warmup, net=None,
                 warm="extrap", diagnostics=False):
     import numpy as np
     import torch
-    gpu = new_context(G, p, precision, pre, n0, cap)
+    gpu = new_context(G, p, precision, pre, n0, cap, warmup + 2 * steps)
     if net is not None:
         warm = "unet"
         gpu.set_warm_start("unet", net)

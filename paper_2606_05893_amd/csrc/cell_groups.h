@@ -49,4 +49,30 @@ __device__ __forceinline__ unsigned cell_of_tile_major(unsigned key,
   return (k * (unsigned)g.ny + j) * (unsigned)g.nx + i;
 }
 
+// Per-chunk LDS tables that aggregate the records of a chunk by cell, so
+// that a cell many records share (the atoms piled above an evaporating spot)
+// takes one global atomic per chunk instead of one per record.  A key whose
+// probes find no room goes to the global counter directly; either way the
+// counts and reservations are exact.
+constexpr int kGHash = 4096;
+constexpr int kGChunk = 4096;
+constexpr unsigned kGEmpty = 0xFFFFFFFFu;
+
+// Slot of key in the table (inserted if absent), or -1 when its two probes
+// find no room.  Keys are cell numbers below 2^30.  Two probes suffice for
+// the keys that repeat within a chunk (they claim a slot early); scattered
+// keys mostly go to the global counter, as they would without the table,
+// and long probe chains would only slow them.
+__device__ __forceinline__ int ghash_slot(unsigned* hk, unsigned key) {
+  const unsigned h = (key * 2654435761u) >> 20;
+#pragma unroll
+  for (int probe = 0; probe < 2; ++probe) {
+    const unsigned s = (h + probe) & (kGHash - 1);
+    unsigned k = hk[s];
+    if (k == kGEmpty) k = atomicCAS(&hk[s], kGEmpty, key);
+    if (k == kGEmpty || k == key) return (int)s;
+  }
+  return -1;
+}
+
 }  // namespace pic

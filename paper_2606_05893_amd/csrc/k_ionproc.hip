@@ -152,18 +152,38 @@ __device__ void swap_records<PartsM>(const PartsM& a, unsigned i,
 }
 
 // ---- grouping ----------------------------------------------------------------
-__global__ void k_ig_count(const uint32_t* __restrict__ ke,
-                           const uint32_t* __restrict__ ki,
-                           const uint32_t* __restrict__ kn,
-                           const Counters* dc, GridC g,
-                           unsigned* __restrict__ cnt) {
+__global__ void __launch_bounds__(kT) k_ig_count(const uint32_t* __restrict__ ke,
+                                                  const uint32_t* __restrict__ ki,
+                                                  const uint32_t* __restrict__ kn,
+                                                  const Counters* dc, GridC g,
+                                                  unsigned* __restrict__ cnt) {
+  __shared__ unsigned hk[kGHash];
+  __shared__ unsigned hc[kGHash];
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2],
                   nn = (long long)dc->n[1];
   long long lo, hi;
   block_range(ne + ni + nn, lo, hi);
-  for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-    const uint32_t c = t < ne ? ke[t] : (t < ne + ni ? ki[t - ne] : kn[t - ne - ni]);
-    if (c != kDead) atomicAdd(&cnt[tile_major(c, g)], 1u);
+  for (long long b = lo; b < hi; b += kGChunk) {
+    for (int q = threadIdx.x; q < kGHash; q += kT) {
+      hk[q] = kGEmpty;
+      hc[q] = 0u;
+    }
+    __syncthreads();
+    const long long e = b + kGChunk < hi ? b + kGChunk : hi;
+    for (long long t = b + threadIdx.x; t < e; t += kT) {
+      const uint32_t c = t < ne ? ke[t] : (t < ne + ni ? ki[t - ne] : kn[t - ne - ni]);
+      if (c == kDead) continue;
+      const unsigned u = tile_major(c, g);
+      const int q = ghash_slot(hk, u);
+      if (q >= 0)
+        atomicAdd(&hc[q], 1u);
+      else
+        atomicAdd(&cnt[u], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kGHash; q += kT)
+      if (hk[q] != kGEmpty) atomicAdd(&cnt[hk[q]], hc[q]);
+    __syncthreads();
   }
 }
 
@@ -215,27 +235,68 @@ __global__ void __launch_bounds__(kScanB) k_ig_scan_apply(
 }
 
 template <class PT>
-__global__ void k_ig_scatter(Sp3<PT> S, const Counters* dc, GridC g,
-                             const unsigned* __restrict__ off,
-                             unsigned* __restrict__ cnt, Rec* __restrict__ rec,
-                             unsigned step, unsigned long long seed) {
+__global__ void __launch_bounds__(kT) k_ig_scatter(
+    Sp3<PT> S, const Counters* dc, GridC g, const unsigned* __restrict__ off,
+    unsigned* __restrict__ cnt, Rec* __restrict__ rec, unsigned step,
+    unsigned long long seed) {
+  // Per chunk: the records' cells counted in LDS, one range per distinct
+  // cell reserved with one global atomic, then each record placed at the
+  // next slot of its cell's range (the order inside a cell is set later by
+  // the rank pass).
+  __shared__ unsigned hk[kGHash];
+  __shared__ unsigned hc[kGHash];
+  __shared__ unsigned hb[kGHash];
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2],
                   nn = (long long)dc->n[1];
   long long lo, hi;
   block_range(ne + ni + nn, lo, hi);
-  for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-    const unsigned s = t < ne ? 0u : (t < ne + ni ? 1u : 2u);
-    const unsigned i = (unsigned)(s == 0 ? t : (s == 1 ? t - ne : t - ne - ni));
-    const uint32_t c0 = s == 0 ? S.ke[i] : (s == 1 ? S.ki[i] : S.kn[i]);
-    if (c0 == kDead) continue;
-    const unsigned c = tile_major(c0, g);
-    const unsigned long long id = s == 0 ? S.e.id[i] : (s == 1 ? S.i.id[i] : S.n.id[i]);
-    const unsigned slot = off[c] + atomicSub(&cnt[c], 1u) - 1u;
-    Rec r;
-    r.lo = ((unsigned long long)s << 62) | ord_key(id, step, seed);
-    r.hi = (c << 2) | s;
-    r.val = i;
-    rec[slot] = r;
+  auto cell_of = [&](long long t, unsigned& s, unsigned& i) {
+    s = t < ne ? 0u : (t < ne + ni ? 1u : 2u);
+    i = (unsigned)(s == 0 ? t : (s == 1 ? t - ne : t - ne - ni));
+    return s == 0 ? S.ke[i] : (s == 1 ? S.ki[i] : S.kn[i]);
+  };
+  for (long long b = lo; b < hi; b += kGChunk) {
+    for (int q = threadIdx.x; q < kGHash; q += kT) {
+      hk[q] = kGEmpty;
+      hc[q] = 0u;
+    }
+    __syncthreads();
+    const long long e = b + kGChunk < hi ? b + kGChunk : hi;
+    for (long long t = b + threadIdx.x; t < e; t += kT) {
+      unsigned s, i;
+      const uint32_t c0 = cell_of(t, s, i);
+      if (c0 == kDead) continue;
+      const int q = ghash_slot(hk, tile_major(c0, g));
+      if (q >= 0) atomicAdd(&hc[q], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kGHash; q += kT) {
+      const unsigned k = hk[q];
+      if (k != kGEmpty) {
+        const unsigned m = hc[q];
+        hb[q] = off[k] + atomicSub(&cnt[k], m) - m;
+        hc[q] = 0u;
+      }
+    }
+    __syncthreads();
+    for (long long t = b + threadIdx.x; t < e; t += kT) {
+      unsigned s, i;
+      const uint32_t c0 = cell_of(t, s, i);
+      if (c0 == kDead) continue;
+      const unsigned c = tile_major(c0, g);
+      // The table is unchanged since the count: a key found there then is
+      // found again, one that found no room finds none again.
+      const int q = ghash_slot(hk, c);
+      const unsigned slot = q >= 0 ? hb[q] + atomicAdd(&hc[q], 1u)
+                                   : off[c] + atomicSub(&cnt[c], 1u) - 1u;
+      const unsigned long long id = s == 0 ? S.e.id[i] : (s == 1 ? S.i.id[i] : S.n.id[i]);
+      Rec r;
+      r.lo = ((unsigned long long)s << 62) | ord_key(id, step, seed);
+      r.hi = (c << 2) | s;
+      r.val = i;
+      rec[slot] = r;
+    }
+    __syncthreads();
   }
 }
 
