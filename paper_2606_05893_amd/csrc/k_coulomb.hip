@@ -1,33 +1,31 @@
 // Coulomb collisions by binary pairing within cells (Takizuka & Abe), the
 // collision model the paper cites for its Monte Carlo collisions.
 //
-// The charged particles are grouped by cell: a count per cell (one pass over
-// the keys), an exclusive scan, and a scatter of one 16-byte record per
-// particle (species in the top bit of the sort key, below it the 53-bit
-// order draw of (id, step)) into its cell's segment.  Cells are numbered
-// tile by tile, so that the cells of a tile, whose particles share one range
-// of the tile-binned arrays, are served together.  A cell's records are then
-// put in (key, id) order, which gives each species a random order that
-// does not depend on where the particles sit in memory; consecutive
-// particles of a species pair, an odd count leaves a triplet of half-weight
-// collisions, and the electrons and ions of the cell collide in a sequence
-// of max(N_e, N_i) collisions.
+// Within a cell the charged particles are put in (key, id) order, the key
+// being the species (top bit) above the 53-bit order draw of (id, step):
+// each species then takes a random order that does not depend on where the
+// particles sit in memory.  Consecutive particles of a species pair (an odd
+// count leaves a leading triplet of half-weight collisions), and then the
+// electrons and ions of the cell collide in a sequence of max(N_e, N_i)
+// collisions, collision j between electron j mod N_e and ion j mod N_i.
 //
-// Most cells hold a few charged particles.  The scatter copies each
-// particle's velocity and id beside its record; a thread per record then
-// finds the record's rank in its cell's order (by comparison with the
-// others of the segment) and writes the copy, with the work it leads (a
-// like pair or triplet, or an electron-ion chain), to its sorted place.
-// The work is gathered into one list by class (pairs, triplets, chains of
-// one, two, more collisions), the like collisions run a thread per pair on
-// the copies, then the electron-ion collisions a thread per chain (the t-th
-// particle of the smaller group with the larger group's t-th, (t+m)-th, ...
-// particles; the chains share no particle, so they equal the sequence of
-// the definition), and the copies go back to the particle arrays in the
-// particles' order.  Crowded cells (more than kSmallCell records) go to a
-// list served by one workgroup each: an LDS sort, the like pairs in
-// parallel, and the electron-ion sequence in rounds of min(N_e, N_i)
-// collisions, each round touching every particle at most once.
+// The particle arrays are binned by tile (8x8x8 cells) and move little
+// between binning passes, so the work is grouped by unit, half a tile (four
+// z-planes, 256 cells): the indices of the unit's electrons and ions are
+// binned (a count and a scatter per chunk of particles, aggregated by unit
+// in LDS, so that a chunk, nearly all of one tile, takes a few global
+// atomics), and one workgroup serves a unit at a time.  It counts the
+// unit's particles by cell, loads them (order key, id, velocity) into LDS
+// in cell order, ranks each in its cell by comparison with the others,
+// runs the like collisions of all cells (disjoint pairs, in parallel), then
+// the electron-ion collisions as chains (the t-th particle of the smaller
+// group meets the larger group's t-th, (t+m)-th, ... particles; the chains
+// share no particle, so they equal the sequence of the definition), and
+// writes the velocities back once.  A unit holding more particles than LDS
+// takes is served in batches of whole cells; a cell holding more than a
+// batch is sorted alone in LDS (a bitonic sort of its keys) and collides on
+// the particle arrays, the electron-ion sequence in rounds of min(N_e, N_i)
+// collisions that touch every particle at most once.
 #include <cmath>
 
 #include "cell_groups.h"
@@ -37,14 +35,15 @@ namespace pic {
 namespace {
 
 constexpr int kT = 256;
-constexpr int kSmallCell = 16;
-constexpr int kBigT = 256;
-constexpr int kCoulBigCell = 2048;    // records a crowded cell may hold
+constexpr int kCoulBigCell = 2048;    // particles a crowded cell may hold
 constexpr unsigned long long kSpBit = 1ull << 63;
-constexpr int kScanB = 1024;          // cells per scan block
-constexpr int kNC = 5;                // classes of the work list
-constexpr int kCB = 2048;             // places per work-counting block
-constexpr unsigned kNoCopy = 0xFFFFFFFFu;  // sorted place without a copy
+constexpr int kScanB = 1024;          // counts per scan block
+constexpr int kUnitShift = 6;         // a unit: 64 tile-major cell numbers
+constexpr int kUnitCells = 1 << kUnitShift;
+constexpr int kUHash = 256;           // per-chunk table of units
+constexpr int kUChunk = 4096;         // particles per chunk of the binning
+constexpr int kCap = 184;             // particles of one LDS batch
+constexpr unsigned kIdxMask = 0x7FFFFFFFu;
 
 enum : uint32_t {
   kTagOrder = 20, kTagDelta = 21, kTagPhi = 22, kTagDeltaEI = 23, kTagPhiEI = 24
@@ -86,30 +85,44 @@ __device__ __forceinline__ void set_v(const Sp2<PT>& S, int s, unsigned i,
   Acc<PT>::set_vel(S.p[s], i, vx, vy, vz);
 }
 
+// The random part of one collision, which does not depend on the
+// velocities: the standard normal variate of (id_c, tag_d) and the cosine
+// and sine of the azimuth drawn from (id_c, tag_p).
+struct Draw {
+  double g, c, s;
+};
+
+__device__ __forceinline__ Draw coll_draw(unsigned long long id_c,
+                                          uint32_t tag_d, uint32_t tag_p,
+                                          const CoulC& k) {
+  double u1, u2, u3, u4;
+  uniform2(id_c, k.step, tag_d, k.seed, u1, u2);
+  uniform2(id_c, k.step, tag_p, k.seed, u3, u4);
+  Draw d;
+  d.g = sqrt(-2.0 * log(1.0 - u1)) * cospi(2.0 * u2);
+  sincospi(2.0 * u3, &d.s, &d.c);
+  return d;
+}
+
 // One binary collision of a pair of type ty on the velocities v1 and v2, in
-// place: delta normal with the stated variance (halved in a triplet), phi
-// uniform; the relative velocity turns by theta = 2 atan(delta) about
-// itself.  Returns false (nothing changed) for zero relative speed.
-__device__ bool pair_kick(double* v1, double* v2, int ty, double n, bool half,
-                          unsigned long long id_c, uint32_t tag_d,
-                          uint32_t tag_p, const CoulC& k) {
+// place, with its draw: delta normal with the stated variance (halved in a
+// triplet), phi uniform; the relative velocity turns by theta =
+// 2 atan(delta) about itself.  Returns false (nothing changed) for zero
+// relative speed.
+__device__ bool kick(double* v1, double* v2, int ty, double n, bool half,
+                     const Draw& d, const CoulC& k) {
   const double ux = v1[0] - v2[0], uy = v1[1] - v2[1], uz = v1[2] - v2[2];
   const double u = sqrt((ux * ux + uy * uy) + uz * uz);
   if (!(u > 0.0)) return false;
   double var = (k.cvar[ty] * n) / ((u * u) * u);
   if (half) var = 0.5 * var;
-  double u1, u2, u3, u4;
-  uniform2(id_c, k.step, tag_d, k.seed, u1, u2);
-  uniform2(id_c, k.step, tag_p, k.seed, u3, u4);
-  const double g = sqrt(-2.0 * log(1.0 - u1)) * cospi(2.0 * u2);
-  const double delta = sqrt(var) * g;
+  const double delta = sqrt(var) * d.g;
   const double uperp = sqrt(ux * ux + uy * uy);
   const double d2 = delta * delta;
   const double inv = 1.0 / (1.0 + d2);
   const double s = (2.0 * delta) * inv;
   const double omc = (2.0 * d2) * inv;
-  double sp, cp;
-  sincospi(2.0 * u3, &sp, &cp);
+  const double sp = d.s, cp = d.c;
   double dux, duy, duz;
   if (uperp > 0.0) {
     const double iu = 1.0 / uperp;
@@ -131,6 +144,14 @@ __device__ bool pair_kick(double* v1, double* v2, int ty, double n, bool half,
   return true;
 }
 
+__device__ __forceinline__ bool pair_kick(double* v1, double* v2, int ty,
+                                          double n, bool half,
+                                          unsigned long long id_c,
+                                          uint32_t tag_d, uint32_t tag_p,
+                                          const CoulC& k) {
+  return kick(v1, v2, ty, n, half, coll_draw(id_c, tag_d, tag_p, k), k);
+}
+
 // The same collision on particle a (species sa) and b (sb) in their arrays.
 template <class PT>
 __device__ void collide(const Sp2<PT>& S, int sa, unsigned a, int sb,
@@ -146,54 +167,72 @@ __device__ void collide(const Sp2<PT>& S, int sa, unsigned a, int sb,
   }
 }
 
-// A particle's velocity and id, copied into its cell-sorted place.
-struct PV {
-  double v[3];
-  unsigned long long id;
-};
-
-// The collision on two such copies.
-__device__ __forceinline__ void collide_pv(PV* __restrict__ pv, unsigned a,
-                                           unsigned b, int ty,
-                                           double n, bool half,
-                                           unsigned long long id_c,
-                                           uint32_t tag_d, uint32_t tag_p,
-                                           const CoulC& k) {
-  double v1[3] = {pv[a].v[0], pv[a].v[1], pv[a].v[2]};
-  double v2[3] = {pv[b].v[0], pv[b].v[1], pv[b].v[2]};
-  if (pair_kick(v1, v2, ty, n, half, id_c, tag_d, tag_p, k)) {
-    pv[a].v[0] = v1[0]; pv[a].v[1] = v1[1]; pv[a].v[2] = v1[2];
-    pv[b].v[0] = v2[0]; pv[b].v[1] = v2[1]; pv[b].v[2] = v2[2];
+// ---- binning of the charged particles' indices by unit ---------------------
+// Charged particle t of the joint range (electrons, then ions): its key, and
+// its index word (species in the top bit, the array index below it).
+__device__ __forceinline__ uint32_t charged_key(const uint32_t* __restrict__ ke,
+                                                const uint32_t* __restrict__ ki,
+                                                long long ne, long long t,
+                                                unsigned& gi) {
+  if (t < ne) {
+    gi = (unsigned)t;
+    return ke[t];
   }
+  gi = (1u << 31) | (unsigned)(t - ne);
+  return ki[t - ne];
 }
 
-// A record's hi word holds its cell above two species bits.
-__device__ __forceinline__ unsigned rec_sp(const Rec& r) { return r.hi & 3u; }
-__device__ __forceinline__ unsigned rec_cell(const Rec& r) { return r.hi >> 2; }
-
-template <class PT>
-__device__ __forceinline__ unsigned long long rec_id(const Sp2<PT>& S,
-                                                     const Rec& r) {
-  return S.p[rec_sp(r)].id[r.val];
+__device__ __forceinline__ unsigned unit_of(uint32_t c, const GridC& g) {
+  return tile_major(c, g) >> kUnitShift;
 }
 
-template <class PT>
-__device__ __forceinline__ bool rec_before(const Sp2<PT>& S, const Rec& a,
-                                           const Rec& b) {
-  return a.lo < b.lo || (a.lo == b.lo && rec_id(S, a) < rec_id(S, b));
+// Slot of a unit in the chunk's table (inserted if absent), or -1 when its
+// two probes find no room (the unit then takes the global counter).  A
+// chunk of tile-binned particles holds a few units; the unbinned tail's
+// chunks hold many, mostly served by the global counters.
+__device__ __forceinline__ int unit_slot(unsigned* hk, unsigned key) {
+  const unsigned h = (key * 2654435761u) >> 24;
+#pragma unroll
+  for (int probe = 0; probe < 2; ++probe) {
+    const unsigned s = (h + probe) & (kUHash - 1);
+    unsigned k = hk[s];
+    if (k == kGEmpty) k = atomicCAS(&hk[s], kGEmpty, key);
+    if (k == kGEmpty || k == key) return (int)s;
+  }
+  return -1;
 }
 
-// ---- grouping ----------------------------------------------------------------
-__global__ void k_cg_count(const uint32_t* __restrict__ ke,
-                           const uint32_t* __restrict__ ki,
-                           const Counters* dc, GridC g,
-                           unsigned* __restrict__ cnt) {
+// Live charged particles per unit.
+__global__ void __launch_bounds__(kT) k_cu_count(
+    const uint32_t* __restrict__ ke, const uint32_t* __restrict__ ki,
+    const Counters* dc, GridC g, unsigned* __restrict__ cnt) {
+  __shared__ unsigned hk[kUHash];
+  __shared__ unsigned hc[kUHash];
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2];
   long long lo, hi;
   block_range(ne + ni, lo, hi);
-  for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-    const uint32_t c = t < ne ? ke[t] : ki[t - ne];
-    if (c != kDead) atomicAdd(&cnt[tile_major(c, g)], 1u);
+  for (long long b = lo; b < hi; b += kUChunk) {
+    for (int q = threadIdx.x; q < kUHash; q += kT) {
+      hk[q] = kGEmpty;
+      hc[q] = 0u;
+    }
+    __syncthreads();
+    const long long e = b + kUChunk < hi ? b + kUChunk : hi;
+    for (long long t = b + threadIdx.x; t < e; t += kT) {
+      unsigned gi;
+      const uint32_t c = charged_key(ke, ki, ne, t, gi);
+      if (c == kDead) continue;
+      const unsigned u = unit_of(c, g);
+      const int q = unit_slot(hk, u);
+      if (q >= 0)
+        atomicAdd(&hc[q], 1u);
+      else
+        atomicAdd(&cnt[u], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kUHash; q += kT)
+      if (hk[q] != kGEmpty) atomicAdd(&cnt[hk[q]], hc[q]);
+    __syncthreads();
   }
 }
 
@@ -246,391 +285,485 @@ __global__ void __launch_bounds__(kScanB) k_cg_scan_apply(
   if (i < n) off[i + 1] += bsum[blockIdx.x];
 }
 
-// One record per live charged particle into its cell's segment (order
-// inside the segment arbitrary; the cell pass sorts it), with a copy of the
-// particle's velocity and id beside it; each particle notes its slot.
-template <class PT>
-__global__ void k_cg_scatter(Sp2<PT> S, const uint32_t* __restrict__ ke,
-                             const uint32_t* __restrict__ ki,
-                             const Counters* dc, GridC g,
-                             const unsigned* __restrict__ off,
-                             unsigned* __restrict__ cnt, Rec* __restrict__ rec,
-                             PV* __restrict__ pvu, unsigned* __restrict__ slot_of,
-                             unsigned step, unsigned long long seed) {
+// Each live charged particle's index word into its unit's range (order
+// inside the range arbitrary: the cell pass sorts).  Per chunk the units
+// are counted in LDS, one range per distinct unit reserved with one global
+// atomic, then each particle placed at the next slot of its unit's range.
+__global__ void __launch_bounds__(kT) k_cu_scatter(
+    const uint32_t* __restrict__ ke, const uint32_t* __restrict__ ki,
+    const Counters* dc, GridC g, const unsigned* __restrict__ off,
+    unsigned* __restrict__ cnt, unsigned* __restrict__ idx) {
+  __shared__ unsigned hk[kUHash];
+  __shared__ unsigned hc[kUHash];
+  __shared__ unsigned hb[kUHash];
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2];
   long long lo, hi;
   block_range(ne + ni, lo, hi);
-  for (long long t = lo + threadIdx.x; t < hi; t += blockDim.x) {
-    const int s = t < ne ? 0 : 1;
-    const unsigned i = (unsigned)(s ? t - ne : t);
-    const uint32_t c0 = s ? ki[i] : ke[i];
-    if (c0 == kDead) {
-      slot_of[t] = kNoCopy;
+  for (long long b = lo; b < hi; b += kUChunk) {
+    for (int q = threadIdx.x; q < kUHash; q += kT) {
+      hk[q] = kGEmpty;
+      hc[q] = 0u;
+    }
+    __syncthreads();
+    const long long e = b + kUChunk < hi ? b + kUChunk : hi;
+    for (long long t = b + threadIdx.x; t < e; t += kT) {
+      unsigned gi;
+      const uint32_t c = charged_key(ke, ki, ne, t, gi);
+      if (c == kDead) continue;
+      const int q = unit_slot(hk, unit_of(c, g));
+      if (q >= 0) atomicAdd(&hc[q], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kUHash; q += kT) {
+      const unsigned u = hk[q];
+      if (u != kGEmpty) {
+        const unsigned m = hc[q];
+        hb[q] = off[u] + atomicSub(&cnt[u], m) - m;
+        hc[q] = 0u;
+      }
+    }
+    __syncthreads();
+    for (long long t = b + threadIdx.x; t < e; t += kT) {
+      unsigned gi;
+      const uint32_t c = charged_key(ke, ki, ne, t, gi);
+      if (c == kDead) continue;
+      const unsigned u = unit_of(c, g);
+      // The table is unchanged since the count: a unit found there then is
+      // found again, one that found no room finds none again.
+      const int q = unit_slot(hk, u);
+      const unsigned slot = q >= 0 ? hb[q] + atomicAdd(&hc[q], 1u)
+                                   : off[u] + atomicSub(&cnt[u], 1u) - 1u;
+      idx[slot] = gi;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- the cell pass -------------------------------------------------------------
+// One wavefront per unit: a workgroup of one wavefront never waits at a
+// barrier for others, so a unit's serial stretches (the longest electron-ion
+// chain) leave the SIMD to the other units' wavefronts.
+constexpr int kCT = 64;
+
+// LDS of a batch of whole cells.  Particles sit in load order (slots); the
+// cell order is a permutation of the slots, and each cell's part of it is
+// then ranked by (key, id).
+struct BatchLds {
+  unsigned long long key[kCap];   // species bit above the order draw
+  unsigned long long id[kCap];
+  double v[3][kCap];
+  unsigned gi[kCap];              // index word
+  unsigned short cell[kCap];      // cell in the unit
+  unsigned short perm[kCap];      // sorted place -> slot
+  unsigned short work[kCap];      // cell order -> slot, then the work items
+};
+
+// Work classes, so that a wavefront runs one kind: like pairs, like
+// triplets, electron-ion chains of one, two, and three or more collisions.
+constexpr int kNCls = 5;
+
+struct UnitLds {
+  unsigned off[kUnitCells + 1];   // cell offsets in the unit's particles
+  unsigned cur[kUnitCells];
+  unsigned short ne[kUnitCells];  // electrons per cell
+  unsigned cls[kNCls + 1];        // class offsets in the work list
+  unsigned ccur[kNCls];
+  int nslot, hi;
+};
+
+// The collision on two slots of the batch.
+__device__ __forceinline__ void collide_lds(BatchLds& L, int a, int b, int ty,
+                                            double n, bool half,
+                                            unsigned long long id_c,
+                                            uint32_t tag_d, uint32_t tag_p,
+                                            const CoulC& k) {
+  double v1[3] = {L.v[0][a], L.v[1][a], L.v[2][a]};
+  double v2[3] = {L.v[0][b], L.v[1][b], L.v[2][b]};
+  if (pair_kick(v1, v2, ty, n, half, id_c, tag_d, tag_p, k)) {
+    L.v[0][a] = v1[0]; L.v[1][a] = v1[1]; L.v[2][a] = v1[2];
+    L.v[0][b] = v2[0]; L.v[1][b] = v2[1]; L.v[2][b] = v2[2];
+  }
+}
+
+// One particle of the unit into slot p of the batch (not yet its key).
+template <class PT>
+__device__ __forceinline__ void load_slot(const Sp2<PT>& S, BatchLds& L, int p,
+                                          unsigned gi, int lc) {
+  const int s = (int)(gi >> 31);
+  const unsigned i = gi & kIdxMask;
+  double vx, vy, vz;
+  get_v(S, s, i, vx, vy, vz);
+  L.id[p] = S.p[s].id[i];
+  L.v[0][p] = vx;
+  L.v[1][p] = vy;
+  L.v[2][p] = vz;
+  L.gi[p] = gi;
+  L.cell[p] = (unsigned short)lc;
+}
+
+// The work a sorted place leads: its like class (0 pair, 1 triplet, -1
+// none) and electron-ion chain class (2, 3, 4 for one, two, three or more
+// collisions, -1 none).
+__device__ __forceinline__ void place_work(const BatchLds& L, const UnitLds& U,
+                                           unsigned ob, int r, int& lcl,
+                                           int& ecl) {
+  lcl = ecl = -1;
+  const int p = L.perm[r];
+  const int lc = L.cell[p];
+  const int m = (int)(U.off[lc + 1] - U.off[lc]);
+  if (m < 2) return;
+  const int b = (int)(U.off[lc] - ob);
+  const int ne = U.ne[lc], ni = m - ne;
+  const int s = (int)(L.key[p] >> 63);
+  const int q = s ? r - b - ne : r - b;    // rank within the species
+  const int N = s ? ni : ne;
+  const int start = (N & 1) ? 3 : 0;
+  const bool trip = (N & 1) && q == 0;
+  if (N >= 2 && (trip || (q >= start && ((q - start) & 1) == 0 && q + 1 < N)))
+    lcl = trip ? 1 : 0;
+  if (ne > 0 && ni > 0 && s == (ne <= ni ? 0 : 1)) {
+    const int K = ne > ni ? ne : ni, mm = ne < ni ? ne : ni;
+    const int len = (K - q + mm - 1) / mm;
+    ecl = len >= 3 ? 4 : len + 1;
+  }
+}
+
+// The cells [c_lo, c_hi) of the unit, nb particles loaded in slots
+// [0, nb): cell order, ranks, work lists, the collisions, the velocities
+// back to the particle arrays.
+template <class PT>
+__device__ void batch_collide(const Sp2<PT>& S, int c_lo, int c_hi, int nb,
+                              BatchLds& L, UnitLds& U, const CoulC& k,
+                              unsigned long long& nl,
+                              unsigned long long& nei) {
+  const int tid = (int)threadIdx.x;
+  const unsigned ob = U.off[c_lo];
+  for (int c = c_lo + tid; c < c_hi; c += kCT) U.cur[c] = U.off[c] - ob;
+  if (tid < kNCls) U.ccur[tid] = 0u;
+  __syncthreads();
+  // Cell order, and the keys of the particles that have a partner.
+  for (int p = tid; p < nb; p += kCT) {
+    const int lc = L.cell[p];
+    L.work[atomicAdd(&U.cur[lc], 1u)] = (unsigned short)p;
+    if (U.off[lc + 1] - U.off[lc] >= 2u) {
+      const unsigned gi = L.gi[p];
+      L.key[p] = (gi >> 31 ? kSpBit : 0ull) | order_key(L.id[p], k.step, k.seed);
+    }
+  }
+  __syncthreads();
+  // Rank of each particle in its cell's (key, id) order.
+  for (int x = tid; x < nb; x += kCT) {
+    const int p = L.work[x];
+    const int lc = L.cell[p];
+    const int b = (int)(U.off[lc] - ob), m = (int)(U.off[lc + 1] - U.off[lc]);
+    if (m < 2) {
+      L.perm[b] = (unsigned short)p;
       continue;
     }
-    const unsigned c = tile_major(c0, g);
-    const unsigned slot = off[c] + atomicSub(&cnt[c], 1u) - 1u;
-    const unsigned long long id = S.p[s].id[i];
-    Rec r;
-    r.lo = (s ? kSpBit : 0ull) | order_key(id, step, seed);
-    r.hi = (c << 2) | (unsigned)s;
-    r.val = i;
-    rec[slot] = r;
-    PV x;
-    get_v(S, s, i, x.v[0], x.v[1], x.v[2]);
-    x.id = id;
-    pvu[slot] = x;
-    slot_of[t] = slot;
-  }
-}
-
-// Cells of at most kSmallCell records, one thread per record: the record's
-// rank in its cell's (key, id) order places it in the sorted array, and at
-// that place goes the work it leads, if any.  Like collisions: the first of
-// each consecutive pair of its species (after a leading triplet when the
-// species count is odd; the triplet's first leads it).  Electron-ion
-// collisions: K = max(N_e, N_i) in sequence, collision j between electron
-// j mod N_e and ion j mod N_i.  Every particle of the larger group takes
-// part once, the t-th of the smaller group (m of them) in collisions t,
-// t + m, ...: m independent chains, each led by its smaller-group record.
-// Every place of the sorted array gets its two work words (zero: none); the
-// first record of a crowded cell lists the cell for the workgroup pass.
-__global__ void __launch_bounds__(kT) k_cg_rank(
-    const unsigned* __restrict__ off, long long ncells,
-    const Rec* __restrict__ rec, const PV* __restrict__ pvu,
-    PV* __restrict__ pv, unsigned* __restrict__ place_at,
-    unsigned* __restrict__ big, long long big_cap, unsigned* __restrict__ nbig,
-    uint2* __restrict__ like_w, uint2* __restrict__ ei_w) {
-  long long lo, hi;
-  block_range((long long)off[ncells], lo, hi);
-  for (long long p = lo + threadIdx.x; p < hi; p += kT) {
-    const Rec r = rec[p];
-    const unsigned c = rec_cell(r);
-    const unsigned b = off[c];
-    const int n = (int)(off[c + 1] - b);
-    uint2 li = make_uint2(0u, 0u), eit = make_uint2(0u, 0u);
-    long long place = p;
-    unsigned pl = kNoCopy;
-    if (n > kSmallCell) {
-      if ((unsigned)p == b) {
-        const unsigned slot = atomicAdd(nbig, 1u);
-        if ((long long)slot < big_cap) big[slot] = c;
-      }
-    } else if (n >= 2) {
-      const PV me = pvu[p];
-      int rank = 0, ne = 0;
-      for (int j = 0; j < n; ++j) {
-        const Rec x = rec[b + j];
-        ne += rec_sp(x) == 0u;
-        rank += (b + (unsigned)j != (unsigned)p) &&
-                (x.lo < r.lo || (x.lo == r.lo && pvu[b + j].id < me.id));
-      }
-      place = (long long)b + rank;
-      pv[place] = me;
-      pl = (unsigned)place;
-      const unsigned s = rec_sp(r);
-      const int ni = n - ne;
-      const int q = s ? rank - ne : rank;           // rank within the species
-      const int N = s ? ni : ne;
-      const int start = (N & 1) ? 3 : 0;
-      const bool trip = (N & 1) && q == 0;
-      const bool lead =
-          N >= 2 && (trip || (q >= start && ((q - start) & 1) == 0 && q + 1 < N));
-      const bool chain = ne > 0 && ni > 0 && s == (ne <= ni ? 0u : 1u);
-      // Both words by selection, not by a branch around the assignment: the
-      // branch form of this code was compiled to a wrong first word.
-      li.x = lead ? (unsigned)place : 0u;
-      li.y = lead ? ((unsigned)N | (trip ? 1u << 30 : 0u) | (s << 31)) : 0u;
-      eit.x = chain ? b : 0u;
-      eit.y = chain ? ((unsigned)q | ((unsigned)ne << 8) | ((unsigned)ni << 16)) : 0u;
+    const unsigned long long kp = L.key[p], ip = L.id[p];
+    int rank = 0, ne = 0;
+    for (int q = b; q < b + m; ++q) {
+      const int o = L.work[q];
+      const unsigned long long kq = L.key[o];
+      ne += kq < kSpBit;
+      rank += kq < kp || (kq == kp && L.id[o] < ip);
     }
-    place_at[p] = pl;
-    like_w[place] = li;
-    ei_w[place] = eit;
-  }
-}
-
-// The copies of the small cells' particles back into their arrays, in the
-// particles' order.
-template <class PT>
-__global__ void __launch_bounds__(kT) k_cg_writeback(
-    Sp2<PT> S, const Counters* dc, const unsigned* __restrict__ slot_of,
-    const unsigned* __restrict__ place_at, const PV* __restrict__ pv) {
-  const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2];
-  long long lo, hi;
-  block_range(ne + ni, lo, hi);
-  for (long long t = lo + threadIdx.x; t < hi; t += kT) {
-    const unsigned slot = slot_of[t];
-    if (slot == kNoCopy) continue;
-    const unsigned pl = place_at[slot];
-    if (pl == kNoCopy) continue;
-    const int s = t < ne ? 0 : 1;
-    const unsigned i = (unsigned)(s ? t - ne : t);
-    set_v(S, s, i, pv[pl].v[0], pv[pl].v[1], pv[pl].v[2]);
-  }
-}
-
-// ---- work lists ----------------------------------------------------------
-// The work words are gathered into one list ordered by class, so that a
-// wavefront runs one kind of work: like pairs, like triplets, then electron-
-// ion chains of one, two, and three or more collisions.  A count per block
-// of kCB places, an exclusive scan of the class-major counts, and a scatter
-// in place order (ballots within each wavefront): deterministic, without
-// contended atomics.
-__device__ __forceinline__ int like_class(uint2 w) {
-  return w.y == 0u ? -1 : (((w.y >> 30) & 1u) ? 1 : 0);
-}
-
-__device__ __forceinline__ int ei_class(uint2 w) {
-  if (w.y == 0u) return -1;
-  const int t = (int)(w.y & 0xFFu), ne = (int)((w.y >> 8) & 0xFFu),
-            ni = (int)(w.y >> 16);
-  const int K = ne > ni ? ne : ni, m = ne < ni ? ne : ni;
-  const int len = (K - t + m - 1) / m;
-  return len == 1 ? 2 : (len == 2 ? 3 : 4);
-}
-
-__global__ void __launch_bounds__(kT) k_cg_wcount(
-    const unsigned* __restrict__ off, long long ncells,
-    const uint2* __restrict__ like_w, const uint2* __restrict__ ei_w,
-    unsigned* __restrict__ bcnt, int G) {
-  __shared__ unsigned sc[kNC];
-  if (threadIdx.x < kNC) sc[threadIdx.x] = 0u;
-  __syncthreads();
-  const long long nrec = (long long)off[ncells];
-  const long long p0 = (long long)blockIdx.x * kCB;
-  for (int i = 0; i < kCB / kT; ++i) {
-    const long long p = p0 + i * kT + threadIdx.x;
-    if (p >= nrec) break;
-    const int lc = like_class(like_w[p]), ec = ei_class(ei_w[p]);
-    if (lc >= 0) atomicAdd(&sc[lc], 1u);
-    if (ec >= 0) atomicAdd(&sc[ec], 1u);
+    L.perm[b + rank] = (unsigned short)p;
+    if (rank == 0) U.ne[lc] = (unsigned short)ne;
   }
   __syncthreads();
-  if (threadIdx.x < kNC) bcnt[threadIdx.x * G + blockIdx.x] = sc[threadIdx.x];
-}
-
-__global__ void __launch_bounds__(kT) k_cg_wscatter(
-    const unsigned* __restrict__ off, long long ncells,
-    const uint2* __restrict__ like_w, const uint2* __restrict__ ei_w,
-    const unsigned* __restrict__ loff, int G, uint2* __restrict__ list) {
-  constexpr int kW = kT / 64;
-  __shared__ unsigned base[kNC];
-  __shared__ unsigned wsum[kW][kNC];
-  if (threadIdx.x < kNC) base[threadIdx.x] = loff[threadIdx.x * G + blockIdx.x];
-  __syncthreads();
-  const long long nrec = (long long)off[ncells];
-  const long long p0 = (long long)blockIdx.x * kCB;
-  const int lane = (int)(threadIdx.x & 63u), wv = (int)(threadIdx.x >> 6);
-  const unsigned long long below = (1ull << lane) - 1ull;
-  for (int i = 0; i < kCB / kT; ++i) {
-    const long long p = p0 + i * kT + threadIdx.x;
-    uint2 lw = make_uint2(0u, 0u), ew = make_uint2(0u, 0u);
-    if (p < nrec) {
-      lw = like_w[p];
-      ew = ei_w[p];
-    }
-    const int lc = like_class(lw), ec = ei_class(ew);
-    int rl = 0, re = 0;
-    for (int c = 0; c < kNC; ++c) {
-      const unsigned long long m = __ballot(lc == c || ec == c);
-      if (lane == 0) wsum[wv][c] = (unsigned)__popcll(m);
-      const int r = __popcll(m & below);
-      if (lc == c) rl = r;
-      if (ec == c) re = r;
-    }
-    __syncthreads();
-    if (lc >= 0) {
-      unsigned o = base[lc];
-      for (int w = 0; w < wv; ++w) o += wsum[w][lc];
-      list[o + (unsigned)rl] = lw;
-    }
-    if (ec >= 0) {
-      unsigned o = base[ec];
-      for (int w = 0; w < wv; ++w) o += wsum[w][ec];
-      list[o + (unsigned)re] = ew;
-    }
-    __syncthreads();
-    if (threadIdx.x < kNC) {
-      unsigned t = 0;
-      for (int w = 0; w < kW; ++w) t += wsum[w][threadIdx.x];
-      base[threadIdx.x] += t;
-    }
-    __syncthreads();
+  // Work items by class: count, class offsets, placement (the list takes
+  // the cell-order array's place).
+  for (int r = tid; r < nb; r += kCT) {
+    int lcl, ecl;
+    place_work(L, U, ob, r, lcl, ecl);
+    if (lcl >= 0) atomicAdd(&U.ccur[lcl], 1u);
+    if (ecl >= 0) atomicAdd(&U.ccur[ecl], 1u);
   }
-}
-
-// Like collisions of the small cells, one thread per pair or triplet (the
-// triplet's three in order).
-template <class PT>
-__global__ void __launch_bounds__(kT) k_cg_like(PV* __restrict__ pv,
-                                                const unsigned* __restrict__ loff,
-                                                int G,
-                                                const uint2* __restrict__ list,
-                                                CoulC k, Counters* dc) {
-  const long long w0 = (long long)loff[0];
-  long long lo, hi;
-  block_range((long long)loff[2 * G] - w0, lo, hi);
-  unsigned long long nl = 0;
-  for (long long w = w0 + lo + threadIdx.x; w < w0 + hi; w += kT) {
-    const uint2 it = list[w];
-    const int s = (int)(it.y >> 31);
-    const bool trip = (it.y >> 30) & 1u;
-    const int N = (int)(it.y & 0x3FFFFFFFu);
+  __syncthreads();
+  if (tid == 0) {
+    unsigned t = 0;
+    for (int c = 0; c < kNCls; ++c) {
+      U.cls[c] = t;
+      t += U.ccur[c];
+      U.ccur[c] = U.cls[c];
+    }
+    U.cls[kNCls] = t;
+  }
+  __syncthreads();
+  for (int r = tid; r < nb; r += kCT) {
+    int lcl, ecl;
+    place_work(L, U, ob, r, lcl, ecl);
+    if (lcl >= 0) L.work[atomicAdd(&U.ccur[lcl], 1u)] = (unsigned short)r;
+    if (ecl >= 0) L.work[atomicAdd(&U.ccur[ecl], 1u)] = (unsigned short)r;
+  }
+  __syncthreads();
+  // Like collisions: pairs, then leading triplets (three in order).
+  const int n_like = (int)U.cls[2], n_pair = (int)U.cls[1];
+  for (int w = tid; w < n_like; w += kCT) {
+    const int r = L.work[w];
+    const int p = L.perm[r];
+    const int lc = L.cell[p];
+    const int m = (int)(U.off[lc + 1] - U.off[lc]);
+    const int ne = U.ne[lc];
+    const int s = (int)(L.gi[p] >> 31);
+    const int N = s ? m - ne : ne;
+    const bool trip = w >= n_pair;
     const double dens = (double)N * k.w_dx3;
-    const unsigned a = it.x;
     const int nc = trip ? 3 : 1;
-    for (int r = 0; r < nc; ++r) {
-      const unsigned x = a + (unsigned)r;
-      const unsigned y = r == 2 ? a : x + 1u;
-      collide_pv(pv, x, y, s, dens, trip, pv[x].id, kTagDelta, kTagPhi, k);
+    for (int rr = 0; rr < nc; ++rr) {
+      const int x = r + rr, y = rr == 2 ? r : x + 1;
+      const int px = L.perm[x];
+      collide_lds(L, px, L.perm[y], s, dens, trip, L.id[px], kTagDelta, kTagPhi, k);
     }
     nl += (unsigned long long)nc;
   }
-  if (nl) atomicAdd(&dc->coul_like, nl);
-}
-
-// Electron-ion chains of the small cells, one thread per chain.
-template <class PT>
-__global__ void __launch_bounds__(kT) k_cg_ei(PV* __restrict__ pv,
-                                              const unsigned* __restrict__ loff,
-                                              int G,
-                                              const uint2* __restrict__ list,
-                                              CoulC k, Counters* dc) {
-  const long long w0 = (long long)loff[2 * G];
-  long long lo, hi;
-  block_range((long long)loff[kNC * G] - w0, lo, hi);
-  unsigned long long nei = 0;
-  for (long long w = w0 + lo + threadIdx.x; w < w0 + hi; w += kT) {
-    const uint2 it = list[w];
-    const unsigned b = it.x;
-    const int t = (int)(it.y & 0xFFu), ne = (int)((it.y >> 8) & 0xFFu),
-              ni = (int)(it.y >> 16);
-    const int K = ne > ni ? ne : ni, m = ne < ni ? ne : ni;
-    const double dens = (double)m * k.w_dx3;
-    for (int j = t; j < K; j += m) {
-      const unsigned a = b + (unsigned)(j % ne), bi = b + (unsigned)(ne + j % ni);
-      const unsigned long long idc = ne >= ni ? pv[a].id : pv[bi].id;
-      collide_pv(pv, a, bi, 2, dens, false, idc, kTagDeltaEI, kTagPhiEI, k);
+  __syncthreads();
+  // Electron-ion chains, shortest first.
+  const int n_all = (int)U.cls[kNCls];
+  for (int w = n_like + tid; w < n_all; w += kCT) {
+    const int r = L.work[w];
+    const int p = L.perm[r];
+    const int lc = L.cell[p];
+    const int b = (int)(U.off[lc] - ob), m = (int)(U.off[lc + 1] - U.off[lc]);
+    const int ne = U.ne[lc], ni = m - ne;
+    const int s = (int)(L.gi[p] >> 31);
+    const int t = s ? r - b - ne : r - b;
+    const int K = ne > ni ? ne : ni, mm = ne < ni ? ne : ni;
+    const double dens = (double)mm * k.w_dx3;
+    for (int j = t; j < K; j += mm) {
+      const int pa = L.perm[b + j % ne], pb = L.perm[b + ne + j % ni];
+      const unsigned long long idc = ne >= ni ? L.id[pa] : L.id[pb];
+      collide_lds(L, pa, pb, 2, dens, false, idc, kTagDeltaEI, kTagPhiEI, k);
       nei += 1;
     }
   }
-  if (nei) atomicAdd(&dc->coul_ei, nei);
+  __syncthreads();
+  for (int p = tid; p < nb; p += kCT) {
+    const int lc = L.cell[p];
+    if (U.off[lc + 1] - U.off[lc] < 2u) continue;
+    const unsigned gi = L.gi[p];
+    set_v(S, (int)(gi >> 31), gi & kIdxMask, L.v[0][p], L.v[1][p], L.v[2][p]);
+  }
+  __syncthreads();
 }
 
-// Crowded cells: one workgroup each (grid-stride over the list).
+// Units in turn (a contiguous run of them, their tiles' particles adjacent
+// in the arrays).  A unit of at most kCap particles is loaded in one pass,
+// counted by cell as it loads; a larger one is counted first and loaded in
+// batches of whole cells; a cell of more than kCap particles is listed for
+// the crowded-cell pass.
 template <class PT>
-__global__ void __launch_bounds__(kBigT) k_cg_big(Sp2<PT> S,
-                                                  const unsigned* __restrict__ off,
-                                                  const Rec* __restrict__ rec,
-                                                  const unsigned* __restrict__ big,
-                                                  const unsigned* __restrict__ nbig,
-                                                  long long big_cap, CoulC k,
-                                                  Counters* dc) {
-  __shared__ unsigned long long sk[kCoulBigCell];
-  __shared__ unsigned sv[kCoulBigCell];
-  __shared__ unsigned char ss[kCoulBigCell];
-  __shared__ int s_ne;
-  long long nlist = (long long)*nbig;
-  if (nlist > big_cap) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&dc->err, kErrEvents);
-    nlist = big_cap;
+__global__ void __launch_bounds__(kCT, 4) k_cu_cells(
+    Sp2<PT> S, const uint32_t* __restrict__ ke, const uint32_t* __restrict__ ki,
+    GridC g, const unsigned* __restrict__ uoff, long long nunits,
+    const unsigned* __restrict__ uidx, unsigned* __restrict__ crowd,
+    long long crowd_cap, unsigned* __restrict__ ncrowd, CoulC k, Counters* dc) {
+  __shared__ BatchLds L;
+  __shared__ UnitLds U;
+  const int tid = (int)threadIdx.x;
+  long long u0, u1;
+  block_range(nunits, u0, u1);
+  unsigned long long nl = 0, nei = 0;
+  for (long long u = u0; u < u1; ++u) {
+    const unsigned base = uoff[u];
+    const int n = (int)(uoff[u + 1] - base);
+    if (n < 2) continue;
+    for (int c = tid; c < kUnitCells; c += kCT) U.cur[c] = 0u;
+    __syncthreads();
+    const bool one = n <= kCap;
+    for (int j = tid; j < n; j += kCT) {
+      const unsigned gi = uidx[base + j];
+      const uint32_t c0 = (gi >> 31) ? ki[gi & kIdxMask] : ke[gi];
+      const int lc = (int)(tile_major(c0, g) & (kUnitCells - 1));
+      atomicAdd(&U.cur[lc], 1u);
+      if (one) load_slot(S, L, j, gi, lc);
+    }
+    __syncthreads();
+    {
+      // Exclusive scan of the unit's cell counts (one per lane).
+      const unsigned t = U.cur[tid];
+      unsigned incl = t;
+      for (int o = 1; o < kCT; o <<= 1) {
+        const unsigned y = __shfl_up(incl, o);
+        if (tid >= o) incl += y;
+      }
+      U.off[tid] = incl - t;
+      if (tid == kCT - 1) U.off[kUnitCells] = incl;
+    }
+    __syncthreads();
+    if (one) {
+      batch_collide(S, 0, kUnitCells, n, L, U, k, nl, nei);
+      continue;
+    }
+    // Batches of whole cells of at most kCap particles.
+    for (int c_lo = 0; c_lo < kUnitCells;) {
+      if (tid == 0) {
+        int c_hi = c_lo + 1;
+        if (U.off[c_lo + 1] - U.off[c_lo] <= (unsigned)kCap)
+          while (c_hi < kUnitCells && U.off[c_hi + 1] - U.off[c_lo] <= (unsigned)kCap)
+            ++c_hi;
+        U.hi = c_hi;
+        U.nslot = 0;
+      }
+      __syncthreads();
+      const int c_hi = U.hi;
+      const int nb = (int)(U.off[c_hi] - U.off[c_lo]);
+      if (nb > kCap) {
+        if (tid == 0) {
+          const unsigned q = atomicAdd(ncrowd, 1u);
+          if ((long long)q < crowd_cap)
+            crowd[q] = ((unsigned)u << kUnitShift) | (unsigned)c_lo;
+          else
+            atomicOr(&dc->err, kErrEvents);
+        }
+      } else if (nb >= 2) {
+        for (int j = tid; j < n; j += kCT) {
+          const unsigned gi = uidx[base + j];
+          const uint32_t c0 = (gi >> 31) ? ki[gi & kIdxMask] : ke[gi];
+          const int lc = (int)(tile_major(c0, g) & (kUnitCells - 1));
+          if (lc >= c_lo && lc < c_hi) load_slot(S, L, atomicAdd(&U.nslot, 1), gi, lc);
+        }
+        __syncthreads();
+        batch_collide(S, c_lo, c_hi, nb, L, U, k, nl, nei);
+      }
+      __syncthreads();
+      c_lo = c_hi;
+    }
   }
+  for (int o = 32; o > 0; o >>= 1) {
+    nl += __shfl_xor(nl, o);
+    nei += __shfl_xor(nei, o);
+  }
+  if (tid == 0) {
+    if (nl) atomicAdd(&dc->coul_like, nl);
+    if (nei) atomicAdd(&dc->coul_ei, nei);
+  }
+}
+
+// ---- crowded cells ---------------------------------------------------------------
+// One workgroup per listed cell: its particles gathered from the unit's
+// index words, their keys sorted in LDS (bitonic), the collisions on the
+// particle arrays, the electron-ion sequence in rounds of min(N_e, N_i)
+// collisions that touch every particle at most once.
+template <class PT>
+__global__ void __launch_bounds__(kT) k_cu_crowd(
+    Sp2<PT> S, const uint32_t* __restrict__ ke, const uint32_t* __restrict__ ki,
+    GridC g, const unsigned* __restrict__ uoff,
+    const unsigned* __restrict__ uidx, const unsigned* __restrict__ crowd,
+    long long crowd_cap, const unsigned* __restrict__ ncrowd, CoulC k,
+    Counters* dc) {
+  __shared__ unsigned long long skey[kCoulBigCell];
+  __shared__ unsigned sgi[kCoulBigCell];
+  __shared__ int s_m, s_ne;
+  const int tid = (int)threadIdx.x;
+  long long nlist = (long long)*ncrowd;
+  if (nlist > crowd_cap) nlist = crowd_cap;
   unsigned long long nl = 0, nei = 0;
   for (long long q = blockIdx.x; q < nlist; q += gridDim.x) {
-    const unsigned c = big[q];
-    const unsigned b = off[c];
-    const int n = (int)(off[c + 1] - b);
-    if (n > kCoulBigCell) {
-      if (threadIdx.x == 0) atomicOr(&dc->err, kErrEvents);
+    const unsigned w = crowd[q];
+    const unsigned u = w >> kUnitShift;
+    const int lc = (int)(w & (kUnitCells - 1));
+    const unsigned base = uoff[u];
+    const int n = (int)(uoff[u + 1] - base);
+    if (tid == 0) s_m = 0;
+    __syncthreads();
+    for (int j = tid; j < n; j += kT) {
+      const unsigned gi = uidx[base + j];
+      const int s = (int)(gi >> 31);
+      const unsigned i = gi & kIdxMask;
+      const uint32_t c0 = s ? ki[i] : ke[i];
+      if ((int)(tile_major(c0, g) & (kUnitCells - 1)) != lc) continue;
+      const int p = atomicAdd(&s_m, 1);
+      if (p < kCoulBigCell) {
+        skey[p] = (s ? kSpBit : 0ull) | order_key(S.p[s].id[i], k.step, k.seed);
+        sgi[p] = gi;
+      }
+    }
+    __syncthreads();
+    const int m = s_m;
+    if (m > kCoulBigCell) {
+      if (tid == 0) atomicOr(&dc->err, kErrEvents);
+      __syncthreads();
       continue;
     }
     int np2 = 1;
-    while (np2 < n) np2 <<= 1;
-    for (int j = threadIdx.x; j < np2; j += kBigT) {
-      if (j < n) {
-        const Rec r = rec[b + j];
-        sk[j] = r.lo;
-        sv[j] = r.val;
-        ss[j] = (unsigned char)rec_sp(r);
-      } else {
-        sk[j] = ~0ull;
-        sv[j] = 0u;
-        ss[j] = 1;
-      }
+    while (np2 < m) np2 <<= 1;
+    for (int j = m + tid; j < np2; j += kT) {
+      skey[j] = ~0ull;
+      sgi[j] = 0u;
     }
     __syncthreads();
     // Bitonic sort by key.
     for (int size = 2; size <= np2; size <<= 1) {
       for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        for (int j = threadIdx.x; j < np2; j += kBigT) {
+        for (int j = tid; j < np2; j += kT) {
           const int p = j ^ stride;
           if (p > j) {
             const bool up = (j & size) == 0;
-            const bool swap = up ? sk[j] > sk[p] : sk[j] < sk[p];
+            const bool swap = up ? skey[j] > skey[p] : skey[j] < skey[p];
             if (swap) {
-              const unsigned long long tk = sk[j]; sk[j] = sk[p]; sk[p] = tk;
-              const unsigned tv = sv[j]; sv[j] = sv[p]; sv[p] = tv;
-              const unsigned char ts = ss[j]; ss[j] = ss[p]; ss[p] = ts;
+              const unsigned long long tk = skey[j]; skey[j] = skey[p]; skey[p] = tk;
+              const unsigned tv = sgi[j]; sgi[j] = sgi[p]; sgi[p] = tv;
             }
           }
         }
         __syncthreads();
       }
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       // Equal keys (practically never) in id order, and the species split.
-      for (int j = 1; j < n; ++j) {
-        int m = j;
-        while (m > 0 && sk[m] == sk[m - 1] &&
-               S.p[ss[m]].id[sv[m]] < S.p[ss[m - 1]].id[sv[m - 1]]) {
-          const unsigned tv = sv[m]; sv[m] = sv[m - 1]; sv[m - 1] = tv;
-          const unsigned char ts = ss[m]; ss[m] = ss[m - 1]; ss[m - 1] = ts;
-          --m;
+      auto id_of = [&](unsigned gi) { return S.p[gi >> 31].id[gi & kIdxMask]; };
+      for (int j = 1; j < m; ++j) {
+        int x = j;
+        while (x > 0 && skey[x] == skey[x - 1] && id_of(sgi[x]) < id_of(sgi[x - 1])) {
+          const unsigned tv = sgi[x]; sgi[x] = sgi[x - 1]; sgi[x - 1] = tv;
+          --x;
         }
       }
       int ne = 0;
-      while (ne < n && ss[ne] == 0) ++ne;
+      while (ne < m && skey[ne] < kSpBit) ++ne;
       s_ne = ne;
     }
     __syncthreads();
-    const int ne = s_ne, ni = n - ne;
+    const int ne = s_ne, ni = m - ne;
     // Like pairs: disjoint, in parallel (a triplet by one thread).
     for (int s = 0; s < 2; ++s) {
-      const int base = s ? ne : 0;
+      const int b0 = s ? ne : 0;
       const int N = s ? ni : ne;
       if (N < 2) continue;
       const double dens = (double)N * k.w_dx3;
       const int start = (N & 1) ? 3 : 0;
-      if (start && threadIdx.x == 0) {
-        const unsigned a = sv[base], bb = sv[base + 1], cc = sv[base + 2];
-        const PT& P = S.p[s];
+      const PT& P = S.p[s];
+      if (start && tid == 0) {
+        const unsigned a = sgi[b0] & kIdxMask, bb = sgi[b0 + 1] & kIdxMask,
+                       cc = sgi[b0 + 2] & kIdxMask;
         collide(S, s, a, s, bb, dens, true, P.id[a], kTagDelta, kTagPhi, k);
         collide(S, s, bb, s, cc, dens, true, P.id[bb], kTagDelta, kTagPhi, k);
         collide(S, s, cc, s, a, dens, true, P.id[cc], kTagDelta, kTagPhi, k);
         nl += 3;
       }
-      for (int j = start + 2 * (int)threadIdx.x; j + 1 < N; j += 2 * kBigT) {
-        const unsigned a = sv[base + j], bb = sv[base + j + 1];
-        collide(S, s, a, s, bb, dens, false, S.p[s].id[a], kTagDelta, kTagPhi, k);
+      for (int j = start + 2 * tid; j + 1 < N; j += 2 * kT) {
+        const unsigned a = sgi[b0 + j] & kIdxMask, bb = sgi[b0 + j + 1] & kIdxMask;
+        collide(S, s, a, s, bb, dens, false, P.id[a], kTagDelta, kTagPhi, k);
         nl += 1;
       }
     }
     __syncthreads();
+    // Electron-ion sequence in rounds of min(N_e, N_i) collisions.
     if (ne > 0 && ni > 0) {
       const int K = ne > ni ? ne : ni, Ns = ne < ni ? ne : ni;
       const double dens = (double)Ns * k.w_dx3;
       for (int r0 = 0; r0 < K; r0 += Ns) {
         const int r1 = r0 + Ns < K ? r0 + Ns : K;
-        for (int j = r0 + (int)threadIdx.x; j < r1; j += kBigT) {
-          const unsigned a = sv[j % ne], bb = sv[ne + j % ni];
-          const unsigned long long idc =
-              ne >= ni ? S.p[0].id[a] : S.p[1].id[bb];
+        for (int j = r0 + tid; j < r1; j += kT) {
+          const unsigned a = sgi[j % ne] & kIdxMask, bb = sgi[ne + j % ni] & kIdxMask;
+          const unsigned long long idc = ne >= ni ? S.p[0].id[a] : S.p[1].id[bb];
           collide(S, 0, a, 1, bb, dens, false, idc, kTagDeltaEI, kTagPhiEI, k);
         }
         __syncthreads();
       }
-      if (threadIdx.x == 0) nei += (unsigned long long)K;
+      if (tid == 0) nei += (unsigned long long)K;
     }
     __syncthreads();
   }
@@ -652,7 +785,6 @@ Sp2<PartsM> sp2<PartsM>(pic_ctx* c) {
 template <class PT>
 void coulomb_t(pic_ctx* c, double dt) {
   hipStream_t st = c->stream;
-  const long long nc = c->cg_nkeys;          // tile-major cell numbers
   CoulC k;
   const double e2 = kE * kE;
   const double den = (8.0 * kPi) * (kEps0 * kEps0);
@@ -669,58 +801,31 @@ void coulomb_t(pic_ctx* c, double dt) {
   k.step = (unsigned)c->step;
   k.seed = c->cfg.seed;
   const Sp2<PT> S = sp2<PT>(c);
-  hipMemsetAsync(c->cg_cnt, 0, nc * sizeof(unsigned), st);
-  hipMemsetAsync(c->cg_nbig, 0, sizeof(unsigned), st);
-  const unsigned nblk = 4096;
-  PV* pv = reinterpret_cast<PV*>(c->cg_pv);
-  PV* pvu = reinterpret_cast<PV*>(c->cg_pvu);
-  k_cg_count<<<nblk, kT, 0, st>>>(c->key[0], c->key[2], c->dc, c->g,
+  const long long nu = c->cg_nkeys >> kUnitShift;   // units (half tiles)
+  hipMemsetAsync(c->cg_cnt, 0, nu * sizeof(unsigned), st);
+  // Grids of a multiple of 8 workgroups (see xcd_block).
+  k_cu_count<<<4096, kT, 0, st>>>(c->key[0], c->key[2], c->dc, c->g,
                                   c->cg_cnt);
-  const long long nb = (nc + kScanB - 1) / kScanB;
-  k_cg_scan_blocks<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_cnt, nc, c->cg_off,
+  const long long nb = (nu + kScanB - 1) / kScanB;
+  k_cg_scan_blocks<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_cnt, nu, c->cg_off,
                                                    c->cg_bsum);
   k_cg_scan_sums<<<1, 1024, 0, st>>>(c->cg_bsum, (int)nb);
-  k_cg_scan_apply<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_off, nc, c->cg_bsum);
-  k_cg_scatter<PT><<<nblk, kT, 0, st>>>(S, c->key[0], c->key[2], c->dc, c->g,
-                                        c->cg_off, c->cg_cnt, c->cg_rec, pvu,
-                                        c->cg_slot, k.step, k.seed);
-  // Grids of a multiple of 8 workgroups (see xcd_block).
-  k_cg_rank<<<8192, kT, 0, st>>>(c->cg_off, nc, c->cg_rec, pvu, pv,
-                                 c->cg_place, c->cg_big, c->cg_big_cap,
-                                 c->cg_nbig,
-                                     c->cg_work, c->cg_work + c->cg_work_cap);
-  const int G = c->cg_wblocks;
-  const long long nw = (long long)kNC * G;
-  const long long nwb = (nw + kScanB - 1) / kScanB;
-  k_cg_wcount<<<G, kT, 0, st>>>(c->cg_off, nc, c->cg_work,
-                                c->cg_work + c->cg_work_cap, c->cg_wcnt, G);
-  k_cg_scan_blocks<<<(unsigned)nwb, kScanB, 0, st>>>(c->cg_wcnt, nw,
-                                                    c->cg_woff, c->cg_wbsum);
-  k_cg_scan_sums<<<1, 1024, 0, st>>>(c->cg_wbsum, (int)nwb);
-  k_cg_scan_apply<<<(unsigned)nwb, kScanB, 0, st>>>(c->cg_woff, nw, c->cg_wbsum);
-  k_cg_wscatter<<<G, kT, 0, st>>>(c->cg_off, nc, c->cg_work,
-                                  c->cg_work + c->cg_work_cap, c->cg_woff, G,
-                                  c->cg_list);
-  k_cg_like<PT><<<8192, kT, 0, st>>>(pv, c->cg_woff, G, c->cg_list, k, c->dc);
-  k_cg_ei<PT><<<8192, kT, 0, st>>>(pv, c->cg_woff, G, c->cg_list, k, c->dc);
-  k_cg_writeback<PT><<<8192, kT, 0, st>>>(S, c->dc, c->cg_slot, c->cg_place,
-                                          pv);
-  k_cg_big<PT><<<512, kBigT, 0, st>>>(S, c->cg_off, c->cg_rec, c->cg_big,
-                                      c->cg_nbig, c->cg_big_cap, k, c->dc);
+  k_cg_scan_apply<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_off, nu, c->cg_bsum);
+  k_cu_scatter<<<4096, kT, 0, st>>>(c->key[0], c->key[2], c->dc, c->g,
+                                    c->cg_off, c->cg_cnt, c->cg_idx);
+  hipMemsetAsync(c->cg_nbig, 0, sizeof(unsigned), st);
+  k_cu_cells<PT><<<8192, kCT, 0, st>>>(S, c->key[0], c->key[2], c->g,
+                                       c->cg_off, nu, c->cg_idx, c->cg_big,
+                                       c->cg_big_cap, c->cg_nbig, k, c->dc);
+  k_cu_crowd<PT><<<256, kT, 0, st>>>(S, c->key[0], c->key[2], c->g, c->cg_off,
+                                     c->cg_idx, c->cg_big, c->cg_big_cap,
+                                     c->cg_nbig, k, c->dc);
 }
 
 }  // namespace
 
 long long coulomb_scan_blocks(long long ncells) {
   return (ncells + kScanB - 1) / kScanB;
-}
-
-long long coulomb_work_blocks(long long records) {
-  return (records + kCB - 1) / kCB;
-}
-
-long long coulomb_work_counts(long long records) {
-  return (long long)kNC * coulomb_work_blocks(records);
 }
 
 void parts_coulomb(pic_ctx* c, double dt) {

@@ -200,11 +200,7 @@ size_t carve(pic_ctx* c, char* base) {
   c->dc = cv.take<Counters>(1);
   c->cg_cnt = c->cg_off = c->cg_bsum = c->cg_big = c->cg_nbig = nullptr;
   c->cg_rec = c->cg_srt = nullptr;
-  c->cg_work = c->cg_list = nullptr;
-  c->cg_pv = c->cg_pvu = nullptr;
-  c->cg_slot = c->cg_place = nullptr;
-  c->cg_wcnt = c->cg_woff = c->cg_wbsum = nullptr;
-  c->cg_wblocks = 0;
+  c->cg_idx = nullptr;
   c->cg_work_cap = 0;
   c->ip_ev = nullptr;
   c->ip_evp = nullptr;
@@ -220,17 +216,7 @@ size_t carve(pic_ctx* c, char* base) {
     c->cg_work_cap = f.capacity[0] + f.capacity[1] + f.capacity[2];
     c->cg_rec = cv.take<Rec>(c->cg_work_cap);
     c->cg_srt = cv.take<Rec>(c->cg_work_cap);
-    c->cg_work = cv.take<uint2>(2 * c->cg_work_cap);
-    c->cg_list = cv.take<uint2>(2 * c->cg_work_cap);
-    c->cg_pv = cv.take<double>(4 * c->cg_work_cap);
-    c->cg_pvu = cv.take<double>(4 * c->cg_work_cap);
-    c->cg_slot = cv.take<unsigned>(c->cg_work_cap);
-    c->cg_place = cv.take<unsigned>(c->cg_work_cap);
-    c->cg_wblocks = (int)coulomb_work_blocks(c->cg_work_cap);
-    const long long nw = coulomb_work_counts(c->cg_work_cap);
-    c->cg_wcnt = cv.take<unsigned>(nw);
-    c->cg_woff = cv.take<unsigned>(nw + 1);
-    c->cg_wbsum = cv.take<unsigned>(coulomb_scan_blocks(nw));
+    c->cg_idx = cv.take<unsigned>(c->cg_work_cap);
     c->ip_ev = cv.take<Rec>(c->ev_cap_p2);
     c->ip_evp = cv.take<uint2>(c->ev_cap_p2);
   }

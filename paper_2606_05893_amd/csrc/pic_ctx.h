@@ -131,22 +131,17 @@ struct pic_ctx {
   double *q_pos, *q_vel;
   unsigned* fn_scan;         // nx*ny + 1
 
-  // Coulomb collisions (buffers only with PIC_FLAG_CELL_GROUPS): charged
-  // particles per cell, segment offsets, scan block sums, one record per
-  // charged particle, the list of crowded cells and its counter.
+  // Cell grouping (buffers only with PIC_FLAG_CELL_GROUPS): counts per key
+  // (cell for the ion processes, half tile for the Coulomb pass), their
+  // offsets and scan block sums; the ion processes' records (scatter and
+  // cell order) and list of crowded cells with its counter; the Coulomb
+  // pass's index words of the charged particles by half tile.
   pic_coulomb coul;
   unsigned *cg_cnt, *cg_off, *cg_bsum, *cg_big, *cg_nbig;
   pic::Rec* cg_rec;
-  uint2* cg_work;                   // two work words per record place
-  long long cg_work_cap;
-  uint2* cg_list;                   // the work in class order (2 per place)
-  double* cg_pv;                    // velocity and id copies (4 words a place)
-  double* cg_pvu;                   // the same in scatter order
-  unsigned* cg_slot;                // each particle's record slot
-  unsigned* cg_place;               // each slot's sorted place
-  pic::Rec* cg_srt;                 // records in cell order (ion processes)
-  unsigned *cg_wcnt, *cg_woff, *cg_wbsum;
-  int cg_wblocks;
+  pic::Rec* cg_srt;
+  long long cg_work_cap;            // records: all particles' capacity
+  unsigned* cg_idx;
   long long cg_big_cap;
   long long cg_nkeys;               // tile-major cell numbers (tiles x 512)
   // Recombination, Cu+ ionisation, charge exchange: settings and the listed
@@ -247,8 +242,6 @@ void parts_debye(pic_ctx* c, int block, double alpha_D, double* lam_out,
 
 // ---- Coulomb collisions (k_coulomb.hip) ----------------------------------
 long long coulomb_scan_blocks(long long ncells);
-long long coulomb_work_blocks(long long records);
-long long coulomb_work_counts(long long records);
 void parts_coulomb(pic_ctx* c, double dt);
 // ---- ion processes (k_ionproc.hip) ----------------------------------------
 void parts_ion_processes(pic_ctx* c, double dt);

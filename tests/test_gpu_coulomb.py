@@ -6,9 +6,10 @@
   velocities within 1e-12 (the collisions call log and sqrt, and the GPU
   takes cos(2 pi u) and the azimuth's sine and cosine from cospi and
   sincospi, which round differently from the oracle's cos and sin).
-* Crowded cells (16 and 17 particles, the switch to one workgroup per
-  cell, and a few hundred electrons against a hundred ions, so the
-  electron-ion sequence runs in rounds): the same.
+* Crowded cells: a few hundred electrons against a hundred ions (long
+  electron-ion chains), two cells of several hundred in one half tile (its
+  particles loaded in batches of whole cells), and a cell of 1500 (sorted
+  alone, the electron-ion sequence in rounds): the same.
 * A cell with more charged particles than a workgroup sorts is reported
   (PIC_ERR_CAPACITY).
 * Mixed precision follows the oracle to FP32 precision.
@@ -104,9 +105,12 @@ def test_coulomb_advance_bit_level_and_crowded_cells(gpu_lib):
     ve.append(rng.standard_normal((4000, 3)) * 1e6)
     pi_.append(rng.random((4000, 3)) * [g.lx, g.ly, g.lz])
     vi.append(rng.standard_normal((4000, 3)) * 2e3)
-    # Crowded cells: (electrons, ions) = (16, 0), (9, 8), (300, 100), (40, 130)
-    for (ne, ni), cell in zip(((16, 0), (9, 8), (300, 100), (40, 130)),
-                              ((2, 3, 4), (7, 7, 7), (10, 1, 12), (5, 14, 3))):
+    # Crowded cells: (electrons, ions) = (16, 0), (9, 8), (300, 100),
+    # (40, 130); (600, 300) and (500, 200) in one half tile; (1100, 400).
+    for (ne, ni), cell in zip(((16, 0), (9, 8), (300, 100), (40, 130),
+                               (600, 300), (500, 200), (1100, 400)),
+                              ((2, 3, 4), (7, 7, 7), (10, 1, 12), (5, 14, 3),
+                               (1, 1, 1), (2, 2, 2), (12, 12, 12))):
         lo = np.array(cell) * p["dx"]
         pe.append(lo + rng.random((ne, 3)) * p["dx"])
         ve.append(rng.standard_normal((ne, 3)) * 1e6)
