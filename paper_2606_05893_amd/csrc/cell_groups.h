@@ -75,4 +75,33 @@ __device__ __forceinline__ int ghash_slot(unsigned* hk, unsigned key) {
   return -1;
 }
 
+// Binning by plane: a plane is one z layer of a tile (8x8 cells, 64
+// consecutive tile-major numbers).  Particles binned by tile fall into few
+// planes per chunk, so a chunk's planes are counted in a small LDS table and
+// each distinct plane takes one global atomic per chunk; a plane whose two
+// probes find no room (the unbinned tail's chunks, with many planes) takes
+// the global counter per particle.
+constexpr int kPlaneShift = 6;
+constexpr int kPlaneCells = 1 << kPlaneShift;
+static_assert(kPlaneCells == kTile * kTile, "a plane is one z layer of a tile");
+constexpr int kPHash = 256;
+constexpr int kPChunk = 4096;
+
+__device__ __forceinline__ unsigned plane_of(unsigned c, const GridC& g) {
+  return tile_major(c, g) >> kPlaneShift;
+}
+
+// Slot of a plane in the chunk's table (inserted if absent), or -1.
+__device__ __forceinline__ int plane_slot(unsigned* hk, unsigned key) {
+  const unsigned h = (key * 2654435761u) >> 24;
+#pragma unroll
+  for (int probe = 0; probe < 2; ++probe) {
+    const unsigned s = (h + probe) & (kPHash - 1);
+    unsigned k = hk[s];
+    if (k == kGEmpty) k = atomicCAS(&hk[s], kGEmpty, key);
+    if (k == kGEmpty || k == key) return (int)s;
+  }
+  return -1;
+}
+
 }  // namespace pic

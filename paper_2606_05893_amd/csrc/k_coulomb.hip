@@ -38,10 +38,6 @@ constexpr int kT = 256;
 constexpr int kCoulBigCell = 2048;    // particles a crowded cell may hold
 constexpr unsigned long long kSpBit = 1ull << 63;
 constexpr int kScanB = 1024;          // counts per scan block
-constexpr int kUnitShift = 6;         // a unit: 64 tile-major cell numbers
-constexpr int kUnitCells = 1 << kUnitShift;
-constexpr int kUHash = 256;           // per-chunk table of units
-constexpr int kUChunk = 4096;         // particles per chunk of the binning
 constexpr int kCap = 184;             // particles of one LDS batch
 constexpr unsigned kIdxMask = 0x7FFFFFFFu;
 
@@ -182,55 +178,35 @@ __device__ __forceinline__ uint32_t charged_key(const uint32_t* __restrict__ ke,
   return ki[t - ne];
 }
 
-__device__ __forceinline__ unsigned unit_of(uint32_t c, const GridC& g) {
-  return tile_major(c, g) >> kUnitShift;
-}
-
-// Slot of a unit in the chunk's table (inserted if absent), or -1 when its
-// two probes find no room (the unit then takes the global counter).  A
-// chunk of tile-binned particles holds a few units; the unbinned tail's
-// chunks hold many, mostly served by the global counters.
-__device__ __forceinline__ int unit_slot(unsigned* hk, unsigned key) {
-  const unsigned h = (key * 2654435761u) >> 24;
-#pragma unroll
-  for (int probe = 0; probe < 2; ++probe) {
-    const unsigned s = (h + probe) & (kUHash - 1);
-    unsigned k = hk[s];
-    if (k == kGEmpty) k = atomicCAS(&hk[s], kGEmpty, key);
-    if (k == kGEmpty || k == key) return (int)s;
-  }
-  return -1;
-}
-
 // Live charged particles per unit.
 __global__ void __launch_bounds__(kT) k_cu_count(
     const uint32_t* __restrict__ ke, const uint32_t* __restrict__ ki,
     const Counters* dc, GridC g, unsigned* __restrict__ cnt) {
-  __shared__ unsigned hk[kUHash];
-  __shared__ unsigned hc[kUHash];
+  __shared__ unsigned hk[kPHash];
+  __shared__ unsigned hc[kPHash];
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2];
   long long lo, hi;
   block_range(ne + ni, lo, hi);
-  for (long long b = lo; b < hi; b += kUChunk) {
-    for (int q = threadIdx.x; q < kUHash; q += kT) {
+  for (long long b = lo; b < hi; b += kPChunk) {
+    for (int q = threadIdx.x; q < kPHash; q += kT) {
       hk[q] = kGEmpty;
       hc[q] = 0u;
     }
     __syncthreads();
-    const long long e = b + kUChunk < hi ? b + kUChunk : hi;
+    const long long e = b + kPChunk < hi ? b + kPChunk : hi;
     for (long long t = b + threadIdx.x; t < e; t += kT) {
       unsigned gi;
       const uint32_t c = charged_key(ke, ki, ne, t, gi);
       if (c == kDead) continue;
-      const unsigned u = unit_of(c, g);
-      const int q = unit_slot(hk, u);
+      const unsigned u = plane_of(c, g);
+      const int q = plane_slot(hk, u);
       if (q >= 0)
         atomicAdd(&hc[q], 1u);
       else
         atomicAdd(&cnt[u], 1u);
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < kUHash; q += kT)
+    for (int q = threadIdx.x; q < kPHash; q += kT)
       if (hk[q] != kGEmpty) atomicAdd(&cnt[hk[q]], hc[q]);
     __syncthreads();
   }
@@ -293,28 +269,28 @@ __global__ void __launch_bounds__(kT) k_cu_scatter(
     const uint32_t* __restrict__ ke, const uint32_t* __restrict__ ki,
     const Counters* dc, GridC g, const unsigned* __restrict__ off,
     unsigned* __restrict__ cnt, unsigned* __restrict__ idx) {
-  __shared__ unsigned hk[kUHash];
-  __shared__ unsigned hc[kUHash];
-  __shared__ unsigned hb[kUHash];
+  __shared__ unsigned hk[kPHash];
+  __shared__ unsigned hc[kPHash];
+  __shared__ unsigned hb[kPHash];
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2];
   long long lo, hi;
   block_range(ne + ni, lo, hi);
-  for (long long b = lo; b < hi; b += kUChunk) {
-    for (int q = threadIdx.x; q < kUHash; q += kT) {
+  for (long long b = lo; b < hi; b += kPChunk) {
+    for (int q = threadIdx.x; q < kPHash; q += kT) {
       hk[q] = kGEmpty;
       hc[q] = 0u;
     }
     __syncthreads();
-    const long long e = b + kUChunk < hi ? b + kUChunk : hi;
+    const long long e = b + kPChunk < hi ? b + kPChunk : hi;
     for (long long t = b + threadIdx.x; t < e; t += kT) {
       unsigned gi;
       const uint32_t c = charged_key(ke, ki, ne, t, gi);
       if (c == kDead) continue;
-      const int q = unit_slot(hk, unit_of(c, g));
+      const int q = plane_slot(hk, plane_of(c, g));
       if (q >= 0) atomicAdd(&hc[q], 1u);
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < kUHash; q += kT) {
+    for (int q = threadIdx.x; q < kPHash; q += kT) {
       const unsigned u = hk[q];
       if (u != kGEmpty) {
         const unsigned m = hc[q];
@@ -327,10 +303,10 @@ __global__ void __launch_bounds__(kT) k_cu_scatter(
       unsigned gi;
       const uint32_t c = charged_key(ke, ki, ne, t, gi);
       if (c == kDead) continue;
-      const unsigned u = unit_of(c, g);
+      const unsigned u = plane_of(c, g);
       // The table is unchanged since the count: a unit found there then is
       // found again, one that found no room finds none again.
-      const int q = unit_slot(hk, u);
+      const int q = plane_slot(hk, u);
       const unsigned slot = q >= 0 ? hb[q] + atomicAdd(&hc[q], 1u)
                                    : off[u] + atomicSub(&cnt[u], 1u) - 1u;
       idx[slot] = gi;
@@ -363,9 +339,9 @@ struct BatchLds {
 constexpr int kNCls = 5;
 
 struct UnitLds {
-  unsigned off[kUnitCells + 1];   // cell offsets in the unit's particles
-  unsigned cur[kUnitCells];
-  unsigned short ne[kUnitCells];  // electrons per cell
+  unsigned off[kPlaneCells + 1];   // cell offsets in the unit's particles
+  unsigned cur[kPlaneCells];
+  unsigned short ne[kPlaneCells];  // electrons per cell
   unsigned cls[kNCls + 1];        // class offsets in the work list
   unsigned ccur[kNCls];
   int nslot, hi;
@@ -569,13 +545,13 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
     const unsigned base = uoff[u];
     const int n = (int)(uoff[u + 1] - base);
     if (n < 2) continue;
-    for (int c = tid; c < kUnitCells; c += kCT) U.cur[c] = 0u;
+    for (int c = tid; c < kPlaneCells; c += kCT) U.cur[c] = 0u;
     __syncthreads();
     const bool one = n <= kCap;
     for (int j = tid; j < n; j += kCT) {
       const unsigned gi = uidx[base + j];
       const uint32_t c0 = (gi >> 31) ? ki[gi & kIdxMask] : ke[gi];
-      const int lc = (int)(tile_major(c0, g) & (kUnitCells - 1));
+      const int lc = (int)(tile_major(c0, g) & (kPlaneCells - 1));
       atomicAdd(&U.cur[lc], 1u);
       if (one) load_slot(S, L, j, gi, lc);
     }
@@ -589,19 +565,19 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
         if (tid >= o) incl += y;
       }
       U.off[tid] = incl - t;
-      if (tid == kCT - 1) U.off[kUnitCells] = incl;
+      if (tid == kCT - 1) U.off[kPlaneCells] = incl;
     }
     __syncthreads();
     if (one) {
-      batch_collide(S, 0, kUnitCells, n, L, U, k, nl, nei);
+      batch_collide(S, 0, kPlaneCells, n, L, U, k, nl, nei);
       continue;
     }
     // Batches of whole cells of at most kCap particles.
-    for (int c_lo = 0; c_lo < kUnitCells;) {
+    for (int c_lo = 0; c_lo < kPlaneCells;) {
       if (tid == 0) {
         int c_hi = c_lo + 1;
         if (U.off[c_lo + 1] - U.off[c_lo] <= (unsigned)kCap)
-          while (c_hi < kUnitCells && U.off[c_hi + 1] - U.off[c_lo] <= (unsigned)kCap)
+          while (c_hi < kPlaneCells && U.off[c_hi + 1] - U.off[c_lo] <= (unsigned)kCap)
             ++c_hi;
         U.hi = c_hi;
         U.nslot = 0;
@@ -613,7 +589,7 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
         if (tid == 0) {
           const unsigned q = atomicAdd(ncrowd, 1u);
           if ((long long)q < crowd_cap)
-            crowd[q] = ((unsigned)u << kUnitShift) | (unsigned)c_lo;
+            crowd[q] = ((unsigned)u << kPlaneShift) | (unsigned)c_lo;
           else
             atomicOr(&dc->err, kErrEvents);
         }
@@ -621,7 +597,7 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
         for (int j = tid; j < n; j += kCT) {
           const unsigned gi = uidx[base + j];
           const uint32_t c0 = (gi >> 31) ? ki[gi & kIdxMask] : ke[gi];
-          const int lc = (int)(tile_major(c0, g) & (kUnitCells - 1));
+          const int lc = (int)(tile_major(c0, g) & (kPlaneCells - 1));
           if (lc >= c_lo && lc < c_hi) load_slot(S, L, atomicAdd(&U.nslot, 1), gi, lc);
         }
         __syncthreads();
@@ -662,8 +638,8 @@ __global__ void __launch_bounds__(kT) k_cu_crowd(
   unsigned long long nl = 0, nei = 0;
   for (long long q = blockIdx.x; q < nlist; q += gridDim.x) {
     const unsigned w = crowd[q];
-    const unsigned u = w >> kUnitShift;
-    const int lc = (int)(w & (kUnitCells - 1));
+    const unsigned u = w >> kPlaneShift;
+    const int lc = (int)(w & (kPlaneCells - 1));
     const unsigned base = uoff[u];
     const int n = (int)(uoff[u + 1] - base);
     if (tid == 0) s_m = 0;
@@ -673,7 +649,7 @@ __global__ void __launch_bounds__(kT) k_cu_crowd(
       const int s = (int)(gi >> 31);
       const unsigned i = gi & kIdxMask;
       const uint32_t c0 = s ? ki[i] : ke[i];
-      if ((int)(tile_major(c0, g) & (kUnitCells - 1)) != lc) continue;
+      if ((int)(tile_major(c0, g) & (kPlaneCells - 1)) != lc) continue;
       const int p = atomicAdd(&s_m, 1);
       if (p < kCoulBigCell) {
         skey[p] = (s ? kSpBit : 0ull) | order_key(S.p[s].id[i], k.step, k.seed);
@@ -801,23 +777,23 @@ void coulomb_t(pic_ctx* c, double dt) {
   k.step = (unsigned)c->step;
   k.seed = c->cfg.seed;
   const Sp2<PT> S = sp2<PT>(c);
-  const long long nu = c->cg_nkeys >> kUnitShift;   // units (half tiles)
+  const long long nu = c->cg_nkeys >> kPlaneShift;   // units (half tiles)
   hipMemsetAsync(c->cg_cnt, 0, nu * sizeof(unsigned), st);
   // Grids of a multiple of 8 workgroups (see xcd_block).
   k_cu_count<<<4096, kT, 0, st>>>(c->key[0], c->key[2], c->dc, c->g,
                                   c->cg_cnt);
   const long long nb = (nu + kScanB - 1) / kScanB;
-  k_cg_scan_blocks<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_cnt, nu, c->cg_off,
+  k_cg_scan_blocks<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_cnt, nu, c->cg_poff,
                                                    c->cg_bsum);
   k_cg_scan_sums<<<1, 1024, 0, st>>>(c->cg_bsum, (int)nb);
-  k_cg_scan_apply<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_off, nu, c->cg_bsum);
+  k_cg_scan_apply<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_poff, nu, c->cg_bsum);
   k_cu_scatter<<<4096, kT, 0, st>>>(c->key[0], c->key[2], c->dc, c->g,
-                                    c->cg_off, c->cg_cnt, c->cg_idx);
+                                    c->cg_poff, c->cg_cnt, c->cg_idx);
   hipMemsetAsync(c->cg_nbig, 0, sizeof(unsigned), st);
   k_cu_cells<PT><<<8192, kCT, 0, st>>>(S, c->key[0], c->key[2], c->g,
-                                       c->cg_off, nu, c->cg_idx, c->cg_big,
+                                       c->cg_poff, nu, c->cg_idx, c->cg_big,
                                        c->cg_big_cap, c->cg_nbig, k, c->dc);
-  k_cu_crowd<PT><<<256, kT, 0, st>>>(S, c->key[0], c->key[2], c->g, c->cg_off,
+  k_cu_crowd<PT><<<256, kT, 0, st>>>(S, c->key[0], c->key[2], c->g, c->cg_poff,
                                      c->cg_idx, c->cg_big, c->cg_big_cap,
                                      c->cg_nbig, k, c->dc);
 }

@@ -152,36 +152,78 @@ __device__ void swap_records<PartsM>(const PartsM& a, unsigned i,
 }
 
 // ---- grouping ----------------------------------------------------------------
-__global__ void __launch_bounds__(kT) k_ig_count(const uint32_t* __restrict__ ke,
-                                                  const uint32_t* __restrict__ ki,
-                                                  const uint32_t* __restrict__ kn,
-                                                  const Counters* dc, GridC g,
-                                                  unsigned* __restrict__ cnt) {
-  __shared__ unsigned hk[kGHash];
-  __shared__ unsigned hc[kGHash];
+// Particle t of the joint range (electrons, Cu+, atoms): its key and its
+// index word (species in the top two bits, the array index below them).
+constexpr unsigned kIxMask = 0x3FFFFFFFu;
+
+template <class PT>
+__device__ __forceinline__ uint32_t joint_key(const Sp3<PT>& S, long long ne,
+                                              long long ni, long long t,
+                                              unsigned& gi) {
+  if (t < ne) {
+    gi = (unsigned)t;
+    return S.ke[t];
+  }
+  if (t < ne + ni) {
+    gi = (1u << 30) | (unsigned)(t - ne);
+    return S.ki[t - ne];
+  }
+  gi = (2u << 30) | (unsigned)(t - ne - ni);
+  return S.kn[t - ne - ni];
+}
+
+template <class PT>
+__device__ __forceinline__ uint32_t key_of(const Sp3<PT>& S, unsigned gi) {
+  const unsigned s = gi >> 30, i = gi & kIxMask;
+  return s == 0 ? S.ke[i] : (s == 1 ? S.ki[i] : S.kn[i]);
+}
+
+// The sort record of a particle: species above its order draw; its
+// tile-major cell above the species; its index.
+template <class PT>
+__device__ __forceinline__ Rec make_rec(const Sp3<PT>& S, unsigned gi,
+                                        unsigned cell, unsigned step,
+                                        unsigned long long seed) {
+  const unsigned s = gi >> 30, i = gi & kIxMask;
+  const unsigned long long id = s == 0 ? S.e.id[i] : (s == 1 ? S.i.id[i] : S.n.id[i]);
+  Rec r;
+  r.lo = ((unsigned long long)s << 62) | ord_key(id, step, seed);
+  r.hi = (cell << 2) | s;
+  r.val = i;
+  return r;
+}
+
+// Live particles per plane.
+template <class PT>
+__global__ void __launch_bounds__(kT) k_pg_count(Sp3<PT> S, const Counters* dc,
+                                                 GridC g,
+                                                 unsigned* __restrict__ cnt) {
+  __shared__ unsigned hk[kPHash];
+  __shared__ unsigned hc[kPHash];
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2],
                   nn = (long long)dc->n[1];
   long long lo, hi;
   block_range(ne + ni + nn, lo, hi);
-  for (long long b = lo; b < hi; b += kGChunk) {
-    for (int q = threadIdx.x; q < kGHash; q += kT) {
+  for (long long b = lo; b < hi; b += kPChunk) {
+    for (int q = threadIdx.x; q < kPHash; q += kT) {
       hk[q] = kGEmpty;
       hc[q] = 0u;
     }
     __syncthreads();
-    const long long e = b + kGChunk < hi ? b + kGChunk : hi;
+    const long long e = b + kPChunk < hi ? b + kPChunk : hi;
     for (long long t = b + threadIdx.x; t < e; t += kT) {
-      const uint32_t c = t < ne ? ke[t] : (t < ne + ni ? ki[t - ne] : kn[t - ne - ni]);
+      unsigned gi;
+      const uint32_t c = joint_key(S, ne, ni, t, gi);
       if (c == kDead) continue;
-      const unsigned u = tile_major(c, g);
-      const int q = ghash_slot(hk, u);
+      const unsigned u = plane_of(c, g);
+      const int q = plane_slot(hk, u);
       if (q >= 0)
         atomicAdd(&hc[q], 1u);
       else
         atomicAdd(&cnt[u], 1u);
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < kGHash; q += kT)
+    for (int q = threadIdx.x; q < kPHash; q += kT)
       if (hk[q] != kGEmpty) atomicAdd(&cnt[hk[q]], hc[q]);
     __syncthreads();
   }
@@ -234,101 +276,479 @@ __global__ void __launch_bounds__(kScanB) k_ig_scan_apply(
   if (i < n) off[i + 1] += bsum[blockIdx.x];
 }
 
+// Each live particle's index word into its plane's range (order inside the
+// range arbitrary); per chunk one range per distinct plane is reserved with
+// one global atomic.
 template <class PT>
-__global__ void __launch_bounds__(kT) k_ig_scatter(
-    Sp3<PT> S, const Counters* dc, GridC g, const unsigned* __restrict__ off,
-    unsigned* __restrict__ cnt, Rec* __restrict__ rec, unsigned step,
-    unsigned long long seed) {
-  // Per chunk: the records' cells counted in LDS, one range per distinct
-  // cell reserved with one global atomic, then each record placed at the
-  // next slot of its cell's range (the order inside a cell is set later by
-  // the rank pass).
-  __shared__ unsigned hk[kGHash];
-  __shared__ unsigned hc[kGHash];
-  __shared__ unsigned hb[kGHash];
+__global__ void __launch_bounds__(kT) k_pg_scatter(
+    Sp3<PT> S, const Counters* dc, GridC g, const unsigned* __restrict__ poff,
+    unsigned* __restrict__ cnt, unsigned* __restrict__ pidx) {
+  __shared__ unsigned hk[kPHash];
+  __shared__ unsigned hc[kPHash];
+  __shared__ unsigned hb[kPHash];
   const long long ne = (long long)dc->n[0], ni = (long long)dc->n[2],
                   nn = (long long)dc->n[1];
   long long lo, hi;
   block_range(ne + ni + nn, lo, hi);
-  auto cell_of = [&](long long t, unsigned& s, unsigned& i) {
-    s = t < ne ? 0u : (t < ne + ni ? 1u : 2u);
-    i = (unsigned)(s == 0 ? t : (s == 1 ? t - ne : t - ne - ni));
-    return s == 0 ? S.ke[i] : (s == 1 ? S.ki[i] : S.kn[i]);
-  };
-  for (long long b = lo; b < hi; b += kGChunk) {
-    for (int q = threadIdx.x; q < kGHash; q += kT) {
+  for (long long b = lo; b < hi; b += kPChunk) {
+    for (int q = threadIdx.x; q < kPHash; q += kT) {
       hk[q] = kGEmpty;
       hc[q] = 0u;
     }
     __syncthreads();
-    const long long e = b + kGChunk < hi ? b + kGChunk : hi;
+    const long long e = b + kPChunk < hi ? b + kPChunk : hi;
     for (long long t = b + threadIdx.x; t < e; t += kT) {
-      unsigned s, i;
-      const uint32_t c0 = cell_of(t, s, i);
-      if (c0 == kDead) continue;
-      const int q = ghash_slot(hk, tile_major(c0, g));
+      unsigned gi;
+      const uint32_t c = joint_key(S, ne, ni, t, gi);
+      if (c == kDead) continue;
+      const int q = plane_slot(hk, plane_of(c, g));
       if (q >= 0) atomicAdd(&hc[q], 1u);
     }
     __syncthreads();
-    for (int q = threadIdx.x; q < kGHash; q += kT) {
-      const unsigned k = hk[q];
-      if (k != kGEmpty) {
+    for (int q = threadIdx.x; q < kPHash; q += kT) {
+      const unsigned u = hk[q];
+      if (u != kGEmpty) {
         const unsigned m = hc[q];
-        hb[q] = off[k] + atomicSub(&cnt[k], m) - m;
+        hb[q] = poff[u] + atomicSub(&cnt[u], m) - m;
         hc[q] = 0u;
       }
     }
     __syncthreads();
     for (long long t = b + threadIdx.x; t < e; t += kT) {
-      unsigned s, i;
-      const uint32_t c0 = cell_of(t, s, i);
-      if (c0 == kDead) continue;
-      const unsigned c = tile_major(c0, g);
-      // The table is unchanged since the count: a key found there then is
-      // found again, one that found no room finds none again.
-      const int q = ghash_slot(hk, c);
+      unsigned gi;
+      const uint32_t c = joint_key(S, ne, ni, t, gi);
+      if (c == kDead) continue;
+      const unsigned u = plane_of(c, g);
+      // The table is unchanged since the count (see k_cu_scatter).
+      const int q = plane_slot(hk, u);
       const unsigned slot = q >= 0 ? hb[q] + atomicAdd(&hc[q], 1u)
-                                   : off[c] + atomicSub(&cnt[c], 1u) - 1u;
-      const unsigned long long id = s == 0 ? S.e.id[i] : (s == 1 ? S.i.id[i] : S.n.id[i]);
-      Rec r;
-      r.lo = ((unsigned long long)s << 62) | ord_key(id, step, seed);
-      r.hi = (c << 2) | s;
-      r.val = i;
-      rec[slot] = r;
+                                   : poff[u] + atomicSub(&cnt[u], 1u) - 1u;
+      pidx[slot] = gi;
     }
     __syncthreads();
   }
 }
 
-// Cells of at most kSmall records, one thread per record: its rank in the
-// cell's (key, id) order places it in the sorted array.  The first record
-// of a crowded cell lists the cell for the workgroup pass.
+// Per plane: its cells' offsets into off (a global prefix over the
+// tile-major cells), the records of its crowded cells (more than kSmall)
+// into rec unsorted, those cells listed for the workgroup pass, and the
+// records of its cells of 2..kSmall into srt in each cell's (key, id)
+// order.  One wavefront a plane, the small cells ranked in LDS in batches
+// of at most kPCap records; a plane of more than kHot records is listed
+// for the hot-plane passes.
+constexpr int kPCap = 512;
+constexpr int kHot = 4096;
+
+struct PlaneLds {
+  unsigned long long key[kPCap];
+  unsigned gi[kPCap];
+  unsigned char cell[kPCap];
+  unsigned short ord[kPCap];      // one-pass plane: cell order -> slot
+  unsigned cnt[kPlaneCells];
+  unsigned off[kPlaneCells + 1];
+  unsigned start[kPlaneCells];    // batch-local first slot of a small cell
+  unsigned cur[kPlaneCells];
+  int hi, nb;
+};
+
+__device__ __forceinline__ bool small_cell(unsigned m) {
+  return m >= 2u && m <= (unsigned)kSmall;
+}
+
 template <class PT>
-__global__ void __launch_bounds__(kT) k_ig_rank(
-    Sp3<PT> S, const unsigned* __restrict__ off, long long nkeys,
-    const Rec* __restrict__ rec, Rec* __restrict__ srt,
-    unsigned* __restrict__ big, unsigned* __restrict__ nbig, long long big_cap) {
-  long long lo, hi;
-  block_range((long long)off[nkeys], lo, hi);
-  for (long long p = lo + threadIdx.x; p < hi; p += kT) {
-    const Rec r = rec[p];
-    const unsigned c = r.hi >> 2;
-    const unsigned b = off[c];
-    const int n = (int)(off[c + 1] - b);
-    if (n > kSmall) {
-      if ((unsigned)p == b) {
-        const unsigned slot = atomicAdd(nbig, 1u);
-        if ((long long)slot < big_cap) big[slot] = c;
-      }
-    } else if (n >= 2) {
-      int rank = 0;
-      for (int j = 0; j < n; ++j) {
-        const Rec x = rec[b + j];
-        rank += (b + (unsigned)j != (unsigned)p) &&
-                (x.lo < r.lo || (x.lo == r.lo && rid(S, x) < rid(S, r)));
-      }
-      srt[b + rank] = r;
+__global__ void __launch_bounds__(kPlaneCells) k_pg_cells(
+    Sp3<PT> S, GridC g, const unsigned* __restrict__ poff, long long nplanes,
+    const unsigned* __restrict__ pidx, unsigned* __restrict__ off,
+    Rec* __restrict__ rec, Rec* __restrict__ srt, unsigned* __restrict__ big,
+    unsigned* __restrict__ nbig, long long big_cap, unsigned* __restrict__ hot,
+    unsigned* __restrict__ nhot, unsigned step, unsigned long long seed) {
+  __shared__ PlaneLds L;
+  const int tid = (int)threadIdx.x;
+  long long u0, u1;
+  block_range(nplanes, u0, u1);
+  for (long long u = u0; u < u1; ++u) {
+    const unsigned base = poff[u];
+    const int n = (int)(poff[u + 1] - base);
+    const unsigned c0 = (unsigned)u << kPlaneShift;
+    if (n > kHot) {
+      if (tid == 0) hot[atomicAdd(nhot, 1u)] = (unsigned)u;
+      continue;
     }
+    L.cnt[tid] = 0u;
+    __syncthreads();
+    // A plane of at most kPCap records is read once: its records are made
+    // as it is counted and kept in LDS in load order.
+    const bool one = n <= kPCap;
+    for (int j = tid; j < n; j += kPlaneCells) {
+      const unsigned gi = pidx[base + j];
+      const unsigned c = tile_major(key_of(S, gi), g);
+      const int lc = (int)(c & (kPlaneCells - 1));
+      atomicAdd(&L.cnt[lc], 1u);
+      if (one) {
+        L.key[j] = make_rec(S, gi, c, step, seed).lo;
+        L.gi[j] = gi;
+        L.cell[j] = (unsigned char)lc;
+      }
+    }
+    __syncthreads();
+    const unsigned m = L.cnt[tid];
+    {
+      unsigned incl = m;
+      for (int o = 1; o < kPlaneCells; o <<= 1) {
+        const unsigned y = __shfl_up(incl, o);
+        if (tid >= o) incl += y;
+      }
+      L.off[tid] = incl - m;
+      off[c0 + tid] = base + incl - m;
+      if (tid == kPlaneCells - 1) {
+        L.off[kPlaneCells] = incl;
+        if (u == nplanes - 1) off[c0 + kPlaneCells] = base + incl;
+      }
+    }
+    __syncthreads();
+    if (one) {
+      // Crowded cells' records from LDS into their segments; the small
+      // cells' slots in cell order, ranked by (key, id) into srt.
+      L.cur[tid] = L.off[tid];
+      if (m > (unsigned)kSmall) {
+        const unsigned q = atomicAdd(nbig, 1u);
+        if ((long long)q < big_cap) big[q] = c0 + tid;
+      }
+      __syncthreads();
+      for (int j = tid; j < n; j += kPlaneCells) {
+        const int lc = L.cell[j];
+        const unsigned mc = L.cnt[lc];
+        const unsigned gi = L.gi[j];
+        const unsigned x = atomicAdd(&L.cur[lc], 1u);
+        L.ord[x] = (unsigned short)j;
+        if (mc > (unsigned)kSmall) {
+          Rec r;
+          r.lo = L.key[j];
+          r.hi = ((c0 + (unsigned)lc) << 2) | (gi >> 30);
+          r.val = gi & kIxMask;
+          rec[base + x] = r;
+        }
+      }
+      __syncthreads();
+      for (int x = tid; x < n; x += kPlaneCells) {
+        const int j = L.ord[x];
+        const int lc = L.cell[j];
+        if (!small_cell(L.cnt[lc])) continue;
+        const int b = (int)L.off[lc], mc = (int)L.cnt[lc];
+        const unsigned long long kp = L.key[j];
+        int rank = 0;
+        for (int y = b; y < b + mc; ++y) {
+          const int o = L.ord[y];
+          const unsigned long long ky = L.key[o];
+          if (ky < kp) {
+            ++rank;
+          } else if (ky == kp && o != j) {
+            const unsigned ga = L.gi[o], gb = L.gi[j];
+            const unsigned sa = ga >> 30, sb = gb >> 30;
+            const unsigned long long ia =
+                sa == 0 ? S.e.id[ga & kIxMask] : (sa == 1 ? S.i.id[ga & kIxMask] : S.n.id[ga & kIxMask]);
+            const unsigned long long ib =
+                sb == 0 ? S.e.id[gb & kIxMask] : (sb == 1 ? S.i.id[gb & kIxMask] : S.n.id[gb & kIxMask]);
+            rank += ia < ib;
+          }
+        }
+        const unsigned gi = L.gi[j];
+        Rec r;
+        r.lo = kp;
+        r.hi = ((c0 + (unsigned)lc) << 2) | (gi >> 30);
+        r.val = gi & kIxMask;
+        srt[base + b + rank] = r;
+      }
+      __syncthreads();
+      continue;
+    }
+    // Crowded cells: records straight into their segments, unsorted.
+    if (__ballot(m > (unsigned)kSmall)) {
+      L.cur[tid] = L.off[tid];
+      if (m > (unsigned)kSmall) {
+        const unsigned q = atomicAdd(nbig, 1u);
+        if ((long long)q < big_cap) big[q] = c0 + tid;
+      }
+      __syncthreads();
+      for (int j = tid; j < n; j += kPlaneCells) {
+        const unsigned gi = pidx[base + j];
+        const unsigned c = tile_major(key_of(S, gi), g);
+        const int lc = (int)(c & (kPlaneCells - 1));
+        if (L.cnt[lc] > (unsigned)kSmall)
+          rec[base + atomicAdd(&L.cur[lc], 1u)] = make_rec(S, gi, c, step, seed);
+      }
+      __syncthreads();
+    }
+    // Small cells in batches.
+    for (int c_lo = 0; c_lo < kPlaneCells;) {
+      if (tid == 0) {
+        int c_hi = c_lo, nb = 0;
+        while (c_hi < kPlaneCells) {
+          const unsigned mc = L.cnt[c_hi];
+          const int add = small_cell(mc) ? (int)mc : 0;
+          if (nb + add > kPCap) break;
+          L.start[c_hi] = (unsigned)nb;
+          L.cur[c_hi] = (unsigned)nb;
+          nb += add;
+          ++c_hi;
+        }
+        L.hi = c_hi;
+        L.nb = nb;
+      }
+      __syncthreads();
+      const int c_hi = L.hi, nb = L.nb;
+      if (nb > 0) {
+        for (int j = tid; j < n; j += kPlaneCells) {
+          const unsigned gi = pidx[base + j];
+          const uint32_t kc = key_of(S, gi);
+          const int lc = (int)(tile_major(kc, g) & (kPlaneCells - 1));
+          if (lc < c_lo || lc >= c_hi || !small_cell(L.cnt[lc])) continue;
+          const int p = (int)atomicAdd(&L.cur[lc], 1u);
+          const Rec r = make_rec(S, gi, c0 + lc, step, seed);
+          L.key[p] = r.lo;
+          L.gi[p] = gi;
+          L.cell[p] = (unsigned char)lc;
+        }
+        __syncthreads();
+        for (int p = tid; p < nb; p += kPlaneCells) {
+          const int lc = L.cell[p];
+          const int b = (int)L.start[lc], mc = (int)L.cnt[lc];
+          const unsigned long long kp = L.key[p];
+          int rank = 0;
+          for (int q = b; q < b + mc; ++q) {
+            const unsigned long long kq = L.key[q];
+            if (kq < kp) {
+              ++rank;
+            } else if (kq == kp && q != p) {
+              // Equal draws (practically never): id order.
+              const unsigned ga = L.gi[q], gb = L.gi[p];
+              const unsigned sa = ga >> 30, sb = gb >> 30;
+              const unsigned long long ia =
+                  sa == 0 ? S.e.id[ga & kIxMask] : (sa == 1 ? S.i.id[ga & kIxMask] : S.n.id[ga & kIxMask]);
+              const unsigned long long ib =
+                  sb == 0 ? S.e.id[gb & kIxMask] : (sb == 1 ? S.i.id[gb & kIxMask] : S.n.id[gb & kIxMask]);
+              rank += ia < ib;
+            }
+          }
+          const unsigned gi = L.gi[p];
+          Rec r;
+          r.lo = kp;
+          r.hi = ((c0 + (unsigned)lc) << 2) | (gi >> 30);
+          r.val = gi & kIxMask;
+          srt[base + L.off[lc] + rank] = r;
+        }
+      }
+      __syncthreads();
+      c_lo = c_hi;
+    }
+  }
+}
+
+// Planes of more than kHot records (the atoms piled above an evaporating
+// spot): their records, taken together as one range (the planes' sizes
+// prefixed), are grouped by cell over the whole GPU: a count per cell
+// aggregated per chunk in LDS, each plane's cell offsets, a scatter into
+// the cells' segments with one reservation per chunk and cell, and the few
+// small cells' records ranked from there.  Per-cell counters of hot plane h
+// are hcnt[64 h + cell].
+__global__ void __launch_bounds__(1024) k_ph_prep(
+    const unsigned* __restrict__ poff, const unsigned* __restrict__ hot,
+    const unsigned* __restrict__ nhot, unsigned* __restrict__ hpre,
+    unsigned* __restrict__ hcnt) {
+  __shared__ unsigned s[1024];
+  const int nh = (int)*nhot;
+  const int per = (nh + 1023) / 1024;
+  const int h0 = threadIdx.x * per;
+  unsigned tot = 0;
+  for (int q = 0; q < per && h0 + q < nh; ++q) {
+    const unsigned u = hot[h0 + q];
+    tot += poff[u + 1] - poff[u];
+  }
+  s[threadIdx.x] = tot;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const unsigned v = threadIdx.x >= (unsigned)o ? s[threadIdx.x - o] : 0u;
+    __syncthreads();
+    s[threadIdx.x] += v;
+    __syncthreads();
+  }
+  unsigned run = s[threadIdx.x] - tot;
+  for (int q = 0; q < per && h0 + q < nh; ++q) {
+    const unsigned u = hot[h0 + q];
+    hpre[h0 + q] = run;
+    run += poff[u + 1] - poff[u];
+  }
+  if (threadIdx.x == 1023) hpre[nh] = s[1023];
+  for (long long j = threadIdx.x; j < (long long)nh * kPlaneCells; j += 1024)
+    hcnt[j] = 0u;
+}
+
+// The hot plane holding record t of the joint range (binary search).
+__device__ __forceinline__ int hot_plane(const unsigned* __restrict__ hpre,
+                                         int nh, unsigned t) {
+  int lo = 0, hi = nh - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (hpre[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Record t of the hot range: its index word and its cell in the plane.
+template <class PT>
+__device__ __forceinline__ void hot_rec(const Sp3<PT>& S, const GridC& g,
+                                        const unsigned* __restrict__ poff,
+                                        const unsigned* __restrict__ hot,
+                                        const unsigned* __restrict__ hpre,
+                                        const unsigned* __restrict__ pidx,
+                                        int nh, unsigned t, int& h,
+                                        unsigned& gi, unsigned& c) {
+  h = hot_plane(hpre, nh, t);
+  gi = pidx[poff[hot[h]] + (t - hpre[h])];
+  c = tile_major(key_of(S, gi), g);
+}
+
+template <class PT>
+__global__ void __launch_bounds__(kT) k_ph_count(
+    Sp3<PT> S, GridC g, const unsigned* __restrict__ poff,
+    const unsigned* __restrict__ hot, const unsigned* __restrict__ nhot,
+    const unsigned* __restrict__ hpre, const unsigned* __restrict__ pidx,
+    unsigned* __restrict__ hcnt) {
+  __shared__ unsigned hk[kPHash];
+  __shared__ unsigned hc[kPHash];
+  const int nh = (int)*nhot;
+  if (nh == 0) return;
+  const unsigned tot = hpre[nh];
+  for (unsigned b = blockIdx.x * (unsigned)kPChunk; b < tot;
+       b += gridDim.x * (unsigned)kPChunk) {
+    for (int q = threadIdx.x; q < kPHash; q += kT) {
+      hk[q] = kGEmpty;
+      hc[q] = 0u;
+    }
+    __syncthreads();
+    const unsigned e = b + kPChunk < tot ? b + kPChunk : tot;
+    for (unsigned t = b + threadIdx.x; t < e; t += kT) {
+      int h;
+      unsigned gi, c;
+      hot_rec(S, g, poff, hot, hpre, pidx, nh, t, h, gi, c);
+      const unsigned key = (unsigned)h * kPlaneCells + (c & (kPlaneCells - 1));
+      const int q = plane_slot(hk, key);
+      if (q >= 0)
+        atomicAdd(&hc[q], 1u);
+      else
+        atomicAdd(&hcnt[key], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kPHash; q += kT)
+      if (hk[q] != kGEmpty) atomicAdd(&hcnt[hk[q]], hc[q]);
+    __syncthreads();
+  }
+}
+
+// Per hot plane (a wavefront each): its cells' offsets, the crowded cells
+// listed, the counters turned into the cells' plane-local cursors.
+__global__ void __launch_bounds__(kPlaneCells) k_ph_off(
+    const unsigned* __restrict__ poff, long long nplanes,
+    const unsigned* __restrict__ hot, const unsigned* __restrict__ nhot,
+    unsigned* __restrict__ hcnt, unsigned* __restrict__ off,
+    unsigned* __restrict__ big, unsigned* __restrict__ nbig,
+    long long big_cap) {
+  const int nh = (int)*nhot;
+  const int lane = (int)threadIdx.x;
+  for (int h = blockIdx.x; h < nh; h += gridDim.x) {
+    const unsigned u = hot[h];
+    const unsigned base = poff[u], c0 = u << kPlaneShift;
+    const unsigned m = hcnt[h * kPlaneCells + lane];
+    unsigned incl = m;
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned y = __shfl_up(incl, o);
+      if (lane >= o) incl += y;
+    }
+    off[c0 + lane] = base + incl - m;
+    if (lane == 63 && (long long)u == nplanes - 1) off[c0 + kPlaneCells] = base + incl;
+    if (m > (unsigned)kSmall) {
+      const unsigned s = atomicAdd(nbig, 1u);
+      if ((long long)s < big_cap) big[s] = c0 + lane;
+    }
+    hcnt[h * kPlaneCells + lane] = incl - m;
+  }
+}
+
+template <class PT>
+__global__ void __launch_bounds__(kT) k_ph_scatter(
+    Sp3<PT> S, GridC g, const unsigned* __restrict__ poff,
+    const unsigned* __restrict__ hot, const unsigned* __restrict__ nhot,
+    const unsigned* __restrict__ hpre, const unsigned* __restrict__ pidx,
+    unsigned* __restrict__ hcnt, Rec* __restrict__ rec, unsigned step,
+    unsigned long long seed) {
+  __shared__ unsigned hk[kPHash];
+  __shared__ unsigned hc[kPHash];
+  __shared__ unsigned hb[kPHash];
+  const int nh = (int)*nhot;
+  if (nh == 0) return;
+  const unsigned tot = hpre[nh];
+  for (unsigned b = blockIdx.x * (unsigned)kPChunk; b < tot;
+       b += gridDim.x * (unsigned)kPChunk) {
+    for (int q = threadIdx.x; q < kPHash; q += kT) {
+      hk[q] = kGEmpty;
+      hc[q] = 0u;
+    }
+    __syncthreads();
+    const unsigned e = b + kPChunk < tot ? b + kPChunk : tot;
+    for (unsigned t = b + threadIdx.x; t < e; t += kT) {
+      int h;
+      unsigned gi, c;
+      hot_rec(S, g, poff, hot, hpre, pidx, nh, t, h, gi, c);
+      const int q = plane_slot(hk, (unsigned)h * kPlaneCells + (c & (kPlaneCells - 1)));
+      if (q >= 0) atomicAdd(&hc[q], 1u);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kPHash; q += kT) {
+      const unsigned key = hk[q];
+      if (key != kGEmpty) {
+        hb[q] = poff[hot[key >> kPlaneShift]] + atomicAdd(&hcnt[key], hc[q]);
+        hc[q] = 0u;
+      }
+    }
+    __syncthreads();
+    for (unsigned t = b + threadIdx.x; t < e; t += kT) {
+      int h;
+      unsigned gi, c;
+      hot_rec(S, g, poff, hot, hpre, pidx, nh, t, h, gi, c);
+      const unsigned key = (unsigned)h * kPlaneCells + (c & (kPlaneCells - 1));
+      // The table is unchanged since the count (see k_cu_scatter).
+      const int q = plane_slot(hk, key);
+      const unsigned slot = q >= 0 ? hb[q] + atomicAdd(&hc[q], 1u)
+                                   : poff[hot[h]] + atomicAdd(&hcnt[key], 1u);
+      rec[slot] = make_rec(S, gi, c, step, seed);
+    }
+    __syncthreads();
+  }
+}
+
+// The small cells of the hot planes, a thread per (cell, record): rank in
+// the cell's (key, id) order from the scattered records.
+template <class PT>
+__global__ void __launch_bounds__(kT) k_ph_rank(
+    Sp3<PT> S, const unsigned* __restrict__ hot,
+    const unsigned* __restrict__ nhot, const unsigned* __restrict__ off,
+    const Rec* __restrict__ rec, Rec* __restrict__ srt) {
+  const long long nt = (long long)*nhot * kPlaneCells * kSmall;
+  for (long long t = blockIdx.x * (long long)kT + threadIdx.x; t < nt;
+       t += (long long)gridDim.x * kT) {
+    const int r = (int)(t % kSmall);
+    const long long hc = t / kSmall;
+    const unsigned c = (hot[hc / kPlaneCells] << kPlaneShift) + (unsigned)(hc % kPlaneCells);
+    const unsigned b = off[c];
+    const int m = (int)(off[c + 1] - b);
+    if (!small_cell((unsigned)m) || r >= m) continue;
+    const Rec x = rec[b + r];
+    int rank = 0;
+    for (int j = 0; j < m; ++j) {
+      const Rec y = rec[b + j];
+      rank += j != r && (y.lo < x.lo || (y.lo == x.lo && rid(S, y) < rid(S, x)));
+    }
+    srt[b + rank] = x;
   }
 }
 
@@ -812,20 +1232,35 @@ void ionproc_t(pic_ctx* c, double dt) {
   k.tcnt_e = c->tcnt[0];
   k.tcnt_i = c->tcnt[1];
   const Sp3<PT> S = sp3<PT>(c);
-  hipMemsetAsync(c->cg_cnt, 0, nc * sizeof(unsigned), st);
-  hipMemsetAsync(c->cg_nbig, 0, sizeof(unsigned), st);
+  const long long np = nc >> kPlaneShift;      // tile planes
+  hipMemsetAsync(c->cg_cnt, 0, np * sizeof(unsigned), st);
+  hipMemsetAsync(c->cg_nbig, 0, 2 * sizeof(unsigned), st);   // crowded cells, hot planes
   // Grids of a multiple of 8 workgroups (see xcd_block).
-  k_ig_count<<<4096, kT, 0, st>>>(c->key[0], c->key[2], c->key[1], c->dc, c->g,
-                                  c->cg_cnt);
-  const long long nb = (nc + kScanB - 1) / kScanB;
-  k_ig_scan_blocks<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_cnt, nc, c->cg_off,
+  k_pg_count<PT><<<4096, kT, 0, st>>>(S, c->dc, c->g, c->cg_cnt);
+  const long long nb = (np + kScanB - 1) / kScanB;
+  k_ig_scan_blocks<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_cnt, np, c->cg_poff,
                                                    c->cg_bsum);
   k_ig_scan_sums<<<1, 1024, 0, st>>>(c->cg_bsum, (int)nb);
-  k_ig_scan_apply<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_off, nc, c->cg_bsum);
-  k_ig_scatter<PT><<<4096, kT, 0, st>>>(S, c->dc, c->g, c->cg_off, c->cg_cnt,
+  k_ig_scan_apply<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_poff, np, c->cg_bsum);
+  k_pg_scatter<PT><<<4096, kT, 0, st>>>(S, c->dc, c->g, c->cg_poff, c->cg_cnt,
+                                        c->cg_idx);
+  k_pg_cells<PT><<<8192, kPlaneCells, 0, st>>>(
+      S, c->g, c->cg_poff, np, c->cg_idx, c->cg_off, c->cg_rec, c->cg_srt,
+      c->cg_big, c->cg_nbig, c->cg_big_cap, c->cg_hot, c->cg_nbig + 1, k.step,
+      k.seed);
+  unsigned* nhot = c->cg_nbig + 1;
+  k_ph_prep<<<1, 1024, 0, st>>>(c->cg_poff, c->cg_hot, nhot, c->cg_hpre,
+                                c->cg_cnt);
+  k_ph_count<PT><<<1024, kT, 0, st>>>(S, c->g, c->cg_poff, c->cg_hot, nhot,
+                                      c->cg_hpre, c->cg_idx, c->cg_cnt);
+  k_ph_off<<<512, kPlaneCells, 0, st>>>(c->cg_poff, np, c->cg_hot, nhot,
+                                        c->cg_cnt, c->cg_off, c->cg_big,
+                                        c->cg_nbig, c->cg_big_cap);
+  k_ph_scatter<PT><<<1024, kT, 0, st>>>(S, c->g, c->cg_poff, c->cg_hot, nhot,
+                                        c->cg_hpre, c->cg_idx, c->cg_cnt,
                                         c->cg_rec, k.step, k.seed);
-  k_ig_rank<PT><<<8192, kT, 0, st>>>(S, c->cg_off, nc, c->cg_rec, c->cg_srt,
-                                     c->cg_big, c->cg_nbig, c->cg_big_cap);
+  k_ph_rank<PT><<<512, kT, 0, st>>>(S, c->cg_hot, nhot, c->cg_off, c->cg_rec,
+                                    c->cg_srt);
   k_ip_small<PT><<<8192, kT, 0, st>>>(S, c->cg_off, nc, c->cg_srt, k, c->g,
                                       c->ncount, c->acc_next, c->dead2,
                                       c->ip_ev, c->ip_evp, c->dc);

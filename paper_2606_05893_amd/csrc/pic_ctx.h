@@ -141,7 +141,10 @@ struct pic_ctx {
   pic::Rec* cg_rec;
   pic::Rec* cg_srt;
   long long cg_work_cap;            // records: all particles' capacity
-  unsigned* cg_idx;
+  unsigned* cg_idx;                 // index words binned by tile plane
+  unsigned* cg_poff;                // tile planes' offsets into cg_idx
+  unsigned* cg_hot;                 // planes of many records (ion processes)
+  unsigned* cg_hpre;                // their sizes prefixed
   long long cg_big_cap;
   long long cg_nkeys;               // tile-major cell numbers (tiles x 512)
   // Recombination, Cu+ ionisation, charge exchange: settings and the listed
