@@ -91,6 +91,14 @@ __device__ __forceinline__ unsigned plane_of(unsigned c, const GridC& g) {
   return tile_major(c, g) >> kPlaneShift;
 }
 
+// The planes a workgroup of a per-plane pass serves: plane xcd_block() +
+// k * gridDim.x, k = 0, 1, ...  The arrays are binned by tile, not by
+// plane, so a plane's particles are spread over its tile's range; with this
+// order the eight planes of a tile are served at the same time by eight
+// workgroups on one XCD, which share the tile's cache lines in its L2.
+// (The grid is a multiple of 8.)
+__device__ __forceinline__ long long plane_first() { return xcd_block(); }
+
 // Slot of a plane in the chunk's table (inserted if absent), or -1.
 __device__ __forceinline__ int plane_slot(unsigned* hk, unsigned key) {
   const unsigned h = (key * 2654435761u) >> 24;

@@ -10,22 +10,25 @@
 // collisions, collision j between electron j mod N_e and ion j mod N_i.
 //
 // The particle arrays are binned by tile (8x8x8 cells) and move little
-// between binning passes, so the work is grouped by unit, half a tile (four
-// z-planes, 256 cells): the indices of the unit's electrons and ions are
-// binned (a count and a scatter per chunk of particles, aggregated by unit
-// in LDS, so that a chunk, nearly all of one tile, takes a few global
-// atomics), and one workgroup serves a unit at a time.  It counts the
-// unit's particles by cell, loads them (order key, id, velocity) into LDS
-// in cell order, ranks each in its cell by comparison with the others,
-// runs the like collisions of all cells (disjoint pairs, in parallel), then
-// the electron-ion collisions as chains (the t-th particle of the smaller
-// group meets the larger group's t-th, (t+m)-th, ... particles; the chains
-// share no particle, so they equal the sequence of the definition), and
-// writes the velocities back once.  A unit holding more particles than LDS
-// takes is served in batches of whole cells; a cell holding more than a
-// batch is sorted alone in LDS (a bitonic sort of its keys) and collides on
-// the particle arrays, the electron-ion sequence in rounds of min(N_e, N_i)
-// collisions that touch every particle at most once.
+// between binning passes, so the work is grouped by tile plane (one z layer
+// of a tile, 64 cells): the index words of the plane's electrons and ions
+// are binned (a count and a scatter per chunk of particles, aggregated by
+// plane in LDS, so that a chunk, nearly all of one tile, takes a few global
+// atomics), and one wavefront serves a plane at a time.  It counts the
+// plane's particles by cell as it loads them (id, velocity) into LDS, puts
+// the slots in cell order, ranks each particle in its cell by comparison
+// with the others, lists the work by class (like pairs, like triplets,
+// electron-ion chains of one, two, three or more collisions, so that a
+// wavefront runs one kind), runs the like collisions of all cells (disjoint
+// pairs, in parallel), then the electron-ion collisions as chains (the t-th
+// particle of the smaller group meets the larger group's t-th, (t+m)-th,
+// ... particles; the chains share no particle, so they equal the sequence
+// of the definition), and writes the velocities back once.  A plane holding
+// more particles than one LDS batch is served in batches of whole cells; a
+// cell holding more than a batch is listed for a workgroup that sorts its
+// keys in LDS (bitonic) and collides on the particle arrays, the
+// electron-ion sequence in rounds of min(N_e, N_i) collisions that touch
+// every particle at most once.
 #include <cmath>
 
 #include "cell_groups.h"
@@ -163,7 +166,7 @@ __device__ void collide(const Sp2<PT>& S, int sa, unsigned a, int sb,
   }
 }
 
-// ---- binning of the charged particles' indices by unit ---------------------
+// ---- binning of the charged particles' indices by plane ---------------------
 // Charged particle t of the joint range (electrons, then ions): its key, and
 // its index word (species in the top bit, the array index below it).
 __device__ __forceinline__ uint32_t charged_key(const uint32_t* __restrict__ ke,
@@ -178,7 +181,7 @@ __device__ __forceinline__ uint32_t charged_key(const uint32_t* __restrict__ ke,
   return ki[t - ne];
 }
 
-// Live charged particles per unit.
+// Live charged particles per plane.
 __global__ void __launch_bounds__(kT) k_cu_count(
     const uint32_t* __restrict__ ke, const uint32_t* __restrict__ ki,
     const Counters* dc, GridC g, unsigned* __restrict__ cnt) {
@@ -261,10 +264,10 @@ __global__ void __launch_bounds__(kScanB) k_cg_scan_apply(
   if (i < n) off[i + 1] += bsum[blockIdx.x];
 }
 
-// Each live charged particle's index word into its unit's range (order
-// inside the range arbitrary: the cell pass sorts).  Per chunk the units
-// are counted in LDS, one range per distinct unit reserved with one global
-// atomic, then each particle placed at the next slot of its unit's range.
+// Each live charged particle's index word into its plane's range (order
+// inside the range arbitrary: the cell pass sorts).  Per chunk the planes
+// are counted in LDS, one range per distinct plane reserved with one global
+// atomic, then each particle placed at the next slot of its plane's range.
 __global__ void __launch_bounds__(kT) k_cu_scatter(
     const uint32_t* __restrict__ ke, const uint32_t* __restrict__ ki,
     const Counters* dc, GridC g, const unsigned* __restrict__ off,
@@ -304,7 +307,7 @@ __global__ void __launch_bounds__(kT) k_cu_scatter(
       const uint32_t c = charged_key(ke, ki, ne, t, gi);
       if (c == kDead) continue;
       const unsigned u = plane_of(c, g);
-      // The table is unchanged since the count: a unit found there then is
+      // The table is unchanged since the count: a plane found there then is
       // found again, one that found no room finds none again.
       const int q = plane_slot(hk, u);
       const unsigned slot = q >= 0 ? hb[q] + atomicAdd(&hc[q], 1u)
@@ -316,9 +319,9 @@ __global__ void __launch_bounds__(kT) k_cu_scatter(
 }
 
 // ---- the cell pass -------------------------------------------------------------
-// One wavefront per unit: a workgroup of one wavefront never waits at a
-// barrier for others, so a unit's serial stretches (the longest electron-ion
-// chain) leave the SIMD to the other units' wavefronts.
+// One wavefront per plane: a workgroup of one wavefront never waits at a
+// barrier for others, so a plane's serial stretches (the longest electron-ion
+// chain) leave the SIMD to the other planes' wavefronts.
 constexpr int kCT = 64;
 
 // LDS of a batch of whole cells.  Particles sit in load order (slots); the
@@ -329,7 +332,7 @@ struct BatchLds {
   unsigned long long id[kCap];
   double v[3][kCap];
   unsigned gi[kCap];              // index word
-  unsigned short cell[kCap];      // cell in the unit
+  unsigned short cell[kCap];      // cell in the plane
   unsigned short perm[kCap];      // sorted place -> slot
   unsigned short work[kCap];      // cell order -> slot, then the work items
 };
@@ -338,8 +341,8 @@ struct BatchLds {
 // triplets, electron-ion chains of one, two, and three or more collisions.
 constexpr int kNCls = 5;
 
-struct UnitLds {
-  unsigned off[kPlaneCells + 1];   // cell offsets in the unit's particles
+struct PlaneLdsC {
+  unsigned off[kPlaneCells + 1];   // cell offsets in the plane's particles
   unsigned cur[kPlaneCells];
   unsigned short ne[kPlaneCells];  // electrons per cell
   unsigned cls[kNCls + 1];        // class offsets in the work list
@@ -361,7 +364,7 @@ __device__ __forceinline__ void collide_lds(BatchLds& L, int a, int b, int ty,
   }
 }
 
-// One particle of the unit into slot p of the batch (not yet its key).
+// One particle of the plane into slot p of the batch (not yet its key).
 template <class PT>
 __device__ __forceinline__ void load_slot(const Sp2<PT>& S, BatchLds& L, int p,
                                           unsigned gi, int lc) {
@@ -380,7 +383,7 @@ __device__ __forceinline__ void load_slot(const Sp2<PT>& S, BatchLds& L, int p,
 // The work a sorted place leads: its like class (0 pair, 1 triplet, -1
 // none) and electron-ion chain class (2, 3, 4 for one, two, three or more
 // collisions, -1 none).
-__device__ __forceinline__ void place_work(const BatchLds& L, const UnitLds& U,
+__device__ __forceinline__ void place_work(const BatchLds& L, const PlaneLdsC& U,
                                            unsigned ob, int r, int& lcl,
                                            int& ecl) {
   lcl = ecl = -1;
@@ -404,12 +407,12 @@ __device__ __forceinline__ void place_work(const BatchLds& L, const UnitLds& U,
   }
 }
 
-// The cells [c_lo, c_hi) of the unit, nb particles loaded in slots
+// The cells [c_lo, c_hi) of the plane, nb particles loaded in slots
 // [0, nb): cell order, ranks, work lists, the collisions, the velocities
 // back to the particle arrays.
 template <class PT>
 __device__ void batch_collide(const Sp2<PT>& S, int c_lo, int c_hi, int nb,
-                              BatchLds& L, UnitLds& U, const CoulC& k,
+                              BatchLds& L, PlaneLdsC& U, const CoulC& k,
                               unsigned long long& nl,
                               unsigned long long& nei) {
   const int tid = (int)threadIdx.x;
@@ -524,24 +527,22 @@ __device__ void batch_collide(const Sp2<PT>& S, int c_lo, int c_hi, int nb,
   __syncthreads();
 }
 
-// Units in turn (a contiguous run of them, their tiles' particles adjacent
-// in the arrays).  A unit of at most kCap particles is loaded in one pass,
+// Planes in turn (plane_first: a tile's eight planes at once on one XCD).
+// A plane of at most kCap particles is loaded in one pass,
 // counted by cell as it loads; a larger one is counted first and loaded in
 // batches of whole cells; a cell of more than kCap particles is listed for
 // the crowded-cell pass.
 template <class PT>
 __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
     Sp2<PT> S, const uint32_t* __restrict__ ke, const uint32_t* __restrict__ ki,
-    GridC g, const unsigned* __restrict__ uoff, long long nunits,
+    GridC g, const unsigned* __restrict__ uoff, long long nplanes,
     const unsigned* __restrict__ uidx, unsigned* __restrict__ crowd,
     long long crowd_cap, unsigned* __restrict__ ncrowd, CoulC k, Counters* dc) {
   __shared__ BatchLds L;
-  __shared__ UnitLds U;
+  __shared__ PlaneLdsC U;
   const int tid = (int)threadIdx.x;
-  long long u0, u1;
-  block_range(nunits, u0, u1);
   unsigned long long nl = 0, nei = 0;
-  for (long long u = u0; u < u1; ++u) {
+  for (long long u = plane_first(); u < nplanes; u += gridDim.x) {
     const unsigned base = uoff[u];
     const int n = (int)(uoff[u + 1] - base);
     if (n < 2) continue;
@@ -557,7 +558,7 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
     }
     __syncthreads();
     {
-      // Exclusive scan of the unit's cell counts (one per lane).
+      // Exclusive scan of the plane's cell counts (one per lane).
       const unsigned t = U.cur[tid];
       unsigned incl = t;
       for (int o = 1; o < kCT; o <<= 1) {
@@ -618,7 +619,7 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
 }
 
 // ---- crowded cells ---------------------------------------------------------------
-// One workgroup per listed cell: its particles gathered from the unit's
+// One workgroup per listed cell: its particles gathered from the plane's
 // index words, their keys sorted in LDS (bitonic), the collisions on the
 // particle arrays, the electron-ion sequence in rounds of min(N_e, N_i)
 // collisions that touch every particle at most once.
@@ -777,7 +778,7 @@ void coulomb_t(pic_ctx* c, double dt) {
   k.step = (unsigned)c->step;
   k.seed = c->cfg.seed;
   const Sp2<PT> S = sp2<PT>(c);
-  const long long nu = c->cg_nkeys >> kPlaneShift;   // units (half tiles)
+  const long long nu = c->cg_nkeys >> kPlaneShift;   // tile planes
   hipMemsetAsync(c->cg_cnt, 0, nu * sizeof(unsigned), st);
   // Grids of a multiple of 8 workgroups (see xcd_block).
   k_cu_count<<<4096, kT, 0, st>>>(c->key[0], c->key[2], c->dc, c->g,

@@ -3,11 +3,15 @@
 // the paper's remaining Monte Carlo collision processes and the higher
 // charge state they lead to.
 //
-// Electrons, Cu+ and Cu atoms are grouped by cell as for the Coulomb
-// collisions (count, scan, scatter of 16-byte records keyed by species and
-// a random order draw, then a sort inside each cell).  Every cell is then
-// processed in sequence by one thread (a workgroup sorts the crowded ones,
-// their atoms a window at a time): first each electron in turn against the
+// Electrons, Cu+ and Cu atoms are grouped by cell: their index words are
+// binned by tile plane as for the Coulomb collisions, then one wavefront a
+// plane writes the cells' offsets and, in each cell's segment, 16-byte
+// records keyed by species and a random order draw: sorted by (key, id) in
+// cells of at most kSmall, unsorted in the crowded ones (the few planes of
+// many records, the atoms piled above an evaporating spot, are grouped by
+// cell over the whole GPU instead).  Every cell is then processed in
+// sequence by one thread (a workgroup sorts the crowded ones, their atoms a
+// window at a time): first each electron in turn against the
 // cell's Cu+ (Eq. 4 evaluated per electron; the r-th colliding electron
 // takes the r-th ion), then the Cu+ left against the cell's atoms (ion k with atom k mod N_n,
 // the real relative speed).  Recombinations and charge exchanges are applied
@@ -364,9 +368,8 @@ __global__ void __launch_bounds__(kPlaneCells) k_pg_cells(
     unsigned* __restrict__ nhot, unsigned step, unsigned long long seed) {
   __shared__ PlaneLds L;
   const int tid = (int)threadIdx.x;
-  long long u0, u1;
-  block_range(nplanes, u0, u1);
-  for (long long u = u0; u < u1; ++u) {
+
+  for (long long u = plane_first(); u < nplanes; u += gridDim.x) {
     const unsigned base = poff[u];
     const int n = (int)(poff[u + 1] - base);
     const unsigned c0 = (unsigned)u << kPlaneShift;
