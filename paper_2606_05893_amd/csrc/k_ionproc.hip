@@ -155,6 +155,172 @@ __device__ void swap_records<PartsM>(const PartsM& a, unsigned i,
   b.id[j] = u;
 }
 
+// A cell's records in (key, id) order as a plane pass holds them in LDS:
+// the keys and index words by slot, the sorted places' slots in perm.
+struct LdsRecs {
+  const unsigned long long* key;
+  const unsigned* gi;
+  const unsigned short* perm;
+  int b;                            // the cell's first place
+  unsigned cell;                    // its tile-major number
+  __device__ Rec operator[](int j) const {
+    const int p = perm[b + j];
+    Rec r;
+    r.lo = key[p];
+    r.hi = (cell << 2) | (gi[p] >> 30);
+    r.val = gi[p] & 0x3FFFFFFFu;
+    return r;
+  }
+  __device__ LdsRecs operator+(int d) const {
+    LdsRecs x = *this;
+    x.b += d;
+    return x;
+  }
+};
+
+struct Tally {
+  unsigned long long rec = 0, cx = 0, starved = 0, near = 0;
+};
+
+// Electrons re[0..ne) against the cell's Cu+ ri[0..ni), both in their
+// random order; returns the number of Cu+ taken.
+template <class PT, class RV>
+__device__ int ip_electrons(const Sp3<PT>& S, RV re, int ne,
+                            RV ri, int ni, unsigned cell,
+                            const IonC& k, const GridC& g,
+                            int* __restrict__ ncount,
+                            long long* __restrict__ acc,
+                            uint32_t* __restrict__ dead2, Rec* __restrict__ ev,
+                            uint2* __restrict__ evp, Counters* dc, Tally& t) {
+  int used = 0;                                     // Cu+ taken by electrons
+  if (ni > 0) {
+    const double dens = (double)ni * k.w_dx3;
+    for (int a = 0; a < ne; ++a) {
+      const unsigned e = re[a].val;
+      double vx, vy, vz;
+      Acc<PT>::vel(S.e, e, vx, vy, vz);
+      const double v2 = (vx * vx + vy * vy) + vz * vz;
+      const double v = sqrt(v2);
+      const double E = (k.half_me * v2) / kE;
+      const double sr = sigma_rec(k, E), si = sigma_ion2(k, E);
+      const double st = sr + si;
+      const double P = 1.0 - exp(-(((dens * st) * v) * k.dt));
+      const unsigned long long eid = S.e.id[e];
+      double u1, u2;
+      uniform2(eid, k.step, kTagEI0, k.seed, u1, u2);
+      const double frac = sr / st;
+      if (fabs(u1 - P) < kNear) t.near += 1;
+      if (!(u1 < P)) continue;
+      if (used >= ni) {
+        t.starved += 1;
+        continue;
+      }
+      if (fabs(u2 - frac) < kNear) t.near += 1;
+      const unsigned ion = ri[used].val;
+      ++used;
+      S.ki[ion] = kDead;
+      if ((long long)ion < k.nb_i) atomicSub(&k.tcnt_i[tile_of(cell, g)], 1u);
+      const unsigned long long d2 = atomicAdd(&dc->n_dead2, 1ull);
+      if (d2 < (unsigned long long)kDeadList) dead2[d2] = ion;
+      if (u2 < frac) {
+        // Recombination: a Cu atom with the ion's position and id and the
+        // pair's centre-of-mass velocity; the electron and the ion leave.
+        const unsigned long long slot = atomicAdd(&dc->n[1], 1ull);
+        if ((long long)slot >= k.cap_n) {
+          atomicOr(&dc->err, kErrCapacity);
+        } else {
+          double ivx, ivy, ivz;
+          Acc<PT>::vel(S.i, ion, ivx, ivy, ivz);
+          const double den = kMcu + kMe;
+          Acc<PT>::copy_pos(S.i, ion, S.n, (long long)slot);
+          Acc<PT>::set_vel(S.n, (long long)slot, (kMcu * ivx + kMe * vx) / den,
+                           (kMcu * ivy + kMe * vy) / den,
+                           (kMcu * ivz + kMe * vz) / den);
+          S.n.id[slot] = S.i.id[ion];
+          S.kn[slot] = cell;
+          atomicAdd(&ncount[cell], 1);
+        }
+        S.ke[e] = kDead;
+        if ((long long)e < k.nb_e) atomicSub(&k.tcnt_e[tile_of(cell, g)], 1u);
+        dep_add(S.e, e, g, acc, 1);
+        dep_add(S.i, ion, g, acc, -1);
+        t.rec += 1;
+      } else {
+        const unsigned long long q = atomicAdd(&dc->f3_ion2, 1ull);
+        if ((long long)q < k.max_ev) {
+          Rec x;
+          x.lo = eid;
+          x.hi = 0u;
+          x.val = (unsigned)q;
+          ev[q] = x;
+          evp[q] = make_uint2(e, ion);
+        } else {
+          atomicOr(&dc->err, kErrEvents);
+        }
+      }
+    }
+  }
+  return used;
+}
+
+// Charge exchange trial of one Cu+ with one atom of its cell (nn atoms).
+template <class PT>
+__device__ void cx_pair(const Sp3<PT>& S, unsigned ion, unsigned at, int nn,
+                        const IonC& k, const GridC& g,
+                        long long* __restrict__ acc, Tally& t) {
+  const double dens = (double)nn * k.w_dx3;
+  const double mr = 0.5 * kMcu;
+  double ix, iy, iz, nx, ny, nz;
+  Acc<PT>::vel(S.i, ion, ix, iy, iz);
+  Acc<PT>::vel(S.n, at, nx, ny, nz);
+  const double ux = ix - nx, uy = iy - ny, uz = iz - nz;
+  const double u2 = (ux * ux + uy * uy) + uz * uz;
+  const double u = sqrt(u2);
+  const double eps = ((0.5 * mr) * u2) / kE;
+  const double P = 1.0 - exp(-(((dens * sigma_cx(k, eps)) * u) * k.dt));
+  double u1, u1b;
+  uniform2(S.i.id[ion], k.step, kTagCX, k.seed, u1, u1b);
+  if (fabs(u1 - P) < kNear) t.near += 1;
+  if (u1 < P) {
+    dep_add(S.i, ion, g, acc, -1);
+    swap_records(S.i, ion, S.n, at);
+    dep_add(S.i, ion, g, acc, 1);
+    t.cx += 1;
+  }
+}
+
+// One small cell's processes on records r[0..n) in (key, id) order:
+// electrons, then Cu+, then atoms.
+template <class PT, class RV>
+__device__ void ip_cell(const Sp3<PT>& S, RV r, int n, unsigned cell,
+                        const IonC& k, const GridC& g, int* __restrict__ ncount,
+                        long long* __restrict__ acc, uint32_t* __restrict__ dead2,
+                        Rec* __restrict__ ev, uint2* __restrict__ evp,
+                        Counters* dc, Tally& t) {
+  int ne = 0, ni = 0;
+  while (ne < n && ip_sp(r[ne]) == 0u) ++ne;
+  while (ne + ni < n && ip_sp(r[ne + ni]) == 1u) ++ni;
+  const int nn = n - ne - ni;
+  const RV ri = r + ne;
+  const RV rn = r + ne + ni;
+  int used = 0;
+  if (ni > 0)
+    used = ip_electrons(S, r, ne, ri, ni, cell, k, g, ncount, acc, dead2, ev,
+                        evp, dc, t);
+  // Charge exchange of the Cu+ left with the cell's atoms.
+  if (nn > 0)
+    for (int a = used; a < ni; ++a)
+      cx_pair(S, ri[a].val, rn[(a - used) % nn].val, nn, k, g, acc, t);
+}
+
+template <class PT>
+__device__ void flush_tally(const Tally& t, Counters* dc) {
+  if (t.rec) atomicAdd(&dc->f3_rec, t.rec);
+  if (t.cx) atomicAdd(&dc->f3_cx, t.cx);
+  if (t.starved) atomicAdd(&dc->f3_starved, t.starved);
+  if (t.near) atomicAdd(&dc->n_near, t.near);
+}
+
 // ---- grouping ----------------------------------------------------------------
 // Particle t of the joint range (electrons, Cu+, atoms): its key and its
 // index word (species in the top two bits, the array index below them).
@@ -333,13 +499,16 @@ __global__ void __launch_bounds__(kT) k_pg_scatter(
   }
 }
 
-// Per plane: its cells' offsets into off (a global prefix over the
-// tile-major cells), the records of its crowded cells (more than kSmall)
-// into rec unsorted, those cells listed for the workgroup pass, and the
-// records of its cells of 2..kSmall into srt in each cell's (key, id)
-// order.  One wavefront a plane, the small cells ranked in LDS in batches
-// of at most kPCap records; a plane of more than kHot records is listed
-// for the hot-plane passes.
+// Per plane, one wavefront: its cells' offsets into off (a global prefix
+// over the tile-major cells), the records of its crowded cells (more than
+// kSmall) into rec unsorted, those cells listed for the workgroup pass.
+// A plane of at most kPCap records is read once; its small cells (2 to
+// kSmall records) are ranked in LDS and their processes run right there, a
+// cell per lane, on the sorted records in LDS.  A larger plane ranks its
+// small cells in batches into srt and is listed for k_ip_small; a plane of
+// more than kHot records is listed for the hot-plane passes (and
+// k_ip_small).  Four wavefronts per SIMD (128 registers, seven spilled):
+// 1.11 ms against 1.25 at three, at the 128x128x512 workload.
 constexpr int kPCap = 512;
 constexpr int kHot = 4096;
 
@@ -348,6 +517,7 @@ struct PlaneLds {
   unsigned gi[kPCap];
   unsigned char cell[kPCap];
   unsigned short ord[kPCap];      // one-pass plane: cell order -> slot
+  unsigned short perm[kPCap];     // one-pass plane: sorted place -> slot
   unsigned cnt[kPlaneCells];
   unsigned off[kPlaneCells + 1];
   unsigned start[kPlaneCells];    // batch-local first slot of a small cell
@@ -360,21 +530,30 @@ __device__ __forceinline__ bool small_cell(unsigned m) {
 }
 
 template <class PT>
-__global__ void __launch_bounds__(kPlaneCells) k_pg_cells(
+__global__ void __launch_bounds__(kPlaneCells, 4) k_pg_cells(
     Sp3<PT> S, GridC g, const unsigned* __restrict__ poff, long long nplanes,
     const unsigned* __restrict__ pidx, unsigned* __restrict__ off,
     Rec* __restrict__ rec, Rec* __restrict__ srt, unsigned* __restrict__ big,
     unsigned* __restrict__ nbig, long long big_cap, unsigned* __restrict__ hot,
-    unsigned* __restrict__ nhot, unsigned step, unsigned long long seed) {
+    unsigned* __restrict__ nhot, unsigned* __restrict__ rest,
+    unsigned* __restrict__ nrest, IonC k, int* __restrict__ ncount,
+    long long* __restrict__ acc, uint32_t* __restrict__ dead2,
+    Rec* __restrict__ ev, uint2* __restrict__ evp, Counters* dc) {
   __shared__ PlaneLds L;
   const int tid = (int)threadIdx.x;
+  const unsigned step = k.step;
+  const unsigned long long seed = k.seed;
+  Tally t;
 
   for (long long u = plane_first(); u < nplanes; u += gridDim.x) {
     const unsigned base = poff[u];
     const int n = (int)(poff[u + 1] - base);
     const unsigned c0 = (unsigned)u << kPlaneShift;
     if (n > kHot) {
-      if (tid == 0) hot[atomicAdd(nhot, 1u)] = (unsigned)u;
+      if (tid == 0) {
+        hot[atomicAdd(nhot, 1u)] = (unsigned)u;
+        rest[atomicAdd(nrest, 1u)] = (unsigned)u;
+      }
       continue;
     }
     L.cnt[tid] = 0u;
@@ -455,16 +634,26 @@ __global__ void __launch_bounds__(kPlaneCells) k_pg_cells(
             rank += ia < ib;
           }
         }
-        const unsigned gi = L.gi[j];
-        Rec r;
-        r.lo = kp;
-        r.hi = ((c0 + (unsigned)lc) << 2) | (gi >> 30);
-        r.val = gi & kIxMask;
-        srt[base + b + rank] = r;
+        L.perm[b + rank] = (unsigned short)j;
+      }
+      __syncthreads();
+      // The processes of the plane's small cells with a Cu+, a cell per
+      // lane, on the sorted records in LDS.
+      const unsigned mc = L.cnt[tid];
+      if (small_cell(mc)) {
+        LdsRecs r{L.key, L.gi, L.perm, (int)L.off[tid], c0 + tid};
+        bool has_ion = false;
+        for (int j = 0; j < (int)mc; ++j) has_ion = has_ion || ip_sp(r[j]) == 1u;
+        if (has_ion)
+          ip_cell(S, r, (int)mc, cell_of_tile_major(c0 + tid, g), k, g, ncount,
+                  acc, dead2, ev, evp, dc, t);
       }
       __syncthreads();
       continue;
     }
+    // A larger plane: its small cells' records go to srt and k_ip_small
+    // runs them.
+    if (tid == 0) rest[atomicAdd(nrest, 1u)] = (unsigned)u;
     // Crowded cells: records straight into their segments, unsorted.
     if (__ballot(m > (unsigned)kSmall)) {
       L.cur[tid] = L.off[tid];
@@ -545,6 +734,14 @@ __global__ void __launch_bounds__(kPlaneCells) k_pg_cells(
       c_lo = c_hi;
     }
   }
+  // The tallies, summed over the wavefront.
+  for (int o = 32; o > 0; o >>= 1) {
+    t.rec += __shfl_xor(t.rec, o);
+    t.cx += __shfl_xor(t.cx, o);
+    t.starved += __shfl_xor(t.starved, o);
+    t.near += __shfl_xor(t.near, o);
+  }
+  if (tid == 0) flush_tally<PT>(t, dc);
 }
 
 // Planes of more than kHot records (the atoms piled above an evaporating
@@ -755,161 +952,24 @@ __global__ void __launch_bounds__(kT) k_ph_rank(
   }
 }
 
-struct Tally {
-  unsigned long long rec = 0, cx = 0, starved = 0, near = 0;
-};
-
-// Electrons re[0..ne) against the cell's Cu+ ri[0..ni), both in their
-// random order; returns the number of Cu+ taken.
+// Small cells with a Cu+ of the planes the plane pass did not run (more
+// than kPCap records, or hot), one thread each, on the sorted records.  Four
+// wavefronts per SIMD (128 registers, two spilled on rare paths): a chain of
+// gathers per cell wants occupancy, 1039 -> 935 us at the 128x128x512
+// workload; five (30 spilled) ran 1413 us.
 template <class PT>
-__device__ int ip_electrons(const Sp3<PT>& S, const Rec* re, int ne,
-                            const Rec* ri, int ni, unsigned cell,
-                            const IonC& k, const GridC& g,
-                            int* __restrict__ ncount,
-                            long long* __restrict__ acc,
-                            uint32_t* __restrict__ dead2, Rec* __restrict__ ev,
-                            uint2* __restrict__ evp, Counters* dc, Tally& t) {
-  int used = 0;                                     // Cu+ taken by electrons
-  if (ni > 0) {
-    const double dens = (double)ni * k.w_dx3;
-    for (int a = 0; a < ne; ++a) {
-      const unsigned e = re[a].val;
-      double vx, vy, vz;
-      Acc<PT>::vel(S.e, e, vx, vy, vz);
-      const double v2 = (vx * vx + vy * vy) + vz * vz;
-      const double v = sqrt(v2);
-      const double E = (k.half_me * v2) / kE;
-      const double sr = sigma_rec(k, E), si = sigma_ion2(k, E);
-      const double st = sr + si;
-      const double P = 1.0 - exp(-(((dens * st) * v) * k.dt));
-      const unsigned long long eid = S.e.id[e];
-      double u1, u2;
-      uniform2(eid, k.step, kTagEI0, k.seed, u1, u2);
-      const double frac = sr / st;
-      if (fabs(u1 - P) < kNear) t.near += 1;
-      if (!(u1 < P)) continue;
-      if (used >= ni) {
-        t.starved += 1;
-        continue;
-      }
-      if (fabs(u2 - frac) < kNear) t.near += 1;
-      const unsigned ion = ri[used].val;
-      ++used;
-      S.ki[ion] = kDead;
-      if ((long long)ion < k.nb_i) atomicSub(&k.tcnt_i[tile_of(cell, g)], 1u);
-      const unsigned long long d2 = atomicAdd(&dc->n_dead2, 1ull);
-      if (d2 < (unsigned long long)kDeadList) dead2[d2] = ion;
-      if (u2 < frac) {
-        // Recombination: a Cu atom with the ion's position and id and the
-        // pair's centre-of-mass velocity; the electron and the ion leave.
-        const unsigned long long slot = atomicAdd(&dc->n[1], 1ull);
-        if ((long long)slot >= k.cap_n) {
-          atomicOr(&dc->err, kErrCapacity);
-        } else {
-          double ivx, ivy, ivz;
-          Acc<PT>::vel(S.i, ion, ivx, ivy, ivz);
-          const double den = kMcu + kMe;
-          Acc<PT>::copy_pos(S.i, ion, S.n, (long long)slot);
-          Acc<PT>::set_vel(S.n, (long long)slot, (kMcu * ivx + kMe * vx) / den,
-                           (kMcu * ivy + kMe * vy) / den,
-                           (kMcu * ivz + kMe * vz) / den);
-          S.n.id[slot] = S.i.id[ion];
-          S.kn[slot] = cell;
-          atomicAdd(&ncount[cell], 1);
-        }
-        S.ke[e] = kDead;
-        if ((long long)e < k.nb_e) atomicSub(&k.tcnt_e[tile_of(cell, g)], 1u);
-        dep_add(S.e, e, g, acc, 1);
-        dep_add(S.i, ion, g, acc, -1);
-        t.rec += 1;
-      } else {
-        const unsigned long long q = atomicAdd(&dc->f3_ion2, 1ull);
-        if ((long long)q < k.max_ev) {
-          Rec x;
-          x.lo = eid;
-          x.hi = 0u;
-          x.val = (unsigned)q;
-          ev[q] = x;
-          evp[q] = make_uint2(e, ion);
-        } else {
-          atomicOr(&dc->err, kErrEvents);
-        }
-      }
-    }
-  }
-  return used;
-}
-
-// Charge exchange trial of one Cu+ with one atom of its cell (nn atoms).
-template <class PT>
-__device__ void cx_pair(const Sp3<PT>& S, unsigned ion, unsigned at, int nn,
-                        const IonC& k, const GridC& g,
-                        long long* __restrict__ acc, Tally& t) {
-  const double dens = (double)nn * k.w_dx3;
-  const double mr = 0.5 * kMcu;
-  double ix, iy, iz, nx, ny, nz;
-  Acc<PT>::vel(S.i, ion, ix, iy, iz);
-  Acc<PT>::vel(S.n, at, nx, ny, nz);
-  const double ux = ix - nx, uy = iy - ny, uz = iz - nz;
-  const double u2 = (ux * ux + uy * uy) + uz * uz;
-  const double u = sqrt(u2);
-  const double eps = ((0.5 * mr) * u2) / kE;
-  const double P = 1.0 - exp(-(((dens * sigma_cx(k, eps)) * u) * k.dt));
-  double u1, u1b;
-  uniform2(S.i.id[ion], k.step, kTagCX, k.seed, u1, u1b);
-  if (fabs(u1 - P) < kNear) t.near += 1;
-  if (u1 < P) {
-    dep_add(S.i, ion, g, acc, -1);
-    swap_records(S.i, ion, S.n, at);
-    dep_add(S.i, ion, g, acc, 1);
-    t.cx += 1;
-  }
-}
-
-// One small cell's processes on records r[0..n) in (key, id) order:
-// electrons, then Cu+, then atoms.
-template <class PT>
-__device__ void ip_cell(const Sp3<PT>& S, const Rec* r, int n, unsigned cell,
-                        const IonC& k, const GridC& g, int* __restrict__ ncount,
-                        long long* __restrict__ acc, uint32_t* __restrict__ dead2,
-                        Rec* __restrict__ ev, uint2* __restrict__ evp,
-                        Counters* dc, Tally& t) {
-  int ne = 0, ni = 0;
-  while (ne < n && ip_sp(r[ne]) == 0u) ++ne;
-  while (ne + ni < n && ip_sp(r[ne + ni]) == 1u) ++ni;
-  const int nn = n - ne - ni;
-  const Rec* ri = r + ne;
-  const Rec* rn = r + ne + ni;
-  int used = 0;
-  if (ni > 0)
-    used = ip_electrons(S, r, ne, ri, ni, cell, k, g, ncount, acc, dead2, ev,
-                        evp, dc, t);
-  // Charge exchange of the Cu+ left with the cell's atoms.
-  if (nn > 0)
-    for (int a = used; a < ni; ++a)
-      cx_pair(S, ri[a].val, rn[(a - used) % nn].val, nn, k, g, acc, t);
-}
-
-template <class PT>
-__device__ void flush_tally(const Tally& t, Counters* dc) {
-  if (t.rec) atomicAdd(&dc->f3_rec, t.rec);
-  if (t.cx) atomicAdd(&dc->f3_cx, t.cx);
-  if (t.starved) atomicAdd(&dc->f3_starved, t.starved);
-  if (t.near) atomicAdd(&dc->n_near, t.near);
-}
-
-// Small cells with a Cu+, one thread each, on the sorted records.
-template <class PT>
-__global__ void __launch_bounds__(kT) k_ip_small(
-    Sp3<PT> S, const unsigned* __restrict__ off, long long nkeys,
+__global__ void __launch_bounds__(kT, 4) k_ip_small(
+    Sp3<PT> S, const unsigned* __restrict__ off,
+    const unsigned* __restrict__ rest, const unsigned* __restrict__ nrest,
     const Rec* __restrict__ srt, IonC k, GridC g,
     int* __restrict__ ncount, long long* __restrict__ acc,
     uint32_t* __restrict__ dead2, Rec* __restrict__ ev,
     uint2* __restrict__ evp, Counters* dc) {
   Tally t;
-  long long lo, hi;
-  block_range(nkeys, lo, hi);
-  for (long long c = lo + threadIdx.x; c < hi; c += kT) {
+  const long long nt = (long long)*nrest * kPlaneCells;
+  for (long long q = blockIdx.x * (long long)kT + threadIdx.x; q < nt;
+       q += (long long)gridDim.x * kT) {
+    const unsigned c = (rest[q / kPlaneCells] << kPlaneShift) + (unsigned)(q % kPlaneCells);
     const unsigned b = off[c], e = off[c + 1];
     const int n = (int)(e - b);
     if (n < 2 || n > kSmall) continue;
@@ -918,8 +978,8 @@ __global__ void __launch_bounds__(kT) k_ip_small(
     bool has_ion = false;
     for (int j = 0; j < n; ++j) has_ion = has_ion || ip_sp(r[j]) == 1u;
     if (has_ion)
-      ip_cell(S, r, n, cell_of_tile_major((unsigned)c, g), k, g, ncount, acc,
-              dead2, ev, evp, dc, t);
+      ip_cell(S, r, n, cell_of_tile_major(c, g), k, g, ncount, acc, dead2, ev,
+              evp, dc, t);
   }
   flush_tally<PT>(t, dc);
 }
@@ -1237,7 +1297,7 @@ void ionproc_t(pic_ctx* c, double dt) {
   const Sp3<PT> S = sp3<PT>(c);
   const long long np = nc >> kPlaneShift;      // tile planes
   hipMemsetAsync(c->cg_cnt, 0, np * sizeof(unsigned), st);
-  hipMemsetAsync(c->cg_nbig, 0, 2 * sizeof(unsigned), st);   // crowded cells, hot planes
+  hipMemsetAsync(c->cg_nbig, 0, 3 * sizeof(unsigned), st);
   // Grids of a multiple of 8 workgroups (see xcd_block).
   k_pg_count<PT><<<4096, kT, 0, st>>>(S, c->dc, c->g, c->cg_cnt);
   const long long nb = (np + kScanB - 1) / kScanB;
@@ -1247,10 +1307,12 @@ void ionproc_t(pic_ctx* c, double dt) {
   k_ig_scan_apply<<<(unsigned)nb, kScanB, 0, st>>>(c->cg_poff, np, c->cg_bsum);
   k_pg_scatter<PT><<<4096, kT, 0, st>>>(S, c->dc, c->g, c->cg_poff, c->cg_cnt,
                                         c->cg_idx);
+  // Counters: crowded cells, hot planes, planes left to k_ip_small.
   k_pg_cells<PT><<<8192, kPlaneCells, 0, st>>>(
       S, c->g, c->cg_poff, np, c->cg_idx, c->cg_off, c->cg_rec, c->cg_srt,
-      c->cg_big, c->cg_nbig, c->cg_big_cap, c->cg_hot, c->cg_nbig + 1, k.step,
-      k.seed);
+      c->cg_big, c->cg_nbig, c->cg_big_cap, c->cg_hot, c->cg_nbig + 1,
+      c->cg_rest, c->cg_nbig + 2, k, c->ncount, c->acc_next, c->dead2,
+      c->ip_ev, c->ip_evp, c->dc);
   unsigned* nhot = c->cg_nbig + 1;
   k_ph_prep<<<1, 1024, 0, st>>>(c->cg_poff, c->cg_hot, nhot, c->cg_hpre,
                                 c->cg_cnt);
@@ -1264,9 +1326,10 @@ void ionproc_t(pic_ctx* c, double dt) {
                                         c->cg_rec, k.step, k.seed);
   k_ph_rank<PT><<<512, kT, 0, st>>>(S, c->cg_hot, nhot, c->cg_off, c->cg_rec,
                                     c->cg_srt);
-  k_ip_small<PT><<<8192, kT, 0, st>>>(S, c->cg_off, nc, c->cg_srt, k, c->g,
-                                      c->ncount, c->acc_next, c->dead2,
-                                      c->ip_ev, c->ip_evp, c->dc);
+  k_ip_small<PT><<<512, kT, 0, st>>>(S, c->cg_off, c->cg_rest, c->cg_nbig + 2,
+                                     c->cg_srt, k, c->g, c->ncount,
+                                     c->acc_next, c->dead2, c->ip_ev,
+                                     c->ip_evp, c->dc);
   k_ip_big<PT><<<512, kT, 0, st>>>(S, c->cg_off, c->cg_rec, c->cg_big,
                                    c->cg_nbig, c->cg_big_cap, k, c->g,
                                    c->ncount, c->acc_next, c->dead2, c->ip_ev,

@@ -200,7 +200,7 @@ size_t carve(pic_ctx* c, char* base) {
   c->dc = cv.take<Counters>(1);
   c->cg_cnt = c->cg_off = c->cg_bsum = c->cg_big = c->cg_nbig = nullptr;
   c->cg_rec = c->cg_srt = nullptr;
-  c->cg_idx = c->cg_poff = c->cg_hot = c->cg_hpre = nullptr;
+  c->cg_idx = c->cg_poff = c->cg_hot = c->cg_hpre = c->cg_rest = nullptr;
   c->cg_work_cap = 0;
   c->ip_ev = nullptr;
   c->ip_evp = nullptr;
@@ -221,6 +221,7 @@ size_t carve(pic_ctx* c, char* base) {
     c->cg_poff = cv.take<unsigned>(c->cg_nkeys / (kTile * kTile) + 1);
     c->cg_hot = cv.take<unsigned>(c->cg_nkeys / (kTile * kTile));
     c->cg_hpre = cv.take<unsigned>(c->cg_nkeys / (kTile * kTile) + 1);
+    c->cg_rest = cv.take<unsigned>(c->cg_nkeys / (kTile * kTile));
     c->ip_ev = cv.take<Rec>(c->ev_cap_p2);
     c->ip_evp = cv.take<uint2>(c->ev_cap_p2);
   }

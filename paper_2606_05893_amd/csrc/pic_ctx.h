@@ -145,6 +145,7 @@ struct pic_ctx {
   unsigned* cg_poff;                // tile planes' offsets into cg_idx
   unsigned* cg_hot;                 // planes of many records (ion processes)
   unsigned* cg_hpre;                // their sizes prefixed
+  unsigned* cg_rest;                // planes whose small cells k_ip_small runs
   long long cg_big_cap;
   long long cg_nkeys;               // tile-major cell numbers (tiles x 512)
   // Recombination, Cu+ ionisation, charge exchange: settings and the listed
