@@ -7,9 +7,9 @@
   takes cos(2 pi u) and the azimuth's sine and cosine from cospi and
   sincospi, which round differently from the oracle's cos and sin).
 * Crowded cells: a few hundred electrons against a hundred ions (long
-  electron-ion chains), two cells of several hundred in one half tile (its
-  particles loaded in batches of whole cells), and a cell of 1500 (sorted
-  alone, the electron-ion sequence in rounds): the same.
+  electron-ion chains), cells of several hundred to 1500 (sorted alone, the
+  electron-ion sequence in rounds), and three cells of 120 in one tile
+  plane (the plane loaded in batches of whole cells): the same.
 * A cell with more charged particles than a workgroup sorts is reported
   (PIC_ERR_CAPACITY).
 * Mixed precision follows the oracle to FP32 precision.
@@ -106,11 +106,15 @@ def test_coulomb_advance_bit_level_and_crowded_cells(gpu_lib):
     pi_.append(rng.random((4000, 3)) * [g.lx, g.ly, g.lz])
     vi.append(rng.standard_normal((4000, 3)) * 2e3)
     # Crowded cells: (electrons, ions) = (16, 0), (9, 8), (300, 100),
-    # (40, 130); (600, 300) and (500, 200) in one half tile; (1100, 400).
+    # (40, 130), (600, 300), (500, 200), (1100, 400) (cells of more than
+    # one LDS batch); three cells of 120 in one tile plane (the plane served
+    # in batches of whole cells).
     for (ne, ni), cell in zip(((16, 0), (9, 8), (300, 100), (40, 130),
-                               (600, 300), (500, 200), (1100, 400)),
+                               (600, 300), (500, 200), (1100, 400),
+                               (80, 40), (70, 50), (60, 60)),
                               ((2, 3, 4), (7, 7, 7), (10, 1, 12), (5, 14, 3),
-                               (1, 1, 1), (2, 2, 2), (12, 12, 12))):
+                               (1, 1, 1), (2, 2, 2), (12, 12, 12),
+                               (9, 9, 3), (10, 9, 3), (11, 9, 3))):
         lo = np.array(cell) * p["dx"]
         pe.append(lo + rng.random((ne, 3)) * p["dx"])
         ve.append(rng.standard_normal((ne, 3)) * 1e6)
