@@ -510,8 +510,13 @@ __device__ void batch_collide(const Sp2<PT>& S, int c_lo, int c_hi, int nb,
     const int t = s ? r - b - ne : r - b;
     const int K = ne > ni ? ne : ni, mm = ne < ni ? ne : ni;
     const double dens = (double)mm * k.w_dx3;
+    // Collision j pairs electron j mod N_e with ion j mod N_i; along the
+    // chain (j = t, t + m, ...) the smaller group's index is t and the
+    // larger group's is j itself (j < K).
+    const bool e_small = ne <= ni;
     for (int j = t; j < K; j += mm) {
-      const int pa = L.perm[b + j % ne], pb = L.perm[b + ne + j % ni];
+      const int pa = L.perm[b + (e_small ? t : j)];
+      const int pb = L.perm[b + ne + (e_small ? j : t)];
       const unsigned long long idc = ne >= ni ? L.id[pa] : L.id[pb];
       collide_lds(L, pa, pb, 2, dens, false, idc, kTagDeltaEI, kTagPhiEI, k);
       nei += 1;
