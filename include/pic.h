@@ -65,9 +65,9 @@ enum { PIC_ION_LOTZ = 0, PIC_ION_CONST = 1 };
  * by cell each step (36 bytes per particle of capacity of electrons, Cu
  * and Cu+ together, and about 8 per cell), needed by the Coulomb
  * collisions (pic_set_coulomb) and the ion processes
- * (pic_set_ion_processes); the grid must then have fewer than 2^30 cells,
- * each of those three capacities must be below 2^30 and together they
- * must sum to at most 0xFFFFFFF0 (else PIC_ERR_ARG).
+ * (pic_set_ion_processes); the grid must then have fewer than 2^30 cells
+ * and those three capacities must sum to at most 0xFFFFFFF0 (else
+ * PIC_ERR_ARG).
  * PIC_FLAG_PLAIN_SMOOTHER: smooth with one launch per colour and sweep
  * instead of the fused two-sweep pass (same arithmetic, same results).
  * PIC_FLAG_MG_ALL_LEVELS: run the V-cycle down to the coarsest level

@@ -75,6 +75,24 @@ __device__ __forceinline__ int ghash_slot(unsigned* hk, unsigned key) {
   return -1;
 }
 
+// Index words of the grouping passes: a particle's position in the range of
+// the grouped species taken one after another (electrons, then Cu+, then Cu
+// atoms), read back with the species counts at grouping time, which the
+// passes leave unchanged until their commits.
+struct JointIx {
+  unsigned n0, n1;                  // electrons, Cu+
+  __device__ __forceinline__ unsigned sp(unsigned t) const {
+    return t < n0 ? 0u : (t - n0 < n1 ? 1u : 2u);
+  }
+  __device__ __forceinline__ unsigned ix(unsigned t) const {
+    return t < n0 ? t : (t - n0 < n1 ? t - n0 : t - n0 - n1);
+  }
+};
+
+__device__ __forceinline__ JointIx joint_ix(const Counters* dc) {
+  return JointIx{(unsigned)dc->n[0], (unsigned)dc->n[2]};
+}
+
 // Binning by plane: a plane is one z layer of a tile (8x8 cells, 64
 // consecutive tile-major numbers).  Particles binned by tile fall into few
 // planes per chunk, so a chunk's planes are counted in a small LDS table and

@@ -42,7 +42,6 @@ constexpr int kCoulBigCell = 2048;    // particles a crowded cell may hold
 constexpr unsigned long long kSpBit = 1ull << 63;
 constexpr int kScanB = 1024;          // counts per scan block
 constexpr int kCap = 184;             // particles of one LDS batch
-constexpr unsigned kIdxMask = 0x7FFFFFFFu;
 
 enum : uint32_t {
   kTagOrder = 20, kTagDelta = 21, kTagPhi = 22, kTagDeltaEI = 23, kTagPhiEI = 24
@@ -168,17 +167,13 @@ __device__ void collide(const Sp2<PT>& S, int sa, unsigned a, int sb,
 
 // ---- binning of the charged particles' indices by plane ---------------------
 // Charged particle t of the joint range (electrons, then ions): its key, and
-// its index word (species in the top bit, the array index below it).
+// its index word t.
 __device__ __forceinline__ uint32_t charged_key(const uint32_t* __restrict__ ke,
                                                 const uint32_t* __restrict__ ki,
                                                 long long ne, long long t,
                                                 unsigned& gi) {
-  if (t < ne) {
-    gi = (unsigned)t;
-    return ke[t];
-  }
-  gi = (1u << 31) | (unsigned)(t - ne);
-  return ki[t - ne];
+  gi = (unsigned)t;
+  return t < ne ? ke[t] : ki[t - ne];
 }
 
 // Live charged particles per plane.
@@ -331,7 +326,7 @@ struct BatchLds {
   unsigned long long key[kCap];   // species bit above the order draw
   unsigned long long id[kCap];
   double v[3][kCap];
-  unsigned gi[kCap];              // index word
+  unsigned gi[kCap];              // index word (joint range)
   unsigned short cell[kCap];      // cell in the plane
   unsigned short perm[kCap];      // sorted place -> slot
   unsigned short work[kCap];      // cell order -> slot, then the work items
@@ -366,10 +361,11 @@ __device__ __forceinline__ void collide_lds(BatchLds& L, int a, int b, int ty,
 
 // One particle of the plane into slot p of the batch (not yet its key).
 template <class PT>
-__device__ __forceinline__ void load_slot(const Sp2<PT>& S, BatchLds& L, int p,
-                                          unsigned gi, int lc) {
-  const int s = (int)(gi >> 31);
-  const unsigned i = gi & kIdxMask;
+__device__ __forceinline__ void load_slot(const Sp2<PT>& S, const JointIx& J,
+                                          BatchLds& L, int p, unsigned gi,
+                                          int lc) {
+  const int s = (int)J.sp(gi);
+  const unsigned i = J.ix(gi);
   double vx, vy, vz;
   get_v(S, s, i, vx, vy, vz);
   L.id[p] = S.p[s].id[i];
@@ -411,7 +407,8 @@ __device__ __forceinline__ void place_work(const BatchLds& L, const PlaneLdsC& U
 // [0, nb): cell order, ranks, work lists, the collisions, the velocities
 // back to the particle arrays.
 template <class PT>
-__device__ void batch_collide(const Sp2<PT>& S, int c_lo, int c_hi, int nb,
+__device__ void batch_collide(const Sp2<PT>& S, const JointIx& J, int c_lo,
+                              int c_hi, int nb,
                               BatchLds& L, PlaneLdsC& U, const CoulC& k,
                               unsigned long long& nl,
                               unsigned long long& nei) {
@@ -426,7 +423,7 @@ __device__ void batch_collide(const Sp2<PT>& S, int c_lo, int c_hi, int nb,
     L.work[atomicAdd(&U.cur[lc], 1u)] = (unsigned short)p;
     if (U.off[lc + 1] - U.off[lc] >= 2u) {
       const unsigned gi = L.gi[p];
-      L.key[p] = (gi >> 31 ? kSpBit : 0ull) | order_key(L.id[p], k.step, k.seed);
+      L.key[p] = (J.sp(gi) ? kSpBit : 0ull) | order_key(L.id[p], k.step, k.seed);
     }
   }
   __syncthreads();
@@ -485,7 +482,7 @@ __device__ void batch_collide(const Sp2<PT>& S, int c_lo, int c_hi, int nb,
     const int lc = L.cell[p];
     const int m = (int)(U.off[lc + 1] - U.off[lc]);
     const int ne = U.ne[lc];
-    const int s = (int)(L.gi[p] >> 31);
+    const int s = (int)J.sp(L.gi[p]);
     const int N = s ? m - ne : ne;
     const bool trip = w >= n_pair;
     const double dens = (double)N * k.w_dx3;
@@ -506,7 +503,7 @@ __device__ void batch_collide(const Sp2<PT>& S, int c_lo, int c_hi, int nb,
     const int lc = L.cell[p];
     const int b = (int)(U.off[lc] - ob), m = (int)(U.off[lc + 1] - U.off[lc]);
     const int ne = U.ne[lc], ni = m - ne;
-    const int s = (int)(L.gi[p] >> 31);
+    const int s = (int)J.sp(L.gi[p]);
     const int t = s ? r - b - ne : r - b;
     const int K = ne > ni ? ne : ni, mm = ne < ni ? ne : ni;
     const double dens = (double)mm * k.w_dx3;
@@ -527,7 +524,7 @@ __device__ void batch_collide(const Sp2<PT>& S, int c_lo, int c_hi, int nb,
     const int lc = L.cell[p];
     if (U.off[lc + 1] - U.off[lc] < 2u) continue;
     const unsigned gi = L.gi[p];
-    set_v(S, (int)(gi >> 31), gi & kIdxMask, L.v[0][p], L.v[1][p], L.v[2][p]);
+    set_v(S, (int)J.sp(gi), J.ix(gi), L.v[0][p], L.v[1][p], L.v[2][p]);
   }
   __syncthreads();
 }
@@ -546,6 +543,7 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
   __shared__ BatchLds L;
   __shared__ PlaneLdsC U;
   const int tid = (int)threadIdx.x;
+  const JointIx J = joint_ix(dc);
   unsigned long long nl = 0, nei = 0;
   for (long long u = plane_first(); u < nplanes; u += gridDim.x) {
     const unsigned base = uoff[u];
@@ -556,10 +554,10 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
     const bool one = n <= kCap;
     for (int j = tid; j < n; j += kCT) {
       const unsigned gi = uidx[base + j];
-      const uint32_t c0 = (gi >> 31) ? ki[gi & kIdxMask] : ke[gi];
+      const uint32_t c0 = J.sp(gi) ? ki[J.ix(gi)] : ke[gi];
       const int lc = (int)(tile_major(c0, g) & (kPlaneCells - 1));
       atomicAdd(&U.cur[lc], 1u);
-      if (one) load_slot(S, L, j, gi, lc);
+      if (one) load_slot(S, J, L, j, gi, lc);
     }
     __syncthreads();
     {
@@ -575,7 +573,7 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
     }
     __syncthreads();
     if (one) {
-      batch_collide(S, 0, kPlaneCells, n, L, U, k, nl, nei);
+      batch_collide(S, J, 0, kPlaneCells, n, L, U, k, nl, nei);
       continue;
     }
     // Batches of whole cells of at most kCap particles.
@@ -602,12 +600,12 @@ __global__ void __launch_bounds__(kCT, 4) k_cu_cells(
       } else if (nb >= 2) {
         for (int j = tid; j < n; j += kCT) {
           const unsigned gi = uidx[base + j];
-          const uint32_t c0 = (gi >> 31) ? ki[gi & kIdxMask] : ke[gi];
+          const uint32_t c0 = J.sp(gi) ? ki[J.ix(gi)] : ke[gi];
           const int lc = (int)(tile_major(c0, g) & (kPlaneCells - 1));
-          if (lc >= c_lo && lc < c_hi) load_slot(S, L, atomicAdd(&U.nslot, 1), gi, lc);
+          if (lc >= c_lo && lc < c_hi) load_slot(S, J, L, atomicAdd(&U.nslot, 1), gi, lc);
         }
         __syncthreads();
-        batch_collide(S, c_lo, c_hi, nb, L, U, k, nl, nei);
+        batch_collide(S, J, c_lo, c_hi, nb, L, U, k, nl, nei);
       }
       __syncthreads();
       c_lo = c_hi;
@@ -639,6 +637,7 @@ __global__ void __launch_bounds__(kT) k_cu_crowd(
   __shared__ unsigned sgi[kCoulBigCell];
   __shared__ int s_m, s_ne;
   const int tid = (int)threadIdx.x;
+  const JointIx J = joint_ix(dc);
   long long nlist = (long long)*ncrowd;
   if (nlist > crowd_cap) nlist = crowd_cap;
   unsigned long long nl = 0, nei = 0;
@@ -652,8 +651,8 @@ __global__ void __launch_bounds__(kT) k_cu_crowd(
     __syncthreads();
     for (int j = tid; j < n; j += kT) {
       const unsigned gi = uidx[base + j];
-      const int s = (int)(gi >> 31);
-      const unsigned i = gi & kIdxMask;
+      const int s = (int)J.sp(gi);
+      const unsigned i = J.ix(gi);
       const uint32_t c0 = s ? ki[i] : ke[i];
       if ((int)(tile_major(c0, g) & (kPlaneCells - 1)) != lc) continue;
       const int p = atomicAdd(&s_m, 1);
@@ -695,7 +694,7 @@ __global__ void __launch_bounds__(kT) k_cu_crowd(
     }
     if (tid == 0) {
       // Equal keys (practically never) in id order, and the species split.
-      auto id_of = [&](unsigned gi) { return S.p[gi >> 31].id[gi & kIdxMask]; };
+      auto id_of = [&](unsigned gi) { return S.p[J.sp(gi)].id[J.ix(gi)]; };
       for (int j = 1; j < m; ++j) {
         int x = j;
         while (x > 0 && skey[x] == skey[x - 1] && id_of(sgi[x]) < id_of(sgi[x - 1])) {
@@ -718,15 +717,15 @@ __global__ void __launch_bounds__(kT) k_cu_crowd(
       const int start = (N & 1) ? 3 : 0;
       const PT& P = S.p[s];
       if (start && tid == 0) {
-        const unsigned a = sgi[b0] & kIdxMask, bb = sgi[b0 + 1] & kIdxMask,
-                       cc = sgi[b0 + 2] & kIdxMask;
+        const unsigned a = J.ix(sgi[b0]), bb = J.ix(sgi[b0 + 1]),
+                       cc = J.ix(sgi[b0 + 2]);
         collide(S, s, a, s, bb, dens, true, P.id[a], kTagDelta, kTagPhi, k);
         collide(S, s, bb, s, cc, dens, true, P.id[bb], kTagDelta, kTagPhi, k);
         collide(S, s, cc, s, a, dens, true, P.id[cc], kTagDelta, kTagPhi, k);
         nl += 3;
       }
       for (int j = start + 2 * tid; j + 1 < N; j += 2 * kT) {
-        const unsigned a = sgi[b0 + j] & kIdxMask, bb = sgi[b0 + j + 1] & kIdxMask;
+        const unsigned a = J.ix(sgi[b0 + j]), bb = J.ix(sgi[b0 + j + 1]);
         collide(S, s, a, s, bb, dens, false, P.id[a], kTagDelta, kTagPhi, k);
         nl += 1;
       }
@@ -739,7 +738,7 @@ __global__ void __launch_bounds__(kT) k_cu_crowd(
       for (int r0 = 0; r0 < K; r0 += Ns) {
         const int r1 = r0 + Ns < K ? r0 + Ns : K;
         for (int j = r0 + tid; j < r1; j += kT) {
-          const unsigned a = sgi[j % ne] & kIdxMask, bb = sgi[ne + j % ni] & kIdxMask;
+          const unsigned a = J.ix(sgi[j % ne]), bb = J.ix(sgi[ne + j % ni]);
           const unsigned long long idc = ne >= ni ? S.p[0].id[a] : S.p[1].id[bb];
           collide(S, 0, a, 1, bb, dens, false, idc, kTagDeltaEI, kTagPhiEI, k);
         }

@@ -158,8 +158,8 @@ __device__ void swap_records<PartsM>(const PartsM& a, unsigned i,
 // A cell's records in (key, id) order as a plane pass holds them in LDS:
 // the keys and index words by slot, the sorted places' slots in perm.
 struct LdsRecs {
-  const unsigned long long* key;
-  const unsigned* gi;
+  const unsigned long long* key;    // species in the top two bits
+  const unsigned* ix;               // array indices
   const unsigned short* perm;
   int b;                            // the cell's first place
   unsigned cell;                    // its tile-major number
@@ -167,8 +167,8 @@ struct LdsRecs {
     const int p = perm[b + j];
     Rec r;
     r.lo = key[p];
-    r.hi = (cell << 2) | (gi[p] >> 30);
-    r.val = gi[p] & 0x3FFFFFFFu;
+    r.hi = (cell << 2) | (unsigned)(key[p] >> 62);
+    r.val = ix[p];
     return r;
   }
   __device__ LdsRecs operator+(int d) const {
@@ -323,44 +323,48 @@ __device__ void flush_tally(const Tally& t, Counters* dc) {
 
 // ---- grouping ----------------------------------------------------------------
 // Particle t of the joint range (electrons, Cu+, atoms): its key and its
-// index word (species in the top two bits, the array index below them).
-constexpr unsigned kIxMask = 0x3FFFFFFFu;
+// index word t.
 
 template <class PT>
 __device__ __forceinline__ uint32_t joint_key(const Sp3<PT>& S, long long ne,
                                               long long ni, long long t,
                                               unsigned& gi) {
-  if (t < ne) {
-    gi = (unsigned)t;
-    return S.ke[t];
-  }
-  if (t < ne + ni) {
-    gi = (1u << 30) | (unsigned)(t - ne);
-    return S.ki[t - ne];
-  }
-  gi = (2u << 30) | (unsigned)(t - ne - ni);
+  gi = (unsigned)t;
+  if (t < ne) return S.ke[t];
+  if (t < ne + ni) return S.ki[t - ne];
   return S.kn[t - ne - ni];
 }
 
 template <class PT>
-__device__ __forceinline__ uint32_t key_of(const Sp3<PT>& S, unsigned gi) {
-  const unsigned s = gi >> 30, i = gi & kIxMask;
+__device__ __forceinline__ uint32_t key_of(const Sp3<PT>& S, const JointIx& J,
+                                           unsigned gi) {
+  const unsigned s = J.sp(gi), i = J.ix(gi);
   return s == 0 ? S.ke[i] : (s == 1 ? S.ki[i] : S.kn[i]);
 }
 
 // The sort record of a particle: species above its order draw; its
 // tile-major cell above the species; its index.
 template <class PT>
-__device__ __forceinline__ Rec make_rec(const Sp3<PT>& S, unsigned gi,
-                                        unsigned cell, unsigned step,
-                                        unsigned long long seed) {
-  const unsigned s = gi >> 30, i = gi & kIxMask;
+__device__ __forceinline__ Rec make_rec(const Sp3<PT>& S, const JointIx& J,
+                                        unsigned gi, unsigned cell,
+                                        unsigned step, unsigned long long seed) {
+  const unsigned s = J.sp(gi), i = J.ix(gi);
   const unsigned long long id = s == 0 ? S.e.id[i] : (s == 1 ? S.i.id[i] : S.n.id[i]);
   Rec r;
   r.lo = ((unsigned long long)s << 62) | ord_key(id, step, seed);
   r.hi = (cell << 2) | s;
   r.val = i;
   return r;
+}
+
+// The id of a particle given its sort key (species in the top two bits)
+// and its array index.
+template <class PT>
+__device__ __forceinline__ unsigned long long key_id(const Sp3<PT>& S,
+                                                     unsigned long long key,
+                                                     unsigned i) {
+  const unsigned s = (unsigned)(key >> 62);
+  return s == 0 ? S.e.id[i] : (s == 1 ? S.i.id[i] : S.n.id[i]);
 }
 
 // Live particles per plane.
@@ -514,7 +518,7 @@ constexpr int kHot = 4096;
 
 struct PlaneLds {
   unsigned long long key[kPCap];
-  unsigned gi[kPCap];
+  unsigned gi[kPCap];             // array indices (the species is in key)
   unsigned char cell[kPCap];
   unsigned short ord[kPCap];      // one-pass plane: cell order -> slot
   unsigned short perm[kPCap];     // one-pass plane: sorted place -> slot
@@ -549,6 +553,8 @@ __global__ void __launch_bounds__(kPlaneCells, 4) k_pg_cells(
     const unsigned base = poff[u];
     const int n = (int)(poff[u + 1] - base);
     const unsigned c0 = (unsigned)u << kPlaneShift;
+    // (Read per plane, so that it is not held through the processes.)
+    const JointIx J = joint_ix(dc);
     if (n > kHot) {
       if (tid == 0) {
         hot[atomicAdd(nhot, 1u)] = (unsigned)u;
@@ -563,12 +569,12 @@ __global__ void __launch_bounds__(kPlaneCells, 4) k_pg_cells(
     const bool one = n <= kPCap;
     for (int j = tid; j < n; j += kPlaneCells) {
       const unsigned gi = pidx[base + j];
-      const unsigned c = tile_major(key_of(S, gi), g);
+      const unsigned c = tile_major(key_of(S, J, gi), g);
       const int lc = (int)(c & (kPlaneCells - 1));
       atomicAdd(&L.cnt[lc], 1u);
       if (one) {
-        L.key[j] = make_rec(S, gi, c, step, seed).lo;
-        L.gi[j] = gi;
+        L.key[j] = make_rec(S, J, gi, c, step, seed).lo;
+        L.gi[j] = J.ix(gi);
         L.cell[j] = (unsigned char)lc;
       }
     }
@@ -600,14 +606,13 @@ __global__ void __launch_bounds__(kPlaneCells, 4) k_pg_cells(
       for (int j = tid; j < n; j += kPlaneCells) {
         const int lc = L.cell[j];
         const unsigned mc = L.cnt[lc];
-        const unsigned gi = L.gi[j];
         const unsigned x = atomicAdd(&L.cur[lc], 1u);
         L.ord[x] = (unsigned short)j;
         if (mc > (unsigned)kSmall) {
           Rec r;
           r.lo = L.key[j];
-          r.hi = ((c0 + (unsigned)lc) << 2) | (gi >> 30);
-          r.val = gi & kIxMask;
+          r.hi = ((c0 + (unsigned)lc) << 2) | (unsigned)(L.key[j] >> 62);
+          r.val = L.gi[j];
           rec[base + x] = r;
         }
       }
@@ -625,13 +630,7 @@ __global__ void __launch_bounds__(kPlaneCells, 4) k_pg_cells(
           if (ky < kp) {
             ++rank;
           } else if (ky == kp && o != j) {
-            const unsigned ga = L.gi[o], gb = L.gi[j];
-            const unsigned sa = ga >> 30, sb = gb >> 30;
-            const unsigned long long ia =
-                sa == 0 ? S.e.id[ga & kIxMask] : (sa == 1 ? S.i.id[ga & kIxMask] : S.n.id[ga & kIxMask]);
-            const unsigned long long ib =
-                sb == 0 ? S.e.id[gb & kIxMask] : (sb == 1 ? S.i.id[gb & kIxMask] : S.n.id[gb & kIxMask]);
-            rank += ia < ib;
+            rank += key_id(S, L.key[o], L.gi[o]) < key_id(S, kp, L.gi[j]);
           }
         }
         L.perm[b + rank] = (unsigned short)j;
@@ -664,10 +663,10 @@ __global__ void __launch_bounds__(kPlaneCells, 4) k_pg_cells(
       __syncthreads();
       for (int j = tid; j < n; j += kPlaneCells) {
         const unsigned gi = pidx[base + j];
-        const unsigned c = tile_major(key_of(S, gi), g);
+        const unsigned c = tile_major(key_of(S, J, gi), g);
         const int lc = (int)(c & (kPlaneCells - 1));
         if (L.cnt[lc] > (unsigned)kSmall)
-          rec[base + atomicAdd(&L.cur[lc], 1u)] = make_rec(S, gi, c, step, seed);
+          rec[base + atomicAdd(&L.cur[lc], 1u)] = make_rec(S, J, gi, c, step, seed);
       }
       __syncthreads();
     }
@@ -692,13 +691,13 @@ __global__ void __launch_bounds__(kPlaneCells, 4) k_pg_cells(
       if (nb > 0) {
         for (int j = tid; j < n; j += kPlaneCells) {
           const unsigned gi = pidx[base + j];
-          const uint32_t kc = key_of(S, gi);
+          const uint32_t kc = key_of(S, J, gi);
           const int lc = (int)(tile_major(kc, g) & (kPlaneCells - 1));
           if (lc < c_lo || lc >= c_hi || !small_cell(L.cnt[lc])) continue;
           const int p = (int)atomicAdd(&L.cur[lc], 1u);
-          const Rec r = make_rec(S, gi, c0 + lc, step, seed);
+          const Rec r = make_rec(S, J, gi, c0 + lc, step, seed);
           L.key[p] = r.lo;
-          L.gi[p] = gi;
+          L.gi[p] = J.ix(gi);
           L.cell[p] = (unsigned char)lc;
         }
         __syncthreads();
@@ -713,20 +712,13 @@ __global__ void __launch_bounds__(kPlaneCells, 4) k_pg_cells(
               ++rank;
             } else if (kq == kp && q != p) {
               // Equal draws (practically never): id order.
-              const unsigned ga = L.gi[q], gb = L.gi[p];
-              const unsigned sa = ga >> 30, sb = gb >> 30;
-              const unsigned long long ia =
-                  sa == 0 ? S.e.id[ga & kIxMask] : (sa == 1 ? S.i.id[ga & kIxMask] : S.n.id[ga & kIxMask]);
-              const unsigned long long ib =
-                  sb == 0 ? S.e.id[gb & kIxMask] : (sb == 1 ? S.i.id[gb & kIxMask] : S.n.id[gb & kIxMask]);
-              rank += ia < ib;
+              rank += key_id(S, kq, L.gi[q]) < key_id(S, kp, L.gi[p]);
             }
           }
-          const unsigned gi = L.gi[p];
           Rec r;
           r.lo = kp;
-          r.hi = ((c0 + (unsigned)lc) << 2) | (gi >> 30);
-          r.val = gi & kIxMask;
+          r.hi = ((c0 + (unsigned)lc) << 2) | (unsigned)(kp >> 62);
+          r.val = L.gi[p];
           srt[base + L.off[lc] + rank] = r;
         }
       }
@@ -796,7 +788,8 @@ __device__ __forceinline__ int hot_plane(const unsigned* __restrict__ hpre,
 
 // Record t of the hot range: its index word and its cell in the plane.
 template <class PT>
-__device__ __forceinline__ void hot_rec(const Sp3<PT>& S, const GridC& g,
+__device__ __forceinline__ void hot_rec(const Sp3<PT>& S, const JointIx& J,
+                                        const GridC& g,
                                         const unsigned* __restrict__ poff,
                                         const unsigned* __restrict__ hot,
                                         const unsigned* __restrict__ hpre,
@@ -805,7 +798,7 @@ __device__ __forceinline__ void hot_rec(const Sp3<PT>& S, const GridC& g,
                                         unsigned& gi, unsigned& c) {
   h = hot_plane(hpre, nh, t);
   gi = pidx[poff[hot[h]] + (t - hpre[h])];
-  c = tile_major(key_of(S, gi), g);
+  c = tile_major(key_of(S, J, gi), g);
 }
 
 template <class PT>
@@ -813,9 +806,10 @@ __global__ void __launch_bounds__(kT) k_ph_count(
     Sp3<PT> S, GridC g, const unsigned* __restrict__ poff,
     const unsigned* __restrict__ hot, const unsigned* __restrict__ nhot,
     const unsigned* __restrict__ hpre, const unsigned* __restrict__ pidx,
-    unsigned* __restrict__ hcnt) {
+    unsigned* __restrict__ hcnt, const Counters* dc) {
   __shared__ unsigned hk[kPHash];
   __shared__ unsigned hc[kPHash];
+  const JointIx J = joint_ix(dc);
   const int nh = (int)*nhot;
   if (nh == 0) return;
   const unsigned tot = hpre[nh];
@@ -830,7 +824,7 @@ __global__ void __launch_bounds__(kT) k_ph_count(
     for (unsigned t = b + threadIdx.x; t < e; t += kT) {
       int h;
       unsigned gi, c;
-      hot_rec(S, g, poff, hot, hpre, pidx, nh, t, h, gi, c);
+      hot_rec(S, J, g, poff, hot, hpre, pidx, nh, t, h, gi, c);
       const unsigned key = (unsigned)h * kPlaneCells + (c & (kPlaneCells - 1));
       const int q = plane_slot(hk, key);
       if (q >= 0)
@@ -880,10 +874,11 @@ __global__ void __launch_bounds__(kT) k_ph_scatter(
     const unsigned* __restrict__ hot, const unsigned* __restrict__ nhot,
     const unsigned* __restrict__ hpre, const unsigned* __restrict__ pidx,
     unsigned* __restrict__ hcnt, Rec* __restrict__ rec, unsigned step,
-    unsigned long long seed) {
+    unsigned long long seed, const Counters* dc) {
   __shared__ unsigned hk[kPHash];
   __shared__ unsigned hc[kPHash];
   __shared__ unsigned hb[kPHash];
+  const JointIx J = joint_ix(dc);
   const int nh = (int)*nhot;
   if (nh == 0) return;
   const unsigned tot = hpre[nh];
@@ -898,7 +893,7 @@ __global__ void __launch_bounds__(kT) k_ph_scatter(
     for (unsigned t = b + threadIdx.x; t < e; t += kT) {
       int h;
       unsigned gi, c;
-      hot_rec(S, g, poff, hot, hpre, pidx, nh, t, h, gi, c);
+      hot_rec(S, J, g, poff, hot, hpre, pidx, nh, t, h, gi, c);
       const int q = plane_slot(hk, (unsigned)h * kPlaneCells + (c & (kPlaneCells - 1)));
       if (q >= 0) atomicAdd(&hc[q], 1u);
     }
@@ -914,13 +909,13 @@ __global__ void __launch_bounds__(kT) k_ph_scatter(
     for (unsigned t = b + threadIdx.x; t < e; t += kT) {
       int h;
       unsigned gi, c;
-      hot_rec(S, g, poff, hot, hpre, pidx, nh, t, h, gi, c);
+      hot_rec(S, J, g, poff, hot, hpre, pidx, nh, t, h, gi, c);
       const unsigned key = (unsigned)h * kPlaneCells + (c & (kPlaneCells - 1));
       // The table is unchanged since the count (see k_cu_scatter).
       const int q = plane_slot(hk, key);
       const unsigned slot = q >= 0 ? hb[q] + atomicAdd(&hc[q], 1u)
                                    : poff[hot[h]] + atomicAdd(&hcnt[key], 1u);
-      rec[slot] = make_rec(S, gi, c, step, seed);
+      rec[slot] = make_rec(S, J, gi, c, step, seed);
     }
     __syncthreads();
   }
@@ -1317,13 +1312,13 @@ void ionproc_t(pic_ctx* c, double dt) {
   k_ph_prep<<<1, 1024, 0, st>>>(c->cg_poff, c->cg_hot, nhot, c->cg_hpre,
                                 c->cg_cnt);
   k_ph_count<PT><<<1024, kT, 0, st>>>(S, c->g, c->cg_poff, c->cg_hot, nhot,
-                                      c->cg_hpre, c->cg_idx, c->cg_cnt);
+                                      c->cg_hpre, c->cg_idx, c->cg_cnt, c->dc);
   k_ph_off<<<512, kPlaneCells, 0, st>>>(c->cg_poff, np, c->cg_hot, nhot,
                                         c->cg_cnt, c->cg_off, c->cg_big,
                                         c->cg_nbig, c->cg_big_cap);
   k_ph_scatter<PT><<<1024, kT, 0, st>>>(S, c->g, c->cg_poff, c->cg_hot, nhot,
                                         c->cg_hpre, c->cg_idx, c->cg_cnt,
-                                        c->cg_rec, k.step, k.seed);
+                                        c->cg_rec, k.step, k.seed, c->dc);
   k_ph_rank<PT><<<512, kT, 0, st>>>(S, c->cg_hot, nhot, c->cg_off, c->cg_rec,
                                     c->cg_srt);
   k_ip_small<PT><<<512, kT, 0, st>>>(S, c->cg_off, c->cg_rest, c->cg_nbig + 2,

@@ -103,12 +103,10 @@ pic_status validate(const pic_config* c) {
       (long long)((c->nx + 7) / 8) * ((c->ny + 7) / 8) * ((c->nz + 7) / 8) * 512 >=
           (1ll << 30))
     return PIC_ERR_ARG;
-  // Their counts and offsets are 32-bit, and an index word keeps a
-  // particle's array index below two species bits.
+  // Their counts, offsets and index words (a particle's position in the
+  // three species taken together) are 32-bit.
   if ((c->flags & PIC_FLAG_CELL_GROUPS) &&
-      (c->capacity[0] + c->capacity[1] + c->capacity[2] > 0xFFFFFFF0ll ||
-       c->capacity[0] >= (1ll << 30) || c->capacity[1] >= (1ll << 30) ||
-       c->capacity[2] >= (1ll << 30)))
+      c->capacity[0] + c->capacity[1] + c->capacity[2] > 0xFFFFFFF0ll)
     return PIC_ERR_ARG;
   return PIC_OK;
 }

@@ -62,10 +62,10 @@ def test_workspace_size_and_validation_on_host():
     assert lib.pic_workspace_bytes(ctypes.byref(odd), ctypes.byref(n)) == -1
     tol = G.make_config(p, rel_tol=0.0)
     assert lib.pic_workspace_bytes(ctypes.byref(tol), ctypes.byref(n)) == -1
-    # Cell groups: index words hold a 30-bit array index per species.
-    ok = G.make_config(p, capacity=((1 << 30) - 1, 1, 1), flags=G.FLAG_CELL_GROUPS)
+    # Cell groups: the three capacities together within 32-bit index words.
+    ok = G.make_config(p, capacity=(0xFFFFFFF0 - 2, 1, 1), flags=G.FLAG_CELL_GROUPS)
     assert lib.pic_workspace_bytes(ctypes.byref(ok), ctypes.byref(n)) == 0
-    big = G.make_config(p, capacity=(1 << 30, 1, 1), flags=G.FLAG_CELL_GROUPS)
+    big = G.make_config(p, capacity=(0xFFFFFFF0 - 1, 1, 1), flags=G.FLAG_CELL_GROUPS)
     assert lib.pic_workspace_bytes(ctypes.byref(big), ctypes.byref(n)) == -1
-    free = G.make_config(p, capacity=(1 << 30, 1, 1))
+    free = G.make_config(p, capacity=(0xFFFFFFF0 - 1, 1, 1))
     assert lib.pic_workspace_bytes(ctypes.byref(free), ctypes.byref(n)) == 0
