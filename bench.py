@@ -177,10 +177,31 @@ def capacities(p, total_steps):
             pl["n_ion"] + extra, 1_000_000 + 10_000 * total_steps), per_step_n
 
 
-def event_capacity(total_steps):
+def sources_label(p):
+    src = p["sources"]
+    parts = []
+    if "fn" in src:
+        parts.append("FN disk")
+    d = src.get("disk", {})
+    if d.get("n_e"):
+        parts.append(f"{d['n_e']} e/step disk")
+    if d.get("n_n"):
+        parts.append(f"{d['n_n']} Cu/step disk")
+    if src.get("sphere", {}).get("n"):
+        sp = src["sphere"]
+        parts.append(f"{sp['n']} Cu/step {sp['radius'] * 1e9:g} nm sphere")
+    return " + ".join(parts)
+
+
+def event_capacity(p, total_steps):
     """Per-step event-list length for a run of total_steps: the evaporated
     atoms pile up above the disk and the ionisation matching lists every
-    atom of a cell with an event, about 1e5 entries per step of the run."""
+    atom of a cell with an event, about 1e5 entries per step of the run.
+    A sphere source's atoms (2e5 a step at 3500 K move about 1e-4 nm a
+    step) stay in the cells around the sphere, tens of thousands to a cell
+    within a few steps, so there a cell with an event lists millions."""
+    if p["sources"].get("sphere", {}).get("n"):
+        return 1 << (24 if total_steps <= 60 else 26)
     if total_steps <= 60:
         return 1 << 17
     return 1 << (22 if total_steps <= 300 else 26)
@@ -190,7 +211,7 @@ def new_context(G, p, precision, pre, n0, cap, total_steps=60):
     q = dict(p)
     q["precision"] = precision
     flags = G.FLAG_CELL_GROUPS if (q.get("coulomb") or q.get("ion_processes")) else 0
-    gpu = G.Pic(q, capacity=cap, max_events=event_capacity(total_steps),
+    gpu = G.Pic(q, capacity=cap, max_events=event_capacity(p, total_steps),
                 queue_capacity=1 << 10, flags=flags)
     for s, (pos, vel, ids) in pre.items():
         gpu.load(s, pos, vel, ids)
@@ -440,7 +461,17 @@ def main():
     torch.cuda.set_device(0)
     net, train_info = None, None
     if "learned_mixed" in variants:
-        net, train_info = train_warm_start(G, W, WS, p, cap)
+        tp, tcap = p, cap
+        if p["nx"] * p["ny"] * p["nz"] > 128 * 128 * 512:
+            # A larger grid takes the network trained on the 128x128x512
+            # workload (same cell size and field): the network is fully
+            # convolutional, and its training runs at that size.
+            tp = W.config("c2")
+            tcap = capacities(tp, 40)[0]
+        net, train_info = train_warm_start(G, W, WS, tp, tcap)
+        if tp is not p:
+            net = G.UNet(p["nz"], p["ny"], p["nx"], params=net.get_params())
+            train_info["grid"] = f"{tp['nx']}x{tp['ny']}x{tp['nz']}"
         progress(f"warm-start network trained: {train_info['pairs']} pairs, "
                  f"{train_info['train_s']} s")
     pre = W.preload(p, seed=1)
@@ -498,8 +529,8 @@ def main():
         "config": {"workload": f"{a.workload}: {p['nx']}x{p['ny']}x{p['nz']} "
                                f"cells dx=2nm 1GV/m, preload "
                                f"{pl['n_e']} e + {pl['n_ion']} Cu+ + "
-                               f"{pl['n_n']} Cu, FN disk + "
-                               f"{per_step_n} Cu/step, Poisson to 1e-10",
+                               f"{pl['n_n']} Cu, {sources_label(p)}, "
+                               f"Poisson to 1e-10",
                    "variant": variants[0]},
         "roofline": roofline,
         "rooflines": rooflines,
