@@ -1748,12 +1748,15 @@ __global__ void __launch_bounds__(kSortT) k_sort_chunks(
   __shared__ Rec s[kSortChunk];
   long long n = (long long)*count;
   if (n > cap) n = cap;
-  const long long base = (long long)blockIdx.x * kSortChunk;
-  if (base >= n || n <= 1) return;
-  const int m = (int)(n - base < kSortChunk ? n - base : kSortChunk);
+  if (n <= 1) return;
   Rec maxr;
   maxr.lo = ~0ull; maxr.hi = ~0u; maxr.val = 0u;
   const int tid = threadIdx.x;
+  // Chunks strided over the grid, which the host bounds (its launch
+  // covers the capacity, not the device count).
+  for (long long base = (long long)blockIdx.x * kSortChunk; base < n;
+       base += (long long)gridDim.x * kSortChunk) {
+  const int m = (int)(n - base < kSortChunk ? n - base : kSortChunk);
   // A short chunk is padded with the largest key, so the network is fixed.
   const Rec r0 = tid < m ? a[base + tid] : maxr;
   const Rec r1 = tid + kSortT < m ? a[base + tid + kSortT] : maxr;
@@ -1776,6 +1779,8 @@ __global__ void __launch_bounds__(kSortT) k_sort_chunks(
     }
   if (tid < m) a[base + tid] = s[tid];
   if (tid + kSortT < m) a[base + tid + kSortT] = s[tid + kSortT];
+  __syncthreads();
+  }
 }
 
 // Record i of a merge round: runs of width w (sorted) pairwise into runs
@@ -1817,8 +1822,9 @@ __global__ void __launch_bounds__(kMergeT) k_merge_lds(
   __shared__ Rec s[kMergeSeg];
   long long n = (long long)*count;
   if (n > cap) n = cap;
-  const long long base = (long long)blockIdx.x * kMergeSeg;
-  if (base >= n || n - base <= kSortChunk) return;
+  // Segments strided over the grid (bounded by the host, as above).
+  for (long long base = (long long)blockIdx.x * kMergeSeg;
+       base + kSortChunk < n; base += (long long)gridDim.x * kMergeSeg) {
   const int m = (int)(n - base < kMergeSeg ? n - base : kMergeSeg);
   const int tid = threadIdx.x;
   constexpr int kPer = kMergeSeg / kMergeT;
@@ -1867,6 +1873,8 @@ __global__ void __launch_bounds__(kMergeT) k_merge_lds(
     const int i = tid + k * kMergeT;
     if (i < m) a[base + i] = s[i];
   }
+  __syncthreads();
+  }
 }
 
 __global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst,
@@ -1875,9 +1883,9 @@ __global__ void k_merge_round(const Rec* __restrict__ src, Rec* __restrict__ dst
   long long n = (long long)*count;
   if (n > cap) n = cap;
   if (w >= n) return;   // one run already
-  const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  merge_one(src, dst, n, w, i);
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    merge_one(src, dst, n, w, i);
 }
 
 // The sorted list back into the first buffer when the merge rounds that
@@ -2517,15 +2525,18 @@ uint32_t* ts_cur(pic_ctx* c, int s) { return c->tsb[s][c->tcur[s]]; }
 void sort_records(pic_ctx* c, Rec* a, Rec* tmp,
                   const unsigned long long* count, long long cap) {
   hipStream_t st = c->stream;
-  const long long nchunk = (cap + kSortChunk - 1) / kSortChunk;
+  // Grids bounded so that a short list in a large capacity costs little:
+  // the kernels stride over the device count.
+  const long long nchunk = std::min<long long>((cap + kSortChunk - 1) / kSortChunk, 4096);
   k_sort_chunks<<<(unsigned)nchunk, kSortT, 0, st>>>(a, tmp, count, cap);
   if (cap > kSortChunk)
-    k_merge_lds<<<(unsigned)((cap + kMergeSeg - 1) / kMergeSeg), kMergeT, 0, st>>>(
-        a, count, cap);
+    k_merge_lds<<<(unsigned)std::min<long long>((cap + kMergeSeg - 1) / kMergeSeg, 1024),
+                  kMergeT, 0, st>>>(a, count, cap);
   Rec* src = a;
   Rec* dst = tmp;
+  const unsigned nround = std::min<unsigned>(nblk(cap), kFixedBlocks);
   for (long long w = kMergeSeg; w < cap; w *= 2) {
-    k_merge_round<<<nblk(cap), kT, 0, st>>>(src, dst, count, cap, w);
+    k_merge_round<<<nround, kT, 0, st>>>(src, dst, count, cap, w);
     Rec* t = src; src = dst; dst = t;
   }
   if (cap > kMergeSeg) k_copy_recs<<<256, kT, 0, st>>>(tmp, a, count, cap);

@@ -337,6 +337,40 @@ def test_absorbed_list_longer_than_a_sort_chunk(gpu_lib):
     assert np.array_equal(ab_g["vel"].cpu().numpy(), vel_o)
 
 
+def test_absorbed_list_of_millions_sorted(gpu_lib):
+    """4.5 M electrons and ions cross the cathode in one step, so each of
+    the record sort's kernels takes several chunks, segments or records per
+    workgroup or thread (their grids are bounded, the device count is
+    not): the cathode list comes back sorted by (species, id), every
+    particle in it once."""
+    p = small_c2(n_e=10, n_ion=10, n_n=10)
+    p["sources"] = {}
+    p["collisions"] = dict(p["collisions"], enabled=False)
+    g = grid_of(p)
+    ne, ni = 2_500_000, 2_000_000
+    gpu = make(p, cap=ne + 1000, max_events=1 << 23)
+    rng = np.random.default_rng(29)
+    n0 = 0
+    want = []
+    for s, n in ((0, ne), (2, ni)):
+        L = np.array([g.lx, g.ly, 0.3 * p["dx"]])
+        pos = rng.random((n, 3)) * L
+        vel = rng.standard_normal((n, 3)) * 1e3
+        vel[:, 2] = -np.abs(vel[:, 2]) - 0.5 * p["dx"] / p["dt"]   # into the cathode
+        ids = rng.permutation(np.arange(n0, n0 + n, dtype=np.uint64) * 7 + 3)
+        gpu.load(s, pos, vel, ids)
+        want.append(np.sort(ids))
+        n0 += n
+    gpu.set_clock(0, 10 ** 8)
+    gpu.set_phi(P.solve_exact(P.add_boundary_terms(np.zeros(g.shape), g), g))
+    ab, _ = gpu.advance(p["dt"])
+    assert ab["n"] == ne + ni
+    sp = ab["species"].cpu().numpy().astype(np.int64)
+    ids = ab["id"].cpu().numpy().astype(np.uint64)
+    assert np.array_equal(sp, np.repeat([0, 2], [ne, ni]))
+    assert np.array_equal(ids[:ne], want[0]) and np.array_equal(ids[ne:], want[1])
+
+
 def test_ions_removed_in_place_over_steps(gpu_lib):
     """8 000 slow ions in the bulk and 600 that reach the cathode over the
     next steps, a few per tile: each step removes the ions that left in
